@@ -1,0 +1,567 @@
+"""FP64 CPU oracle of DeepMatching's hot path.
+
+TEST INFRASTRUCTURE ONLY.  This module is the checker the GPU library is held
+against.  Only the test suite, the smoke entry point and the CPU-baseline leg
+of the benchmark may import it; the product path never does, and it shares no
+code, table or helper with the GPU library.
+
+It follows Revaud, Weinzaepfel, Harchaoui and Schmid, "DeepMatching:
+Hierarchical Deformable Dense Matching" (IJCV 2016), in float64 NumPy:
+
+* pixel descriptor ............ Sec. 3.2, paragraph "Pixel descriptor"
+* bottom correlation .......... Sec. 3.2, Eqs. (3)-(4), Algorithm 1 (first loop)
+* max-pool + subsample ........ Sec. 3.2, Eqs. (8)-(9)
+* patch grids ................. Sec. 3.2, Eq. (7) and "Boundary effects"
+* shift + average + rectify ... Sec. 3.2, Eqs. (5), (10)-(12), Algorithm 1
+* backtracking + merge ........ Sec. 3.3, Eqs. (13)-(15)
+* reciprocal verification ..... Sec. 3.3, Eq. (16)
+* gradient of the top-level loss (no counterpart in the paper): the adjoint
+  of each forward step above, written out by hand.
+
+Where the GPU path uses a dense gather formulation of the backtracking, this
+oracle keeps the paper's literal sets of tuples (N, p, p', s) and merges equal
+(N, p, p') by keeping the highest score.
+
+Readings taken where the paper is silent, ambiguous or inconsistent (the GPU
+library takes the same ones):
+
+ R1  A parent exists when its centre lies inside the image and at least one of
+     its four children exists; the average runs over the existing children
+     ("Boundary effects" example), not over all four as Eq. (7) literally says.
+ R2  The neighbourhood Theta_i has radius N/8, i.e. the 3x3 window of Eq. (9)
+     in subsampled units.
+ R3  The shifted child map is read at q + o_i (the sign that makes an image
+     match itself at the identity position, and the one the backtracking of
+     Eq. (13) uses).
+ R4  The bottom level is rectified too (Algorithm 1).
+ R5  Target borders: the bottom correlation treats I' as zero outside; pooling
+     ignores positions outside the map; an aggregated child read outside the
+     map counts as 0 but the child still counts in the average; backtracking
+     does not expand a child whose position falls outside the map.  Map sizes
+     halve with rounding up.
+ R6  Atomic centres are 2+4a with the whole 4x4 patch inside I (floor(W/4)
+     columns); trailing pixels are never a source.
+ R7  The pyramid top is Algorithm 1's loop bound (N < max(W, H)) or an
+     explicit N_max, capped at the last level whose grid is non-empty.
+ R8  A patch of even size N centred at p covers [p - N/2, p + N/2 - 1].
+ R9  Argmax ties: first maximum in the order k = 3(m_y + 1) + (m_x + 1).
+ R10 Descriptor: intensities scaled by 255; Gaussian "radius" nu = standard
+     deviation, truncated at ceil(3 nu), replicated borders; central
+     differences with replicated borders; orientations k*pi/4 with y down.
+ R11 Match score: the top-level value plus the pooled child values along the
+     backtracking path (Eq. (14)).
+ R12 Reciprocal vicinities are the fixed 4x4 cells floor(p/4) and
+     floor(p'/4); BestAt ties go to the smallest (p'_y, p'_x), BestAt' ties to
+     the smallest (p_y, p_x, p'_y, p'_x).
+ R13 Loss for the gradient: the sum over top-level patches of the maximum of
+     their rectified map (ties: first in raster order).
+
+Parity of the descriptor against the paper itself is unpinned (R10 fills in
+details the paper does not give); it is pinned only by its invariants.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Child offsets o_i as (x, y), Eq. (5).
+OFFSETS = ((-1, -1), (-1, +1), (+1, -1), (+1, +1))
+
+
+@dataclass
+class Params:
+    """Method parameters (Sec. 5.2.1: nu1=0, mu=0.1 for uncompressed images;
+    nu2=nu3=1, slope 0.2, lambda=1.4)."""
+    nu1: float = 0.0
+    nu2: float = 1.0
+    nu3: float = 1.0
+    slope: float = 0.2
+    mu: float = 0.1
+    scale: float = 255.0
+    lam: float = 1.4
+    max_patch: int = 0
+
+
+# ----------------------------------------------------------------------------
+# Pixel descriptor (Sec. 3.2, "Pixel descriptor")
+# ----------------------------------------------------------------------------
+
+def gaussian_taps(sigma: float) -> np.ndarray:
+    r = int(math.ceil(3.0 * sigma))
+    t = np.arange(-r, r + 1, dtype=np.float64)
+    g = np.exp(-t * t / (2.0 * sigma * sigma))
+    return g / g.sum()
+
+
+def _smooth_axis(a: np.ndarray, g: np.ndarray, axis: int) -> np.ndarray:
+    r = len(g) // 2
+    n = a.shape[axis]
+    out = np.zeros_like(a)
+    for t in range(-r, r + 1):
+        idx = np.clip(np.arange(n) + t, 0, n - 1)
+        out += g[t + r] * np.take(a, idx, axis=axis)
+    return out
+
+
+def smooth(a: np.ndarray, sigma: float) -> np.ndarray:
+    """Gaussian smoothing of an H x W (x C) array, replicated borders (R10)."""
+    if sigma <= 0:
+        return a
+    g = gaussian_taps(sigma)
+    return _smooth_axis(_smooth_axis(a, g, 1), g, 0)
+
+
+def descriptors(img: np.ndarray, prm: Params = Params()) -> np.ndarray:
+    """Per-pixel descriptor R_ij in R^9 (H x W x 9), unit l2 norm.
+
+    Smooth (nu1), gradient, non-negative projections on the 8 orientations
+    (cos k pi/4, sin k pi/4), smooth (nu2), sigmoid cap 2/(1+exp(-slope x))-1,
+    smooth (nu3), append mu, l2-normalise."""
+    J = prm.scale * np.asarray(img, dtype=np.float64)
+    J = smooth(J, prm.nu1)
+    H, W = J.shape
+    xp = np.minimum(np.arange(W) + 1, W - 1)
+    xm = np.maximum(np.arange(W) - 1, 0)
+    yp = np.minimum(np.arange(H) + 1, H - 1)
+    ym = np.maximum(np.arange(H) - 1, 0)
+    gx = (J[:, xp] - J[:, xm]) / 2.0
+    gy = (J[yp, :] - J[ym, :]) / 2.0
+    O = np.stack([np.maximum(0.0, gx * math.cos(k * math.pi / 4) + gy * math.sin(k * math.pi / 4))
+                  for k in range(1, 9)], axis=-1)
+    O = smooth(O, prm.nu2)
+    O = 2.0 / (1.0 + np.exp(-prm.slope * O)) - 1.0
+    O = smooth(O, prm.nu3)
+    d = np.concatenate([O, np.full((H, W, 1), prm.mu)], axis=-1)
+    return d / np.sqrt((d * d).sum(-1, keepdims=True))
+
+
+# ----------------------------------------------------------------------------
+# Geometry: patch grids and map sizes (Sec. 3.2, Eq. (7), "Boundary effects")
+# ----------------------------------------------------------------------------
+
+def lattice_shape(level: int, W: int, H: int):
+    """(ny, nx) of the lattice of candidate centres at a level.
+
+    Level 0: atomic centres (2+4a, 2+4b) with the patch inside (R6).
+    Level >= 1: centres (4a, 4b) inside the image."""
+    if level == 0:
+        return H // 4, W // 4
+    return (H - 1) // 4 + 1, (W - 1) // 4 + 1
+
+
+def lattice_centres(level: int, W: int, H: int):
+    ny, nx = lattice_shape(level, W, H)
+    base = 2 if level == 0 else 0
+    return base + 4 * np.arange(ny), base + 4 * np.arange(nx)
+
+
+def lattice_index(level: int, W: int, H: int, cy, cx):
+    """Lattice indices (b, a) of centres at a level, and whether they exist."""
+    ny, nx = lattice_shape(level, W, H)
+    base = 2 if level == 0 else 0
+    cy = np.asarray(cy)
+    cx = np.asarray(cx)
+    ok = ((cy - base) % 4 == 0) & ((cx - base) % 4 == 0)
+    b = (cy - base) // 4
+    a = (cx - base) // 4
+    ok &= (b >= 0) & (b < ny) & (a >= 0) & (a < nx)
+    return np.where(ok, b, 0), np.where(ok, a, 0), ok
+
+
+def grids(W: int, H: int, lmax: int):
+    """Boolean masks G_l over each level's lattice, for l = 0..lmax (R1)."""
+    ny, nx = lattice_shape(0, W, H)
+    G = [np.ones((ny, nx), dtype=bool)]
+    for lv in range(1, lmax + 1):
+        cy, cx = lattice_centres(lv, W, H)
+        CY, CX = np.meshgrid(cy, cx, indexing="ij")
+        g = np.zeros(CY.shape, dtype=bool)
+        for ox, oy in OFFSETS:
+            b, a, ok = lattice_index(lv - 1, W, H, CY + (2 ** lv) * oy, CX + (2 ** lv) * ox)
+            g |= ok & G[lv - 1][b, a]
+        G.append(g)
+    return G
+
+
+def pyramid_top(W: int, H: int, max_patch: int = 0) -> int:
+    """Top level index lmax (N_max = 4 * 2^lmax), R7."""
+    if max_patch:
+        if max_patch < 4 or (max_patch & (max_patch - 1)):
+            raise ValueError("max_patch must be a power of two >= 4")
+        N = max_patch
+    else:
+        N = 4
+        while N < max(W, H):          # Algorithm 1's loop bound
+            N *= 2
+    lmax = int(round(math.log2(N // 4)))
+    G = grids(W, H, lmax)
+    while lmax > 0 and not G[lmax].any():
+        lmax -= 1
+    return lmax
+
+
+def map_dims(H2: int, W2: int, lmax: int):
+    """(h_l, w_l) for l = 0..lmax+1: h_0 = H', h_l = ceil(h_{l-1}/2)."""
+    h, w = [H2], [W2]
+    for _ in range(lmax + 1):
+        h.append((h[-1] + 1) // 2)
+        w.append((w[-1] + 1) // 2)
+    return h, w
+
+
+# ----------------------------------------------------------------------------
+# Bottom level (Eqs. (3)-(4)) and pyramid (Eqs. (8)-(12), Algorithm 1)
+# ----------------------------------------------------------------------------
+
+def bottom_scores(D1: np.ndarray, D2: np.ndarray, rows=None) -> np.ndarray:
+    """A_0(p, q) = 1/16 sum_{i,j} R_ij(p)^T R'_ij(q), Eq. (3), for atomic
+    centres p (patch rows `rows` of G_4) and every pixel q of I' (R5: I' is
+    zero outside).  Returns shape (n_rows, nx0, H', W')."""
+    H, W, C = D1.shape
+    H2, W2, _ = D2.shape
+    ny, nx = lattice_shape(0, W, H)
+    rows = np.arange(ny) if rows is None else np.asarray(rows)
+    cy = 2 + 4 * rows
+    cx = 2 + 4 * np.arange(nx)
+    D2p = np.zeros((H2 + 3, W2 + 3, C))
+    D2p[2:2 + H2, 2:2 + W2] = D2
+    # Patch vectors and target im2col over the 16 offsets of the 4x4 patch
+    # (offsets -2..+1 around the centre, R8), in the same (dy, dx, c) order.
+    offs = [(dy, dx) for dy in (-2, -1, 0, 1) for dx in (-2, -1, 0, 1)]
+    P = np.concatenate([D1[np.ix_(cy + dy, cx + dx)].reshape(-1, C) for dy, dx in offs], axis=1)
+    S = np.concatenate([D2p[2 + dy:2 + dy + H2, 2 + dx:2 + dx + W2].reshape(-1, C)
+                        for dy, dx in offs], axis=1)
+    A = P @ S.T
+    return (A / 16.0).reshape(len(rows), nx, H2, W2)
+
+
+def rectify(A: np.ndarray, lam: float) -> np.ndarray:
+    """R_lambda, Eq. (11), on max(A, 0)."""
+    return np.maximum(A, 0.0) ** lam
+
+
+def pool_subsample(C: np.ndarray):
+    """(S o P)(C), Eqs. (8)-(9): C'(r) = max_{m in {-1,0,1}^2} C(2r + m) over
+    positions inside the map.  Returns (C', code, gap): code = 3(m_y+1)+(m_x+1)
+    of the first maximum (R9), gap = best minus second-best candidate."""
+    h, w = C.shape[-2:]
+    h2, w2 = (h + 1) // 2, (w + 1) // 2
+    Cp = np.full(C.shape[:-2] + (h + 3, w + 3), -np.inf)
+    Cp[..., 1:1 + h, 1:1 + w] = C
+    best = np.full(C.shape[:-2] + (h2, w2), -np.inf)
+    second = np.full_like(best, -np.inf)
+    code = np.zeros(best.shape, dtype=np.int8)
+    for my in (-1, 0, 1):
+        for mx in (-1, 0, 1):
+            k = 3 * (my + 1) + (mx + 1)
+            v = Cp[..., 1 + my:1 + my + 2 * h2:2, 1 + mx:1 + mx + 2 * w2:2]
+            upd = v > best                      # strict: the first maximum wins
+            np.maximum(second, np.minimum(v, best), out=second)
+            np.copyto(code, np.int8(k), where=upd)
+            np.maximum(best, v, out=best)
+    return best, code, best - second
+
+
+def risky(gap: np.ndarray) -> np.ndarray:
+    """Gap as a risk margin: an exact tie (gap 0) comes from the same value
+    reaching several candidates (overlapping pooling windows, equal sums) and
+    is resolved by the tie rule in any precision, so it carries no risk."""
+    return np.where(gap == 0, np.inf, gap)
+
+
+def shift_read(M: np.ndarray, ox: int, oy: int) -> np.ndarray:
+    """T applied as in R3: S(q) = M(q + o), 0 outside the map (R5)."""
+    h, w = M.shape[-2:]
+    Mp = np.zeros(M.shape[:-2] + (h + 2, w + 2))
+    Mp[..., 1:1 + h, 1:1 + w] = M
+    return Mp[..., 1 + oy:1 + oy + h, 1 + ox:1 + ox + w]
+
+
+@dataclass
+class Pyramid:
+    W: int
+    H: int
+    W2: int
+    H2: int
+    lmax: int
+    lam: float
+    G: list
+    h: list
+    w: list
+    Cp: list = field(default_factory=list)      # pooled maps C'_l, l < lmax
+    code: list = field(default_factory=list)    # argmax codes of C'_l
+    gap: list = field(default_factory=list)     # top-2 gaps of the pooling
+    top: np.ndarray = None                      # C_lmax (unpooled)
+    A: list = field(default_factory=list)       # pre-rectification maps (keep_full)
+
+
+def aggregate(prev_pooled: np.ndarray, lv: int, pyr: Pyramid) -> np.ndarray:
+    """A_l(p, q) = 1/|V(p)| sum_{i in V(p)} C'_{l-1}(p + 2^l o_i, q + o_i),
+    Eqs. (6), (10), (12) with R1, R3, R5.  Invalid parents get NaN maps."""
+    W, H = pyr.W, pyr.H
+    cy, cx = lattice_centres(lv, W, H)
+    CY, CX = np.meshgrid(cy, cx, indexing="ij")
+    h, w = pyr.h[lv], pyr.w[lv]
+    acc = np.zeros(CY.shape + (h, w))
+    cnt = np.zeros(CY.shape)
+    for ox, oy in OFFSETS:
+        b, a, ok = lattice_index(lv - 1, W, H, CY + (2 ** lv) * oy, CX + (2 ** lv) * ox)
+        ok &= pyr.G[lv - 1][b, a]
+        child = np.where(ok[..., None, None], prev_pooled[b, a], 0.0)
+        acc += shift_read(child, ox, oy)
+        cnt += ok
+    A = acc / np.maximum(cnt, 1)[..., None, None]
+    A[~pyr.G[lv]] = np.nan
+    return A
+
+
+def pyramid(D1: np.ndarray, D2: np.ndarray, prm: Params = Params(), keep_full: bool = False,
+            row_chunk: int = 8) -> Pyramid:
+    """Multi-level correlation pyramid, Algorithm 1."""
+    H, W, _ = D1.shape
+    H2, W2, _ = D2.shape
+    lmax = pyramid_top(W, H, prm.max_patch)
+    G = grids(W, H, lmax)
+    h, w = map_dims(H2, W2, lmax)
+    pyr = Pyramid(W, H, W2, H2, lmax, prm.lam, G, h, w)
+    ny0 = lattice_shape(0, W, H)[0]
+    # Level 0: C_4 = R_lambda(I_4^F * I'), then S o P unless it is the top.
+    parts_cp, parts_code, parts_gap, parts_A, parts_top = [], [], [], [], []
+    for r0 in range(0, ny0, row_chunk):
+        A0 = bottom_scores(D1, D2, np.arange(r0, min(ny0, r0 + row_chunk)))
+        C0 = rectify(A0, prm.lam)
+        if keep_full:
+            parts_A.append(A0)
+        if lmax == 0:
+            parts_top.append(C0)
+        else:
+            cp, cd, gp = pool_subsample(C0)
+            parts_cp.append(cp)
+            parts_code.append(cd)
+            parts_gap.append(gp)
+    if keep_full:
+        pyr.A.append(np.concatenate(parts_A))
+    if lmax == 0:
+        pyr.top = np.concatenate(parts_top)
+        return pyr
+    pyr.Cp.append(np.concatenate(parts_cp))
+    pyr.code.append(np.concatenate(parts_code))
+    pyr.gap.append(np.concatenate(parts_gap))
+    for lv in range(1, lmax + 1):
+        A = aggregate(pyr.Cp[lv - 1], lv, pyr)
+        C = rectify(A, prm.lam)
+        if keep_full:
+            pyr.A.append(A)
+        if lv == lmax:
+            pyr.top = C
+        else:
+            cp, cd, gp = pool_subsample(C)
+            pyr.Cp.append(cp)
+            pyr.code.append(cd)
+            pyr.gap.append(gp)
+    return pyr
+
+
+# ----------------------------------------------------------------------------
+# Top-down backtracking with merging (Sec. 3.3, Eqs. (13)-(15))
+# ----------------------------------------------------------------------------
+
+def _dedup_max(key: np.ndarray, s: np.ndarray):
+    """Indices of the highest-score tuple of each key, and the gap to the
+    runner-up (inf for singletons)."""
+    order = np.lexsort((-s, key))
+    k = key[order]
+    first = np.ones(len(k), dtype=bool)
+    first[1:] = k[1:] != k[:-1]
+    keep = order[first]
+    starts = np.flatnonzero(first)
+    gap = np.full(len(starts), np.inf)
+    has2 = np.append(starts[1:], len(k)) - starts > 1
+    gap[has2] = s[order[starts[has2]]] - s[order[starts[has2] + 1]]
+    return keep, gap
+
+
+def backtrack(pyr: Pyramid, entries=None):
+    """M' = B o ... o B (M), Eq. (15), merging equal (N, p, p') by max.
+
+    Entry points are all top-level (p, p') (Sec. 3.3, "Merging
+    correspondences").  Returns a dict of arrays over the atomic tuples:
+    b, a (atomic lattice indices of p), qy, qx (pixel p' in I'), s (score),
+    margin (smallest pooling-argmax gap along the tuple's path)."""
+    W, H, lmax = pyr.W, pyr.H, pyr.lmax
+    Gt = pyr.G[lmax]
+    if entries is None:
+        bb, aa = np.nonzero(Gt)
+        ht, wt = pyr.h[lmax], pyr.w[lmax]
+        qy, qx = np.meshgrid(np.arange(ht), np.arange(wt), indexing="ij")
+        n = len(bb)
+        b = np.repeat(bb, ht * wt)
+        a = np.repeat(aa, ht * wt)
+        qy = np.tile(qy.ravel(), n)
+        qx = np.tile(qx.ravel(), n)
+    else:
+        b, a, qy, qx = (np.asarray(e) for e in entries)
+    s = pyr.top[b, a, qy, qx].astype(np.float64)
+    margin = np.full(len(s), np.inf)
+    for lv in range(lmax, 0, -1):
+        h, w = pyr.h[lv], pyr.w[lv]
+        cy, cx = lattice_centres(lv, W, H)
+        out = {k: [] for k in ("b", "a", "qy", "qx", "s", "m")}
+        for ox, oy in OFFSETS:
+            cb, ca, ok = lattice_index(lv - 1, W, H, cy[b] + (2 ** lv) * oy, cx[a] + (2 ** lv) * ox)
+            ok &= pyr.G[lv - 1][cb, ca]
+            ry, rx = qy + oy, qx + ox
+            ok &= (ry >= 0) & (ry < h) & (rx >= 0) & (rx < w)
+            cb, ca, ry, rx = cb[ok], ca[ok], ry[ok], rx[ok]
+            k = pyr.code[lv - 1][cb, ca, ry, rx].astype(np.int64)
+            out["b"].append(cb)
+            out["a"].append(ca)
+            out["qy"].append(2 * ry + (k // 3 - 1))        # p'_i = 2(p' + o_i) + m_i, Eq. (13)
+            out["qx"].append(2 * rx + (k % 3 - 1))
+            out["s"].append(s[ok] + pyr.Cp[lv - 1][cb, ca, ry, rx])   # Eq. (14)
+            out["m"].append(np.minimum(margin[ok], risky(pyr.gap[lv - 1][cb, ca, ry, rx])))
+        b, a, qy, qx, s, margin = (np.concatenate(out[k]) for k in ("b", "a", "qy", "qx", "s", "m"))
+        ny, nx = lattice_shape(lv - 1, W, H)
+        key = ((b * nx + a) * pyr.h[lv - 1] + qy) * pyr.w[lv - 1] + qx
+        keep, _ = _dedup_max(key, s)
+        b, a, qy, qx, s, margin = b[keep], a[keep], qy[keep], qx[keep], s[keep], margin[keep]
+    return dict(b=b, a=a, qy=qy, qx=qx, s=s, margin=margin)
+
+
+# ----------------------------------------------------------------------------
+# Reciprocal verification (Sec. 3.3, Eq. (16))
+# ----------------------------------------------------------------------------
+
+def reciprocal(M: dict, W: int, H: int, W2: int, H2: int):
+    """M'' = {t in M' : BestAt(p) = t = BestAt'(p')} with R12.
+
+    Returns an (n, 5) array [x1, y1, x2, y2, score] sorted by (y1, x1), and
+    the per-match margin (smallest decision gap: path argmaxes, BestAt and
+    BestAt')."""
+    b, a, qy, qx, s = M["b"], M["a"], M["qy"], M["qx"], M["s"]
+    nx = lattice_shape(0, W, H)[1]
+    n = len(s)
+    if n == 0:
+        return np.zeros((0, 5)), np.zeros(0)
+    pid = b * nx + a
+    # BestAt(p): max score, ties -> smallest (p'_y, p'_x).
+    o1 = np.lexsort((qy * W2 + qx, -s, pid))
+    f1 = np.ones(n, dtype=bool)
+    f1[1:] = pid[o1][1:] != pid[o1][:-1]
+    best_p = o1[f1]
+    gap_p = np.full(n, np.inf)
+    st = np.flatnonzero(f1)
+    two = np.append(st[1:], n) - st > 1
+    gap_p[best_p[two]] = s[o1[st[two]]] - s[o1[st[two] + 1]]
+    # BestAt'(cell of p'): max score, ties -> smallest (p_y, p_x, p'_y, p'_x).
+    cw = (W2 + 3) // 4
+    cell = (qy // 4) * cw + (qx // 4)
+    o2 = np.lexsort(((pid * H2 + qy) * W2 + qx, -s, cell))
+    f2 = np.ones(n, dtype=bool)
+    f2[1:] = cell[o2][1:] != cell[o2][:-1]
+    best_c = o2[f2]
+    gap_c = np.full(n, np.inf)
+    st = np.flatnonzero(f2)
+    two = np.append(st[1:], n) - st > 1
+    gap_c[best_c[two]] = s[o2[st[two]]] - s[o2[st[two] + 1]]
+    is_p = np.zeros(n, dtype=bool)
+    is_p[best_p] = True
+    is_c = np.zeros(n, dtype=bool)
+    is_c[best_c] = True
+    sel = np.flatnonzero(is_p & is_c)
+    sel = sel[np.lexsort((a[sel], b[sel]))]
+    out = np.stack([2 + 4 * a[sel], 2 + 4 * b[sel], qx[sel], qy[sel], s[sel]], axis=1).astype(np.float64)
+    margin = np.minimum(M["margin"][sel], risky(np.minimum(gap_p[sel], gap_c[sel])))
+    return out, margin
+
+
+def match_descriptors(D1: np.ndarray, D2: np.ndarray, prm: Params = Params()):
+    """Descriptors -> pyramid -> backtracking -> reciprocal matches."""
+    pyr = pyramid(D1, D2, prm)
+    M = backtrack(pyr)
+    out, margin = reciprocal(M, pyr.W, pyr.H, pyr.W2, pyr.H2)
+    return out, margin, pyr, M
+
+
+def match(img1: np.ndarray, img2: np.ndarray, prm: Params = Params()):
+    """Images -> quasi-dense reciprocal matches [x1, y1, x2, y2, score]."""
+    return match_descriptors(descriptors(img1, prm), descriptors(img2, prm), prm)
+
+
+# ----------------------------------------------------------------------------
+# Gradient of L = sum_{p in G_top} max_q C_top(p, q) w.r.t. both descriptors
+# ----------------------------------------------------------------------------
+
+def top_loss(pyr: Pyramid) -> float:
+    """R13: sum over existing top patches of the map maximum."""
+    t = pyr.top[pyr.G[pyr.lmax]]
+    return float(t.reshape(len(t), -1).max(1).sum())
+
+
+def pyramid_backward(D1: np.ndarray, D2: np.ndarray, pyr: Pyramid):
+    """dL/dD1, dL/dD2 for the loss of `top_loss`, by hand-written adjoints of
+    rectification, shift-average, max-pool/subsample (routed to the stored
+    argmax) and the bottom correlation.  `pyr` must come from
+    pyramid(..., keep_full=True)."""
+    W, H, lmax, lam = pyr.W, pyr.H, pyr.lmax, pyr.lam
+    top = pyr.top
+    G = pyr.G[lmax]
+    flat = np.where(G[..., None], top.reshape(top.shape[0], top.shape[1], -1), -np.inf)
+    am = flat.argmax(-1)                                  # first maximum in raster order
+    dC = np.zeros_like(top)
+    bb, aa = np.nonzero(G)
+    dC.reshape(top.shape[0], top.shape[1], -1)[bb, aa, am[bb, aa]] = 1.0
+    for lv in range(lmax, 0, -1):
+        A = pyr.A[lv]
+        dA = np.where(A > 0, dC * lam * np.where(A > 0, A, 1.0) ** (lam - 1.0), 0.0)
+        dA[~pyr.G[lv]] = 0.0
+        # adjoint of the shifted average
+        h, w = pyr.h[lv], pyr.w[lv]
+        ny, nx = lattice_shape(lv - 1, W, H)
+        dCp = np.zeros((ny, nx, h + 2, w + 2))
+        cy, cx = lattice_centres(lv, W, H)
+        CY, CX = np.meshgrid(cy, cx, indexing="ij")
+        cnt = np.zeros(CY.shape)
+        links = []
+        for ox, oy in OFFSETS:
+            cb, ca, ok = lattice_index(lv - 1, W, H, CY + (2 ** lv) * oy, CX + (2 ** lv) * ox)
+            ok &= pyr.G[lv - 1][cb, ca] & pyr.G[lv]
+            cnt += ok
+            links.append((ox, oy, cb, ca, ok))
+        for ox, oy, cb, ca, ok in links:
+            pb, pa = np.nonzero(ok)
+            contrib = dA[pb, pa] / cnt[pb, pa][:, None, None]
+            dCp[cb[pb, pa], ca[pb, pa], 1 + oy:1 + oy + h, 1 + ox:1 + ox + w] += contrib
+        dCp = dCp[:, :, 1:1 + h, 1:1 + w]
+        # adjoint of S o P: route to the stored argmax
+        hp, wp = pyr.h[lv - 1], pyr.w[lv - 1]
+        dC = np.zeros((ny, nx, hp + 3, wp + 3))
+        code = pyr.code[lv - 1]
+        for my in (-1, 0, 1):
+            for mx in (-1, 0, 1):
+                k = 3 * (my + 1) + (mx + 1)
+                sel = np.where(code == k, dCp, 0.0)
+                dC[..., 1 + my:1 + my + 2 * h:2, 1 + mx:1 + mx + 2 * w:2] += sel
+        dC = dC[..., 1:1 + hp, 1:1 + wp]
+    A0 = pyr.A[0]
+    dA0 = np.where(A0 > 0, dC * lam * np.where(A0 > 0, A0, 1.0) ** (lam - 1.0), 0.0)
+    # adjoint of the bottom correlation, Eq. (3)
+    Hh, Ww, C = D1.shape
+    H2, W2, _ = D2.shape
+    ny0, nx0 = lattice_shape(0, W, H)
+    cy = 2 + 4 * np.arange(ny0)
+    cx = 2 + 4 * np.arange(nx0)
+    D2p = np.zeros((H2 + 3, W2 + 3, C))
+    D2p[2:2 + H2, 2:2 + W2] = D2
+    dD1 = np.zeros_like(D1, dtype=np.float64)
+    dD2p = np.zeros_like(D2p)
+    g = dA0.reshape(ny0 * nx0, H2 * W2) / 16.0
+    for dy in (-2, -1, 0, 1):
+        for dx in (-2, -1, 0, 1):
+            S = D2p[2 + dy:2 + dy + H2, 2 + dx:2 + dx + W2].reshape(-1, C)
+            P = D1[np.ix_(cy + dy, cx + dx)].reshape(-1, C)
+            dD1[np.ix_(cy + dy, cx + dx)] += (g @ S).reshape(ny0, nx0, C)
+            dD2p[2 + dy:2 + dy + H2, 2 + dx:2 + dx + W2] += (g.T @ P).reshape(H2, W2, C)
+    return dD1, dD2p[2:2 + H2, 2:2 + W2]
