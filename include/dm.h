@@ -1,0 +1,189 @@
+/*
+ * dm.h -- C ABI of the MI355X DeepMatching library (libdm.so).
+ *
+ * The library computes the hot path of DeepMatching (Revaud, Weinzaepfel,
+ * Harchaoui, Schmid, "DeepMatching: Hierarchical Deformable Dense Matching",
+ * IJCV 2016): per-pixel descriptors (Sec. 3.2, "Pixel descriptor"), the
+ * bottom-up multi-level correlation pyramid (Sec. 3.2, Eqs. (3)-(12),
+ * Algorithm 1) and the top-down backtracking with merging and reciprocal
+ * verification (Sec. 3.3, Eqs. (13)-(16)).  Given two images I (W x H) and
+ * I' (W' x H') it returns quasi-dense correspondences (p, p', s).
+ *
+ * Conventions shared by every entry point:
+ *  - Pixels are 0-based, x to the right, y down.  Images are row-major
+ *    float32 grey values in [0, 1] with a leading dimension `ld` (>= W,
+ *    in elements).  Descriptors are float32, H x W x 9, channel innermost.
+ *  - Every buffer is owned by the caller.  Pointers named *_host are host
+ *    memory; all others are device memory of the current HIP device.  The
+ *    library allocates no device memory: scratch space comes from the caller
+ *    as a workspace whose size dm_plan() reports.
+ *  - Calls that take a stream enqueue their work on it and return without
+ *    waiting; results are ready once the stream has reached that point.
+ *    Arguments are validated on the host before anything is enqueued; on an
+ *    error nothing is enqueued and dm_last_error() describes the problem.
+ *  - The library keeps no state between calls other than the thread-local
+ *    error text.  Calls on different streams with different workspaces may
+ *    run concurrently; two calls sharing a workspace must be ordered.
+ */
+#ifndef DM_H
+#define DM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DM_MAX_LEVELS 16   /* level index l < 16, patch size N = 4 * 2^l   */
+#define DM_MAX_DIM 8192    /* largest supported image width or height      */
+
+typedef enum {
+    DM_OK = 0,
+    DM_ERR_INVALID_ARG = -1,   /* null pointer, bad parameter value          */
+    DM_ERR_SHAPE = -2,         /* image smaller than one atomic patch, too big */
+    DM_ERR_WORKSPACE = -3,     /* workspace smaller than dm_plan() reports   */
+    DM_ERR_CAPACITY = -4,      /* output smaller than plan.max_matches       */
+    DM_ERR_UNSUPPORTED = -5,   /* precision or mode not available for a call */
+    DM_ERR_HIP = -6            /* a HIP runtime call failed                  */
+} dm_status;
+
+typedef enum {
+    DM_FP32 = 0,   /* bottom correlation on FP32 MFMA, pyramid FP32          */
+    DM_BF16 = 1,   /* bottom correlation on BF16 MFMA with FP32 accumulation */
+    DM_FP64 = 2    /* every stage in FP64 (gradient checks)                  */
+} dm_precision;
+
+/* Method parameters.  Descriptor (Sec. 3.2 "Pixel descriptor", values of
+ * Sec. 5.2.1 for uncompressed images): Gaussian smoothing with standard
+ * deviation nu1 before the gradient (0 = none), nu2 on the 8 oriented
+ * gradient maps, nu3 after the sigmoid 2/(1+exp(-sigmoid_slope x))-1, the
+ * ninth component mu, intensities multiplied by intensity_scale.
+ * Rectification exponent lambda (Eq. (11)).  max_patch: pyramid top N_max
+ * (power of two >= 4), 0 = the loop bound of Algorithm 1 (N < max(W, H));
+ * either way capped at the last level whose patch grid is non-empty. */
+typedef struct {
+    float nu1, nu2, nu3, sigmoid_slope, mu, intensity_scale, lambda;
+    int32_t max_patch;
+    int32_t precision;          /* dm_precision */
+    int32_t reserved[7];        /* must be 0 */
+} dm_params;
+
+/* One correspondence: atomic patch centre p = (x1, y1) in I, pixel
+ * p' = (x2, y2) in I', score s = the top-level value plus the pooled child
+ * values along the backtracking path (Eq. (14)). */
+typedef struct {
+    int32_t x1, y1, x2, y2;
+    float score;
+} dm_match;
+
+/* Geometry and workspace layout of one image pair.  Level l has patches on
+ * a lattice of gx[l] x gy[l] candidate centres ((2+4a, 2+4b) at l = 0,
+ * (4a, 4b) above), of which n_valid[l] exist (Eq. (7) with the boundary rule
+ * of Sec. 3.2); its correlation maps C_l have h[l] x w[l] entries, with
+ * h[0] = H', w[0] = W', h[l+1] = ceil(h[l]/2).
+ *
+ * Workspace contents after a match call (byte offsets from the workspace
+ * base, all 256-byte aligned):
+ *   off_cp[l]   l < lmax: pooled maps C'_l, float32 [gy][gx][h[l+1]][w[l+1]]
+ *               (entries of non-existing patches are undefined)
+ *   off_code[l] l < lmax: argmax codes of C'_l, uint8, same shape, value
+ *               3(m_y+1)+(m_x+1) of the first maximum (Eq. (9))
+ *   off_top     C_lmax, float32 [gy][gx][h[lmax]][w[lmax]]
+ *   off_u[l]    1 <= l < lmax: best backtracking score reaching each pooled
+ *               node of level l, float32, shape of C'_l, -inf if unreached
+ *   off_desc1/2 descriptors of I and I' (dm_match_images), float32 HWC
+ *   off_best    per atomic patch: packed best tuple (uint64)
+ *   off_cell    per 4x4 target cell: packed best tuple (uint64)
+ */
+typedef struct {
+    int32_t W1, H1, W2, H2;
+    int32_t lmax;              /* top level index; N_max = 4 << lmax        */
+    int32_t N_max;
+    int32_t n_atomic;          /* |G_4| = floor(W/4) * floor(H/4)            */
+    int32_t max_matches;       /* sufficient output capacity (= n_atomic)    */
+    int32_t precision;
+    int32_t gx[DM_MAX_LEVELS], gy[DM_MAX_LEVELS], n_valid[DM_MAX_LEVELS];
+    int32_t h[DM_MAX_LEVELS + 1], w[DM_MAX_LEVELS + 1];
+    uint64_t off_cp[DM_MAX_LEVELS], off_code[DM_MAX_LEVELS], off_u[DM_MAX_LEVELS];
+    uint64_t off_top, off_desc1, off_desc2, off_bf1, off_bf2, off_valid;
+    uint64_t off_best, off_cell, off_misc;
+    uint64_t workspace_bytes;
+} dm_plan_info;
+
+/* Fills *p with the defaults: nu1=0, nu2=nu3=1, sigmoid_slope=0.2, mu=0.1,
+ * intensity_scale=255, lambda=1.4, max_patch=0, precision=DM_FP32.
+ * Host only.  Errors: DM_ERR_INVALID_ARG if p is null. */
+dm_status dm_default_params(dm_params* p);
+
+/* Plans the pyramid of an I (W1 x H1) / I' (W2 x H2) pair: levels, patch
+ * grids, map sizes (Algorithm 1 with the boundary rule of Sec. 3.2) and the
+ * workspace layout, written to *out.  Host only; touches no device.
+ * Errors: DM_ERR_INVALID_ARG (null pointer, parameter out of range,
+ * max_patch not a power of two >= 4), DM_ERR_SHAPE (W1 or H1 < 4, W2 or
+ * H2 < 1, any size above DM_MAX_DIM). */
+dm_status dm_plan(const dm_params* prm, int W1, int H1, int W2, int H2, dm_plan_info* out);
+
+/* Per-pixel descriptors of one image (Sec. 3.2, "Pixel descriptor"):
+ * img is W x H float32 with leading dimension ld; desc receives H x W x 9
+ * float32 (unit l2 norm, non-negative).  Errors: DM_ERR_INVALID_ARG,
+ * DM_ERR_SHAPE (W or H < 1 or > DM_MAX_DIM, ld < W), DM_ERR_HIP. */
+dm_status dm_descriptors(const float* img, int W, int H, int ld, const dm_params* prm,
+                         float* desc, hipStream_t stream);
+
+/* Matches two descriptor fields (d1: H1 x W1 x 9, d2: H2 x W2 x 9, float32;
+ * float64 when prm->precision == DM_FP64): bottom correlation (Eq. (4)),
+ * pyramid levels (Eq. (12)), backtracking from every top-level entry with
+ * merging (Eq. (15)) and reciprocal verification (Eq. (16)).  Writes the
+ * matches, sorted by (y1, x1), to out[0 .. *n_out) and their count to the
+ * DEVICE int n_out.  At most one match per atomic patch, so capacity >=
+ * plan.max_matches is always enough.  ws must hold plan.workspace_bytes
+ * bytes (256-byte aligned); it keeps the pyramid afterwards (see
+ * dm_plan_info).  Errors: DM_ERR_INVALID_ARG, DM_ERR_SHAPE,
+ * DM_ERR_WORKSPACE, DM_ERR_CAPACITY (capacity < plan.max_matches),
+ * DM_ERR_UNSUPPORTED, DM_ERR_HIP. */
+dm_status dm_match_descriptors(const void* d1, int W1, int H1, const void* d2, int W2, int H2,
+                               const dm_params* prm, void* ws, size_t ws_bytes,
+                               dm_match* out, int capacity, int* n_out, hipStream_t stream);
+
+/* dm_descriptors on both images (into the workspace), then
+ * dm_match_descriptors.  Same outputs and errors; FP64 is not available on
+ * this entry point (DM_ERR_UNSUPPORTED). */
+dm_status dm_match_images(const float* img1, int W1, int H1, int ld1,
+                          const float* img2, int W2, int H2, int ld2,
+                          const dm_params* prm, void* ws, size_t ws_bytes,
+                          dm_match* out, int capacity, int* n_out, hipStream_t stream);
+
+/* Per-stage timing (for benchmarks and profiling).  While enabled, every
+ * kernel launch the library makes is bracketed by two HIP events recorded on
+ * the stream of the call, so the measured time is that kernel's own time on
+ * that stream.  Enabling clears earlier records.  Records are process-wide.
+ * Errors: none (dm_timing_enable), DM_ERR_HIP (dm_timing_read). */
+typedef struct {
+    char name[40];       /* stage name, e.g. "corr_pool_bf16", "level", "backtrack" */
+    int32_t level;       /* pyramid level of the launch, -1 if none            */
+    int32_t count;       /* launches recorded                                  */
+    double total_ms;     /* summed event-measured duration                     */
+} dm_stage_time;
+
+dm_status dm_timing_enable(int on);
+
+/* Waits for the recorded events, then writes up to max aggregated entries
+ * (one per stage name and level, in first-launch order) to out and their
+ * number to *n (which may exceed max).  Host pointers. */
+dm_status dm_timing_read(dm_stage_time* out, int max, int* n);
+
+/* Text of a status code (static storage). */
+const char* dm_status_string(dm_status s);
+
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char* dm_last_error(void);
+
+/* Library version string. */
+const char* dm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DM_H */

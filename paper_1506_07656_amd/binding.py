@@ -1,0 +1,273 @@
+"""ctypes binding of libdm.so.  Argument marshalling only: every stage of the
+matching runs in the library's HIP kernels; torch supplies device memory and
+the current stream.  There is no fallback: if the library is missing, every
+call raises."""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_float, c_int, c_int32, c_size_t, c_uint64, c_void_p
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdm.so")
+
+DM_MAX_LEVELS = 16
+DM_FP32, DM_BF16, DM_FP64 = 0, 1, 2
+PRECISIONS = {"fp32": DM_FP32, "bf16": DM_BF16, "fp64": DM_FP64}
+STATUS = {0: "DM_OK", -1: "DM_ERR_INVALID_ARG", -2: "DM_ERR_SHAPE", -3: "DM_ERR_WORKSPACE",
+          -4: "DM_ERR_CAPACITY", -5: "DM_ERR_UNSUPPORTED", -6: "DM_ERR_HIP"}
+
+
+class DMError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{STATUS.get(status, status)}: {detail}")
+        self.status = status
+        self.detail = detail
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nu1", c_float), ("nu2", c_float), ("nu3", c_float), ("sigmoid_slope", c_float),
+                ("mu", c_float), ("intensity_scale", c_float), ("lam", c_float),
+                ("max_patch", c_int32), ("precision", c_int32), ("reserved", c_int32 * 7)]
+
+
+class Match(ctypes.Structure):
+    _fields_ = [("x1", c_int32), ("y1", c_int32), ("x2", c_int32), ("y2", c_int32), ("score", c_float)]
+
+
+_L = DM_MAX_LEVELS
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("W1", c_int32), ("H1", c_int32), ("W2", c_int32), ("H2", c_int32),
+                ("lmax", c_int32), ("N_max", c_int32), ("n_atomic", c_int32), ("max_matches", c_int32),
+                ("precision", c_int32),
+                ("gx", c_int32 * _L), ("gy", c_int32 * _L), ("n_valid", c_int32 * _L),
+                ("h", c_int32 * (_L + 1)), ("w", c_int32 * (_L + 1)),
+                ("off_cp", c_uint64 * _L), ("off_code", c_uint64 * _L), ("off_u", c_uint64 * _L),
+                ("off_top", c_uint64), ("off_desc1", c_uint64), ("off_desc2", c_uint64),
+                ("off_bf1", c_uint64), ("off_bf2", c_uint64), ("off_valid", c_uint64),
+                ("off_best", c_uint64), ("off_cell", c_uint64), ("off_misc", c_uint64),
+                ("workspace_bytes", c_uint64)]
+
+
+class StageTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("level", c_int32), ("count", c_int32), ("total_ms", ctypes.c_double)]
+
+
+# name -> (restype, argtypes); every symbol declared in include/dm.h.
+SIGNATURES = {
+    "dm_default_params": (c_int, [POINTER(Params)]),
+    "dm_plan": (c_int, [POINTER(Params), c_int, c_int, c_int, c_int, POINTER(PlanInfo)]),
+    "dm_descriptors": (c_int, [c_void_p, c_int, c_int, c_int, POINTER(Params), c_void_p, c_void_p]),
+    "dm_match_descriptors": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int, c_int, POINTER(Params),
+                                     c_void_p, c_size_t, c_void_p, c_int, c_void_p, c_void_p]),
+    "dm_match_images": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_int, c_int,
+                                POINTER(Params), c_void_p, c_size_t, c_void_p, c_int, c_void_p, c_void_p]),
+    "dm_timing_enable": (c_int, [c_int]),
+    "dm_timing_read": (c_int, [POINTER(StageTime), c_int, POINTER(c_int)]),
+    "dm_status_string": (c_char_p, [c_int]),
+    "dm_last_error": (c_char_p, []),
+    "dm_version": (c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1506_07656_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise DMError(status, lib().dm_last_error().decode())
+
+
+def params(**kw) -> Params:
+    """Library defaults overridden by keyword (nu1, nu2, nu3, sigmoid_slope, mu,
+    intensity_scale, lam, max_patch, precision in {'fp32','bf16','fp64'} or int)."""
+    p = Params()
+    _check(lib().dm_default_params(ctypes.byref(p)))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
+        if k == "lambda":
+            k = "lam"
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def plan(W1: int, H1: int, W2: int, H2: int, prm: Params | None = None) -> PlanInfo:
+    prm = prm or params()
+    out = PlanInfo()
+    _check(lib().dm_plan(ctypes.byref(prm), W1, H1, W2, H2, ctypes.byref(out)))
+    return out
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, ndim: int, name: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype or t.dim() != ndim:
+        raise ValueError(f"{name} must be {dtype} with {ndim} dims")
+    return t
+
+
+def workspace(pl: PlanInfo, device=None) -> torch.Tensor:
+    """A device byte tensor of the planned workspace size (256-byte aligned by
+    the caching allocator)."""
+    return torch.empty(int(pl.workspace_bytes), dtype=torch.uint8, device=device or "cuda")
+
+
+def descriptors(img: torch.Tensor, prm: Params | None = None) -> torch.Tensor:
+    """H x W float32 image in [0, 1] -> H x W x 9 descriptors."""
+    prm = prm or params()
+    img = _dev(img, torch.float32, 2, "img")
+    H, W = img.shape
+    out = torch.empty((H, W, 9), dtype=torch.float32, device=img.device)
+    _check(lib().dm_descriptors(c_void_p(img.data_ptr()), W, H, img.stride(0), ctypes.byref(prm),
+                                c_void_p(out.data_ptr()), _stream()))
+    return out
+
+
+def _matches_tensor(buf: torch.Tensor, n: int) -> torch.Tensor:
+    rec = buf[:n]
+    out = torch.empty((n, 5), dtype=torch.float64, device=buf.device)
+    out[:, :4] = rec[:, :4].to(torch.float64)
+    out[:, 4] = rec[:, 4].view(torch.float32).to(torch.float64)
+    return out
+
+
+def match_descriptors(d1: torch.Tensor, d2: torch.Tensor, prm: Params | None = None,
+                      ws: torch.Tensor | None = None, return_state: bool = False):
+    """Descriptors (H x W x 9 float32) -> matches (n x 5: x1, y1, x2, y2, score)."""
+    prm = prm or params()
+    d1 = _dev(d1, torch.float32, 3, "d1")
+    d2 = _dev(d2, torch.float32, 3, "d2")
+    H1, W1, _ = d1.shape
+    H2, W2, _ = d2.shape
+    pl = plan(W1, H1, W2, H2, prm)
+    ws = workspace(pl, d1.device) if ws is None else ws
+    buf = torch.empty((pl.max_matches, 5), dtype=torch.int32, device=d1.device)
+    n_out = torch.zeros(1, dtype=torch.int32, device=d1.device)
+    _check(lib().dm_match_descriptors(c_void_p(d1.contiguous().data_ptr()), W1, H1,
+                                      c_void_p(d2.contiguous().data_ptr()), W2, H2, ctypes.byref(prm),
+                                      c_void_p(ws.data_ptr()), ws.numel(), c_void_p(buf.data_ptr()),
+                                      pl.max_matches, c_void_p(n_out.data_ptr()), _stream()))
+    m = _matches_tensor(buf, int(n_out.item()))
+    return (m, ws, pl) if return_state else m
+
+
+def match_images(img1: torch.Tensor, img2: torch.Tensor, prm: Params | None = None,
+                 ws: torch.Tensor | None = None, return_state: bool = False):
+    """Two H x W float32 images in [0, 1] -> matches (n x 5: x1, y1, x2, y2, score)."""
+    prm = prm or params()
+    img1 = _dev(img1, torch.float32, 2, "img1")
+    img2 = _dev(img2, torch.float32, 2, "img2")
+    H1, W1 = img1.shape
+    H2, W2 = img2.shape
+    pl = plan(W1, H1, W2, H2, prm)
+    ws = workspace(pl, img1.device) if ws is None else ws
+    buf = torch.empty((pl.max_matches, 5), dtype=torch.int32, device=img1.device)
+    n_out = torch.zeros(1, dtype=torch.int32, device=img1.device)
+    _check(lib().dm_match_images(c_void_p(img1.data_ptr()), W1, H1, img1.stride(0),
+                                 c_void_p(img2.data_ptr()), W2, H2, img2.stride(0), ctypes.byref(prm),
+                                 c_void_p(ws.data_ptr()), ws.numel(), c_void_p(buf.data_ptr()),
+                                 pl.max_matches, c_void_p(n_out.data_ptr()), _stream()))
+    m = _matches_tensor(buf, int(n_out.item()))
+    return (m, ws, pl) if return_state else m
+
+
+class Matcher:
+    """Preallocated workspace and output buffers for repeated matching of
+    pairs of one size; run() only enqueues work on the current stream."""
+
+    def __init__(self, W1: int, H1: int, W2: int, H2: int, prm: Params | None = None, device="cuda"):
+        self.prm = prm or params()
+        self.plan = plan(W1, H1, W2, H2, self.prm)
+        self.shape = (W1, H1, W2, H2)
+        self.ws = workspace(self.plan, device)
+        self.buf = torch.empty((self.plan.max_matches, 5), dtype=torch.int32, device=device)
+        self.n_out = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def run_images(self, img1: torch.Tensor, img2: torch.Tensor):
+        W1, H1, W2, H2 = self.shape
+        assert tuple(img1.shape) == (H1, W1) and tuple(img2.shape) == (H2, W2)
+        _check(lib().dm_match_images(c_void_p(img1.data_ptr()), W1, H1, img1.stride(0),
+                                     c_void_p(img2.data_ptr()), W2, H2, img2.stride(0), ctypes.byref(self.prm),
+                                     c_void_p(self.ws.data_ptr()), self.ws.numel(), c_void_p(self.buf.data_ptr()),
+                                     self.plan.max_matches, c_void_p(self.n_out.data_ptr()), _stream()))
+
+    def run_descriptors(self, d1: torch.Tensor, d2: torch.Tensor):
+        W1, H1, W2, H2 = self.shape
+        assert d1.is_contiguous() and d2.is_contiguous()
+        _check(lib().dm_match_descriptors(c_void_p(d1.data_ptr()), W1, H1, c_void_p(d2.data_ptr()), W2, H2,
+                                          ctypes.byref(self.prm), c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                          c_void_p(self.buf.data_ptr()), self.plan.max_matches,
+                                          c_void_p(self.n_out.data_ptr()), _stream()))
+
+    def result(self) -> torch.Tensor:
+        """Matches of the last run (synchronises on the count)."""
+        return _matches_tensor(self.buf, int(self.n_out.item()))
+
+
+def workspace_views(ws: torch.Tensor, pl: PlanInfo) -> dict:
+    """Typed views of the pyramid a match call leaves in its workspace."""
+    fsz = 8 if pl.precision == DM_FP64 else 4
+    fdt = torch.float64 if pl.precision == DM_FP64 else torch.float32
+
+    def view(off, count, dtype, shape, esz):
+        return ws[off:off + count * esz].view(dtype).view(*shape)
+
+    levels = []
+    for lv in range(pl.lmax):
+        shp = (pl.gy[lv], pl.gx[lv], pl.h[lv + 1], pl.w[lv + 1])
+        n = shp[0] * shp[1] * shp[2] * shp[3]
+        d = dict(cp=view(pl.off_cp[lv], n, fdt, shp, fsz), code=view(pl.off_code[lv], n, torch.uint8, shp, 1))
+        if lv >= 1:
+            d["u"] = view(pl.off_u[lv], n, fdt, shp, fsz)
+        levels.append(d)
+    L = pl.lmax
+    tshp = (pl.gy[L], pl.gx[L], pl.h[L], pl.w[L])
+    top = view(pl.off_top, tshp[0] * tshp[1] * tshp[2] * tshp[3], fdt, tshp, fsz)
+    out = dict(levels=levels, top=top)
+    out["best"] = view(pl.off_best, pl.n_atomic, torch.int64, (pl.n_atomic,), 8)
+    out["desc1"] = view(pl.off_desc1, pl.H1 * pl.W1 * 9, fdt, (pl.H1, pl.W1, 9), fsz)
+    out["desc2"] = view(pl.off_desc2, pl.H2 * pl.W2 * 9, fdt, (pl.H2, pl.W2, 9), fsz)
+    return out
+
+
+def timing_enable(on: bool = True):
+    """Bracket every library kernel launch with HIP events on its stream."""
+    _check(lib().dm_timing_enable(1 if on else 0))
+
+
+def timing_read() -> list:
+    """[(name, level, count, total_ms)] aggregated since timing_enable()."""
+    n = c_int(0)
+    _check(lib().dm_timing_read(None, 0, ctypes.byref(n)))
+    arr = (StageTime * max(1, n.value))()
+    _check(lib().dm_timing_read(arr, n.value, ctypes.byref(n)))
+    return [(a.name.decode(), a.level, a.count, a.total_ms) for a in arr[:n.value]]
+
+
+def version() -> str:
+    return lib().dm_version().decode()

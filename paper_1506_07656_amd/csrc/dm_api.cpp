@@ -1,0 +1,190 @@
+// C-ABI entry points of libdm.so (declared in include/dm.h).  Every call
+// validates its arguments on the host, then enqueues the stages of the hot
+// path on the caller's stream; nothing here allocates device memory.
+#include <string.h>
+
+#include "dm_internal.h"
+
+namespace dm {
+const char* last_error_text();
+void clear_error();
+void timing_begin(const char* name, int level, hipStream_t s);
+void timing_end(hipStream_t s);
+}  // namespace dm
+
+using namespace dm;
+
+namespace {
+
+template <typename P>
+inline P* at(void* ws, uint64_t off) {
+    return reinterpret_cast<P*>(static_cast<char*>(ws) + off);
+}
+
+// Launches one stage (bracketed by timing events when timing is enabled).
+#define DM_LAUNCH(name, level, expr)                                  \
+    do {                                                              \
+        timing_begin((name), (level), s);                             \
+        const hipError_t e_ = (expr);                                 \
+        timing_end(s);                                                \
+        const dm_status st_ = check_hip(e_, (name));                  \
+        if (st_ != DM_OK) return st_;                                 \
+    } while (0)
+
+// Stages a1..a4 on descriptors d1, d2 (float32) already in device memory.
+dm_status run_match(const float* d1, const float* d2, const dm_plan_info& pi, const dm_params* prm, void* ws,
+                    bool have_bf16, dm_match* out, int* n_out, hipStream_t s) {
+    const Geom g = make_geom(pi);
+    const float lam = prm->lambda;
+    uint8_t* vt = at<uint8_t>(ws, pi.off_valid);
+    DM_LAUNCH("valid_init", -1, launch_valid_init(g, vt, s));
+    float* top = at<float>(ws, pi.off_top);
+    auto cp = [&](int l) { return at<float>(ws, pi.off_cp[l]); };
+    auto code = [&](int l) { return at<uint8_t>(ws, pi.off_code[l]); };
+    auto u = [&](int l) { return at<float>(ws, pi.off_u[l]); };
+    // a1: bottom correlation + rectification + pooled level 0.
+    if (pi.lmax == 0) {
+        DM_LAUNCH("corr_top", 0, launch_corr_top<float>(d1, d2, g, lam, top, s));
+    } else if (prm->precision == DM_BF16) {
+        uint16_t* b1 = at<uint16_t>(ws, pi.off_bf1);
+        uint16_t* b2 = at<uint16_t>(ws, pi.off_bf2);
+        if (!have_bf16) {
+            DM_LAUNCH("to_bf16", -1, launch_to_bf16(d1, pi.W1 * pi.H1, b1, s));
+            DM_LAUNCH("to_bf16", -1, launch_to_bf16(d2, pi.W2 * pi.H2, b2, s));
+        }
+        DM_LAUNCH("corr_pool_bf16", 0, launch_corr_pool_bf16(b1, b2, g, lam, cp(0), code(0), s));
+    } else {
+        DM_LAUNCH("corr_pool_f32", 0, launch_corr_pool_f32(d1, d2, g, lam, cp(0), code(0), s));
+    }
+    // a2: levels 1..lmax.
+    for (int l = 1; l <= pi.lmax; ++l)
+        DM_LAUNCH("level", l, launch_level<float>(l, cp(l - 1), vt, g, lam, l < pi.lmax ? cp(l) : nullptr,
+                                                  l < pi.lmax ? code(l) : nullptr, top, s));
+    // a3 + a4: backtracking, bottom reduction, reciprocal check, compaction.
+    uint64_t* best = at<uint64_t>(ws, pi.off_best);
+    uint64_t* cell = at<uint64_t>(ws, pi.off_cell);
+    DM_LAUNCH("fill", -1, launch_fill_u64(best, (size_t)pi.n_atomic, 0, s));
+    DM_LAUNCH("fill", -1, launch_fill_u64(cell, (size_t)((pi.H2 + 3) / 4) * ((pi.W2 + 3) / 4), 0, s));
+    if (pi.lmax == 0) {
+        DM_LAUNCH("top_reduce", 0, launch_top_reduce<float>(top, g, best, cell, s));
+    } else {
+        for (int l = pi.lmax; l >= 1; --l)
+            DM_LAUNCH("backtrack", l,
+                      launch_backtrack<float>(l, cp(l - 1), code(l - 1), l < pi.lmax ? u(l) : nullptr,
+                                              l < pi.lmax ? code(l) : nullptr, top, vt, g,
+                                              l >= 2 ? u(l - 1) : nullptr, best, cell, s));
+    }
+    DM_LAUNCH("finalize", -1, launch_finalize(best, cell, g, out, n_out, s));
+    return DM_OK;
+}
+
+dm_status check_ws(const dm_plan_info& pi, void* ws, size_t ws_bytes) {
+    if (!ws) return fail(DM_ERR_INVALID_ARG, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(DM_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < pi.workspace_bytes)
+        return fail(DM_ERR_WORKSPACE, "workspace holds %zu bytes, the plan needs %llu", ws_bytes,
+                    (unsigned long long)pi.workspace_bytes);
+    return DM_OK;
+}
+
+dm_status check_out(const dm_plan_info& pi, dm_match* out, int capacity, int* n_out) {
+    if (!out || !n_out) return fail(DM_ERR_INVALID_ARG, "output pointer is null");
+    if (capacity < pi.max_matches)
+        return fail(DM_ERR_CAPACITY, "capacity %d is below the %d matches one call can return", capacity,
+                    pi.max_matches);
+    return DM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dm_status dm_default_params(dm_params* p) {
+    clear_error();
+    if (!p) return fail(DM_ERR_INVALID_ARG, "params is null");
+    memset(p, 0, sizeof(*p));
+    p->nu1 = 0.f;
+    p->nu2 = 1.f;
+    p->nu3 = 1.f;
+    p->sigmoid_slope = 0.2f;
+    p->mu = 0.1f;
+    p->intensity_scale = 255.f;
+    p->lambda = 1.4f;
+    p->max_patch = 0;
+    p->precision = DM_FP32;
+    return DM_OK;
+}
+
+dm_status dm_plan(const dm_params* prm, int W1, int H1, int W2, int H2, dm_plan_info* out) {
+    clear_error();
+    return plan_pair(prm, W1, H1, W2, H2, out);
+}
+
+dm_status dm_descriptors(const float* img, int W, int H, int ld, const dm_params* prm, float* desc,
+                         hipStream_t stream) {
+    clear_error();
+    dm_status st = check_params(prm);
+    if (st != DM_OK) return st;
+    if (!img || !desc) return fail(DM_ERR_INVALID_ARG, "image or descriptor pointer is null");
+    if (W < 1 || H < 1 || W > DM_MAX_DIM || H > DM_MAX_DIM) return fail(DM_ERR_SHAPE, "image is %dx%d", W, H);
+    if (ld < W) return fail(DM_ERR_SHAPE, "leading dimension %d < width %d", ld, W);
+    const DescParams dp = make_desc_params(prm);
+    hipStream_t s = stream;
+    DM_LAUNCH("descriptor", -1, launch_descriptor(img, W, H, ld, dp, desc, nullptr, s));
+    return DM_OK;
+}
+
+dm_status dm_match_descriptors(const void* d1, int W1, int H1, const void* d2, int W2, int H2,
+                               const dm_params* prm, void* ws, size_t ws_bytes, dm_match* out, int capacity,
+                               int* n_out, hipStream_t stream) {
+    clear_error();
+    dm_plan_info pi;
+    dm_status st = plan_pair(prm, W1, H1, W2, H2, &pi);
+    if (st != DM_OK) return st;
+    if (!d1 || !d2) return fail(DM_ERR_INVALID_ARG, "descriptor pointer is null");
+    if ((st = check_ws(pi, ws, ws_bytes)) != DM_OK) return st;
+    if ((st = check_out(pi, out, capacity, n_out)) != DM_OK) return st;
+    if (prm->precision == DM_FP64) return fail(DM_ERR_UNSUPPORTED, "matching runs in FP32 or BF16");
+    return run_match((const float*)d1, (const float*)d2, pi, prm, ws, false, out, n_out, stream);
+}
+
+dm_status dm_match_images(const float* img1, int W1, int H1, int ld1, const float* img2, int W2, int H2, int ld2,
+                          const dm_params* prm, void* ws, size_t ws_bytes, dm_match* out, int capacity,
+                          int* n_out, hipStream_t stream) {
+    clear_error();
+    dm_plan_info pi;
+    dm_status st = plan_pair(prm, W1, H1, W2, H2, &pi);
+    if (st != DM_OK) return st;
+    if (!img1 || !img2) return fail(DM_ERR_INVALID_ARG, "image pointer is null");
+    if (ld1 < W1 || ld2 < W2) return fail(DM_ERR_SHAPE, "leading dimension below the width");
+    if ((st = check_ws(pi, ws, ws_bytes)) != DM_OK) return st;
+    if ((st = check_out(pi, out, capacity, n_out)) != DM_OK) return st;
+    if (prm->precision == DM_FP64) return fail(DM_ERR_UNSUPPORTED, "matching runs in FP32 or BF16");
+    const DescParams dp = make_desc_params(prm);
+    float* d1 = at<float>(ws, pi.off_desc1);
+    float* d2 = at<float>(ws, pi.off_desc2);
+    const bool bf = prm->precision == DM_BF16;
+    hipStream_t s = stream;
+    DM_LAUNCH("descriptor", -1, launch_descriptor(img1, W1, H1, ld1, dp, d1, bf ? at<uint16_t>(ws, pi.off_bf1) : nullptr, s));
+    DM_LAUNCH("descriptor", -1, launch_descriptor(img2, W2, H2, ld2, dp, d2, bf ? at<uint16_t>(ws, pi.off_bf2) : nullptr, s));
+    return run_match(d1, d2, pi, prm, ws, bf, out, n_out, stream);
+}
+
+const char* dm_status_string(dm_status s) {
+    switch (s) {
+        case DM_OK: return "ok";
+        case DM_ERR_INVALID_ARG: return "invalid argument";
+        case DM_ERR_SHAPE: return "unsupported shape";
+        case DM_ERR_WORKSPACE: return "workspace too small";
+        case DM_ERR_CAPACITY: return "output capacity too small";
+        case DM_ERR_UNSUPPORTED: return "unsupported mode";
+        case DM_ERR_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char* dm_last_error(void) { return last_error_text(); }
+
+const char* dm_version(void) { return "dm-mi355x 0.1"; }
+
+}  // extern "C"

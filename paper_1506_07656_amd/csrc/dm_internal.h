@@ -1,0 +1,94 @@
+// Internal declarations shared by the host side (planning, validation,
+// launches) and the HIP kernels of libdm.so.
+#pragma once
+
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+#include "dm.h"
+
+namespace dm {
+
+// Geometry of one pair as the kernels see it (passed by value).
+// Level l lattice: gx[l] x gy[l] centres; maps of C_l: h[l] x w[l].
+struct Geom {
+    int W1, H1, W2, H2;
+    int lmax;
+    int gx[DM_MAX_LEVELS], gy[DM_MAX_LEVELS];
+    int h[DM_MAX_LEVELS + 1], w[DM_MAX_LEVELS + 1];
+    int vstride;  // bytes per validity table (one per level and axis)
+};
+
+// Lattice index, at level l-1, of the child of lattice index `a` at level l
+// on the side s in {-1,+1} of one axis (Eq. (5): child centre = parent centre
+// + 2^l * s).  Level 0 centres are 2+4a, higher levels 4a.
+__host__ __device__ inline int child_index(int l, int a, int s) {
+    return l == 1 ? a + ((s - 1) >> 1) : a + s * (1 << (l - 2));
+}
+
+// Inverse of child_index: the parent (level l) of child index c (level l-1)
+// lying on side s of that parent.
+__host__ __device__ inline int parent_index(int l, int c, int s) {
+    return l == 1 ? c - ((s - 1) >> 1) : c - s * (1 << (l - 2));
+}
+
+// Validity table of level l and axis (0 = x, 1 = y) inside the workspace.
+__host__ __device__ inline const uint8_t* vtab(const uint8_t* base, const Geom& g, int l, int axis) {
+    return base + (size_t)(2 * l + axis) * g.vstride;
+}
+
+// Rectification R_lambda of Eq. (11) on a non-negative argument.
+__device__ inline float rect_pow(float x, float lam) {
+    return x > 0.f ? exp2f(lam * log2f(x)) : 0.f;
+}
+__device__ inline double rect_pow(double x, double lam) {
+    return x > 0.0 ? exp2(lam * log2(x)) : 0.0;
+}
+
+// Error reporting (thread-local text read back by dm_last_error).
+dm_status fail(dm_status s, const char* fmt, ...);
+dm_status check_hip(hipError_t e, const char* what);
+
+// Host planning (dm_plan.cpp).
+dm_status plan_pair(const dm_params* prm, int W1, int H1, int W2, int H2, dm_plan_info* out);
+dm_status check_params(const dm_params* prm);
+Geom make_geom(const dm_plan_info& pi);
+
+// Descriptor parameters with the Gaussian taps precomputed on the host.
+constexpr int kMaxRadius = 6;   // smoothing nu <= 2 (LDS budget of the descriptor kernel)
+struct DescParams {
+    float scale, slope, mu;
+    int r1, r2, r3;
+    float g1[2 * kMaxRadius + 1], g2[2 * kMaxRadius + 1], g3[2 * kMaxRadius + 1];
+};
+DescParams make_desc_params(const dm_params* prm);
+
+// Kernel launchers (each returns the launch status).
+hipError_t launch_valid_init(const Geom& g, uint8_t* vt, hipStream_t s);
+hipError_t launch_descriptor(const float* img, int W, int H, int ld, const DescParams& p,
+                             float* out, uint16_t* out_bf16, hipStream_t s);
+hipError_t launch_to_bf16(const float* d, int n_pix, uint16_t* out, hipStream_t s);
+hipError_t launch_corr_pool_f32(const float* d1, const float* d2, const Geom& g, float lam,
+                                float* cp, uint8_t* code, hipStream_t s);
+hipError_t launch_corr_pool_bf16(const uint16_t* d1, const uint16_t* d2, const Geom& g, float lam,
+                                 float* cp, uint8_t* code, hipStream_t s);
+template <typename T>
+hipError_t launch_corr_top(const T* d1, const T* d2, const Geom& g, T lam, T* top, hipStream_t s);
+template <typename T>
+hipError_t launch_corr_pool_ref(const T* d1, const T* d2, const Geom& g, T lam, T* cp,
+                                uint8_t* code, hipStream_t s);
+template <typename T>
+hipError_t launch_level(int l, const T* prev, const uint8_t* vt, const Geom& g, T lam, T* cp,
+                        uint8_t* code, T* top, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s);
+template <typename T>
+hipError_t launch_backtrack(int l, const T* cp_prev, const uint8_t* code_prev, const T* u_cur,
+                            const uint8_t* code_cur, const T* top, const uint8_t* vt, const Geom& g,
+                            T* u_prev, uint64_t* best, uint64_t* cell, hipStream_t s);
+template <typename T>
+hipError_t launch_top_reduce(const T* top, const Geom& g, uint64_t* best, uint64_t* cell,
+                             hipStream_t s);
+hipError_t launch_finalize(const uint64_t* best, const uint64_t* cell, const Geom& g,
+                           dm_match* out, int* n_out, hipStream_t s);
+
+}  // namespace dm

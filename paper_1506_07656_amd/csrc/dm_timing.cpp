@@ -1,0 +1,103 @@
+// Opt-in per-stage timing: HIP events recorded on the launch stream around
+// each library kernel launch, aggregated by (stage name, level).
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "dm_internal.h"
+
+namespace dm {
+namespace {
+
+struct Rec {
+    const char* name;
+    int level;
+    hipEvent_t a, b;
+};
+
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Rec> g_recs;
+std::vector<hipEvent_t> g_pool;
+int g_open = -1;
+
+hipEvent_t take_event() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void recycle_all() {
+    for (Rec& r : g_recs) {
+        if (r.a) g_pool.push_back(r.a);
+        if (r.b) g_pool.push_back(r.b);
+    }
+    g_recs.clear();
+    g_open = -1;
+}
+
+}  // namespace
+
+void timing_begin(const char* name, int level, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_on) return;
+    Rec r{name, level, take_event(), take_event()};
+    if (r.a) (void)hipEventRecord(r.a, s);
+    g_recs.push_back(r);
+    g_open = (int)g_recs.size() - 1;
+}
+
+void timing_end(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_on || g_open < 0) return;
+    if (g_recs[g_open].b) (void)hipEventRecord(g_recs[g_open].b, s);
+    g_open = -1;
+}
+
+}  // namespace dm
+
+using namespace dm;
+
+extern "C" {
+
+dm_status dm_timing_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    recycle_all();
+    g_on = on != 0;
+    return DM_OK;
+}
+
+dm_status dm_timing_read(dm_stage_time* out, int max, int* n) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::vector<dm_stage_time> agg;
+    for (const Rec& r : g_recs) {
+        if (!r.a || !r.b) continue;
+        if (hipEventSynchronize(r.b) != hipSuccess) return fail(DM_ERR_HIP, "event synchronize failed");
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return fail(DM_ERR_HIP, "event elapsed time failed");
+        dm_stage_time* t = nullptr;
+        for (dm_stage_time& x : agg)
+            if (x.level == r.level && !strncmp(x.name, r.name, sizeof(x.name))) t = &x;
+        if (!t) {
+            dm_stage_time z;
+            memset(&z, 0, sizeof(z));
+            strncpy(z.name, r.name, sizeof(z.name) - 1);
+            z.level = r.level;
+            agg.push_back(z);
+            t = &agg.back();
+        }
+        t->count += 1;
+        t->total_ms += ms;
+    }
+    if (n) *n = (int)agg.size();
+    for (int i = 0; i < (int)agg.size() && i < max && out; ++i) out[i] = agg[i];
+    return DM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,323 @@
+// Top-down correspondence extraction (Sec. 3.3, Eqs. (13)-(16)).
+//
+// The paper expands tuples (N, p, p', s) with B (Eq. (14)) from every
+// top-level entry and, whenever two tuples share (N, p, p'), keeps the higher
+// score.  Since the subtree below a tuple depends only on (N, p, p'), this is
+// the max-plus recursion, evaluated here densely level by level as a gather:
+//
+//   V_l(P, q)   best score of a tuple reaching node (l, P, q);  V_top = C_top
+//   U_{l-1}(c, r) = C'_{l-1}(c, r) + max_{i: P = c - 2^l o_i exists} V_l(P, r - o_i)
+//   V_{l-1}(c, x) = max { U_{l-1}(c, r) : 2r + m_{l-1}(c, r) = x }        (Eq. (13))
+//
+// U lives on the pooled grid (a quarter of V's), so only U and the argmax
+// codes are stored.  At the bottom U_0 is not written: each (c, r) gives the
+// atomic tuple (c, x = 2r + m, U_0) of M' (Eq. (15)), which is folded into
+// two tables of packed keys (score bits << 32 | inverted tie-break index):
+//   best[c]     BestAt(p):   max score, ties to the smallest (x'_y, x'_x)
+//   cell[c']    BestAt'(p'): max score over the 4x4 target cell, ties to the
+//               smallest (p_y, p_x, p'_y, p'_x)
+// Scores are sums of non-negative values, so their float bits order like the
+// floats and the packed 64-bit maxima are exact and order independent.
+#include "dm_internal.h"
+
+namespace dm {
+namespace {
+
+__device__ inline int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// Non-negative float <-> order-preserving code with 0 = "no tuple".
+__device__ inline uint32_t enc(float v) { return __float_as_uint(v) + 1u; }
+__device__ inline float dec(uint32_t e) { return __uint_as_float(e - 1u); }
+
+struct BtArgs {
+    int l;                       // the step reads level l and produces level l-1
+    int gxp, gyp, gxc, gyc;      // parent (level l) and child (level l-1) lattices
+    int h, w;                    // child pooled grid = maps of level l (h_l x w_l)
+    int hu, wu;                  // U_l grid (h_{l+1} x w_{l+1}); unused at the top
+    int is_top, is_bottom;
+    int TR, TC, CB;              // tile rows, cols, children per block
+    int n_cblk, n_rt;
+    int cy0, cx0, ncy, ncx;      // cell-table window parameters (bottom only)
+    int W2, cw;                  // target width, cells per target row
+};
+
+__global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __restrict__ cp_prev,
+                                                   const uint8_t* __restrict__ code_prev,
+                                                   const float* __restrict__ u_cur,
+                                                   const uint8_t* __restrict__ code_cur,
+                                                   const float* __restrict__ top, const uint8_t* __restrict__ vt,
+                                                   Geom g, float* __restrict__ u_prev,
+                                                   unsigned long long* __restrict__ best,
+                                                   unsigned long long* __restrict__ cell) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int T = a.TR * a.TC;
+    uint32_t* sV = (uint32_t*)smem_raw;                                   // [CB][4][TR][TC]
+    unsigned long long* sBest = (unsigned long long*)(sV + 4 * a.CB * T);  // [CB]
+    unsigned long long* sCell = sBest + a.CB;                               // [ncy][ncx]
+    const int bid = blockIdx.x;
+    const int cblk = bid % a.n_cblk, rest = bid / a.n_cblk;
+    const int R0 = (rest % a.n_rt) * a.TR, C0 = (rest / a.n_rt) * a.TC;
+    const uint8_t *vxp = vtab(vt, g, a.l, 0), *vyp = vtab(vt, g, a.l, 1);
+    const uint8_t *vxc = vtab(vt, g, a.l - 1, 0), *vyc = vtab(vt, g, a.l - 1, 1);
+    const int tid = threadIdx.x;
+
+    // Phase 1: V_l of the up-to-4 parents of each child, on the shifted tile.
+    if (a.is_top) {
+        for (int e = tid; e < 4 * a.CB * T; e += 256) {
+            const int ks = e / T, rem = e - ks * T;
+            const int k = ks >> 2, side = ks & 3;
+            const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;  // o_i of Eq. (5), i = side
+            const int c = cblk * a.CB + k;
+            uint32_t v = 0;
+            if (c < a.gxc * a.gyc) {
+                const int cb = c / a.gxc, ca = c - cb * a.gxc;
+                const int pb = parent_index(a.l, cb, sy), pa = parent_index(a.l, ca, sx);
+                const int qy = R0 + rem / a.TC - sy, qx = C0 + rem % a.TC - sx;
+                if (pb >= 0 && pb < a.gyp && pa >= 0 && pa < a.gxp && vxp[pa] && vyp[pb] && qy >= 0 && qy < a.h &&
+                    qx >= 0 && qx < a.w)
+                    v = enc(top[(((size_t)pb * a.gxp + pa) * a.h + qy) * a.w + qx]);
+            }
+            sV[e] = v;
+        }
+    } else {
+        for (int e = tid; e < 4 * a.CB * T; e += 256) sV[e] = 0u;
+        __syncthreads();
+        // U_l entries r' whose argmax 2r' + m can land in this side's q-range
+        // [q0, q0 + TR): r' in [floor(q0/2), floor((q0 + TR)/2)].
+        const int RH = a.TR / 2 + 2, RWd = a.TC / 2 + 2;
+        for (int e = tid; e < 4 * a.CB * RH * RWd; e += 256) {
+            const int ks = e / (RH * RWd), rem = e - ks * (RH * RWd);
+            const int k = ks >> 2, side = ks & 3;
+            const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;
+            const int c = cblk * a.CB + k;
+            if (c >= a.gxc * a.gyc) continue;
+            const int cb = c / a.gxc, ca = c - cb * a.gxc;
+            const int pb = parent_index(a.l, cb, sy), pa = parent_index(a.l, ca, sx);
+            if (!(pb >= 0 && pb < a.gyp && pa >= 0 && pa < a.gxp && vxp[pa] && vyp[pb])) continue;
+            const int qy0 = R0 - sy, qx0 = C0 - sx;
+            const int ry = floordiv(qy0, 2) + rem / RWd, rx = floordiv(qx0, 2) + rem % RWd;
+            if (ry > floordiv(qy0 + a.TR, 2) || rx > floordiv(qx0 + a.TC, 2)) continue;
+            if (ry < 0 || ry >= a.hu || rx < 0 || rx >= a.wu) continue;
+            const size_t o = (((size_t)pb * a.gxp + pa) * a.hu + ry) * a.wu + rx;
+            const float u = u_cur[o];
+            if (!(u >= 0.f)) continue;                       // node not reached
+            const int m = code_cur[o];
+            const int qy = 2 * ry + m / 3 - 1, qx = 2 * rx + m % 3 - 1;
+            const int ty = qy - qy0, tx = qx - qx0;   // tile index of r = q + o_i
+            if (ty < 0 || ty >= a.TR || tx < 0 || tx >= a.TC) continue;
+            atomicMax(&sV[(ks * a.TR + ty) * a.TC + tx], enc(u));
+        }
+    }
+    if (a.is_bottom) {
+        for (int e = tid; e < a.CB; e += 256) sBest[e] = 0ull;
+        for (int e = tid; e < a.ncy * a.ncx; e += 256) sCell[e] = 0ull;
+    }
+    __syncthreads();
+
+    // Phase 2: U_{l-1}(c, r) = C'_{l-1}(c, r) + max over parents.
+    const int cyb = floordiv(2 * R0 - 1, 4), cxb = floordiv(2 * C0 - 1, 4);
+    for (int e = tid; e < a.CB * T; e += 256) {
+        const int k = e / T, rem = e - k * T;
+        const int ty = rem / a.TC, tx = rem - ty * a.TC;
+        const int c = cblk * a.CB + k, ry = R0 + ty, rx = C0 + tx;
+        if (c >= a.gxc * a.gyc || ry >= a.h || rx >= a.w) continue;
+        const int cb = c / a.gxc, ca = c - cb * a.gxc;
+        if (!(vxc[ca] && vyc[cb])) continue;
+        uint32_t vb = 0;
+#pragma unroll
+        for (int side = 0; side < 4; ++side) vb = max(vb, sV[((k * 4 + side) * a.TR + ty) * a.TC + tx]);
+        const size_t o = (((size_t)cb * a.gxc + ca) * a.h + ry) * a.w + rx;
+        if (!a.is_bottom) {
+            u_prev[o] = vb ? cp_prev[o] + dec(vb) : -INFINITY;
+            continue;
+        }
+        if (!vb) continue;
+        const float u = cp_prev[o] + dec(vb);
+        const int m = code_prev[o];
+        const int xy = 2 * ry + m / 3 - 1, xx = 2 * rx + m % 3 - 1;
+        const unsigned long long hi = (unsigned long long)__float_as_uint(u) << 32;
+        atomicMax(&sBest[k], hi | (0xFFFFFFFFull - (uint32_t)(xy * a.W2 + xx)));
+        const unsigned long long kc = hi | (0xFFFFFFFFull - (uint32_t)(c * 16 + (xy & 3) * 4 + (xx & 3)));
+        atomicMax(&sCell[((xy >> 2) - cyb) * a.ncx + ((xx >> 2) - cxb)], kc);
+    }
+    if (a.is_bottom) {
+        __syncthreads();
+        for (int e = tid; e < a.CB; e += 256) {
+            const int c = cblk * a.CB + e;
+            if (c < a.gxc * a.gyc && sBest[e]) atomicMax(&best[c], sBest[e]);
+        }
+        for (int e = tid; e < a.ncy * a.ncx; e += 256) {
+            const unsigned long long v = sCell[e];
+            if (!v) continue;
+            const int cy = cyb + e / a.ncx, cx = cxb + e % a.ncx;
+            atomicMax(&cell[(size_t)cy * a.cw + cx], v);
+        }
+    }
+}
+
+// A pyramid whose top is the bottom level: M' = every (p, q) of C_top.
+__global__ void k_top_reduce(const float* __restrict__ top, Geom g, unsigned long long* __restrict__ best,
+                             unsigned long long* __restrict__ cell) {
+    const size_t n = (size_t)g.gx[0] * g.gy[0] * g.H2 * g.W2;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int xx = i % g.W2, xy = (i / g.W2) % g.H2;
+    const int c = i / ((size_t)g.W2 * g.H2);
+    const unsigned long long hi = (unsigned long long)__float_as_uint(top[i]) << 32;
+    atomicMax(&best[c], hi | (0xFFFFFFFFull - (uint32_t)(xy * g.W2 + xx)));
+    atomicMax(&cell[(size_t)(xy >> 2) * ((g.W2 + 3) / 4) + (xx >> 2)],
+              hi | (0xFFFFFFFFull - (uint32_t)(c * 16 + (xy & 3) * 4 + (xx & 3))));
+}
+
+// Reciprocal verification (Eq. (16)) and compaction in patch order (y1, x1).
+__global__ __launch_bounds__(1024) void k_finalize(const unsigned long long* __restrict__ best,
+                                                   const unsigned long long* __restrict__ cell, Geom g,
+                                                   dm_match* __restrict__ out, int* __restrict__ n_out) {
+    __shared__ int wsum[16];
+    __shared__ int base;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int gx0 = g.gx[0], natom = g.gx[0] * g.gy[0], cw = (g.W2 + 3) / 4;
+    if (tid == 0) base = 0;
+    __syncthreads();
+    for (int start = 0; start < natom; start += 1024) {
+        const int j = start + tid;
+        int flag = 0;
+        dm_match m;
+        if (j < natom) {
+            const unsigned long long key = best[j];
+            if (key) {
+                const uint32_t xi = 0xFFFFFFFFu - (uint32_t)key;
+                const int xy = xi / g.W2, xx = xi % g.W2;
+                const unsigned long long expect =
+                    (key & 0xFFFFFFFF00000000ull) | (0xFFFFFFFFull - (uint32_t)(j * 16 + (xy & 3) * 4 + (xx & 3)));
+                flag = cell[(size_t)(xy >> 2) * cw + (xx >> 2)] == expect;
+                m.x1 = 2 + 4 * (j % gx0);
+                m.y1 = 2 + 4 * (j / gx0);
+                m.x2 = xx;
+                m.y2 = xy;
+                m.score = __uint_as_float((uint32_t)(key >> 32));
+            }
+        }
+        const unsigned long long mask = __ballot(flag);
+        const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+        if (lane == 0) wsum[wave] = __popcll(mask);
+        __syncthreads();
+        int off = base;
+        for (int w = 0; w < wave; ++w) off += wsum[w];
+        if (flag) out[off + rank] = m;
+        __syncthreads();
+        if (tid == 0) {
+            int tot = 0;
+            for (int w = 0; w < 16; ++w) tot += wsum[w];
+            base += tot;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *n_out = base;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Validity of each level's lattice along x and y (Eq. (7) with the boundary
+// rule): level 0 is complete; an index exists above when one of its two
+// children along that axis exists.  The grid of a level is the product of
+// its two axes.
+__global__ __launch_bounds__(1024) void k_valid_init(Geom g, uint8_t* __restrict__ vt) {
+    __shared__ uint8_t cur[2][DM_MAX_DIM / 4 + 2], prv[2][DM_MAX_DIM / 4 + 2];
+    for (int l = 0; l <= g.lmax; ++l) {
+        for (int axis = 0; axis < 2; ++axis) {
+            const int n = axis ? g.gy[l] : g.gx[l];
+            const int np = l ? (axis ? g.gy[l - 1] : g.gx[l - 1]) : 0;
+            for (int a = threadIdx.x; a < n; a += blockDim.x) {
+                uint8_t v = 1;
+                if (l) {
+                    const int c0 = child_index(l, a, -1), c1 = child_index(l, a, 1);
+                    v = (c0 >= 0 && c0 < np && prv[axis][c0]) || (c1 >= 0 && c1 < np && prv[axis][c1]);
+                }
+                cur[axis][a] = v;
+                vt[(size_t)(2 * l + axis) * g.vstride + a] = v;
+            }
+        }
+        __syncthreads();
+        for (int axis = 0; axis < 2; ++axis) {
+            const int n = axis ? g.gy[l] : g.gx[l];
+            for (int a = threadIdx.x; a < n; a += blockDim.x) prv[axis][a] = cur[axis][a];
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+template <>
+hipError_t launch_backtrack<float>(int l, const float* cp_prev, const uint8_t* code_prev, const float* u_cur,
+                                   const uint8_t* code_cur, const float* top, const uint8_t* vt, const Geom& g,
+                                   float* u_prev, uint64_t* best, uint64_t* cell, hipStream_t s) {
+    BtArgs a;
+    a.l = l;
+    a.gxp = g.gx[l];
+    a.gyp = g.gy[l];
+    a.gxc = g.gx[l - 1];
+    a.gyc = g.gy[l - 1];
+    a.h = g.h[l];
+    a.w = g.w[l];
+    a.hu = g.h[l + 1];
+    a.wu = g.w[l + 1];
+    a.is_top = (l == g.lmax);
+    a.is_bottom = (l == 1);
+    a.TC = a.w < 128 ? a.w : 128;
+    a.TR = 1024 / a.TC;
+    if (a.TR > a.h) a.TR = a.h;
+    if (a.TR < 1) a.TR = 1;
+    a.CB = 1024 / (a.TR * a.TC);
+    if (a.CB < 1) a.CB = 1;
+    if (a.CB > 64) a.CB = 64;
+    const int nc = a.gxc * a.gyc;
+    a.n_cblk = (nc + a.CB - 1) / a.CB;
+    a.n_rt = (a.h + a.TR - 1) / a.TR;
+    const int n_ct = (a.w + a.TC - 1) / a.TC;
+    a.W2 = g.W2;
+    a.cw = (g.W2 + 3) / 4;
+    a.ncy = a.TR / 2 + 2;
+    a.ncx = a.TC / 2 + 2;
+    a.cy0 = a.cx0 = 0;
+    const size_t smem = (size_t)4 * a.CB * a.TR * a.TC * sizeof(uint32_t) +
+                        (a.is_bottom ? ((size_t)a.CB + (size_t)a.ncy * a.ncx) * 8 : 0);
+    const dim3 grid(a.n_cblk * a.n_rt * n_ct);
+    hipLaunchKernelGGL(k_backtrack, grid, dim3(256), smem, s, a, cp_prev, code_prev, u_cur, code_cur, top, vt, g,
+                       u_prev, (unsigned long long*)best, (unsigned long long*)cell);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t launch_top_reduce<float>(const float* top, const Geom& g, uint64_t* best, uint64_t* cell,
+                                    hipStream_t s) {
+    const size_t n = (size_t)g.gx[0] * g.gy[0] * g.H2 * g.W2;
+    hipLaunchKernelGGL(k_top_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, top, g,
+                       (unsigned long long*)best, (unsigned long long*)cell);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const uint64_t* best, const uint64_t* cell, const Geom& g, dm_match* out, int* n_out,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, (const unsigned long long*)best,
+                       (const unsigned long long*)cell, g, out, n_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (unsigned long long*)p, n,
+                       (unsigned long long)v);
+    return hipGetLastError();
+}
+
+hipError_t launch_valid_init(const Geom& g, uint8_t* vt, hipStream_t s) {
+    hipLaunchKernelGGL(k_valid_init, dim3(1), dim3(1024), 0, s, g, vt);
+    return hipGetLastError();
+}
+
+}  // namespace dm

@@ -1,0 +1,353 @@
+// Bottom level of the pyramid (Sec. 3.2, Eqs. (3)-(4), Algorithm 1):
+//   A_0(p, q) = 1/16 sum_{4x4 offsets d} <D1[p+d], D2[q+d]>   (D2 = 0 outside I')
+//   C_0 = max(A_0, 0)^lambda,  C'_0 = (S o P)(C_0) with argmax codes (Eqs. (8)-(9)).
+//
+// The correlation is an implicit GEMM on the matrix cores: M = atomic
+// patches, N = target positions, K = 16 offsets x 9 channels.  The K order is
+// chosen so that each 16-lane group of a wave owns one row of the 4x4 patch:
+// its K slice is 4 consecutive pixels x channels, i.e. one contiguous run in
+// the HWC descriptor layout for both operands.  Patch fragments stay in
+// registers for the whole block; the target tile sits in LDS.
+//
+// Epilogue: the 3x3/stride-2 max-pool with its first-maximum argmax and the
+// rectification are fused, so C_0 itself is never written.  Because x^lambda
+// is increasing on [0, inf), the pool runs on max(A, 0) and only the pooled
+// value is raised to lambda.
+//
+// Block = 4 waves; each wave owns 2 M-tiles of 16 patches (128 patches per
+// block).  A block covers TR pooled rows x TC pooled columns: per pooled row
+// it needs A on the 3 rows 2r-1..2r+1, and on the 32 positions
+// 2C0-1 .. 2C0+30 (two 16-wide N-tiles), which give TC = 15 pooled columns.
+#include "dm_internal.h"
+
+namespace dm {
+namespace {
+
+constexpr int MT = 2;                // M-tiles (16 patches) per wave
+constexpr int WAVES = 4;
+constexpr int PT = 16 * MT * WAVES;  // patches per block
+constexpr int TR = 8;                // pooled rows per block
+constexpr int TC = 15;               // pooled columns per block
+constexpr int NPOS = 32;             // A positions per A-row (2 N-tiles)
+constexpr int ARS = 2 * TR + 1;      // A-rows per block
+constexpr int D2R = 2 * TR + 4;      // target tile rows (A-rows + patch height - 1)
+constexpr int D2C = NPOS + 3;        // target tile columns
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+struct PoolArgs {
+    int natom, n0x, W1, W2, H2, h1, w1;
+    int n_ptiles, n_rtiles;
+};
+
+// Fused pool + rectify + store of pooled row r from the three staged A-rows.
+// sAw: this wave's staging [16*MT patches][3 slots][NPOS].
+__device__ inline void pool_row(const float (*sAw)[3][NPOS], int ia, int R0, int C0, int pbase,
+                                const PoolArgs& a, float lam, float* __restrict__ cp,
+                                uint8_t* __restrict__ code) {
+    const int lane = threadIdx.x & 63;
+    const int n = lane & 15, grp = lane >> 4;
+    const int r = R0 + ia / 2 - 1;
+    const int c = C0 + n;
+    if (n >= TC || r >= a.h1 || c >= a.w1) return;
+#pragma unroll
+    for (int pp = 0; pp < 4 * MT; ++pp) {
+        const int lp = grp + 4 * pp;
+        const int j = pbase + lp;
+        if (j >= a.natom) continue;
+        float best = -1.f;
+        int bk = 0;
+#pragma unroll
+        for (int my = -1; my <= 1; ++my) {
+            const int y = 2 * r + my;
+            if (y < 0 || y >= a.H2) continue;
+            const int slot = (ia - 1 + my) % 3;
+#pragma unroll
+            for (int mx = -1; mx <= 1; ++mx) {
+                const int x = 2 * c + mx;
+                if (x < 0 || x >= a.W2) continue;
+                const float v = sAw[lp][slot][2 * n + 1 + mx];
+                if (v > best) {
+                    best = v;
+                    bk = 3 * (my + 1) + (mx + 1);
+                }
+            }
+        }
+        const size_t o = ((size_t)j * a.h1 + r) * a.w1 + c;
+        cp[o] = rect_pow(best, lam);
+        code[o] = (uint8_t)bk;
+    }
+}
+
+__device__ inline void block_coords(const PoolArgs& a, int& pt, int& R0, int& C0) {
+    const int bid = blockIdx.x;
+    pt = bid % a.n_ptiles;
+    const int rest = bid / a.n_ptiles;
+    R0 = (rest % a.n_rtiles) * TR;
+    C0 = (rest / a.n_rtiles) * TC;
+}
+
+__global__ __launch_bounds__(256, 2) void k_corr_pool_f32(const float* __restrict__ d1,
+                                                          const float* __restrict__ d2, PoolArgs a,
+                                                          float lam, float* __restrict__ cp,
+                                                          uint8_t* __restrict__ code) {
+    __shared__ float sD2[D2R * D2C * 9];
+    __shared__ float sA[WAVES][16 * MT][3][NPOS];
+    int pt, R0, C0;
+    block_coords(a, pt, R0, C0);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = lane & 15, grp = lane >> 4;
+    const int pbase = pt * PT + wave * 16 * MT;
+
+    // Patch fragments: lane (n, grp) holds row grp of the 4x4 patch of patch
+    // pbase + 16 mt + n: 4 pixels x 9 channels, contiguous in D1.
+    float fa[MT][36];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int j = pbase + mt * 16 + n;
+        if (j < a.natom) {
+            const int b = j / a.n0x, aa = j - b * a.n0x;
+            const float* src = d1 + ((size_t)(4 * b + grp) * a.W1 + 4 * aa) * 9;
+#pragma unroll
+            for (int t = 0; t < 36; ++t) fa[mt][t] = src[t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < 36; ++t) fa[mt][t] = 0.f;
+        }
+    }
+    // Target tile: rows 2R0-3 .. 2R0+2TR, columns 2C0-3 .. 2C0+NPOS-1, zero outside I'.
+    const int ybase = 2 * R0 - 3, xbase = 2 * C0 - 3;
+    for (int e = tid; e < D2R * D2C * 9; e += 256) {
+        const int row = e / (D2C * 9), rem = e - row * (D2C * 9);
+        const int y = ybase + row, x = xbase + rem / 9, ch = rem % 9;
+        sD2[e] = (y >= 0 && y < a.H2 && x >= 0 && x < a.W2) ? d2[((size_t)y * a.W2 + x) * 9 + ch] : 0.f;
+    }
+    __syncthreads();
+
+    for (int ia = 0; ia < ARS; ++ia) {
+        const int slot = ia % 3;
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const float* bs = sD2 + ((ia + grp) * D2C + 16 * nt + n) * 9;
+            float fb[36];
+#pragma unroll
+            for (int t = 0; t < 36; ++t) fb[t] = bs[t];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int t = 0; t < 36; ++t) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[mt][t], fb[t], acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    sA[wave][mt * 16 + 4 * grp + r][slot][16 * nt + n] = fmaxf(acc[r] * 0.0625f, 0.f);
+            }
+        }
+        if (ia >= 2 && !(ia & 1)) {
+            __syncthreads();
+            pool_row(sA[wave], ia, R0, C0, pbase, a, lam, cp, code);
+            __syncthreads();
+        }
+    }
+}
+
+__device__ inline bf8 load_bf8(const uint32_t* p) {
+    union {
+        uint32_t u[4];
+        bf8 v;
+    } x;
+    x.u[0] = p[0];
+    x.u[1] = p[1];
+    x.u[2] = p[2];
+    x.u[3] = p[3];
+    return x.v;
+}
+
+// BF16 variant: descriptors stored as H x W x 10 bf16 (9 channels + a zero),
+// so each 16-lane group's K slice is 4 pixels x 10 = 40 values = 5 steps of
+// the 16x16x32 MFMA (K = 160, of which 16 are zero pads).
+__global__ __launch_bounds__(256, 2) void k_corr_pool_bf16(const uint16_t* __restrict__ d1,
+                                                           const uint16_t* __restrict__ d2, PoolArgs a,
+                                                           float lam, float* __restrict__ cp,
+                                                           uint8_t* __restrict__ code) {
+    __shared__ uint32_t sD2[D2R * D2C * 5];  // bf16 pairs
+    __shared__ float sA[WAVES][16 * MT][3][NPOS];
+    int pt, R0, C0;
+    block_coords(a, pt, R0, C0);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = lane & 15, grp = lane >> 4;
+    const int pbase = pt * PT + wave * 16 * MT;
+
+    bf8 fa[MT][5];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int j = pbase + mt * 16 + n;
+        uint32_t tmp[20];
+        if (j < a.natom) {
+            const int b = j / a.n0x, aa = j - b * a.n0x;
+            const uint32_t* src = (const uint32_t*)(d1 + ((size_t)(4 * b + grp) * a.W1 + 4 * aa) * 10);
+#pragma unroll
+            for (int t = 0; t < 20; ++t) tmp[t] = src[t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < 20; ++t) tmp[t] = 0u;
+        }
+#pragma unroll
+        for (int s = 0; s < 5; ++s) fa[mt][s] = load_bf8(tmp + 4 * s);
+    }
+    const int ybase = 2 * R0 - 3, xbase = 2 * C0 - 3;
+    const uint32_t* d2u = (const uint32_t*)d2;
+    for (int e = tid; e < D2R * D2C * 5; e += 256) {
+        const int row = e / (D2C * 5), rem = e - row * (D2C * 5);
+        const int y = ybase + row, x = xbase + rem / 5, pr = rem % 5;
+        sD2[e] = (y >= 0 && y < a.H2 && x >= 0 && x < a.W2) ? d2u[((size_t)y * a.W2 + x) * 5 + pr] : 0u;
+    }
+    __syncthreads();
+
+    for (int ia = 0; ia < ARS; ++ia) {
+        const int slot = ia % 3;
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const uint32_t* bs = sD2 + ((ia + grp) * D2C + 16 * nt + n) * 5;
+            bf8 fb[5];
+#pragma unroll
+            for (int s = 0; s < 5; ++s) fb[s] = load_bf8(bs + 4 * s);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < 5; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[mt][s], fb[s], acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    sA[wave][mt * 16 + 4 * grp + r][slot][16 * nt + n] = fmaxf(acc[r] * 0.0625f, 0.f);
+            }
+        }
+        if (ia >= 2 && !(ia & 1)) {
+            __syncthreads();
+            pool_row(sA[wave], ia, R0, C0, pbase, a, lam, cp, code);
+            __syncthreads();
+        }
+    }
+}
+
+PoolArgs make_pool_args(const Geom& g, int& nblocks) {
+    PoolArgs a;
+    a.natom = g.gx[0] * g.gy[0];
+    a.n0x = g.gx[0];
+    a.W1 = g.W1;
+    a.W2 = g.W2;
+    a.H2 = g.H2;
+    a.h1 = g.h[1];
+    a.w1 = g.w[1];
+    a.n_ptiles = (a.natom + PT - 1) / PT;
+    a.n_rtiles = (a.h1 + TR - 1) / TR;
+    const int n_ctiles = (a.w1 + TC - 1) / TC;
+    nblocks = a.n_ptiles * a.n_rtiles * n_ctiles;
+    return a;
+}
+
+// Straightforward kernels (thread per output, direct dot products) for the
+// FP64 instantiation and for a pyramid whose top is the bottom level.
+template <typename T>
+__device__ inline T atomic_score(const T* __restrict__ d1, const T* __restrict__ d2, const Geom& g, int b,
+                                 int aa, int y, int x) {
+    T acc = 0;
+    for (int dy = -2; dy <= 1; ++dy) {
+        const int yy = y + dy;
+        if (yy < 0 || yy >= g.H2) continue;
+        for (int dx = -2; dx <= 1; ++dx) {
+            const int xx = x + dx;
+            if (xx < 0 || xx >= g.W2) continue;
+            const T* p = d1 + ((size_t)(2 + 4 * b + dy) * g.W1 + 2 + 4 * aa + dx) * 9;
+            const T* q = d2 + ((size_t)yy * g.W2 + xx) * 9;
+            for (int c = 0; c < 9; ++c) acc += p[c] * q[c];
+        }
+    }
+    return acc / 16;
+}
+
+template <typename T>
+__global__ void k_corr_top(const T* __restrict__ d1, const T* __restrict__ d2, Geom g, T lam,
+                           T* __restrict__ top) {
+    const size_t n = (size_t)g.gx[0] * g.gy[0] * g.H2 * g.W2;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int x = i % g.W2, y = (i / g.W2) % g.H2;
+    const int j = i / ((size_t)g.W2 * g.H2);
+    const int b = j / g.gx[0], aa = j % g.gx[0];
+    T v = atomic_score(d1, d2, g, b, aa, y, x);
+    top[i] = rect_pow(v > 0 ? v : T(0), lam);
+}
+
+template <typename T>
+__global__ void k_corr_pool_ref(const T* __restrict__ d1, const T* __restrict__ d2, Geom g, T lam,
+                                T* __restrict__ cp, uint8_t* __restrict__ code) {
+    const int h1 = g.h[1], w1 = g.w[1];
+    const size_t n = (size_t)g.gx[0] * g.gy[0] * h1 * w1;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = i % w1, r = (i / w1) % h1;
+    const int j = i / ((size_t)w1 * h1);
+    const int b = j / g.gx[0], aa = j % g.gx[0];
+    T best = -1;
+    int bk = 0;
+    for (int my = -1; my <= 1; ++my) {
+        const int y = 2 * r + my;
+        if (y < 0 || y >= g.H2) continue;
+        for (int mx = -1; mx <= 1; ++mx) {
+            const int x = 2 * c + mx;
+            if (x < 0 || x >= g.W2) continue;
+            T v = atomic_score(d1, d2, g, b, aa, y, x);
+            v = v > 0 ? v : T(0);
+            if (v > best) {
+                best = v;
+                bk = 3 * (my + 1) + (mx + 1);
+            }
+        }
+    }
+    cp[i] = rect_pow(best, lam);
+    code[i] = (uint8_t)bk;
+}
+
+}  // namespace
+
+hipError_t launch_corr_pool_f32(const float* d1, const float* d2, const Geom& g, float lam, float* cp,
+                                uint8_t* code, hipStream_t s) {
+    int nb;
+    const PoolArgs a = make_pool_args(g, nb);
+    hipLaunchKernelGGL(k_corr_pool_f32, dim3(nb), dim3(256), 0, s, d1, d2, a, lam, cp, code);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr_pool_bf16(const uint16_t* d1, const uint16_t* d2, const Geom& g, float lam, float* cp,
+                                 uint8_t* code, hipStream_t s) {
+    int nb;
+    const PoolArgs a = make_pool_args(g, nb);
+    hipLaunchKernelGGL(k_corr_pool_bf16, dim3(nb), dim3(256), 0, s, d1, d2, a, lam, cp, code);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_corr_top(const T* d1, const T* d2, const Geom& g, T lam, T* top, hipStream_t s) {
+    const size_t n = (size_t)g.gx[0] * g.gy[0] * g.H2 * g.W2;
+    hipLaunchKernelGGL(k_corr_top<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d1, d2, g, lam, top);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_corr_pool_ref(const T* d1, const T* d2, const Geom& g, T lam, T* cp, uint8_t* code,
+                                hipStream_t s) {
+    const size_t n = (size_t)g.gx[0] * g.gy[0] * g.h[1] * g.w[1];
+    hipLaunchKernelGGL(k_corr_pool_ref<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d1, d2, g, lam, cp,
+                       code);
+    return hipGetLastError();
+}
+
+template hipError_t launch_corr_top<float>(const float*, const float*, const Geom&, float, float*, hipStream_t);
+template hipError_t launch_corr_top<double>(const double*, const double*, const Geom&, double, double*, hipStream_t);
+template hipError_t launch_corr_pool_ref<float>(const float*, const float*, const Geom&, float, float*, uint8_t*,
+                                                hipStream_t);
+template hipError_t launch_corr_pool_ref<double>(const double*, const double*, const Geom&, double, double*,
+                                                 uint8_t*, hipStream_t);
+
+}  // namespace dm

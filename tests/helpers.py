@@ -1,0 +1,71 @@
+"""Shared helpers of the GPU tests: cached oracle runs and match comparison."""
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+
+import synth
+from oracle import dm_oracle as O
+
+# FP32 decisions closer than this (relative to 1 + value) count as oracle
+# near-ties: an FP32 evaluation may legitimately take the other branch.
+FP32_TIE = 2e-5
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_pair(name: str, max_patch: int | None = None):
+    """Oracle descriptors, pyramid, M' and M'' of a named synthetic pair."""
+    p = synth.make_pair(name)
+    mp = synth.CONFIG_NMAX[name] if max_patch is None else max_patch
+    prm = O.Params(max_patch=mp)
+    D1 = O.descriptors(p["img1"], prm)
+    D2 = O.descriptors(p["img2"], prm)
+    out, margin, pyr, M = O.match_descriptors(D1, D2, prm)
+    return dict(pair=p, prm=prm, D1=D1, D2=D2, out=out, margin=margin, pyr=pyr, M=M)
+
+
+def oracle_from_desc(D1: np.ndarray, D2: np.ndarray, max_patch: int = 0):
+    prm = O.Params(max_patch=max_patch)
+    out, margin, pyr, M = O.match_descriptors(D1, D2, prm)
+    return dict(D1=D1, D2=D2, out=out, margin=margin, pyr=pyr, M=M, prm=prm)
+
+
+def compare_matches(gpu: np.ndarray, ref: np.ndarray, margin: np.ndarray, tie: float = FP32_TIE,
+                    score_rtol: float = 1e-5):
+    """Every oracle match whose decisions all have a margin above the tie
+    threshold must appear in the GPU output with the same coordinates and a
+    score within score_rtol.  Returns counts for reporting."""
+    g = {(int(r[0]), int(r[1])): r for r in gpu}
+    near = margin < tie * (1 + np.abs(ref[:, 4]))
+    missing, moved, bad_score, worst = [], [], [], 0.0
+    for r, nt in zip(ref, near):
+        key = (int(r[0]), int(r[1]))
+        if nt:
+            continue
+        if key not in g:
+            missing.append(key)
+            continue
+        q = g[key]
+        if (int(q[2]), int(q[3])) != (int(r[2]), int(r[3])):
+            moved.append((key, (int(r[2]), int(r[3])), (int(q[2]), int(q[3]))))
+            continue
+        rel = abs(q[4] - r[4]) / abs(r[4])
+        worst = max(worst, rel)
+        if rel > score_rtol:
+            bad_score.append((key, r[4], q[4]))
+    refkeys = {(int(r[0]), int(r[1])) for r in ref}
+    extra = [k for k in g if k not in refkeys]
+    return dict(n_ref=len(ref), n_gpu=len(gpu), near_ties=int(near.sum()), missing=missing, moved=moved,
+                bad_score=bad_score, extra=extra, worst_rel=worst)
+
+
+def within_px(gpu: np.ndarray, ref: np.ndarray, px: float = 1.0) -> float:
+    """Fraction of oracle matches whose patch has a GPU match within px (inf-norm)."""
+    g = {(int(r[0]), int(r[1])): r for r in gpu}
+    ok = 0
+    for r in ref:
+        q = g.get((int(r[0]), int(r[1])))
+        if q is not None and max(abs(q[2] - r[2]), abs(q[3] - r[3])) <= px:
+            ok += 1
+    return ok / max(1, len(ref))

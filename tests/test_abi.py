@@ -1,0 +1,111 @@
+"""Host-side tests of the C ABI (no GPU): the library loads and exports every
+symbol include/dm.h declares; dm_plan's geometry equals the oracle's; every
+validation error is raised before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1506_07656_amd as dm
+from paper_1506_07656_amd import binding as B
+from oracle import dm_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "dm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = dm.lib()
+    syms = declared_symbols()
+    assert "dm_match_images" in syms and "dm_plan" in syms
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) <= set(B.SIGNATURES), set(syms) - set(B.SIGNATURES)
+
+
+def test_status_strings_and_version():
+    L = dm.lib()
+    for code in B.STATUS:
+        assert L.dm_status_string(code)
+    assert dm.version().startswith("dm-mi355x")
+
+
+def test_default_params():
+    p = dm.params()
+    assert abs(p.nu1) < 1e-9 and p.nu2 == 1 and p.nu3 == 1 and abs(p.sigmoid_slope - 0.2) < 1e-7
+    assert abs(p.mu - 0.1) < 1e-7 and p.intensity_scale == 255 and abs(p.lam - 1.4) < 1e-7
+    assert p.max_patch == 0 and p.precision == 0
+
+
+@pytest.mark.parametrize("W,H,W2,H2,mp", [(64, 64, 64, 64, 32), (256, 192, 256, 192, 64), (512, 256, 512, 256, 0),
+                                           (621, 188, 621, 188, 0), (256, 192, 256, 192, 0), (37, 23, 19, 41, 0),
+                                           (4, 4, 4, 4, 0), (9, 5, 3, 2, 0), (128, 96, 300, 150, 0)])
+def test_plan_matches_oracle_geometry(W, H, W2, H2, mp):
+    pl = dm.plan(W, H, W2, H2, dm.params(max_patch=mp))
+    lmax = O.pyramid_top(W, H, mp)
+    assert pl.lmax == lmax and pl.N_max == 4 << lmax
+    G = O.grids(W, H, lmax)
+    h, w = O.map_dims(H2, W2, lmax)
+    assert pl.n_atomic == G[0].size == pl.max_matches
+    for lv in range(lmax + 1):
+        assert (pl.gy[lv], pl.gx[lv]) == G[lv].shape
+        assert pl.n_valid[lv] == G[lv].sum()
+    for lv in range(lmax + 2):
+        assert (pl.h[lv], pl.w[lv]) == (h[lv], w[lv])
+    offs = [pl.off_top, pl.off_best, pl.off_cell, pl.off_valid] + [pl.off_cp[i] for i in range(lmax)]
+    assert all(o % 256 == 0 for o in offs)
+    assert pl.workspace_bytes >= pl.off_cell + ((H2 + 3) // 4) * ((W2 + 3) // 4) * 8
+
+
+@pytest.mark.parametrize("kw", [dict(max_patch=12), dict(max_patch=2), dict(lam=0.5), dict(mu=-1.0),
+                                dict(nu2=3.0), dict(sigmoid_slope=0.0), dict(precision=7), dict(nu1=float("nan"))])
+def test_plan_rejects_bad_params(kw):
+    with pytest.raises(dm.DMError) as e:
+        dm.plan(64, 64, 64, 64, dm.params(**kw))
+    assert e.value.status == -1
+
+
+def test_plan_rejects_bad_shapes():
+    for args in [(3, 64, 64, 64), (64, 2, 64, 64), (64, 64, 0, 64), (9000, 64, 64, 64)]:
+        with pytest.raises(dm.DMError) as e:
+            dm.plan(*args, dm.params())
+        assert e.value.status == -2
+    p = dm.params()
+    p.reserved[3] = 1
+    with pytest.raises(dm.DMError):
+        dm.plan(64, 64, 64, 64, p)
+
+
+def _call_match(ws_bytes, capacity, ws=0x10000, out=0x20000, n_out=0x30000, d1=0x40000, d2=0x50000, prm=None):
+    prm = prm or dm.params()
+    return dm.lib().dm_match_descriptors(ctypes.c_void_p(d1), 64, 64, ctypes.c_void_p(d2), 64, 64,
+                                         ctypes.byref(prm), ctypes.c_void_p(ws), ws_bytes, ctypes.c_void_p(out),
+                                         capacity, ctypes.c_void_p(n_out), None)
+
+
+def test_match_validation_before_any_launch():
+    """Fake device addresses are fine: every call below fails validation on
+    the host, so nothing dereferences them."""
+    pl = dm.plan(64, 64, 64, 64)
+    need = pl.workspace_bytes
+    assert _call_match(need - 1, pl.max_matches) == -3                 # workspace too small
+    assert b"workspace" in dm.lib().dm_last_error()
+    assert _call_match(need, pl.max_matches - 1) == -4                 # capacity too small
+    assert _call_match(need, pl.max_matches, ws=0) == -1               # null workspace
+    assert _call_match(need, pl.max_matches, ws=0x10010) == -1         # misaligned workspace
+    assert _call_match(need, pl.max_matches, d1=0) == -1               # null descriptors
+    assert _call_match(need, pl.max_matches, n_out=0) == -1
+    assert _call_match(need, pl.max_matches, prm=dm.params(precision="fp64")) in (-5, -3)
+    L = dm.lib()
+    assert L.dm_match_descriptors(None, 64, 64, None, 64, 64, None, None, 0, None, 0, None, None) == -1
+    assert L.dm_descriptors(ctypes.c_void_p(0x1000), 0, 5, 0, ctypes.byref(dm.params()),
+                            ctypes.c_void_p(0x2000), None) == -2
+    assert L.dm_descriptors(ctypes.c_void_p(0x1000), 8, 5, 4, ctypes.byref(dm.params()),
+                            ctypes.c_void_p(0x2000), None) == -2

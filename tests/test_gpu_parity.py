@@ -1,0 +1,126 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1506_07656_amd as dm
+import synth
+from oracle import dm_oracle as O
+from tests.helpers import FP32_TIE, compare_matches, oracle_from_desc, oracle_pair, within_px
+
+pytestmark = pytest.mark.gpu
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def run_desc(D1, D2, **kw):
+    m, ws, pl = dm.match_descriptors(cuda(D1), cuda(D2), dm.params(**kw), return_state=True)
+    torch.cuda.synchronize()
+    return m.cpu().numpy(), dm.workspace_views(ws, pl), pl
+
+
+def report(name, r):
+    print(f"{name}: ref {r['n_ref']} gpu {r['n_gpu']} near-ties {r['near_ties']} missing {len(r['missing'])} "
+          f"moved {len(r['moved'])} bad-score {len(r['bad_score'])} extra {len(r['extra'])} "
+          f"worst rel {r['worst_rel']:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_descriptors_match_oracle(name):
+    o = oracle_pair(name)
+    p = synth.make_pair(name)
+    for img, ref in ((p["img1"], o["D1"]), (p["img2"], o["D2"])):
+        d = dm.descriptors(cuda(img)).cpu().numpy()
+        np.testing.assert_allclose(d, ref, rtol=0, atol=3e-6)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_pyramid_levels_match_oracle(name):
+    o = oracle_pair(name)
+    pyr = o["pyr"]
+    gpu, views, pl = run_desc(o["D1"], o["D2"], max_patch=synth.CONFIG_NMAX[name])
+    assert pl.lmax == pyr.lmax
+    for lv in range(pyr.lmax):
+        G = pyr.G[lv]
+        cp = views["levels"][lv]["cp"].cpu().numpy()[G]
+        code = views["levels"][lv]["code"].cpu().numpy()[G]
+        ref = pyr.Cp[lv][G]
+        np.testing.assert_allclose(cp, ref, rtol=1e-5, atol=1e-7, err_msg=f"level {lv}")
+        gap = O.risky(pyr.gap[lv][G])
+        clear = gap > FP32_TIE * (1 + ref)
+        mism = (code != pyr.code[lv][G]) & clear
+        assert mism.sum() == 0, f"level {lv}: {mism.sum()} codes differ away from near-ties"
+        print(f"level {lv}: codes compared {clear.sum()} / {clear.size}", flush=True)
+    G = pyr.G[pyr.lmax]
+    np.testing.assert_allclose(views["top"].cpu().numpy()[G], pyr.top[G], rtol=1e-5, atol=1e-7)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_matches_fp32_match_oracle(name):
+    o = oracle_pair(name)
+    gpu, _, _ = run_desc(o["D1"], o["D2"], max_patch=synth.CONFIG_NMAX[name])
+    r = compare_matches(gpu, o["out"], o["margin"])
+    report(name, r)
+    assert not r["missing"] and not r["moved"] and not r["bad_score"]
+    assert len(r["extra"]) <= r["near_ties"]
+    # order (y1, x1) and at most one match per atomic patch / target cell
+    keys = gpu[:, 1] * 1e6 + gpu[:, 0]
+    assert (np.diff(keys) > 0).all()
+    assert len(np.unique(gpu[:, 2:4] // 4, axis=0)) == len(gpu)
+
+
+def test_match_images_end_to_end_c1():
+    o = oracle_pair("c1")
+    p = o["pair"]
+    m = dm.match_images(cuda(p["img1"]), cuda(p["img2"]), dm.params(max_patch=32)).cpu().numpy()
+    r = compare_matches(m, o["out"], o["margin"], tie=1e-4, score_rtol=2e-5)
+    report("c1 images", r)
+    assert not r["missing"] and not r["moved"] and not r["bad_score"]
+    x1, y1 = m[:, 0], m[:, 1]
+    inner = (x1 >= 8) & (x1 < 64 - 13) & (y1 >= 11) & (y1 < 56)
+    assert ((m[inner, 2] - x1[inner] == 5) & (m[inner, 3] - y1[inner] == -3)).all()
+
+
+@pytest.mark.parametrize("W1,H1,W2,H2,mp", [(4, 4, 4, 4, 0), (8, 8, 5, 3, 0), (9, 5, 3, 2, 0), (37, 23, 19, 41, 0),
+                                             (41, 19, 37, 23, 16), (64, 40, 50, 70, 0), (30, 30, 30, 30, 8)])
+def test_ragged_and_tiny_shapes(W1, H1, W2, H2, mp):
+    rng = np.random.default_rng(W1 * 1000 + H1 * 10 + W2)
+    i1 = synth.blurred_noise(rng, H1, W1)
+    i2 = synth.blurred_noise(rng, H2, W2)
+    D1 = O.descriptors(i1)
+    D2 = O.descriptors(i2)
+    o = oracle_from_desc(D1, D2, mp)
+    gpu, _, pl = run_desc(D1, D2, max_patch=mp)
+    assert pl.lmax == o["pyr"].lmax
+    r = compare_matches(gpu, o["out"], o["margin"])
+    report(f"{W1}x{H1}/{W2}x{H2}", r)
+    assert not r["missing"] and not r["moved"] and not r["bad_score"]
+    assert len(r["extra"]) <= r["near_ties"]
+
+
+def test_identity_pair_matches_itself():
+    img = synth.make_pair("c1")["img1"]
+    D = O.descriptors(img)
+    gpu, _, _ = run_desc(D, D, max_patch=32)
+    assert len(gpu) == 256
+    np.testing.assert_array_equal(gpu[:, 0:2], gpu[:, 2:4])
+
+
+def test_deterministic():
+    o = oracle_pair("c1")
+    a, va, _ = run_desc(o["D1"], o["D2"], max_patch=32)
+    b, vb, _ = run_desc(o["D1"], o["D2"], max_patch=32)
+    np.testing.assert_array_equal(a, b)
+    for la, lb in zip(va["levels"], vb["levels"]):
+        assert torch.equal(la["cp"], lb["cp"]) and torch.equal(la["code"], lb["code"])
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_bf16_agreement(name):
+    o = oracle_pair(name)
+    gpu, _, _ = run_desc(o["D1"], o["D2"], max_patch=synth.CONFIG_NMAX[name], precision="bf16")
+    frac = within_px(gpu, o["out"], 1.0)
+    print(f"{name} bf16: {len(gpu)} matches, {frac:.4f} of oracle matches within 1 px", flush=True)
+    assert frac >= 0.99
