@@ -37,9 +37,23 @@ __host__ __device__ inline const uint8_t* vtab(const uint8_t* base, const Geom& 
     return base + (size_t)(2 * l + axis) * g.vstride;
 }
 
+// Division by a runtime constant d via a multiply-high: exact for numerators
+// e with e * d < 2^32 (all tile and block index ranges here are far below).
+struct FastDiv {
+    uint32_t d, m;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f;
+    f.d = d;
+    f.m = d > 1 ? (uint32_t)((0x100000000ull + d - 1) / d) : 0u;
+    return f;
+}
+__device__ inline uint32_t fdiv(uint32_t e, const FastDiv& f) { return f.d == 1 ? e : __umulhi(e, f.m); }
+
 // Rectification R_lambda of Eq. (11) on a non-negative argument.
 __device__ inline float rect_pow(float x, float lam) {
-    return x > 0.f ? exp2f(lam * log2f(x)) : 0.f;
+    // hardware log2 / exp2 (v_log_f32, v_exp_f32: about 1 ulp on normal inputs)
+    return x > 0.f ? __builtin_amdgcn_exp2f(lam * __builtin_amdgcn_logf(x)) : 0.f;
 }
 __device__ inline double rect_pow(double x, double lam) {
     return x > 0.0 ? exp2(lam * log2(x)) : 0.0;

@@ -23,8 +23,6 @@
 namespace dm {
 namespace {
 
-__device__ inline int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
-
 // Non-negative float <-> order-preserving code with 0 = "no tuple".
 __device__ inline uint32_t enc(float v) { return __float_as_uint(v) + 1u; }
 __device__ inline float dec(uint32_t e) { return __uint_as_float(e - 1u); }
@@ -39,7 +37,13 @@ struct BtArgs {
     int n_cblk, n_rt;
     int cy0, cx0, ncy, ncx;      // cell-table window parameters (bottom only)
     int W2, cw;                  // target width, cells per target row
+    FastDiv f_t, f_tc, f_nr, f_rwd;   // divisions by TR*TC, TC, RH*RWd, RWd (element indices < 2^14)
 };
+
+__device__ inline int xcd_block(int nblocks) {
+    const int per = (nblocks + 7) / 8;
+    return (blockIdx.x % 8) * per + blockIdx.x / 8;
+}
 
 __global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __restrict__ cp_prev,
                                                    const uint8_t* __restrict__ code_prev,
@@ -48,97 +52,156 @@ __global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __rest
                                                    const float* __restrict__ top, const uint8_t* __restrict__ vt,
                                                    Geom g, float* __restrict__ u_prev,
                                                    unsigned long long* __restrict__ best,
-                                                   unsigned long long* __restrict__ cell) {
+                                                   unsigned long long* __restrict__ cell, int nblocks) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int T = a.TR * a.TC;
     uint32_t* sV = (uint32_t*)smem_raw;                                   // [CB][4][TR][TC]
     unsigned long long* sBest = (unsigned long long*)(sV + 4 * a.CB * T);  // [CB]
     unsigned long long* sCell = sBest + a.CB;                               // [ncy][ncx]
-    const int bid = blockIdx.x;
-    const int cblk = bid % a.n_cblk, rest = bid / a.n_cblk;
+    int* sPar = (int*)(sCell + a.ncy * a.ncx);                              // [CB][4] parent map index
+    int* sCv = sPar + 4 * a.CB;                                             // [CB] child exists
+    const int bid = xcd_block(nblocks);
+    if (bid >= nblocks) return;
+    const int cblk = bid % a.n_cblk, rest = bid / a.n_cblk;   // once per block (scalar)
     const int R0 = (rest % a.n_rt) * a.TR, C0 = (rest / a.n_rt) * a.TC;
-    const uint8_t *vxp = vtab(vt, g, a.l, 0), *vyp = vtab(vt, g, a.l, 1);
-    const uint8_t *vxc = vtab(vt, g, a.l - 1, 0), *vyc = vtab(vt, g, a.l - 1, 1);
     const int tid = threadIdx.x;
-
-    // Phase 1: V_l of the up-to-4 parents of each child, on the shifted tile.
-    if (a.is_top) {
-        for (int e = tid; e < 4 * a.CB * T; e += 256) {
-            const int ks = e / T, rem = e - ks * T;
-            const int k = ks >> 2, side = ks & 3;
+    {
+        const uint8_t *vxp = vtab(vt, g, a.l, 0), *vyp = vtab(vt, g, a.l, 1);
+        const uint8_t *vxc = vtab(vt, g, a.l - 1, 0), *vyc = vtab(vt, g, a.l - 1, 1);
+        for (int e = tid; e < 4 * a.CB; e += 256) {
+            const int k = e >> 2, side = e & 3;
             const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;  // o_i of Eq. (5), i = side
             const int c = cblk * a.CB + k;
-            uint32_t v = 0;
+            int par = -1;
             if (c < a.gxc * a.gyc) {
                 const int cb = c / a.gxc, ca = c - cb * a.gxc;
                 const int pb = parent_index(a.l, cb, sy), pa = parent_index(a.l, ca, sx);
-                const int qy = R0 + rem / a.TC - sy, qx = C0 + rem % a.TC - sx;
-                if (pb >= 0 && pb < a.gyp && pa >= 0 && pa < a.gxp && vxp[pa] && vyp[pb] && qy >= 0 && qy < a.h &&
-                    qx >= 0 && qx < a.w)
-                    v = enc(top[(((size_t)pb * a.gxp + pa) * a.h + qy) * a.w + qx]);
+                if (pb >= 0 && pb < a.gyp && pa >= 0 && pa < a.gxp && vxp[pa] && vyp[pb]) par = pb * a.gxp + pa;
+                if (side == 0) sCv[k] = vxc[ca] && vyc[cb];
+            } else if (side == 0) {
+                sCv[k] = 0;
             }
-            sV[e] = v;
+            sPar[e] = par;
+        }
+        if (a.is_bottom) {
+            for (int e = tid; e < a.CB; e += 256) sBest[e] = 0ull;
+            for (int e = tid; e < a.ncy * a.ncx; e += 256) sCell[e] = 0ull;
+        }
+        if (!a.is_top)
+            for (int e = tid; e < 4 * a.CB * T; e += 256) sV[e] = 0u;
+    }
+    __syncthreads();
+
+    // Phase 1: V_l of the up-to-4 parents of each child, on the shifted tile.
+    if (a.is_top) {
+        for (int e0 = tid; e0 < 4 * a.CB * T; e0 += 4 * 256) {
+            uint32_t v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * 256;
+                v[u] = 0u;
+                if (e < 4 * a.CB * T) {
+                    const int ks = fdiv(e, a.f_t), rem = e - ks * T;
+                    const int side = ks & 3;
+                    const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;
+                    const int par = sPar[ks];
+                    const int ty = fdiv(rem, a.f_tc);
+                    const int qy = R0 + ty - sy, qx = C0 + rem - ty * a.TC - sx;
+                    if (par >= 0 && qy >= 0 && qy < a.h && qx >= 0 && qx < a.w)
+                        v[u] = enc(top[((size_t)par * a.h + qy) * a.w + qx]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (e0 + u * 256 < 4 * a.CB * T) sV[e0 + u * 256] = v[u];
         }
     } else {
-        for (int e = tid; e < 4 * a.CB * T; e += 256) sV[e] = 0u;
-        __syncthreads();
         // U_l entries r' whose argmax 2r' + m can land in this side's q-range
         // [q0, q0 + TR): r' in [floor(q0/2), floor((q0 + TR)/2)].
-        const int RH = a.TR / 2 + 2, RWd = a.TC / 2 + 2;
-        for (int e = tid; e < 4 * a.CB * RH * RWd; e += 256) {
-            const int ks = e / (RH * RWd), rem = e - ks * (RH * RWd);
-            const int k = ks >> 2, side = ks & 3;
-            const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;
-            const int c = cblk * a.CB + k;
-            if (c >= a.gxc * a.gyc) continue;
-            const int cb = c / a.gxc, ca = c - cb * a.gxc;
-            const int pb = parent_index(a.l, cb, sy), pa = parent_index(a.l, ca, sx);
-            if (!(pb >= 0 && pb < a.gyp && pa >= 0 && pa < a.gxp && vxp[pa] && vyp[pb])) continue;
-            const int qy0 = R0 - sy, qx0 = C0 - sx;
-            const int ry = floordiv(qy0, 2) + rem / RWd, rx = floordiv(qx0, 2) + rem % RWd;
-            if (ry > floordiv(qy0 + a.TR, 2) || rx > floordiv(qx0 + a.TC, 2)) continue;
-            if (ry < 0 || ry >= a.hu || rx < 0 || rx >= a.wu) continue;
-            const size_t o = (((size_t)pb * a.gxp + pa) * a.hu + ry) * a.wu + rx;
-            const float u = u_cur[o];
-            if (!(u >= 0.f)) continue;                       // node not reached
-            const int m = code_cur[o];
-            const int qy = 2 * ry + m / 3 - 1, qx = 2 * rx + m % 3 - 1;
-            const int ty = qy - qy0, tx = qx - qx0;   // tile index of r = q + o_i
-            if (ty < 0 || ty >= a.TR || tx < 0 || tx >= a.TC) continue;
-            atomicMax(&sV[(ks * a.TR + ty) * a.TC + tx], enc(u));
+        const int RH = a.TR / 2 + 2, RWd = a.TC / 2 + 2, NR = RH * RWd;
+        for (int e0 = tid; e0 < 4 * a.CB * NR; e0 += 2 * 256) {
+            float uv[2];
+            int m[2], idx[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int e = e0 + u * 256;
+                idx[u] = -1;
+                uv[u] = -1.f;
+                m[u] = 0;
+                if (e >= 4 * a.CB * NR) continue;
+                const int ks = fdiv(e, a.f_nr), rem = e - ks * NR;
+                const int par = sPar[ks];
+                if (par < 0) continue;
+                const int side = ks & 3;
+                const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;
+                const int qy0 = R0 - sy, qx0 = C0 - sx;
+                const int rr = fdiv(rem, a.f_rwd);
+                const int ry = (qy0 >> 1) + rr, rx = (qx0 >> 1) + rem - rr * RWd;   // >> 1: floor division
+                if (ry > ((qy0 + a.TR) >> 1) || rx > ((qx0 + a.TC) >> 1)) continue;
+                if (ry < 0 || ry >= a.hu || rx < 0 || rx >= a.wu) continue;
+                const size_t o = ((size_t)par * a.hu + ry) * a.wu + rx;
+                uv[u] = u_cur[o];
+                m[u] = code_cur[o];
+                const int qy = 2 * ry + m[u] / 3 - 1, qx = 2 * rx + m[u] % 3 - 1;
+                const int ty = qy - qy0, tx = qx - qx0;   // tile index of r = q + o_i
+                if (ty >= 0 && ty < a.TR && tx >= 0 && tx < a.TC) idx[u] = (ks * a.TR + ty) * a.TC + tx;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (idx[u] >= 0 && uv[u] >= 0.f) atomicMax(&sV[idx[u]], enc(uv[u]));   // unreached: -inf
         }
-    }
-    if (a.is_bottom) {
-        for (int e = tid; e < a.CB; e += 256) sBest[e] = 0ull;
-        for (int e = tid; e < a.ncy * a.ncx; e += 256) sCell[e] = 0ull;
     }
     __syncthreads();
 
     // Phase 2: U_{l-1}(c, r) = C'_{l-1}(c, r) + max over parents.
-    const int cyb = floordiv(2 * R0 - 1, 4), cxb = floordiv(2 * C0 - 1, 4);
-    for (int e = tid; e < a.CB * T; e += 256) {
-        const int k = e / T, rem = e - k * T;
-        const int ty = rem / a.TC, tx = rem - ty * a.TC;
-        const int c = cblk * a.CB + k, ry = R0 + ty, rx = C0 + tx;
-        if (c >= a.gxc * a.gyc || ry >= a.h || rx >= a.w) continue;
-        const int cb = c / a.gxc, ca = c - cb * a.gxc;
-        if (!(vxc[ca] && vyc[cb])) continue;
-        uint32_t vb = 0;
+    const int cyb = (2 * R0 - 1) >> 2, cxb = (2 * C0 - 1) >> 2;   // floor division by 4
+    for (int e0 = tid; e0 < a.CB * T; e0 += 4 * 256) {
+        float cpv[4];
+        int mv[4];
+        uint32_t vb[4];
+        size_t off[4];
+        bool live[4];
 #pragma unroll
-        for (int side = 0; side < 4; ++side) vb = max(vb, sV[((k * 4 + side) * a.TR + ty) * a.TC + tx]);
-        const size_t o = (((size_t)cb * a.gxc + ca) * a.h + ry) * a.w + rx;
-        if (!a.is_bottom) {
-            u_prev[o] = vb ? cp_prev[o] + dec(vb) : -INFINITY;
-            continue;
+        for (int u = 0; u < 4; ++u) {   // loads of 4 entries first, so they overlap
+            const int e = e0 + u * 256;
+            live[u] = false;
+            vb[u] = 0u;
+            cpv[u] = 0.f;
+            mv[u] = 0;
+            off[u] = 0;
+            if (e >= a.CB * T) continue;
+            const int k = fdiv(e, a.f_t), rem = e - k * T;
+            const int ty = fdiv(rem, a.f_tc), tx = rem - ty * a.TC;
+            const int ry = R0 + ty, rx = C0 + tx;
+            if (!sCv[k] || ry >= a.h || rx >= a.w) continue;
+            live[u] = true;
+#pragma unroll
+            for (int side = 0; side < 4; ++side) vb[u] = max(vb[u], sV[((k * 4 + side) * a.TR + ty) * a.TC + tx]);
+            off[u] = (((size_t)cblk * a.CB + k) * a.h + ry) * a.w + rx;
+            if (vb[u] || !a.is_bottom) {
+                cpv[u] = cp_prev[off[u]];
+                if (a.is_bottom) mv[u] = code_prev[off[u]];
+            }
         }
-        if (!vb) continue;
-        const float u = cp_prev[o] + dec(vb);
-        const int m = code_prev[o];
-        const int xy = 2 * ry + m / 3 - 1, xx = 2 * rx + m % 3 - 1;
-        const unsigned long long hi = (unsigned long long)__float_as_uint(u) << 32;
-        atomicMax(&sBest[k], hi | (0xFFFFFFFFull - (uint32_t)(xy * a.W2 + xx)));
-        const unsigned long long kc = hi | (0xFFFFFFFFull - (uint32_t)(c * 16 + (xy & 3) * 4 + (xx & 3)));
-        atomicMax(&sCell[((xy >> 2) - cyb) * a.ncx + ((xx >> 2) - cxb)], kc);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (!live[u]) continue;
+            if (!a.is_bottom) {
+                u_prev[off[u]] = vb[u] ? cpv[u] + dec(vb[u]) : -INFINITY;
+                continue;
+            }
+            if (!vb[u]) continue;
+            const int e = e0 + u * 256;
+            const int k = fdiv(e, a.f_t), rem = e - k * T;
+            const int ty = fdiv(rem, a.f_tc), tx = rem - ty * a.TC;
+            const int c = cblk * a.CB + k, ry = R0 + ty, rx = C0 + tx;
+            const float uu = cpv[u] + dec(vb[u]);
+            const int xy = 2 * ry + mv[u] / 3 - 1, xx = 2 * rx + mv[u] % 3 - 1;
+            const unsigned long long hi = (unsigned long long)__float_as_uint(uu) << 32;
+            atomicMax(&sBest[k], hi | (0xFFFFFFFFull - (uint32_t)(xy * a.W2 + xx)));
+            const unsigned long long kc = hi | (0xFFFFFFFFull - (uint32_t)(c * 16 + (xy & 3) * 4 + (xx & 3)));
+            atomicMax(&sCell[((xy >> 2) - cyb) * a.ncx + ((xx >> 2) - cxb)], kc);
+        }
     }
     if (a.is_bottom) {
         __syncthreads();
@@ -285,10 +348,15 @@ hipError_t launch_backtrack<float>(int l, const float* cp_prev, const uint8_t* c
     a.ncx = a.TC / 2 + 2;
     a.cy0 = a.cx0 = 0;
     const size_t smem = (size_t)4 * a.CB * a.TR * a.TC * sizeof(uint32_t) +
-                        (a.is_bottom ? ((size_t)a.CB + (size_t)a.ncy * a.ncx) * 8 : 0);
-    const dim3 grid(a.n_cblk * a.n_rt * n_ct);
+                        ((size_t)a.CB + (size_t)a.ncy * a.ncx) * 8 + (size_t)5 * a.CB * sizeof(int);
+    const int nblocks = a.n_cblk * a.n_rt * n_ct;
+    a.f_t = make_fastdiv(a.TR * a.TC);
+    a.f_tc = make_fastdiv(a.TC);
+    a.f_nr = make_fastdiv((a.TR / 2 + 2) * (a.TC / 2 + 2));
+    a.f_rwd = make_fastdiv(a.TC / 2 + 2);
+    const dim3 grid(((nblocks + 7) / 8) * 8);
     hipLaunchKernelGGL(k_backtrack, grid, dim3(256), smem, s, a, cp_prev, code_prev, u_cur, code_cur, top, vt, g,
-                       u_prev, (unsigned long long*)best, (unsigned long long*)cell);
+                       u_prev, (unsigned long long*)best, (unsigned long long*)cell, nblocks);
     return hipGetLastError();
 }
 

@@ -15,9 +15,14 @@
 // value is raised to lambda.
 //
 // Block = 4 waves; each wave owns 2 M-tiles of 16 patches (128 patches per
-// block).  A block covers TR pooled rows x TC pooled columns: per pooled row
-// it needs A on the 3 rows 2r-1..2r+1, and on the 32 positions
-// 2C0-1 .. 2C0+30 (two 16-wide N-tiles), which give TC = 15 pooled columns.
+// block).  A block owns a band of TR pooled rows and sweeps it from left to
+// right, 16 pooled columns per step.  Per A-row it computes two N-tiles: the
+// even positions x = 2c and the odd positions x = 2c+1 of the 16 columns c,
+// so pooled column c needs O[c-1], E[c], O[c]: O[c-1] comes from the
+// neighbouring lane (DPP row shift) or, for the first column of a step, from
+// the previous step (a per-row carry in LDS).  Every pooled row of a patch is
+// then written as one aligned 16-float run, and consecutive steps complete
+// the same cache lines.
 #include "dm_internal.h"
 
 namespace dm {
@@ -26,129 +31,23 @@ namespace {
 constexpr int MT = 2;                // M-tiles (16 patches) per wave
 constexpr int WAVES = 4;
 constexpr int PT = 16 * MT * WAVES;  // patches per block
-constexpr int TR = 8;                // pooled rows per block
-constexpr int TC = 15;               // pooled columns per block
-constexpr int NPOS = 32;             // A positions per A-row (2 N-tiles)
-constexpr int ARS = 2 * TR + 1;      // A-rows per block
+constexpr int TR = 8;                // pooled rows per band
+constexpr int ARS = 2 * TR + 1;      // A-rows per band
 constexpr int D2R = 2 * TR + 4;      // target tile rows (A-rows + patch height - 1)
-constexpr int D2C = NPOS + 3;        // target tile columns
+constexpr int D2C = 35;              // target tile columns: 2C0-2 .. 2C0+32
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 struct PoolArgs {
     int natom, n0x, W1, W2, H2, h1, w1;
-    int n_ptiles, n_rtiles;
+    int n_ptiles, n_steps;
 };
 
-// Fused pool + rectify + store of pooled row r from the three staged A-rows.
-// sAw: this wave's staging [16*MT patches][3 slots][NPOS].
-__device__ inline void pool_row(const float (*sAw)[3][NPOS], int ia, int R0, int C0, int pbase,
-                                const PoolArgs& a, float lam, float* __restrict__ cp,
-                                uint8_t* __restrict__ code) {
-    const int lane = threadIdx.x & 63;
-    const int n = lane & 15, grp = lane >> 4;
-    const int r = R0 + ia / 2 - 1;
-    const int c = C0 + n;
-    if (n >= TC || r >= a.h1 || c >= a.w1) return;
-#pragma unroll
-    for (int pp = 0; pp < 4 * MT; ++pp) {
-        const int lp = grp + 4 * pp;
-        const int j = pbase + lp;
-        if (j >= a.natom) continue;
-        float best = -1.f;
-        int bk = 0;
-#pragma unroll
-        for (int my = -1; my <= 1; ++my) {
-            const int y = 2 * r + my;
-            if (y < 0 || y >= a.H2) continue;
-            const int slot = (ia - 1 + my) % 3;
-#pragma unroll
-            for (int mx = -1; mx <= 1; ++mx) {
-                const int x = 2 * c + mx;
-                if (x < 0 || x >= a.W2) continue;
-                const float v = sAw[lp][slot][2 * n + 1 + mx];
-                if (v > best) {
-                    best = v;
-                    bk = 3 * (my + 1) + (mx + 1);
-                }
-            }
-        }
-        const size_t o = ((size_t)j * a.h1 + r) * a.w1 + c;
-        cp[o] = rect_pow(best, lam);
-        code[o] = (uint8_t)bk;
-    }
-}
-
-__device__ inline void block_coords(const PoolArgs& a, int& pt, int& R0, int& C0) {
-    const int bid = blockIdx.x;
-    pt = bid % a.n_ptiles;
-    const int rest = bid / a.n_ptiles;
-    R0 = (rest % a.n_rtiles) * TR;
-    C0 = (rest / a.n_rtiles) * TC;
-}
-
-__global__ __launch_bounds__(256, 2) void k_corr_pool_f32(const float* __restrict__ d1,
-                                                          const float* __restrict__ d2, PoolArgs a,
-                                                          float lam, float* __restrict__ cp,
-                                                          uint8_t* __restrict__ code) {
-    __shared__ float sD2[D2R * D2C * 9];
-    __shared__ float sA[WAVES][16 * MT][3][NPOS];
-    int pt, R0, C0;
-    block_coords(a, pt, R0, C0);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n = lane & 15, grp = lane >> 4;
-    const int pbase = pt * PT + wave * 16 * MT;
-
-    // Patch fragments: lane (n, grp) holds row grp of the 4x4 patch of patch
-    // pbase + 16 mt + n: 4 pixels x 9 channels, contiguous in D1.
-    float fa[MT][36];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-        const int j = pbase + mt * 16 + n;
-        if (j < a.natom) {
-            const int b = j / a.n0x, aa = j - b * a.n0x;
-            const float* src = d1 + ((size_t)(4 * b + grp) * a.W1 + 4 * aa) * 9;
-#pragma unroll
-            for (int t = 0; t < 36; ++t) fa[mt][t] = src[t];
-        } else {
-#pragma unroll
-            for (int t = 0; t < 36; ++t) fa[mt][t] = 0.f;
-        }
-    }
-    // Target tile: rows 2R0-3 .. 2R0+2TR, columns 2C0-3 .. 2C0+NPOS-1, zero outside I'.
-    const int ybase = 2 * R0 - 3, xbase = 2 * C0 - 3;
-    for (int e = tid; e < D2R * D2C * 9; e += 256) {
-        const int row = e / (D2C * 9), rem = e - row * (D2C * 9);
-        const int y = ybase + row, x = xbase + rem / 9, ch = rem % 9;
-        sD2[e] = (y >= 0 && y < a.H2 && x >= 0 && x < a.W2) ? d2[((size_t)y * a.W2 + x) * 9 + ch] : 0.f;
-    }
-    __syncthreads();
-
-    for (int ia = 0; ia < ARS; ++ia) {
-        const int slot = ia % 3;
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-            const float* bs = sD2 + ((ia + grp) * D2C + 16 * nt + n) * 9;
-            float fb[36];
-#pragma unroll
-            for (int t = 0; t < 36; ++t) fb[t] = bs[t];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int t = 0; t < 36; ++t) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[mt][t], fb[t], acc, 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    sA[wave][mt * 16 + 4 * grp + r][slot][16 * nt + n] = fmaxf(acc[r] * 0.0625f, 0.f);
-            }
-        }
-        if (ia >= 2 && !(ia & 1)) {
-            __syncthreads();
-            pool_row(sA[wave], ia, R0, C0, pbase, a, lam, cp, code);
-            __syncthreads();
-        }
-    }
+// Lane n of each 16-lane row receives v from lane n-1; lane 0 receives `first`.
+__device__ inline float shift_in(float v, float first) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(first), __float_as_int(v), 0x111, 0xF, 0xF,
+                                                      false));
 }
 
 __device__ inline bf8 load_bf8(const uint32_t* p) {
@@ -163,6 +62,186 @@ __device__ inline bf8 load_bf8(const uint32_t* p) {
     return x.v;
 }
 
+// Two packed bf16 values times 1/16: an exponent shift, exact for normal
+// values (zero stays zero; values below 2^-122 would flush to zero).
+__device__ inline uint32_t bf16x2_scale16(uint32_t u) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t b = (u >> (16 * h)) & 0xFFFFu;
+        const uint32_t e = (b >> 7) & 0xFFu;
+        const uint32_t v = e > 4 ? b - (4u << 7) : (b & 0x8000u);
+        r |= v << (16 * h);
+    }
+    return r;
+}
+
+// One x-step of the sweep for both precisions.  Engine supplies the MFMA chain
+// for an N-tile (E or O) of all MT M-tiles.
+template <typename Engine>
+__device__ inline void sweep_band(const Engine& eng, const PoolArgs& a, int pt, int R0, float lam,
+                                  float* __restrict__ cp, uint8_t* __restrict__ code,
+                                  float (*carry)[16 * MT]) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = lane & 15, grp = lane >> 4;
+    const int pbase = pt * PT + wave * 16 * MT;
+    // Output offsets of this lane's 4*MT patches (a patch map is h1 x w1).
+    size_t obase[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) obase[mt][j] = (size_t)(pbase + mt * 16 + 4 * grp + j) * a.h1 * a.w1;
+    for (int step = 0; step < a.n_steps; ++step) {
+        const int C0 = 16 * step;
+        __syncthreads();                         // previous tile fully consumed
+        eng.load_tile(a, R0, C0);
+        __syncthreads();
+        const int c = C0 + n;
+        const bool e_ok = 2 * c < a.W2, o_ok = 2 * c + 1 < a.W2;
+        float best[MT][4];
+        int bk[MT][4];
+        for (int ia = 0; ia < ARS; ++ia) {
+            const int y = 2 * R0 - 1 + ia;
+            const bool y_ok = y >= 0 && y < a.H2;
+            f4 accE[MT], accO[MT];
+            eng.mfma_row(ia, 2 * n, accE);
+            eng.mfma_row(ia, 2 * n + 1, accO);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int lp = mt * 16 + 4 * grp + j;
+                    const float E = (y_ok && e_ok) ? fmaxf(accE[mt][j], 0.f) : -1.f;
+                    const float O = (y_ok && o_ok) ? fmaxf(accO[mt][j], 0.f) : -1.f;
+                    const float cin = step ? carry[ia][lp] : -1.f;   // O of column C0-1
+                    const float L = shift_in(O, cin);
+                    if (n == 15) carry[ia][lp] = O;
+                    // row maximum, first in order mx = -1, 0, +1
+                    float rm = L;
+                    int rk = 0;
+                    if (E > rm) {
+                        rm = E;
+                        rk = 1;
+                    }
+                    if (O > rm) {
+                        rm = O;
+                        rk = 2;
+                    }
+                    if (ia & 1) {                              // my = 0 of pooled row R0 + ia/2
+                        if (rm > best[mt][j]) {
+                            best[mt][j] = rm;
+                            bk[mt][j] = 3 + rk;
+                        }
+                    } else {
+                        if (ia > 0) {                          // my = +1: finish pooled row R0 + ia/2 - 1
+                            float bv = best[mt][j];
+                            int bc = bk[mt][j];
+                            if (rm > bv) {
+                                bv = rm;
+                                bc = 6 + rk;
+                            }
+                            const int r = R0 + ia / 2 - 1, jp = pbase + lp;
+                            if (r < a.h1 && c < a.w1 && jp < a.natom) {
+                                const size_t o = obase[mt][j] + (uint32_t)(r * a.w1 + c);
+                                cp[o] = rect_pow(bv, lam);
+                                code[o] = (uint8_t)bc;
+                            }
+                        }
+                        best[mt][j] = rm;                      // my = -1 of pooled row R0 + ia/2
+                        bk[mt][j] = rk;
+                    }
+                }
+            }
+        }
+    }
+}
+
+struct EngineF32 {
+    const float* fa;   // [MT][36] patch fragments (registers of the caller)
+    float* sD2;        // [D2R][D2C][9]
+    const float* d2;
+    __device__ void load_tile(const PoolArgs& a, int R0, int C0) const {
+        const int ybase = 2 * R0 - 3, xbase = 2 * C0 - 2;
+        for (int e = threadIdx.x; e < D2R * D2C * 9; e += 256) {
+            const int row = e / (D2C * 9), rem = e - row * (D2C * 9);
+            const int y = ybase + row, x = xbase + rem / 9, ch = rem % 9;
+            sD2[e] = (y >= 0 && y < a.H2 && x >= 0 && x < a.W2) ? d2[((size_t)y * a.W2 + x) * 9 + ch] : 0.f;
+        }
+    }
+    // A on A-row ia for the 16 positions whose tile column (minus 2) is col0 + 2*lane.
+    __device__ void mfma_row(int ia, int col, f4* acc) const {
+        const int grp = (threadIdx.x & 63) >> 4;
+        const float* bs = sD2 + ((ia + grp) * D2C + col) * 9;
+        float fb[36];
+#pragma unroll
+        for (int t = 0; t < 36; ++t) fb[t] = bs[t];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            f4 r = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int t = 0; t < 36; ++t) r = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[mt * 36 + t], fb[t], r, 0, 0, 0);
+            acc[mt] = r;
+        }
+    }
+};
+
+struct EngineBF16 {
+    const bf8* fa;     // [MT][5]
+    uint32_t* sD2;     // [D2R][D2C][5] bf16 pairs
+    const uint32_t* d2;
+    __device__ void load_tile(const PoolArgs& a, int R0, int C0) const {
+        const int ybase = 2 * R0 - 3, xbase = 2 * C0 - 2;
+        for (int e = threadIdx.x; e < D2R * D2C * 5; e += 256) {
+            const int row = e / (D2C * 5), rem = e - row * (D2C * 5);
+            const int y = ybase + row, x = xbase + rem / 5, pr = rem % 5;
+            sD2[e] = (y >= 0 && y < a.H2 && x >= 0 && x < a.W2) ? d2[((size_t)y * a.W2 + x) * 5 + pr] : 0u;
+        }
+    }
+    __device__ void mfma_row(int ia, int col, f4* acc) const {
+        const int grp = (threadIdx.x & 63) >> 4;
+        const uint32_t* bs = sD2 + ((ia + grp) * D2C + col) * 5;
+        bf8 fb[5];
+#pragma unroll
+        for (int s = 0; s < 5; ++s) fb[s] = load_bf8(bs + 4 * s);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            f4 r = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 5; ++s) r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[mt * 5 + s], fb[s], r, 0, 0, 0);
+            acc[mt] = r;
+        }
+    }
+};
+
+__global__ __launch_bounds__(256, 2) void k_corr_pool_f32(const float* __restrict__ d1,
+                                                          const float* __restrict__ d2, PoolArgs a,
+                                                          float lam, float* __restrict__ cp,
+                                                          uint8_t* __restrict__ code) {
+    __shared__ float sD2[D2R * D2C * 9];
+    __shared__ float sCarry[WAVES][ARS][16 * MT];
+    const int pt = blockIdx.x % a.n_ptiles, R0 = (blockIdx.x / a.n_ptiles) * TR;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = lane & 15, grp = lane >> 4;
+    // Patch fragments: lane (n, grp) holds row grp of the 4x4 patch of patch
+    // pbase + 16 mt + n: 4 pixels x 9 channels, contiguous in D1.
+    float fa[MT * 36];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int j = pt * PT + wave * 16 * MT + mt * 16 + n;
+        if (j < a.natom) {
+            const int b = j / a.n0x, aa = j - b * a.n0x;
+            const float* src = d1 + ((size_t)(4 * b + grp) * a.W1 + 4 * aa) * 9;
+#pragma unroll
+            for (int t = 0; t < 36; ++t) fa[mt * 36 + t] = src[t] * 0.0625f;   // the 1/16 of Eq. (3), exact
+        } else {
+#pragma unroll
+            for (int t = 0; t < 36; ++t) fa[mt * 36 + t] = 0.f;
+        }
+    }
+    EngineF32 eng{fa, sD2, d2};
+    sweep_band(eng, a, pt, R0, lam, cp, code, sCarry[wave]);
+}
+
 // BF16 variant: descriptors stored as H x W x 10 bf16 (9 channels + a zero),
 // so each 16-lane group's K slice is 4 pixels x 10 = 40 values = 5 steps of
 // the 16x16x32 MFMA (K = 160, of which 16 are zero pads).
@@ -170,18 +249,15 @@ __global__ __launch_bounds__(256, 2) void k_corr_pool_bf16(const uint16_t* __res
                                                            const uint16_t* __restrict__ d2, PoolArgs a,
                                                            float lam, float* __restrict__ cp,
                                                            uint8_t* __restrict__ code) {
-    __shared__ uint32_t sD2[D2R * D2C * 5];  // bf16 pairs
-    __shared__ float sA[WAVES][16 * MT][3][NPOS];
-    int pt, R0, C0;
-    block_coords(a, pt, R0, C0);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ uint32_t sD2[D2R * D2C * 5];
+    __shared__ float sCarry[WAVES][ARS][16 * MT];
+    const int pt = blockIdx.x % a.n_ptiles, R0 = (blockIdx.x / a.n_ptiles) * TR;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n = lane & 15, grp = lane >> 4;
-    const int pbase = pt * PT + wave * 16 * MT;
-
-    bf8 fa[MT][5];
+    bf8 fa[MT * 5];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-        const int j = pbase + mt * 16 + n;
+        const int j = pt * PT + wave * 16 * MT + mt * 16 + n;
         uint32_t tmp[20];
         if (j < a.natom) {
             const int b = j / a.n0x, aa = j - b * a.n0x;
@@ -193,41 +269,12 @@ __global__ __launch_bounds__(256, 2) void k_corr_pool_bf16(const uint16_t* __res
             for (int t = 0; t < 20; ++t) tmp[t] = 0u;
         }
 #pragma unroll
-        for (int s = 0; s < 5; ++s) fa[mt][s] = load_bf8(tmp + 4 * s);
+        for (int t = 0; t < 20; ++t) tmp[t] = bf16x2_scale16(tmp[t]);   // the 1/16 of Eq. (3)
+#pragma unroll
+        for (int s = 0; s < 5; ++s) fa[mt * 5 + s] = load_bf8(tmp + 4 * s);
     }
-    const int ybase = 2 * R0 - 3, xbase = 2 * C0 - 3;
-    const uint32_t* d2u = (const uint32_t*)d2;
-    for (int e = tid; e < D2R * D2C * 5; e += 256) {
-        const int row = e / (D2C * 5), rem = e - row * (D2C * 5);
-        const int y = ybase + row, x = xbase + rem / 5, pr = rem % 5;
-        sD2[e] = (y >= 0 && y < a.H2 && x >= 0 && x < a.W2) ? d2u[((size_t)y * a.W2 + x) * 5 + pr] : 0u;
-    }
-    __syncthreads();
-
-    for (int ia = 0; ia < ARS; ++ia) {
-        const int slot = ia % 3;
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-            const uint32_t* bs = sD2 + ((ia + grp) * D2C + 16 * nt + n) * 5;
-            bf8 fb[5];
-#pragma unroll
-            for (int s = 0; s < 5; ++s) fb[s] = load_bf8(bs + 4 * s);
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int s = 0; s < 5; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[mt][s], fb[s], acc, 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    sA[wave][mt * 16 + 4 * grp + r][slot][16 * nt + n] = fmaxf(acc[r] * 0.0625f, 0.f);
-            }
-        }
-        if (ia >= 2 && !(ia & 1)) {
-            __syncthreads();
-            pool_row(sA[wave], ia, R0, C0, pbase, a, lam, cp, code);
-            __syncthreads();
-        }
-    }
+    EngineBF16 eng{fa, sD2, (const uint32_t*)d2};
+    sweep_band(eng, a, pt, R0, lam, cp, code, sCarry[wave]);
 }
 
 PoolArgs make_pool_args(const Geom& g, int& nblocks) {
@@ -240,9 +287,8 @@ PoolArgs make_pool_args(const Geom& g, int& nblocks) {
     a.h1 = g.h[1];
     a.w1 = g.w[1];
     a.n_ptiles = (a.natom + PT - 1) / PT;
-    a.n_rtiles = (a.h1 + TR - 1) / TR;
-    const int n_ctiles = (a.w1 + TC - 1) / TC;
-    nblocks = a.n_ptiles * a.n_rtiles * n_ctiles;
+    a.n_steps = (a.w1 + 15) / 16;
+    nblocks = a.n_ptiles * ((a.h1 + TR - 1) / TR);
     return a;
 }
 
