@@ -92,6 +92,35 @@ def time_path(dm, torch, img1, img2, precision, steps, warmup):
     return dt, matches, stages, m.plan
 
 
+def time_fwd_bwd(dm, torch, d1, d2, precision, recompute, steps, warmup):
+    """Leaf descriptors -> pyramid -> L = sum of top-map maxima -> dL/dD1, dL/dD2."""
+    pyr = dm.Pyramid(d1, d2, dm.params(precision=precision), recompute)
+    P = pyr.top_shape()[0] * pyr.top_shape()[1]
+
+    def step():
+        top = pyr.forward()
+        flat = top.reshape(P, -1)
+        dtop = torch.zeros_like(flat)
+        dtop.scatter_(1, flat.argmax(1, keepdim=True), 1.0)
+        return pyr.backward(dtop.view_as(top))
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    dm.timing_enable(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    stages = dm.timing_read()
+    dm.timing_enable(False)
+    return dt, stages
+
+
 def within_1px(a, b):
     """Fraction of b's matches whose source patch has a match in a within 1 px."""
     ga = {(int(r[0]), int(r[1])): r for r in a}
@@ -150,6 +179,15 @@ def main():
         dt, matches, stages, pl = time_path(dm, torch, img1, img2, prec, args.steps, args.warmup)
         res[prec] = dict(ms=dt * 1e3, pairs_s=1.0 / dt, matches=matches, stages=stages, plan=pl)
     agree = within_1px(res["bf16"]["matches"], res["fp32"]["matches"])
+    # fwd+bwd on leaf descriptors of the same pair
+    d1 = dm.descriptors(img1)
+    d2 = dm.descriptors(img2)
+    fb = {}
+    for prec in ("fp32", "bf16"):
+        for rc in (False, True):
+            dt, stages = time_fwd_bwd(dm, torch, d1, d2, prec, rc, max(3, args.steps // 2), 2)
+            fb[f"{prec}{'_recompute' if rc else ''}"] = dict(pairs_s=round(1.0 / dt, 3), ms_per_step=round(dt * 1e3, 4),
+                                                          stages=stages)
     head = res["bf16"]
     rows = roofline_of(head["stages"], head["plan"], "bf16")
     dom = rows[0]
@@ -175,6 +213,11 @@ def main():
                  "matches": int(len(res["fp32"]["matches"]))},
         "bf16": {"pairs_s": round(head["pairs_s"], 3), "ms_per_step": round(head["ms"], 4),
                  "matches": int(len(head["matches"])), "within_1px_of_fp32": round(agree, 5)},
+        "fwd_bwd": {k: {kk: vv for kk, vv in v.items() if kk != "stages"} for k, v in fb.items()},
+        "fwd_bwd_top_kernels_bf16": sorted([(n + ("" if l < 0 else "_l%d" % l), round(t / c, 4))
+                                            for n, l, c, t in fb["bf16"]["stages"]], key=lambda x: -x[1])[:6],
+        "fwd_bwd_top_kernels_fp32": sorted([(n + ("" if l < 0 else "_l%d" % l), round(t / c, 4))
+                                            for n, l, c, t in fb["fp32"]["stages"]], key=lambda x: -x[1])[:6],
         "roofline": {"bound": dom["bound"], "kernel": dom["kernel"], "achieved": round(dom["achieved"], 2),
                      "peak": dom["peak"], "unit": dom["unit"], "frac": round(dom["frac"], 4), "traffic": None,
                      "avg_ms": round(dom["avg_ms"], 5)},

@@ -155,6 +155,59 @@ dm_status dm_match_images(const float* img1, int W1, int H1, int ld1,
                           const dm_params* prm, void* ws, size_t ws_bytes,
                           dm_match* out, int capacity, int* n_out, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Gradient of a loss on the top-level maps (no counterpart in the paper).
+ *
+ * dm_pyramid_forward computes the pyramid of two descriptor fields (Eqs.
+ * (3)-(12), Algorithm 1) and keeps what the backward needs in the caller's
+ * `saved` buffer: C'_0 and its argmax codes, C_top, and (unless recompute
+ * is set) C'_l and codes of every coarser level.  dm_pyramid_backward takes
+ * dL/dC_top and returns dL/dD1 and dL/dD2 through the hand-written adjoints of
+ * rectification, the shifted average over existing children, the max-pool
+ * routed to the stored argmax, and the bottom correlation; with recompute set
+ * it first recomputes the coarse levels from C'_0 into scratch.
+ * Precision: DM_FP32 (FP32 MFMA GEMMs), DM_BF16 (BF16 operands, FP32
+ * accumulation and pyramid) or DM_FP64 (every stage in FP64, direct
+ * kernels; meant for finite-difference checks on small inputs).
+ * --------------------------------------------------------------------------- */
+typedef struct {
+    dm_plan_info geom;         /* levels and map sizes (its offsets belong to the match calls) */
+    int32_t recompute;
+    int32_t nsplit;            /* position splits of the dD1 contraction */
+    uint64_t saved_bytes;      /* size of `saved` */
+    uint64_t scratch_bytes;    /* size of `scratch` */
+    /* Byte offsets of C'_l, codes_l (l < lmax) and C_top: in `saved` when the
+     * matching *_in_saved flag is 1, else in `scratch`. */
+    uint64_t off_cp[DM_MAX_LEVELS], off_code[DM_MAX_LEVELS];
+    int32_t cp_in_saved[DM_MAX_LEVELS];
+    uint64_t off_top;          /* in `saved` */
+    uint64_t off_valid, off_bf1, off_bf2, off_g[2], off_part, off_t;  /* in `scratch` */
+} dm_grad_plan;
+
+/* Plans dm_pyramid_forward / dm_pyramid_backward for a pair of sizes.
+ * Host only.  Errors as dm_plan; DM_ERR_UNSUPPORTED if the pyramid has a
+ * single level (N_max = 4: no pooled level to route through). */
+dm_status dm_plan_grad(const dm_params* prm, int W1, int H1, int W2, int H2, int recompute, dm_grad_plan* out);
+
+/* Forward pyramid of descriptor fields d1 (H1 x W1 x 9) and d2 (H2 x W2 x 9),
+ * float32 (float64 when prm->precision == DM_FP64).  C_top, [gy][gx][h][w]
+ * of the top level (maps of non-existing lattice points are zeros), is left
+ * in `saved` at plan.off_top.  Errors: DM_ERR_INVALID_ARG, DM_ERR_SHAPE,
+ * DM_ERR_WORKSPACE (either buffer too small), DM_ERR_UNSUPPORTED, DM_ERR_HIP. */
+dm_status dm_pyramid_forward(const void* d1, int W1, int H1, const void* d2, int W2, int H2,
+                             const dm_params* prm, int recompute, void* saved, size_t saved_bytes,
+                             void* scratch, size_t scratch_bytes, hipStream_t stream);
+
+/* Backward of the pyramid left in `saved` by dm_pyramid_forward with the
+ * same inputs and parameters: dc_top = dL/dC_top (layout of C_top; entries of
+ * non-existing patches are ignored) -> dd1 (H1 x W1 x 9) and dd2 (H2 x W2 x
+ * 9), overwritten; pixels outside every atomic patch get 0 in dd1.
+ * Deterministic.  Errors as dm_pyramid_forward. */
+dm_status dm_pyramid_backward(const void* d1, int W1, int H1, const void* d2, int W2, int H2,
+                              const dm_params* prm, int recompute, const void* saved, size_t saved_bytes,
+                              const void* dc_top, void* dd1, void* dd2, void* scratch, size_t scratch_bytes,
+                              hipStream_t stream);
+
 /* Per-stage timing (for benchmarks and profiling).  While enabled, every
  * kernel launch the library makes is bracketed by two HIP events recorded on
  * the stream of the call, so the measured time is that kernel's own time on

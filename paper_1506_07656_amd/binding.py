@@ -53,6 +53,14 @@ class PlanInfo(ctypes.Structure):
                 ("workspace_bytes", c_uint64)]
 
 
+class GradPlan(ctypes.Structure):
+    _fields_ = [("geom", PlanInfo), ("recompute", c_int32), ("nsplit", c_int32),
+                ("saved_bytes", c_uint64), ("scratch_bytes", c_uint64),
+                ("off_cp", c_uint64 * _L), ("off_code", c_uint64 * _L), ("cp_in_saved", c_int32 * _L),
+                ("off_top", c_uint64), ("off_valid", c_uint64), ("off_bf1", c_uint64), ("off_bf2", c_uint64),
+                ("off_g", c_uint64 * 2), ("off_part", c_uint64), ("off_t", c_uint64)]
+
+
 class StageTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 40), ("level", c_int32), ("count", c_int32), ("total_ms", ctypes.c_double)]
 
@@ -66,6 +74,12 @@ SIGNATURES = {
                                      c_void_p, c_size_t, c_void_p, c_int, c_void_p, c_void_p]),
     "dm_match_images": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_int, c_int,
                                 POINTER(Params), c_void_p, c_size_t, c_void_p, c_int, c_void_p, c_void_p]),
+    "dm_plan_grad": (c_int, [POINTER(Params), c_int, c_int, c_int, c_int, c_int, POINTER(GradPlan)]),
+    "dm_pyramid_forward": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int, c_int, POINTER(Params), c_int,
+                                   c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]),
+    "dm_pyramid_backward": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int, c_int, POINTER(Params), c_int,
+                                    c_void_p, c_size_t, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                                    c_void_p]),
     "dm_timing_enable": (c_int, [c_int]),
     "dm_timing_read": (c_int, [POINTER(StageTime), c_int, POINTER(c_int)]),
     "dm_status_string": (c_char_p, [c_int]),
@@ -253,6 +267,92 @@ def workspace_views(ws: torch.Tensor, pl: PlanInfo) -> dict:
     out["desc1"] = view(pl.off_desc1, pl.H1 * pl.W1 * 9, fdt, (pl.H1, pl.W1, 9), fsz)
     out["desc2"] = view(pl.off_desc2, pl.H2 * pl.W2 * 9, fdt, (pl.H2, pl.W2, 9), fsz)
     return out
+
+
+def plan_grad(W1: int, H1: int, W2: int, H2: int, prm: Params | None = None, recompute: bool = False) -> GradPlan:
+    prm = prm or params()
+    out = GradPlan()
+    _check(lib().dm_plan_grad(ctypes.byref(prm), W1, H1, W2, H2, int(recompute), ctypes.byref(out)))
+    return out
+
+
+class Pyramid:
+    """State of dm_pyramid_forward for one pair of descriptor fields: the
+    `saved` buffer the backward needs and a transient `scratch` buffer."""
+
+    def __init__(self, d1: torch.Tensor, d2: torch.Tensor, prm: Params | None = None, recompute: bool = False):
+        self.prm = prm or params()
+        fdt = torch.float64 if self.prm.precision == DM_FP64 else torch.float32
+        self.d1 = _dev(d1, fdt, 3, "d1").contiguous()
+        self.d2 = _dev(d2, fdt, 3, "d2").contiguous()
+        H1, W1, _ = self.d1.shape
+        H2, W2, _ = self.d2.shape
+        self.dims = (W1, H1, W2, H2)
+        self.recompute = bool(recompute)
+        self.plan = plan_grad(W1, H1, W2, H2, self.prm, self.recompute)
+        dev = self.d1.device
+        self.saved = torch.empty(int(self.plan.saved_bytes), dtype=torch.uint8, device=dev)
+        self.scratch = torch.empty(int(self.plan.scratch_bytes), dtype=torch.uint8, device=dev)
+        self.fdt = fdt
+
+    def top_shape(self):
+        g = self.plan.geom
+        L = g.lmax
+        return (g.gy[L], g.gx[L], g.h[L], g.w[L])
+
+    def top(self) -> torch.Tensor:
+        shp = self.top_shape()
+        n = shp[0] * shp[1] * shp[2] * shp[3]
+        es = 8 if self.fdt == torch.float64 else 4
+        o = int(self.plan.off_top)
+        return self.saved[o:o + n * es].view(self.fdt).view(*shp)
+
+    def forward(self):
+        W1, H1, W2, H2 = self.dims
+        _check(lib().dm_pyramid_forward(c_void_p(self.d1.data_ptr()), W1, H1, c_void_p(self.d2.data_ptr()), W2, H2,
+                                        ctypes.byref(self.prm), int(self.recompute), c_void_p(self.saved.data_ptr()),
+                                        self.saved.numel(), c_void_p(self.scratch.data_ptr()), self.scratch.numel(),
+                                        _stream()))
+        return self.top()
+
+    def backward(self, dtop: torch.Tensor):
+        W1, H1, W2, H2 = self.dims
+        dtop = dtop.to(self.fdt).contiguous()
+        assert tuple(dtop.shape) == self.top_shape()
+        dd1 = torch.empty_like(self.d1)
+        dd2 = torch.empty_like(self.d2)
+        _check(lib().dm_pyramid_backward(c_void_p(self.d1.data_ptr()), W1, H1, c_void_p(self.d2.data_ptr()), W2, H2,
+                                         ctypes.byref(self.prm), int(self.recompute),
+                                         c_void_p(self.saved.data_ptr()), self.saved.numel(),
+                                         c_void_p(dtop.data_ptr()), c_void_p(dd1.data_ptr()), c_void_p(dd2.data_ptr()),
+                                         c_void_p(self.scratch.data_ptr()), self.scratch.numel(), _stream()))
+        return dd1, dd2
+
+
+class DMPyramid(torch.autograd.Function):
+    """C_top = pyramid(d1, d2) with the library's hand-written backward.
+
+    forward(d1, d2, prm, recompute) -> C_top [gy, gx, h, w] of the top level
+    (maps of non-existing top patches are zeros)."""
+
+    @staticmethod
+    def forward(ctx, d1, d2, prm=None, recompute=False):
+        pyr = Pyramid(d1.detach(), d2.detach(), prm, recompute)
+        top = pyr.forward().clone()
+        ctx.pyr = pyr
+        return top
+
+    @staticmethod
+    def backward(ctx, dtop):
+        dd1, dd2 = ctx.pyr.backward(dtop)
+        ctx.pyr = None
+        return dd1, dd2, None, None
+
+
+def top_loss(top: torch.Tensor) -> torch.Tensor:
+    """Sum over top-level patches of the maximum of their map (the gradient
+    goes to the first maximum in raster order)."""
+    return top.reshape(top.shape[0] * top.shape[1], -1).max(1).values.sum()
 
 
 def timing_enable(on: bool = True):

@@ -3,6 +3,8 @@
 // path on the caller's stream; nothing here allocates device memory.
 #include <string.h>
 
+#include <type_traits>
+
 #include "dm_internal.h"
 
 namespace dm {
@@ -95,9 +97,123 @@ dm_status check_out(const dm_plan_info& pi, dm_match* out, int capacity, int* n_
     return DM_OK;
 }
 
+dm_status check_grad_bufs(const dm_grad_plan& gp, const void* d1, const void* d2, const void* saved,
+                          size_t saved_bytes, void* scratch, size_t scratch_bytes) {
+    if (!d1 || !d2) return fail(DM_ERR_INVALID_ARG, "descriptor pointer is null");
+    if (!saved || !scratch) return fail(DM_ERR_INVALID_ARG, "saved or scratch buffer is null");
+    if ((reinterpret_cast<uintptr_t>(saved) | reinterpret_cast<uintptr_t>(scratch)) & 255)
+        return fail(DM_ERR_INVALID_ARG, "saved and scratch buffers must be 256-byte aligned");
+    if (saved_bytes < gp.saved_bytes || scratch_bytes < gp.scratch_bytes)
+        return fail(DM_ERR_WORKSPACE, "buffers hold %zu / %zu bytes, the plan needs %llu / %llu", saved_bytes,
+                    scratch_bytes, (unsigned long long)gp.saved_bytes, (unsigned long long)gp.scratch_bytes);
+    return DM_OK;
+}
+
+// Pointers of the grad layout.
+template <typename T>
+struct GradBufs {
+    const dm_grad_plan& gp;
+    void* saved;
+    void* scratch;
+    T* cp(int l) const { return at<T>(gp.cp_in_saved[l] ? saved : scratch, gp.off_cp[l]); }
+    uint8_t* code(int l) const { return at<uint8_t>(gp.cp_in_saved[l] ? saved : scratch, gp.off_code[l]); }
+    T* top() const { return at<T>(saved, gp.off_top); }
+    uint8_t* vt() const { return at<uint8_t>(scratch, gp.off_valid); }
+    T* gbuf(int i) const { return at<T>(scratch, gp.off_g[i]); }
+};
+
+// Levels first..last of the pyramid (C'_l and codes, or C_top at lmax).
+template <typename T>
+dm_status run_levels(const GradBufs<T>& B, const Geom& g, int first, int last, T lam, hipStream_t s) {
+    for (int l = first; l <= last; ++l)
+        DM_LAUNCH("level", l, launch_level<T>(l, B.cp(l - 1), B.vt(), g, lam, l < g.lmax ? B.cp(l) : nullptr,
+                                              l < g.lmax ? B.code(l) : nullptr, B.top(), s));
+    return DM_OK;
+}
+
+template <typename T>
+dm_status grad_forward(const T* d1, const T* d2, const dm_grad_plan& gp, const dm_params* prm, void* saved,
+                       void* scratch, hipStream_t s) {
+    const Geom g = make_geom(gp.geom);
+    const GradBufs<T> B{gp, saved, scratch};
+    const T lam = (T)prm->lambda;
+    DM_LAUNCH("valid_init", -1, launch_valid_init(g, B.vt(), s));
+    if constexpr (std::is_same<T, double>::value) {
+        DM_LAUNCH("corr_pool_ref", 0, launch_corr_pool_ref<double>(d1, d2, g, lam, B.cp(0), B.code(0), s));
+    } else if (prm->precision == DM_BF16) {
+        uint16_t* b1 = at<uint16_t>(scratch, gp.off_bf1);
+        uint16_t* b2 = at<uint16_t>(scratch, gp.off_bf2);
+        DM_LAUNCH("to_bf16", -1, launch_to_bf16(d1, g.W1 * g.H1, b1, s));
+        DM_LAUNCH("to_bf16", -1, launch_to_bf16(d2, g.W2 * g.H2, b2, s));
+        DM_LAUNCH("corr_pool_bf16", 0, launch_corr_pool_bf16(b1, b2, g, lam, B.cp(0), B.code(0), s));
+    } else {
+        DM_LAUNCH("corr_pool_f32", 0, launch_corr_pool_f32(d1, d2, g, lam, B.cp(0), B.code(0), s));
+    }
+    return run_levels<T>(B, g, 1, g.lmax, lam, s);
+}
+
+template <typename T>
+dm_status grad_backward(const T* d1, const T* d2, const dm_grad_plan& gp, const dm_params* prm, void* saved,
+                        const T* dtop, T* dd1, T* dd2, void* scratch, hipStream_t s) {
+    const Geom g = make_geom(gp.geom);
+    const GradBufs<T> B{gp, saved, scratch};
+    const T lam = (T)prm->lambda;
+    DM_LAUNCH("valid_init", -1, launch_valid_init(g, B.vt(), s));
+    if (gp.recompute && g.lmax > 1) {
+        const dm_status st = run_levels<T>(B, g, 1, g.lmax - 1, lam, s);
+        if (st != DM_OK) return st;
+    }
+    for (int l = g.lmax; l >= 1; --l) {
+        const T* gcur = l < g.lmax ? B.gbuf(l & 1) : nullptr;
+        DM_LAUNCH("bwd_level", l,
+                  launch_bwd_level<T>(l, dtop, B.top(), gcur, l < g.lmax ? B.code(l) : nullptr, B.cp(l - 1), B.vt(),
+                                      g, lam, B.gbuf((l - 1) & 1), s));
+    }
+    const int mode = std::is_same<T, double>::value ? 2 : (prm->precision == DM_BF16 ? 1 : 0);
+    DM_LAUNCH("bwd_bottom", 0,
+              launch_bwd_bottom<T>(mode, B.gbuf(0), B.code(0), d1, d2, g, at<T>(scratch, gp.off_part),
+                                   at<T>(scratch, gp.off_t), dd1, dd2, s));
+    return DM_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+dm_status dm_plan_grad(const dm_params* prm, int W1, int H1, int W2, int H2, int recompute, dm_grad_plan* out) {
+    clear_error();
+    return plan_grad(prm, W1, H1, W2, H2, recompute, out);
+}
+
+dm_status dm_pyramid_forward(const void* d1, int W1, int H1, const void* d2, int W2, int H2, const dm_params* prm,
+                             int recompute, void* saved, size_t saved_bytes, void* scratch, size_t scratch_bytes,
+                             hipStream_t stream) {
+    clear_error();
+    dm_grad_plan gp;
+    dm_status st = plan_grad(prm, W1, H1, W2, H2, recompute, &gp);
+    if (st != DM_OK) return st;
+    if ((st = check_grad_bufs(gp, d1, d2, saved, saved_bytes, scratch, scratch_bytes)) != DM_OK) return st;
+    if (prm->precision == DM_FP64)
+        return grad_forward<double>((const double*)d1, (const double*)d2, gp, prm, saved, scratch, stream);
+    return grad_forward<float>((const float*)d1, (const float*)d2, gp, prm, saved, scratch, stream);
+}
+
+dm_status dm_pyramid_backward(const void* d1, int W1, int H1, const void* d2, int W2, int H2, const dm_params* prm,
+                              int recompute, const void* saved, size_t saved_bytes, const void* dc_top, void* dd1,
+                              void* dd2, void* scratch, size_t scratch_bytes, hipStream_t stream) {
+    clear_error();
+    dm_grad_plan gp;
+    dm_status st = plan_grad(prm, W1, H1, W2, H2, recompute, &gp);
+    if (st != DM_OK) return st;
+    if ((st = check_grad_bufs(gp, d1, d2, saved, saved_bytes, scratch, scratch_bytes)) != DM_OK) return st;
+    if (!dc_top || !dd1 || !dd2) return fail(DM_ERR_INVALID_ARG, "gradient pointer is null");
+    void* sv = const_cast<void*>(saved);
+    if (prm->precision == DM_FP64)
+        return grad_backward<double>((const double*)d1, (const double*)d2, gp, prm, sv, (const double*)dc_top,
+                                     (double*)dd1, (double*)dd2, scratch, stream);
+    return grad_backward<float>((const float*)d1, (const float*)d2, gp, prm, sv, (const float*)dc_top, (float*)dd1,
+                                (float*)dd2, scratch, stream);
+}
 
 dm_status dm_default_params(dm_params* p) {
     clear_error();

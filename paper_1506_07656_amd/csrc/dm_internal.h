@@ -66,6 +66,7 @@ dm_status check_hip(hipError_t e, const char* what);
 // Host planning (dm_plan.cpp).
 dm_status plan_pair(const dm_params* prm, int W1, int H1, int W2, int H2, dm_plan_info* out);
 dm_status check_params(const dm_params* prm);
+dm_status plan_grad(const dm_params* prm, int W1, int H1, int W2, int H2, int recompute, dm_grad_plan* out);
 Geom make_geom(const dm_plan_info& pi);
 
 // Descriptor parameters with the Gaussian taps precomputed on the host.
@@ -95,6 +96,14 @@ template <typename T>
 hipError_t launch_level(int l, const T* prev, const uint8_t* vt, const Geom& g, T lam, T* cp,
                         uint8_t* code, T* top, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s);
+template <typename T>
+hipError_t launch_bwd_level(int l, const T* dtop, const T* top, const T* gp_cur, const uint8_t* code_cur,
+                            const T* cp_prev, const uint8_t* vt, const Geom& g, T lam, T* gp_prev, hipStream_t s);
+// mode 0: FP32 MFMA, 1: BF16 MFMA operands with FP32 accumulation, 2: reference kernels (any T)
+template <typename T>
+hipError_t launch_bwd_bottom(int mode, const T* gp, const uint8_t* code, const T* d1, const T* d2, const Geom& g,
+                             T* part, T* tbuf, T* dd1, T* dd2, hipStream_t s);
+int bwd_nsplit(const Geom& g);
 template <typename T>
 hipError_t launch_backtrack(int l, const T* cp_prev, const uint8_t* code_prev, const T* u_cur,
                             const uint8_t* code_cur, const T* top, const uint8_t* vt, const Geom& g,

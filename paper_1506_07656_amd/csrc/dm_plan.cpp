@@ -157,6 +157,50 @@ dm_status plan_pair(const dm_params* prm, int W1, int H1, int W2, int H2, dm_pla
     return DM_OK;
 }
 
+dm_status plan_grad(const dm_params* prm, int W1, int H1, int W2, int H2, int recompute, dm_grad_plan* out) {
+    if (!out) return fail(DM_ERR_INVALID_ARG, "plan output is null");
+    dm_plan_info pi;
+    dm_status st = plan_pair(prm, W1, H1, W2, H2, &pi);
+    if (st != DM_OK) return st;
+    if (pi.lmax == 0) return fail(DM_ERR_UNSUPPORTED, "the pyramid has a single level; nothing to route a gradient through");
+    memset(out, 0, sizeof(*out));
+    out->geom = pi;
+    out->recompute = recompute ? 1 : 0;
+    const Geom g = make_geom(pi);
+    const bool fp64 = prm->precision == DM_FP64;
+    out->nsplit = fp64 ? 1 : bwd_nsplit(g);
+    const uint64_t es = fp64 ? 8 : 4;
+    uint64_t so = 0, xo = 0;  // saved / scratch cursors
+    auto take = [](uint64_t& cur, uint64_t bytes) {
+        const uint64_t o = cur;
+        cur = align256(cur + bytes);
+        return o;
+    };
+    for (int l = 0; l < pi.lmax; ++l) {
+        const uint64_t n = (uint64_t)pi.gx[l] * pi.gy[l] * pi.h[l + 1] * pi.w[l + 1];
+        const bool keep = l == 0 || !recompute;
+        out->cp_in_saved[l] = keep ? 1 : 0;
+        out->off_cp[l] = take(keep ? so : xo, n * es);
+        out->off_code[l] = take(keep ? so : xo, n);
+    }
+    out->off_top = take(so, (uint64_t)pi.gx[pi.lmax] * pi.gy[pi.lmax] * pi.h[pi.lmax] * pi.w[pi.lmax] * es);
+    const int glx = (W1 - 1) / 4 + 1, gly = (H1 - 1) / 4 + 1;
+    const uint64_t vstride = align256((uint64_t)(glx > gly ? glx : gly));
+    out->off_valid = take(xo, (uint64_t)(pi.lmax + 1) * 2 * vstride);
+    if (prm->precision == DM_BF16) {
+        out->off_bf1 = take(xo, (uint64_t)W1 * H1 * 10 * 2);
+        out->off_bf2 = take(xo, (uint64_t)W2 * H2 * 10 * 2);
+    }
+    const uint64_t ng = (uint64_t)pi.gx[0] * pi.gy[0] * pi.h[1] * pi.w[1];  // largest pooled level
+    out->off_g[0] = take(xo, ng * es);
+    out->off_g[1] = take(xo, ng * es);
+    out->off_part = take(xo, (uint64_t)out->nsplit * pi.n_atomic * 144 * es);
+    out->off_t = take(xo, (uint64_t)W2 * H2 * 144 * es);
+    out->saved_bytes = so;
+    out->scratch_bytes = xo;
+    return DM_OK;
+}
+
 Geom make_geom(const dm_plan_info& pi) {
     Geom g;
     memset(&g, 0, sizeof(g));

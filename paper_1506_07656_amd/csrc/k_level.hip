@@ -190,8 +190,9 @@ __global__ __launch_bounds__(256) void k_level_top(LevelArgs a, const T* __restr
         const int orow = fdiv(rem, a.f_tco);
         const int qy = R0 + orow, qx = C0 + rem - orow * a.TCo;
         const int P = pblk * a.PB + k;
-        if (!sp[k].valid || qy >= a.h || qx >= a.w) continue;
-        const T A = staged_aggregate(a, sp[k], prev, qy, qx);
+        if (P >= a.gx * a.gy || qy >= a.h || qx >= a.w) continue;
+        // maps of non-existing top patches are written as zeros
+        const T A = sp[k].valid ? staged_aggregate(a, sp[k], prev, qy, qx) : T(0);
         top[((size_t)P * a.h + qy) * a.w + qx] = rect_pow(A, lam);
     }
 }

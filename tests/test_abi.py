@@ -109,3 +109,29 @@ def test_match_validation_before_any_launch():
                             ctypes.c_void_p(0x2000), None) == -2
     assert L.dm_descriptors(ctypes.c_void_p(0x1000), 8, 5, 4, ctypes.byref(dm.params()),
                             ctypes.c_void_p(0x2000), None) == -2
+
+
+def test_grad_plan_layout_and_errors():
+    gp = dm.plan_grad(256, 192, 256, 192, dm.params(), recompute=False)
+    assert gp.geom.lmax == 6 and gp.nsplit >= 1
+    assert all(gp.cp_in_saved[i] == 1 for i in range(gp.geom.lmax))
+    gr = dm.plan_grad(256, 192, 256, 192, dm.params(), recompute=True)
+    assert gr.cp_in_saved[0] == 1 and all(gr.cp_in_saved[i] == 0 for i in range(1, gr.geom.lmax))
+    assert gr.saved_bytes < gp.saved_bytes
+    g64 = dm.plan_grad(48, 48, 48, 48, dm.params(precision="fp64", max_patch=64))
+    assert g64.nsplit == 1 and g64.geom.lmax == 4
+    with pytest.raises(dm.DMError) as e:
+        dm.plan_grad(4, 4, 4, 4, dm.params())
+    assert e.value.status == -5
+    L = dm.lib()
+    prm = dm.params()
+    # validation happens before anything is enqueued (fake device addresses)
+    st = L.dm_pyramid_forward(ctypes.c_void_p(0x1000), 256, 192, ctypes.c_void_p(0x2000), 256, 192,
+                              ctypes.byref(prm), 0, ctypes.c_void_p(0x10000), gp.saved_bytes - 1,
+                              ctypes.c_void_p(0x20000), gp.scratch_bytes, None)
+    assert st == -3
+    st = L.dm_pyramid_backward(ctypes.c_void_p(0x1000), 256, 192, ctypes.c_void_p(0x2000), 256, 192,
+                               ctypes.byref(prm), 0, ctypes.c_void_p(0x10000), gp.saved_bytes, None,
+                               ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), ctypes.c_void_p(0x20000),
+                               gp.scratch_bytes, None)
+    assert st == -1

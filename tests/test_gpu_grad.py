@@ -1,0 +1,156 @@
+"""GPU gradient of L = sum over top-level patches of the map maximum with
+respect to both descriptor fields: FP64 central differences and the FP64
+oracle on the central 48x48 sub-pair, the oracle at full 256x192 size,
+recompute on/off, BF16 vs FP32, and the autograd Function."""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1506_07656_amd as dm
+import synth
+from oracle import dm_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@functools.lru_cache(maxsize=None)
+def c4_descriptors():
+    p = synth.make_pair("c4")
+    return O.descriptors(p["img1"]), O.descriptors(p["img2"])
+
+
+def sub_pair():
+    D1, D2 = c4_descriptors()
+    return (np.ascontiguousarray(D1[72:120, 104:152]), np.ascontiguousarray(D2[72:120, 104:152]))
+
+
+def gpu_grad(D1, D2, prec, max_patch=0, recompute=False):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    d1 = torch.tensor(D1, dtype=dt, device="cuda")
+    d2 = torch.tensor(D2, dtype=dt, device="cuda")
+    pyr = dm.Pyramid(d1, d2, dm.params(precision=prec, max_patch=max_patch), recompute)
+    top = pyr.forward()
+    t = top.detach().clone().requires_grad_()
+    L = dm.top_loss(t)
+    L.backward()
+    g1, g2 = pyr.backward(t.grad)
+    torch.cuda.synchronize()
+    return float(L), g1.cpu().numpy().astype(np.float64), g2.cpu().numpy().astype(np.float64), pyr
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_fp64_gradient_matches_central_differences():
+    D1, D2 = sub_pair()
+    L0, g1, g2, pyr = gpu_grad(D1, D2, "fp64", max_patch=64)
+    assert pyr.plan.geom.lmax == 4
+    d1 = torch.tensor(D1, dtype=torch.float64, device="cuda")
+    d2 = torch.tensor(D2, dtype=torch.float64, device="cuda")
+    prm = dm.params(precision="fp64", max_patch=64)
+    fwd = dm.Pyramid(d1, d2, prm)
+
+    def loss():
+        return float(dm.top_loss(fwd.forward()))
+
+    eps = 1e-6
+    rng = np.random.default_rng(4)
+    n_each = 512
+    checked = kinks = 0
+    errs = []
+    for which, D, g in ((0, d1, g1), (1, d2, g2)):
+        flat = D.view(-1)
+        for idx in rng.choice(flat.numel(), n_each, replace=False):
+            old = float(flat[idx])
+            flat[idx] = old + eps
+            lp = loss()
+            flat[idx] = old - eps
+            lm = loss()
+            flat[idx] = old
+            fd = (lp - lm) / (2 * eps)
+            if abs((lp - L0) - (L0 - lm)) > 1e-9:      # an argmax flips within +-eps: not differentiable here
+                kinks += 1
+                continue
+            checked += 1
+            errs.append(abs(fd - g.reshape(-1)[idx]))
+    # random directional derivatives of the whole field
+    dirs_ok = 0
+    for k in range(16):
+        v1 = torch.tensor(rng.standard_normal(D1.shape), device="cuda")
+        v2 = torch.tensor(rng.standard_normal(D2.shape), device="cuda")
+        d1 += eps * v1
+        d2 += eps * v2
+        lp = loss()
+        d1 -= 2 * eps * v1
+        d2 -= 2 * eps * v2
+        lm = loss()
+        d1 += eps * v1
+        d2 += eps * v2
+        if abs((lp - L0) - (L0 - lm)) > 1e-9:
+            continue
+        fd = (lp - lm) / (2 * eps)
+        an = float((g1 * v1.cpu().numpy()).sum() + (g2 * v2.cpu().numpy()).sum())
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (k, fd, an)
+        dirs_ok += 1
+    print(f"directional derivatives checked: {dirs_ok} / 16", flush=True)
+    assert dirs_ok >= 4
+    gmax = max(np.abs(g1).max(), np.abs(g2).max())
+    print(f"FD: {checked} coordinates checked, {kinks} kinks skipped, max abs err {max(errs):.2e} "
+          f"(gradient max {gmax:.3e})", flush=True)
+    assert checked > 900
+    assert max(errs) <= 1e-6 * gmax
+
+
+def test_fp64_gradient_matches_oracle():
+    D1, D2 = sub_pair()
+    L, g1, g2, _ = gpu_grad(D1, D2, "fp64", max_patch=64)
+    # the library's lambda parameter is a float32 field: compare at that value
+    lam32 = float(np.float32(1.4))
+    pyr = O.pyramid(D1, D2, O.Params(max_patch=64, lam=lam32), keep_full=True)
+    r1, r2 = O.pyramid_backward(D1, D2, pyr)
+    assert abs(L - O.top_loss(pyr)) < 1e-10 * abs(L)
+    print(f"fp64 vs oracle: rel {rel(g1, r1):.2e} {rel(g2, r2):.2e}", flush=True)
+    assert rel(g1, r1) < 1e-10 and rel(g2, r2) < 1e-10
+
+
+def test_fp32_gradient_matches_oracle_full_size():
+    D1, D2 = c4_descriptors()
+    L, g1, g2, gp = gpu_grad(D1, D2, "fp32")
+    assert gp.plan.geom.lmax == 6
+    pyr = O.pyramid(D1, D2, O.Params(), keep_full=True)
+    r1, r2 = O.pyramid_backward(D1, D2, pyr)
+    e1, e2 = rel(g1, r1), rel(g2, r2)
+    print(f"fp32 256x192: loss {L:.6f} vs {O.top_loss(pyr):.6f}; gradient rel err {e1:.2e} {e2:.2e}", flush=True)
+    assert abs(L - O.top_loss(pyr)) < 1e-5 * abs(L)
+    assert e1 <= 1e-4 and e2 <= 1e-4
+
+
+def test_recompute_gives_identical_gradients():
+    D1, D2 = c4_descriptors()
+    _, a1, a2, _ = gpu_grad(D1, D2, "fp32", recompute=False)
+    _, b1, b2, _ = gpu_grad(D1, D2, "fp32", recompute=True)
+    np.testing.assert_array_equal(a1, b1)
+    np.testing.assert_array_equal(a2, b2)
+
+
+def test_bf16_gradient_close_to_fp32():
+    D1, D2 = c4_descriptors()
+    _, a1, a2, _ = gpu_grad(D1, D2, "fp32")
+    _, b1, b2, _ = gpu_grad(D1, D2, "bf16")
+    print(f"bf16 vs fp32 gradient: rel {rel(b1, a1):.2e} {rel(b2, a2):.2e}", flush=True)
+    assert rel(b1, a1) < 0.1 and rel(b2, a2) < 0.1
+
+
+def test_autograd_function():
+    D1, D2 = sub_pair()
+    d1 = torch.tensor(D1, dtype=torch.float32, device="cuda", requires_grad=True)
+    d2 = torch.tensor(D2, dtype=torch.float32, device="cuda", requires_grad=True)
+    top = dm.DMPyramid.apply(d1, d2, dm.params(max_patch=64))
+    L = dm.top_loss(top)
+    L.backward()
+    _, g1, g2, _ = gpu_grad(D1, D2, "fp32", max_patch=64)
+    np.testing.assert_array_equal(d1.grad.cpu().numpy(), g1.astype(np.float32))
+    np.testing.assert_array_equal(d2.grad.cpu().numpy(), g2.astype(np.float32))
