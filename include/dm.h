@@ -182,6 +182,7 @@ typedef struct {
     int32_t cp_in_saved[DM_MAX_LEVELS];
     uint64_t off_top;          /* in `saved` */
     uint64_t off_valid, off_bf1, off_bf2, off_g[2], off_part, off_t;  /* in `scratch` */
+    uint64_t off_dense;        /* in `scratch`: dense dA_0 and patch matrix of the bottom GEMMs */
 } dm_grad_plan;
 
 /* Plans dm_pyramid_forward / dm_pyramid_backward for a pair of sizes.

@@ -58,7 +58,7 @@ class GradPlan(ctypes.Structure):
                 ("saved_bytes", c_uint64), ("scratch_bytes", c_uint64),
                 ("off_cp", c_uint64 * _L), ("off_code", c_uint64 * _L), ("cp_in_saved", c_int32 * _L),
                 ("off_top", c_uint64), ("off_valid", c_uint64), ("off_bf1", c_uint64), ("off_bf2", c_uint64),
-                ("off_g", c_uint64 * 2), ("off_part", c_uint64), ("off_t", c_uint64)]
+                ("off_g", c_uint64 * 2), ("off_part", c_uint64), ("off_t", c_uint64), ("off_dense", c_uint64)]
 
 
 class StageTime(ctypes.Structure):

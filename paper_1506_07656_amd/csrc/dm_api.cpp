@@ -10,8 +10,6 @@
 namespace dm {
 const char* last_error_text();
 void clear_error();
-void timing_begin(const char* name, int level, hipStream_t s);
-void timing_end(hipStream_t s);
 }  // namespace dm
 
 using namespace dm;
@@ -172,7 +170,7 @@ dm_status grad_backward(const T* d1, const T* d2, const dm_grad_plan& gp, const 
     const int mode = std::is_same<T, double>::value ? 2 : (prm->precision == DM_BF16 ? 1 : 0);
     DM_LAUNCH("bwd_bottom", 0,
               launch_bwd_bottom<T>(mode, B.gbuf(0), B.code(0), d1, d2, g, at<T>(scratch, gp.off_part),
-                                   at<T>(scratch, gp.off_t), dd1, dd2, s));
+                                   at<T>(scratch, gp.off_t), at<void>(scratch, gp.off_dense), dd1, dd2, s));
     return DM_OK;
 }
 

@@ -78,6 +78,10 @@ struct DescParams {
 };
 DescParams make_desc_params(const dm_params* prm);
 
+// Opt-in stage timing (dm_timing.cpp); calls may nest.
+void timing_begin(const char* name, int level, hipStream_t s);
+void timing_end(hipStream_t s);
+
 // Kernel launchers (each returns the launch status).
 hipError_t launch_valid_init(const Geom& g, uint8_t* vt, hipStream_t s);
 hipError_t launch_descriptor(const float* img, int W, int H, int ld, const DescParams& p,
@@ -100,10 +104,12 @@ template <typename T>
 hipError_t launch_bwd_level(int l, const T* dtop, const T* top, const T* gp_cur, const uint8_t* code_cur,
                             const T* cp_prev, const uint8_t* vt, const Geom& g, T lam, T* gp_prev, hipStream_t s);
 // mode 0: FP32 MFMA, 1: BF16 MFMA operands with FP32 accumulation, 2: reference kernels (any T)
+// dense: scratch of bwd_dense_bytes() for the dense dA_0 and the patch matrix (modes 0, 1)
 template <typename T>
 hipError_t launch_bwd_bottom(int mode, const T* gp, const uint8_t* code, const T* d1, const T* d2, const Geom& g,
-                             T* part, T* tbuf, T* dd1, T* dd2, hipStream_t s);
+                             T* part, T* tbuf, void* dense, T* dd1, T* dd2, hipStream_t s);
 int bwd_nsplit(const Geom& g);
+size_t bwd_dense_bytes(const Geom& g, int precision);
 template <typename T>
 hipError_t launch_backtrack(int l, const T* cp_prev, const uint8_t* code_prev, const T* u_cur,
                             const uint8_t* code_cur, const T* top, const uint8_t* vt, const Geom& g,

@@ -1,5 +1,6 @@
 // Opt-in per-stage timing: HIP events recorded on the launch stream around
-// each library kernel launch, aggregated by (stage name, level).
+// each library kernel launch, aggregated by (stage name, level).  Stages may
+// nest (a composite stage and the kernels it launches are both recorded).
 #include <string.h>
 
 #include <mutex>
@@ -20,7 +21,7 @@ std::mutex g_mu;
 bool g_on = false;
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
-int g_open = -1;
+std::vector<int> g_open;
 
 hipEvent_t take_event() {
     if (!g_pool.empty()) {
@@ -39,7 +40,7 @@ void recycle_all() {
         if (r.b) g_pool.push_back(r.b);
     }
     g_recs.clear();
-    g_open = -1;
+    g_open.clear();
 }
 
 }  // namespace
@@ -50,14 +51,15 @@ void timing_begin(const char* name, int level, hipStream_t s) {
     Rec r{name, level, take_event(), take_event()};
     if (r.a) (void)hipEventRecord(r.a, s);
     g_recs.push_back(r);
-    g_open = (int)g_recs.size() - 1;
+    g_open.push_back((int)g_recs.size() - 1);
 }
 
 void timing_end(hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (!g_on || g_open < 0) return;
-    if (g_recs[g_open].b) (void)hipEventRecord(g_recs[g_open].b, s);
-    g_open = -1;
+    if (!g_on || g_open.empty()) return;
+    const int i = g_open.back();
+    g_open.pop_back();
+    if (g_recs[i].b) (void)hipEventRecord(g_recs[i].b, s);
 }
 
 }  // namespace dm

@@ -31,67 +31,140 @@ struct BwdArgs {
     int h, w;      // maps of level l (= child pooled grid)
     int hu, wu;    // pooled grid of level l
     int is_top;
+    int TR, TC, CB;            // tile rows, cols, children per block
+    int n_cblk, n_rt;
+    FastDiv f_t, f_tc, f_nr, f_rwd;   // divisions by TR*TC, TC, RH*RWd, RWd
 };
 
-template <typename T>
-__device__ inline T parent_grad(const BwdArgs& a, int pb, int pa, int qy, int qx, const T* __restrict__ dtop,
-                                const T* __restrict__ top, const T* __restrict__ gp_cur,
-                                const uint8_t* __restrict__ code_cur, T lam) {
-    if (a.is_top) {
-        const size_t o = (((size_t)pb * a.gxp + pa) * a.h + qy) * a.w + qx;
-        return dtop[o] * rect_grad_factor(top[o], lam);
-    }
-    T acc = 0;
-    const int y0 = (qy - 1) >> 1, x0 = (qx - 1) >> 1;  // floor((q-1)/2)
-    for (int ry = y0; ry <= (qy + 1) >> 1; ++ry) {
-        if (ry < 0 || ry >= a.hu) continue;
-        const int my = qy - 2 * ry;
-        if (my < -1 || my > 1) continue;
-        for (int rx = x0; rx <= (qx + 1) >> 1; ++rx) {
-            if (rx < 0 || rx >= a.wu) continue;
-            const int mx = qx - 2 * rx;
-            if (mx < -1 || mx > 1) continue;
-            const size_t o = (((size_t)pb * a.gxp + pa) * a.hu + ry) * a.wu + rx;
-            if (code_cur[o] == 3 * (my + 1) + (mx + 1)) acc += gp_cur[o];
-        }
-    }
-    return acc;
+__device__ inline int xcd_block(int nblocks) {
+    const int per = (nblocks + 7) / 8;
+    return (blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
+// Block: CB children x a TR x TC tile of their pooled grid.  For each child
+// and side i (parent P = c - 2^l o_i), the parent's data covering the tile is
+// staged in LDS: at the top the gradient G_top on q = r - o_i, below the
+// pooled gradient g'_l and codes on the r' whose argmax can land there.
 template <typename T>
 __global__ __launch_bounds__(256) void k_bwd_level(BwdArgs a, const T* __restrict__ dtop, const T* __restrict__ top,
                                                    const T* __restrict__ gp_cur, const uint8_t* __restrict__ code_cur,
                                                    const T* __restrict__ cp_prev, const uint8_t* __restrict__ vt,
-                                                   Geom g, T lam, T* __restrict__ gp_prev) {
-    const size_t n = (size_t)a.gxc * a.gyc * a.h * a.w;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int rx = i % a.w, ry = (i / a.w) % a.h;
-    const int c = i / ((size_t)a.w * a.h);
-    const int cb = c / a.gxc, ca = c - cb * a.gxc;
-    const uint8_t *vxp = vtab(vt, g, a.l, 0), *vyp = vtab(vt, g, a.l, 1);
-    const uint8_t *vxc = vtab(vt, g, a.l - 1, 0), *vyc = vtab(vt, g, a.l - 1, 1);
-    if (!(vxc[ca] && vyc[cb])) {
-        gp_prev[i] = T(0);
-        return;
-    }
-    T acc = 0;
-    for (int side = 0; side < 4; ++side) {
-        const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;   // o_i, i = side
-        const int pb = parent_index(a.l, cb, sy), pa = parent_index(a.l, ca, sx);
-        if (pb < 0 || pb >= a.gyp || pa < 0 || pa >= a.gxp || !vxp[pa] || !vyp[pb]) continue;
-        const int qy = ry - sy, qx = rx - sx;
-        if (qy < 0 || qy >= a.h || qx < 0 || qx >= a.w) continue;
-        // |V(P)|: existing children of the parent along each axis.
-        int nx = 0, ny = 0;
-        for (int s = -1; s <= 1; s += 2) {
-            const int ccx = child_index(a.l, pa, s), ccy = child_index(a.l, pb, s);
-            nx += ccx >= 0 && ccx < a.gxc && vxc[ccx];
-            ny += ccy >= 0 && ccy < a.gyc && vyc[ccy];
+                                                   Geom g, T lam, T* __restrict__ gp_prev, int nblocks) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int RH = a.TR / 2 + 2, RWd = a.TC / 2 + 2, NR = RH * RWd;
+    const int T_ = a.TR * a.TC;
+    const int per_side = a.is_top ? T_ : NR;
+    T* sG = (T*)smem_raw;                                                  // [CB*4][per_side]
+    uint8_t* sM = (uint8_t*)(sG + 4 * a.CB * per_side);                    // codes (below the top)
+    int* sPar = (int*)(((uintptr_t)(sM + 4 * a.CB * per_side) + 15) & ~(uintptr_t)15);  // [CB*4]
+    T* sInv = (T*)(sPar + 4 * a.CB);                                       // [CB*4] 1/|V(P)|
+    int* sCv = (int*)(sInv + 4 * a.CB);                                    // [CB]
+    const int bid = xcd_block(nblocks);
+    if (bid >= nblocks) return;
+    const int cblk = bid % a.n_cblk, rest = bid / a.n_cblk;
+    const int R0 = (rest % a.n_rt) * a.TR, C0 = (rest / a.n_rt) * a.TC;
+    const int tid = threadIdx.x;
+    {
+        const uint8_t *vxp = vtab(vt, g, a.l, 0), *vyp = vtab(vt, g, a.l, 1);
+        const uint8_t *vxc = vtab(vt, g, a.l - 1, 0), *vyc = vtab(vt, g, a.l - 1, 1);
+        for (int e = tid; e < 4 * a.CB; e += 256) {
+            const int k = e >> 2, side = e & 3;
+            const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;   // o_i, i = side
+            const int c = cblk * a.CB + k;
+            int par = -1;
+            T inv = 0;
+            if (c < a.gxc * a.gyc) {
+                const int cb = c / a.gxc, ca = c - cb * a.gxc;
+                const int pb = parent_index(a.l, cb, sy), pa = parent_index(a.l, ca, sx);
+                if (pb >= 0 && pb < a.gyp && pa >= 0 && pa < a.gxp && vxp[pa] && vyp[pb]) {
+                    par = pb * a.gxp + pa;
+                    int nx = 0, ny = 0;
+                    for (int s2 = -1; s2 <= 1; s2 += 2) {
+                        const int ccx = child_index(a.l, pa, s2), ccy = child_index(a.l, pb, s2);
+                        nx += ccx >= 0 && ccx < a.gxc && vxc[ccx];
+                        ny += ccy >= 0 && ccy < a.gyc && vyc[ccy];
+                    }
+                    inv = T(1) / T(nx * ny);
+                }
+                if (side == 0) sCv[k] = vxc[ca] && vyc[cb];
+            } else if (side == 0) {
+                sCv[k] = -1;   // past the last child: nothing to write
+            }
+            sPar[e] = par;
+            sInv[e] = inv;
         }
-        acc += parent_grad(a, pb, pa, qy, qx, dtop, top, gp_cur, code_cur, lam) / T(nx * ny);
     }
-    gp_prev[i] = acc * rect_grad_factor(cp_prev[i], lam);
+    __syncthreads();
+    // Stage the parents' data.
+    for (int e = tid; e < 4 * a.CB * per_side; e += 256) {
+        const int ks = a.is_top ? (int)fdiv(e, a.f_t) : (int)fdiv(e, a.f_nr);
+        const int rem = e - ks * per_side;
+        const int side = ks & 3;
+        const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;
+        const int par = sPar[ks];
+        T v = 0;
+        uint8_t m = 255;
+        if (par >= 0) {
+            if (a.is_top) {
+                const int ty = fdiv(rem, a.f_tc);
+                const int qy = R0 + ty - sy, qx = C0 + rem - ty * a.TC - sx;
+                if (qy >= 0 && qy < a.h && qx >= 0 && qx < a.w) {
+                    const size_t o = ((size_t)par * a.h + qy) * a.w + qx;
+                    v = dtop[o] * rect_grad_factor(top[o], lam);
+                }
+            } else {
+                const int rr = fdiv(rem, a.f_rwd);
+                const int ry = ((R0 - sy) >> 1) + rr, rx = ((C0 - sx) >> 1) + rem - rr * RWd;
+                if (ry >= 0 && ry < a.hu && rx >= 0 && rx < a.wu) {
+                    const size_t o = ((size_t)par * a.hu + ry) * a.wu + rx;
+                    v = gp_cur[o];
+                    m = code_cur[o];
+                }
+            }
+        }
+        sG[e] = v;
+        if (!a.is_top) sM[e] = m;
+    }
+    __syncthreads();
+    // g'_{l-1}(c, r) = lambda C'^((lambda-1)/lambda) * sum_i G_l(P_i, r - o_i) / |V(P_i)|
+    for (int e = tid; e < a.CB * T_; e += 256) {
+        const int k = fdiv(e, a.f_t), rem = e - k * T_;
+        const int ty = fdiv(rem, a.f_tc), tx = rem - ty * a.TC;
+        const int ry = R0 + ty, rx = C0 + tx;
+        if (ry >= a.h || rx >= a.w || sCv[k] < 0) continue;
+        const size_t o = (((size_t)cblk * a.CB + k) * a.h + ry) * a.w + rx;
+        if (!sCv[k]) {
+            gp_prev[o] = T(0);
+            continue;
+        }
+        T acc = 0;
+#pragma unroll
+        for (int side = 0; side < 4; ++side) {
+            const int ks = k * 4 + side;
+            if (sPar[ks] < 0) continue;
+            const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;
+            const int qy = ry - sy, qx = rx - sx;
+            if (qy < 0 || qy >= a.h || qx < 0 || qx >= a.w) continue;
+            T gsum = 0;
+            if (a.is_top) {
+                gsum = sG[ks * per_side + rem];
+            } else {
+                const int ry0 = (R0 - sy) >> 1, rx0 = (C0 - sx) >> 1;
+                for (int py = (qy - 1) >> 1; py <= (qy + 1) >> 1; ++py) {
+                    const int my = qy - 2 * py;
+                    if (my < -1 || my > 1) continue;
+                    for (int px = (qx - 1) >> 1; px <= (qx + 1) >> 1; ++px) {
+                        const int mx = qx - 2 * px;
+                        if (mx < -1 || mx > 1) continue;
+                        const int li = ks * per_side + (py - ry0) * RWd + (px - rx0);
+                        if (sM[li] == 3 * (my + 1) + (mx + 1)) gsum += sG[li];
+                    }
+                }
+            }
+            acc += gsum * sInv[ks];
+        }
+        gp_prev[o] = acc * rect_grad_factor(cp_prev[o], lam);
+    }
 }
 
 }  // namespace
@@ -110,9 +183,29 @@ hipError_t launch_bwd_level(int l, const T* dtop, const T* top, const T* gp_cur,
     a.hu = g.h[l + 1];
     a.wu = g.w[l + 1];
     a.is_top = (l == g.lmax);
-    const size_t n = (size_t)a.gxc * a.gyc * a.h * a.w;
-    hipLaunchKernelGGL(k_bwd_level<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, dtop, top, gp_cur,
-                       code_cur, cp_prev, vt, g, lam, gp_prev);
+    a.TC = a.w < 128 ? a.w : 128;
+    a.TR = 1024 / a.TC;
+    if (a.TR > a.h) a.TR = a.h;
+    if (a.TR < 1) a.TR = 1;
+    a.CB = 1024 / (a.TR * a.TC);
+    if (a.CB < 1) a.CB = 1;
+    if (a.CB > 64) a.CB = 64;
+    const int nc = a.gxc * a.gyc;
+    a.n_cblk = (nc + a.CB - 1) / a.CB;
+    a.n_rt = (a.h + a.TR - 1) / a.TR;
+    const int n_ct = (a.w + a.TC - 1) / a.TC;
+    const int RH = a.TR / 2 + 2, RWd = a.TC / 2 + 2;
+    a.f_t = make_fastdiv(a.TR * a.TC);
+    a.f_tc = make_fastdiv(a.TC);
+    a.f_nr = make_fastdiv(RH * RWd);
+    a.f_rwd = make_fastdiv(RWd);
+    const int per_side = a.is_top ? a.TR * a.TC : RH * RWd;
+    size_t smem = (size_t)4 * a.CB * per_side * (sizeof(T) + 1);
+    smem = (smem + 15) & ~size_t(15);
+    smem += (size_t)4 * a.CB * (sizeof(int) + sizeof(T)) + (size_t)a.CB * sizeof(int) + 16;
+    const int nblocks = a.n_cblk * a.n_rt * n_ct;
+    hipLaunchKernelGGL(k_bwd_level<T>, dim3(((nblocks + 7) / 8) * 8), dim3(256), smem, s, a, dtop, top, gp_cur,
+                       code_cur, cp_prev, vt, g, lam, gp_prev, nblocks);
     return hipGetLastError();
 }
 

@@ -7,10 +7,11 @@
 //   dD1[p + d_k][c_k] = 1/16 sum_x dA_0(p, x) D2[x + d_k][c_k]          (GEMM 1)
 //   T[x][k]           =      sum_p dA_0(p, x) D1[p + d_k][c_k]          (GEMM 2)
 //   dD2[y][c]         = 1/16 sum_{dy,dx} T[y - d][(d, c)]               (col2im)
-// Atomic patches do not overlap, so GEMM 1 writes each D1 pixel once.  Both
-// GEMMs run on the matrix cores with dA_0 rebuilt tile by tile in LDS from
-// g'_0 and the argmax codes (never stored densely); partial sums over split
-// ranges are added in a fixed order, so the result is deterministic.
+// Atomic patches do not overlap, so GEMM 1 writes each D1 pixel once.  dA_0
+// is rebuilt once from g'_0 and the argmax codes into a dense scratch array
+// (BF16 or FP32, the GEMM operand type), which both GEMMs stream through LDS
+// tiles on the matrix cores; partial sums over row splits are added in a
+// fixed order, so the result is deterministic.
 //
 // Reference kernels (thread per output, direct loops) serve the FP64
 // instantiation used by the finite-difference check.
@@ -74,81 +75,126 @@ __device__ inline bf8 as_bf8(const uint16_t* p) {   // 8 consecutive bf16 (16-by
     return x.v;
 }
 
+// ---------------------------------------------------------------- dense dA_0
+// dA_0 is written once, densely ([patch][target pixel], operand type E), and
+// both contractions stream it with coalesced loads.
+template <typename E>
+__global__ __launch_bounds__(256) void k_bwd_da(const float* __restrict__ gp, const uint8_t* __restrict__ code,
+                                                BotArgs a, int xblocks, E* __restrict__ dA) {
+    const int p = blockIdx.x / xblocks, xb = blockIdx.x - p * xblocks;
+    const int npos = a.H2 * a.W2;
+    const size_t pm = (size_t)a.h1 * a.w1;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int x = xb * 1024 + u * 256 + threadIdx.x;
+        if (x >= npos) continue;
+        const int xy = x / a.W2, xx = x - xy * a.W2;
+        const float v = dA_at(gp + p * pm, code + p * pm, a.h1, a.w1, xy, xx);
+        if constexpr (std::is_same<E, float>::value) dA[(size_t)p * npos + x] = v;
+        else dA[(size_t)p * npos + x] = to_bf16(v);
+    }
+}
+
+// Patch matrix P[p][k] = D1[p + d_k][c_k] (k = (dy, dx, c)), operand type E.
+template <typename E>
+__global__ void k_bwd_patchmat(const float* __restrict__ d1, BotArgs a, E* __restrict__ P) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)a.natom * 144) return;
+    const int p = i / 144, k = i % 144;
+    const float v = d1_at(d1, a, p, k);
+    if constexpr (std::is_same<E, float>::value) P[i] = v;
+    else P[i] = to_bf16(v);
+}
+
 // ---------------------------------------------------------------- GEMM 1: dD1
-// Block: 64 patches (16 per wave) x all 144 K columns (9 N-tiles); it reduces
-// over the positions of one split.  Each chunk of 64 positions rebuilds the
-// dA tile [64 patches][64 positions] and the im2col tile [144][64 positions]
-// in LDS (operand type E: float or bf16), then runs the MFMA chain.
-constexpr int BP = 64, KC = 64;
+// Block: 128 patches (32 per wave = 2 M-tiles) x all 144 K columns (9
+// N-tiles), reducing over the target rows of one split in chunks of 64
+// pixels of one row: the dA tile [128][64] comes straight from the dense dA,
+// the im2col tile [144][64] is built from an LDS copy of the 4 x 67 target
+// pixels it covers.
+constexpr int G1P = 128, KC = 64;
 
 template <bool BF16>
-__global__ __launch_bounds__(256) void k_bwd_dd1_mfma(const float* __restrict__ gp, const uint8_t* __restrict__ code,
+__global__ __launch_bounds__(256) void k_bwd_dd1_gemm(const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ dA,
                                                       const float* __restrict__ d2, BotArgs a, int nsplit,
                                                       float* __restrict__ part) {
     typedef typename std::conditional<BF16, uint16_t, float>::type E;
-    __shared__ __align__(16) E sA[BP][KC + (BF16 ? 8 : 1)];
-    __shared__ __align__(16) E sB[144][KC + (BF16 ? 8 : 1)];
+    constexpr int PAD = BF16 ? 8 : 1;
+    __shared__ __align__(16) E sA[G1P][KC + PAD];
+    __shared__ __align__(16) E sB[144][KC + PAD];
+    __shared__ float sD2[4][KC + 3][9];
     const int ptile = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
     const int npos = a.H2 * a.W2;
-    const int per = (npos + nsplit - 1) / nsplit;
-    const int x_begin = split * per, x_end = min(npos, x_begin + per);
-    const size_t pm = (size_t)a.h1 * a.w1;
-    f4 acc[9];
+    const int rows_per = (a.H2 + nsplit - 1) / nsplit;
+    const int y_begin = split * rows_per, y_end = min(a.H2, y_begin + rows_per);
+    f4 acc[2][9];
 #pragma unroll
-    for (int nt = 0; nt < 9; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int x0 = x_begin; x0 < x_end; x0 += KC) {
-        __syncthreads();
-        for (int e = tid; e < BP * KC; e += 256) {
-            const int pl = e / KC, xi = e - pl * KC;
-            const int p = ptile * BP + pl, xl = x0 + xi;
-            float v = 0.f;
-            if (p < a.natom && xl < x_end) {
-                const int xy = xl / a.W2, xx = xl - xy * a.W2;
-                v = dA_at(gp + p * pm, code + p * pm, a.h1, a.w1, xy, xx);
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 9; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int y = y_begin; y < y_end; ++y) {
+        for (int x0 = 0; x0 < a.W2; x0 += KC) {
+            __syncthreads();
+            // target pixels rows y-2..y+1, columns x0-2..x0+KC, zero outside
+            for (int e = tid; e < 4 * (KC + 3) * 9; e += 256) {
+                const int r = e / ((KC + 3) * 9), rem = e - r * ((KC + 3) * 9);
+                const int col = rem / 9, c = rem - col * 9;
+                const int yy = y - 2 + r, xx = x0 - 2 + col;
+                sD2[r][col][c] = (yy >= 0 && yy < a.H2 && xx >= 0 && xx < a.W2) ? d2[((size_t)yy * a.W2 + xx) * 9 + c] : 0.f;
             }
-            if constexpr (BF16) sA[pl][xi] = to_bf16(v); else sA[pl][xi] = v;
-        }
-        for (int e = tid; e < 144 * KC; e += 256) {
-            const int k = e / KC, xi = e - k * KC;
-            const int xl = x0 + xi;
-            float v = 0.f;
-            if (xl < x_end) {
-                const int xy = xl / a.W2, xx = xl - xy * a.W2;
-                v = d2_at(d2, a, xy, xx, k);
+            for (int e = tid; e < G1P * KC; e += 256) {
+                const int pl = e / KC, xi = e - pl * KC;
+                const int p = ptile * G1P + pl, x = x0 + xi;
+                E v = E(0);
+                if (p < a.natom && x < a.W2) v = dA[(size_t)p * npos + y * a.W2 + x];
+                sA[pl][xi] = v;
             }
-            if constexpr (BF16) sB[k][xi] = to_bf16(v); else sB[k][xi] = v;
-        }
-        __syncthreads();
-        const int pr = wave * 16 + n;
-        if constexpr (BF16) {
+            __syncthreads();
+            for (int e = tid; e < 144 * KC; e += 256) {
+                const int k = e / KC, xi = e - k * KC;
+                const int dy = k / 36, dx = (k / 9) % 4, c = k % 9;
+                const float v = (x0 + xi < a.W2) ? sD2[dy][xi + dx][c] : 0.f;
+                if constexpr (BF16) sB[k][xi] = to_bf16(v); else sB[k][xi] = v;
+            }
+            __syncthreads();
+            if constexpr (BF16) {
 #pragma unroll
-            for (int s = 0; s < KC / 32; ++s) {
-                const bf8 av = as_bf8(&sA[pr][32 * s + 8 * g]);
+                for (int s = 0; s < KC / 32; ++s) {
+                    bf8 av[2];
 #pragma unroll
-                for (int nt = 0; nt < 9; ++nt) {
-                    const bf8 bv = as_bf8(&sB[16 * nt + n][32 * s + 8 * g]);
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
+                    for (int mt = 0; mt < 2; ++mt) av[mt] = as_bf8(&sA[wave * 32 + mt * 16 + n][32 * s + 8 * g]);
+#pragma unroll
+                    for (int nt = 0; nt < 9; ++nt) {
+                        const bf8 bv = as_bf8(&sB[16 * nt + n][32 * s + 8 * g]);
+#pragma unroll
+                        for (int mt = 0; mt < 2; ++mt)
+                            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv, acc[mt][nt], 0, 0, 0);
+                    }
                 }
-            }
-        } else {
-#pragma unroll 4
-            for (int t = 0; t < KC / 4; ++t) {
-                const float av = sA[pr][4 * t + g];
+            } else {
+#pragma unroll 2
+                for (int t = 0; t < KC / 4; ++t) {
+                    const float a0 = sA[wave * 32 + n][4 * t + g], a1 = sA[wave * 32 + 16 + n][4 * t + g];
 #pragma unroll
-                for (int nt = 0; nt < 9; ++nt)
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sB[16 * nt + n][4 * t + g], acc[nt], 0, 0, 0);
+                    for (int nt = 0; nt < 9; ++nt) {
+                        const float bv = sB[16 * nt + n][4 * t + g];
+                        acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv, acc[0][nt], 0, 0, 0);
+                        acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv, acc[1][nt], 0, 0, 0);
+                    }
+                }
             }
         }
     }
-    // acc[nt][j]: patch wave*16 + 4g + j, column 16 nt + n
 #pragma unroll
-    for (int nt = 0; nt < 9; ++nt)
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int p = ptile * BP + wave * 16 + 4 * g + j;
-            if (p < a.natom) part[((size_t)split * a.natom + p) * 144 + 16 * nt + n] = acc[nt][j];
-        }
+        for (int nt = 0; nt < 9; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int p = ptile * G1P + wave * 32 + mt * 16 + 4 * g + j;
+                if (p < a.natom) part[((size_t)split * a.natom + p) * 144 + 16 * nt + n] = acc[mt][nt][j];
+            }
 }
 
 // dD1 (HWC) from the split partials: each pixel belongs to at most one patch.
@@ -171,69 +217,74 @@ __global__ void k_bwd_dd1_reduce(const T* __restrict__ part, BotArgs a, int nspl
 }
 
 // ---------------------------------------------------------------- GEMM 2: T
-// Block: 64 positions (16 per wave) x 144 columns; reduces over all patches
-// in chunks of 64: dA tile [64 patches][64 positions] and patch tile
-// [144][64 patches] in LDS.
+// Block: 128 target pixels (32 per wave = 2 M-tiles) x 144 columns, reducing
+// over all patches in chunks of 64: dA tile kept transposed [pixel][patch]
+// and patch tile [144][patch] in LDS.
 template <bool BF16>
-__global__ __launch_bounds__(256) void k_bwd_t_mfma(const float* __restrict__ gp, const uint8_t* __restrict__ code,
-                                                    const float* __restrict__ d1, BotArgs a, float* __restrict__ tbuf) {
+__global__ __launch_bounds__(256) void k_bwd_t_gemm(const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ dA,
+                                                    const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ P,
+                                                    BotArgs a, float* __restrict__ tbuf) {
     typedef typename std::conditional<BF16, uint16_t, float>::type E;
-    __shared__ __align__(16) E sA[64][64 + (BF16 ? 8 : 1)];     // [position][patch]
-    __shared__ __align__(16) E sB[144][64 + (BF16 ? 8 : 1)];    // [k][patch]
+    constexpr int PAD = BF16 ? 8 : 1;
+    __shared__ __align__(16) E sAT[128][64 + PAD];   // [pixel][patch]
+    __shared__ __align__(16) E sP[144][64 + PAD];    // [k][patch]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
     const int npos = a.H2 * a.W2;
-    const int xb = blockIdx.x * 64;
-    const size_t pm = (size_t)a.h1 * a.w1;
-    f4 acc[9];
+    const int xb = blockIdx.x * 128;
+    f4 acc[2][9];
 #pragma unroll
-    for (int nt = 0; nt < 9; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 9; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
     for (int p0 = 0; p0 < a.natom; p0 += 64) {
         __syncthreads();
-        for (int e = tid; e < 64 * 64; e += 256) {
-            const int xi = e / 64, pl = e - xi * 64;
-            const int p = p0 + pl, xl = xb + xi;
-            float v = 0.f;
-            if (p < a.natom && xl < npos) {
-                const int xy = xl / a.W2, xx = xl - xy * a.W2;
-                v = dA_at(gp + p * pm, code + p * pm, a.h1, a.w1, xy, xx);
-            }
-            if constexpr (BF16) sA[xi][pl] = to_bf16(v); else sA[xi][pl] = v;
+        for (int e = tid; e < 64 * 128; e += 256) {
+            const int pl = e / 128, xi = e - pl * 128;
+            const int p = p0 + pl, x = xb + xi;
+            sAT[xi][pl] = (p < a.natom && x < npos) ? dA[(size_t)p * npos + x] : E(0);
         }
-        for (int e = tid; e < 144 * 64; e += 256) {
+        for (int e = tid; e < 64 * 144; e += 256) {
             const int pl = e / 144, k = e - pl * 144;
             const int p = p0 + pl;
-            const float v = p < a.natom ? d1_at(d1, a, p, k) : 0.f;
-            if constexpr (BF16) sB[k][pl] = to_bf16(v); else sB[k][pl] = v;
+            sP[k][pl] = p < a.natom ? P[(size_t)p * 144 + k] : E(0);
         }
         __syncthreads();
-        const int xr = wave * 16 + n;
         if constexpr (BF16) {
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                const bf8 av = as_bf8(&sA[xr][32 * s + 8 * g]);
+                bf8 av[2];
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) av[mt] = as_bf8(&sAT[wave * 32 + mt * 16 + n][32 * s + 8 * g]);
 #pragma unroll
                 for (int nt = 0; nt < 9; ++nt) {
-                    const bf8 bv = as_bf8(&sB[16 * nt + n][32 * s + 8 * g]);
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
+                    const bf8 bv = as_bf8(&sP[16 * nt + n][32 * s + 8 * g]);
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv, acc[mt][nt], 0, 0, 0);
                 }
             }
         } else {
-#pragma unroll 4
+#pragma unroll 2
             for (int t = 0; t < 16; ++t) {
-                const float av = sA[xr][4 * t + g];
+                const float a0 = sAT[wave * 32 + n][4 * t + g], a1 = sAT[wave * 32 + 16 + n][4 * t + g];
 #pragma unroll
-                for (int nt = 0; nt < 9; ++nt)
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sB[16 * nt + n][4 * t + g], acc[nt], 0, 0, 0);
+                for (int nt = 0; nt < 9; ++nt) {
+                    const float bv = sP[16 * nt + n][4 * t + g];
+                    acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv, acc[0][nt], 0, 0, 0);
+                    acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv, acc[1][nt], 0, 0, 0);
+                }
             }
         }
     }
 #pragma unroll
-    for (int nt = 0; nt < 9; ++nt)
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int xl = xb + wave * 16 + 4 * g + j;
-            if (xl < npos) tbuf[(size_t)xl * 144 + 16 * nt + n] = acc[nt][j];
-        }
+        for (int nt = 0; nt < 9; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int x = xb + wave * 32 + mt * 16 + 4 * g + j;
+                if (x < npos) tbuf[(size_t)x * 144 + 16 * nt + n] = acc[mt][nt][j];
+            }
 }
 
 // dD2[y][c] = 1/16 sum_d T[y - d][(d, c)]  (T is zero outside the target).
@@ -310,37 +361,57 @@ BotArgs make_bot(const Geom& g) {
 }  // namespace
 
 int bwd_nsplit(const Geom& g) {
-    // enough blocks for the 256 CUs: patch tiles x splits >= ~1024
-    const int ptiles = (g.gx[0] * g.gy[0] + BP - 1) / BP;
+    // enough blocks for the 256 CUs: patch tiles x row splits >= ~1024
+    const int ptiles = (g.gx[0] * g.gy[0] + G1P - 1) / G1P;
     int ns = (1024 + ptiles - 1) / ptiles;
-    const int npos = g.H2 * g.W2;
-    const int maxs = (npos + KC - 1) / KC;
-    if (ns > maxs) ns = maxs;
+    if (ns > g.H2) ns = g.H2;
     if (ns < 1) ns = 1;
     if (ns > 64) ns = 64;
     return ns;
 }
 
+size_t bwd_dense_bytes(const Geom& g, int precision) {
+    const size_t es = precision == DM_BF16 ? 2 : 4;
+    return (size_t)g.gx[0] * g.gy[0] * ((size_t)g.H2 * g.W2 + 144) * es;
+}
+
 template <typename T>
 hipError_t launch_bwd_bottom(int mode, const T* gp, const uint8_t* code, const T* d1, const T* d2, const Geom& g,
-                             T* part, T* tbuf, T* dd1, T* dd2, hipStream_t s) {
+                             T* part, T* tbuf, void* dense, T* dd1, T* dd2, hipStream_t s) {
+#define DM_SUB(name, ...)                  \
+    do {                                   \
+        timing_begin(name, 0, s);          \
+        hipLaunchKernelGGL(__VA_ARGS__);   \
+        timing_end(s);                     \
+    } while (0)
     const BotArgs a = make_bot(g);
     int ns = 1;
     if (mode == 2) {  // reference kernels
         const size_t n1 = (size_t)a.natom * 144, n2 = (size_t)a.H2 * a.W2 * 144;
-        hipLaunchKernelGGL(k_bwd_dd1_ref<T>, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, gp, code, d2, a, part);
-        hipLaunchKernelGGL(k_bwd_t_ref<T>, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, gp, code, d1, a, tbuf);
+        DM_SUB("bwd_dd1_ref", k_bwd_dd1_ref<T>, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, gp, code, d2, a, part);
+        DM_SUB("bwd_t_ref", k_bwd_t_ref<T>, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, gp, code, d1, a, tbuf);
     } else {
         if constexpr (std::is_same<T, float>::value) {
             ns = bwd_nsplit(g);
-            const int ptiles = (a.natom + BP - 1) / BP;
-            const int tblocks = (a.H2 * a.W2 + 63) / 64;
+            const int npos = a.H2 * a.W2;
+            const int xblocks = (npos + 1023) / 1024;
+            const int ptiles = (a.natom + G1P - 1) / G1P;
+            const int tblocks = (npos + 127) / 128;
+            const size_t pmat = (size_t)a.natom * 144;
             if (mode == 1) {
-                hipLaunchKernelGGL(k_bwd_dd1_mfma<true>, dim3(ptiles * ns), dim3(256), 0, s, gp, code, d2, a, ns, part);
-                hipLaunchKernelGGL(k_bwd_t_mfma<true>, dim3(tblocks), dim3(256), 0, s, gp, code, d1, a, tbuf);
+                uint16_t* dA = (uint16_t*)dense;
+                uint16_t* P = dA + (size_t)a.natom * npos;
+                DM_SUB("bwd_da", k_bwd_da<uint16_t>, dim3(a.natom * xblocks), dim3(256), 0, s, gp, code, a, xblocks, dA);
+                DM_SUB("bwd_patchmat", k_bwd_patchmat<uint16_t>, dim3((unsigned)((pmat + 255) / 256)), dim3(256), 0, s, d1, a, P);
+                DM_SUB("bwd_dd1_gemm", k_bwd_dd1_gemm<true>, dim3(ptiles * ns), dim3(256), 0, s, dA, d2, a, ns, part);
+                DM_SUB("bwd_t_gemm", k_bwd_t_gemm<true>, dim3(tblocks), dim3(256), 0, s, dA, P, a, tbuf);
             } else {
-                hipLaunchKernelGGL(k_bwd_dd1_mfma<false>, dim3(ptiles * ns), dim3(256), 0, s, gp, code, d2, a, ns, part);
-                hipLaunchKernelGGL(k_bwd_t_mfma<false>, dim3(tblocks), dim3(256), 0, s, gp, code, d1, a, tbuf);
+                float* dA = (float*)dense;
+                float* P = dA + (size_t)a.natom * npos;
+                DM_SUB("bwd_da", k_bwd_da<float>, dim3(a.natom * xblocks), dim3(256), 0, s, gp, code, a, xblocks, dA);
+                DM_SUB("bwd_patchmat", k_bwd_patchmat<float>, dim3((unsigned)((pmat + 255) / 256)), dim3(256), 0, s, d1, a, P);
+                DM_SUB("bwd_dd1_gemm", k_bwd_dd1_gemm<false>, dim3(ptiles * ns), dim3(256), 0, s, dA, d2, a, ns, part);
+                DM_SUB("bwd_t_gemm", k_bwd_t_gemm<false>, dim3(tblocks), dim3(256), 0, s, dA, P, a, tbuf);
             }
         } else {
             return hipErrorInvalidValue;
@@ -349,14 +420,15 @@ hipError_t launch_bwd_bottom(int mode, const T* gp, const uint8_t* code, const T
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t n1 = (size_t)a.H1 * a.W1 * 9, n2 = (size_t)a.H2 * a.W2 * 9;
-    hipLaunchKernelGGL(k_bwd_dd1_reduce<T>, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, part, a, ns, dd1);
-    hipLaunchKernelGGL(k_bwd_col2im<T>, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, tbuf, a, dd2);
+    DM_SUB("bwd_dd1_reduce", k_bwd_dd1_reduce<T>, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, part, a, ns, dd1);
+    DM_SUB("bwd_col2im", k_bwd_col2im<T>, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, tbuf, a, dd2);
     return hipGetLastError();
+#undef DM_SUB
 }
 
 template hipError_t launch_bwd_bottom<float>(int, const float*, const uint8_t*, const float*, const float*,
-                                             const Geom&, float*, float*, float*, float*, hipStream_t);
+                                             const Geom&, float*, float*, void*, float*, float*, hipStream_t);
 template hipError_t launch_bwd_bottom<double>(int, const double*, const uint8_t*, const double*, const double*,
-                                              const Geom&, double*, double*, double*, double*, hipStream_t);
+                                              const Geom&, double*, double*, void*, double*, double*, hipStream_t);
 
 }  // namespace dm
