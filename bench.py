@@ -154,6 +154,15 @@ def cpu_baseline(pair):
                        f"pair: {t:.1f} s, scaled by the O(LL') cost ratio {scale:.0f} to a full pair")
 
 
+def copy_probe(torch):
+    """A plain 1 GiB device-to-device copy: its FETCH_SIZE / WRITE_SIZE readings
+    calibrate the HBM byte counters (1 GiB each way is the truth)."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +171,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the run, copy 1 GiB device to device (calibrates HBM byte counters)")
+    ap.add_argument("--only", choices=("all", "fwd_bf16"), default="all",
+                    help="fwd_bf16: run only the BF16 forward (short profiler runs); prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the matcher has no multi-GPU path, "
@@ -174,6 +185,12 @@ def main():
     pair = synth.make_pair("c3")
     img1 = torch.from_numpy(pair["img1"]).cuda()
     img2 = torch.from_numpy(pair["img2"]).cuda()
+    if args.only == "fwd_bf16":
+        dt, _, _, _ = time_path(dm, torch, img1, img2, "bf16", args.steps, args.warmup)
+        if args.copy_probe:
+            copy_probe(torch)
+        print(f"bf16 forward: {dt * 1e3:.3f} ms/pair", flush=True)
+        return
     res = {}
     for prec in ("fp32", "bf16"):
         dt, matches, stages, pl = time_path(dm, torch, img1, img2, prec, args.steps, args.warmup)
@@ -229,10 +246,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pair)
     if args.copy_probe:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
+        copy_probe(torch)
         out["copy_probe_bytes"] = 1 << 30
     print(json.dumps(out))
 

@@ -218,6 +218,216 @@ __global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __rest
     }
 }
 
+// Row-streaming form of k_backtrack below the top, for child maps at least
+// 32 columns wide.  One wave owns a child c, a band of TR rows of its pooled
+// grid and 64 columns (one per lane).  It walks down the rows of U_l of the
+// child's (up to 4) parents.  Each U_l entry of parent P_i = c - 2^l o_i
+// reaches V_l(P_i, x) at x = 2r' + m, hence the child's candidate at
+// r = x + o_i, so the entry goes straight (max on collision, packed keys) into
+// a small ring of candidate rows R(c, r) = max_i V_l(P_i, r - o_i) in LDS.
+// U_l row r' is the last that can reach rows <= 2r', so after it the output
+// rows 2r'-2, 2r'-1 are final: each entry is taken out of the ring with an
+// exchange against 0 (so the ring is clean for its next row), and C'_{l-1}
+// and its code are read only where a tuple arrived (lanes without one use an
+// out-of-range buffer offset, which touches no memory).  Only window entries
+// are scattered, so every scattered entry is taken exactly once.  Loads run
+// one step ahead of their use.
+// At the bottom the 4 waves of a block (4 children, same rows and columns)
+// share the cell-table window; BestAt(c) is reduced within the wave.
+constexpr int kBtCols = 64;
+constexpr int kBtWaves = 4;
+constexpr int kBtRing = 6;     // live candidate rows: 2r'-2 .. 2r'+2
+constexpr int kBtMaxTR = 32;
+constexpr int kOOB = 0x7ffffff0;   // buffer offset past any map
+
+struct BtStreamArgs {
+    int l;
+    int gxp, gyp, gxc, gyc;
+    int h, w, hu, wu;
+    int is_bottom;
+    int TR, n_band, n_ct, n_cgrp;
+    int W2, cw;
+};
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Buffer descriptor over [p, p + nbytes): loads outside return 0.
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, int nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, nbytes, 0x00020000);
+}
+
+__global__ __launch_bounds__(64 * kBtWaves) void k_backtrack_stream(
+    BtStreamArgs a, const float* __restrict__ cp_prev, const uint8_t* __restrict__ code_prev,
+    const float* __restrict__ u_cur, const uint8_t* __restrict__ code_cur, const uint8_t* __restrict__ vt, Geom g,
+    float* __restrict__ u_prev, unsigned long long* __restrict__ best, unsigned long long* __restrict__ cell,
+    int nblocks) {
+    constexpr int NCX = kBtCols / 2 + 2;
+    __shared__ uint32_t sR[kBtWaves][kBtRing][kBtCols];
+    __shared__ unsigned long long sCell[(kBtMaxTR / 2 + 2) * NCX];
+    const int bid = xcd_block(nblocks);
+    if (bid >= nblocks) return;
+    const int cgrp = bid % a.n_cgrp, rest = bid / a.n_cgrp;
+    const int ct = rest % a.n_ct, band = rest / a.n_ct;
+    const int tid = threadIdx.x, t = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index: uniform
+    const int R0 = band * a.TR, R1 = min(R0 + a.TR, a.h);
+    const int C0 = ct * kBtCols, Cend = min(C0 + kBtCols, a.w);
+    const int ncy = a.TR / 2 + 2;
+    const int cyb = (2 * R0 - 1) >> 2, cxb = (2 * C0 - 1) >> 2;   // floor division by 4
+    {
+        uint32_t* flat = &sR[0][0][0];
+        for (int e = tid; e < kBtWaves * kBtRing * kBtCols; e += 64 * kBtWaves) flat[e] = 0u;
+        if (a.is_bottom)
+            for (int e = tid; e < ncy * NCX; e += 64 * kBtWaves) sCell[e] = 0ull;
+    }
+    __syncthreads();
+    const int c = cgrp * kBtWaves + wv;
+    const uint8_t *vxc = vtab(vt, g, a.l - 1, 0), *vyc = vtab(vt, g, a.l - 1, 1);
+    int cb = 0, ca = 0;
+    bool live = c < a.gxc * a.gyc;
+    if (live) {
+        cb = c / a.gxc;
+        ca = c - cb * a.gxc;
+        live = vxc[ca] && vyc[cb];
+    }
+    unsigned long long mybest = 0ull;
+    if (live) {
+        const uint8_t *vxp = vtab(vt, g, a.l, 0), *vyp = vtab(vt, g, a.l, 1);
+        // One descriptor per array (every array here stays below 2^31 bytes,
+        // checked at launch); parents are selected by element offsets.
+        const int usz = a.hu * a.wu, csz = a.h * a.w;
+        const int nparent = a.gxp * a.gyp, nchild = a.gxc * a.gyc;
+        const __amdgpu_buffer_rsrc_t rsU = rsrc(u_cur, nparent * usz * 4), rsM = rsrc(code_cur, nparent * usz);
+        const __amdgpu_buffer_rsrc_t rsC = rsrc(cp_prev, nchild * csz * 4);
+        const __amdgpu_buffer_rsrc_t rsK = rsrc(code_prev, a.is_bottom ? nchild * csz : 0);
+        int pbase[4];
+#pragma unroll
+        for (int side = 0; side < 4; ++side) {
+            const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;   // o_i of Eq. (5), i = side
+            const int pb = parent_index(a.l, cb, sy), pa = parent_index(a.l, ca, sx);
+            const bool ok = pb >= 0 && pb < a.gyp && pa >= 0 && pa < a.gxp && vxp[pa] && vyp[pb];
+            pbase[side] = ok ? (pb * a.gxp + pa) * usz : -1;
+        }
+        const int cbase = c * csz;
+        uint32_t (*ring)[kBtCols] = sR[wv];
+        const int rx = C0 + t;                       // the lane's output column
+        const int ux = (C0 >> 1) - 1 + t;            // the lane's U_l column while scattering
+        const bool lane_u = t < NCX && ux >= 0 && ux < a.wu;
+        const bool lane_o = rx < Cend;
+        const int rp0 = (R0 - 1) >> 1, rp1 = ((R1 - 1) >> 1) + 1;
+
+        struct UBuf { float u[4]; int m[4]; };
+        struct OBuf { uint32_t vb[2]; float cv[2]; int cm[2]; };
+        auto load_u = [&](int rp, UBuf& st) {
+            const bool rok = lane_u && rp >= 0 && rp < a.hu;
+            const int roff = rp * a.wu + ux;
+#pragma unroll
+            for (int side = 0; side < 4; ++side) {
+                const bool ok = rok && pbase[side] >= 0;
+                const int off = ok ? pbase[side] + roff : kOOB;
+                const float v = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsU, off * 4, 0, 0));
+                st.m[side] = __builtin_amdgcn_raw_buffer_load_b8(rsM, off, 0, 0);
+                st.u[side] = ok ? v : -1.f;
+            }
+        };
+        auto scatter = [&](int rp, const UBuf& st) {
+#pragma unroll
+            for (int side = 0; side < 4; ++side) {
+                if (!(st.u[side] >= 0.f)) continue;       // no parent or column, or U = -inf (unreached)
+                const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;
+                const int ry = 2 * rp + st.m[side] / 3 - 1 + sy, rxx = 2 * ux + st.m[side] % 3 - 1 + sx;
+                if (ry < R0 || ry >= R1 || rxx < C0 || rxx >= Cend) continue;
+                atomicMax(&ring[ry % kBtRing][rxx - C0], enc(st.u[side]));
+            }
+        };
+        auto collect = [&](int rp, OBuf& o) {
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy) {
+                const int ry = 2 * rp - 2 + dy;
+                const bool rok = ry >= R0 && ry < R1;                          // uniform
+                o.vb[dy] = (rok && lane_o) ? atomicExch(&ring[(ry + kBtRing) % kBtRing][t], 0u) : 0u;
+                const int off = o.vb[dy] ? cbase + ry * a.w + rx : kOOB;
+                o.cv[dy] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsC, off * 4, 0, 0));
+                o.cm[dy] = __builtin_amdgcn_raw_buffer_load_b8(rsK, off, 0, 0);
+            }
+        };
+        auto finish = [&](int rp, const OBuf& o) {
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy) {
+                const int ry = 2 * rp - 2 + dy;
+                if (ry < R0 || ry >= R1 || !lane_o) continue;
+                const uint32_t vb = o.vb[dy];
+                if (!a.is_bottom) {
+                    u_prev[((size_t)c * a.h + ry) * a.w + rx] = vb ? o.cv[dy] + dec(vb) : -INFINITY;
+                } else if (vb) {
+                    const float uu = o.cv[dy] + dec(vb);
+                    const int mm = o.cm[dy];
+                    const int xy = 2 * ry + mm / 3 - 1, xx = 2 * rx + mm % 3 - 1;
+                    const unsigned long long hi = (unsigned long long)__float_as_uint(uu) << 32;
+                    const unsigned long long kb = hi | (0xFFFFFFFFull - (uint32_t)(xy * a.W2 + xx));
+                    mybest = kb > mybest ? kb : mybest;
+                    const unsigned long long kc = hi | (0xFFFFFFFFull - (uint32_t)(c * 16 + (xy & 3) * 4 + (xx & 3)));
+                    atomicMax(&sCell[((xy >> 2) - cyb) * NCX + ((xx >> 2) - cxb)], kc);
+                }
+            }
+        };
+        // Step rp: U_l row rp+1 is loading, row rp is scattered, output rows of
+        // step rp are collected (their C' loads issued) and those of step rp-1
+        // finished.  All loads are unconditional instructions, so no wait has
+        // to drain the ones still in flight.
+        UBuf u0, u1;
+        OBuf o0, o1;
+        o1.vb[0] = o1.vb[1] = 0u;
+        o1.cv[0] = o1.cv[1] = 0.f;
+        o1.cm[0] = o1.cm[1] = 0;
+        load_u(rp0, u0);
+        int rp = rp0;
+        for (;;) {
+            load_u(rp + 1, u1);
+            scatter(rp, u0);
+            wave_sync();
+            collect(rp, o0);
+            finish(rp - 1, o1);
+            wave_sync();
+            if (rp == rp1) {
+                finish(rp, o0);
+                break;
+            }
+            ++rp;
+            load_u(rp + 1, u0);
+            scatter(rp, u1);
+            wave_sync();
+            collect(rp, o1);
+            finish(rp - 1, o0);
+            wave_sync();
+            if (rp == rp1) {
+                finish(rp, o1);
+                break;
+            }
+            ++rp;
+        }
+    }
+    if (!a.is_bottom) return;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)mybest, d), hi = __shfl_xor((uint32_t)(mybest >> 32), d);
+        const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+        mybest = o > mybest ? o : mybest;
+    }
+    if (live && t == 0 && mybest) atomicMax(&best[c], mybest);
+    __syncthreads();
+    for (int e = tid; e < ncy * NCX; e += 64 * kBtWaves) {
+        const unsigned long long v = sCell[e];
+        if (!v) continue;
+        const int cy = cyb + e / NCX, cx = cxb + e % NCX;
+        atomicMax(&cell[(size_t)cy * a.cw + cx], v);
+    }
+}
+
 // A pyramid whose top is the bottom level: M' = every (p, q) of C_top.
 __global__ void k_top_reduce(const float* __restrict__ top, Geom g, unsigned long long* __restrict__ best,
                              unsigned long long* __restrict__ cell) {
@@ -354,6 +564,32 @@ hipError_t launch_backtrack<float>(int l, const float* cp_prev, const uint8_t* c
     a.f_tc = make_fastdiv(a.TC);
     a.f_nr = make_fastdiv((a.TR / 2 + 2) * (a.TC / 2 + 2));
     a.f_rwd = make_fastdiv(a.TC / 2 + 2);
+    const bool fits31 = (double)g.gx[l] * g.gy[l] * a.hu * a.wu * 4 < 2.0e9 &&
+                        (double)nc * a.h * a.w * 4 < 2.0e9;   // buffer offsets of the streaming form
+    if (!a.is_top && a.w >= 32 && fits31) {
+        BtStreamArgs b;
+        b.l = l;
+        b.gxp = a.gxp;
+        b.gyp = a.gyp;
+        b.gxc = a.gxc;
+        b.gyc = a.gyc;
+        b.h = a.h;
+        b.w = a.w;
+        b.hu = a.hu;
+        b.wu = a.wu;
+        b.is_bottom = a.is_bottom;
+        b.TR = a.h < kBtMaxTR ? ((a.h + 1) & ~1) : kBtMaxTR;
+        b.n_band = (a.h + b.TR - 1) / b.TR;
+        b.n_ct = (a.w + kBtCols - 1) / kBtCols;
+        b.n_cgrp = (nc + kBtWaves - 1) / kBtWaves;
+        b.W2 = a.W2;
+        b.cw = a.cw;
+        const int nb = b.n_cgrp * b.n_ct * b.n_band;
+        hipLaunchKernelGGL(k_backtrack_stream, dim3(((nb + 7) / 8) * 8), dim3(64 * kBtWaves), 0, s, b, cp_prev,
+                           code_prev, u_cur, code_cur, vt, g, u_prev, (unsigned long long*)best,
+                           (unsigned long long*)cell, nb);
+        return hipGetLastError();
+    }
     const dim3 grid(((nblocks + 7) / 8) * 8);
     hipLaunchKernelGGL(k_backtrack, grid, dim3(256), smem, s, a, cp_prev, code_prev, u_cur, code_cur, top, vt, g,
                        u_prev, (unsigned long long*)best, (unsigned long long*)cell, nblocks);

@@ -9,6 +9,8 @@
 // touch (each A value feeds up to 4 windows), then pools from LDS.  Child maps
 // are read straight from global memory, coalesced along x; a child is shared
 // by up to 4 parents, which neighbouring blocks read at the same time.
+#include <type_traits>
+
 #include "dm_internal.h"
 
 namespace dm {
@@ -171,6 +173,177 @@ __global__ __launch_bounds__(256) void k_level_pool(LevelArgs a, const T* __rest
     }
 }
 
+// Row-streaming form of k_level_pool for maps at least 32 pooled columns
+// wide.  One wave owns a parent, a band of pooled rows and up to 128 pooled
+// columns, and walks down the rows of A.  Lane t owns the 4 A columns
+// X0 + 4t .. X0 + 4t + 3 (X0 = 2 C0 - 1) and the pooled columns C0 + 2t,
+// C0 + 2t + 1; the fifth A value the second window needs comes from lane
+// t + 1 (lane 63: a halo column every lane loads).  Each A row is computed
+// once from 4 child rows (no branches around the loads: clamped addresses,
+// then selects), pooled horizontally in registers and merged into a running
+// vertical maximum; the loads of the next row are in flight meanwhile.
+// Scanning my outer and mx inner with strict comparisons keeps the first
+// maximum in code order, as the direct 3x3 scan does.
+constexpr int kStreamCols = 128;     // pooled columns per wave
+constexpr int kStreamWaves = 4;      // independent waves per block
+
+struct StreamArgs {
+    int l;
+    int gx, gy, gxc, gyc;
+    int h, w, hp, wp;
+    int TRo, n_band, n_ct, n_items;
+    int vec;                         // w % 4 == 0: 16-byte child row segments
+};
+
+// Child values of one A row for a lane: v[k][j] for its 4 columns, hv[k] for
+// the halo column (0 where the child, its row or the column does not exist).
+struct RowBuf {
+    float v[4][4];
+    float hv[4];
+};
+
+// Vector elements are read with __uint_as_float(f[j]): a bit cast applied to
+// an element expression of an ext_vector reads element 0 on this compiler.
+// Buffer descriptor of one child row: loads at byte offsets outside
+// [0, nbytes) return 0 in hardware, which is exactly the rule for child
+// values outside the map (and nbytes = 0 for a missing child or row).
+__device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const float* row, int nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(row), (short)0, nbytes, 0x00020000);
+}
+
+template <bool VEC>
+__device__ inline void load_row(const StreamArgs& a, const float* prev, const float* const cmap[4], int y, int X0,
+                                int t, RowBuf& b) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int yy = y + 2 * (k >> 1) - 1, dx = 2 * (k & 1) - 1;
+        const bool rok = cmap[k] != nullptr && yy >= 0 && yy < a.h;     // uniform over the wave
+        const __amdgpu_buffer_rsrc_t rs = row_rsrc(rok ? cmap[k] + (size_t)yy * a.w : prev, rok ? a.w * 4 : 0);
+        const int s0 = X0 + 4 * t + dx;   // may be -2: the unsigned offset is then out of range
+        if constexpr (VEC) {
+            if (k & 1) {   // s0 = 2 C0 + 4t: 16-byte aligned, entirely inside or outside the row
+                const auto f = __builtin_amdgcn_raw_buffer_load_b128(rs, s0 * 4, 0, 0);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b.v[k][j] = __uint_as_float(f[j]);
+            } else {       // s0 = 2 C0 + 4t - 2: two 8-byte halves, each inside or outside
+                const auto f0 = __builtin_amdgcn_raw_buffer_load_b64(rs, s0 * 4, 0, 0);
+                const auto f1 = __builtin_amdgcn_raw_buffer_load_b64(rs, s0 * 4 + 8, 0, 0);
+                b.v[k][0] = __uint_as_float(f0[0]);
+                b.v[k][1] = __uint_as_float(f0[1]);
+                b.v[k][2] = __uint_as_float(f1[0]);
+                b.v[k][3] = __uint_as_float(f1[1]);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                b.v[k][j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (s0 + j) * 4, 0, 0));
+        }
+        b.hv[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (X0 + 4 * 64 + dx) * 4, 0, 0));
+    }
+}
+
+// Horizontal first maxima (value, mx code 0..2) of the lane's two windows.
+__device__ inline void pool_row(const StreamArgs& a, const RowBuf& b, float inv, int y, int X0, int t, float hv[2],
+                                int hk[2]) {
+    const bool yin = y >= 0 && y < a.h;
+    float av[5];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float s = (((0.f + b.v[0][j]) + b.v[1][j]) + b.v[2][j]) + b.v[3][j];
+        const float m = s * inv;
+        const int x = X0 + 4 * t + j;
+        av[j] = (yin && x >= 0 && x < a.w) ? fmaxf(m, 0.f) : -1.f;
+    }
+    {
+        const float s = (((0.f + b.hv[0]) + b.hv[1]) + b.hv[2]) + b.hv[3];
+        const float m = s * inv;
+        const float halo = (yin && X0 + 4 * 64 < a.w) ? fmaxf(m, 0.f) : -1.f;
+        const float nb = __shfl_down(av[0], 1);
+        av[4] = t == 63 ? halo : nb;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const float v0 = av[2 * q], v1 = av[2 * q + 1], v2 = av[2 * q + 2];
+        float best = v0;
+        int k = 0;
+        if (v1 > best) { best = v1; k = 1; }
+        if (v2 > best) { best = v2; k = 2; }
+        hv[q] = best;
+        hk[q] = k;
+    }
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(64 * kStreamWaves) void k_level_stream(StreamArgs a, const float* __restrict__ prev,
+                                                                     const uint8_t* __restrict__ vt, Geom g, float lam,
+                                                                     float* __restrict__ cp,
+                                                                     uint8_t* __restrict__ code, int nblocks) {
+    const int bid = xcd_block(nblocks);
+    if (bid >= nblocks) return;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), t = threadIdx.x & 63;   // wave index: uniform
+    const int item = bid * kStreamWaves + wv;
+    if (item >= a.n_items) return;
+    const int np = a.gx * a.gy;
+    const int P = item % np, rest = item / np;
+    const int ct = rest % a.n_ct, band = rest / a.n_ct;
+    const int pb = P / a.gx, pa = P - pb * a.gx;
+    const uint8_t *vxp = vtab(vt, g, a.l, 0), *vyp = vtab(vt, g, a.l, 1);
+    if (!(vxp[pa] && vyp[pb])) return;
+    const uint8_t *vxc = vtab(vt, g, a.l - 1, 0), *vyc = vtab(vt, g, a.l - 1, 1);
+    const size_t hw = (size_t)a.h * a.w;
+    const float* cmap[4];
+    int nx = 0, ny = 0, ex[2], ey[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int ca = child_index(a.l, pa, 2 * k - 1), cb = child_index(a.l, pb, 2 * k - 1);
+        ex[k] = (ca >= 0 && ca < a.gxc && vxc[ca]) ? ca : -1;
+        ey[k] = (cb >= 0 && cb < a.gyc && vyc[cb]) ? cb : -1;
+        nx += ex[k] >= 0;
+        ny += ey[k] >= 0;
+    }
+    if (nx * ny == 0) return;   // a valid parent always has a child; kept for safety
+#pragma unroll
+    for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < 2; ++kx)
+            cmap[2 * ky + kx] = (ey[ky] >= 0 && ex[kx] >= 0) ? prev + (size_t)(ey[ky] * a.gxc + ex[kx]) * hw : nullptr;
+    const float inv = 1.f / float(nx * ny);
+    const int R0 = band * a.TRo, R1 = min(R0 + a.TRo, a.hp);
+    const int C0 = ct * kStreamCols, ncol = min(kStreamCols, a.wp - C0);
+    const int X0 = 2 * C0 - 1;
+
+    RowBuf b0, b1;
+    float pv[2], hv[2];
+    int pk[2], hk[2];
+    load_row<VEC>(a, prev, cmap, 2 * R0 - 1, X0, t, b0);
+    load_row<VEC>(a, prev, cmap, 2 * R0, X0, t, b1);
+    pool_row(a, b0, inv, 2 * R0 - 1, X0, t, pv, pk);
+    for (int r = R0; r < R1; ++r) {
+        // b1 holds row 2r
+        load_row<VEC>(a, prev, cmap, 2 * r + 1, X0, t, b0);
+        float best[2];
+        int bk[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) { best[q] = pv[q]; bk[q] = pk[q]; }
+        pool_row(a, b1, inv, 2 * r, X0, t, hv, hk);
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (hv[q] > best[q]) { best[q] = hv[q]; bk[q] = 3 + hk[q]; }
+        load_row<VEC>(a, prev, cmap, 2 * r + 2, X0, t, b1);   // row 2R1 is in range or masked
+        pool_row(a, b0, inv, 2 * r + 1, X0, t, pv, pk);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (pv[q] > best[q]) { best[q] = pv[q]; bk[q] = 6 + pk[q]; }
+            const int u = 2 * t + q;
+            if (u < ncol) {
+                const size_t o = ((size_t)P * a.hp + r) * a.wp + C0 + u;
+                cp[o] = rect_pow(best[q], lam);
+                code[o] = (uint8_t)bk[q];
+            }
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_level_top(LevelArgs a, const T* __restrict__ prev,
                                                    const uint8_t* __restrict__ vt, Geom g, T lam,
@@ -233,6 +406,31 @@ hipError_t launch_level(int l, const T* prev, const uint8_t* vt, const Geom& g, 
     const size_t sp_bytes = ((size_t)a.PB * sizeof(ParentLDS<T>) + 15) & ~size_t(15);
     if (is_top) {
         hipLaunchKernelGGL(k_level_top<T>, grid, dim3(256), sp_bytes, s, a, prev, vt, g, lam, top, nblocks);
+    } else if (std::is_same<T, float>::value && a.wp >= 32) {
+        StreamArgs b;
+        b.l = l;
+        b.gx = a.gx;
+        b.gy = a.gy;
+        b.gxc = a.gxc;
+        b.gyc = a.gyc;
+        b.h = a.h;
+        b.w = a.w;
+        b.hp = a.hp;
+        b.wp = a.wp;
+        b.TRo = a.hp < 16 ? a.hp : 16;
+        b.n_band = (a.hp + b.TRo - 1) / b.TRo;
+        b.n_ct = (a.wp + kStreamCols - 1) / kStreamCols;
+        b.n_items = np * b.n_ct * b.n_band;
+        b.vec = (a.w % 4) == 0;
+        const int nb = (b.n_items + kStreamWaves - 1) / kStreamWaves;
+        const float* pf = reinterpret_cast<const float*>(prev);
+        float* cf = reinterpret_cast<float*>(cp);
+        if (b.vec)
+            hipLaunchKernelGGL(k_level_stream<true>, dim3(((nb + 7) / 8) * 8), dim3(64 * kStreamWaves), 0, s, b, pf,
+                               vt, g, (float)lam, cf, code, nb);
+        else
+            hipLaunchKernelGGL(k_level_stream<false>, dim3(((nb + 7) / 8) * 8), dim3(64 * kStreamWaves), 0, s, b, pf,
+                               vt, g, (float)lam, cf, code, nb);
     } else {
         const size_t smem = sp_bytes + (size_t)a.PB * (2 * a.TRo + 1) * (2 * a.TCo + 1) * sizeof(T);
         hipLaunchKernelGGL(k_level_pool<T>, grid, dim3(256), smem, s, a, prev, vt, g, lam, cp, code, nblocks);
