@@ -22,8 +22,12 @@
  *    Arguments are validated on the host before anything is enqueued; on an
  *    error nothing is enqueued and dm_last_error() describes the problem.
  *  - The library keeps no state between calls other than the thread-local
- *    error text.  Calls on different streams with different workspaces may
- *    run concurrently; two calls sharing a workspace must be ordered.
+ *    error text, the per-stage timing records (when enabled) and, for
+ *    dm_match_batch, one cached batch schedule per workspace (job tables,
+ *    chosen tile shapes and, with DM_BATCH_GRAPH, an instantiated HIP graph),
+ *    dropped by dm_batch_release.  Calls on different streams with different
+ *    workspaces may run concurrently; two calls sharing a workspace must be
+ *    ordered.
  */
 #ifndef DM_H
 #define DM_H
@@ -208,6 +212,85 @@ dm_status dm_pyramid_backward(const void* d1, int W1, int H1, const void* d2, in
                               const dm_params* prm, int recompute, const void* saved, size_t saved_bytes,
                               const void* dc_top, void* dd1, void* dd2, void* scratch, size_t scratch_bytes,
                               hipStream_t stream);
+
+/* ------------------------------------------------------------------ batches
+ * Many image pairs of uneven sizes in one call (a throughput extension: the
+ * method itself is defined per pair, Sec. 3, and its per-patch loops are
+ * independent, Algorithm 2).  Each pair goes through exactly the stages of
+ * dm_match_images, with the same kernels and the same arithmetic, so its
+ * matches are identical to those of a dm_match_images call with its images;
+ * but every stage runs as ONE persistent grouped launch covering all pairs
+ * (a fixed grid of resident blocks walks a table of (pair, tile) work items),
+ * so small pairs and the small upper levels fill the GPU together.
+ *
+ * flags:
+ *  DM_BATCH_BWD       also the gradient of the loss L = sum over top-level
+ *                     patches P of max_q C_top(P, q) (the top map's first
+ *                     maximum takes the gradient) with respect to both
+ *                     descriptor fields, into pair.dd1 / pair.dd2; the same
+ *                     kernels as dm_pyramid_backward with recompute = 0.
+ *  DM_BATCH_GRAPH     capture the whole sequence of launches in a HIP graph on
+ *                     the first call and replay it on later calls with the
+ *                     same arguments (stream must not be the null stream).
+ *  DM_BATCH_AUTOTUNE  on the first call, time candidate tile shapes (band
+ *                     heights of the streaming level and backtracking
+ *                     kernels, resident blocks per CU of each grouped launch)
+ *                     on this batch and keep the fastest (dm_batch_tiles_get).
+ * The schedule (job tables in the workspace, tiles, graph) is cached per
+ * workspace and rebuilt when any argument changes.  Precisions DM_FP32 and
+ * DM_BF16; every pair needs at least one pooled level (N_max >= 8). */
+#define DM_MAX_BATCH 256
+#define DM_BATCH_BWD 1
+#define DM_BATCH_GRAPH 2
+#define DM_BATCH_AUTOTUNE 4
+
+typedef struct {
+    const float* img1;   /* I: W1 x H1, leading dimension ld1 (device)      */
+    int32_t W1, H1, ld1;
+    const float* img2;   /* I': W2 x H2, leading dimension ld2 (device)     */
+    int32_t W2, H2, ld2;
+    float* dd1;          /* DM_BATCH_BWD: dL/dD1, H1 x W1 x 9 (device)      */
+    float* dd2;          /* DM_BATCH_BWD: dL/dD2, H2 x W2 x 9 (device)      */
+} dm_pair;
+
+typedef struct {
+    int32_t n_pairs;
+    int32_t n_launches;                  /* grouped launches per call        */
+    int32_t max_matches[DM_MAX_BATCH];   /* per pair (= dm_plan max_matches) */
+    int32_t lmax[DM_MAX_BATCH];          /* per pair pyramid top level       */
+    uint64_t workspace_bytes;
+} dm_batch_info;
+
+typedef struct {
+    int32_t level_rows;          /* pooled rows per band, streaming level kernel  */
+    int32_t bt_rows;             /* rows per band, streaming backtracking kernel  */
+    int32_t blocks_per_cu[32];   /* resident blocks per CU, per grouped kernel kind */
+    int32_t tuned;               /* 1 if the autotuner chose these values         */
+    float tuned_ms;              /* forward time of the batch with them (tuner)   */
+} dm_batch_tiles;
+
+/* Sizes of a batch of n pairs (1 <= n <= DM_MAX_BATCH).  Host only; reads
+ * the sizes in pairs[] only.  Errors: DM_ERR_INVALID_ARG, DM_ERR_SHAPE,
+ * DM_ERR_UNSUPPORTED (FP64, or a pair without a pooled level). */
+dm_status dm_plan_batch(int n, const dm_pair* pairs, const dm_params* prm, int flags, dm_batch_info* out);
+
+/* Matches of every pair: pair k writes its matches (sorted by (y1, x1)) to
+ * out + out_offsets_host[k] and their number to n_out[k] (device).  The
+ * caller sizes out so that pair k has max_matches[k] entries from its offset
+ * on; offsets must leave that room (checked).  ws (256-byte aligned) must hold
+ * info.workspace_bytes and is owned by the batch schedule between calls with
+ * the same arguments.  Errors: those of dm_plan_batch, DM_ERR_WORKSPACE,
+ * DM_ERR_CAPACITY (overlapping output ranges), DM_ERR_HIP. */
+dm_status dm_match_batch(int n, const dm_pair* pairs, const dm_params* prm, int flags, void* ws, size_t ws_bytes,
+                         dm_match* out, const int32_t* out_offsets_host, int32_t* n_out, hipStream_t stream);
+
+/* Tile shapes of the schedule cached for workspace ws (host).  Errors:
+ * DM_ERR_INVALID_ARG if no schedule is cached for ws. */
+dm_status dm_batch_tiles_get(const void* ws, dm_batch_tiles* out);
+
+/* Drops the schedule (and graph) cached for workspace ws; call before freeing
+ * or reusing ws for other data.  Errors: none. */
+dm_status dm_batch_release(const void* ws);
 
 /* Per-stage timing (for benchmarks and profiling).  While enabled, every
  * kernel launch the library makes is bracketed by two HIP events recorded on

@@ -65,6 +65,26 @@ class StageTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 40), ("level", c_int32), ("count", c_int32), ("total_ms", ctypes.c_double)]
 
 
+DM_MAX_BATCH = 256
+DM_BATCH_BWD, DM_BATCH_GRAPH, DM_BATCH_AUTOTUNE = 1, 2, 4
+
+
+class Pair(ctypes.Structure):
+    _fields_ = [("img1", c_void_p), ("W1", c_int32), ("H1", c_int32), ("ld1", c_int32),
+                ("img2", c_void_p), ("W2", c_int32), ("H2", c_int32), ("ld2", c_int32),
+                ("dd1", c_void_p), ("dd2", c_void_p)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_pairs", c_int32), ("n_launches", c_int32), ("max_matches", c_int32 * DM_MAX_BATCH),
+                ("lmax", c_int32 * DM_MAX_BATCH), ("workspace_bytes", c_uint64)]
+
+
+class BatchTiles(ctypes.Structure):
+    _fields_ = [("level_rows", c_int32), ("bt_rows", c_int32), ("blocks_per_cu", c_int32 * 32),
+                ("tuned", c_int32), ("tuned_ms", c_float)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/dm.h.
 SIGNATURES = {
     "dm_default_params": (c_int, [POINTER(Params)]),
@@ -80,6 +100,11 @@ SIGNATURES = {
     "dm_pyramid_backward": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int, c_int, POINTER(Params), c_int,
                                     c_void_p, c_size_t, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                     c_void_p]),
+    "dm_plan_batch": (c_int, [c_int, POINTER(Pair), POINTER(Params), c_int, POINTER(BatchInfo)]),
+    "dm_match_batch": (c_int, [c_int, POINTER(Pair), POINTER(Params), c_int, c_void_p, c_size_t, c_void_p,
+                               POINTER(c_int32), c_void_p, c_void_p]),
+    "dm_batch_tiles_get": (c_int, [c_void_p, POINTER(BatchTiles)]),
+    "dm_batch_release": (c_int, [c_void_p]),
     "dm_timing_enable": (c_int, [c_int]),
     "dm_timing_read": (c_int, [POINTER(StageTime), c_int, POINTER(c_int)]),
     "dm_status_string": (c_char_p, [c_int]),
@@ -347,6 +372,83 @@ class DMPyramid(torch.autograd.Function):
         dd1, dd2 = ctx.pyr.backward(dtop)
         ctx.pyr = None
         return dd1, dd2, None, None
+
+
+class Batch:
+    """Many image pairs of uneven sizes matched together (dm_match_batch).
+
+    Buffers (workspace, outputs, gradients) live here so that repeated
+    run() calls present the same arguments and replay the cached schedule
+    (with graph=True, one HIP graph launch per call).  Calls go to a side
+    stream of default priority, joined with the current stream on entry and
+    exit.  Images are copied into the batch's own input buffers by
+    set_images(); run() takes no tensors."""
+
+    def __init__(self, sizes, prm: Params | None = None, bwd: bool = False, graph: bool = True,
+                 autotune: bool = False, device="cuda"):
+        self.prm = prm or params()
+        self.sizes = [tuple(int(v) for v in sz) for sz in sizes]   # (W1, H1, W2, H2)
+        self.n = len(self.sizes)
+        self.flags = (DM_BATCH_BWD if bwd else 0) | (DM_BATCH_GRAPH if graph else 0) | \
+            (DM_BATCH_AUTOTUNE if autotune else 0)
+        self.img1 = [torch.zeros((H1, W1), dtype=torch.float32, device=device) for W1, H1, _, _ in self.sizes]
+        self.img2 = [torch.zeros((H2, W2), dtype=torch.float32, device=device) for _, _, W2, H2 in self.sizes]
+        self.dd1 = [torch.zeros((H1, W1, 9), dtype=torch.float32, device=device) if bwd else None
+                    for W1, H1, _, _ in self.sizes]
+        self.dd2 = [torch.zeros((H2, W2, 9), dtype=torch.float32, device=device) if bwd else None
+                    for _, _, W2, H2 in self.sizes]
+        self.pairs = (Pair * self.n)()
+        for k, (W1, H1, W2, H2) in enumerate(self.sizes):
+            self.pairs[k] = Pair(self.img1[k].data_ptr(), W1, H1, W1, self.img2[k].data_ptr(), W2, H2, W2,
+                                 self.dd1[k].data_ptr() if bwd else None, self.dd2[k].data_ptr() if bwd else None)
+        self.info = BatchInfo()
+        _check(lib().dm_plan_batch(self.n, self.pairs, ctypes.byref(self.prm), self.flags, ctypes.byref(self.info)))
+        offs, o = [], 0
+        for k in range(self.n):
+            offs.append(o)
+            o += self.info.max_matches[k]
+        self.offsets = (c_int32 * self.n)(*offs)
+        self.out = torch.empty((max(1, o), 5), dtype=torch.int32, device=device)
+        self.n_out = torch.zeros(self.n, dtype=torch.int32, device=device)
+        self.ws = torch.empty(int(self.info.workspace_bytes), dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.Stream(device=device)
+
+    def set_images(self, imgs1, imgs2):
+        for k in range(self.n):
+            self.img1[k].copy_(imgs1[k])
+            self.img2[k].copy_(imgs2[k])
+
+    def run(self):
+        """Enqueue the batch (on the side stream, ordered after the current
+        stream's work; the current stream waits for it)."""
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        with torch.cuda.stream(self.stream):
+            _check(lib().dm_match_batch(self.n, self.pairs, ctypes.byref(self.prm), self.flags,
+                                        c_void_p(self.ws.data_ptr()), self.ws.numel(), c_void_p(self.out.data_ptr()),
+                                        self.offsets, c_void_p(self.n_out.data_ptr()),
+                                        c_void_p(self.stream.cuda_stream)))
+        cur.wait_stream(self.stream)
+
+    def matches(self) -> list:
+        """Matches of the last run, one (n, 5) tensor per pair."""
+        cnt = self.n_out.cpu().tolist()
+        return [_matches_tensor(self.out[self.offsets[k]:], cnt[k]) for k in range(self.n)]
+
+    def tiles(self) -> BatchTiles:
+        t = BatchTiles()
+        _check(lib().dm_batch_tiles_get(c_void_p(self.ws.data_ptr()), ctypes.byref(t)))
+        return t
+
+    def release(self):
+        lib().dm_batch_release(c_void_p(self.ws.data_ptr()))
+
+    def __del__(self):
+        try:
+            if _lib is not None and hasattr(self, "ws"):
+                _lib.dm_batch_release(c_void_p(self.ws.data_ptr()))
+        except Exception:
+            pass
 
 
 def top_loss(top: torch.Tensor) -> torch.Tensor:

@@ -4,6 +4,9 @@
 
 #include <stdint.h>
 #include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <vector>
 
 #include "dm.h"
 
@@ -77,6 +80,81 @@ struct DescParams {
     float g1[2 * kMaxRadius + 1], g2[2 * kMaxRadius + 1], g3[2 * kMaxRadius + 1];
 };
 DescParams make_desc_params(const dm_params* prm);
+
+// Grouped (batched) stages: each .hip file turns one pair's stage into a job
+// record (the kernel's arguments for that pair as a byte image, its block
+// count and LDS need); jobs of one kind run together in one persistent launch
+// (dm_group.h) through launch_group().
+enum JobKind : int {
+    JK_DESC = 0,
+    JK_VALID,
+    JK_CORR_BF16,
+    JK_CORR_F32,
+    JK_LEVEL_STREAM_VEC,
+    JK_LEVEL_STREAM,
+    JK_LEVEL_POOL,
+    JK_LEVEL_TOP,
+    JK_FILL,
+    JK_BT,
+    JK_BT_STREAM,
+    JK_TOP_REDUCE,
+    JK_FINALIZE,
+    JK_TOP_GRAD,
+    JK_BWD_LEVEL,
+    JK_BWD_DA_BF16,
+    JK_BWD_DA_F32,
+    JK_PATCH_BF16,
+    JK_PATCH_F32,
+    JK_DD1_BF16,
+    JK_DD1_F32,
+    JK_TG_BF16,
+    JK_TG_F32,
+    JK_DD1_REDUCE,
+    JK_COL2IM,
+    JK_COUNT
+};
+
+struct JobRec {
+    int kind = -1;
+    int blocks = 0;     // virtual blocks of this job
+    size_t smem = 0;    // dynamic LDS per block
+    std::vector<unsigned char> bytes;
+    template <class J>
+    void set(int k, int nb, size_t lds, const J& j) {
+        kind = k;
+        blocks = nb;
+        smem = lds;
+        bytes.resize(sizeof(J));
+        memcpy(bytes.data(), &j, sizeof(J));
+    }
+};
+struct GroupLaunch;
+// Per-kind launch parameters: job record size, threads per block, resident
+// blocks per CU the kernel allows.
+size_t job_size(int kind);
+hipError_t launch_group(int kind, const GroupLaunch& gl, hipStream_t s);
+hipError_t launch_group_desc(int kind, const GroupLaunch& gl, hipStream_t s);
+JobRec desc_job(const float* img, int W, int H, int ld, const DescParams& p, float* out, uint16_t* out_bf16);
+hipError_t launch_group_corr(int kind, const GroupLaunch& gl, hipStream_t s);
+JobRec corr_job(bool bf16, const void* d1, const void* d2, const Geom& g, float lam, float* cp, uint8_t* code);
+hipError_t launch_group_level(int kind, const GroupLaunch& gl, hipStream_t s);
+JobRec level_job(int l, const float* prev, const uint8_t* vt, const Geom& g, float lam, float* cp, uint8_t* code,
+                 float* top, int tro);
+hipError_t launch_group_bt(int kind, const GroupLaunch& gl, hipStream_t s);
+JobRec bt_job(int l, const float* cp_prev, const uint8_t* code_prev, const float* u_cur, const uint8_t* code_cur,
+              const float* top, const uint8_t* vt, const Geom& g, float* u_prev, uint64_t* best, uint64_t* cell,
+              int tr);
+JobRec top_reduce_job(const float* top, const Geom& g, uint64_t* best, uint64_t* cell);
+JobRec finalize_job(const uint64_t* best, const uint64_t* cell, const Geom& g, dm_match* out, int* n_out);
+JobRec fill_job(uint64_t* p, size_t n, uint64_t v);
+JobRec valid_job(const Geom& g, uint8_t* vt);
+hipError_t launch_group_bwd(int kind, const GroupLaunch& gl, hipStream_t s);
+JobRec bwd_level_job(int l, const float* dtop, const float* top, const float* gp_cur, const uint8_t* code_cur,
+                     const float* cp_prev, const uint8_t* vt, const Geom& g, float lam, float* gp_prev);
+JobRec top_grad_job(const float* top, const Geom& g, float* dtop);
+hipError_t launch_group_bot(int kind, const GroupLaunch& gl, hipStream_t s);
+std::vector<JobRec> bot_jobs(bool bf16, const float* gp, const uint8_t* code, const float* d1, const float* d2,
+                             const Geom& g, float* part, float* tbuf, void* dense, float* dd1, float* dd2);
 
 // Opt-in stage timing (dm_timing.cpp); calls may nest.
 void timing_begin(const char* name, int level, hipStream_t s);

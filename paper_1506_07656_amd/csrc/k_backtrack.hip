@@ -18,7 +18,7 @@
 //               smallest (p_y, p_x, p'_y, p'_x)
 // Scores are sums of non-negative values, so their float bits order like the
 // floats and the packed 64-bit maxima are exact and order independent.
-#include "dm_internal.h"
+#include "dm_group.h"
 
 namespace dm {
 namespace {
@@ -45,14 +45,11 @@ __device__ inline int xcd_block(int nblocks) {
     return (blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
-__global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __restrict__ cp_prev,
-                                                   const uint8_t* __restrict__ code_prev,
-                                                   const float* __restrict__ u_cur,
-                                                   const uint8_t* __restrict__ code_cur,
-                                                   const float* __restrict__ top, const uint8_t* __restrict__ vt,
-                                                   Geom g, float* __restrict__ u_prev,
-                                                   unsigned long long* __restrict__ best,
-                                                   unsigned long long* __restrict__ cell, int nblocks) {
+__device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_prev,
+                               const uint8_t* __restrict__ code_prev, const float* __restrict__ u_cur,
+                               const uint8_t* __restrict__ code_cur, const float* __restrict__ top,
+                               const uint8_t* __restrict__ vt, const Geom& g, float* __restrict__ u_prev,
+                               unsigned long long* __restrict__ best, unsigned long long* __restrict__ cell, int bid) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int T = a.TR * a.TC;
     uint32_t* sV = (uint32_t*)smem_raw;                                   // [CB][4][TR][TC]
@@ -60,8 +57,6 @@ __global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __rest
     unsigned long long* sCell = sBest + a.CB;                               // [ncy][ncx]
     int* sPar = (int*)(sCell + a.ncy * a.ncx);                              // [CB][4] parent map index
     int* sCv = sPar + 4 * a.CB;                                             // [CB] child exists
-    const int bid = xcd_block(nblocks);
-    if (bid >= nblocks) return;
     const int cblk = bid % a.n_cblk, rest = bid / a.n_cblk;   // once per block (scalar)
     const int R0 = (rest % a.n_rt) * a.TR, C0 = (rest / a.n_rt) * a.TC;
     const int tid = threadIdx.x;
@@ -238,7 +233,7 @@ constexpr int kBtCols = 64;
 constexpr int kBtWaves = 4;
 constexpr int kBtRing = 6;     // live candidate rows: 2r'-2 .. 2r'+2
 constexpr int kBtMaxTR = 32;
-constexpr int kOOB = 0x7ffffff0;   // buffer offset past any map
+constexpr int kOOB = 0x7ffffff0;   // buffer byte offset past any map (element offsets stay < 2^29)
 
 struct BtStreamArgs {
     int l;
@@ -260,16 +255,15 @@ __device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, int nbytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, nbytes, 0x00020000);
 }
 
-__global__ __launch_bounds__(64 * kBtWaves) void k_backtrack_stream(
-    BtStreamArgs a, const float* __restrict__ cp_prev, const uint8_t* __restrict__ code_prev,
-    const float* __restrict__ u_cur, const uint8_t* __restrict__ code_cur, const uint8_t* __restrict__ vt, Geom g,
-    float* __restrict__ u_prev, unsigned long long* __restrict__ best, unsigned long long* __restrict__ cell,
-    int nblocks) {
+__device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __restrict__ cp_prev,
+                                      const uint8_t* __restrict__ code_prev, const float* __restrict__ u_cur,
+                                      const uint8_t* __restrict__ code_cur, const uint8_t* __restrict__ vt,
+                                      const Geom& g, float* __restrict__ u_prev,
+                                      unsigned long long* __restrict__ best, unsigned long long* __restrict__ cell,
+                                      int bid) {
     constexpr int NCX = kBtCols / 2 + 2;
     __shared__ uint32_t sR[kBtWaves][kBtRing][kBtCols];
     __shared__ unsigned long long sCell[(kBtMaxTR / 2 + 2) * NCX];
-    const int bid = xcd_block(nblocks);
-    if (bid >= nblocks) return;
     const int cgrp = bid % a.n_cgrp, rest = bid / a.n_cgrp;
     const int ct = rest % a.n_ct, band = rest / a.n_ct;
     const int tid = threadIdx.x, t = tid & 63;
@@ -328,9 +322,10 @@ __global__ __launch_bounds__(64 * kBtWaves) void k_backtrack_stream(
 #pragma unroll
             for (int side = 0; side < 4; ++side) {
                 const bool ok = rok && pbase[side] >= 0;
-                const int off = ok ? pbase[side] + roff : kOOB;
-                const float v = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsU, off * 4, 0, 0));
-                st.m[side] = __builtin_amdgcn_raw_buffer_load_b8(rsM, off, 0, 0);
+                const int off = pbase[side] + roff;   // element offset, used only when ok
+                const float v =
+                    __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsU, ok ? off * 4 : kOOB, 0, 0));
+                st.m[side] = __builtin_amdgcn_raw_buffer_load_b8(rsM, ok ? off : kOOB, 0, 0);
                 st.u[side] = ok ? v : -1.f;
             }
         };
@@ -350,9 +345,10 @@ __global__ __launch_bounds__(64 * kBtWaves) void k_backtrack_stream(
                 const int ry = 2 * rp - 2 + dy;
                 const bool rok = ry >= R0 && ry < R1;                          // uniform
                 o.vb[dy] = (rok && lane_o) ? atomicExch(&ring[(ry + kBtRing) % kBtRing][t], 0u) : 0u;
-                const int off = o.vb[dy] ? cbase + ry * a.w + rx : kOOB;
-                o.cv[dy] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsC, off * 4, 0, 0));
-                o.cm[dy] = __builtin_amdgcn_raw_buffer_load_b8(rsK, off, 0, 0);
+                const int off = cbase + ry * a.w + rx;   // element offset, used only where a tuple arrived
+                o.cv[dy] = __uint_as_float(
+                    __builtin_amdgcn_raw_buffer_load_b32(rsC, o.vb[dy] ? off * 4 : kOOB, 0, 0));
+                o.cm[dy] = __builtin_amdgcn_raw_buffer_load_b8(rsK, o.vb[dy] ? off : kOOB, 0, 0);
             }
         };
         auto finish = [&](int rp, const OBuf& o) {
@@ -429,10 +425,11 @@ __global__ __launch_bounds__(64 * kBtWaves) void k_backtrack_stream(
 }
 
 // A pyramid whose top is the bottom level: M' = every (p, q) of C_top.
-__global__ void k_top_reduce(const float* __restrict__ top, Geom g, unsigned long long* __restrict__ best,
-                             unsigned long long* __restrict__ cell) {
+__device__ inline void top_reduce_body(const float* __restrict__ top, const Geom& g,
+                                       unsigned long long* __restrict__ best, unsigned long long* __restrict__ cell,
+                                       int bid) {
     const size_t n = (size_t)g.gx[0] * g.gy[0] * g.H2 * g.W2;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t i = (size_t)bid * 256 + threadIdx.x;
     if (i >= n) return;
     const int xx = i % g.W2, xy = (i / g.W2) % g.H2;
     const int c = i / ((size_t)g.W2 * g.H2);
@@ -443,9 +440,9 @@ __global__ void k_top_reduce(const float* __restrict__ top, Geom g, unsigned lon
 }
 
 // Reciprocal verification (Eq. (16)) and compaction in patch order (y1, x1).
-__global__ __launch_bounds__(1024) void k_finalize(const unsigned long long* __restrict__ best,
-                                                   const unsigned long long* __restrict__ cell, Geom g,
-                                                   dm_match* __restrict__ out, int* __restrict__ n_out) {
+__device__ inline void finalize_body(const unsigned long long* __restrict__ best,
+                                     const unsigned long long* __restrict__ cell, const Geom& g,
+                                     dm_match* __restrict__ out, int* __restrict__ n_out) {
     __shared__ int wsum[16];
     __shared__ int base;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -489,8 +486,8 @@ __global__ __launch_bounds__(1024) void k_finalize(const unsigned long long* __r
     if (tid == 0) *n_out = base;
 }
 
-__global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void fill_body(unsigned long long* p, size_t n, unsigned long long v, int bid) {
+    const size_t i = (size_t)bid * 256 + threadIdx.x;
     if (i < n) p[i] = v;
 }
 
@@ -498,7 +495,7 @@ __global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v
 // rule): level 0 is complete; an index exists above when one of its two
 // children along that axis exists.  The grid of a level is the product of
 // its two axes.
-__global__ __launch_bounds__(1024) void k_valid_init(Geom g, uint8_t* __restrict__ vt) {
+__device__ inline void valid_body(const Geom& g, uint8_t* __restrict__ vt) {
     __shared__ uint8_t cur[2][DM_MAX_DIM / 4 + 2], prv[2][DM_MAX_DIM / 4 + 2];
     for (int l = 0; l <= g.lmax; ++l) {
         for (int axis = 0; axis < 2; ++axis) {
@@ -523,12 +520,105 @@ __global__ __launch_bounds__(1024) void k_valid_init(Geom g, uint8_t* __restrict
     }
 }
 
-}  // namespace
+__global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __restrict__ cp_prev,
+                                                   const uint8_t* __restrict__ code_prev,
+                                                   const float* __restrict__ u_cur,
+                                                   const uint8_t* __restrict__ code_cur,
+                                                   const float* __restrict__ top, const uint8_t* __restrict__ vt,
+                                                   Geom g, float* __restrict__ u_prev,
+                                                   unsigned long long* __restrict__ best,
+                                                   unsigned long long* __restrict__ cell, int nblocks) {
+    const int bid = xcd_block(nblocks);
+    if (bid >= nblocks) return;
+    bt_body(a, cp_prev, code_prev, u_cur, code_cur, top, vt, g, u_prev, best, cell, bid);
+}
 
-template <>
-hipError_t launch_backtrack<float>(int l, const float* cp_prev, const uint8_t* code_prev, const float* u_cur,
-                                   const uint8_t* code_cur, const float* top, const uint8_t* vt, const Geom& g,
-                                   float* u_prev, uint64_t* best, uint64_t* cell, hipStream_t s) {
+__global__ __launch_bounds__(64 * kBtWaves) void k_backtrack_stream(
+    BtStreamArgs a, const float* __restrict__ cp_prev, const uint8_t* __restrict__ code_prev,
+    const float* __restrict__ u_cur, const uint8_t* __restrict__ code_cur, const uint8_t* __restrict__ vt, Geom g,
+    float* __restrict__ u_prev, unsigned long long* __restrict__ best, unsigned long long* __restrict__ cell,
+    int nblocks) {
+    const int bid = xcd_block(nblocks);
+    if (bid >= nblocks) return;
+    bt_stream_body(a, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, best, cell, bid);
+}
+
+__global__ void k_top_reduce(const float* __restrict__ top, Geom g, unsigned long long* __restrict__ best,
+                             unsigned long long* __restrict__ cell) {
+    top_reduce_body(top, g, best, cell, blockIdx.x);
+}
+
+__global__ __launch_bounds__(1024) void k_finalize(const unsigned long long* __restrict__ best,
+                                                   const unsigned long long* __restrict__ cell, Geom g,
+                                                   dm_match* __restrict__ out, int* __restrict__ n_out) {
+    finalize_body(best, cell, g, out, n_out);
+}
+
+__global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v) { fill_body(p, n, v, blockIdx.x); }
+
+__global__ __launch_bounds__(1024) void k_valid_init(Geom g, uint8_t* __restrict__ vt) { valid_body(g, vt); }
+
+struct BtJob {
+    BtArgs a;
+    const float* cp_prev;
+    const uint8_t* code_prev;
+    const float* u_cur;
+    const uint8_t* code_cur;
+    const float* top;
+    const uint8_t* vt;
+    Geom g;
+    float* u_prev;
+    unsigned long long *best, *cell;
+    static __device__ void run(const BtJob& j, int v) {
+        bt_body(j.a, j.cp_prev, j.code_prev, j.u_cur, j.code_cur, j.top, j.vt, j.g, j.u_prev, j.best, j.cell, v);
+    }
+};
+
+struct BtStreamJob {
+    BtStreamArgs a;
+    const float* cp_prev;
+    const uint8_t* code_prev;
+    const float* u_cur;
+    const uint8_t* code_cur;
+    const uint8_t* vt;
+    Geom g;
+    float* u_prev;
+    unsigned long long *best, *cell;
+    static __device__ void run(const BtStreamJob& j, int v) {
+        bt_stream_body(j.a, j.cp_prev, j.code_prev, j.u_cur, j.code_cur, j.vt, j.g, j.u_prev, j.best, j.cell, v);
+    }
+};
+
+struct TopReduceJob {
+    const float* top;
+    Geom g;
+    unsigned long long *best, *cell;
+    static __device__ void run(const TopReduceJob& j, int v) { top_reduce_body(j.top, j.g, j.best, j.cell, v); }
+};
+
+struct FinalizeJob {
+    const unsigned long long *best, *cell;
+    Geom g;
+    dm_match* out;
+    int* n_out;
+    static __device__ void run(const FinalizeJob& j, int) { finalize_body(j.best, j.cell, j.g, j.out, j.n_out); }
+};
+
+struct FillJob {
+    unsigned long long* p;
+    size_t n;
+    unsigned long long v;
+    static __device__ void run(const FillJob& j, int v) { fill_body(j.p, j.n, j.v, v); }
+};
+
+struct ValidJob {
+    Geom g;
+    uint8_t* vt;
+    static __device__ void run(const ValidJob& j, int) { valid_body(j.g, j.vt); }
+};
+
+// Tiled form of backtracking step l (reads level l, produces level l-1).
+BtArgs make_bt_args(int l, const Geom& g, int& nblocks, size_t& smem) {
     BtArgs a;
     a.l = l;
     a.gxp = g.gx[l];
@@ -557,43 +647,126 @@ hipError_t launch_backtrack<float>(int l, const float* cp_prev, const uint8_t* c
     a.ncy = a.TR / 2 + 2;
     a.ncx = a.TC / 2 + 2;
     a.cy0 = a.cx0 = 0;
-    const size_t smem = (size_t)4 * a.CB * a.TR * a.TC * sizeof(uint32_t) +
-                        ((size_t)a.CB + (size_t)a.ncy * a.ncx) * 8 + (size_t)5 * a.CB * sizeof(int);
-    const int nblocks = a.n_cblk * a.n_rt * n_ct;
+    smem = (size_t)4 * a.CB * a.TR * a.TC * sizeof(uint32_t) + ((size_t)a.CB + (size_t)a.ncy * a.ncx) * 8 +
+           (size_t)5 * a.CB * sizeof(int);
+    nblocks = a.n_cblk * a.n_rt * n_ct;
     a.f_t = make_fastdiv(a.TR * a.TC);
     a.f_tc = make_fastdiv(a.TC);
     a.f_nr = make_fastdiv((a.TR / 2 + 2) * (a.TC / 2 + 2));
     a.f_rwd = make_fastdiv(a.TC / 2 + 2);
-    const bool fits31 = (double)g.gx[l] * g.gy[l] * a.hu * a.wu * 4 < 2.0e9 &&
-                        (double)nc * a.h * a.w * 4 < 2.0e9;   // buffer offsets of the streaming form
-    if (!a.is_top && a.w >= 32 && fits31) {
-        BtStreamArgs b;
-        b.l = l;
-        b.gxp = a.gxp;
-        b.gyp = a.gyp;
-        b.gxc = a.gxc;
-        b.gyc = a.gyc;
-        b.h = a.h;
-        b.w = a.w;
-        b.hu = a.hu;
-        b.wu = a.wu;
-        b.is_bottom = a.is_bottom;
-        b.TR = a.h < kBtMaxTR ? ((a.h + 1) & ~1) : kBtMaxTR;
-        b.n_band = (a.h + b.TR - 1) / b.TR;
-        b.n_ct = (a.w + kBtCols - 1) / kBtCols;
-        b.n_cgrp = (nc + kBtWaves - 1) / kBtWaves;
-        b.W2 = a.W2;
-        b.cw = a.cw;
-        const int nb = b.n_cgrp * b.n_ct * b.n_band;
+    return a;
+}
+
+// The streaming form serves every step below the top whose child maps are at
+// least 32 columns wide and whose arrays stay below 2^31 bytes (buffer offsets).
+bool use_bt_stream(int l, const Geom& g) {
+    if (l == g.lmax || g.w[l] < 32) return false;
+    return (double)g.gx[l] * g.gy[l] * g.h[l + 1] * g.w[l + 1] * 4 < 2.0e9 &&
+           (double)g.gx[l - 1] * g.gy[l - 1] * g.h[l] * g.w[l] * 4 < 2.0e9;
+}
+
+// Streaming form with bands of tr rows (even, at most kBtMaxTR).
+BtStreamArgs make_bt_stream_args(int l, const Geom& g, int tr, int& nblocks) {
+    BtStreamArgs b;
+    b.l = l;
+    b.gxp = g.gx[l];
+    b.gyp = g.gy[l];
+    b.gxc = g.gx[l - 1];
+    b.gyc = g.gy[l - 1];
+    b.h = g.h[l];
+    b.w = g.w[l];
+    b.hu = g.h[l + 1];
+    b.wu = g.w[l + 1];
+    b.is_bottom = (l == 1);
+    tr = tr < 2 ? 2 : (tr > kBtMaxTR ? kBtMaxTR : tr & ~1);
+    b.TR = b.h < tr ? ((b.h + 1) & ~1) : tr;
+    b.n_band = (b.h + b.TR - 1) / b.TR;
+    b.n_ct = (b.w + kBtCols - 1) / kBtCols;
+    b.n_cgrp = (b.gxc * b.gyc + kBtWaves - 1) / kBtWaves;
+    b.W2 = g.W2;
+    b.cw = (g.W2 + 3) / 4;
+    nblocks = b.n_cgrp * b.n_ct * b.n_band;
+    return b;
+}
+
+}  // namespace
+
+template <>
+hipError_t launch_backtrack<float>(int l, const float* cp_prev, const uint8_t* code_prev, const float* u_cur,
+                                   const uint8_t* code_cur, const float* top, const uint8_t* vt, const Geom& g,
+                                   float* u_prev, uint64_t* best, uint64_t* cell, hipStream_t s) {
+    if (use_bt_stream(l, g)) {
+        int nb;
+        const BtStreamArgs b = make_bt_stream_args(l, g, kBtMaxTR, nb);
         hipLaunchKernelGGL(k_backtrack_stream, dim3(((nb + 7) / 8) * 8), dim3(64 * kBtWaves), 0, s, b, cp_prev,
                            code_prev, u_cur, code_cur, vt, g, u_prev, (unsigned long long*)best,
                            (unsigned long long*)cell, nb);
         return hipGetLastError();
     }
+    int nblocks;
+    size_t smem;
+    const BtArgs a = make_bt_args(l, g, nblocks, smem);
     const dim3 grid(((nblocks + 7) / 8) * 8);
     hipLaunchKernelGGL(k_backtrack, grid, dim3(256), smem, s, a, cp_prev, code_prev, u_cur, code_cur, top, vt, g,
                        u_prev, (unsigned long long*)best, (unsigned long long*)cell, nblocks);
     return hipGetLastError();
+}
+
+JobRec bt_job(int l, const float* cp_prev, const uint8_t* code_prev, const float* u_cur, const uint8_t* code_cur,
+              const float* top, const uint8_t* vt, const Geom& g, float* u_prev, uint64_t* best, uint64_t* cell,
+              int tr) {
+    JobRec r;
+    auto* b64 = (unsigned long long*)best;
+    auto* c64 = (unsigned long long*)cell;
+    if (use_bt_stream(l, g)) {
+        int nb;
+        const BtStreamArgs b = make_bt_stream_args(l, g, tr, nb);
+        r.set(JK_BT_STREAM, nb, 0, BtStreamJob{b, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, b64, c64});
+        return r;
+    }
+    int nb;
+    size_t smem;
+    const BtArgs a = make_bt_args(l, g, nb, smem);
+    r.set(JK_BT, nb, smem, BtJob{a, cp_prev, code_prev, u_cur, code_cur, top, vt, g, u_prev, b64, c64});
+    return r;
+}
+
+JobRec top_reduce_job(const float* top, const Geom& g, uint64_t* best, uint64_t* cell) {
+    const size_t n = (size_t)g.gx[0] * g.gy[0] * g.H2 * g.W2;
+    JobRec r;
+    r.set(JK_TOP_REDUCE, (int)((n + 255) / 256), 0,
+          TopReduceJob{top, g, (unsigned long long*)best, (unsigned long long*)cell});
+    return r;
+}
+
+JobRec finalize_job(const uint64_t* best, const uint64_t* cell, const Geom& g, dm_match* out, int* n_out) {
+    JobRec r;
+    r.set(JK_FINALIZE, 1, 0, FinalizeJob{(const unsigned long long*)best, (const unsigned long long*)cell, g, out, n_out});
+    return r;
+}
+
+JobRec fill_job(uint64_t* p, size_t n, uint64_t v) {
+    JobRec r;
+    r.set(JK_FILL, (int)((n + 255) / 256), 0, FillJob{(unsigned long long*)p, n, (unsigned long long)v});
+    return r;
+}
+
+JobRec valid_job(const Geom& g, uint8_t* vt) {
+    JobRec r;
+    r.set(JK_VALID, 1, 0, ValidJob{g, vt});
+    return r;
+}
+
+hipError_t launch_group_bt(int kind, const GroupLaunch& gl, hipStream_t s) {
+    switch (kind) {
+        case JK_BT: return launch_grouped<BtJob, 256, 1>(gl, s);
+        case JK_BT_STREAM: return launch_grouped<BtStreamJob, 64 * kBtWaves, 1>(gl, s);
+        case JK_TOP_REDUCE: return launch_grouped<TopReduceJob, 256, 1>(gl, s);
+        case JK_FINALIZE: return launch_grouped<FinalizeJob, 1024, 1>(gl, s);
+        case JK_FILL: return launch_grouped<FillJob, 256, 1>(gl, s);
+        case JK_VALID: return launch_grouped<ValidJob, 1024, 1>(gl, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <>

@@ -14,7 +14,7 @@
 //   g'_{l-1}(c, r)  = dC'_{l-1}(c, r) * lambda * C'_{l-1}(c, r)^((lambda-1)/lambda)
 // and at the bottom dA_0(p, x) = sum_{r: 2r + m_0(p, r) = x} g'_0(p, r).
 // Every sum runs in a fixed order: results are deterministic.
-#include "dm_internal.h"
+#include "dm_group.h"
 
 namespace dm {
 namespace {
@@ -46,10 +46,10 @@ __device__ inline int xcd_block(int nblocks) {
 // staged in LDS: at the top the gradient G_top on q = r - o_i, below the
 // pooled gradient g'_l and codes on the r' whose argmax can land there.
 template <typename T>
-__global__ __launch_bounds__(256) void k_bwd_level(BwdArgs a, const T* __restrict__ dtop, const T* __restrict__ top,
-                                                   const T* __restrict__ gp_cur, const uint8_t* __restrict__ code_cur,
-                                                   const T* __restrict__ cp_prev, const uint8_t* __restrict__ vt,
-                                                   Geom g, T lam, T* __restrict__ gp_prev, int nblocks) {
+__device__ inline void bwd_level_body(const BwdArgs& a, const T* __restrict__ dtop, const T* __restrict__ top,
+                                      const T* __restrict__ gp_cur, const uint8_t* __restrict__ code_cur,
+                                      const T* __restrict__ cp_prev, const uint8_t* __restrict__ vt, const Geom& g,
+                                      T lam, T* __restrict__ gp_prev, int bid) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int RH = a.TR / 2 + 2, RWd = a.TC / 2 + 2, NR = RH * RWd;
     const int T_ = a.TR * a.TC;
@@ -59,8 +59,6 @@ __global__ __launch_bounds__(256) void k_bwd_level(BwdArgs a, const T* __restric
     int* sPar = (int*)(((uintptr_t)(sM + 4 * a.CB * per_side) + 15) & ~(uintptr_t)15);  // [CB*4]
     T* sInv = (T*)(sPar + 4 * a.CB);                                       // [CB*4] 1/|V(P)|
     int* sCv = (int*)(sInv + 4 * a.CB);                                    // [CB]
-    const int bid = xcd_block(nblocks);
-    if (bid >= nblocks) return;
     const int cblk = bid % a.n_cblk, rest = bid / a.n_cblk;
     const int R0 = (rest % a.n_rt) * a.TR, C0 = (rest / a.n_rt) * a.TC;
     const int tid = threadIdx.x;
@@ -167,7 +165,127 @@ __global__ __launch_bounds__(256) void k_bwd_level(BwdArgs a, const T* __restric
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_level(BwdArgs a, const T* __restrict__ dtop, const T* __restrict__ top,
+                                                   const T* __restrict__ gp_cur, const uint8_t* __restrict__ code_cur,
+                                                   const T* __restrict__ cp_prev, const uint8_t* __restrict__ vt,
+                                                   Geom g, T lam, T* __restrict__ gp_prev, int nblocks) {
+    const int bid = xcd_block(nblocks);
+    if (bid >= nblocks) return;
+    bwd_level_body<T>(a, dtop, top, gp_cur, code_cur, cp_prev, vt, g, lam, gp_prev, bid);
+}
+
+struct BwdLevelJob {
+    BwdArgs a;
+    const float *dtop, *top, *gp_cur;
+    const uint8_t* code_cur;
+    const float* cp_prev;
+    const uint8_t* vt;
+    Geom g;
+    float lam;
+    float* gp_prev;
+    static __device__ void run(const BwdLevelJob& j, int v) {
+        bwd_level_body<float>(j.a, j.dtop, j.top, j.gp_cur, j.code_cur, j.cp_prev, j.vt, j.g, j.lam, j.gp_prev, v);
+    }
+};
+
+// Gradient of L = sum over top patches P of max_q C_top(P, q): 1 at the first
+// maximum of each top map (lowest index), 0 elsewhere.  One block per patch.
+__device__ inline void top_grad_body(const float* __restrict__ top, int hw, float* __restrict__ dtop, int P) {
+    __shared__ float sv[4];
+    __shared__ int si[4];
+    const float* m = top + (size_t)P * hw;
+    float bv = -INFINITY;
+    int bi = 0x7fffffff;
+    for (int q = threadIdx.x; q < hw; q += 256) {
+        const float v = m[q];
+        if (v > bv) { bv = v; bi = q; }   // q increases: the first maximum of this thread's share
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const float ov = __shfl_xor(bv, d);
+        const int oi = __shfl_xor(bi, d);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { sv[wave] = bv; si[wave] = bi; }
+    __syncthreads();
+    bv = sv[0];
+    bi = si[0];
+    for (int w = 1; w < 4; ++w)
+        if (sv[w] > bv || (sv[w] == bv && si[w] < bi)) { bv = sv[w]; bi = si[w]; }
+    for (int q = threadIdx.x; q < hw; q += 256) dtop[(size_t)P * hw + q] = q == bi ? 1.f : 0.f;
+}
+
+struct TopGradJob {
+    const float* top;
+    int hw;
+    float* dtop;
+    static __device__ void run(const TopGradJob& j, int v) { top_grad_body(j.top, j.hw, j.dtop, v); }
+};
+
+BwdArgs make_bwd_args(int l, const Geom& g, int& nblocks, size_t& smem) {
+    BwdArgs a;
+    a.l = l;
+    a.gxp = g.gx[l];
+    a.gyp = g.gy[l];
+    a.gxc = g.gx[l - 1];
+    a.gyc = g.gy[l - 1];
+    a.h = g.h[l];
+    a.w = g.w[l];
+    a.hu = g.h[l + 1];
+    a.wu = g.w[l + 1];
+    a.is_top = (l == g.lmax);
+    a.TC = a.w < 128 ? a.w : 128;
+    a.TR = 1024 / a.TC;
+    if (a.TR > a.h) a.TR = a.h;
+    if (a.TR < 1) a.TR = 1;
+    a.CB = 1024 / (a.TR * a.TC);
+    if (a.CB < 1) a.CB = 1;
+    if (a.CB > 64) a.CB = 64;
+    const int nc = a.gxc * a.gyc;
+    a.n_cblk = (nc + a.CB - 1) / a.CB;
+    a.n_rt = (a.h + a.TR - 1) / a.TR;
+    const int n_ct = (a.w + a.TC - 1) / a.TC;
+    const int RH = a.TR / 2 + 2, RWd = a.TC / 2 + 2;
+    a.f_t = make_fastdiv(a.TR * a.TC);
+    a.f_tc = make_fastdiv(a.TC);
+    a.f_nr = make_fastdiv(RH * RWd);
+    a.f_rwd = make_fastdiv(RWd);
+    const int per_side = a.is_top ? a.TR * a.TC : RH * RWd;
+    smem = (size_t)4 * a.CB * per_side * (sizeof(float) + 1);
+    smem = (smem + 15) & ~size_t(15);
+    smem += (size_t)4 * a.CB * (sizeof(int) + sizeof(double)) + (size_t)a.CB * sizeof(int) + 16;
+    nblocks = a.n_cblk * a.n_rt * n_ct;
+    return a;
+}
+
 }  // namespace
+
+JobRec bwd_level_job(int l, const float* dtop, const float* top, const float* gp_cur, const uint8_t* code_cur,
+                     const float* cp_prev, const uint8_t* vt, const Geom& g, float lam, float* gp_prev) {
+    int nb;
+    size_t smem;
+    const BwdArgs a = make_bwd_args(l, g, nb, smem);
+    JobRec r;
+    r.set(JK_BWD_LEVEL, nb, smem, BwdLevelJob{a, dtop, top, gp_cur, code_cur, cp_prev, vt, g, lam, gp_prev});
+    return r;
+}
+
+JobRec top_grad_job(const float* top, const Geom& g, float* dtop) {
+    JobRec r;
+    const int lt = g.lmax;
+    r.set(JK_TOP_GRAD, g.gx[lt] * g.gy[lt], 0, TopGradJob{top, g.h[lt] * g.w[lt], dtop});
+    return r;
+}
+
+hipError_t launch_group_bwd(int kind, const GroupLaunch& gl, hipStream_t s) {
+    switch (kind) {
+        case JK_BWD_LEVEL: return launch_grouped<BwdLevelJob, 256, 1>(gl, s);
+        case JK_TOP_GRAD: return launch_grouped<TopGradJob, 256, 1>(gl, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 template <typename T>
 hipError_t launch_bwd_level(int l, const T* dtop, const T* top, const T* gp_cur, const uint8_t* code_cur,

@@ -17,7 +17,7 @@
 // instantiation used by the finite-difference check.
 #include <type_traits>
 
-#include "dm_internal.h"
+#include "dm_group.h"
 
 namespace dm {
 namespace {
@@ -79,9 +79,9 @@ __device__ inline bf8 as_bf8(const uint16_t* p) {   // 8 consecutive bf16 (16-by
 // dA_0 is written once, densely ([patch][target pixel], operand type E), and
 // both contractions stream it with coalesced loads.
 template <typename E>
-__global__ __launch_bounds__(256) void k_bwd_da(const float* __restrict__ gp, const uint8_t* __restrict__ code,
-                                                BotArgs a, int xblocks, E* __restrict__ dA) {
-    const int p = blockIdx.x / xblocks, xb = blockIdx.x - p * xblocks;
+__device__ inline void bwd_da_body(const float* __restrict__ gp, const uint8_t* __restrict__ code, const BotArgs& a,
+                                   int xblocks, E* __restrict__ dA, int bid) {
+    const int p = bid / xblocks, xb = bid - p * xblocks;
     const int npos = a.H2 * a.W2;
     const size_t pm = (size_t)a.h1 * a.w1;
 #pragma unroll
@@ -97,8 +97,8 @@ __global__ __launch_bounds__(256) void k_bwd_da(const float* __restrict__ gp, co
 
 // Patch matrix P[p][k] = D1[p + d_k][c_k] (k = (dy, dx, c)), operand type E.
 template <typename E>
-__global__ void k_bwd_patchmat(const float* __restrict__ d1, BotArgs a, E* __restrict__ P) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void bwd_patchmat_body(const float* __restrict__ d1, const BotArgs& a, E* __restrict__ P, int bid) {
+    const size_t i = (size_t)bid * 256 + threadIdx.x;
     if (i >= (size_t)a.natom * 144) return;
     const int p = i / 144, k = i % 144;
     const float v = d1_at(d1, a, p, k);
@@ -115,15 +115,15 @@ __global__ void k_bwd_patchmat(const float* __restrict__ d1, BotArgs a, E* __res
 constexpr int G1P = 128, KC = 64;
 
 template <bool BF16>
-__global__ __launch_bounds__(256) void k_bwd_dd1_gemm(const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ dA,
-                                                      const float* __restrict__ d2, BotArgs a, int nsplit,
-                                                      float* __restrict__ part) {
+__device__ inline void bwd_dd1_gemm_body(const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ dA,
+                                         const float* __restrict__ d2, const BotArgs& a, int nsplit,
+                                         float* __restrict__ part, int bid) {
     typedef typename std::conditional<BF16, uint16_t, float>::type E;
     constexpr int PAD = BF16 ? 8 : 1;
     __shared__ __align__(16) E sA[G1P][KC + PAD];
     __shared__ __align__(16) E sB[144][KC + PAD];
     __shared__ float sD2[4][KC + 3][9];
-    const int ptile = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
+    const int ptile = bid / nsplit, split = bid % nsplit;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
     const int npos = a.H2 * a.W2;
     const int rows_per = (a.H2 + nsplit - 1) / nsplit;
@@ -199,9 +199,10 @@ __global__ __launch_bounds__(256) void k_bwd_dd1_gemm(const typename std::condit
 
 // dD1 (HWC) from the split partials: each pixel belongs to at most one patch.
 template <typename T>
-__global__ void k_bwd_dd1_reduce(const T* __restrict__ part, BotArgs a, int nsplit, T* __restrict__ dd1) {
+__device__ inline void bwd_dd1_reduce_body(const T* __restrict__ part, const BotArgs& a, int nsplit, T* __restrict__ dd1,
+                                           int bid) {
     const size_t n = (size_t)a.H1 * a.W1 * 9;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t i = (size_t)bid * 256 + threadIdx.x;
     if (i >= n) return;
     const int c = i % 9;
     const int x = (i / 9) % a.W1, y = i / (9 * (size_t)a.W1);
@@ -221,16 +222,16 @@ __global__ void k_bwd_dd1_reduce(const T* __restrict__ part, BotArgs a, int nspl
 // over all patches in chunks of 64: dA tile kept transposed [pixel][patch]
 // and patch tile [144][patch] in LDS.
 template <bool BF16>
-__global__ __launch_bounds__(256) void k_bwd_t_gemm(const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ dA,
-                                                    const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ P,
-                                                    BotArgs a, float* __restrict__ tbuf) {
+__device__ inline void bwd_t_gemm_body(const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ dA,
+                                       const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ P,
+                                       const BotArgs& a, float* __restrict__ tbuf, int bid) {
     typedef typename std::conditional<BF16, uint16_t, float>::type E;
     constexpr int PAD = BF16 ? 8 : 1;
     __shared__ __align__(16) E sAT[128][64 + PAD];   // [pixel][patch]
     __shared__ __align__(16) E sP[144][64 + PAD];    // [k][patch]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
     const int npos = a.H2 * a.W2;
-    const int xb = blockIdx.x * 128;
+    const int xb = bid * 128;
     f4 acc[2][9];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
@@ -289,9 +290,9 @@ __global__ __launch_bounds__(256) void k_bwd_t_gemm(const typename std::conditio
 
 // dD2[y][c] = 1/16 sum_d T[y - d][(d, c)]  (T is zero outside the target).
 template <typename T>
-__global__ void k_bwd_col2im(const T* __restrict__ tbuf, BotArgs a, T* __restrict__ dd2) {
+__device__ inline void bwd_col2im_body(const T* __restrict__ tbuf, const BotArgs& a, T* __restrict__ dd2, int bid) {
     const size_t n = (size_t)a.H2 * a.W2 * 9;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t i = (size_t)bid * 256 + threadIdx.x;
     if (i >= n) return;
     const int c = i % 9;
     const int x = (i / 9) % a.W2, y = i / (9 * (size_t)a.W2);
@@ -345,6 +346,84 @@ __global__ void k_bwd_t_ref(const T* __restrict__ gp, const uint8_t* __restrict_
     tbuf[i] = acc;
 }
 
+template <typename E>
+__global__ __launch_bounds__(256) void k_bwd_da(const float* __restrict__ gp, const uint8_t* __restrict__ code,
+                                                BotArgs a, int xblocks, E* __restrict__ dA) {
+    bwd_da_body<E>(gp, code, a, xblocks, dA, blockIdx.x);
+}
+template <typename E>
+__global__ __launch_bounds__(256) void k_bwd_patchmat(const float* __restrict__ d1, BotArgs a, E* __restrict__ P) {
+    bwd_patchmat_body<E>(d1, a, P, blockIdx.x);
+}
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_bwd_dd1_gemm(
+    const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ dA, const float* __restrict__ d2,
+    BotArgs a, int nsplit, float* __restrict__ part) {
+    bwd_dd1_gemm_body<BF16>(dA, d2, a, nsplit, part, blockIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_dd1_reduce(const T* __restrict__ part, BotArgs a, int nsplit,
+                                                        T* __restrict__ dd1) {
+    bwd_dd1_reduce_body<T>(part, a, nsplit, dd1, blockIdx.x);
+}
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_bwd_t_gemm(
+    const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ dA,
+    const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ P, BotArgs a,
+    float* __restrict__ tbuf) {
+    bwd_t_gemm_body<BF16>(dA, P, a, tbuf, blockIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_col2im(const T* __restrict__ tbuf, BotArgs a, T* __restrict__ dd2) {
+    bwd_col2im_body<T>(tbuf, a, dd2, blockIdx.x);
+}
+
+template <typename E>
+struct DaJob {
+    const float* gp;
+    const uint8_t* code;
+    BotArgs a;
+    int xblocks;
+    E* dA;
+    static __device__ void run(const DaJob& j, int v) { bwd_da_body<E>(j.gp, j.code, j.a, j.xblocks, j.dA, v); }
+};
+template <typename E>
+struct PatchJob {
+    const float* d1;
+    BotArgs a;
+    E* P;
+    static __device__ void run(const PatchJob& j, int v) { bwd_patchmat_body<E>(j.d1, j.a, j.P, v); }
+};
+template <bool BF16>
+struct Dd1Job {
+    const typename std::conditional<BF16, uint16_t, float>::type* dA;
+    const float* d2;
+    BotArgs a;
+    int nsplit;
+    float* part;
+    static __device__ void run(const Dd1Job& j, int v) { bwd_dd1_gemm_body<BF16>(j.dA, j.d2, j.a, j.nsplit, j.part, v); }
+};
+template <bool BF16>
+struct TgJob {
+    const typename std::conditional<BF16, uint16_t, float>::type *dA, *P;
+    BotArgs a;
+    float* tbuf;
+    static __device__ void run(const TgJob& j, int v) { bwd_t_gemm_body<BF16>(j.dA, j.P, j.a, j.tbuf, v); }
+};
+struct Dd1ReduceJob {
+    const float* part;
+    BotArgs a;
+    int nsplit;
+    float* dd1;
+    static __device__ void run(const Dd1ReduceJob& j, int v) { bwd_dd1_reduce_body<float>(j.part, j.a, j.nsplit, j.dd1, v); }
+};
+struct Col2imJob {
+    const float* tbuf;
+    BotArgs a;
+    float* dd2;
+    static __device__ void run(const Col2imJob& j, int v) { bwd_col2im_body<float>(j.tbuf, j.a, j.dd2, v); }
+};
+
 BotArgs make_bot(const Geom& g) {
     BotArgs a;
     a.W1 = g.W1;
@@ -373,6 +452,56 @@ int bwd_nsplit(const Geom& g) {
 size_t bwd_dense_bytes(const Geom& g, int precision) {
     const size_t es = precision == DM_BF16 ? 2 : 4;
     return (size_t)g.gx[0] * g.gy[0] * ((size_t)g.H2 * g.W2 + 144) * es;
+}
+
+// The six stages of the bottom backward of one pair as job records (FP32
+// storage; bf16 selects BF16 MFMA operands), in launch order.
+std::vector<JobRec> bot_jobs(bool bf16, const float* gp, const uint8_t* code, const float* d1, const float* d2,
+                             const Geom& g, float* part, float* tbuf, void* dense, float* dd1, float* dd2) {
+    const BotArgs a = make_bot(g);
+    const int ns = bwd_nsplit(g);
+    const int npos = a.H2 * a.W2;
+    const int xblocks = (npos + 1023) / 1024;
+    const int ptiles = (a.natom + G1P - 1) / G1P;
+    const int tblocks = (npos + 127) / 128;
+    const size_t pmat = (size_t)a.natom * 144;
+    const int pm_blocks = (int)((pmat + 255) / 256);
+    std::vector<JobRec> r(6);
+    if (bf16) {
+        uint16_t* dA = (uint16_t*)dense;
+        uint16_t* P = dA + (size_t)a.natom * npos;
+        r[0].set(JK_BWD_DA_BF16, a.natom * xblocks, 0, DaJob<uint16_t>{gp, code, a, xblocks, dA});
+        r[1].set(JK_PATCH_BF16, pm_blocks, 0, PatchJob<uint16_t>{d1, a, P});
+        r[2].set(JK_DD1_BF16, ptiles * ns, 0, Dd1Job<true>{dA, d2, a, ns, part});
+        r[3].set(JK_TG_BF16, tblocks, 0, TgJob<true>{dA, P, a, tbuf});
+    } else {
+        float* dA = (float*)dense;
+        float* P = dA + (size_t)a.natom * npos;
+        r[0].set(JK_BWD_DA_F32, a.natom * xblocks, 0, DaJob<float>{gp, code, a, xblocks, dA});
+        r[1].set(JK_PATCH_F32, pm_blocks, 0, PatchJob<float>{d1, a, P});
+        r[2].set(JK_DD1_F32, ptiles * ns, 0, Dd1Job<false>{dA, d2, a, ns, part});
+        r[3].set(JK_TG_F32, tblocks, 0, TgJob<false>{dA, P, a, tbuf});
+    }
+    const size_t n1 = (size_t)a.H1 * a.W1 * 9, n2 = (size_t)a.H2 * a.W2 * 9;
+    r[4].set(JK_DD1_REDUCE, (int)((n1 + 255) / 256), 0, Dd1ReduceJob{part, a, ns, dd1});
+    r[5].set(JK_COL2IM, (int)((n2 + 255) / 256), 0, Col2imJob{tbuf, a, dd2});
+    return r;
+}
+
+hipError_t launch_group_bot(int kind, const GroupLaunch& gl, hipStream_t s) {
+    switch (kind) {
+        case JK_BWD_DA_BF16: return launch_grouped<DaJob<uint16_t>, 256, 1>(gl, s);
+        case JK_BWD_DA_F32: return launch_grouped<DaJob<float>, 256, 1>(gl, s);
+        case JK_PATCH_BF16: return launch_grouped<PatchJob<uint16_t>, 256, 1>(gl, s);
+        case JK_PATCH_F32: return launch_grouped<PatchJob<float>, 256, 1>(gl, s);
+        case JK_DD1_BF16: return launch_grouped<Dd1Job<true>, 256, 1>(gl, s);
+        case JK_DD1_F32: return launch_grouped<Dd1Job<false>, 256, 1>(gl, s);
+        case JK_TG_BF16: return launch_grouped<TgJob<true>, 256, 1>(gl, s);
+        case JK_TG_F32: return launch_grouped<TgJob<false>, 256, 1>(gl, s);
+        case JK_DD1_REDUCE: return launch_grouped<Dd1ReduceJob, 256, 1>(gl, s);
+        case JK_COL2IM: return launch_grouped<Col2imJob, 256, 1>(gl, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T>

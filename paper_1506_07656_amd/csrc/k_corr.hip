@@ -23,7 +23,7 @@
 // the previous step (a per-row carry in LDS).  Every pooled row of a patch is
 // then written as one aligned 16-float run, and consecutive steps complete
 // the same cache lines.
-#include "dm_internal.h"
+#include "dm_group.h"
 
 namespace dm {
 namespace {
@@ -213,13 +213,11 @@ struct EngineBF16 {
     }
 };
 
-__global__ __launch_bounds__(256, 2) void k_corr_pool_f32(const float* __restrict__ d1,
-                                                          const float* __restrict__ d2, PoolArgs a,
-                                                          float lam, float* __restrict__ cp,
-                                                          uint8_t* __restrict__ code) {
+__device__ inline void corr_f32_body(const float* __restrict__ d1, const float* __restrict__ d2, const PoolArgs& a,
+                                     float lam, float* __restrict__ cp, uint8_t* __restrict__ code, int bid) {
     __shared__ float sD2[D2R * D2C * 9];
     __shared__ float sCarry[WAVES][ARS][16 * MT];
-    const int pt = blockIdx.x % a.n_ptiles, R0 = (blockIdx.x / a.n_ptiles) * TR;
+    const int pt = bid % a.n_ptiles, R0 = (bid / a.n_ptiles) * TR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n = lane & 15, grp = lane >> 4;
     // Patch fragments: lane (n, grp) holds row grp of the 4x4 patch of patch
@@ -245,13 +243,12 @@ __global__ __launch_bounds__(256, 2) void k_corr_pool_f32(const float* __restric
 // BF16 variant: descriptors stored as H x W x 10 bf16 (9 channels + a zero),
 // so each 16-lane group's K slice is 4 pixels x 10 = 40 values = 5 steps of
 // the 16x16x32 MFMA (K = 160, of which 16 are zero pads).
-__global__ __launch_bounds__(256, 2) void k_corr_pool_bf16(const uint16_t* __restrict__ d1,
-                                                           const uint16_t* __restrict__ d2, PoolArgs a,
-                                                           float lam, float* __restrict__ cp,
-                                                           uint8_t* __restrict__ code) {
+__device__ inline void corr_bf16_body(const uint16_t* __restrict__ d1, const uint16_t* __restrict__ d2,
+                                      const PoolArgs& a, float lam, float* __restrict__ cp,
+                                      uint8_t* __restrict__ code, int bid) {
     __shared__ uint32_t sD2[D2R * D2C * 5];
     __shared__ float sCarry[WAVES][ARS][16 * MT];
-    const int pt = blockIdx.x % a.n_ptiles, R0 = (blockIdx.x / a.n_ptiles) * TR;
+    const int pt = bid % a.n_ptiles, R0 = (bid / a.n_ptiles) * TR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n = lane & 15, grp = lane >> 4;
     bf8 fa[MT * 5];
@@ -276,6 +273,40 @@ __global__ __launch_bounds__(256, 2) void k_corr_pool_bf16(const uint16_t* __res
     EngineBF16 eng{fa, sD2, (const uint32_t*)d2};
     sweep_band(eng, a, pt, R0, lam, cp, code, sCarry[wave]);
 }
+
+__global__ __launch_bounds__(256, 2) void k_corr_pool_f32(const float* __restrict__ d1,
+                                                          const float* __restrict__ d2, PoolArgs a,
+                                                          float lam, float* __restrict__ cp,
+                                                          uint8_t* __restrict__ code) {
+    corr_f32_body(d1, d2, a, lam, cp, code, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256, 2) void k_corr_pool_bf16(const uint16_t* __restrict__ d1,
+                                                           const uint16_t* __restrict__ d2, PoolArgs a,
+                                                           float lam, float* __restrict__ cp,
+                                                           uint8_t* __restrict__ code) {
+    corr_bf16_body(d1, d2, a, lam, cp, code, blockIdx.x);
+}
+
+struct CorrF32Job {
+    const float *d1, *d2;
+    PoolArgs a;
+    float lam;
+    float* cp;
+    uint8_t* code;
+    static __device__ void run(const CorrF32Job& j, int v) { corr_f32_body(j.d1, j.d2, j.a, j.lam, j.cp, j.code, v); }
+};
+
+struct CorrBF16Job {
+    const uint16_t *d1, *d2;
+    PoolArgs a;
+    float lam;
+    float* cp;
+    uint8_t* code;
+    static __device__ void run(const CorrBF16Job& j, int v) {
+        corr_bf16_body(j.d1, j.d2, j.a, j.lam, j.cp, j.code, v);
+    }
+};
 
 PoolArgs make_pool_args(const Geom& g, int& nblocks) {
     PoolArgs a;
@@ -371,6 +402,21 @@ hipError_t launch_corr_pool_bf16(const uint16_t* d1, const uint16_t* d2, const G
     const PoolArgs a = make_pool_args(g, nb);
     hipLaunchKernelGGL(k_corr_pool_bf16, dim3(nb), dim3(256), 0, s, d1, d2, a, lam, cp, code);
     return hipGetLastError();
+}
+
+JobRec corr_job(bool bf16, const void* d1, const void* d2, const Geom& g, float lam, float* cp, uint8_t* code) {
+    int nb;
+    const PoolArgs a = make_pool_args(g, nb);
+    JobRec r;
+    if (bf16) r.set(JK_CORR_BF16, nb, 0, CorrBF16Job{(const uint16_t*)d1, (const uint16_t*)d2, a, lam, cp, code});
+    else r.set(JK_CORR_F32, nb, 0, CorrF32Job{(const float*)d1, (const float*)d2, a, lam, cp, code});
+    return r;
+}
+
+hipError_t launch_group_corr(int kind, const GroupLaunch& gl, hipStream_t s) {
+    if (kind == JK_CORR_BF16) return launch_grouped<CorrBF16Job, 256, 2>(gl, s);
+    if (kind == JK_CORR_F32) return launch_grouped<CorrF32Job, 256, 2>(gl, s);
+    return hipErrorInvalidValue;
 }
 
 template <typename T>

@@ -7,7 +7,7 @@
 // by each stage's radius.  Borders replicate: every LDS entry holds the value
 // of its stage at the CLAMPED image position, and reads clamp again, so a
 // stage never needs values outside the image.
-#include "dm_internal.h"
+#include "dm_group.h"
 
 namespace dm {
 namespace {
@@ -32,11 +32,10 @@ __device__ inline uint16_t to_bf16(float f) {
     return (uint16_t)(u >> 16);
 }
 
-__global__ __launch_bounds__(NT) void k_descriptor(const float* __restrict__ img, int W, int H, int ld,
-                                                   DescParams p, float* __restrict__ out,
-                                                   uint16_t* __restrict__ out_bf) {
+__device__ inline void descriptor_body(const float* __restrict__ img, int W, int H, int ld, const DescParams& p,
+                                       float* __restrict__ out, uint16_t* __restrict__ out_bf, int bx, int by) {
     extern __shared__ float smem[];
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int x0 = bx * TX, y0 = by * TY;
     const int r1 = p.r1, r2 = p.r2, r3 = p.r3;
     const int tid = threadIdx.x;
     // Regions, from the output tile outwards.
@@ -150,6 +149,24 @@ __global__ __launch_bounds__(NT) void k_descriptor(const float* __restrict__ img
     }
 }
 
+__global__ __launch_bounds__(NT) void k_descriptor(const float* __restrict__ img, int W, int H, int ld,
+                                                   DescParams p, float* __restrict__ out,
+                                                   uint16_t* __restrict__ out_bf) {
+    descriptor_body(img, W, H, ld, p, out, out_bf, blockIdx.x, blockIdx.y);
+}
+
+struct DescJob {
+    const float* img;
+    int W, H, ld, gx;
+    float* out;
+    uint16_t* out_bf;
+    DescParams p;
+    static __device__ void run(const DescJob& j, int v) {
+        const int by = v / j.gx;
+        descriptor_body(j.img, j.W, j.H, j.ld, j.p, j.out, j.out_bf, v - by * j.gx, by);
+    }
+};
+
 // FP32 HWC (9 channels) -> BF16 with a zero 10th channel.
 __global__ void k_to_bf16(const float* __restrict__ d, int n_pix, uint16_t* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -182,6 +199,18 @@ hipError_t launch_descriptor(const float* img, int W, int H, int ld, const DescP
     if (smem > 160 * 1024) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_descriptor, grid, dim3(NT), smem, s, img, W, H, ld, p, out, out_bf16);
     return hipGetLastError();
+}
+
+JobRec desc_job(const float* img, int W, int H, int ld, const DescParams& p, float* out, uint16_t* out_bf16) {
+    DescJob j{img, W, H, ld, (W + TX - 1) / TX, out, out_bf16, p};
+    JobRec r;
+    r.set(JK_DESC, j.gx * ((H + TY - 1) / TY), desc_smem_bytes(p), j);
+    return r;
+}
+
+hipError_t launch_group_desc(int kind, const GroupLaunch& gl, hipStream_t s) {
+    if (kind != JK_DESC) return hipErrorInvalidValue;
+    return launch_grouped<DescJob, NT, 1>(gl, s);
 }
 
 hipError_t launch_to_bf16(const float* d, int n_pix, uint16_t* out, hipStream_t s) {

@@ -11,7 +11,7 @@
 // by up to 4 parents, which neighbouring blocks read at the same time.
 #include <type_traits>
 
-#include "dm_internal.h"
+#include "dm_group.h"
 
 namespace dm {
 namespace {
@@ -109,14 +109,11 @@ __device__ inline T staged_aggregate(const LevelArgs& a, const ParentLDS<T>& pr,
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_level_pool(LevelArgs a, const T* __restrict__ prev,
-                                                    const uint8_t* __restrict__ vt, Geom g, T lam,
-                                                    T* __restrict__ cp, uint8_t* __restrict__ code, int nblocks) {
+__device__ inline void level_pool_body(const LevelArgs& a, const T* __restrict__ prev, const uint8_t* __restrict__ vt,
+                                       const Geom& g, T lam, T* __restrict__ cp, uint8_t* __restrict__ code, int bid) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     ParentLDS<T>* sp = (ParentLDS<T>*)smem_raw;
     T* sA = (T*)(smem_raw + ((a.PB * sizeof(ParentLDS<T>) + 15) & ~size_t(15)));
-    const int bid = xcd_block(nblocks);
-    if (bid >= nblocks) return;
     const int rest = bid / a.n_pblk, pblk = bid - rest * a.n_pblk;   // once per block (scalar)
     const int ct = rest / a.n_rt, R0 = (rest - ct * a.n_rt) * a.TRo, C0 = ct * a.TCo;
     const uint8_t *vxp = vtab(vt, g, a.l, 0), *vyp = vtab(vt, g, a.l, 1);
@@ -185,6 +182,7 @@ __global__ __launch_bounds__(256) void k_level_pool(LevelArgs a, const T* __rest
 // Scanning my outer and mx inner with strict comparisons keeps the first
 // maximum in code order, as the direct 3x3 scan does.
 constexpr int kStreamCols = 128;     // pooled columns per wave
+constexpr int kOOB = 0x7ffffff0;     // buffer byte offset past any row
 constexpr int kStreamWaves = 4;      // independent waves per block
 
 struct StreamArgs {
@@ -219,14 +217,17 @@ __device__ inline void load_row(const StreamArgs& a, const float* prev, const fl
         const int yy = y + 2 * (k >> 1) - 1, dx = 2 * (k & 1) - 1;
         const bool rok = cmap[k] != nullptr && yy >= 0 && yy < a.h;     // uniform over the wave
         const __amdgpu_buffer_rsrc_t rs = row_rsrc(rok ? cmap[k] + (size_t)yy * a.w : prev, rok ? a.w * 4 : 0);
-        const int s0 = X0 + 4 * t + dx;   // may be -2: the unsigned offset is then out of range
+        // Column offsets are never negative: a column left of the row gets
+        // kOOB (a byte offset past any row), so that each load is in or out of
+        // range on its own whatever the compiler folds into immediate offsets.
+        const int s0 = X0 + 4 * t + dx;   // >= -2
         if constexpr (VEC) {
-            if (k & 1) {   // s0 = 2 C0 + 4t: 16-byte aligned, entirely inside or outside the row
+            if (k & 1) {   // s0 = 2 C0 + 4t >= 0: 16-byte aligned, entirely inside or outside the row
                 const auto f = __builtin_amdgcn_raw_buffer_load_b128(rs, s0 * 4, 0, 0);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) b.v[k][j] = __uint_as_float(f[j]);
             } else {       // s0 = 2 C0 + 4t - 2: two 8-byte halves, each inside or outside
-                const auto f0 = __builtin_amdgcn_raw_buffer_load_b64(rs, s0 * 4, 0, 0);
+                const auto f0 = __builtin_amdgcn_raw_buffer_load_b64(rs, s0 >= 0 ? s0 * 4 : kOOB, 0, 0);
                 const auto f1 = __builtin_amdgcn_raw_buffer_load_b64(rs, s0 * 4 + 8, 0, 0);
                 b.v[k][0] = __uint_as_float(f0[0]);
                 b.v[k][1] = __uint_as_float(f0[1]);
@@ -236,7 +237,8 @@ __device__ inline void load_row(const StreamArgs& a, const float* prev, const fl
         } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                b.v[k][j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (s0 + j) * 4, 0, 0));
+                b.v[k][j] = __uint_as_float(
+                    __builtin_amdgcn_raw_buffer_load_b32(rs, s0 + j >= 0 ? (s0 + j) * 4 : kOOB, 0, 0));
         }
         b.hv[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (X0 + 4 * 64 + dx) * 4, 0, 0));
     }
@@ -274,12 +276,9 @@ __device__ inline void pool_row(const StreamArgs& a, const RowBuf& b, float inv,
 }
 
 template <bool VEC>
-__global__ __launch_bounds__(64 * kStreamWaves) void k_level_stream(StreamArgs a, const float* __restrict__ prev,
-                                                                     const uint8_t* __restrict__ vt, Geom g, float lam,
-                                                                     float* __restrict__ cp,
-                                                                     uint8_t* __restrict__ code, int nblocks) {
-    const int bid = xcd_block(nblocks);
-    if (bid >= nblocks) return;
+__device__ inline void level_stream_body(const StreamArgs& a, const float* __restrict__ prev,
+                                         const uint8_t* __restrict__ vt, const Geom& g, float lam,
+                                         float* __restrict__ cp, uint8_t* __restrict__ code, int bid) {
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), t = threadIdx.x & 63;   // wave index: uniform
     const int item = bid * kStreamWaves + wv;
     if (item >= a.n_items) return;
@@ -345,13 +344,10 @@ __global__ __launch_bounds__(64 * kStreamWaves) void k_level_stream(StreamArgs a
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_level_top(LevelArgs a, const T* __restrict__ prev,
-                                                   const uint8_t* __restrict__ vt, Geom g, T lam,
-                                                   T* __restrict__ top, int nblocks) {
+__device__ inline void level_top_body(const LevelArgs& a, const T* __restrict__ prev, const uint8_t* __restrict__ vt,
+                                      const Geom& g, T lam, T* __restrict__ top, int bid) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     ParentLDS<T>* sp = (ParentLDS<T>*)smem_raw;
-    const int bid = xcd_block(nblocks);
-    if (bid >= nblocks) return;
     const int rest = bid / a.n_pblk, pblk = bid - rest * a.n_pblk;   // once per block (scalar)
     const int ct = rest / a.n_rt, R0 = (rest - ct * a.n_rt) * a.TRo, C0 = ct * a.TCo;
     const uint8_t *vxp = vtab(vt, g, a.l, 0), *vyp = vtab(vt, g, a.l, 1);
@@ -370,11 +366,76 @@ __global__ __launch_bounds__(256) void k_level_top(LevelArgs a, const T* __restr
     }
 }
 
-}  // namespace
+template <typename T>
+__global__ __launch_bounds__(256) void k_level_pool(LevelArgs a, const T* __restrict__ prev,
+                                                    const uint8_t* __restrict__ vt, Geom g, T lam,
+                                                    T* __restrict__ cp, uint8_t* __restrict__ code, int nblocks) {
+    const int bid = xcd_block(nblocks);
+    if (bid >= nblocks) return;
+    level_pool_body<T>(a, prev, vt, g, lam, cp, code, bid);
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(64 * kStreamWaves) void k_level_stream(StreamArgs a, const float* __restrict__ prev,
+                                                                     const uint8_t* __restrict__ vt, Geom g, float lam,
+                                                                     float* __restrict__ cp,
+                                                                     uint8_t* __restrict__ code, int nblocks) {
+    const int bid = xcd_block(nblocks);
+    if (bid >= nblocks) return;
+    level_stream_body<VEC>(a, prev, vt, g, lam, cp, code, bid);
+}
 
 template <typename T>
-hipError_t launch_level(int l, const T* prev, const uint8_t* vt, const Geom& g, T lam, T* cp, uint8_t* code,
-                        T* top, hipStream_t s) {
+__global__ __launch_bounds__(256) void k_level_top(LevelArgs a, const T* __restrict__ prev,
+                                                   const uint8_t* __restrict__ vt, Geom g, T lam,
+                                                   T* __restrict__ top, int nblocks) {
+    const int bid = xcd_block(nblocks);
+    if (bid >= nblocks) return;
+    level_top_body<T>(a, prev, vt, g, lam, top, bid);
+}
+
+struct LevelPoolJob {
+    LevelArgs a;
+    const float* prev;
+    const uint8_t* vt;
+    Geom g;
+    float lam;
+    float* cp;
+    uint8_t* code;
+    static __device__ void run(const LevelPoolJob& j, int v) {
+        level_pool_body<float>(j.a, j.prev, j.vt, j.g, j.lam, j.cp, j.code, v);
+    }
+};
+
+struct LevelTopJob {
+    LevelArgs a;
+    const float* prev;
+    const uint8_t* vt;
+    Geom g;
+    float lam;
+    float* top;
+    static __device__ void run(const LevelTopJob& j, int v) {
+        level_top_body<float>(j.a, j.prev, j.vt, j.g, j.lam, j.top, v);
+    }
+};
+
+template <bool VEC>
+struct LevelStreamJob {
+    StreamArgs a;
+    const float* prev;
+    const uint8_t* vt;
+    Geom g;
+    float lam;
+    float* cp;
+    uint8_t* code;
+    static __device__ void run(const LevelStreamJob& j, int v) {
+        level_stream_body<VEC>(j.a, j.prev, j.vt, j.g, j.lam, j.cp, j.code, v);
+    }
+};
+
+// Tiled form of level l: the launch arguments, block count and LDS bytes.
+template <typename T>
+LevelArgs make_level_args(int l, const Geom& g, int& nblocks, size_t& smem) {
     LevelArgs a;
     a.l = l;
     a.gx = g.gx[l];
@@ -397,44 +458,96 @@ hipError_t launch_level(int l, const T* prev, const uint8_t* vt, const Geom& g, 
     a.n_pblk = (np + a.PB - 1) / a.PB;
     a.n_rt = (th + a.TRo - 1) / a.TRo;
     const int n_ct = (tw + a.TCo - 1) / a.TCo;
-    const int nblocks = a.n_pblk * a.n_rt * n_ct;
+    nblocks = a.n_pblk * a.n_rt * n_ct;
     a.f_ra = make_fastdiv((2 * a.TRo + 1) * (2 * a.TCo + 1));
     a.f_rw = make_fastdiv(2 * a.TCo + 1);
     a.f_tile = make_fastdiv(a.TRo * a.TCo);
     a.f_tco = make_fastdiv(a.TCo);
-    const dim3 grid(((nblocks + 7) / 8) * 8);
     const size_t sp_bytes = ((size_t)a.PB * sizeof(ParentLDS<T>) + 15) & ~size_t(15);
-    if (is_top) {
-        hipLaunchKernelGGL(k_level_top<T>, grid, dim3(256), sp_bytes, s, a, prev, vt, g, lam, top, nblocks);
-    } else if (std::is_same<T, float>::value && a.wp >= 32) {
-        StreamArgs b;
-        b.l = l;
-        b.gx = a.gx;
-        b.gy = a.gy;
-        b.gxc = a.gxc;
-        b.gyc = a.gyc;
-        b.h = a.h;
-        b.w = a.w;
-        b.hp = a.hp;
-        b.wp = a.wp;
-        b.TRo = a.hp < 16 ? a.hp : 16;
-        b.n_band = (a.hp + b.TRo - 1) / b.TRo;
-        b.n_ct = (a.wp + kStreamCols - 1) / kStreamCols;
-        b.n_items = np * b.n_ct * b.n_band;
-        b.vec = (a.w % 4) == 0;
-        const int nb = (b.n_items + kStreamWaves - 1) / kStreamWaves;
+    smem = is_top ? sp_bytes : sp_bytes + (size_t)a.PB * (2 * a.TRo + 1) * (2 * a.TCo + 1) * sizeof(T);
+    return a;
+}
+
+// Streaming form of level l with bands of tro pooled rows.
+StreamArgs make_stream_args(int l, const Geom& g, int tro, int& nblocks) {
+    StreamArgs b;
+    b.l = l;
+    b.gx = g.gx[l];
+    b.gy = g.gy[l];
+    b.gxc = g.gx[l - 1];
+    b.gyc = g.gy[l - 1];
+    b.h = g.h[l];
+    b.w = g.w[l];
+    b.hp = g.h[l + 1];
+    b.wp = g.w[l + 1];
+    b.TRo = b.hp < tro ? b.hp : tro;
+    b.n_band = (b.hp + b.TRo - 1) / b.TRo;
+    b.n_ct = (b.wp + kStreamCols - 1) / kStreamCols;
+    b.n_items = b.gx * b.gy * b.n_ct * b.n_band;
+    b.vec = (b.w % 4) == 0;
+    nblocks = (b.n_items + kStreamWaves - 1) / kStreamWaves;
+    return b;
+}
+
+// The streaming form serves FP32 levels below the top whose pooled maps are
+// at least 32 columns wide.
+inline bool use_stream(int l, const Geom& g) { return l < g.lmax && g.w[l + 1] >= 32; }
+
+}  // namespace
+
+JobRec level_job(int l, const float* prev, const uint8_t* vt, const Geom& g, float lam, float* cp, uint8_t* code,
+                 float* top, int tro) {
+    JobRec r;
+    if (use_stream(l, g)) {
+        int nb;
+        const StreamArgs b = make_stream_args(l, g, tro, nb);
+        if (b.vec) r.set(JK_LEVEL_STREAM_VEC, nb, 0, LevelStreamJob<true>{b, prev, vt, g, lam, cp, code});
+        else r.set(JK_LEVEL_STREAM, nb, 0, LevelStreamJob<false>{b, prev, vt, g, lam, cp, code});
+        return r;
+    }
+    int nb;
+    size_t smem;
+    const LevelArgs a = make_level_args<float>(l, g, nb, smem);
+    if (l == g.lmax) r.set(JK_LEVEL_TOP, nb, smem, LevelTopJob{a, prev, vt, g, lam, top});
+    else r.set(JK_LEVEL_POOL, nb, smem, LevelPoolJob{a, prev, vt, g, lam, cp, code});
+    return r;
+}
+
+hipError_t launch_group_level(int kind, const GroupLaunch& gl, hipStream_t s) {
+    switch (kind) {
+        case JK_LEVEL_STREAM_VEC: return launch_grouped<LevelStreamJob<true>, 64 * kStreamWaves, 1>(gl, s);
+        case JK_LEVEL_STREAM: return launch_grouped<LevelStreamJob<false>, 64 * kStreamWaves, 1>(gl, s);
+        case JK_LEVEL_POOL: return launch_grouped<LevelPoolJob, 256, 1>(gl, s);
+        case JK_LEVEL_TOP: return launch_grouped<LevelTopJob, 256, 1>(gl, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_level(int l, const T* prev, const uint8_t* vt, const Geom& g, T lam, T* cp, uint8_t* code,
+                        T* top, hipStream_t s) {
+    if (std::is_same<T, float>::value && use_stream(l, g)) {
+        int nb;
+        const StreamArgs b = make_stream_args(l, g, 16, nb);
         const float* pf = reinterpret_cast<const float*>(prev);
         float* cf = reinterpret_cast<float*>(cp);
+        const dim3 grid(((nb + 7) / 8) * 8);
         if (b.vec)
-            hipLaunchKernelGGL(k_level_stream<true>, dim3(((nb + 7) / 8) * 8), dim3(64 * kStreamWaves), 0, s, b, pf,
-                               vt, g, (float)lam, cf, code, nb);
+            hipLaunchKernelGGL(k_level_stream<true>, grid, dim3(64 * kStreamWaves), 0, s, b, pf, vt, g, (float)lam, cf,
+                               code, nb);
         else
-            hipLaunchKernelGGL(k_level_stream<false>, dim3(((nb + 7) / 8) * 8), dim3(64 * kStreamWaves), 0, s, b, pf,
-                               vt, g, (float)lam, cf, code, nb);
-    } else {
-        const size_t smem = sp_bytes + (size_t)a.PB * (2 * a.TRo + 1) * (2 * a.TCo + 1) * sizeof(T);
-        hipLaunchKernelGGL(k_level_pool<T>, grid, dim3(256), smem, s, a, prev, vt, g, lam, cp, code, nblocks);
+            hipLaunchKernelGGL(k_level_stream<false>, grid, dim3(64 * kStreamWaves), 0, s, b, pf, vt, g, (float)lam,
+                               cf, code, nb);
+        return hipGetLastError();
     }
+    int nblocks;
+    size_t smem;
+    const LevelArgs a = make_level_args<T>(l, g, nblocks, smem);
+    const dim3 grid(((nblocks + 7) / 8) * 8);
+    if (l == g.lmax)
+        hipLaunchKernelGGL(k_level_top<T>, grid, dim3(256), smem, s, a, prev, vt, g, lam, top, nblocks);
+    else
+        hipLaunchKernelGGL(k_level_pool<T>, grid, dim3(256), smem, s, a, prev, vt, g, lam, cp, code, nblocks);
     return hipGetLastError();
 }
 

@@ -135,3 +135,63 @@ def test_grad_plan_layout_and_errors():
                                ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), ctypes.c_void_p(0x20000),
                                gp.scratch_bytes, None)
     assert st == -1
+
+
+def _pairs(sizes, img=0x1000, dd=None):
+    P = (dm.Pair * len(sizes))()
+    for k, (a, b, c, d) in enumerate(sizes):
+        P[k] = dm.Pair(img, a, b, a, img, c, d, c, dd, dd)
+    return P
+
+
+def test_plan_batch_layout_and_errors():
+    L = dm.lib()
+    sizes = [(64, 64, 64, 64), (203, 117, 190, 121), (621, 188, 621, 188)]
+    prm = dm.params(precision="bf16")
+    info, info_b = B.BatchInfo(), B.BatchInfo()
+    assert L.dm_plan_batch(3, _pairs(sizes), ctypes.byref(prm), 0, ctypes.byref(info)) == 0
+    assert L.dm_plan_batch(3, _pairs(sizes), ctypes.byref(prm), B.DM_BATCH_BWD, ctypes.byref(info_b)) == 0
+    ws_sum = grad_sum = 0
+    for k, sz in enumerate(sizes):
+        pl = dm.plan(*sz, prm)
+        assert info.max_matches[k] == pl.max_matches and info.lmax[k] == pl.lmax
+        ws_sum += pl.workspace_bytes
+        grad_sum += dm.plan_grad(*sz, prm).scratch_bytes
+    assert info.n_pairs == 3 and info.workspace_bytes >= ws_sum
+    assert info_b.workspace_bytes >= ws_sum + grad_sum and info_b.n_launches > info.n_launches
+    bad = [(0, sizes, prm, -1), (257, sizes * 86, prm, -1), (3, sizes, dm.params(precision="fp64"), -5),
+           (1, [(4, 4, 4, 4)], prm, -5), (1, [(3, 64, 64, 64)], prm, -2)]
+    for n, sz, p, want in bad:
+        P = _pairs(sz[:max(n, 1)])
+        assert L.dm_plan_batch(n, P, ctypes.byref(p), 0, ctypes.byref(info)) == want, (n, want)
+    assert L.dm_plan_batch(1, None, ctypes.byref(prm), 0, ctypes.byref(info)) == -1
+
+
+def test_match_batch_validation_before_any_launch():
+    """Fake device addresses: every call below fails on the host."""
+    L = dm.lib()
+    sizes = [(64, 64, 64, 64), (128, 96, 120, 100)]
+    prm = dm.params(precision="bf16")
+    info = B.BatchInfo()
+    assert L.dm_plan_batch(2, _pairs(sizes), ctypes.byref(prm), 0, ctypes.byref(info)) == 0
+    need = info.workspace_bytes
+    offs_ok = (ctypes.c_int32 * 2)(0, info.max_matches[0])
+    offs_bad = (ctypes.c_int32 * 2)(0, info.max_matches[0] - 1)
+
+    def call(P=None, flags=0, ws=0x100000, nbytes=need, out=0x200000, offs=offs_ok, n_out=0x300000, stream=None):
+        return L.dm_match_batch(2, P if P is not None else _pairs(sizes), ctypes.byref(prm), flags,
+                                ctypes.c_void_p(ws), nbytes, ctypes.c_void_p(out), offs, ctypes.c_void_p(n_out),
+                                stream)
+
+    assert call(nbytes=need - 1) == -3
+    assert call(ws=0x100010) == -1
+    assert call(ws=0) == -1
+    assert call(offs=offs_bad) == -4
+    assert b"overlap" in L.dm_last_error()
+    assert call(n_out=0) == -1
+    assert call(flags=B.DM_BATCH_GRAPH) == -1              # graph capture needs a stream of its own
+    assert call(flags=B.DM_BATCH_BWD, nbytes=1 << 40) == -1   # no gradient buffers
+    assert call(P=_pairs(sizes, img=0)) == -1
+    t = B.BatchTiles()
+    assert L.dm_batch_tiles_get(ctypes.c_void_p(0x100000), ctypes.byref(t)) == -1
+    assert L.dm_batch_release(ctypes.c_void_p(0x100000)) == 0

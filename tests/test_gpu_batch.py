@@ -1,0 +1,120 @@
+"""Batches of uneven pairs (dm_match_batch): every pair's matches and
+gradients equal those of the single-pair entry points bit for bit (same
+kernels, same arithmetic, grouped into one launch per stage); HIP graph
+replays equal the eager run, replay after replay, with unrelated eager work
+and synchronisations in between; the autotuner changes launch shapes only."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1506_07656_amd as dm
+import synth
+
+pytestmark = pytest.mark.gpu
+
+# (W1, H1, W2, H2) crops of the uneven batch recipe: mixed sizes, I != I'
+# sizes, widths that are and are not multiples of 4, pyramids of 4 to 7 levels.
+SIZES = [(128, 96, 128, 96), (203, 117, 190, 121), (64, 64, 72, 60), (310, 150, 300, 156), (157, 99, 157, 99),
+         (96, 130, 101, 128)]
+
+
+def batch_images():
+    pairs = synth.make_batch(len(SIZES), base_seed=7100, max_disp=20.0)
+    i1, i2 = [], []
+    for (W1, H1, W2, H2), p in zip(SIZES, pairs):
+        a = np.zeros((H1, W1), np.float32)
+        b = np.zeros((H2, W2), np.float32)
+        h, w = min(H1, p["img1"].shape[0]), min(W1, p["img1"].shape[1])
+        a[:h, :w] = p["img1"][:h, :w]
+        h, w = min(H2, p["img2"].shape[0]), min(W2, p["img2"].shape[1])
+        b[:h, :w] = p["img2"][:h, :w]
+        i1.append(torch.from_numpy(a).cuda())
+        i2.append(torch.from_numpy(b).cuda())
+    return i1, i2
+
+
+def single(i1, i2, prec):
+    return [dm.match_images(a, b, dm.params(precision=prec)) for a, b in zip(i1, i2)]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_batch_equals_single_pairs(prec):
+    i1, i2 = batch_images()
+    B = dm.Batch(SIZES, dm.params(precision=prec), graph=False)
+    B.set_images(i1, i2)
+    B.run()
+    got = B.matches()
+    ref = single(i1, i2, prec)
+    for k, (g, r) in enumerate(zip(got, ref)):
+        print(f"pair {k} {SIZES[k]}: lmax {B.info.lmax[k]}, {len(g)} matches", flush=True)
+        assert len(g) > 0
+        assert torch.equal(g, r), k
+    B.release()
+
+
+def test_graph_replays_equal_eager():
+    i1, i2 = batch_images()
+    E = dm.Batch(SIZES, dm.params(precision="bf16"), graph=False)
+    E.set_images(i1, i2)
+    E.run()
+    want = E.matches()
+    G = dm.Batch(SIZES, dm.params(precision="bf16"), graph=True)
+    G.set_images(i1, i2)
+    other = dm.Matcher(96, 80, 96, 80, dm.params(precision="fp32"))
+    x = torch.rand(96 * 80, device="cuda").reshape(80, 96)
+    for rep in range(4):
+        G.n_out.zero_()
+        G.out.fill_(-1)
+        G.run()
+        got = G.matches()
+        for k in range(len(SIZES)):
+            assert torch.equal(got[k], want[k]), (rep, k)
+        # unrelated eager work and a synchronisation between replays
+        other.run_images(x, x.flip(1).contiguous())
+        _ = (x @ x.t()).sum().item()
+        torch.cuda.synchronize()
+    E.release()
+    G.release()
+
+
+def test_batch_backward_equals_single_pyramid():
+    i1, i2 = batch_images()
+    prm = dm.params(precision="bf16")
+    B = dm.Batch(SIZES, prm, bwd=True, graph=True)
+    B.set_images(i1, i2)
+    B.run()
+    torch.cuda.synchronize()
+    for k, (a, b) in enumerate(zip(i1, i2)):
+        d1, d2 = dm.descriptors(a, prm), dm.descriptors(b, prm)
+        pyr = dm.Pyramid(d1, d2, prm, False)
+        top = pyr.forward()
+        flat = top.reshape(top.shape[0] * top.shape[1], -1)
+        dtop = torch.zeros_like(flat)
+        dtop.scatter_(1, flat.argmax(1, keepdim=True), 1.0)     # first maximum of each top map
+        g1, g2 = pyr.backward(dtop.view_as(top))
+        torch.cuda.synchronize()
+        e1 = (B.dd1[k] - g1).abs().max().item()
+        e2 = (B.dd2[k] - g2).abs().max().item()
+        print(f"pair {k}: |dd1| max {g1.abs().max().item():.3e} diff {e1:.1e}; |dd2| max {g2.abs().max().item():.3e} "
+              f"diff {e2:.1e}", flush=True)
+        assert g1.abs().max().item() > 0 and g2.abs().max().item() > 0
+        assert torch.equal(B.dd1[k], g1) and torch.equal(B.dd2[k], g2), k
+    # the forward of the same batch call is unchanged by the backward
+    ref = single(i1, i2, "bf16")
+    for k, g in enumerate(B.matches()):
+        assert torch.equal(g, ref[k]), k
+    B.release()
+
+
+def test_autotuner_keeps_results():
+    i1, i2 = batch_images()
+    T = dm.Batch(SIZES, dm.params(precision="bf16"), graph=True, autotune=True)
+    T.set_images(i1, i2)
+    T.run()
+    t = T.tiles()
+    print(f"tuned: level rows {t.level_rows}, backtrack rows {t.bt_rows}, forward {t.tuned_ms:.3f} ms", flush=True)
+    assert t.tuned == 1 and t.level_rows in (8, 16, 32) and t.bt_rows in (8, 16, 32) and t.tuned_ms > 0
+    ref = single(i1, i2, "bf16")
+    for k, g in enumerate(T.matches()):
+        assert torch.equal(g, ref[k]), k
+    T.release()

@@ -1,4 +1,6 @@
 """GPU parity of the HIP path (through the C ABI) against the FP64 oracle."""
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -64,11 +66,28 @@ def test_descriptors_match_oracle(name):
         np.testing.assert_allclose(d, ref, rtol=0, atol=3e-6)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
+@functools.lru_cache(maxsize=None)
+def odd_case():
+    """Uneven crops of the 512x256 pair, I 310x150 and I' 300x156: the level
+    maps are 150, 75, 38, ... wide, so the streaming kernels run on widths
+    that are not multiples of 4 (scalar loads) and on odd widths."""
+    p = synth.make_pair("c3")
+    i1 = np.ascontiguousarray(p["img1"][40:190, 60:370])
+    i2 = np.ascontiguousarray(p["img2"][37:193, 66:366])
+    o = oracle_from_desc(O.descriptors(i1), O.descriptors(i2))
+    o["img1"], o["img2"] = i1, i2
+    return o
+
+
+def case(name):
+    return (odd_case(), 0) if name == "odd" else (oracle_pair(name), synth.CONFIG_NMAX[name])
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "odd"])
 def test_pyramid_levels_match_oracle(name):
-    o = oracle_pair(name)
+    o, mp = case(name)
     pyr = o["pyr"]
-    gpu, views, pl = run_desc(o["D1"], o["D2"], max_patch=synth.CONFIG_NMAX[name])
+    gpu, views, pl = run_desc(o["D1"], o["D2"], max_patch=mp)
     assert pl.lmax == pyr.lmax
     for lv in range(pyr.lmax):
         G = pyr.G[lv]
@@ -98,10 +117,10 @@ def test_pyramid_levels_match_oracle(name):
     np.testing.assert_allclose(views["top"].cpu().numpy()[G], pyr.top[G], rtol=1e-5, atol=1e-7)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
+@pytest.mark.parametrize("name", ["c1", "c2", "odd"])
 def test_matches_fp32_match_oracle(name):
-    o = oracle_pair(name)
-    gpu, _, _ = run_desc(o["D1"], o["D2"], max_patch=synth.CONFIG_NMAX[name])
+    o, mp = case(name)
+    gpu, _, _ = run_desc(o["D1"], o["D2"], max_patch=mp)
     r = compare_matches(gpu, o["out"], o["margin"])
     report(name, r)
     assert not r["missing"] and not r["moved"] and not r["bad_score"]
