@@ -10,6 +10,12 @@ correlation path (FP32 pyramid); the plain FP32 path is timed beside it.
 Prints one JSON line.  Stage times come from HIP events the library records
 on the launch stream around each kernel (dm_timing_*), in a second pass of
 the same steps right after the timed one.
+
+The "batch" entry is the uneven-batch workload: 32 pairs with W ~ U{128..621},
+H ~ U{96..188} (half of a 1242x375 driving-frame shape), BF16 correlation,
+FP32 pyramid, forward plus backward of the top loss, every stage one
+persistent grouped launch over all pairs, the whole sequence one HIP graph
+replay with autotuned tiles; beside it the same pairs one by one.
 """
 from __future__ import annotations
 
@@ -131,9 +137,9 @@ def within_1px(a, b):
     return ok / max(1, len(b))
 
 
-def cpu_baseline(pair):
-    """The FP64 oracle on the central 256x128 crop of the pair, scaled to a
-    full pair by the method's O(L L') cost (factor (512*256)^2/(256*128)^2)."""
+def cpu_baseline(pair, cw=384, ch=192):
+    """The FP64 oracle on the central cw x ch crop of the pair, scaled to a
+    full pair by the method's O(L L') cost (factor (W H)^2 / (cw ch)^2)."""
     import numpy as np
     from oracle import dm_oracle as O
     try:
@@ -142,16 +148,116 @@ def cpu_baseline(pair):
     except Exception:
         cores = os.cpu_count()
     H, W = pair["img1"].shape
-    y0, x0 = (H - 128) // 2, (W - 256) // 2
-    c1 = np.ascontiguousarray(pair["img1"][y0:y0 + 128, x0:x0 + 256])
-    c2 = np.ascontiguousarray(pair["img2"][y0:y0 + 128, x0:x0 + 256])
+    y0, x0 = (H - ch) // 2, (W - cw) // 2
+    c1 = np.ascontiguousarray(pair["img1"][y0:y0 + ch, x0:x0 + cw])
+    c2 = np.ascontiguousarray(pair["img2"][y0:y0 + ch, x0:x0 + cw])
     t0 = time.perf_counter()
     O.match(c1, c2, O.Params())
     t = time.perf_counter() - t0
-    scale = (W * H) ** 2 / (256 * 128) ** 2
+    scale = (W * H) ** 2 / (cw * ch) ** 2
     return dict(value=1.0 / (t * scale), unit="pairs/s", cores=int(cores), kind="oracle",
-                sample=f"oracle (FP64 NumPy) descriptors-to-matches on the central 256x128 crop of the 512x256 "
+                sample=f"oracle (FP64 NumPy) descriptors-to-matches on the central {cw}x{ch} crop of the {W}x{H} "
                        f"pair: {t:.1f} s, scaled by the O(LL') cost ratio {scale:.0f} to a full pair")
+
+
+def pair_work(pl):
+    """Algorithmic (HBM bytes, MFMA FLOPs) of one pair's forward and of its
+    backward, from its plan: every stage's compulsory reads and writes."""
+    gx, gy, h, w, L = list(pl.gx), list(pl.gy), list(pl.h), list(pl.w), pl.lmax
+    npat = lambda l: gx[l] * gy[l]
+    by = (pl.W1 * pl.H1 + pl.W2 * pl.H2) * (4 + 36 + 20)                 # descriptors: image in, FP32 + BF16 out
+    by += pl.n_atomic * h[1] * w[1] * 5.0                                   # C'_0 + codes out of the correlation
+    for l in range(1, L + 1):
+        by += stage_work(pl, "level", l, "bf16")[1] + stage_work(pl, "backtrack", l, "bf16")[1]
+    fl = 2.0 * pl.n_atomic * pl.H2 * pl.W2 * 144
+    npos = pl.H2 * pl.W2
+    bb = npat(L) * h[L] * w[L] * 8.0                                          # top + its gradient
+    for l in range(1, L + 1):
+        bb += npat(l - 1) * h[l] * w[l] * (4 + 4 + 1) + (npat(l) * h[l + 1] * w[l + 1] * 5.0 if l < L else 0)
+    bb += pl.n_atomic * npos * 2 * 3.0 + (pl.W1 * pl.H1 + pl.W2 * pl.H2) * 9 * 4 * 2   # dense dA: write + 2 reads
+    return by, fl, bb, 2 * fl
+
+
+def batch_bench(dm, torch, steps):
+    import synth
+    prm = dm.params(precision="bf16")
+    pairs = synth.make_batch(32)
+    sizes = [(p["img1"].shape[1], p["img1"].shape[0], p["img2"].shape[1], p["img2"].shape[0]) for p in pairs]
+    i1 = [torch.from_numpy(p["img1"]).cuda() for p in pairs]
+    i2 = [torch.from_numpy(p["img2"]).cuda() for p in pairs]
+    plans = [dm.plan(*sz, prm) for sz in sizes]
+    work = [pair_work(pl) for pl in plans]
+    fwd_bytes = sum(x[0] for x in work)
+    fwd_flops = sum(x[1] for x in work)
+    all_bytes = fwd_bytes + sum(x[2] for x in work)
+    all_flops = fwd_flops + sum(x[3] for x in work)
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    res = {}
+    B = dm.Batch(sizes, prm, bwd=True, graph=True, autotune=True)
+    B.set_images(i1, i2)
+    B.run()
+    torch.cuda.synchronize()
+    tiles = B.tiles()
+    t = timed(B.run, steps)
+    res["batch_fwd_bwd"] = dict(pairs_s=round(32 / t, 2), ms=round(t * 1e3, 3),
+                                hbm_gbs=round(all_bytes / t / 1e9, 1),
+                                mfma_util=round(all_flops / t / 1e12 / PEAKS_TFLOPS["bf16"], 4))
+    n_launch = B.info.n_launches
+    B.release()
+    del B
+    # the same pairs one by one: one-pair schedules of the same kernels, replayed in turn
+    singles = []
+    for k in range(32):
+        S = dm.Batch([sizes[k]], prm, bwd=True, graph=True)
+        S.set_images([i1[k]], [i2[k]])
+        singles.append(S)
+    t1 = timed(lambda: [S.run() for S in singles], max(1, steps // 2))
+    res["one_by_one_fwd_bwd"] = dict(pairs_s=round(32 / t1, 2), ms=round(t1 * 1e3, 3),
+                                     hbm_gbs=round(all_bytes / t1 / 1e9, 1),
+                                     mfma_util=round(all_flops / t1 / 1e12 / PEAKS_TFLOPS["bf16"], 4))
+    for S in singles:
+        S.release()
+    del singles
+    F = dm.Batch(sizes, prm, bwd=False, graph=True, autotune=True)
+    F.set_images(i1, i2)
+    F.run()
+    t2 = timed(F.run, steps)
+    res["batch_fwd"] = dict(pairs_s=round(32 / t2, 2), ms=round(t2 * 1e3, 3), hbm_gbs=round(fwd_bytes / t2 / 1e9, 1),
+                            mfma_util=round(fwd_flops / t2 / 1e12 / PEAKS_TFLOPS["bf16"], 4))
+    F.release()
+    del F
+    ms = [dm.Matcher(*sz, prm) for sz in sizes]
+    t3 = timed(lambda: [m.run_images(a, b) for m, a, b in zip(ms, i1, i2)], max(1, steps // 2))
+    res["one_by_one_fwd"] = dict(pairs_s=round(32 / t3, 2), ms=round(t3 * 1e3, 3),
+                                 hbm_gbs=round(fwd_bytes / t3 / 1e9, 1),
+                                 mfma_util=round(fwd_flops / t3 / 1e12 / PEAKS_TFLOPS["bf16"], 4))
+    del ms
+    res["workload"] = ("32 uneven pairs, W ~ U{128..621}, H ~ U{96..188}, warped blurred noise (max 30 px); "
+                       "BF16 correlation, FP32 pyramid; fwd_bwd = matches + gradient of the top loss")
+    res["grouped_launches"] = n_launch
+    res["tiles"] = dict(level_rows=tiles.level_rows, bt_rows=tiles.bt_rows, tuned_fwd_ms=round(tiles.tuned_ms, 3))
+    res["algorithmic_gb_fwd_bwd"] = round(all_bytes / 1e9, 2)
+    res["gflop_fwd_bwd"] = round(all_flops / 1e9, 1)
+    return res
+
+
+def oracle_agreement(matches):
+    """Fraction of the stored oracle matches of the pair reproduced within 1 px."""
+    import numpy as np
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "c3_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)["matches"]
+    return round(within_1px(matches, ref), 5)
 
 
 def copy_probe(torch):
@@ -171,6 +277,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the run, copy 1 GiB device to device (calibrates HBM byte counters)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 32-pair uneven batch")
     ap.add_argument("--only", choices=("all", "fwd_bf16"), default="all",
                     help="fwd_bf16: run only the BF16 forward (short profiler runs); prints no JSON line")
     args = ap.parse_args()
@@ -210,7 +317,7 @@ def main():
     dom = rows[0]
     rows32 = roofline_of(res["fp32"]["stages"], res["fp32"]["plan"], "fp32")
     out = {
-        "metric": "pairs/s @512x256 fwd (images to matches), BF16 correlation + FP32 pyramid",
+        "metric": "pairs/s @512x256 fwd & fwd+bwd; BF16 vs FP32 plain at >=99% match agreement",
         "value": round(head["pairs_s"], 3),
         "unit": "pairs/s",
         "n_gpus": 1,
@@ -227,9 +334,11 @@ def main():
                                "reciprocal matches", "W": 512, "H": 256, "N_max": head["plan"].N_max,
                    "global_batch": 1, "parallelism": "single GPU"},
         "fp32": {"pairs_s": round(res["fp32"]["pairs_s"], 3), "ms_per_step": round(res["fp32"]["ms"], 4),
-                 "matches": int(len(res["fp32"]["matches"]))},
+                 "matches": int(len(res["fp32"]["matches"])),
+                 "oracle_matches_within_1px": oracle_agreement(res["fp32"]["matches"])},
         "bf16": {"pairs_s": round(head["pairs_s"], 3), "ms_per_step": round(head["ms"], 4),
-                 "matches": int(len(head["matches"])), "within_1px_of_fp32": round(agree, 5)},
+                 "matches": int(len(head["matches"])), "within_1px_of_fp32": round(agree, 5),
+                 "oracle_matches_within_1px": oracle_agreement(head["matches"])},
         "fwd_bwd": {k: {kk: vv for kk, vv in v.items() if kk != "stages"} for k, v in fb.items()},
         "fwd_bwd_top_kernels_bf16": sorted([(n + ("" if l < 0 else "_l%d" % l), round(t / c, 4))
                                             for n, l, c, t in fb["bf16"]["stages"]], key=lambda x: -x[1])[:6],
@@ -243,6 +352,8 @@ def main():
         "kernels_fp32": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items() if k != "work"}
                          for r in rows32[:4]],
     }
+    if not args.no_batch:
+        out["batch"] = batch_bench(dm, torch, max(3, args.steps // 2))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pair)
     if args.copy_probe:
