@@ -26,6 +26,19 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE on the
+# kernels as they are now, scaled by the 1 GiB copy calibration (read = 2 x
+# FETCH_SIZE, written = 1 x WRITE_SIZE); source:
+# profiles/bf16_forward_512x256_hbm_bytes.md.  Only valid for the 512x256
+# pair; a kernel changed since then must be dropped from this table.
+MEASURED_TRAFFIC_512x256 = {
+    "corr_pool_bf16_l0": 36.6e6 + 1610.8e6,
+    "level_l1": 2320.5e6 + 337.9e6,
+    "level_l2": 540.9e6 + 85.6e6,
+    "backtrack_l1": 1646.1e6 + 46.2e6,
+    "backtrack_l2": 423.6e6 + 268.4e6,
+}
 PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
 
 
@@ -345,10 +358,12 @@ def main():
         "fwd_bwd_top_kernels_fp32": sorted([(n + ("" if l < 0 else "_l%d" % l), round(t / c, 4))
                                             for n, l, c, t in fb["fp32"]["stages"]], key=lambda x: -x[1])[:6],
         "roofline": {"bound": dom["bound"], "kernel": dom["kernel"], "achieved": round(dom["achieved"], 2),
-                     "peak": dom["peak"], "unit": dom["unit"], "frac": round(dom["frac"], 4), "traffic": None,
+                     "peak": dom["peak"], "unit": dom["unit"], "frac": round(dom["frac"], 4),
+                     "traffic": MEASURED_TRAFFIC_512x256.get(dom["kernel"]),
+                     "algorithmic_bytes": round(dom["work"]) if dom["unit"] == "GB/s" else None,
                      "avg_ms": round(dom["avg_ms"], 5)},
-        "kernels_bf16": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items() if k != "work"}
-                         for r in rows],
+        "kernels_bf16": [dict({k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items() if k != "work"},
+                              traffic=MEASURED_TRAFFIC_512x256.get(r["kernel"])) for r in rows],
         "kernels_fp32": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items() if k != "work"}
                          for r in rows32[:4]],
     }
