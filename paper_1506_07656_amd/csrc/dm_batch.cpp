@@ -274,15 +274,16 @@ void build(int n, const dm_pair* pairs, const dm_params* prm, int flags, const s
         }
         B.stage("bwd_level", l, J, false);
     }
-    std::vector<std::vector<JobRec>> bot(6);
+    std::vector<std::vector<JobRec>> bot(7);
     for (int k = 0; k < n; ++k) {
         std::vector<JobRec> r = bot_jobs(bf, gbuf(k, 0), code(k, 0), d1(k), d2(k), G[k], at<float>(S(k), P[k].gp.off_part),
                                          at<float>(S(k), P[k].gp.off_t), at<void>(S(k), P[k].gp.off_dense),
                                          pairs[k].dd1, pairs[k].dd2);
-        for (int i = 0; i < 6; ++i) bot[i].push_back(r[i]);
+        for (int i = 0; i < 7; ++i) bot[i].push_back(r[i]);
     }
-    static const char* names[6] = {"bwd_da", "bwd_patchmat", "bwd_dd1_gemm", "bwd_t_gemm", "bwd_dd1_reduce", "bwd_col2im"};
-    for (int i = 0; i < 6; ++i) B.stage(names[i], 0, bot[i], false);
+    static const char* names[7] = {"bwd_da",       "bwd_d2col",      "bwd_pt",    "bwd_dd1_gemm",
+                                   "bwd_t_gemm", "bwd_dd1_reduce", "bwd_col2im"};
+    for (int i = 0; i < 7; ++i) B.stage(names[i], 0, bot[i], false);
 }
 
 struct Schedule {

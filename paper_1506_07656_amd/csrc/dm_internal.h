@@ -105,6 +105,8 @@ enum JobKind : int {
     JK_BWD_DA_F32,
     JK_PATCH_BF16,
     JK_PATCH_F32,
+    JK_D2COL_BF16,
+    JK_D2COL_F32,
     JK_DD1_BF16,
     JK_DD1_F32,
     JK_TG_BF16,
@@ -188,6 +190,7 @@ hipError_t launch_bwd_bottom(int mode, const T* gp, const uint8_t* code, const T
                              T* part, T* tbuf, void* dense, T* dd1, T* dd2, hipStream_t s);
 int bwd_nsplit(const Geom& g);
 size_t bwd_dense_bytes(const Geom& g, int precision);
+size_t bwd_t_bytes(const Geom& g, int precision);
 template <typename T>
 hipError_t launch_backtrack(int l, const T* cp_prev, const uint8_t* code_prev, const T* u_cur,
                             const uint8_t* code_cur, const T* top, const uint8_t* vt, const Geom& g,

@@ -195,7 +195,7 @@ dm_status plan_grad(const dm_params* prm, int W1, int H1, int W2, int H2, int re
     out->off_g[0] = take(xo, ng * es);
     out->off_g[1] = take(xo, ng * es);
     out->off_part = take(xo, (uint64_t)out->nsplit * pi.n_atomic * 144 * es);
-    out->off_t = take(xo, (uint64_t)W2 * H2 * 144 * es);
+    out->off_t = take(xo, bwd_t_bytes(g, prm->precision));
     if (!fp64) out->off_dense = take(xo, bwd_dense_bytes(g, prm->precision));
     out->saved_bytes = so;
     out->scratch_bytes = xo;

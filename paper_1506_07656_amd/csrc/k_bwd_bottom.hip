@@ -5,13 +5,24 @@
 //   dA_0(p, x) = sum_{r: 2r + m_0(p, r) = x} g'_0(p, r)        (<= 4 candidates)
 // and, with K index k = (dy, dx, c) over the 4x4 patch and 9 channels,
 //   dD1[p + d_k][c_k] = 1/16 sum_x dA_0(p, x) D2[x + d_k][c_k]          (GEMM 1)
-//   T[x][k]           =      sum_p dA_0(p, x) D1[p + d_k][c_k]          (GEMM 2)
-//   dD2[y][c]         = 1/16 sum_{dy,dx} T[y - d][(d, c)]               (col2im)
-// Atomic patches do not overlap, so GEMM 1 writes each D1 pixel once.  dA_0
-// is rebuilt once from g'_0 and the argmax codes into a dense scratch array
-// (BF16 or FP32, the GEMM operand type), which both GEMMs stream through LDS
-// tiles on the matrix cores; partial sums over row splits are added in a
-// fixed order, so the result is deterministic.
+//   T[k][x]           =      sum_p D1[p + d_k][c_k] dA_0(p, x)          (GEMM 2)
+//   dD2[y][c]         = 1/16 sum_{dy,dx} T[(d, c)][y - d]               (col2im)
+// Atomic patches do not overlap, so GEMM 1 writes each D1 pixel once.
+//
+// Matrix-core path (FP32 or BF16 operands, FP32 accumulation):
+//  - dA_0 is written once, densely, by a gather over the <= 4 candidates in
+//    a fixed order (deterministic), as a [Pp][Xp] array: target positions on
+//    an H2p x Wp grid (width rounded up to 8, so rows of 8 values are
+//    16-byte aligned, height up to 16, so Xp is a multiple of 128), patches padded to Pp
+//    (a multiple of 128); padding entries are 0, so GEMM tiles never check
+//    bounds.
+//  - GEMM 1 (M = patches, N = 144, K = positions, split over K) and GEMM 2
+//    (M = 144, N = positions, K = patches) read operands that are contiguous
+//    along K: dA_0 rows, the transposed im2col of D2 ([144][Xp], built once)
+//    and the transposed patch matrix of D1 ([144][Pp], built once).  GEMM 2
+//    needs dA_0 along patches: 8 x 8 blocks are transposed in registers on
+//    their way into LDS.  Tiles go through LDS with the next chunk's loads in
+//    flight.  Split partial sums are added in a fixed order.
 //
 // Reference kernels (thread per output, direct loops) serve the FP64
 // instantiation used by the finite-difference check.
@@ -27,6 +38,7 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 struct BotArgs {
     int W1, H1, W2, H2, n0x, natom, h1, w1;
+    int Wp, H2p, Xp, Pp;   // padded dense layout (matrix-core path)
 };
 
 // dA_0(p, x) from the pooled gradient and codes of patch p (maps h1 x w1).
@@ -75,113 +87,193 @@ __device__ inline bf8 as_bf8(const uint16_t* p) {   // 8 consecutive bf16 (16-by
     return x.v;
 }
 
-// ---------------------------------------------------------------- dense dA_0
-// dA_0 is written once, densely ([patch][target pixel], operand type E), and
-// both contractions stream it with coalesced loads.
+// 8 values -> one 16-byte (BF16) or two 16-byte (FP32) stores.
 template <typename E>
-__device__ inline void bwd_da_body(const float* __restrict__ gp, const uint8_t* __restrict__ code, const BotArgs& a,
-                                   int xblocks, E* __restrict__ dA, int bid) {
-    const int p = bid / xblocks, xb = bid - p * xblocks;
-    const int npos = a.H2 * a.W2;
-    const size_t pm = (size_t)a.h1 * a.w1;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int x = xb * 1024 + u * 256 + threadIdx.x;
-        if (x >= npos) continue;
-        const int xy = x / a.W2, xx = x - xy * a.W2;
-        const float v = dA_at(gp + p * pm, code + p * pm, a.h1, a.w1, xy, xx);
-        if constexpr (std::is_same<E, float>::value) dA[(size_t)p * npos + x] = v;
-        else dA[(size_t)p * npos + x] = to_bf16(v);
+__device__ inline void store8(E* dst, const float v[8]) {
+    if constexpr (std::is_same<E, float>::value) {
+        reinterpret_cast<float4*>(dst)[0] = make_float4(v[0], v[1], v[2], v[3]);
+        reinterpret_cast<float4*>(dst)[1] = make_float4(v[4], v[5], v[6], v[7]);
+    } else {
+        uint4 u;
+        u.x = (uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16);
+        u.y = (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16);
+        u.z = (uint32_t)to_bf16(v[4]) | ((uint32_t)to_bf16(v[5]) << 16);
+        u.w = (uint32_t)to_bf16(v[6]) | ((uint32_t)to_bf16(v[7]) << 16);
+        *reinterpret_cast<uint4*>(dst) = u;
     }
 }
 
-// Patch matrix P[p][k] = D1[p + d_k][c_k] (k = (dy, dx, c)), operand type E.
+// ---------------------------------------------------------------- dense dA_0
+// Block: one patch x 8 target rows x 256 target columns of the padded grid.
+// The pooled entries whose windows reach the tile (6 rows x 130 columns) are
+// staged in LDS; each thread forms 8 consecutive outputs of one row, summing
+// its candidates in the order of dA_at (pooled row, then pooled column).
+constexpr int DA_ROWS = 8, DA_COLS = 256, DA_SR = 6, DA_SC = DA_COLS / 2 + 2;
+
 template <typename E>
-__device__ inline void bwd_patchmat_body(const float* __restrict__ d1, const BotArgs& a, E* __restrict__ P, int bid) {
-    const size_t i = (size_t)bid * 256 + threadIdx.x;
-    if (i >= (size_t)a.natom * 144) return;
-    const int p = i / 144, k = i % 144;
-    const float v = d1_at(d1, a, p, k);
-    if constexpr (std::is_same<E, float>::value) P[i] = v;
-    else P[i] = to_bf16(v);
+__device__ inline void bwd_da_body(const float* __restrict__ gp, const uint8_t* __restrict__ code, const BotArgs& a,
+                                   int nct, E* __restrict__ dA, int bid) {
+    __shared__ float sg[DA_SR][DA_SC];
+    __shared__ int sm[DA_SR][DA_SC];
+    const int nband = a.H2p / DA_ROWS;
+    const int ct = bid % nct, rest = bid / nct, band = rest % nband, p = rest / nband;
+    const int Y0 = band * DA_ROWS, X0 = ct * DA_COLS;
+    const int ry0 = (Y0 >> 1) - 1, rx0 = (X0 >> 1) - 1;
+    const size_t pm = (size_t)a.h1 * a.w1;
+    for (int e = threadIdx.x; e < DA_SR * DA_SC; e += 256) {
+        const int i = e / DA_SC, j = e - i * DA_SC;
+        const int ry = ry0 + i, rx = rx0 + j;
+        float g = 0.f;
+        int m = -1;
+        if (p < a.natom && ry >= 0 && ry < a.h1 && rx >= 0 && rx < a.w1) {
+            const size_t o = p * pm + (size_t)ry * a.w1 + rx;
+            g = gp[o];
+            m = code[o];
+        }
+        sg[i][j] = g;
+        sm[i][j] = m;
+    }
+    __syncthreads();
+    const int row = threadIdx.x >> 5, grp = threadIdx.x & 31;
+    const int y = Y0 + row, xb = X0 + 8 * grp;
+    if (xb >= a.Wp) return;
+    float out[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) out[q] = 0.f;
+    if (y < a.H2) {
+        for (int ry = (y - 1) >> 1; ry <= (y + 1) >> 1; ++ry) {
+            const int my = y - 2 * ry;
+            if (my < -1 || my > 1) continue;
+            const int i = ry - ry0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int x = xb + q;
+                if (x >= a.W2) continue;
+                for (int rx = (x - 1) >> 1; rx <= (x + 1) >> 1; ++rx) {
+                    const int mx = x - 2 * rx;
+                    if (mx < -1 || mx > 1) continue;
+                    const int j = rx - rx0;
+                    if (sm[i][j] == 3 * (my + 1) + (mx + 1)) out[q] += sg[i][j];
+                }
+            }
+        }
+    }
+    store8<E>(dA + (size_t)p * a.Xp + (size_t)y * a.Wp + xb, out);
 }
 
-// ---------------------------------------------------------------- GEMM 1: dD1
-// Block: 128 patches (32 per wave = 2 M-tiles) x all 144 K columns (9
-// N-tiles), reducing over the target rows of one split in chunks of 64
-// pixels of one row: the dA tile [128][64] comes straight from the dense dA,
-// the im2col tile [144][64] is built from an LDS copy of the 4 x 67 target
-// pixels it covers.
-constexpr int G1P = 128, KC = 64;
+// Transposed im2col of D2: D2colT[k][x] = D2[x + d_k][c_k] on the padded grid.
+template <typename E>
+__device__ inline void bwd_d2col_body(const float* __restrict__ d2, const BotArgs& a, E* __restrict__ d2colT,
+                                      int bid) {
+    const size_t v = (size_t)bid * 256 + threadIdx.x;   // one group of 8 positions
+    const int gpr = a.Xp / 8;
+    if (v >= (size_t)144 * gpr) return;
+    const int k = v / gpr, x0 = (int)(v - (size_t)k * gpr) * 8;
+    const int y = x0 / a.Wp, xx0 = x0 - y * a.Wp;
+    float out[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) out[q] = (y < a.H2 && xx0 + q < a.W2) ? d2_at(d2, a, y, xx0 + q, k) : 0.f;
+    store8<E>(d2colT + (size_t)k * a.Xp + x0, out);
+}
+
+// Transposed patch matrix of D1: PT[k][p] = D1[p + d_k][c_k] (0 for padding patches).
+template <typename E>
+__device__ inline void bwd_pt_body(const float* __restrict__ d1, const BotArgs& a, E* __restrict__ PT, int bid) {
+    const size_t v = (size_t)bid * 256 + threadIdx.x;
+    const int gpr = a.Pp / 8;
+    if (v >= (size_t)144 * gpr) return;
+    const int k = v / gpr, p0 = (int)(v - (size_t)k * gpr) * 8;
+    float out[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) out[q] = p0 + q < a.natom ? d1_at(d1, a, p0 + q, k) : 0.f;
+    store8<E>(PT + (size_t)k * a.Pp + p0, out);
+}
+
+// ---------------------------------------------------------------- GEMMs
+constexpr int GK = 64;     // K chunk
+constexpr int G1M = 128;   // GEMM 1: patches per block
+constexpr int G2N = 128;   // GEMM 2: positions per block
 
 template <bool BF16>
-__device__ inline void bwd_dd1_gemm_body(const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ dA,
-                                         const float* __restrict__ d2, const BotArgs& a, int nsplit,
-                                         float* __restrict__ part, int bid) {
+struct Op {
     typedef typename std::conditional<BF16, uint16_t, float>::type E;
-    constexpr int PAD = BF16 ? 8 : 1;
-    __shared__ __align__(16) E sA[G1P][KC + PAD];
-    __shared__ __align__(16) E sB[144][KC + PAD];
-    __shared__ float sD2[4][KC + 3][9];
-    const int ptile = bid / nsplit, split = bid % nsplit;
+    static constexpr int VPR = BF16 ? 8 : 4;     // values per 16-byte vector
+    static constexpr int PAD = BF16 ? 8 : 4;     // LDS row padding (keeps rows 16-byte aligned)
+    static constexpr int CV = GK / VPR;          // vectors per chunk row
+};
+
+// C[M=128 patches][N=144] += A[M][K] * B[N][K]^T over the chunks of one split.
+template <bool BF16>
+__device__ inline void bwd_gemm1_body(const typename Op<BF16>::E* __restrict__ dA,
+                                      const typename Op<BF16>::E* __restrict__ d2colT, const BotArgs& a, int nsplit,
+                                      float* __restrict__ part, int bid) {
+    typedef Op<BF16> O;
+    typedef typename O::E E;
+    __shared__ __align__(16) E sA[G1M][GK + O::PAD];
+    __shared__ __align__(16) E sB[144][GK + O::PAD];
+    constexpr int NA = G1M * O::CV / 256, NB = (144 * O::CV + 255) / 256;
+    const int ptiles = a.Pp / G1M;
+    const int split = bid / ptiles, ptile = bid - split * ptiles;
+    const int kper = ((a.Xp / GK + nsplit - 1) / nsplit) * GK;
+    const int k_begin = split * kper, k_end = min(a.Xp, k_begin + kper);
+    const int P0 = ptile * G1M;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
-    const int npos = a.H2 * a.W2;
-    const int rows_per = (a.H2 + nsplit - 1) / nsplit;
-    const int y_begin = split * rows_per, y_end = min(a.H2, y_begin + rows_per);
+    uint4 ra[NA], rb[NB];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int v = tid + 256 * i, r = v / O::CV, c = v - r * O::CV;
+            ra[i] = *reinterpret_cast<const uint4*>(dA + (size_t)(P0 + r) * a.Xp + k0 + c * O::VPR);
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int v = tid + 256 * i, r = v / O::CV, c = v - r * O::CV;
+            if (v < 144 * O::CV) rb[i] = *reinterpret_cast<const uint4*>(d2colT + (size_t)r * a.Xp + k0 + c * O::VPR);
+        }
+    };
     f4 acc[2][9];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 9; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int y = y_begin; y < y_end; ++y) {
-        for (int x0 = 0; x0 < a.W2; x0 += KC) {
-            __syncthreads();
-            // target pixels rows y-2..y+1, columns x0-2..x0+KC, zero outside
-            for (int e = tid; e < 4 * (KC + 3) * 9; e += 256) {
-                const int r = e / ((KC + 3) * 9), rem = e - r * ((KC + 3) * 9);
-                const int col = rem / 9, c = rem - col * 9;
-                const int yy = y - 2 + r, xx = x0 - 2 + col;
-                sD2[r][col][c] = (yy >= 0 && yy < a.H2 && xx >= 0 && xx < a.W2) ? d2[((size_t)yy * a.W2 + xx) * 9 + c] : 0.f;
-            }
-            for (int e = tid; e < G1P * KC; e += 256) {
-                const int pl = e / KC, xi = e - pl * KC;
-                const int p = ptile * G1P + pl, x = x0 + xi;
-                E v = E(0);
-                if (p < a.natom && x < a.W2) v = dA[(size_t)p * npos + y * a.W2 + x];
-                sA[pl][xi] = v;
-            }
-            __syncthreads();
-            for (int e = tid; e < 144 * KC; e += 256) {
-                const int k = e / KC, xi = e - k * KC;
-                const int dy = k / 36, dx = (k / 9) % 4, c = k % 9;
-                const float v = (x0 + xi < a.W2) ? sD2[dy][xi + dx][c] : 0.f;
-                if constexpr (BF16) sB[k][xi] = to_bf16(v); else sB[k][xi] = v;
-            }
-            __syncthreads();
-            if constexpr (BF16) {
+    if (k_begin < k_end) load(k_begin);
+    for (int k0 = k_begin; k0 < k_end; k0 += GK) {
+        __syncthreads();
 #pragma unroll
-                for (int s = 0; s < KC / 32; ++s) {
-                    bf8 av[2];
+        for (int i = 0; i < NA; ++i) {
+            const int v = tid + 256 * i, r = v / O::CV, c = v - r * O::CV;
+            *reinterpret_cast<uint4*>(&sA[r][c * O::VPR]) = ra[i];
+        }
 #pragma unroll
-                    for (int mt = 0; mt < 2; ++mt) av[mt] = as_bf8(&sA[wave * 32 + mt * 16 + n][32 * s + 8 * g]);
+        for (int i = 0; i < NB; ++i) {
+            const int v = tid + 256 * i, r = v / O::CV, c = v - r * O::CV;
+            if (v < 144 * O::CV) *reinterpret_cast<uint4*>(&sB[r][c * O::VPR]) = rb[i];
+        }
+        __syncthreads();
+        if (k0 + GK < k_end) load(k0 + GK);   // next chunk in flight during the MFMAs
+        if constexpr (BF16) {
 #pragma unroll
-                    for (int nt = 0; nt < 9; ++nt) {
-                        const bf8 bv = as_bf8(&sB[16 * nt + n][32 * s + 8 * g]);
+            for (int s = 0; s < GK / 32; ++s) {
+                bf8 av[2];
 #pragma unroll
-                        for (int mt = 0; mt < 2; ++mt)
-                            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv, acc[mt][nt], 0, 0, 0);
-                    }
+                for (int mt = 0; mt < 2; ++mt) av[mt] = as_bf8(&sA[wave * 32 + mt * 16 + n][32 * s + 8 * g]);
+#pragma unroll
+                for (int nt = 0; nt < 9; ++nt) {
+                    const bf8 bv = as_bf8(&sB[16 * nt + n][32 * s + 8 * g]);
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv, acc[mt][nt], 0, 0, 0);
                 }
-            } else {
-#pragma unroll 2
-                for (int t = 0; t < KC / 4; ++t) {
-                    const float a0 = sA[wave * 32 + n][4 * t + g], a1 = sA[wave * 32 + 16 + n][4 * t + g];
+            }
+        } else {
+#pragma unroll 4
+            for (int t = 0; t < GK / 4; ++t) {
+                const float a0 = sA[wave * 32 + n][4 * t + g], a1 = sA[wave * 32 + 16 + n][4 * t + g];
 #pragma unroll
-                    for (int nt = 0; nt < 9; ++nt) {
-                        const float bv = sB[16 * nt + n][4 * t + g];
-                        acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv, acc[0][nt], 0, 0, 0);
-                        acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv, acc[1][nt], 0, 0, 0);
-                    }
+                for (int nt = 0; nt < 9; ++nt) {
+                    const float bv = sB[16 * nt + n][4 * t + g];
+                    acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv, acc[0][nt], 0, 0, 0);
+                    acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv, acc[1][nt], 0, 0, 0);
                 }
             }
         }
@@ -192,7 +284,7 @@ __device__ inline void bwd_dd1_gemm_body(const typename std::conditional<BF16, u
         for (int nt = 0; nt < 9; ++nt)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int p = ptile * G1P + wave * 32 + mt * 16 + 4 * g + j;
+                const int p = P0 + wave * 32 + mt * 16 + 4 * g + j;
                 if (p < a.natom) part[((size_t)split * a.natom + p) * 144 + 16 * nt + n] = acc[mt][nt][j];
             }
 }
@@ -217,96 +309,152 @@ __device__ inline void bwd_dd1_reduce_body(const T* __restrict__ part, const Bot
     dd1[i] = v;
 }
 
-// ---------------------------------------------------------------- GEMM 2: T
-// Block: 128 target pixels (32 per wave = 2 M-tiles) x 144 columns, reducing
-// over all patches in chunks of 64: dA tile kept transposed [pixel][patch]
-// and patch tile [144][patch] in LDS.
+// T[M=144][N=128 positions] += PT[M][K] * dA[K][N] over all patch chunks.
+// The dA chunk (64 patches x 128 positions) comes through registers, its
+// 8 x 8 (BF16) or 4 x 4 (FP32) blocks transposed so that LDS holds it as
+// [position][patch]; the PT chunk is copied as it is.
 template <bool BF16>
-__device__ inline void bwd_t_gemm_body(const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ dA,
-                                       const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ P,
-                                       const BotArgs& a, float* __restrict__ tbuf, int bid) {
-    typedef typename std::conditional<BF16, uint16_t, float>::type E;
-    constexpr int PAD = BF16 ? 8 : 1;
-    __shared__ __align__(16) E sAT[128][64 + PAD];   // [pixel][patch]
-    __shared__ __align__(16) E sP[144][64 + PAD];    // [k][patch]
+__device__ inline void bwd_gemm2_body(const typename Op<BF16>::E* __restrict__ dA,
+                                      const typename Op<BF16>::E* __restrict__ PT, const BotArgs& a,
+                                      float* __restrict__ tt, int bid) {
+    typedef Op<BF16> O;
+    typedef typename O::E E;
+    __shared__ __align__(16) E sA[144][GK + O::PAD];   // PT chunk [k][patch]
+    __shared__ __align__(16) E sB[G2N][GK + O::PAD];   // dA chunk [position][patch]
+    const int X0 = bid * G2N;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
-    const int npos = a.H2 * a.W2;
-    const int xb = bid * 128;
-    f4 acc[2][9];
+    // BF16: threads 0..127 take one 8x8 dA block each, threads 128..255 the
+    // PT chunk; FP32: every thread takes two 4x4 dA blocks and part of PT.
+    constexpr int BR = BF16 ? 8 : 4, NBLK = BF16 ? 1 : 2;
+    constexpr int NTH_A = BF16 ? 128 : 256, NTH_P = BF16 ? 128 : 256;   // threads per role
+    constexpr int NPT = (144 * O::CV + NTH_P - 1) / NTH_P;             // PT vectors per thread
+    uint4 rd[NBLK][BR];
+    uint4 rp[NPT];
+    const bool loader_a = BF16 ? tid < 128 : true;    // wave-uniform
+    const bool loader_p = BF16 ? tid >= 128 : true;
+    const int tp = BF16 ? tid - 128 : tid;
+    auto load = [&](int p0) {
+        if (loader_a) {
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+            for (int b = 0; b < NBLK; ++b) {
+                const int blk = tid + NTH_A * b;                     // BF16: 8 x 16 blocks; FP32: 16 x 32
+                const int xbn = G2N / BR, pb = blk / xbn, xb = blk - pb * xbn;
 #pragma unroll
-        for (int nt = 0; nt < 9; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int p0 = 0; p0 < a.natom; p0 += 64) {
-        __syncthreads();
-        for (int e = tid; e < 64 * 128; e += 256) {
-            const int pl = e / 128, xi = e - pl * 128;
-            const int p = p0 + pl, x = xb + xi;
-            sAT[xi][pl] = (p < a.natom && x < npos) ? dA[(size_t)p * npos + x] : E(0);
+                for (int i = 0; i < BR; ++i)
+                    rd[b][i] = *reinterpret_cast<const uint4*>(dA + (size_t)(p0 + BR * pb + i) * a.Xp + X0 + BR * xb);
+            }
         }
-        for (int e = tid; e < 64 * 144; e += 256) {
-            const int pl = e / 144, k = e - pl * 144;
-            const int p = p0 + pl;
-            sP[k][pl] = p < a.natom ? P[(size_t)p * 144 + k] : E(0);
+        if (loader_p) {
+#pragma unroll
+            for (int i = 0; i < NPT; ++i) {
+                const int v = tp + NTH_P * i, r = v / O::CV, c = v - r * O::CV;
+                if (v < 144 * O::CV) rp[i] = *reinterpret_cast<const uint4*>(PT + (size_t)r * a.Pp + p0 + c * O::VPR);
+            }
         }
+    };
+    auto store = [&]() {
+        if (loader_a) {
+#pragma unroll
+            for (int b = 0; b < NBLK; ++b) {
+                const int blk = tid + NTH_A * b;
+                const int xbn = G2N / BR, pb = blk / xbn, xb = blk - pb * xbn;
+                if constexpr (BF16) {
+                    // rd[b][i] = 8 bf16 of patch row i (positions 2j, 2j+1 in dword j);
+                    // column q (position) = 8 patches, packed 2 per dword.
+                    const uint32_t* w = reinterpret_cast<const uint32_t*>(rd[b]);   // w[4 i + j]
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        uint32_t o[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const uint32_t lo = w[4 * (2 * j) + (q >> 1)], hi = w[4 * (2 * j + 1) + (q >> 1)];
+                            o[j] = (q & 1) ? ((lo >> 16) | (hi & 0xFFFF0000u)) : ((lo & 0xFFFFu) | (hi << 16));
+                        }
+                        *reinterpret_cast<uint4*>(&sB[BR * xb + q][BR * pb]) = make_uint4(o[0], o[1], o[2], o[3]);
+                    }
+                } else {
+                    const uint32_t* w = reinterpret_cast<const uint32_t*>(rd[b]);   // w[4 i + q]
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        *reinterpret_cast<uint4*>(&sB[BR * xb + q][BR * pb]) =
+                            make_uint4(w[q], w[4 + q], w[8 + q], w[12 + q]);
+                }
+            }
+        }
+        if (loader_p) {
+#pragma unroll
+            for (int i = 0; i < NPT; ++i) {
+                const int v = tp + NTH_P * i, r = v / O::CV, c = v - r * O::CV;
+                if (v < 144 * O::CV) *reinterpret_cast<uint4*>(&sA[r][c * O::VPR]) = rp[i];
+            }
+        }
+    };
+    f4 acc[9][2];
+#pragma unroll
+    for (int mt = 0; mt < 9; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+    load(0);
+    for (int p0 = 0; p0 < a.Pp; p0 += GK) {
         __syncthreads();
+        store();
+        __syncthreads();
+        if (p0 + GK < a.Pp) load(p0 + GK);
         if constexpr (BF16) {
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                bf8 av[2];
+            for (int s = 0; s < GK / 32; ++s) {
+                bf8 bv[2];
 #pragma unroll
-                for (int mt = 0; mt < 2; ++mt) av[mt] = as_bf8(&sAT[wave * 32 + mt * 16 + n][32 * s + 8 * g]);
+                for (int nt = 0; nt < 2; ++nt) bv[nt] = as_bf8(&sB[wave * 32 + nt * 16 + n][32 * s + 8 * g]);
 #pragma unroll
-                for (int nt = 0; nt < 9; ++nt) {
-                    const bf8 bv = as_bf8(&sP[16 * nt + n][32 * s + 8 * g]);
+                for (int mt = 0; mt < 9; ++mt) {
+                    const bf8 av = as_bf8(&sA[16 * mt + n][32 * s + 8 * g]);
 #pragma unroll
-                    for (int mt = 0; mt < 2; ++mt)
-                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv, acc[mt][nt], 0, 0, 0);
+                    for (int nt = 0; nt < 2; ++nt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nt], acc[mt][nt], 0, 0, 0);
                 }
             }
         } else {
-#pragma unroll 2
-            for (int t = 0; t < 16; ++t) {
-                const float a0 = sAT[wave * 32 + n][4 * t + g], a1 = sAT[wave * 32 + 16 + n][4 * t + g];
+#pragma unroll 4
+            for (int t = 0; t < GK / 4; ++t) {
+                const float b0 = sB[wave * 32 + n][4 * t + g], b1 = sB[wave * 32 + 16 + n][4 * t + g];
 #pragma unroll
-                for (int nt = 0; nt < 9; ++nt) {
-                    const float bv = sP[16 * nt + n][4 * t + g];
-                    acc[0][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv, acc[0][nt], 0, 0, 0);
-                    acc[1][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv, acc[1][nt], 0, 0, 0);
+                for (int mt = 0; mt < 9; ++mt) {
+                    const float av = sA[16 * mt + n][4 * t + g];
+                    acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b0, acc[mt][0], 0, 0, 0);
+                    acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b1, acc[mt][1], 0, 0, 0);
                 }
             }
         }
     }
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+    for (int mt = 0; mt < 9; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 9; ++nt)
+        for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int x = xb + wave * 32 + mt * 16 + 4 * g + j;
-                if (x < npos) tbuf[(size_t)x * 144 + 16 * nt + n] = acc[mt][nt][j];
-            }
+            for (int j = 0; j < 4; ++j)
+                tt[(size_t)(16 * mt + 4 * g + j) * a.Xp + X0 + wave * 32 + nt * 16 + n] = acc[mt][nt][j];
 }
 
-// dD2[y][c] = 1/16 sum_d T[y - d][(d, c)]  (T is zero outside the target).
-template <typename T>
-__device__ inline void bwd_col2im_body(const T* __restrict__ tbuf, const BotArgs& a, T* __restrict__ dd2, int bid) {
+// dD2[y][c] = 1/16 sum_d T[(d, c)][y - d] on the padded grid (T is zero outside the target).
+__device__ inline void bwd_col2im_body(const float* __restrict__ tt, const BotArgs& a, float* __restrict__ dd2,
+                                       int bid) {
     const size_t n = (size_t)a.H2 * a.W2 * 9;
     const size_t i = (size_t)bid * 256 + threadIdx.x;
     if (i >= n) return;
     const int c = i % 9;
     const int x = (i / 9) % a.W2, y = i / (9 * (size_t)a.W2);
-    T v = 0;
+    float v = 0.f;
     for (int dy = 0; dy < 4; ++dy) {
         const int qy = y + 2 - dy;          // position whose patch covers y at row offset dy
         if (qy < 0 || qy >= a.H2) continue;
         for (int dx = 0; dx < 4; ++dx) {
             const int qx = x + 2 - dx;
             if (qx < 0 || qx >= a.W2) continue;
-            v += tbuf[((size_t)qy * a.W2 + qx) * 144 + dy * 36 + dx * 9 + c];
+            v += tt[(size_t)(dy * 36 + dx * 9 + c) * a.Xp + (size_t)qy * a.Wp + qx];
         }
     }
-    dd2[i] = v / T(16);
+    dd2[i] = v / 16.f;
 }
 
 // ---------------------------------------------------------------- reference kernels
@@ -346,36 +494,60 @@ __global__ void k_bwd_t_ref(const T* __restrict__ gp, const uint8_t* __restrict_
     tbuf[i] = acc;
 }
 
+// col2im of the reference layout tbuf[x][k].
+template <typename T>
+__global__ void k_bwd_col2im_ref(const T* __restrict__ tbuf, BotArgs a, T* __restrict__ dd2) {
+    const size_t n = (size_t)a.H2 * a.W2 * 9;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = i % 9;
+    const int x = (i / 9) % a.W2, y = i / (9 * (size_t)a.W2);
+    T v = 0;
+    for (int dy = 0; dy < 4; ++dy) {
+        const int qy = y + 2 - dy;
+        if (qy < 0 || qy >= a.H2) continue;
+        for (int dx = 0; dx < 4; ++dx) {
+            const int qx = x + 2 - dx;
+            if (qx < 0 || qx >= a.W2) continue;
+            v += tbuf[((size_t)qy * a.W2 + qx) * 144 + dy * 36 + dx * 9 + c];
+        }
+    }
+    dd2[i] = v / T(16);
+}
+
+// ---------------------------------------------------------------- kernels and jobs
 template <typename E>
 __global__ __launch_bounds__(256) void k_bwd_da(const float* __restrict__ gp, const uint8_t* __restrict__ code,
-                                                BotArgs a, int xblocks, E* __restrict__ dA) {
-    bwd_da_body<E>(gp, code, a, xblocks, dA, blockIdx.x);
+                                                BotArgs a, int nct, E* __restrict__ dA) {
+    bwd_da_body<E>(gp, code, a, nct, dA, blockIdx.x);
 }
 template <typename E>
-__global__ __launch_bounds__(256) void k_bwd_patchmat(const float* __restrict__ d1, BotArgs a, E* __restrict__ P) {
-    bwd_patchmat_body<E>(d1, a, P, blockIdx.x);
+__global__ __launch_bounds__(256) void k_bwd_d2col(const float* __restrict__ d2, BotArgs a, E* __restrict__ d2colT) {
+    bwd_d2col_body<E>(d2, a, d2colT, blockIdx.x);
+}
+template <typename E>
+__global__ __launch_bounds__(256) void k_bwd_pt(const float* __restrict__ d1, BotArgs a, E* __restrict__ PT) {
+    bwd_pt_body<E>(d1, a, PT, blockIdx.x);
 }
 template <bool BF16>
-__global__ __launch_bounds__(256) void k_bwd_dd1_gemm(
-    const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ dA, const float* __restrict__ d2,
-    BotArgs a, int nsplit, float* __restrict__ part) {
-    bwd_dd1_gemm_body<BF16>(dA, d2, a, nsplit, part, blockIdx.x);
+__global__ __launch_bounds__(256) void k_bwd_gemm1(const typename Op<BF16>::E* __restrict__ dA,
+                                                   const typename Op<BF16>::E* __restrict__ d2colT, BotArgs a,
+                                                   int nsplit, float* __restrict__ part) {
+    bwd_gemm1_body<BF16>(dA, d2colT, a, nsplit, part, blockIdx.x);
+}
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_bwd_gemm2(const typename Op<BF16>::E* __restrict__ dA,
+                                                   const typename Op<BF16>::E* __restrict__ PT, BotArgs a,
+                                                   float* __restrict__ tt) {
+    bwd_gemm2_body<BF16>(dA, PT, a, tt, blockIdx.x);
 }
 template <typename T>
 __global__ __launch_bounds__(256) void k_bwd_dd1_reduce(const T* __restrict__ part, BotArgs a, int nsplit,
                                                         T* __restrict__ dd1) {
     bwd_dd1_reduce_body<T>(part, a, nsplit, dd1, blockIdx.x);
 }
-template <bool BF16>
-__global__ __launch_bounds__(256) void k_bwd_t_gemm(
-    const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ dA,
-    const typename std::conditional<BF16, uint16_t, float>::type* __restrict__ P, BotArgs a,
-    float* __restrict__ tbuf) {
-    bwd_t_gemm_body<BF16>(dA, P, a, tbuf, blockIdx.x);
-}
-template <typename T>
-__global__ __launch_bounds__(256) void k_bwd_col2im(const T* __restrict__ tbuf, BotArgs a, T* __restrict__ dd2) {
-    bwd_col2im_body<T>(tbuf, a, dd2, blockIdx.x);
+__global__ __launch_bounds__(256) void k_bwd_col2im(const float* __restrict__ tt, BotArgs a, float* __restrict__ dd2) {
+    bwd_col2im_body(tt, a, dd2, blockIdx.x);
 }
 
 template <typename E>
@@ -383,32 +555,38 @@ struct DaJob {
     const float* gp;
     const uint8_t* code;
     BotArgs a;
-    int xblocks;
+    int nct;
     E* dA;
-    static __device__ void run(const DaJob& j, int v) { bwd_da_body<E>(j.gp, j.code, j.a, j.xblocks, j.dA, v); }
+    static __device__ void run(const DaJob& j, int v) { bwd_da_body<E>(j.gp, j.code, j.a, j.nct, j.dA, v); }
 };
 template <typename E>
-struct PatchJob {
+struct D2colJob {
+    const float* d2;
+    BotArgs a;
+    E* d2colT;
+    static __device__ void run(const D2colJob& j, int v) { bwd_d2col_body<E>(j.d2, j.a, j.d2colT, v); }
+};
+template <typename E>
+struct PtJob {
     const float* d1;
     BotArgs a;
-    E* P;
-    static __device__ void run(const PatchJob& j, int v) { bwd_patchmat_body<E>(j.d1, j.a, j.P, v); }
+    E* PT;
+    static __device__ void run(const PtJob& j, int v) { bwd_pt_body<E>(j.d1, j.a, j.PT, v); }
 };
 template <bool BF16>
-struct Dd1Job {
-    const typename std::conditional<BF16, uint16_t, float>::type* dA;
-    const float* d2;
+struct Gemm1Job {
+    const typename Op<BF16>::E *dA, *d2colT;
     BotArgs a;
     int nsplit;
     float* part;
-    static __device__ void run(const Dd1Job& j, int v) { bwd_dd1_gemm_body<BF16>(j.dA, j.d2, j.a, j.nsplit, j.part, v); }
+    static __device__ void run(const Gemm1Job& j, int v) { bwd_gemm1_body<BF16>(j.dA, j.d2colT, j.a, j.nsplit, j.part, v); }
 };
 template <bool BF16>
-struct TgJob {
-    const typename std::conditional<BF16, uint16_t, float>::type *dA, *P;
+struct Gemm2Job {
+    const typename Op<BF16>::E *dA, *PT;
     BotArgs a;
-    float* tbuf;
-    static __device__ void run(const TgJob& j, int v) { bwd_t_gemm_body<BF16>(j.dA, j.P, j.a, j.tbuf, v); }
+    float* tt;
+    static __device__ void run(const Gemm2Job& j, int v) { bwd_gemm2_body<BF16>(j.dA, j.PT, j.a, j.tt, v); }
 };
 struct Dd1ReduceJob {
     const float* part;
@@ -418,10 +596,10 @@ struct Dd1ReduceJob {
     static __device__ void run(const Dd1ReduceJob& j, int v) { bwd_dd1_reduce_body<float>(j.part, j.a, j.nsplit, j.dd1, v); }
 };
 struct Col2imJob {
-    const float* tbuf;
+    const float* tt;
     BotArgs a;
     float* dd2;
-    static __device__ void run(const Col2imJob& j, int v) { bwd_col2im_body<float>(j.tbuf, j.a, j.dd2, v); }
+    static __device__ void run(const Col2imJob& j, int v) { bwd_col2im_body(j.tt, j.a, j.dd2, v); }
 };
 
 BotArgs make_bot(const Geom& g) {
@@ -434,57 +612,102 @@ BotArgs make_bot(const Geom& g) {
     a.natom = g.gx[0] * g.gy[0];
     a.h1 = g.h[1];
     a.w1 = g.w[1];
+    a.Wp = (g.W2 + 7) & ~7;
+    a.H2p = (g.H2 + 15) & ~15;
+    a.Xp = a.Wp * a.H2p;
+    a.Pp = (a.natom + G1M - 1) / G1M * G1M;
     return a;
 }
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Byte offsets of dA_0, D2colT and PT inside the dense scratch region.
+struct DenseLayout {
+    size_t da, d2col, pt, total;
+};
+DenseLayout dense_layout(const BotArgs& a, size_t es) {
+    DenseLayout d;
+    d.da = 0;
+    d.d2col = align256((size_t)a.Pp * a.Xp * es);
+    d.pt = d.d2col + align256((size_t)144 * a.Xp * es);
+    d.total = d.pt + align256((size_t)144 * a.Pp * es);
+    return d;
+}
+
+struct BotPlan {
+    BotArgs a;
+    int ns, nct, da_blocks, d2_blocks, pt_blocks, g1_blocks, g2_blocks, red_blocks, c2i_blocks;
+};
 
 }  // namespace
 
 int bwd_nsplit(const Geom& g) {
-    // enough blocks for the 256 CUs: patch tiles x row splits >= ~1024
-    const int ptiles = (g.gx[0] * g.gy[0] + G1P - 1) / G1P;
+    // enough blocks for the 256 CUs: patch tiles x K splits >= ~1024
+    const int natom = g.gx[0] * g.gy[0];
+    const int ptiles = (natom + G1M - 1) / G1M;
+    const int xp = ((g.W2 + 7) & ~7) * ((g.H2 + 15) & ~15);
     int ns = (1024 + ptiles - 1) / ptiles;
-    if (ns > g.H2) ns = g.H2;
-    if (ns < 1) ns = 1;
+    if (ns > xp / GK) ns = xp / GK;
     if (ns > 64) ns = 64;
+    if (ns < 1) ns = 1;
     return ns;
 }
 
+namespace {
+BotPlan bot_plan(const Geom& g) {
+    BotPlan b;
+    b.a = make_bot(g);
+    b.ns = bwd_nsplit(g);
+    b.nct = (b.a.Wp + DA_COLS - 1) / DA_COLS;
+    b.da_blocks = b.a.Pp * (b.a.H2p / DA_ROWS) * b.nct;
+    b.d2_blocks = (int)(((size_t)144 * (b.a.Xp / 8) + 255) / 256);
+    b.pt_blocks = (int)(((size_t)144 * (b.a.Pp / 8) + 255) / 256);
+    b.g1_blocks = (b.a.Pp / G1M) * b.ns;
+    b.g2_blocks = b.a.Xp / G2N;
+    b.red_blocks = (int)(((size_t)b.a.H1 * b.a.W1 * 9 + 255) / 256);
+    b.c2i_blocks = (int)(((size_t)b.a.H2 * b.a.W2 * 9 + 255) / 256);
+    return b;
+}
+}  // namespace
+
 size_t bwd_dense_bytes(const Geom& g, int precision) {
-    const size_t es = precision == DM_BF16 ? 2 : 4;
-    return (size_t)g.gx[0] * g.gy[0] * ((size_t)g.H2 * g.W2 + 144) * es;
+    return dense_layout(make_bot(g), precision == DM_BF16 ? 2 : 4).total;
 }
 
-// The six stages of the bottom backward of one pair as job records (FP32
+size_t bwd_t_bytes(const Geom& g, int precision) {
+    if (precision == DM_FP64) return (size_t)g.W2 * g.H2 * 144 * 8;
+    return (size_t)144 * make_bot(g).Xp * 4;
+}
+
+// The seven stages of the bottom backward of one pair as job records (FP32
 // storage; bf16 selects BF16 MFMA operands), in launch order.
 std::vector<JobRec> bot_jobs(bool bf16, const float* gp, const uint8_t* code, const float* d1, const float* d2,
                              const Geom& g, float* part, float* tbuf, void* dense, float* dd1, float* dd2) {
-    const BotArgs a = make_bot(g);
-    const int ns = bwd_nsplit(g);
-    const int npos = a.H2 * a.W2;
-    const int xblocks = (npos + 1023) / 1024;
-    const int ptiles = (a.natom + G1P - 1) / G1P;
-    const int tblocks = (npos + 127) / 128;
-    const size_t pmat = (size_t)a.natom * 144;
-    const int pm_blocks = (int)((pmat + 255) / 256);
-    std::vector<JobRec> r(6);
+    const BotPlan b = bot_plan(g);
+    const DenseLayout d = dense_layout(b.a, bf16 ? 2 : 4);
+    char* base = static_cast<char*>(dense);
+    std::vector<JobRec> r(7);
     if (bf16) {
-        uint16_t* dA = (uint16_t*)dense;
-        uint16_t* P = dA + (size_t)a.natom * npos;
-        r[0].set(JK_BWD_DA_BF16, a.natom * xblocks, 0, DaJob<uint16_t>{gp, code, a, xblocks, dA});
-        r[1].set(JK_PATCH_BF16, pm_blocks, 0, PatchJob<uint16_t>{d1, a, P});
-        r[2].set(JK_DD1_BF16, ptiles * ns, 0, Dd1Job<true>{dA, d2, a, ns, part});
-        r[3].set(JK_TG_BF16, tblocks, 0, TgJob<true>{dA, P, a, tbuf});
+        uint16_t* dA = (uint16_t*)(base + d.da);
+        uint16_t* dc = (uint16_t*)(base + d.d2col);
+        uint16_t* pt = (uint16_t*)(base + d.pt);
+        r[0].set(JK_BWD_DA_BF16, b.da_blocks, 0, DaJob<uint16_t>{gp, code, b.a, b.nct, dA});
+        r[1].set(JK_D2COL_BF16, b.d2_blocks, 0, D2colJob<uint16_t>{d2, b.a, dc});
+        r[2].set(JK_PATCH_BF16, b.pt_blocks, 0, PtJob<uint16_t>{d1, b.a, pt});
+        r[3].set(JK_DD1_BF16, b.g1_blocks, 0, Gemm1Job<true>{dA, dc, b.a, b.ns, part});
+        r[4].set(JK_TG_BF16, b.g2_blocks, 0, Gemm2Job<true>{dA, pt, b.a, tbuf});
     } else {
-        float* dA = (float*)dense;
-        float* P = dA + (size_t)a.natom * npos;
-        r[0].set(JK_BWD_DA_F32, a.natom * xblocks, 0, DaJob<float>{gp, code, a, xblocks, dA});
-        r[1].set(JK_PATCH_F32, pm_blocks, 0, PatchJob<float>{d1, a, P});
-        r[2].set(JK_DD1_F32, ptiles * ns, 0, Dd1Job<false>{dA, d2, a, ns, part});
-        r[3].set(JK_TG_F32, tblocks, 0, TgJob<false>{dA, P, a, tbuf});
+        float* dA = (float*)(base + d.da);
+        float* dc = (float*)(base + d.d2col);
+        float* pt = (float*)(base + d.pt);
+        r[0].set(JK_BWD_DA_F32, b.da_blocks, 0, DaJob<float>{gp, code, b.a, b.nct, dA});
+        r[1].set(JK_D2COL_F32, b.d2_blocks, 0, D2colJob<float>{d2, b.a, dc});
+        r[2].set(JK_PATCH_F32, b.pt_blocks, 0, PtJob<float>{d1, b.a, pt});
+        r[3].set(JK_DD1_F32, b.g1_blocks, 0, Gemm1Job<false>{dA, dc, b.a, b.ns, part});
+        r[4].set(JK_TG_F32, b.g2_blocks, 0, Gemm2Job<false>{dA, pt, b.a, tbuf});
     }
-    const size_t n1 = (size_t)a.H1 * a.W1 * 9, n2 = (size_t)a.H2 * a.W2 * 9;
-    r[4].set(JK_DD1_REDUCE, (int)((n1 + 255) / 256), 0, Dd1ReduceJob{part, a, ns, dd1});
-    r[5].set(JK_COL2IM, (int)((n2 + 255) / 256), 0, Col2imJob{tbuf, a, dd2});
+    r[5].set(JK_DD1_REDUCE, b.red_blocks, 0, Dd1ReduceJob{part, b.a, b.ns, dd1});
+    r[6].set(JK_COL2IM, b.c2i_blocks, 0, Col2imJob{tbuf, b.a, dd2});
     return r;
 }
 
@@ -492,12 +715,14 @@ hipError_t launch_group_bot(int kind, const GroupLaunch& gl, hipStream_t s) {
     switch (kind) {
         case JK_BWD_DA_BF16: return launch_grouped<DaJob<uint16_t>, 256, 1>(gl, s);
         case JK_BWD_DA_F32: return launch_grouped<DaJob<float>, 256, 1>(gl, s);
-        case JK_PATCH_BF16: return launch_grouped<PatchJob<uint16_t>, 256, 1>(gl, s);
-        case JK_PATCH_F32: return launch_grouped<PatchJob<float>, 256, 1>(gl, s);
-        case JK_DD1_BF16: return launch_grouped<Dd1Job<true>, 256, 1>(gl, s);
-        case JK_DD1_F32: return launch_grouped<Dd1Job<false>, 256, 1>(gl, s);
-        case JK_TG_BF16: return launch_grouped<TgJob<true>, 256, 1>(gl, s);
-        case JK_TG_F32: return launch_grouped<TgJob<false>, 256, 1>(gl, s);
+        case JK_D2COL_BF16: return launch_grouped<D2colJob<uint16_t>, 256, 1>(gl, s);
+        case JK_D2COL_F32: return launch_grouped<D2colJob<float>, 256, 1>(gl, s);
+        case JK_PATCH_BF16: return launch_grouped<PtJob<uint16_t>, 256, 1>(gl, s);
+        case JK_PATCH_F32: return launch_grouped<PtJob<float>, 256, 1>(gl, s);
+        case JK_DD1_BF16: return launch_grouped<Gemm1Job<true>, 256, 1>(gl, s);
+        case JK_DD1_F32: return launch_grouped<Gemm1Job<false>, 256, 1>(gl, s);
+        case JK_TG_BF16: return launch_grouped<Gemm2Job<true>, 256, 1>(gl, s);
+        case JK_TG_F32: return launch_grouped<Gemm2Job<false>, 256, 1>(gl, s);
         case JK_DD1_REDUCE: return launch_grouped<Dd1ReduceJob, 256, 1>(gl, s);
         case JK_COL2IM: return launch_grouped<Col2imJob, 256, 1>(gl, s);
         default: return hipErrorInvalidValue;
@@ -513,45 +738,46 @@ hipError_t launch_bwd_bottom(int mode, const T* gp, const uint8_t* code, const T
         hipLaunchKernelGGL(__VA_ARGS__);   \
         timing_end(s);                     \
     } while (0)
-    const BotArgs a = make_bot(g);
-    int ns = 1;
     if (mode == 2) {  // reference kernels
+        const BotArgs a = make_bot(g);
         const size_t n1 = (size_t)a.natom * 144, n2 = (size_t)a.H2 * a.W2 * 144;
+        const size_t r1 = (size_t)a.H1 * a.W1 * 9, r2 = (size_t)a.H2 * a.W2 * 9;
         DM_SUB("bwd_dd1_ref", k_bwd_dd1_ref<T>, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, gp, code, d2, a, part);
         DM_SUB("bwd_t_ref", k_bwd_t_ref<T>, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, gp, code, d1, a, tbuf);
-    } else {
-        if constexpr (std::is_same<T, float>::value) {
-            ns = bwd_nsplit(g);
-            const int npos = a.H2 * a.W2;
-            const int xblocks = (npos + 1023) / 1024;
-            const int ptiles = (a.natom + G1P - 1) / G1P;
-            const int tblocks = (npos + 127) / 128;
-            const size_t pmat = (size_t)a.natom * 144;
-            if (mode == 1) {
-                uint16_t* dA = (uint16_t*)dense;
-                uint16_t* P = dA + (size_t)a.natom * npos;
-                DM_SUB("bwd_da", k_bwd_da<uint16_t>, dim3(a.natom * xblocks), dim3(256), 0, s, gp, code, a, xblocks, dA);
-                DM_SUB("bwd_patchmat", k_bwd_patchmat<uint16_t>, dim3((unsigned)((pmat + 255) / 256)), dim3(256), 0, s, d1, a, P);
-                DM_SUB("bwd_dd1_gemm", k_bwd_dd1_gemm<true>, dim3(ptiles * ns), dim3(256), 0, s, dA, d2, a, ns, part);
-                DM_SUB("bwd_t_gemm", k_bwd_t_gemm<true>, dim3(tblocks), dim3(256), 0, s, dA, P, a, tbuf);
-            } else {
-                float* dA = (float*)dense;
-                float* P = dA + (size_t)a.natom * npos;
-                DM_SUB("bwd_da", k_bwd_da<float>, dim3(a.natom * xblocks), dim3(256), 0, s, gp, code, a, xblocks, dA);
-                DM_SUB("bwd_patchmat", k_bwd_patchmat<float>, dim3((unsigned)((pmat + 255) / 256)), dim3(256), 0, s, d1, a, P);
-                DM_SUB("bwd_dd1_gemm", k_bwd_dd1_gemm<false>, dim3(ptiles * ns), dim3(256), 0, s, dA, d2, a, ns, part);
-                DM_SUB("bwd_t_gemm", k_bwd_t_gemm<false>, dim3(tblocks), dim3(256), 0, s, dA, P, a, tbuf);
-            }
-        } else {
-            return hipErrorInvalidValue;
-        }
+        DM_SUB("bwd_dd1_reduce", k_bwd_dd1_reduce<T>, dim3((unsigned)((r1 + 255) / 256)), dim3(256), 0, s, part, a, 1, dd1);
+        DM_SUB("bwd_col2im", k_bwd_col2im_ref<T>, dim3((unsigned)((r2 + 255) / 256)), dim3(256), 0, s, tbuf, a, dd2);
+        return hipGetLastError();
     }
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const size_t n1 = (size_t)a.H1 * a.W1 * 9, n2 = (size_t)a.H2 * a.W2 * 9;
-    DM_SUB("bwd_dd1_reduce", k_bwd_dd1_reduce<T>, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, part, a, ns, dd1);
-    DM_SUB("bwd_col2im", k_bwd_col2im<T>, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, tbuf, a, dd2);
-    return hipGetLastError();
+    if constexpr (std::is_same<T, float>::value) {
+        const BotPlan b = bot_plan(g);
+        const BotArgs& a = b.a;
+        const DenseLayout d = dense_layout(a, mode == 1 ? 2 : 4);
+        char* base = static_cast<char*>(dense);
+        if (mode == 1) {
+            uint16_t* dA = (uint16_t*)(base + d.da);
+            uint16_t* dc = (uint16_t*)(base + d.d2col);
+            uint16_t* pt = (uint16_t*)(base + d.pt);
+            DM_SUB("bwd_da", k_bwd_da<uint16_t>, dim3(b.da_blocks), dim3(256), 0, s, gp, code, a, b.nct, dA);
+            DM_SUB("bwd_d2col", k_bwd_d2col<uint16_t>, dim3(b.d2_blocks), dim3(256), 0, s, d2, a, dc);
+            DM_SUB("bwd_pt", k_bwd_pt<uint16_t>, dim3(b.pt_blocks), dim3(256), 0, s, d1, a, pt);
+            DM_SUB("bwd_dd1_gemm", k_bwd_gemm1<true>, dim3(b.g1_blocks), dim3(256), 0, s, dA, dc, a, b.ns, part);
+            DM_SUB("bwd_t_gemm", k_bwd_gemm2<true>, dim3(b.g2_blocks), dim3(256), 0, s, dA, pt, a, tbuf);
+        } else {
+            float* dA = (float*)(base + d.da);
+            float* dc = (float*)(base + d.d2col);
+            float* pt = (float*)(base + d.pt);
+            DM_SUB("bwd_da", k_bwd_da<float>, dim3(b.da_blocks), dim3(256), 0, s, gp, code, a, b.nct, dA);
+            DM_SUB("bwd_d2col", k_bwd_d2col<float>, dim3(b.d2_blocks), dim3(256), 0, s, d2, a, dc);
+            DM_SUB("bwd_pt", k_bwd_pt<float>, dim3(b.pt_blocks), dim3(256), 0, s, d1, a, pt);
+            DM_SUB("bwd_dd1_gemm", k_bwd_gemm1<false>, dim3(b.g1_blocks), dim3(256), 0, s, dA, dc, a, b.ns, part);
+            DM_SUB("bwd_t_gemm", k_bwd_gemm2<false>, dim3(b.g2_blocks), dim3(256), 0, s, dA, pt, a, tbuf);
+        }
+        DM_SUB("bwd_dd1_reduce", k_bwd_dd1_reduce<float>, dim3(b.red_blocks), dim3(256), 0, s, part, a, b.ns, dd1);
+        DM_SUB("bwd_col2im", k_bwd_col2im, dim3(b.c2i_blocks), dim3(256), 0, s, tbuf, a, dd2);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
 #undef DM_SUB
 }
 
