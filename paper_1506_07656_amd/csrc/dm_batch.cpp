@@ -49,6 +49,7 @@ hipError_t launch_group(int kind, const GroupLaunch& gl, hipStream_t s) {
             return launch_group_bt(kind, gl, s);
         case JK_TOP_GRAD:
         case JK_BWD_LEVEL:
+        case JK_BWD_LEVEL_STREAM:
             return launch_group_bwd(kind, gl, s);
         default:
             return launch_group_bot(kind, gl, s);
@@ -73,6 +74,7 @@ int default_res(int kind) {
         case JK_LEVEL_STREAM_VEC:
         case JK_LEVEL_STREAM:
         case JK_BT_STREAM:
+        case JK_BWD_LEVEL_STREAM:
             return 6;
         case JK_VALID:
         case JK_FINALIZE:

@@ -101,6 +101,7 @@ enum JobKind : int {
     JK_FINALIZE,
     JK_TOP_GRAD,
     JK_BWD_LEVEL,
+    JK_BWD_LEVEL_STREAM,
     JK_BWD_DA_BF16,
     JK_BWD_DA_F32,
     JK_PATCH_BF16,

@@ -14,6 +14,8 @@
 //   g'_{l-1}(c, r)  = dC'_{l-1}(c, r) * lambda * C'_{l-1}(c, r)^((lambda-1)/lambda)
 // and at the bottom dA_0(p, x) = sum_{r: 2r + m_0(p, r) = x} g'_0(p, r).
 // Every sum runs in a fixed order: results are deterministic.
+#include <type_traits>
+
 #include "dm_group.h"
 
 namespace dm {
@@ -165,6 +167,228 @@ __device__ inline void bwd_level_body(const BwdArgs& a, const T* __restrict__ dt
     }
 }
 
+// Row-streaming form of the level adjoint below the top (FP32, child maps at
+// least 32 columns wide).  One wave owns a child c, a band of rows and 64
+// output columns (one per lane).  Step rp brings pooled row rp of each
+// parent's g'_l and codes (lanes 0..33 cover the pooled columns the wave's
+// outputs can receive from) and adds every entry, times 1/|V(P_i)|, to the
+// output it reaches, r = 2r' + m + o_i, in a 6-row ring of output sums in
+// LDS.  Entries of one row are added in two passes (even pooled columns,
+// then odd ones), so that no two lanes of a pass touch one sum: every sum
+// is formed in a fixed order (step, side, pass) and the result is
+// deterministic.  U_l row r' is the last to reach output rows <= 2r' - 1,
+// so after step rp the rows 2rp-2, 2rp-1 are final: they are taken out of
+// the ring (cleared for reuse) and C'_{l-1} is read only where the sum is
+// non-zero (an out-of-range offset elsewhere), one step ahead of the
+// multiply by the rectification factor.  Only window outputs are added to,
+// so every added sum is taken exactly once.
+constexpr int kBwCols = 64;
+constexpr int kBwWaves = 4;
+constexpr int kBwRing = 6;
+constexpr int kOOB = 0x7ffffff0;   // buffer byte offset past any map
+
+struct BwStreamArgs {
+    int l;
+    int gxp, gyp, gxc, gyc;
+    int h, w;      // child pooled grid (maps of level l)
+    int hu, wu;    // pooled grid of level l
+    int TR, n_band, n_ct, n_cgrp;
+};
+
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, int nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, nbytes, 0x00020000);
+}
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline void bwd_level_stream_body(const BwStreamArgs& a, const float* __restrict__ gp_cur,
+                                             const uint8_t* __restrict__ code_cur, const float* __restrict__ cp_prev,
+                                             const uint8_t* __restrict__ vt, const Geom& g, float lam,
+                                             float* __restrict__ gp_prev, int bid) {
+    constexpr int NPX = kBwCols / 2 + 2;
+    __shared__ float sR[kBwWaves][kBwRing][kBwCols];
+    const int cgrp = bid % a.n_cgrp, rest = bid / a.n_cgrp;
+    const int ct = rest % a.n_ct, band = rest / a.n_ct;
+    const int t = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index: uniform
+    const int R0 = band * a.TR, R1 = min(R0 + a.TR, a.h);
+    const int C0 = ct * kBwCols, Cend = min(C0 + kBwCols, a.w);
+    const int c = cgrp * kBwWaves + wv;
+    if (c >= a.gxc * a.gyc) return;
+    const int cb = c / a.gxc, ca = c - cb * a.gxc;
+    const uint8_t *vxp = vtab(vt, g, a.l, 0), *vyp = vtab(vt, g, a.l, 1);
+    const uint8_t *vxc = vtab(vt, g, a.l - 1, 0), *vyc = vtab(vt, g, a.l - 1, 1);
+    const int rx = C0 + t;
+    const bool lane_o = rx < Cend;
+    const size_t obase = (size_t)c * a.h * a.w;
+    if (!(vxc[ca] && vyc[cb])) {   // no child here: its gradient is 0
+        for (int ry = R0; ry < R1; ++ry)
+            if (lane_o) gp_prev[obase + (size_t)ry * a.w + rx] = 0.f;
+        return;
+    }
+    const int usz = a.hu * a.wu, nparent = a.gxp * a.gyp;
+    const __amdgpu_buffer_rsrc_t rsG = rsrc(gp_cur, nparent * usz * 4), rsM = rsrc(code_cur, nparent * usz);
+    const __amdgpu_buffer_rsrc_t rsC = rsrc(cp_prev, a.gxc * a.gyc * a.h * a.w * 4);
+    int pbase[4];
+    float inv[4];
+#pragma unroll
+    for (int side = 0; side < 4; ++side) {
+        const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;   // o_i, i = side
+        const int pb = parent_index(a.l, cb, sy), pa = parent_index(a.l, ca, sx);
+        const bool ok = pb >= 0 && pb < a.gyp && pa >= 0 && pa < a.gxp && vxp[pa] && vyp[pb];
+        pbase[side] = ok ? (pb * a.gxp + pa) * usz : -1;
+        int nx = 0, ny = 0;
+        if (ok) {
+            for (int s2 = -1; s2 <= 1; s2 += 2) {
+                const int ccx = child_index(a.l, pa, s2), ccy = child_index(a.l, pb, s2);
+                nx += ccx >= 0 && ccx < a.gxc && vxc[ccx];
+                ny += ccy >= 0 && ccy < a.gyc && vyc[ccy];
+            }
+        }
+        inv[side] = ok ? 1.f / float(nx * ny) : 0.f;
+    }
+    float (*ring)[kBwCols] = sR[wv];
+    for (int e = t; e < kBwRing * kBwCols; e += 64) (&ring[0][0])[e] = 0.f;
+    wave_sync();
+    const int ux = (C0 >> 1) - 1 + t;          // the lane's pooled column while adding
+    const bool lane_u = t < NPX && ux >= 0 && ux < a.wu;
+    struct RowBuf { float g[4]; int m[4]; };
+    struct OutBuf { float acc[2]; float cv[2]; };
+    auto load_row = [&](int rp, RowBuf& b) {
+        const bool rok = lane_u && rp >= 0 && rp < a.hu;
+#pragma unroll
+        for (int side = 0; side < 4; ++side) {
+            const bool ok = rok && pbase[side] >= 0;
+            const int off = pbase[side] + rp * a.wu + ux;   // used only when ok
+            const float v = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsG, ok ? off * 4 : kOOB, 0, 0));
+            const int m = __builtin_amdgcn_raw_buffer_load_b8(rsM, ok ? off : kOOB, 0, 0);
+            b.g[side] = ok ? v : 0.f;
+            b.m[side] = m;
+        }
+    };
+    auto add_row = [&](int rp, const RowBuf& b) {
+#pragma unroll
+        for (int side = 0; side < 4; ++side) {
+            if (pbase[side] < 0) continue;
+            const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;
+            const int ry = 2 * rp + b.m[side] / 3 - 1 + sy, rxx = 2 * ux + b.m[side] % 3 - 1 + sx;
+            const bool hit = b.g[side] != 0.f && ry >= R0 && ry < R1 && rxx >= C0 && rxx < Cend;
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+                if (hit && (ux & 1) == pass) ring[ry % kBwRing][rxx - C0] += b.g[side] * inv[side];
+                wave_sync();
+            }
+        }
+    };
+    auto collect = [&](int rp, OutBuf& o) {
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            const int ry = 2 * rp - 2 + dy;
+            float acc = 0.f;
+            if (ry >= R0 && ry < R1 && lane_o) {
+                acc = ring[ry % kBwRing][t];
+                ring[ry % kBwRing][t] = 0.f;
+            }
+            o.acc[dy] = acc;
+            const int off = ry * a.w + rx;   // used only where acc != 0
+            o.cv[dy] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                rsC, acc != 0.f ? (int)(obase + off) * 4 : kOOB, 0, 0));
+        }
+    };
+    auto finish = [&](int rp, const OutBuf& o) {
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            const int ry = 2 * rp - 2 + dy;
+            if (ry < R0 || ry >= R1 || !lane_o) continue;
+            gp_prev[obase + (size_t)ry * a.w + rx] = o.acc[dy] * rect_grad_factor(o.cv[dy], lam);
+        }
+    };
+    const int rpa = (R0 - 2) >> 1, rp1 = ((R1 - 1) >> 1) + 1;
+    RowBuf b0, b1;
+    OutBuf o0, o1;
+    o1.acc[0] = o1.acc[1] = 0.f;
+    o1.cv[0] = o1.cv[1] = 0.f;
+    load_row(rpa, b0);
+    int rp = rpa;
+    for (;;) {
+        load_row(rp + 1, b1);
+        add_row(rp, b0);
+        collect(rp, o0);
+        finish(rp - 1, o1);
+        wave_sync();
+        if (rp == rp1) {
+            finish(rp, o0);
+            break;
+        }
+        ++rp;
+        load_row(rp + 1, b0);
+        add_row(rp, b1);
+        collect(rp, o1);
+        finish(rp - 1, o0);
+        wave_sync();
+        if (rp == rp1) {
+            finish(rp, o1);
+            break;
+        }
+        ++rp;
+    }
+}
+
+__global__ __launch_bounds__(64 * kBwWaves) void k_bwd_level_stream(BwStreamArgs a, const float* __restrict__ gp_cur,
+                                                                     const uint8_t* __restrict__ code_cur,
+                                                                     const float* __restrict__ cp_prev,
+                                                                     const uint8_t* __restrict__ vt, Geom g, float lam,
+                                                                     float* __restrict__ gp_prev, int nblocks) {
+    const int bid = xcd_block(nblocks);
+    if (bid >= nblocks) return;
+    bwd_level_stream_body(a, gp_cur, code_cur, cp_prev, vt, g, lam, gp_prev, bid);
+}
+
+struct BwdLevelStreamJob {
+    BwStreamArgs a;
+    const float* gp_cur;
+    const uint8_t* code_cur;
+    const float* cp_prev;
+    const uint8_t* vt;
+    Geom g;
+    float lam;
+    float* gp_prev;
+    static __device__ void run(const BwdLevelStreamJob& j, int v) {
+        bwd_level_stream_body(j.a, j.gp_cur, j.code_cur, j.cp_prev, j.vt, j.g, j.lam, j.gp_prev, v);
+    }
+};
+
+// The streaming form serves FP32 steps below the top whose child maps are at
+// least 32 columns wide and whose arrays stay below 2^31 bytes.
+bool use_bwd_stream(int l, const Geom& g) {
+    if (l == g.lmax || g.w[l] < 32) return false;
+    return (double)g.gx[l] * g.gy[l] * g.h[l + 1] * g.w[l + 1] * 4 < 2.0e9 &&
+           (double)g.gx[l - 1] * g.gy[l - 1] * g.h[l] * g.w[l] * 4 < 2.0e9;
+}
+
+BwStreamArgs make_bwd_stream_args(int l, const Geom& g, int& nblocks) {
+    BwStreamArgs b;
+    b.l = l;
+    b.gxp = g.gx[l];
+    b.gyp = g.gy[l];
+    b.gxc = g.gx[l - 1];
+    b.gyc = g.gy[l - 1];
+    b.h = g.h[l];
+    b.w = g.w[l];
+    b.hu = g.h[l + 1];
+    b.wu = g.w[l + 1];
+    b.TR = b.h < 32 ? ((b.h + 1) & ~1) : 32;
+    b.n_band = (b.h + b.TR - 1) / b.TR;
+    b.n_ct = (b.w + kBwCols - 1) / kBwCols;
+    b.n_cgrp = (b.gxc * b.gyc + kBwWaves - 1) / kBwWaves;
+    nblocks = b.n_cgrp * b.n_ct * b.n_band;
+    return b;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_bwd_level(BwdArgs a, const T* __restrict__ dtop, const T* __restrict__ top,
                                                    const T* __restrict__ gp_cur, const uint8_t* __restrict__ code_cur,
@@ -265,6 +489,12 @@ BwdArgs make_bwd_args(int l, const Geom& g, int& nblocks, size_t& smem) {
 JobRec bwd_level_job(int l, const float* dtop, const float* top, const float* gp_cur, const uint8_t* code_cur,
                      const float* cp_prev, const uint8_t* vt, const Geom& g, float lam, float* gp_prev) {
     int nb;
+    if (use_bwd_stream(l, g)) {
+        const BwStreamArgs b = make_bwd_stream_args(l, g, nb);
+        JobRec r;
+        r.set(JK_BWD_LEVEL_STREAM, nb, 0, BwdLevelStreamJob{b, gp_cur, code_cur, cp_prev, vt, g, lam, gp_prev});
+        return r;
+    }
     size_t smem;
     const BwdArgs a = make_bwd_args(l, g, nb, smem);
     JobRec r;
@@ -282,6 +512,7 @@ JobRec top_grad_job(const float* top, const Geom& g, float* dtop) {
 hipError_t launch_group_bwd(int kind, const GroupLaunch& gl, hipStream_t s) {
     switch (kind) {
         case JK_BWD_LEVEL: return launch_grouped<BwdLevelJob, 256, 1>(gl, s);
+        case JK_BWD_LEVEL_STREAM: return launch_grouped<BwdLevelStreamJob, 64 * kBwWaves, 1>(gl, s);
         case JK_TOP_GRAD: return launch_grouped<TopGradJob, 256, 1>(gl, s);
         default: return hipErrorInvalidValue;
     }
@@ -290,6 +521,15 @@ hipError_t launch_group_bwd(int kind, const GroupLaunch& gl, hipStream_t s) {
 template <typename T>
 hipError_t launch_bwd_level(int l, const T* dtop, const T* top, const T* gp_cur, const uint8_t* code_cur,
                             const T* cp_prev, const uint8_t* vt, const Geom& g, T lam, T* gp_prev, hipStream_t s) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (use_bwd_stream(l, g)) {
+            int nb;
+            const BwStreamArgs b = make_bwd_stream_args(l, g, nb);
+            hipLaunchKernelGGL(k_bwd_level_stream, dim3(((nb + 7) / 8) * 8), dim3(64 * kBwWaves), 0, s, b, gp_cur,
+                               code_cur, cp_prev, vt, g, lam, gp_prev, nb);
+            return hipGetLastError();
+        }
+    }
     BwdArgs a;
     a.l = l;
     a.gxp = g.gx[l];

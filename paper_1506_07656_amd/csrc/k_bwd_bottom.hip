@@ -104,18 +104,19 @@ __device__ inline void store8(E* dst, const float v[8]) {
 }
 
 // ---------------------------------------------------------------- dense dA_0
-// Block: one patch x 8 target rows x 256 target columns of the padded grid.
-// The pooled entries whose windows reach the tile (6 rows x 130 columns) are
-// staged in LDS; each thread forms 8 consecutive outputs of one row, summing
-// its candidates in the order of dA_at (pooled row, then pooled column).
-constexpr int DA_ROWS = 8, DA_COLS = 256, DA_SR = 6, DA_SC = DA_COLS / 2 + 2;
+// Block: one patch x 32 target rows x 256 target columns of the padded grid.
+// The pooled entries whose windows reach the tile (18 rows x 130 columns)
+// are staged in LDS; each thread forms 8 consecutive outputs in each of 4
+// rows, summing its candidates in the order of dA_at (pooled row, then
+// pooled column).
+constexpr int DA_ROWS = 32, DA_COLS = 256, DA_SR = DA_ROWS / 2 + 2, DA_SC = DA_COLS / 2 + 2;
 
 template <typename E>
 __device__ inline void bwd_da_body(const float* __restrict__ gp, const uint8_t* __restrict__ code, const BotArgs& a,
                                    int nct, E* __restrict__ dA, int bid) {
     __shared__ float sg[DA_SR][DA_SC];
     __shared__ int sm[DA_SR][DA_SC];
-    const int nband = a.H2p / DA_ROWS;
+    const int nband = (a.H2p + DA_ROWS - 1) / DA_ROWS;
     const int ct = bid % nct, rest = bid / nct, band = rest % nband, p = rest / nband;
     const int Y0 = band * DA_ROWS, X0 = ct * DA_COLS;
     const int ry0 = (Y0 >> 1) - 1, rx0 = (X0 >> 1) - 1;
@@ -134,9 +135,11 @@ __device__ inline void bwd_da_body(const float* __restrict__ gp, const uint8_t* 
         sm[i][j] = m;
     }
     __syncthreads();
-    const int row = threadIdx.x >> 5, grp = threadIdx.x & 31;
-    const int y = Y0 + row, xb = X0 + 8 * grp;
+    const int grp = threadIdx.x & 31, xb = X0 + 8 * grp;
     if (xb >= a.Wp) return;
+    for (int row = threadIdx.x >> 5; row < DA_ROWS; row += 8) {
+    const int y = Y0 + row;
+    if (y >= a.H2p) break;
     float out[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) out[q] = 0.f;
@@ -159,6 +162,7 @@ __device__ inline void bwd_da_body(const float* __restrict__ gp, const uint8_t* 
         }
     }
     store8<E>(dA + (size_t)p * a.Xp + (size_t)y * a.Wp + xb, out);
+    }
 }
 
 // Transposed im2col of D2: D2colT[k][x] = D2[x + d_k][c_k] on the padded grid.
@@ -516,10 +520,19 @@ __global__ void k_bwd_col2im_ref(const T* __restrict__ tbuf, BotArgs a, T* __res
 }
 
 // ---------------------------------------------------------------- kernels and jobs
+// Blocks are dealt to the 8 XCDs round-robin; renumber them so that each XCD
+// works through one contiguous range (GEMM 1: the patch tiles of one K split
+// share its slice of the im2col operand in that XCD's L2).
+__device__ inline int xcd_block(int nblocks) {
+    const int per = (nblocks + 7) / 8;
+    return (blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
 template <typename E>
 __global__ __launch_bounds__(256) void k_bwd_da(const float* __restrict__ gp, const uint8_t* __restrict__ code,
-                                                BotArgs a, int nct, E* __restrict__ dA) {
-    bwd_da_body<E>(gp, code, a, nct, dA, blockIdx.x);
+                                                BotArgs a, int nct, E* __restrict__ dA, int nblocks) {
+    const int bid = xcd_block(nblocks);
+    if (bid < nblocks) bwd_da_body<E>(gp, code, a, nct, dA, bid);
 }
 template <typename E>
 __global__ __launch_bounds__(256) void k_bwd_d2col(const float* __restrict__ d2, BotArgs a, E* __restrict__ d2colT) {
@@ -532,14 +545,16 @@ __global__ __launch_bounds__(256) void k_bwd_pt(const float* __restrict__ d1, Bo
 template <bool BF16>
 __global__ __launch_bounds__(256) void k_bwd_gemm1(const typename Op<BF16>::E* __restrict__ dA,
                                                    const typename Op<BF16>::E* __restrict__ d2colT, BotArgs a,
-                                                   int nsplit, float* __restrict__ part) {
-    bwd_gemm1_body<BF16>(dA, d2colT, a, nsplit, part, blockIdx.x);
+                                                   int nsplit, float* __restrict__ part, int nblocks) {
+    const int bid = xcd_block(nblocks);
+    if (bid < nblocks) bwd_gemm1_body<BF16>(dA, d2colT, a, nsplit, part, bid);
 }
 template <bool BF16>
 __global__ __launch_bounds__(256) void k_bwd_gemm2(const typename Op<BF16>::E* __restrict__ dA,
                                                    const typename Op<BF16>::E* __restrict__ PT, BotArgs a,
-                                                   float* __restrict__ tt) {
-    bwd_gemm2_body<BF16>(dA, PT, a, tt, blockIdx.x);
+                                                   float* __restrict__ tt, int nblocks) {
+    const int bid = xcd_block(nblocks);
+    if (bid < nblocks) bwd_gemm2_body<BF16>(dA, PT, a, tt, bid);
 }
 template <typename T>
 __global__ __launch_bounds__(256) void k_bwd_dd1_reduce(const T* __restrict__ part, BotArgs a, int nsplit,
@@ -620,6 +635,7 @@ BotArgs make_bot(const Geom& g) {
 }
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+inline unsigned g8(int nblocks) { return (unsigned)(((nblocks + 7) / 8) * 8); }
 
 // Byte offsets of dA_0, D2colT and PT inside the dense scratch region.
 struct DenseLayout {
@@ -659,7 +675,7 @@ BotPlan bot_plan(const Geom& g) {
     b.a = make_bot(g);
     b.ns = bwd_nsplit(g);
     b.nct = (b.a.Wp + DA_COLS - 1) / DA_COLS;
-    b.da_blocks = b.a.Pp * (b.a.H2p / DA_ROWS) * b.nct;
+    b.da_blocks = b.a.Pp * ((b.a.H2p + DA_ROWS - 1) / DA_ROWS) * b.nct;
     b.d2_blocks = (int)(((size_t)144 * (b.a.Xp / 8) + 255) / 256);
     b.pt_blocks = (int)(((size_t)144 * (b.a.Pp / 8) + 255) / 256);
     b.g1_blocks = (b.a.Pp / G1M) * b.ns;
@@ -757,20 +773,26 @@ hipError_t launch_bwd_bottom(int mode, const T* gp, const uint8_t* code, const T
             uint16_t* dA = (uint16_t*)(base + d.da);
             uint16_t* dc = (uint16_t*)(base + d.d2col);
             uint16_t* pt = (uint16_t*)(base + d.pt);
-            DM_SUB("bwd_da", k_bwd_da<uint16_t>, dim3(b.da_blocks), dim3(256), 0, s, gp, code, a, b.nct, dA);
+            DM_SUB("bwd_da", k_bwd_da<uint16_t>, dim3(g8(b.da_blocks)), dim3(256), 0, s, gp, code, a, b.nct, dA,
+                   b.da_blocks);
             DM_SUB("bwd_d2col", k_bwd_d2col<uint16_t>, dim3(b.d2_blocks), dim3(256), 0, s, d2, a, dc);
             DM_SUB("bwd_pt", k_bwd_pt<uint16_t>, dim3(b.pt_blocks), dim3(256), 0, s, d1, a, pt);
-            DM_SUB("bwd_dd1_gemm", k_bwd_gemm1<true>, dim3(b.g1_blocks), dim3(256), 0, s, dA, dc, a, b.ns, part);
-            DM_SUB("bwd_t_gemm", k_bwd_gemm2<true>, dim3(b.g2_blocks), dim3(256), 0, s, dA, pt, a, tbuf);
+            DM_SUB("bwd_dd1_gemm", k_bwd_gemm1<true>, dim3(g8(b.g1_blocks)), dim3(256), 0, s, dA, dc, a, b.ns, part,
+                   b.g1_blocks);
+            DM_SUB("bwd_t_gemm", k_bwd_gemm2<true>, dim3(g8(b.g2_blocks)), dim3(256), 0, s, dA, pt, a, tbuf,
+                   b.g2_blocks);
         } else {
             float* dA = (float*)(base + d.da);
             float* dc = (float*)(base + d.d2col);
             float* pt = (float*)(base + d.pt);
-            DM_SUB("bwd_da", k_bwd_da<float>, dim3(b.da_blocks), dim3(256), 0, s, gp, code, a, b.nct, dA);
+            DM_SUB("bwd_da", k_bwd_da<float>, dim3(g8(b.da_blocks)), dim3(256), 0, s, gp, code, a, b.nct, dA,
+                   b.da_blocks);
             DM_SUB("bwd_d2col", k_bwd_d2col<float>, dim3(b.d2_blocks), dim3(256), 0, s, d2, a, dc);
             DM_SUB("bwd_pt", k_bwd_pt<float>, dim3(b.pt_blocks), dim3(256), 0, s, d1, a, pt);
-            DM_SUB("bwd_dd1_gemm", k_bwd_gemm1<false>, dim3(b.g1_blocks), dim3(256), 0, s, dA, dc, a, b.ns, part);
-            DM_SUB("bwd_t_gemm", k_bwd_gemm2<false>, dim3(b.g2_blocks), dim3(256), 0, s, dA, pt, a, tbuf);
+            DM_SUB("bwd_dd1_gemm", k_bwd_gemm1<false>, dim3(g8(b.g1_blocks)), dim3(256), 0, s, dA, dc, a, b.ns, part,
+                   b.g1_blocks);
+            DM_SUB("bwd_t_gemm", k_bwd_gemm2<false>, dim3(g8(b.g2_blocks)), dim3(256), 0, s, dA, pt, a, tbuf,
+                   b.g2_blocks);
         }
         DM_SUB("bwd_dd1_reduce", k_bwd_dd1_reduce<float>, dim3(b.red_blocks), dim3(256), 0, s, part, a, b.ns, dd1);
         DM_SUB("bwd_col2im", k_bwd_col2im, dim3(b.c2i_blocks), dim3(256), 0, s, tbuf, a, dd2);
