@@ -291,8 +291,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the run, copy 1 GiB device to device (calibrates HBM byte counters)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-pair uneven batch")
-    ap.add_argument("--only", choices=("all", "fwd_bf16"), default="all",
-                    help="fwd_bf16: run only the BF16 forward (short profiler runs); prints no JSON line")
+    ap.add_argument("--only", choices=("all", "fwd_bf16", "fwd_bwd_bf16"), default="all",
+                    help="fwd_bf16 / fwd_bwd_bf16: run only that pass (short profiler runs); prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the matcher has no multi-GPU path, "
@@ -310,6 +310,11 @@ def main():
         if args.copy_probe:
             copy_probe(torch)
         print(f"bf16 forward: {dt * 1e3:.3f} ms/pair", flush=True)
+        return
+    if args.only == "fwd_bwd_bf16":
+        d1, d2 = dm.descriptors(img1), dm.descriptors(img2)
+        dt, _ = time_fwd_bwd(dm, torch, d1, d2, "bf16", False, args.steps, args.warmup)
+        print(f"bf16 forward + backward: {dt * 1e3:.3f} ms/pair", flush=True)
         return
     res = {}
     for prec in ("fp32", "bf16"):

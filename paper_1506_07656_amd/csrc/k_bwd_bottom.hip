@@ -35,6 +35,9 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+// Native 16-byte vector: copies are plain loads and stores, never memcpy of a
+// struct, so arrays of them stay in registers.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 struct BotArgs {
     int W1, H1, W2, H2, n0x, natom, h1, w1;
@@ -109,7 +112,7 @@ __device__ inline void store8(E* dst, const float v[8]) {
 // are staged in LDS; each thread forms 8 consecutive outputs in each of 4
 // rows, summing its candidates in the order of dA_at (pooled row, then
 // pooled column).
-constexpr int DA_ROWS = 32, DA_COLS = 256, DA_SR = DA_ROWS / 2 + 2, DA_SC = DA_COLS / 2 + 2;
+constexpr int DA_ROWS = 32, DA_COLS = 256, DA_SR = DA_ROWS / 2 + 2, DA_SC = DA_COLS / 2 + 4;   // rows 16-byte aligned
 
 template <typename E>
 __device__ inline void bwd_da_body(const float* __restrict__ gp, const uint8_t* __restrict__ code, const BotArgs& a,
@@ -121,7 +124,7 @@ __device__ inline void bwd_da_body(const float* __restrict__ gp, const uint8_t* 
     const int Y0 = band * DA_ROWS, X0 = ct * DA_COLS;
     const int ry0 = (Y0 >> 1) - 1, rx0 = (X0 >> 1) - 1;
     const size_t pm = (size_t)a.h1 * a.w1;
-    for (int e = threadIdx.x; e < DA_SR * DA_SC; e += 256) {
+    for (int e = threadIdx.x; e < DA_SR * DA_SC; e += 256) {   // (the last 2 columns of a row are never read)
         const int i = e / DA_SC, j = e - i * DA_SC;
         const int ry = ry0 + i, rx = rx0 + j;
         float g = 0.f;
@@ -144,19 +147,28 @@ __device__ inline void bwd_da_body(const float* __restrict__ gp, const uint8_t* 
 #pragma unroll
     for (int q = 0; q < 8; ++q) out[q] = 0.f;
     if (y < a.H2) {
+        // the lane's outputs x = xb..xb+7 take pooled columns j0..j0+5, j0 = 4 grp (16-byte aligned)
+        const int j0 = 4 * grp;
         for (int ry = (y - 1) >> 1; ry <= (y + 1) >> 1; ++ry) {
             const int my = y - 2 * ry;
             if (my < -1 || my > 1) continue;
             const int i = ry - ry0;
+            const float4 g4 = *reinterpret_cast<const float4*>(&sg[i][j0]);
+            const float2 g2 = *reinterpret_cast<const float2*>(&sg[i][j0 + 4]);
+            const int4 m4 = *reinterpret_cast<const int4*>(&sm[i][j0]);
+            const int2 m2 = *reinterpret_cast<const int2*>(&sm[i][j0 + 4]);
+            const float gv[6] = {g4.x, g4.y, g4.z, g4.w, g2.x, g2.y};
+            const int mv[6] = {m4.x, m4.y, m4.z, m4.w, m2.x, m2.y};
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int x = xb + q;
-                if (x >= a.W2) continue;
-                for (int rx = (x - 1) >> 1; rx <= (x + 1) >> 1; ++rx) {
-                    const int mx = x - 2 * rx;
-                    if (mx < -1 || mx > 1) continue;
-                    const int j = rx - rx0;
-                    if (sm[i][j] == 3 * (my + 1) + (mx + 1)) out[q] += sg[i][j];
+                // pooled columns (x-1)>>1 and (x+1)>>1, relative to j0: (q-1)>>1 + 1 and (q+1)>>1 + 1
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    const int jj = d == 0 ? ((q - 1) >> 1) + 1 : ((q + 1) >> 1) + 1;
+                    const int mx = q - 2 * (jj - 1);                  // x - 2 rx, with rx = X0/2 + 4 grp + jj - 1
+                    if (mx < -1 || mx > 1) continue;                  // q even: only the second candidate
+                    if (x < a.W2 && mv[jj] == 3 * (my + 1) + (mx + 1)) out[q] += gv[jj];
                 }
             }
         }
@@ -208,7 +220,7 @@ struct Op {
 
 // C[M=128 patches][N=144] += A[M][K] * B[N][K]^T over the chunks of one split.
 template <bool BF16>
-__device__ inline void bwd_gemm1_body(const typename Op<BF16>::E* __restrict__ dA,
+__device__ __forceinline__ void bwd_gemm1_body(const typename Op<BF16>::E* __restrict__ dA,
                                       const typename Op<BF16>::E* __restrict__ d2colT, const BotArgs& a, int nsplit,
                                       float* __restrict__ part, int bid) {
     typedef Op<BF16> O;
@@ -222,39 +234,48 @@ __device__ inline void bwd_gemm1_body(const typename Op<BF16>::E* __restrict__ d
     const int k_begin = split * kper, k_end = min(a.Xp, k_begin + kper);
     const int P0 = ptile * G1M;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
-    uint4 ra[NA], rb[NB];
-    auto load = [&](int k0) {
+    // Prefetch registers, filled by unconditional loads (rows of the B chunk
+    // past its 144 are clamped and not stored): they must stay in VGPRs.
+    u32x4 ra[NA], rb[NB];
+    size_t aoff[NA], boff[NB];   // element offsets of each vector's row at chunk start 0
+    int aidx[NA], bidx[NB];   // LDS destinations (element index), -1 = none
 #pragma unroll
-        for (int i = 0; i < NA; ++i) {
-            const int v = tid + 256 * i, r = v / O::CV, c = v - r * O::CV;
-            ra[i] = *reinterpret_cast<const uint4*>(dA + (size_t)(P0 + r) * a.Xp + k0 + c * O::VPR);
-        }
+    for (int i = 0; i < NA; ++i) {
+        const int v = tid + 256 * i, r = v / O::CV, c = v - r * O::CV;
+        aoff[i] = (size_t)(P0 + r) * a.Xp + c * O::VPR;
+        aidx[i] = r * (GK + O::PAD) + c * O::VPR;
+    }
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const int v = tid + 256 * i, r = v / O::CV, c = v - r * O::CV;
-            if (v < 144 * O::CV) rb[i] = *reinterpret_cast<const uint4*>(d2colT + (size_t)r * a.Xp + k0 + c * O::VPR);
-        }
-    };
+    for (int i = 0; i < NB; ++i) {
+        const int v = tid + 256 * i, vc = min(v, 144 * O::CV - 1), r = vc / O::CV, c = vc - r * O::CV;
+        boff[i] = (size_t)r * a.Xp + c * O::VPR;
+        bidx[i] = v < 144 * O::CV ? r * (GK + O::PAD) + c * O::VPR : -1;
+    }
     f4 acc[2][9];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 9; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
-    if (k_begin < k_end) load(k_begin);
+    if (k_begin < k_end) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) ra[i] = *reinterpret_cast<const u32x4*>(dA + aoff[i] + k_begin);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) rb[i] = *reinterpret_cast<const u32x4*>(d2colT + boff[i] + k_begin);
+    }
     for (int k0 = k_begin; k0 < k_end; k0 += GK) {
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < NA; ++i) {
-            const int v = tid + 256 * i, r = v / O::CV, c = v - r * O::CV;
-            *reinterpret_cast<uint4*>(&sA[r][c * O::VPR]) = ra[i];
-        }
+        for (int i = 0; i < NA; ++i) *reinterpret_cast<u32x4*>(&sA[0][0] + aidx[i]) = ra[i];
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const int v = tid + 256 * i, r = v / O::CV, c = v - r * O::CV;
-            if (v < 144 * O::CV) *reinterpret_cast<uint4*>(&sB[r][c * O::VPR]) = rb[i];
-        }
+        for (int i = 0; i < NB; ++i)
+            if (bidx[i] >= 0) *reinterpret_cast<u32x4*>(&sB[0][0] + bidx[i]) = rb[i];
         __syncthreads();
-        if (k0 + GK < k_end) load(k0 + GK);   // next chunk in flight during the MFMAs
+        if (k0 + GK < k_end) {   // next chunk in flight during the MFMAs
+#pragma unroll
+            for (int i = 0; i < NA; ++i) ra[i] = *reinterpret_cast<const u32x4*>(dA + aoff[i] + k0 + GK);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) rb[i] = *reinterpret_cast<const u32x4*>(d2colT + boff[i] + k0 + GK);
+        }
         if constexpr (BF16) {
 #pragma unroll
             for (int s = 0; s < GK / 32; ++s) {
@@ -318,7 +339,7 @@ __device__ inline void bwd_dd1_reduce_body(const T* __restrict__ part, const Bot
 // 8 x 8 (BF16) or 4 x 4 (FP32) blocks transposed so that LDS holds it as
 // [position][patch]; the PT chunk is copied as it is.
 template <bool BF16>
-__device__ inline void bwd_gemm2_body(const typename Op<BF16>::E* __restrict__ dA,
+__device__ __forceinline__ void bwd_gemm2_body(const typename Op<BF16>::E* __restrict__ dA,
                                       const typename Op<BF16>::E* __restrict__ PT, const BotArgs& a,
                                       float* __restrict__ tt, int bid) {
     typedef Op<BF16> O;
@@ -332,78 +353,84 @@ __device__ inline void bwd_gemm2_body(const typename Op<BF16>::E* __restrict__ d
     constexpr int BR = BF16 ? 8 : 4, NBLK = BF16 ? 1 : 2;
     constexpr int NTH_A = BF16 ? 128 : 256, NTH_P = BF16 ? 128 : 256;   // threads per role
     constexpr int NPT = (144 * O::CV + NTH_P - 1) / NTH_P;             // PT vectors per thread
-    uint4 rd[NBLK][BR];
-    uint4 rp[NPT];
+    // Prefetch registers, filled by unconditional loads (PT rows past 144 are
+    // clamped and not stored) so that they stay in VGPRs.
+    u32x4 rd[NBLK][BR];
+    u32x4 rp[NPT];
     const bool loader_a = BF16 ? tid < 128 : true;    // wave-uniform
     const bool loader_p = BF16 ? tid >= 128 : true;
     const int tp = BF16 ? tid - 128 : tid;
-    auto load = [&](int p0) {
-        if (loader_a) {
+    const E* dsrc[NBLK];   // first dA row of this thread's block at chunk start 0
+    int dcol[NBLK], drow[NBLK];
 #pragma unroll
-            for (int b = 0; b < NBLK; ++b) {
-                const int blk = tid + NTH_A * b;                     // BF16: 8 x 16 blocks; FP32: 16 x 32
-                const int xbn = G2N / BR, pb = blk / xbn, xb = blk - pb * xbn;
+    for (int b = 0; b < NBLK; ++b) {
+        // patch block fastest: each LDS row gets contiguous stores
+        const int blk = (loader_a ? tid : 0) + NTH_A * b;
+        const int pbn = GK / BR, xb = blk / pbn, pb = blk - xb * pbn;
+        dsrc[b] = dA + (size_t)(BR * pb) * a.Xp + X0 + BR * xb;
+        drow[b] = BR * xb;
+        dcol[b] = BR * pb;
+    }
+    const E* psrc[NPT];
+    int pidx[NPT];
 #pragma unroll
-                for (int i = 0; i < BR; ++i)
-                    rd[b][i] = *reinterpret_cast<const uint4*>(dA + (size_t)(p0 + BR * pb + i) * a.Xp + X0 + BR * xb);
-            }
-        }
-        if (loader_p) {
-#pragma unroll
-            for (int i = 0; i < NPT; ++i) {
-                const int v = tp + NTH_P * i, r = v / O::CV, c = v - r * O::CV;
-                if (v < 144 * O::CV) rp[i] = *reinterpret_cast<const uint4*>(PT + (size_t)r * a.Pp + p0 + c * O::VPR);
-            }
-        }
-    };
-    auto store = [&]() {
-        if (loader_a) {
-#pragma unroll
-            for (int b = 0; b < NBLK; ++b) {
-                const int blk = tid + NTH_A * b;
-                const int xbn = G2N / BR, pb = blk / xbn, xb = blk - pb * xbn;
-                if constexpr (BF16) {
-                    // rd[b][i] = 8 bf16 of patch row i (positions 2j, 2j+1 in dword j);
-                    // column q (position) = 8 patches, packed 2 per dword.
-                    const uint32_t* w = reinterpret_cast<const uint32_t*>(rd[b]);   // w[4 i + j]
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        uint32_t o[4];
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const uint32_t lo = w[4 * (2 * j) + (q >> 1)], hi = w[4 * (2 * j + 1) + (q >> 1)];
-                            o[j] = (q & 1) ? ((lo >> 16) | (hi & 0xFFFF0000u)) : ((lo & 0xFFFFu) | (hi << 16));
-                        }
-                        *reinterpret_cast<uint4*>(&sB[BR * xb + q][BR * pb]) = make_uint4(o[0], o[1], o[2], o[3]);
-                    }
-                } else {
-                    const uint32_t* w = reinterpret_cast<const uint32_t*>(rd[b]);   // w[4 i + q]
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        *reinterpret_cast<uint4*>(&sB[BR * xb + q][BR * pb]) =
-                            make_uint4(w[q], w[4 + q], w[8 + q], w[12 + q]);
-                }
-            }
-        }
-        if (loader_p) {
-#pragma unroll
-            for (int i = 0; i < NPT; ++i) {
-                const int v = tp + NTH_P * i, r = v / O::CV, c = v - r * O::CV;
-                if (v < 144 * O::CV) *reinterpret_cast<uint4*>(&sA[r][c * O::VPR]) = rp[i];
-            }
-        }
-    };
+    for (int i = 0; i < NPT; ++i) {
+        const int v = (loader_p ? tp : 0) + NTH_P * i, vc = min(v, 144 * O::CV - 1), r = vc / O::CV,
+                  c = vc - r * O::CV;
+        psrc[i] = PT + (size_t)r * a.Pp + c * O::VPR;
+        pidx[i] = v < 144 * O::CV ? r * (GK + O::PAD) + c * O::VPR : -1;
+    }
     f4 acc[9][2];
 #pragma unroll
     for (int mt = 0; mt < 9; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
-    load(0);
+#define DM_G2_LOAD(P0_)                                                                              \
+    do {                                                                                             \
+        if (loader_a) {                                                                              \
+            _Pragma("unroll") for (int b = 0; b < NBLK; ++b)                                         \
+                _Pragma("unroll") for (int i = 0; i < BR; ++i) rd[b][i] =                            \
+                    *reinterpret_cast<const u32x4*>(dsrc[b] + (size_t)((P0_) + i) * a.Xp);           \
+        }                                                                                            \
+        if (loader_p) {                                                                              \
+            _Pragma("unroll") for (int i = 0; i < NPT; ++i) rp[i] =                                  \
+                *reinterpret_cast<const u32x4*>(psrc[i] + (P0_));                                    \
+        }                                                                                            \
+    } while (0)
+    DM_G2_LOAD(0);
     for (int p0 = 0; p0 < a.Pp; p0 += GK) {
         __syncthreads();
-        store();
+        if (loader_a) {
+#pragma unroll
+            for (int b = 0; b < NBLK; ++b) {
+                if constexpr (BF16) {
+                    // rd[b][i] = 8 bf16 of patch row i (positions 2j, 2j+1 in dword j);
+                    // column q (position) = 8 patches, packed 2 per dword.
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        u32x4 o;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const uint32_t lo = rd[b][2 * j][q >> 1], hi = rd[b][2 * j + 1][q >> 1];
+                            o[j] = (q & 1) ? ((lo >> 16) | (hi & 0xFFFF0000u)) : ((lo & 0xFFFFu) | (hi << 16));
+                        }
+                        *reinterpret_cast<u32x4*>(&sB[drow[b] + q][dcol[b]]) = o;
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        *reinterpret_cast<u32x4*>(&sB[drow[b] + q][dcol[b]]) =
+                            u32x4{rd[b][0][q], rd[b][1][q], rd[b][2][q], rd[b][3][q]};
+                }
+            }
+        }
+        if (loader_p) {
+#pragma unroll
+            for (int i = 0; i < NPT; ++i)
+                if (pidx[i] >= 0) *reinterpret_cast<u32x4*>(&sA[0][0] + pidx[i]) = rp[i];
+        }
         __syncthreads();
-        if (p0 + GK < a.Pp) load(p0 + GK);
+        if (p0 + GK < a.Pp) DM_G2_LOAD(p0 + GK);
         if constexpr (BF16) {
 #pragma unroll
             for (int s = 0; s < GK / 32; ++s) {
@@ -439,6 +466,7 @@ __device__ inline void bwd_gemm2_body(const typename Op<BF16>::E* __restrict__ d
             for (int j = 0; j < 4; ++j)
                 tt[(size_t)(16 * mt + 4 * g + j) * a.Xp + X0 + wave * 32 + nt * 16 + n] = acc[mt][nt][j];
 }
+#undef DM_G2_LOAD
 
 // dD2[y][c] = 1/16 sum_d T[(d, c)][y - d] on the padded grid (T is zero outside the target).
 __device__ inline void bwd_col2im_body(const float* __restrict__ tt, const BotArgs& a, float* __restrict__ dd2,
