@@ -213,6 +213,163 @@ struct EngineBF16 {
     }
 };
 
+// ---------------------------------------------------------------- BF16 sweep
+// Same band and step order as sweep_band, with two changes.
+//
+// Target tile: a tile row is one contiguous run of D2C pixels x 5 words of
+// the HWC bf16 layout, so each thread owns fixed (row, word) slots; the next
+// step's tile is fetched into registers while the current one is computed.
+//
+// Packed-key epilogue: each rectified value v (clamped below at 2^-126, whose
+// power is 0 in FP32 like that of 0) becomes the key
+//   (bits(v) with the low 4 mantissa bits cleared) | (15 - k)
+// for window position k.  Non-negative floats order like their bit patterns,
+// so the max over keys is the max over values, with equal values (and values
+// within 2^-19 of each other) going to the first position k: every pool
+// comparison is one integer max.  Positions outside I' keep only the position
+// bits and lose against every valid key.  The pooled value is the kept
+// 19-bit-mantissa maximum, well inside the rounding of the BF16 operands.
+constexpr int TILE_W = D2C * 5;                          // words per tile row
+constexpr int TILE_N = D2R * TILE_W;                     // words per tile
+constexpr int TILE_PER_T = (TILE_N + 255) / 256;         // words per thread
+constexpr int kOOB = 0x7ffffff0;                         // buffer byte offset past any buffer
+
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
+}
+
+// Keys of A-row ia of the step for this lane's 4 * MT patches: the row
+// maximum over the window columns k = 0, 1, 2 (odd column left of the lane's
+// pooled column, even column, odd column), each carrying 15 - k.
+__device__ __forceinline__ void row_keys(const EngineBF16& eng, const PoolArgs& a, int R0, int ia, int n,
+                                         uint32_t me, uint32_t mo, const float* cr, float* cw,
+                                         uint32_t (&rk)[MT][4]) {
+    const int y = 2 * R0 - 1 + ia;
+    const bool y_ok = y >= 0 && y < a.H2;
+    const uint32_t mE = y_ok ? me : 0u, mO = y_ok ? mo : 0u;
+    const int lo = 0x00800000;   // bits of 2^-126; as signed integers, floats below it (negatives too) are smaller
+    f4 accE[MT], accO[MT];
+    eng.mfma_row(ia, 2 * n, accE);
+    eng.mfma_row(ia, 2 * n + 1, accO);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t kE = ((uint32_t)max(__float_as_int(accE[mt][j]), lo) & mE) | 14u;   // k = 1
+            const uint32_t kO = ((uint32_t)max(__float_as_int(accO[mt][j]), lo) & mO) | 13u;   // k = 2
+            const uint32_t cin = __float_as_uint(cr[mt * 16 + j]);                           // O of column C0-1
+            const uint32_t kL =
+                (uint32_t)__builtin_amdgcn_update_dpp((int)cin, (int)kO, 0x111, 0xF, 0xF, false) | 15u;   // k = 0
+            cw[mt * 16 + j] = __uint_as_float(kO);
+            rk[mt][j] = max(max(kL, kE), kO);
+        }
+}
+
+__device__ inline void sweep_band_bf16(const bf8* fa, uint32_t* sD2, const uint32_t* __restrict__ d2,
+                                       const PoolArgs& a, int pt, int R0, float lam, float* __restrict__ cp,
+                                       uint8_t* __restrict__ code, float (*carry)[16 * MT], float* dummy) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n = lane & 15, grp = lane >> 4;
+    const int pbase = pt * PT + wave * 16 * MT;
+    const uint32_t mapsz = (uint32_t)a.h1 * a.w1;
+    // Output buffers of this wave's patches: patches past natom are out of range.
+    const uint32_t nmap = __builtin_amdgcn_readfirstlane(max(0, min(16 * MT, a.natom - pbase)) * (int)mapsz);
+    const auto rsC = buf_rsrc(cp + (size_t)pbase * mapsz, nmap * 4);
+    const auto rsK = buf_rsrc(code + (size_t)pbase * mapsz, nmap);
+    const auto rsD = buf_rsrc(d2, (uint32_t)a.H2 * a.W2 * 20);
+    // Tile slots of this thread.
+    int trow[TILE_PER_T], tword[TILE_PER_T];
+    bool tok[TILE_PER_T];
+    const int ybase = 2 * R0 - 3;
+#pragma unroll
+    for (int it = 0; it < TILE_PER_T; ++it) {
+        const int idx = tid + 256 * it;
+        trow[it] = idx / TILE_W;
+        tword[it] = idx - trow[it] * TILE_W;
+        const int y = ybase + trow[it];
+        tok[it] = idx < TILE_N && y >= 0 && y < a.H2;
+        trow[it] = y * a.W2 * 5;   // word offset of the target row
+    }
+    uint32_t tv[TILE_PER_T];
+    auto fetch = [&](int C0) {
+        const int xw = (2 * C0 - 2) * 5;   // word offset of the tile's first pixel within a row
+#pragma unroll
+        for (int it = 0; it < TILE_PER_T; ++it) {
+            const int w = xw + tword[it];
+            const bool ok = tok[it] && w >= 0 && w < a.W2 * 5;
+            tv[it] = __builtin_amdgcn_raw_buffer_load_b32(rsD, ok ? (trow[it] + w) * 4 : kOOB, 0, 0);
+        }
+    };
+    // Carry (key of the odd column left of the step) starts as "outside".
+#pragma unroll
+    for (int e = lane; e < ARS * 16 * MT; e += 64) (&carry[0][0])[e] = 0.f;
+    // Lanes other than n = 15 write their carry into a private dummy slot.
+    float* const cw0 = n == 15 ? &carry[0][4 * grp] : dummy + lane;
+    const int cstep = n == 15 ? 16 * MT : 0;
+    // Output offsets (pooled row 0, column 0) of this lane's 4 * MT patches,
+    // in bytes for the codes and for the values; patches past natom get
+    // offsets past the end of the buffers, so their stores are dropped.
+    uint32_t ob[MT][4], ob4[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t lp = mt * 16 + 4 * grp + j;
+            const bool ok = lp * mapsz < nmap;
+            ob[mt][j] = ok ? lp * mapsz : (uint32_t)kOOB;
+            ob4[mt][j] = ok ? lp * mapsz * 4 : (uint32_t)kOOB;
+        }
+    fetch(0);
+    for (int step = 0; step < a.n_steps; ++step) {
+        const int C0 = 16 * step;
+        __syncthreads();                         // previous tile fully consumed
+#pragma unroll
+        for (int it = 0; it < TILE_PER_T; ++it)
+            if (tid + 256 * it < TILE_N) sD2[tid + 256 * it] = tv[it];
+        __syncthreads();
+        if (step + 1 < a.n_steps) fetch(C0 + 16);
+        const EngineBF16 eng{fa, sD2, d2};
+        const int c = C0 + n;
+        const uint32_t me = 2 * c < a.W2 ? ~15u : 0u, mo = 2 * c + 1 < a.W2 ? ~15u : 0u;
+        uint32_t best[MT][4], rk[MT][4];
+        row_keys(eng, a, R0, 0, n, me, mo, carry[0] + 4 * grp, cw0, rk);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) best[mt][j] = rk[mt][j];   // my = -1 of pooled row R0
+        for (int pr = 0; pr < TR; ++pr) {
+            const int r = R0 + pr;
+            row_keys(eng, a, R0, 2 * pr + 1, n, me, mo, carry[2 * pr + 1] + 4 * grp, cw0 + (2 * pr + 1) * cstep, rk);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) best[mt][j] = max(best[mt][j], rk[mt][j] - 3u);   // my = 0
+            row_keys(eng, a, R0, 2 * pr + 2, n, me, mo, carry[2 * pr + 2] + 4 * grp, cw0 + (2 * pr + 2) * cstep, rk);
+            uint32_t fin[MT][4];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    fin[mt][j] = max(best[mt][j], rk[mt][j] - 6u);   // my = +1 finishes pooled row r
+                    best[mt][j] = rk[mt][j];                         // my = -1 of pooled row r + 1
+                }
+            if (r < a.h1 && c < a.w1) {
+                const uint32_t rc = (uint32_t)(r * a.w1 + c);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        __builtin_amdgcn_raw_buffer_store_b32(
+                            __float_as_uint(rect_pow(__uint_as_float(fin[mt][j] & ~15u), lam)), rsC,
+                            (int)(ob4[mt][j] + 4 * rc), 0, 0);
+                        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(15u - (fin[mt][j] & 15u)), rsK,
+                                                             (int)(ob[mt][j] + rc), 0, 0);
+                    }
+            }
+        }
+    }
+}
+
 __device__ inline void corr_f32_body(const float* __restrict__ d1, const float* __restrict__ d2, const PoolArgs& a,
                                      float lam, float* __restrict__ cp, uint8_t* __restrict__ code, int bid) {
     __shared__ float sD2[D2R * D2C * 9];
@@ -248,6 +405,7 @@ __device__ inline void corr_bf16_body(const uint16_t* __restrict__ d1, const uin
                                       uint8_t* __restrict__ code, int bid) {
     __shared__ uint32_t sD2[D2R * D2C * 5];
     __shared__ float sCarry[WAVES][ARS][16 * MT];
+    __shared__ float sDummy[WAVES][64 + 16 * MT];   // carry writes of lanes other than the row's last
     const int pt = bid % a.n_ptiles, R0 = (bid / a.n_ptiles) * TR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n = lane & 15, grp = lane >> 4;
@@ -270,8 +428,7 @@ __device__ inline void corr_bf16_body(const uint16_t* __restrict__ d1, const uin
 #pragma unroll
         for (int s = 0; s < 5; ++s) fa[mt * 5 + s] = load_bf8(tmp + 4 * s);
     }
-    EngineBF16 eng{fa, sD2, (const uint32_t*)d2};
-    sweep_band(eng, a, pt, R0, lam, cp, code, sCarry[wave]);
+    sweep_band_bf16(fa, sD2, (const uint32_t*)d2, a, pt, R0, lam, cp, code, sCarry[wave], sDummy[wave]);
 }
 
 __global__ __launch_bounds__(256, 2) void k_corr_pool_f32(const float* __restrict__ d1,
