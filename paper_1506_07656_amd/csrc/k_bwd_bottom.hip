@@ -107,73 +107,74 @@ __device__ inline void store8(E* dst, const float v[8]) {
 }
 
 // ---------------------------------------------------------------- dense dA_0
-// Block: one patch x 32 target rows x 256 target columns of the padded grid.
-// The pooled entries whose windows reach the tile (18 rows x 130 columns)
-// are staged in LDS; each thread forms 8 consecutive outputs in each of 4
-// rows, summing its candidates in the order of dA_at (pooled row, then
-// pooled column).
-constexpr int DA_ROWS = 32, DA_COLS = 256, DA_SR = DA_ROWS / 2 + 2, DA_SC = DA_COLS / 2 + 4;   // rows 16-byte aligned
+// Block: one patch x 32 target rows x 256 target columns of the padded grid,
+// accumulated in LDS.  Each pooled entry (ry, rx) sends its gradient to the
+// one position its code names, (2 ry + my, 2 rx + mx); entries with the same
+// parities of ry and rx never name the same position, so the four parity
+// classes are added in four passes, in a fixed order, without atomics
+// (deterministic).  Codes never name positions outside I' (the forward pool
+// never selects one), so the padding of the grid stays 0.  A thread owns a
+// 2 x 2 quad of pooled entries per round; then the tile leaves as rows of 8
+// values (16 bytes in BF16).
+constexpr int DA_ROWS = 32, DA_COLS = 256;
+constexpr int DA_QR = DA_ROWS / 4 + 1, DA_QC = DA_COLS / 4 + 1;   // quads reaching the tile
+constexpr int DA_NQ = DA_QR * DA_QC, DA_ROUNDS = (DA_NQ + 255) / 256;
+constexpr int kOOB = 0x7ffffff0;                                   // buffer byte offset past any map
+
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
+}
 
 template <typename E>
 __device__ inline void bwd_da_body(const float* __restrict__ gp, const uint8_t* __restrict__ code, const BotArgs& a,
                                    int nct, E* __restrict__ dA, int bid) {
-    __shared__ float sg[DA_SR][DA_SC];
-    __shared__ int sm[DA_SR][DA_SC];
+    __shared__ __align__(16) float sT[DA_ROWS][DA_COLS];
+    const int tid = threadIdx.x;
     const int nband = (a.H2p + DA_ROWS - 1) / DA_ROWS;
     const int ct = bid % nct, rest = bid / nct, band = rest % nband, p = rest / nband;
     const int Y0 = band * DA_ROWS, X0 = ct * DA_COLS;
-    const int ry0 = (Y0 >> 1) - 1, rx0 = (X0 >> 1) - 1;
-    const size_t pm = (size_t)a.h1 * a.w1;
-    for (int e = threadIdx.x; e < DA_SR * DA_SC; e += 256) {   // (the last 2 columns of a row are never read)
-        const int i = e / DA_SC, j = e - i * DA_SC;
-        const int ry = ry0 + i, rx = rx0 + j;
-        float g = 0.f;
-        int m = -1;
-        if (p < a.natom && ry >= 0 && ry < a.h1 && rx >= 0 && rx < a.w1) {
-            const size_t o = p * pm + (size_t)ry * a.w1 + rx;
-            g = gp[o];
-            m = code[o];
+    const int ry0 = Y0 >> 1, rx0 = X0 >> 1;
+    const uint32_t pm = (uint32_t)a.h1 * a.w1;
+    const uint32_t nrec = __builtin_amdgcn_readfirstlane(p < a.natom ? pm : 0u);
+    const auto rsG = buf_rsrc(gp + (size_t)p * pm, nrec * 4), rsM = buf_rsrc(code + (size_t)p * pm, nrec);
+    // the quads' gradients and codes, in flight while the tile is cleared
+    float g[DA_ROUNDS][4];
+    int m[DA_ROUNDS][4];
+#pragma unroll
+    for (int k = 0; k < DA_ROUNDS; ++k) {
+        const int q = tid + 256 * k, qi = q / DA_QC, qj = q - qi * DA_QC;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int ry = ry0 + 2 * qi + (e >> 1), rx = rx0 + 2 * qj + (e & 1);
+            const bool ok = q < DA_NQ && rx < a.w1 && ry < a.h1;
+            const int off = ry * a.w1 + rx;   // used only when ok
+            g[k][e] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsG, ok ? off * 4 : kOOB, 0, 0));
+            m[k][e] = __builtin_amdgcn_raw_buffer_load_b8(rsM, ok ? off : kOOB, 0, 0);
         }
-        sg[i][j] = g;
-        sm[i][j] = m;
+    }
+    for (int e = tid; e < DA_ROWS * DA_COLS / 4; e += 256) reinterpret_cast<float4*>(&sT[0][0])[e] = float4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {   // parity class (ry - ry0) & 1 = e >> 1, (rx - rx0) & 1 = e & 1
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < DA_ROUNDS; ++k) {
+            const int q = tid + 256 * k, qi = q / DA_QC, qj = q - qi * DA_QC;
+            const int my = (m[k][e] * 11) >> 5, mx = m[k][e] - 3 * my;   // code = 3 (my + 1) + (mx + 1), 0..8
+            const int ly = 4 * qi + 2 * (e >> 1) + my - 1, lx = 4 * qj + 2 * (e & 1) + mx - 1;
+            if (g[k][e] != 0.f && ly >= 0 && ly < DA_ROWS && lx >= 0 && lx < DA_COLS) sT[ly][lx] += g[k][e];
+        }
     }
     __syncthreads();
-    const int grp = threadIdx.x & 31, xb = X0 + 8 * grp;
+    const int grp = tid & 31, xb = X0 + 8 * grp;
     if (xb >= a.Wp) return;
-    for (int row = threadIdx.x >> 5; row < DA_ROWS; row += 8) {
-    const int y = Y0 + row;
-    if (y >= a.H2p) break;
-    float out[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) out[q] = 0.f;
-    if (y < a.H2) {
-        // the lane's outputs x = xb..xb+7 take pooled columns j0..j0+5, j0 = 4 grp (16-byte aligned)
-        const int j0 = 4 * grp;
-        for (int ry = (y - 1) >> 1; ry <= (y + 1) >> 1; ++ry) {
-            const int my = y - 2 * ry;
-            if (my < -1 || my > 1) continue;
-            const int i = ry - ry0;
-            const float4 g4 = *reinterpret_cast<const float4*>(&sg[i][j0]);
-            const float2 g2 = *reinterpret_cast<const float2*>(&sg[i][j0 + 4]);
-            const int4 m4 = *reinterpret_cast<const int4*>(&sm[i][j0]);
-            const int2 m2 = *reinterpret_cast<const int2*>(&sm[i][j0 + 4]);
-            const float gv[6] = {g4.x, g4.y, g4.z, g4.w, g2.x, g2.y};
-            const int mv[6] = {m4.x, m4.y, m4.z, m4.w, m2.x, m2.y};
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int x = xb + q;
-                // pooled columns (x-1)>>1 and (x+1)>>1, relative to j0: (q-1)>>1 + 1 and (q+1)>>1 + 1
-#pragma unroll
-                for (int d = 0; d < 2; ++d) {
-                    const int jj = d == 0 ? ((q - 1) >> 1) + 1 : ((q + 1) >> 1) + 1;
-                    const int mx = q - 2 * (jj - 1);                  // x - 2 rx, with rx = X0/2 + 4 grp + jj - 1
-                    if (mx < -1 || mx > 1) continue;                  // q even: only the second candidate
-                    if (x < a.W2 && mv[jj] == 3 * (my + 1) + (mx + 1)) out[q] += gv[jj];
-                }
-            }
-        }
-    }
-    store8<E>(dA + (size_t)p * a.Xp + (size_t)y * a.Wp + xb, out);
+    for (int k = 0; k < DA_ROWS / 8; ++k) {
+        const int row = (tid >> 5) + 8 * k, y = Y0 + row;
+        if (y >= a.H2p) break;
+        const float4 v0 = *reinterpret_cast<const float4*>(&sT[row][8 * grp]);
+        const float4 v1 = *reinterpret_cast<const float4*>(&sT[row][8 * grp + 4]);
+        const float out[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        store8<E>(dA + (size_t)p * a.Xp + (size_t)y * a.Wp + xb, out);
     }
 }
 
