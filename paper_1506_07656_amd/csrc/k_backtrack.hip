@@ -231,7 +231,7 @@ __device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_pre
 // share the cell-table window; BestAt(c) is reduced within the wave.
 constexpr int kBtCols = 64;
 constexpr int kBtWaves = 4;
-constexpr int kBtRing = 6;     // live candidate rows: 2r'-2 .. 2r'+2
+constexpr int kBtRing = 8;     // live candidate rows 2r'-2 .. 2r'+2 (5), rounded up to a power of two
 constexpr int kBtMaxTR = 32;
 constexpr int kOOB = 0x7ffffff0;   // buffer byte offset past any map (element offsets stay < 2^29)
 
@@ -243,6 +243,11 @@ struct BtStreamArgs {
     int TR, n_band, n_ct, n_cgrp;
     int W2, cw;
 };
+
+// Window offsets of an argmax code k = 3 m_y + m_x (m in 0..2): 2-bit fields
+// of two constants, read with one bit-field extract each.
+__device__ inline int code_my(int k) { return (0x2A540u >> (2 * k)) & 3u; }
+__device__ inline int code_mx(int k) { return (0x24924u >> (2 * k)) & 3u; }
 
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -298,13 +303,18 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
         const __amdgpu_buffer_rsrc_t rsU = rsrc(u_cur, nparent * usz * 4), rsM = rsrc(code_cur, nparent * usz);
         const __amdgpu_buffer_rsrc_t rsC = rsrc(cp_prev, nchild * csz * 4);
         const __amdgpu_buffer_rsrc_t rsK = rsrc(code_prev, a.is_bottom ? nchild * csz : 0);
+        // Element offset of each parent's map, or a large negative value for a
+        // missing parent: with a lane's row offset added (also large negative
+        // when the lane or row has no U_l entry), an entry exists exactly when
+        // the sum is >= 0, so validity needs no lane masks per side.
+        constexpr int kNone = -(1 << 30);
         int pbase[4];
 #pragma unroll
         for (int side = 0; side < 4; ++side) {
             const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;   // o_i of Eq. (5), i = side
             const int pb = parent_index(a.l, cb, sy), pa = parent_index(a.l, ca, sx);
             const bool ok = pb >= 0 && pb < a.gyp && pa >= 0 && pa < a.gxp && vxp[pa] && vyp[pb];
-            pbase[side] = ok ? (pb * a.gxp + pa) * usz : -1;
+            pbase[side] = ok ? (pb * a.gxp + pa) * usz : kNone;
         }
         const int cbase = c * csz;
         uint32_t (*ring)[kBtCols] = sR[wv];
@@ -318,11 +328,11 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
         struct OBuf { uint32_t vb[2]; float cv[2]; int cm[2]; };
         auto load_u = [&](int rp, UBuf& st) {
             const bool rok = lane_u && rp >= 0 && rp < a.hu;
-            const int roff = rp * a.wu + ux;
+            const int roff = rok ? rp * a.wu + ux : kNone;
 #pragma unroll
             for (int side = 0; side < 4; ++side) {
-                const bool ok = rok && pbase[side] >= 0;
-                const int off = pbase[side] + roff;   // element offset, used only when ok
+                const int off = pbase[side] + roff;   // >= 0 exactly for an existing entry
+                const bool ok = off >= 0;
                 const float v =
                     __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsU, ok ? off * 4 : kOOB, 0, 0));
                 st.m[side] = __builtin_amdgcn_raw_buffer_load_b8(rsM, ok ? off : kOOB, 0, 0);
@@ -332,11 +342,12 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
         auto scatter = [&](int rp, const UBuf& st) {
 #pragma unroll
             for (int side = 0; side < 4; ++side) {
-                if (!(st.u[side] >= 0.f)) continue;       // no parent or column, or U = -inf (unreached)
                 const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;
-                const int ry = 2 * rp + st.m[side] / 3 - 1 + sy, rxx = 2 * ux + st.m[side] % 3 - 1 + sx;
-                if (ry < R0 || ry >= R1 || rxx < C0 || rxx >= Cend) continue;
-                atomicMax(&ring[ry % kBtRing][rxx - C0], enc(st.u[side]));
+                const int ry = 2 * rp + code_my(st.m[side]) - 1 + sy, rxx = 2 * ux + code_mx(st.m[side]) - 1 + sx;
+                // an entry (U = -inf: unreached; -1: no parent or column) whose target is in the tile
+                const bool act = st.u[side] >= 0.f && (unsigned)(ry - R0) < (unsigned)(R1 - R0) &&
+                                 (unsigned)(rxx - C0) < (unsigned)(Cend - C0);
+                if (act) atomicMax(&ring[ry & (kBtRing - 1)][rxx - C0], enc(st.u[side]));
             }
         };
         auto collect = [&](int rp, OBuf& o) {
@@ -344,7 +355,7 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
             for (int dy = 0; dy < 2; ++dy) {
                 const int ry = 2 * rp - 2 + dy;
                 const bool rok = ry >= R0 && ry < R1;                          // uniform
-                o.vb[dy] = (rok && lane_o) ? atomicExch(&ring[(ry + kBtRing) % kBtRing][t], 0u) : 0u;
+                o.vb[dy] = (rok && lane_o) ? atomicExch(&ring[ry & (kBtRing - 1)][t], 0u) : 0u;
                 const int off = cbase + ry * a.w + rx;   // element offset, used only where a tuple arrived
                 o.cv[dy] = __uint_as_float(
                     __builtin_amdgcn_raw_buffer_load_b32(rsC, o.vb[dy] ? off * 4 : kOOB, 0, 0));
@@ -362,7 +373,7 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
                 } else if (vb) {
                     const float uu = o.cv[dy] + dec(vb);
                     const int mm = o.cm[dy];
-                    const int xy = 2 * ry + mm / 3 - 1, xx = 2 * rx + mm % 3 - 1;
+                    const int xy = 2 * ry + code_my(mm) - 1, xx = 2 * rx + code_mx(mm) - 1;
                     const unsigned long long hi = (unsigned long long)__float_as_uint(uu) << 32;
                     const unsigned long long kb = hi | (0xFFFFFFFFull - (uint32_t)(xy * a.W2 + xx));
                     mybest = kb > mybest ? kb : mybest;

@@ -184,7 +184,7 @@ __device__ inline void bwd_level_body(const BwdArgs& a, const T* __restrict__ dt
 // so every added sum is taken exactly once.
 constexpr int kBwCols = 64;
 constexpr int kBwWaves = 4;
-constexpr int kBwRing = 6;
+constexpr int kBwRing = 8;     // live output rows 2r'-2 .. 2r'+2 (5), rounded up to a power of two
 constexpr int kOOB = 0x7ffffff0;   // buffer byte offset past any map
 
 struct BwStreamArgs {
@@ -194,6 +194,11 @@ struct BwStreamArgs {
     int hu, wu;    // pooled grid of level l
     int TR, n_band, n_ct, n_cgrp;
 };
+
+// Window offsets of an argmax code k = 3 m_y + m_x (m in 0..2): 2-bit fields
+// of two constants, read with one bit-field extract each.
+__device__ inline int code_my(int k) { return (0x2A540u >> (2 * k)) & 3u; }
+__device__ inline int code_mx(int k) { return (0x24924u >> (2 * k)) & 3u; }
 
 __device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, int nbytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, nbytes, 0x00020000);
@@ -233,6 +238,11 @@ __device__ inline void bwd_level_stream_body(const BwStreamArgs& a, const float*
     const int usz = a.hu * a.wu, nparent = a.gxp * a.gyp;
     const __amdgpu_buffer_rsrc_t rsG = rsrc(gp_cur, nparent * usz * 4), rsM = rsrc(code_cur, nparent * usz);
     const __amdgpu_buffer_rsrc_t rsC = rsrc(cp_prev, a.gxc * a.gyc * a.h * a.w * 4);
+    // Element offset of each parent's map, or a large negative value for a
+    // missing parent: with a lane's row offset added (also large negative
+    // when the lane or row has no entry), an entry exists exactly when the
+    // sum is >= 0, so validity needs no lane masks per side.
+    constexpr int kNone = -(1 << 30);
     int pbase[4];
     float inv[4];
 #pragma unroll
@@ -240,7 +250,7 @@ __device__ inline void bwd_level_stream_body(const BwStreamArgs& a, const float*
         const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;   // o_i, i = side
         const int pb = parent_index(a.l, cb, sy), pa = parent_index(a.l, ca, sx);
         const bool ok = pb >= 0 && pb < a.gyp && pa >= 0 && pa < a.gxp && vxp[pa] && vyp[pb];
-        pbase[side] = ok ? (pb * a.gxp + pa) * usz : -1;
+        pbase[side] = ok ? (pb * a.gxp + pa) * usz : kNone;
         int nx = 0, ny = 0;
         if (ok) {
             for (int s2 = -1; s2 <= 1; s2 += 2) {
@@ -260,10 +270,11 @@ __device__ inline void bwd_level_stream_body(const BwStreamArgs& a, const float*
     struct OutBuf { float acc[2]; float cv[2]; };
     auto load_row = [&](int rp, RowBuf& b) {
         const bool rok = lane_u && rp >= 0 && rp < a.hu;
+        const int roff = rok ? rp * a.wu + ux : kNone;
 #pragma unroll
         for (int side = 0; side < 4; ++side) {
-            const bool ok = rok && pbase[side] >= 0;
-            const int off = pbase[side] + rp * a.wu + ux;   // used only when ok
+            const int off = pbase[side] + roff;   // >= 0 exactly for an existing entry
+            const bool ok = off >= 0;
             const float v = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsG, ok ? off * 4 : kOOB, 0, 0));
             const int m = __builtin_amdgcn_raw_buffer_load_b8(rsM, ok ? off : kOOB, 0, 0);
             b.g[side] = ok ? v : 0.f;
@@ -273,13 +284,14 @@ __device__ inline void bwd_level_stream_body(const BwStreamArgs& a, const float*
     auto add_row = [&](int rp, const RowBuf& b) {
 #pragma unroll
         for (int side = 0; side < 4; ++side) {
-            if (pbase[side] < 0) continue;
+            if (pbase[side] < 0) continue;   // uniform: no parent on this side
             const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;
-            const int ry = 2 * rp + b.m[side] / 3 - 1 + sy, rxx = 2 * ux + b.m[side] % 3 - 1 + sx;
-            const bool hit = b.g[side] != 0.f && ry >= R0 && ry < R1 && rxx >= C0 && rxx < Cend;
+            const int ry = 2 * rp + code_my(b.m[side]) - 1 + sy, rxx = 2 * ux + code_mx(b.m[side]) - 1 + sx;
+            const bool hit = b.g[side] != 0.f && (unsigned)(ry - R0) < (unsigned)(R1 - R0) &&
+                             (unsigned)(rxx - C0) < (unsigned)(Cend - C0);
 #pragma unroll
             for (int pass = 0; pass < 2; ++pass) {
-                if (hit && (ux & 1) == pass) ring[ry % kBwRing][rxx - C0] += b.g[side] * inv[side];
+                if (hit && (ux & 1) == pass) ring[ry & (kBwRing - 1)][rxx - C0] += b.g[side] * inv[side];
                 wave_sync();
             }
         }
@@ -290,8 +302,8 @@ __device__ inline void bwd_level_stream_body(const BwStreamArgs& a, const float*
             const int ry = 2 * rp - 2 + dy;
             float acc = 0.f;
             if (ry >= R0 && ry < R1 && lane_o) {
-                acc = ring[ry % kBwRing][t];
-                ring[ry % kBwRing][t] = 0.f;
+                acc = ring[ry & (kBwRing - 1)][t];
+                ring[ry & (kBwRing - 1)][t] = 0.f;
             }
             o.acc[dy] = acc;
             const int off = ry * a.w + rx;   // used only where acc != 0

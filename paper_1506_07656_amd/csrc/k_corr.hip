@@ -241,7 +241,8 @@ __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t nbytes
 // Keys of A-row ia of the step for this lane's 4 * MT patches: the row
 // maximum over the window columns k = 0, 1, 2 (odd column left of the lane's
 // pooled column, even column, odd column), each carrying 15 - k.
-__device__ __forceinline__ void row_keys(const EngineBF16& eng, const PoolArgs& a, int R0, int ia, int n,
+__device__ __forceinline__ void row_keys(const EngineBF16& eng, const EngineBF16& engO, const PoolArgs& a, int R0,
+                                         int ia, int n,
                                          uint32_t me, uint32_t mo, const float* cr, float* cw,
                                          uint32_t (&rk)[MT][4]) {
     const int y = 2 * R0 - 1 + ia;
@@ -250,7 +251,7 @@ __device__ __forceinline__ void row_keys(const EngineBF16& eng, const PoolArgs& 
     const int lo = 0x00800000;   // bits of 2^-126; as signed integers, floats below it (negatives too) are smaller
     f4 accE[MT], accO[MT];
     eng.mfma_row(ia, 2 * n, accE);
-    eng.mfma_row(ia, 2 * n + 1, accO);
+    engO.mfma_row(ia, 2 * n, accO);   // column 2n + 1 of the tile
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -265,7 +266,7 @@ __device__ __forceinline__ void row_keys(const EngineBF16& eng, const PoolArgs& 
         }
 }
 
-__device__ inline void sweep_band_bf16(const bf8* fa, uint32_t* sD2, const uint32_t* __restrict__ d2,
+__device__ inline void sweep_band_bf16(const bf8* fa, uint32_t* sD2, uint32_t* sD2O, const uint32_t* __restrict__ d2,
                                        const PoolArgs& a, int pt, int R0, float lam, float* __restrict__ cp,
                                        uint8_t* __restrict__ code, float (*carry)[16 * MT], float* dummy) {
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -277,27 +278,17 @@ __device__ inline void sweep_band_bf16(const bf8* fa, uint32_t* sD2, const uint3
     const auto rsC = buf_rsrc(cp + (size_t)pbase * mapsz, nmap * 4);
     const auto rsK = buf_rsrc(code + (size_t)pbase * mapsz, nmap);
     const auto rsD = buf_rsrc(d2, (uint32_t)a.H2 * a.W2 * 20);
-    // Tile slots of this thread.
-    int trow[TILE_PER_T], tword[TILE_PER_T];
-    bool tok[TILE_PER_T];
+    // Tile slots of this thread: words tid + 256 it of the tile (row-major,
+    // TILE_W words per row), recomputed at each fetch to keep registers free.
     const int ybase = 2 * R0 - 3;
-#pragma unroll
-    for (int it = 0; it < TILE_PER_T; ++it) {
-        const int idx = tid + 256 * it;
-        trow[it] = idx / TILE_W;
-        tword[it] = idx - trow[it] * TILE_W;
-        const int y = ybase + trow[it];
-        tok[it] = idx < TILE_N && y >= 0 && y < a.H2;
-        trow[it] = y * a.W2 * 5;   // word offset of the target row
-    }
     uint32_t tv[TILE_PER_T];
     auto fetch = [&](int C0) {
         const int xw = (2 * C0 - 2) * 5;   // word offset of the tile's first pixel within a row
 #pragma unroll
         for (int it = 0; it < TILE_PER_T; ++it) {
-            const int w = xw + tword[it];
-            const bool ok = tok[it] && w >= 0 && w < a.W2 * 5;
-            tv[it] = __builtin_amdgcn_raw_buffer_load_b32(rsD, ok ? (trow[it] + w) * 4 : kOOB, 0, 0);
+            const int idx = tid + 256 * it, row = idx / TILE_W, w = xw + idx - row * TILE_W, y = ybase + row;
+            const bool ok = idx < TILE_N && y >= 0 && y < a.H2 && w >= 0 && w < a.W2 * 5;
+            tv[it] = __builtin_amdgcn_raw_buffer_load_b32(rsD, ok ? (y * a.W2 * 5 + w) * 4 : kOOB, 0, 0);
         }
     };
     // Carry (key of the odd column left of the step) starts as "outside".
@@ -324,27 +315,35 @@ __device__ inline void sweep_band_bf16(const bf8* fa, uint32_t* sD2, const uint3
         const int C0 = 16 * step;
         __syncthreads();                         // previous tile fully consumed
 #pragma unroll
-        for (int it = 0; it < TILE_PER_T; ++it)
-            if (tid + 256 * it < TILE_N) sD2[tid + 256 * it] = tv[it];
+        for (int it = 0; it < TILE_PER_T; ++it) {
+            const int idx = tid + 256 * it;
+            if (idx < TILE_N) sD2[idx] = tv[it];
+            if (idx >= 5 && idx < TILE_N) sD2O[idx - 5] = tv[it];   // the same tile one pixel to the left
+        }
         __syncthreads();
         if (step + 1 < a.n_steps) fetch(C0 + 16);
-        const EngineBF16 eng{fa, sD2, d2};
+        // Even and odd columns read separate copies, so that both fragments
+        // load straight into aligned registers (a pixel is 5 words; reading
+        // the odd fragment from the even copy would need register moves).
+        const EngineBF16 eng{fa, sD2, d2}, engO{fa, sD2O, d2};
         const int c = C0 + n;
         const uint32_t me = 2 * c < a.W2 ? ~15u : 0u, mo = 2 * c + 1 < a.W2 ? ~15u : 0u;
         uint32_t best[MT][4], rk[MT][4];
-        row_keys(eng, a, R0, 0, n, me, mo, carry[0] + 4 * grp, cw0, rk);
+        row_keys(eng, engO, a, R0, 0, n, me, mo, carry[0] + 4 * grp, cw0, rk);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int j = 0; j < 4; ++j) best[mt][j] = rk[mt][j];   // my = -1 of pooled row R0
         for (int pr = 0; pr < TR; ++pr) {
             const int r = R0 + pr;
-            row_keys(eng, a, R0, 2 * pr + 1, n, me, mo, carry[2 * pr + 1] + 4 * grp, cw0 + (2 * pr + 1) * cstep, rk);
+            row_keys(eng, engO, a, R0, 2 * pr + 1, n, me, mo, carry[2 * pr + 1] + 4 * grp, cw0 + (2 * pr + 1) * cstep,
+                     rk);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) best[mt][j] = max(best[mt][j], rk[mt][j] - 3u);   // my = 0
-            row_keys(eng, a, R0, 2 * pr + 2, n, me, mo, carry[2 * pr + 2] + 4 * grp, cw0 + (2 * pr + 2) * cstep, rk);
+            row_keys(eng, engO, a, R0, 2 * pr + 2, n, me, mo, carry[2 * pr + 2] + 4 * grp, cw0 + (2 * pr + 2) * cstep,
+                     rk);
             uint32_t fin[MT][4];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
@@ -360,7 +359,9 @@ __device__ inline void sweep_band_bf16(const bf8* fa, uint32_t* sD2, const uint3
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         __builtin_amdgcn_raw_buffer_store_b32(
-                            __float_as_uint(rect_pow(__uint_as_float(fin[mt][j] & ~15u), lam)), rsC,
+                            // the kept value is >= 2^-126 > 0: the power needs no test for 0
+                            __float_as_uint(__builtin_amdgcn_exp2f(lam * __builtin_amdgcn_logf(
+                                __uint_as_float(fin[mt][j] & ~15u)))), rsC,
                             (int)(ob4[mt][j] + 4 * rc), 0, 0);
                         __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(15u - (fin[mt][j] & 15u)), rsK,
                                                              (int)(ob[mt][j] + rc), 0, 0);
@@ -403,7 +404,8 @@ __device__ inline void corr_f32_body(const float* __restrict__ d1, const float* 
 __device__ inline void corr_bf16_body(const uint16_t* __restrict__ d1, const uint16_t* __restrict__ d2,
                                       const PoolArgs& a, float lam, float* __restrict__ cp,
                                       uint8_t* __restrict__ code, int bid) {
-    __shared__ uint32_t sD2[D2R * D2C * 5];
+    __shared__ __align__(16) uint32_t sD2[D2R * D2C * 5];
+    __shared__ __align__(16) uint32_t sD2O[D2R * D2C * 5];
     __shared__ float sCarry[WAVES][ARS][16 * MT];
     __shared__ float sDummy[WAVES][64 + 16 * MT];   // carry writes of lanes other than the row's last
     const int pt = bid % a.n_ptiles, R0 = (bid / a.n_ptiles) * TR;
@@ -428,7 +430,7 @@ __device__ inline void corr_bf16_body(const uint16_t* __restrict__ d1, const uin
 #pragma unroll
         for (int s = 0; s < 5; ++s) fa[mt * 5 + s] = load_bf8(tmp + 4 * s);
     }
-    sweep_band_bf16(fa, sD2, (const uint32_t*)d2, a, pt, R0, lam, cp, code, sCarry[wave], sDummy[wave]);
+    sweep_band_bf16(fa, sD2, sD2O, (const uint32_t*)d2, a, pt, R0, lam, cp, code, sCarry[wave], sDummy[wave]);
 }
 
 __global__ __launch_bounds__(256, 2) void k_corr_pool_f32(const float* __restrict__ d1,
