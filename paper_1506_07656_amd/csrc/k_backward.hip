@@ -289,11 +289,13 @@ __device__ inline void bwd_level_stream_body(const BwStreamArgs& a, const float*
             const int ry = 2 * rp + code_my(b.m[side]) - 1 + sy, rxx = 2 * ux + code_mx(b.m[side]) - 1 + sx;
             const bool hit = b.g[side] != 0.f && (unsigned)(ry - R0) < (unsigned)(R1 - R0) &&
                              (unsigned)(rxx - C0) < (unsigned)(Cend - C0);
+            // Within one instruction no two lanes of the same column parity
+            // meet on a position, so an LDS add without return is exactly
+            // old + v; the even pass precedes the odd one (a wave's LDS
+            // operations run in order), which fixes the order of every sum.
 #pragma unroll
-            for (int pass = 0; pass < 2; ++pass) {
-                if (hit && (ux & 1) == pass) ring[ry & (kBwRing - 1)][rxx - C0] += b.g[side] * inv[side];
-                wave_sync();
-            }
+            for (int pass = 0; pass < 2; ++pass)
+                if (hit && (ux & 1) == pass) atomicAdd(&ring[ry & (kBwRing - 1)][rxx - C0], b.g[side] * inv[side]);
         }
     };
     auto collect = [&](int rp, OutBuf& o) {

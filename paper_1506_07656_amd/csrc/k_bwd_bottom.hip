@@ -161,7 +161,8 @@ __device__ inline void bwd_da_body(const float* __restrict__ gp, const uint8_t* 
             const int q = tid + 256 * k, qi = q / DA_QC, qj = q - qi * DA_QC;
             const int my = (m[k][e] * 11) >> 5, mx = m[k][e] - 3 * my;   // code = 3 (my + 1) + (mx + 1), 0..8
             const int ly = 4 * qi + 2 * (e >> 1) + my - 1, lx = 4 * qj + 2 * (e & 1) + mx - 1;
-            if (g[k][e] != 0.f && ly >= 0 && ly < DA_ROWS && lx >= 0 && lx < DA_COLS) sT[ly][lx] += g[k][e];
+            // no two entries of one class meet: an LDS add without return is exactly old + g
+            if (g[k][e] != 0.f && ly >= 0 && ly < DA_ROWS && lx >= 0 && lx < DA_COLS) atomicAdd(&sT[ly][lx], g[k][e]);
         }
     }
     __syncthreads();
