@@ -63,8 +63,8 @@ def stage_work(pl, name: str, level: int, precision: str):
         rd += npat(level) * (h[level] * w[level] * 4.0 if level == L else h[level + 1] * w[level + 1] * 5.0)
         wr = 0.0 if level == 1 else npat(level - 1) * h[level] * w[level] * 4.0
         return "hbm", rd + wr, "B"
-    if name == "descriptor":
-        return "hbm", (pl.W1 * pl.H1 + pl.W2 * pl.H2) / 2 * 40.0, "B"
+    if name == "descriptor":   # one launch for both images: 4 B in, 36 B out (+ 20 B BF16 copy) per pixel
+        return "hbm", (pl.W1 * pl.H1 + pl.W2 * pl.H2) * (40.0 + (20.0 if precision == "bf16" else 0.0)), "B"
     return "hbm", 0.0, "B"
 
 

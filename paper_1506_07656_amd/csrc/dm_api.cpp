@@ -279,8 +279,9 @@ dm_status dm_match_images(const float* img1, int W1, int H1, int ld1, const floa
     float* d2 = at<float>(ws, pi.off_desc2);
     const bool bf = prm->precision == DM_BF16;
     hipStream_t s = stream;
-    DM_LAUNCH("descriptor", -1, launch_descriptor(img1, W1, H1, ld1, dp, d1, bf ? at<uint16_t>(ws, pi.off_bf1) : nullptr, s));
-    DM_LAUNCH("descriptor", -1, launch_descriptor(img2, W2, H2, ld2, dp, d2, bf ? at<uint16_t>(ws, pi.off_bf2) : nullptr, s));
+    DM_LAUNCH("descriptor", -1,
+              launch_descriptor_pair(img1, W1, H1, ld1, d1, bf ? at<uint16_t>(ws, pi.off_bf1) : nullptr, img2, W2, H2,
+                                     ld2, d2, bf ? at<uint16_t>(ws, pi.off_bf2) : nullptr, dp, s));
     return run_match(d1, d2, pi, prm, ws, bf, out, n_out, stream);
 }
 

@@ -167,6 +167,9 @@ void timing_end(hipStream_t s);
 hipError_t launch_valid_init(const Geom& g, uint8_t* vt, hipStream_t s);
 hipError_t launch_descriptor(const float* img, int W, int H, int ld, const DescParams& p,
                              float* out, uint16_t* out_bf16, hipStream_t s);
+hipError_t launch_descriptor_pair(const float* img1, int W1, int H1, int ld1, float* out1, uint16_t* bf1,
+                                  const float* img2, int W2, int H2, int ld2, float* out2, uint16_t* bf2,
+                                  const DescParams& p, hipStream_t s);
 hipError_t launch_to_bf16(const float* d, int n_pix, uint16_t* out, hipStream_t s);
 hipError_t launch_corr_pool_f32(const float* d1, const float* d2, const Geom& g, float lam,
                                 float* cp, uint8_t* code, hipStream_t s);

@@ -201,6 +201,27 @@ hipError_t launch_descriptor(const float* img, int W, int H, int ld, const DescP
     return hipGetLastError();
 }
 
+// Both images of a pair in one launch (blockIdx.z picks the image): each
+// image alone fills only one block per CU, as a block's stencil stages need
+// most of the LDS.
+__global__ __launch_bounds__(NT) void k_descriptor_pair(DescJob j0, DescJob j1) {
+    const DescJob& j = blockIdx.z ? j1 : j0;
+    if ((int)blockIdx.x >= j.gx || (int)blockIdx.y * TY >= j.H) return;
+    descriptor_body(j.img, j.W, j.H, j.ld, j.p, j.out, j.out_bf, blockIdx.x, blockIdx.y);
+}
+
+hipError_t launch_descriptor_pair(const float* img1, int W1, int H1, int ld1, float* out1, uint16_t* bf1,
+                                  const float* img2, int W2, int H2, int ld2, float* out2, uint16_t* bf2,
+                                  const DescParams& p, hipStream_t s) {
+    const DescJob j0{img1, W1, H1, ld1, (W1 + TX - 1) / TX, out1, bf1, p};
+    const DescJob j1{img2, W2, H2, ld2, (W2 + TX - 1) / TX, out2, bf2, p};
+    const dim3 grid(j0.gx > j1.gx ? j0.gx : j1.gx, ((H1 > H2 ? H1 : H2) + TY - 1) / TY, 2);
+    const size_t smem = desc_smem_bytes(p);
+    if (smem > 160 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_descriptor_pair, grid, dim3(NT), smem, s, j0, j1);
+    return hipGetLastError();
+}
+
 JobRec desc_job(const float* img, int W, int H, int ld, const DescParams& p, float* out, uint16_t* out_bf16) {
     DescJob j{img, W, H, ld, (W + TX - 1) / TX, out, out_bf16, p};
     JobRec r;
