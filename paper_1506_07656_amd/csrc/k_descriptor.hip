@@ -203,22 +203,31 @@ hipError_t launch_descriptor(const float* img, int W, int H, int ld, const DescP
 
 // Both images of a pair in one launch (blockIdx.z picks the image): each
 // image alone fills only one block per CU, as a block's stencil stages need
-// most of the LDS.
-__global__ __launch_bounds__(NT) void k_descriptor_pair(DescJob j0, DescJob j1) {
-    const DescJob& j = blockIdx.z ? j1 : j0;
-    if ((int)blockIdx.x >= j.gx || (int)blockIdx.y * TY >= j.H) return;
-    descriptor_body(j.img, j.W, j.H, j.ld, j.p, j.out, j.out_bf, blockIdx.x, blockIdx.y);
+// most of the LDS.  The per-image fields are selected one by one (selecting
+// between two by-value structs would put them in scratch memory).
+struct DescImage {
+    const float* img;
+    int W, H, ld;
+    float* out;
+    uint16_t* out_bf;
+};
+
+__global__ __launch_bounds__(NT) void k_descriptor_pair(DescImage i0, DescImage i1, DescParams p) {
+    const bool second = blockIdx.z != 0;
+    const int W = second ? i1.W : i0.W, H = second ? i1.H : i0.H;
+    if ((int)blockIdx.x * TX >= W || (int)blockIdx.y * TY >= H) return;
+    descriptor_body(second ? i1.img : i0.img, W, H, second ? i1.ld : i0.ld, p, second ? i1.out : i0.out,
+                    second ? i1.out_bf : i0.out_bf, blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_descriptor_pair(const float* img1, int W1, int H1, int ld1, float* out1, uint16_t* bf1,
                                   const float* img2, int W2, int H2, int ld2, float* out2, uint16_t* bf2,
                                   const DescParams& p, hipStream_t s) {
-    const DescJob j0{img1, W1, H1, ld1, (W1 + TX - 1) / TX, out1, bf1, p};
-    const DescJob j1{img2, W2, H2, ld2, (W2 + TX - 1) / TX, out2, bf2, p};
-    const dim3 grid(j0.gx > j1.gx ? j0.gx : j1.gx, ((H1 > H2 ? H1 : H2) + TY - 1) / TY, 2);
+    const DescImage i0{img1, W1, H1, ld1, out1, bf1}, i1{img2, W2, H2, ld2, out2, bf2};
+    const dim3 grid(((W1 > W2 ? W1 : W2) + TX - 1) / TX, ((H1 > H2 ? H1 : H2) + TY - 1) / TY, 2);
     const size_t smem = desc_smem_bytes(p);
     if (smem > 160 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_descriptor_pair, grid, dim3(NT), smem, s, j0, j1);
+    hipLaunchKernelGGL(k_descriptor_pair, grid, dim3(NT), smem, s, i0, i1, p);
     return hipGetLastError();
 }
 
