@@ -161,13 +161,14 @@ dm_status grad_backward(const T* d1, const T* d2, const dm_grad_plan& gp, const 
         const dm_status st = run_levels<T>(B, g, 1, g.lmax - 1, lam, s);
         if (st != DM_OK) return st;
     }
+    const int mode = std::is_same<T, double>::value ? 2 : (prm->precision == DM_BF16 ? 1 : 0);
+    const bool g16 = mode == 1;   // the BF16 bottom reads the level-1 gradient as BF16
     for (int l = g.lmax; l >= 1; --l) {
         const T* gcur = l < g.lmax ? B.gbuf(l & 1) : nullptr;
         DM_LAUNCH("bwd_level", l,
                   launch_bwd_level<T>(l, dtop, B.top(), gcur, l < g.lmax ? B.code(l) : nullptr, B.cp(l - 1), B.vt(),
-                                      g, lam, B.gbuf((l - 1) & 1), s));
+                                      g, lam, B.gbuf((l - 1) & 1), s, l == 1 && g16));
     }
-    const int mode = std::is_same<T, double>::value ? 2 : (prm->precision == DM_BF16 ? 1 : 0);
     DM_LAUNCH("bwd_bottom", 0,
               launch_bwd_bottom<T>(mode, B.gbuf(0), B.code(0), d1, d2, g, at<T>(scratch, gp.off_part),
                                    at<T>(scratch, gp.off_t), at<void>(scratch, gp.off_dense), dd1, dd2, s));

@@ -272,7 +272,8 @@ void build(int n, const dm_pair* pairs, const dm_params* prm, int flags, const s
             const int lm = P[k].pi.lmax;
             if (lm < l) continue;
             J.push_back(bwd_level_job(l, dtop(k), top(k), l < lm ? gbuf(k, l & 1) : nullptr, l < lm ? code(k, l) : nullptr,
-                                      cp(k, l - 1), vt(k), G[k], lam, gbuf(k, (l - 1) & 1)));
+                                      cp(k, l - 1), vt(k), G[k], lam, gbuf(k, (l - 1) & 1),
+                                      l == 1 && bf));   // the BF16 bottom reads the level-1 gradient as BF16
         }
         B.stage("bwd_level", l, J, false);
     }

@@ -153,7 +153,8 @@ JobRec fill_job(uint64_t* p, size_t n, uint64_t v);
 JobRec valid_job(const Geom& g, uint8_t* vt);
 hipError_t launch_group_bwd(int kind, const GroupLaunch& gl, hipStream_t s);
 JobRec bwd_level_job(int l, const float* dtop, const float* top, const float* gp_cur, const uint8_t* code_cur,
-                     const float* cp_prev, const uint8_t* vt, const Geom& g, float lam, float* gp_prev);
+                     const float* cp_prev, const uint8_t* vt, const Geom& g, float lam, float* gp_prev,
+                     bool out16 = false);
 JobRec top_grad_job(const float* top, const Geom& g, float* dtop);
 hipError_t launch_group_bot(int kind, const GroupLaunch& gl, hipStream_t s);
 std::vector<JobRec> bot_jobs(bool bf16, const float* gp, const uint8_t* code, const float* d1, const float* d2,
@@ -186,8 +187,10 @@ hipError_t launch_level(int l, const T* prev, const uint8_t* vt, const Geom& g, 
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s);
 template <typename T>
 hipError_t launch_bwd_level(int l, const T* dtop, const T* top, const T* gp_cur, const uint8_t* code_cur,
-                            const T* cp_prev, const uint8_t* vt, const Geom& g, T lam, T* gp_prev, hipStream_t s);
-// mode 0: FP32 MFMA, 1: BF16 MFMA operands with FP32 accumulation, 2: reference kernels (any T)
+                            const T* cp_prev, const uint8_t* vt, const Geom& g, T lam, T* gp_prev, hipStream_t s,
+                            bool out16 = false);
+// mode 0: FP32 MFMA, 1: BF16 MFMA operands with FP32 accumulation (then the pooled gradient gp is
+// stored as BF16: the level-1 adjoint writes it with out16), 2: reference kernels (any T)
 // dense: scratch of bwd_dense_bytes() for the dense dA_0 and the patch matrix (modes 0, 1)
 template <typename T>
 hipError_t launch_bwd_bottom(int mode, const T* gp, const uint8_t* code, const T* d1, const T* d2, const Geom& g,

@@ -27,6 +27,19 @@ __device__ inline T rect_grad_factor(T c, T lam) {
     return c > T(0) ? lam * rect_pow(c, (lam - T(1)) / lam) : T(0);
 }
 
+// A gradient entry as FP32, or rounded to BF16 (nearest even) when the
+// array holds BF16.
+template <typename T>
+__device__ inline void store_grad(T* p, size_t i, T v, int as_bf16) {
+    if (std::is_same<T, float>::value && as_bf16) {
+        uint32_t u = __float_as_uint((float)v);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        reinterpret_cast<uint16_t*>(p)[i] = (uint16_t)(u >> 16);
+    } else {
+        p[i] = v;
+    }
+}
+
 struct BwdArgs {
     int l;
     int gxp, gyp, gxc, gyc;
@@ -36,6 +49,7 @@ struct BwdArgs {
     int TR, TC, CB;            // tile rows, cols, children per block
     int n_cblk, n_rt;
     FastDiv f_t, f_tc, f_nr, f_rwd;   // divisions by TR*TC, TC, RH*RWd, RWd
+    int out16;                        // the output gradient is stored as BF16 (FP32 path only)
 };
 
 __device__ inline int xcd_block(int nblocks) {
@@ -134,7 +148,7 @@ __device__ inline void bwd_level_body(const BwdArgs& a, const T* __restrict__ dt
         if (ry >= a.h || rx >= a.w || sCv[k] < 0) continue;
         const size_t o = (((size_t)cblk * a.CB + k) * a.h + ry) * a.w + rx;
         if (!sCv[k]) {
-            gp_prev[o] = T(0);
+            store_grad(gp_prev, o, T(0), a.out16);
             continue;
         }
         T acc = 0;
@@ -163,7 +177,7 @@ __device__ inline void bwd_level_body(const BwdArgs& a, const T* __restrict__ dt
             }
             acc += gsum * sInv[ks];
         }
-        gp_prev[o] = acc * rect_grad_factor(cp_prev[o], lam);
+        store_grad(gp_prev, o, acc * rect_grad_factor(cp_prev[o], lam), a.out16);
     }
 }
 
@@ -193,6 +207,7 @@ struct BwStreamArgs {
     int h, w;      // child pooled grid (maps of level l)
     int hu, wu;    // pooled grid of level l
     int TR, n_band, n_ct, n_cgrp;
+    int out16;     // the output gradient is stored as BF16 (level 1 feeding the BF16 bottom)
 };
 
 // Window offsets of an argmax code k = 3 m_y + m_x (m in 0..2): 2-bit fields
@@ -232,7 +247,7 @@ __device__ inline void bwd_level_stream_body(const BwStreamArgs& a, const float*
     const size_t obase = (size_t)c * a.h * a.w;
     if (!(vxc[ca] && vyc[cb])) {   // no child here: its gradient is 0
         for (int ry = R0; ry < R1; ++ry)
-            if (lane_o) gp_prev[obase + (size_t)ry * a.w + rx] = 0.f;
+            if (lane_o) store_grad(gp_prev, obase + (size_t)ry * a.w + rx, 0.f, a.out16);
         return;
     }
     const int usz = a.hu * a.wu, nparent = a.gxp * a.gyp;
@@ -318,7 +333,7 @@ __device__ inline void bwd_level_stream_body(const BwStreamArgs& a, const float*
         for (int dy = 0; dy < 2; ++dy) {
             const int ry = 2 * rp - 2 + dy;
             if (ry < R0 || ry >= R1 || !lane_o) continue;
-            gp_prev[obase + (size_t)ry * a.w + rx] = o.acc[dy] * rect_grad_factor(o.cv[dy], lam);
+            store_grad(gp_prev, obase + (size_t)ry * a.w + rx, o.acc[dy] * rect_grad_factor(o.cv[dy], lam), a.out16);
         }
     };
     const int rpa = (R0 - 2) >> 1, rp1 = ((R1 - 1) >> 1) + 1;
@@ -386,6 +401,7 @@ bool use_bwd_stream(int l, const Geom& g) {
 
 BwStreamArgs make_bwd_stream_args(int l, const Geom& g, int& nblocks) {
     BwStreamArgs b;
+    b.out16 = 0;
     b.l = l;
     b.gxp = g.gx[l];
     b.gyp = g.gy[l];
@@ -473,6 +489,7 @@ BwdArgs make_bwd_args(int l, const Geom& g, int& nblocks, size_t& smem) {
     a.w = g.w[l];
     a.hu = g.h[l + 1];
     a.wu = g.w[l + 1];
+    a.out16 = 0;
     a.is_top = (l == g.lmax);
     a.TC = a.w < 128 ? a.w : 128;
     a.TR = 1024 / a.TC;
@@ -501,16 +518,18 @@ BwdArgs make_bwd_args(int l, const Geom& g, int& nblocks, size_t& smem) {
 }  // namespace
 
 JobRec bwd_level_job(int l, const float* dtop, const float* top, const float* gp_cur, const uint8_t* code_cur,
-                     const float* cp_prev, const uint8_t* vt, const Geom& g, float lam, float* gp_prev) {
+                     const float* cp_prev, const uint8_t* vt, const Geom& g, float lam, float* gp_prev, bool out16) {
     int nb;
     if (use_bwd_stream(l, g)) {
-        const BwStreamArgs b = make_bwd_stream_args(l, g, nb);
+        BwStreamArgs b = make_bwd_stream_args(l, g, nb);
+        b.out16 = out16;
         JobRec r;
         r.set(JK_BWD_LEVEL_STREAM, nb, 0, BwdLevelStreamJob{b, gp_cur, code_cur, cp_prev, vt, g, lam, gp_prev});
         return r;
     }
     size_t smem;
-    const BwdArgs a = make_bwd_args(l, g, nb, smem);
+    BwdArgs a = make_bwd_args(l, g, nb, smem);
+    a.out16 = out16;
     JobRec r;
     r.set(JK_BWD_LEVEL, nb, smem, BwdLevelJob{a, dtop, top, gp_cur, code_cur, cp_prev, vt, g, lam, gp_prev});
     return r;
@@ -534,11 +553,13 @@ hipError_t launch_group_bwd(int kind, const GroupLaunch& gl, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_bwd_level(int l, const T* dtop, const T* top, const T* gp_cur, const uint8_t* code_cur,
-                            const T* cp_prev, const uint8_t* vt, const Geom& g, T lam, T* gp_prev, hipStream_t s) {
+                            const T* cp_prev, const uint8_t* vt, const Geom& g, T lam, T* gp_prev, hipStream_t s,
+                            bool out16) {
     if constexpr (std::is_same<T, float>::value) {
         if (use_bwd_stream(l, g)) {
             int nb;
-            const BwStreamArgs b = make_bwd_stream_args(l, g, nb);
+            BwStreamArgs b = make_bwd_stream_args(l, g, nb);
+            b.out16 = out16;
             hipLaunchKernelGGL(k_bwd_level_stream, dim3(((nb + 7) / 8) * 8), dim3(64 * kBwWaves), 0, s, b, gp_cur,
                                code_cur, cp_prev, vt, g, lam, gp_prev, nb);
             return hipGetLastError();
@@ -554,6 +575,7 @@ hipError_t launch_bwd_level(int l, const T* dtop, const T* top, const T* gp_cur,
     a.w = g.w[l];
     a.hu = g.h[l + 1];
     a.wu = g.w[l + 1];
+    a.out16 = out16;
     a.is_top = (l == g.lmax);
     a.TC = a.w < 128 ? a.w : 128;
     a.TR = 1024 / a.TC;
@@ -582,9 +604,10 @@ hipError_t launch_bwd_level(int l, const T* dtop, const T* top, const T* gp_cur,
 }
 
 template hipError_t launch_bwd_level<float>(int, const float*, const float*, const float*, const uint8_t*,
-                                            const float*, const uint8_t*, const Geom&, float, float*, hipStream_t);
+                                            const float*, const uint8_t*, const Geom&, float, float*, hipStream_t,
+                                            bool);
 template hipError_t launch_bwd_level<double>(int, const double*, const double*, const double*, const uint8_t*,
                                              const double*, const uint8_t*, const Geom&, double, double*,
-                                             hipStream_t);
+                                             hipStream_t, bool);
 
 }  // namespace dm

@@ -126,7 +126,7 @@ __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t nbytes
 }
 
 template <typename E>
-__device__ inline void bwd_da_body(const float* __restrict__ gp, const uint8_t* __restrict__ code, const BotArgs& a,
+__device__ __forceinline__ void bwd_da_body(const float* __restrict__ gp, const uint8_t* __restrict__ code, const BotArgs& a,
                                    int nct, E* __restrict__ dA, int bid) {
     __shared__ __align__(16) float sT[DA_ROWS][DA_COLS];
     const int tid = threadIdx.x;
@@ -136,7 +136,11 @@ __device__ inline void bwd_da_body(const float* __restrict__ gp, const uint8_t* 
     const int ry0 = Y0 >> 1, rx0 = X0 >> 1;
     const uint32_t pm = (uint32_t)a.h1 * a.w1;
     const uint32_t nrec = __builtin_amdgcn_readfirstlane(p < a.natom ? pm : 0u);
-    const auto rsG = buf_rsrc(gp + (size_t)p * pm, nrec * 4), rsM = buf_rsrc(code + (size_t)p * pm, nrec);
+    // BF16 operands come with a BF16 pooled gradient, FP32 with FP32
+    constexpr bool G16 = std::is_same<E, uint16_t>::value;
+    constexpr int gsz = G16 ? 2 : 4;   // bytes per stored gradient entry
+    const auto rsG = buf_rsrc(reinterpret_cast<const char*>(gp) + (size_t)p * pm * gsz, nrec * gsz),
+               rsM = buf_rsrc(code + (size_t)p * pm, nrec);
     // the quads' gradients and codes, in flight while the tile is cleared
     float g[DA_ROUNDS][4];
     int m[DA_ROUNDS][4];
@@ -148,7 +152,11 @@ __device__ inline void bwd_da_body(const float* __restrict__ gp, const uint8_t* 
             const int ry = ry0 + 2 * qi + (e >> 1), rx = rx0 + 2 * qj + (e & 1);
             const bool ok = q < DA_NQ && rx < a.w1 && ry < a.h1;
             const int off = ry * a.w1 + rx;   // used only when ok
-            g[k][e] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsG, ok ? off * 4 : kOOB, 0, 0));
+            if constexpr (G16)
+                g[k][e] = __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rsG, ok ? off * 2 : kOOB, 0, 0)
+                                          << 16);
+            else
+                g[k][e] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsG, ok ? off * 4 : kOOB, 0, 0));
             m[k][e] = __builtin_amdgcn_raw_buffer_load_b8(rsM, ok ? off : kOOB, 0, 0);
         }
     }
