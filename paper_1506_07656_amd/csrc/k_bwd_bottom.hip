@@ -696,12 +696,16 @@ struct BotPlan {
 }  // namespace
 
 int bwd_nsplit(const Geom& g) {
-    // enough blocks for the 256 CUs: patch tiles x K splits >= ~1024
+    // Enough blocks for the 256 CUs (patch tiles x K splits >= ~1024), but
+    // at least 8192 target positions per split: small pairs then add few
+    // partial sums, which matters when many of them share the GPU in a batch.
+    // The count depends on the pair alone, so a batch sums in the same order
+    // as the single-pair call.
     const int natom = g.gx[0] * g.gy[0];
     const int ptiles = (natom + G1M - 1) / G1M;
     const int xp = ((g.W2 + 7) & ~7) * ((g.H2 + 15) & ~15);
     int ns = (1024 + ptiles - 1) / ptiles;
-    if (ns > xp / GK) ns = xp / GK;
+    if (ns > xp / 8192) ns = xp / 8192;
     if (ns > 64) ns = 64;
     if (ns < 1) ns = 1;
     return ns;
