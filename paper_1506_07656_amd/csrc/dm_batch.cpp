@@ -374,7 +374,7 @@ dm_status autotune(Schedule& S, int n, const dm_pair* pairs, const dm_params* pr
     const int reps = 3;
     // band heights (job tables change)
     {
-        const int cand[3] = {8, 16, 32};
+        const int cand[4] = {8, 16, 32, 64};
         float bestt = 1e30f;
         int bestv = S.tiles.level_rows;
         for (int c : cand) {
@@ -386,7 +386,7 @@ dm_status autotune(Schedule& S, int n, const dm_pair* pairs, const dm_params* pr
         S.tiles.level_rows = bestv;
     }
     {
-        const int cand[3] = {8, 16, 32};
+        const int cand[4] = {8, 16, 32, 64};
         float bestt = 1e30f;
         int bestv = S.tiles.bt_rows;
         for (int c : cand) {

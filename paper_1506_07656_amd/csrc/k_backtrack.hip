@@ -232,7 +232,8 @@ __device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_pre
 constexpr int kBtCols = 64;
 constexpr int kBtWaves = 4;
 constexpr int kBtRing = 8;     // live candidate rows 2r'-2 .. 2r'+2 (5), rounded up to a power of two
-constexpr int kBtMaxTR = 32;
+constexpr int kBtMaxTR = 64;   // tallest band (sizes the cell window in LDS)
+constexpr int kBtTR = 32;      // band of the single-pair launch
 constexpr int kOOB = 0x7ffffff0;   // buffer byte offset past any map (element offsets stay < 2^29)
 
 struct BtStreamArgs {
@@ -708,7 +709,7 @@ hipError_t launch_backtrack<float>(int l, const float* cp_prev, const uint8_t* c
                                    float* u_prev, uint64_t* best, uint64_t* cell, hipStream_t s) {
     if (use_bt_stream(l, g)) {
         int nb;
-        const BtStreamArgs b = make_bt_stream_args(l, g, kBtMaxTR, nb);
+        const BtStreamArgs b = make_bt_stream_args(l, g, kBtTR, nb);
         hipLaunchKernelGGL(k_backtrack_stream, dim3(((nb + 7) / 8) * 8), dim3(64 * kBtWaves), 0, s, b, cp_prev,
                            code_prev, u_cur, code_cur, vt, g, u_prev, (unsigned long long*)best,
                            (unsigned long long*)cell, nb);
