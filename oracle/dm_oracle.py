@@ -318,8 +318,11 @@ def aggregate(prev_pooled: np.ndarray, lv: int, pyr: Pyramid) -> np.ndarray:
 
 
 def pyramid(D1: np.ndarray, D2: np.ndarray, prm: Params = Params(), keep_full: bool = False,
-            row_chunk: int = 8) -> Pyramid:
-    """Multi-level correlation pyramid, Algorithm 1."""
+            row_chunk: int = 8, keep_bottom: bool = True) -> Pyramid:
+    """Multi-level correlation pyramid, Algorithm 1.  keep_full keeps the
+    pre-rectification maps for the gradient; keep_bottom=False leaves out the
+    bottom one (full resolution), which pyramid_backward then recomputes in
+    chunks of patch rows."""
     H, W, _ = D1.shape
     H2, W2, _ = D2.shape
     lmax = pyramid_top(W, H, prm.max_patch)
@@ -332,7 +335,7 @@ def pyramid(D1: np.ndarray, D2: np.ndarray, prm: Params = Params(), keep_full: b
     for r0 in range(0, ny0, row_chunk):
         A0 = bottom_scores(D1, D2, np.arange(r0, min(ny0, r0 + row_chunk)))
         C0 = rectify(A0, prm.lam)
-        if keep_full:
+        if keep_full and (keep_bottom or lmax == 0):
             parts_A.append(A0)
         if lmax == 0:
             parts_top.append(C0)
@@ -342,7 +345,7 @@ def pyramid(D1: np.ndarray, D2: np.ndarray, prm: Params = Params(), keep_full: b
             parts_code.append(cd)
             parts_gap.append(gp)
     if keep_full:
-        pyr.A.append(np.concatenate(parts_A))
+        pyr.A.append(np.concatenate(parts_A) if parts_A else None)
     if lmax == 0:
         pyr.top = np.concatenate(parts_top)
         return pyr
@@ -535,33 +538,45 @@ def pyramid_backward(D1: np.ndarray, D2: np.ndarray, pyr: Pyramid):
             contrib = dA[pb, pa] / cnt[pb, pa][:, None, None]
             dCp[cb[pb, pa], ca[pb, pa], 1 + oy:1 + oy + h, 1 + ox:1 + ox + w] += contrib
         dCp = dCp[:, :, 1:1 + h, 1:1 + w]
-        # adjoint of S o P: route to the stored argmax
-        hp, wp = pyr.h[lv - 1], pyr.w[lv - 1]
-        dC = np.zeros((ny, nx, hp + 3, wp + 3))
-        code = pyr.code[lv - 1]
-        for my in (-1, 0, 1):
-            for mx in (-1, 0, 1):
-                k = 3 * (my + 1) + (mx + 1)
-                sel = np.where(code == k, dCp, 0.0)
-                dC[..., 1 + my:1 + my + 2 * h:2, 1 + mx:1 + mx + 2 * w:2] += sel
-        dC = dC[..., 1:1 + hp, 1:1 + wp]
-    A0 = pyr.A[0]
-    dA0 = np.where(A0 > 0, dC * lam * np.where(A0 > 0, A0, 1.0) ** (lam - 1.0), 0.0)
-    # adjoint of the bottom correlation, Eq. (3)
+        if lv == 1:
+            break   # dCp is the gradient of the pooled bottom maps C'_0
+        dC = unpool_adjoint(dCp, pyr.code[lv - 1], pyr.h[lv - 1], pyr.w[lv - 1])
+    # adjoint of the bottom correlation, Eq. (3), over chunks of patch rows
+    # (the bottom maps are full resolution; a chunk at a time bounds memory)
     Hh, Ww, C = D1.shape
     H2, W2, _ = D2.shape
     ny0, nx0 = lattice_shape(0, W, H)
-    cy = 2 + 4 * np.arange(ny0)
     cx = 2 + 4 * np.arange(nx0)
     D2p = np.zeros((H2 + 3, W2 + 3, C))
     D2p[2:2 + H2, 2:2 + W2] = D2
     dD1 = np.zeros_like(D1, dtype=np.float64)
     dD2p = np.zeros_like(D2p)
-    g = dA0.reshape(ny0 * nx0, H2 * W2) / 16.0
-    for dy in (-2, -1, 0, 1):
-        for dx in (-2, -1, 0, 1):
-            S = D2p[2 + dy:2 + dy + H2, 2 + dx:2 + dx + W2].reshape(-1, C)
-            P = D1[np.ix_(cy + dy, cx + dx)].reshape(-1, C)
-            dD1[np.ix_(cy + dy, cx + dx)] += (g @ S).reshape(ny0, nx0, C)
-            dD2p[2 + dy:2 + dy + H2, 2 + dx:2 + dx + W2] += (g.T @ P).reshape(H2, W2, C)
+    chunk = ny0 if pyr.A[0] is not None else 4
+    for r0 in range(0, ny0, chunk):
+        rows = np.arange(r0, min(ny0, r0 + chunk))
+        A0 = pyr.A[0][rows] if pyr.A[0] is not None else bottom_scores(D1, D2, rows)
+        # gradient of C_0: the top's own (lmax = 0) or routed through the pool
+        dC0 = dC[rows] if lmax == 0 else unpool_adjoint(dCp[rows], pyr.code[0][rows], H2, W2)
+        dA0 = np.where(A0 > 0, dC0 * lam * np.where(A0 > 0, A0, 1.0) ** (lam - 1.0), 0.0)
+        g = dA0.reshape(len(rows) * nx0, H2 * W2) / 16.0
+        cy = 2 + 4 * rows
+        for dy in (-2, -1, 0, 1):
+            for dx in (-2, -1, 0, 1):
+                S = D2p[2 + dy:2 + dy + H2, 2 + dx:2 + dx + W2].reshape(-1, C)
+                P = D1[np.ix_(cy + dy, cx + dx)].reshape(-1, C)
+                dD1[np.ix_(cy + dy, cx + dx)] += (g @ S).reshape(len(rows), nx0, C)
+                dD2p[2 + dy:2 + dy + H2, 2 + dx:2 + dx + W2] += (g.T @ P).reshape(H2, W2, C)
     return dD1, dD2p[2:2 + H2, 2:2 + W2]
+
+
+def unpool_adjoint(dCp: np.ndarray, code: np.ndarray, hp: int, wp: int) -> np.ndarray:
+    """Adjoint of S o P (Eqs. (8)-(9)): each pooled gradient goes to the
+    window position its stored argmax names, on the hp x wp map below."""
+    h, w = dCp.shape[-2:]
+    dC = np.zeros(dCp.shape[:-2] + (hp + 3, wp + 3))
+    for my in (-1, 0, 1):
+        for mx in (-1, 0, 1):
+            k = 3 * (my + 1) + (mx + 1)
+            sel = np.where(code == k, dCp, 0.0)
+            dC[..., 1 + my:1 + my + 2 * h:2, 1 + mx:1 + mx + 2 * w:2] += sel
+    return dC[..., 1:1 + hp, 1:1 + wp]

@@ -3,8 +3,9 @@
 Calls only oracle/ and synth/.  For each pair it stores the reciprocal matches
 [x1, y1, x2, y2, score], their decision margins, and the SHA-256 of the two
 input images, so a test can check that it regenerated the same inputs before
-comparing against the stored matches.  Usage:
-    python tests/golden/make_golden.py c3 [c2 ...]
+comparing against the stored matches.  With a name ending in "grad" (c3grad)
+it stores a sample of the oracle's gradient of the top loss instead.  Usage:
+    python tests/golden/make_golden.py c3 [c2 ...] [c3grad]
 """
 from __future__ import annotations
 
@@ -34,8 +35,41 @@ def path_of(name: str) -> str:
     return os.path.join(HERE, f"{name}_oracle.npz")
 
 
+def grad_path_of(name: str) -> str:
+    return os.path.join(HERE, f"{name}_grad_oracle.npz")
+
+
+def make_grad(name: str, n_sample: int = 4096, n_top: int = 256):
+    """The FP64 oracle gradient of L = sum of the top-map maxima with respect
+    to both descriptor fields, from the oracle's own descriptors of the pair,
+    at a seeded sample of coordinates plus the largest entries (the full
+    fields are too large to store)."""
+    p = synth.make_pair(name)
+    D1, D2 = O.descriptors(p["img1"]), O.descriptors(p["img2"])
+    lam32 = float(np.float32(1.4))   # the library's lambda is a float32 parameter
+    prm = O.Params(max_patch=synth.CONFIG_NMAX[name], lam=lam32)
+    t0 = time.time()
+    pyr = O.pyramid(D1, D2, prm, keep_full=True, keep_bottom=False)
+    g1, g2 = O.pyramid_backward(D1, D2, pyr)
+    dt = time.time() - t0
+    rng = np.random.default_rng(20261)
+    out = dict(sha256=image_hash(p["img1"], p["img2"]), lmax=pyr.lmax, loss=O.top_loss(pyr), oracle_seconds=dt)
+    for k, g in (("1", g1), ("2", g2)):
+        flat = g.reshape(-1)
+        idx = np.union1d(rng.choice(flat.size, n_sample, replace=False), np.argsort(-np.abs(flat))[:n_top])
+        out["idx" + k] = idx.astype(np.int64)
+        out["val" + k] = flat[idx]
+        out["norm" + k] = float(np.linalg.norm(flat))
+    np.savez_compressed(grad_path_of(name), **out)
+    print(f"{name} gradient: lmax {pyr.lmax}, loss {out['loss']:.6f}, |g1| {out['norm1']:.4e}, "
+          f"|g2| {out['norm2']:.4e}, {dt:.1f} s", flush=True)
+
+
 def main(names):
     for name in names:
+        if name.endswith("grad"):
+            make_grad(name[:-4])
+            continue
         p = synth.make_pair(name)
         prm = O.Params(max_patch=synth.CONFIG_NMAX[name])
         t0 = time.time()
