@@ -282,6 +282,21 @@ def copy_probe(torch):
     torch.cuda.synchronize()
 
 
+def copy_bandwidth(torch, reps: int = 10) -> float:
+    """Achievable HBM bandwidth on this GPU: a 1 GiB device-to-device copy
+    (1 GiB read + 1 GiB written per copy), timed with HIP events; GB/s."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2.0 * (1 << 30) * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,6 +348,7 @@ def main():
             fb[f"{prec}{'_recompute' if rc else ''}"] = dict(pairs_s=round(1.0 / dt, 3), ms_per_step=round(dt * 1e3, 4),
                                                           stages=stages)
     head = res["bf16"]
+    copy_gbs = copy_bandwidth(torch)
     rows = roofline_of(head["stages"], head["plan"], "bf16")
     dom = rows[0]
     rows32 = roofline_of(res["fp32"]["stages"], res["fp32"]["plan"], "fp32")
@@ -368,7 +384,10 @@ def main():
                      "peak": dom["peak"], "unit": dom["unit"], "frac": round(dom["frac"], 4),
                      "traffic": MEASURED_TRAFFIC_512x256.get(dom["kernel"]),
                      "algorithmic_bytes": round(dom["work"]) if dom["unit"] == "GB/s" else None,
-                     "avg_ms": round(dom["avg_ms"], 5)},
+                     "avg_ms": round(dom["avg_ms"], 5),
+                     # context: the bandwidth a plain 1 GiB copy reaches on this GPU
+                     "copy_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(dom["achieved"] / copy_gbs, 4) if dom["unit"] == "GB/s" else None},
         "kernels_bf16": [dict({k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items() if k != "work"},
                               traffic=MEASURED_TRAFFIC_512x256.get(r["kernel"])) for r in rows],
         "kernels_fp32": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items() if k != "work"}
