@@ -56,6 +56,29 @@ library takes the same ones):
  R13 Loss for the gradient: the sum over top-level patches of the maximum of
      their rectified map (ties: first in raster order).
 
+ R14 Near-ties: decisions whose FP64 gap is below 2e-5 (1 + score) may go
+     either way in FP32 (the GPU tests leave them out of exact comparisons).
+ R15 lambda is a float32 parameter of the library.
+ R16 Approximate DeepMatching (Sec. 4.1): k-means runs over the vectors of
+     the atomic patches of I (the 16 pixel descriptors of the 4x4 patch in
+     (dy, dx, channel) order, 144 values, norm 4 since every pixel descriptor
+     has norm 1).  Keeping the centroids on the inputs' hypersphere means
+     rescaling each one to norm 4 after every update.  D ranges over
+     1 .. |G_4|; D = 0 is the exact method.
+ R17 The paper does not say how k-means starts: centroid d starts as atomic
+     patch floor((2d + 1) n / (2D)) of the n patches in raster order (evenly
+     spread over the image, no random draw; D = n starts from every patch).
+ R18 A fixed number of iterations (default 10), each an assignment then an
+     update; a final assignment follows the last update.  Assignment: the
+     nearest centroid on the sphere, i.e. the largest dot product; dot
+     products within 1e-11 of the largest count as equal and the lowest
+     index wins.  Update: the sum of the assigned vectors rescaled to norm 4;
+     a centroid with no vector keeps its value.
+ R19 Each atomic patch takes its prototype's bottom map C'_0; every level
+     above is computed per patch as in the exact method (parents whose
+     children have the same prototypes get equal maps; sharing them would
+     save work but changes no value).
+
 Parity of the descriptor against the paper itself is unpinned (R10 fills in
 details the paper does not give); it is pinned only by its invariants.
 """
@@ -82,6 +105,10 @@ class Params:
     scale: float = 255.0
     lam: float = 1.4
     max_patch: int = 0
+    # Approximate DeepMatching (Sec. 4.1): D prototypes (0 = the exact
+    # method) and the spherical k-means iterations (R16-R19).
+    prototypes: int = 0
+    kmeans_iters: int = 10
 
 
 # ----------------------------------------------------------------------------
@@ -295,6 +322,8 @@ class Pyramid:
     gap: list = field(default_factory=list)     # top-2 gaps of the pooling
     top: np.ndarray = None                      # C_lmax (unpooled)
     A: list = field(default_factory=list)       # pre-rectification maps (keep_full)
+    protos: np.ndarray = None                   # approximate DM: prototypes (D x 144)
+    assign: np.ndarray = None                   # approximate DM: prototype of each atomic patch
 
 
 def aggregate(prev_pooled: np.ndarray, lv: int, pyr: Pyramid) -> np.ndarray:
@@ -317,6 +346,71 @@ def aggregate(prev_pooled: np.ndarray, lv: int, pyr: Pyramid) -> np.ndarray:
     return A
 
 
+# ----------------------------------------------------------------------------
+# Approximate DeepMatching: spherical k-means prototypes (Sec. 4.1, R16-R19)
+# ----------------------------------------------------------------------------
+
+KMEANS_TIE = 1e-11      # R18: dot products this close to the largest count as equal
+SPHERE_RADIUS = 4.0     # R16: norm of an atomic patch vector
+
+
+def kmeans_init(n: int, D: int) -> np.ndarray:
+    """Indices of the D starting centroids among n patches (R17)."""
+    if not 1 <= D <= n:
+        raise ValueError("the number of prototypes must be in [1, number of atomic patches]")
+    return (2 * np.arange(D, dtype=np.int64) + 1) * n // (2 * D)
+
+
+def nearest_prototype(X: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """Index of the nearest centroid of each row of X on the sphere: the
+    largest dot product, ties within KMEANS_TIE to the lowest index (R18)."""
+    S = X @ C.T
+    return np.argmax(S >= S.max(axis=1, keepdims=True) - KMEANS_TIE, axis=1)
+
+
+def atomic_patch_vectors(D1: np.ndarray) -> np.ndarray:
+    """The 144-vector of every atomic patch of G_4 in lattice order: its 16
+    pixel descriptors in (dy, dx) raster order, channels innermost (R8, R16)."""
+    H, W, C = D1.shape
+    ny, nx = lattice_shape(0, W, H)
+    cy, cx = 2 + 4 * np.arange(ny), 2 + 4 * np.arange(nx)
+    offs = [(dy, dx) for dy in (-2, -1, 0, 1) for dx in (-2, -1, 0, 1)]
+    return np.concatenate([D1[np.ix_(cy + dy, cx + dx)].reshape(-1, C) for dy, dx in offs], axis=1)
+
+
+def spherical_kmeans(X: np.ndarray, D: int, iters: int, radius: float = SPHERE_RADIUS):
+    """Spherical k-means (Sec. 4.1): the D prototypes, each of norm `radius`,
+    and the prototype of every row of X (R16-R18)."""
+    C = X[kmeans_init(len(X), D)].astype(np.float64)
+    C *= radius / np.linalg.norm(C, axis=1, keepdims=True)
+    for _ in range(iters):
+        a = nearest_prototype(X, C)
+        for d in range(D):
+            s = X[a == d].sum(axis=0)
+            ns = np.linalg.norm(s)
+            if ns > 0:
+                C[d] = s * (radius / ns)
+    return C, nearest_prototype(X, C)
+
+
+def kmeans_objective(X: np.ndarray, C: np.ndarray, a: np.ndarray) -> float:
+    """Sum over the rows of X of the dot product with their centroid, the
+    quantity spherical k-means increases at every step."""
+    return float(np.einsum("pk,pk->", X, C[a]))
+
+
+def prototype_scores(C: np.ndarray, D2: np.ndarray) -> np.ndarray:
+    """A_0 for prototype vectors instead of atomic patches: Eq. (3) with the
+    patch vector replaced by its prototype (same (dy, dx, channel) order).
+    Returns shape (D, H', W')."""
+    H2, W2, Cc = D2.shape
+    D2p = np.zeros((H2 + 3, W2 + 3, Cc))
+    D2p[2:2 + H2, 2:2 + W2] = D2
+    offs = [(dy, dx) for dy in (-2, -1, 0, 1) for dx in (-2, -1, 0, 1)]
+    S = np.concatenate([D2p[2 + dy:2 + dy + H2, 2 + dx:2 + dx + W2].reshape(-1, Cc) for dy, dx in offs], axis=1)
+    return ((C @ S.T) / 16.0).reshape(len(C), H2, W2)
+
+
 def pyramid(D1: np.ndarray, D2: np.ndarray, prm: Params = Params(), keep_full: bool = False,
             row_chunk: int = 8, keep_bottom: bool = True) -> Pyramid:
     """Multi-level correlation pyramid, Algorithm 1.  keep_full keeps the
@@ -329,7 +423,25 @@ def pyramid(D1: np.ndarray, D2: np.ndarray, prm: Params = Params(), keep_full: b
     G = grids(W, H, lmax)
     h, w = map_dims(H2, W2, lmax)
     pyr = Pyramid(W, H, W2, H2, lmax, prm.lam, G, h, w)
-    ny0 = lattice_shape(0, W, H)[0]
+    ny0, nx0 = lattice_shape(0, W, H)
+    if prm.prototypes > 0:
+        # Approximate DeepMatching: C_0 and (S o P)(C_0) of the D prototypes,
+        # then every atomic patch takes its prototype's (R19).
+        if keep_full:
+            raise ValueError("the gradient is defined for the exact method only (no prototypes)")
+        X = atomic_patch_vectors(D1)
+        pyr.protos, pyr.assign = spherical_kmeans(X, prm.prototypes, prm.kmeans_iters)
+        a2 = pyr.assign.reshape(ny0, nx0)
+        chunks = range(0, prm.prototypes, 64)
+        if lmax == 0:
+            pyr.top = np.concatenate([rectify(prototype_scores(pyr.protos[d:d + 64], D2), prm.lam)
+                                      for d in chunks])[a2]
+            return pyr
+        pooled = [pool_subsample(rectify(prototype_scores(pyr.protos[d:d + 64], D2), prm.lam)) for d in chunks]
+        pyr.Cp.append(np.concatenate([q[0] for q in pooled])[a2])
+        pyr.code.append(np.concatenate([q[1] for q in pooled])[a2])
+        pyr.gap.append(np.concatenate([q[2] for q in pooled])[a2])
+        return _upper_levels(pyr, prm, keep_full)
     # Level 0: C_4 = R_lambda(I_4^F * I'), then S o P unless it is the top.
     parts_cp, parts_code, parts_gap, parts_A, parts_top = [], [], [], [], []
     for r0 in range(0, ny0, row_chunk):
@@ -352,6 +464,12 @@ def pyramid(D1: np.ndarray, D2: np.ndarray, prm: Params = Params(), keep_full: b
     pyr.Cp.append(np.concatenate(parts_cp))
     pyr.code.append(np.concatenate(parts_code))
     pyr.gap.append(np.concatenate(parts_gap))
+    return _upper_levels(pyr, prm, keep_full)
+
+
+def _upper_levels(pyr: Pyramid, prm: Params, keep_full: bool) -> Pyramid:
+    """Levels 1..lmax of Algorithm 1 from the pooled level 0 in `pyr`."""
+    lmax = pyr.lmax
     for lv in range(1, lmax + 1):
         A = aggregate(pyr.Cp[lv - 1], lv, pyr)
         C = rectify(A, prm.lam)
@@ -508,6 +626,8 @@ def pyramid_backward(D1: np.ndarray, D2: np.ndarray, pyr: Pyramid):
     rectification, shift-average, max-pool/subsample (routed to the stored
     argmax) and the bottom correlation.  `pyr` must come from
     pyramid(..., keep_full=True)."""
+    if pyr.assign is not None:
+        raise ValueError("the gradient is defined for the exact method only (no prototypes)")
     W, H, lmax, lam = pyr.W, pyr.H, pyr.lmax, pyr.lam
     top = pyr.top
     G = pyr.G[lmax]

@@ -493,3 +493,123 @@ def test_gradient_matches_autograd_reexpression():
     L.backward()
     np.testing.assert_allclose(g1, t1.grad.numpy(), rtol=1e-10, atol=1e-13)
     np.testing.assert_allclose(g2, t2.grad.numpy(), rtol=1e-10, atol=1e-13)
+
+
+# ---------------------------------------------------------------- approximate DeepMatching (Sec. 4.1)
+
+def _sphere_patches(rng, n):
+    """n atomic-patch vectors: 16 unit pixel descriptors each (norm 4)."""
+    P = rng.random((n, 16, 9)) + 0.05
+    P /= np.linalg.norm(P, axis=-1, keepdims=True)
+    return P.reshape(n, 144)
+
+
+def test_kmeans_init_evenly_spread():
+    assert O.kmeans_init(10, 10).tolist() == list(range(10))
+    assert O.kmeans_init(10, 3).tolist() == [1, 5, 8]
+    assert O.kmeans_init(7, 1).tolist() == [3]
+    for n, D in ((1000, 999), (1000, 7), (8192, 1024), (6912, 4096)):
+        idx = O.kmeans_init(n, D)
+        assert len(np.unique(idx)) == D and idx.min() >= 0 and idx.max() < n
+    for D in (0, 11):
+        with pytest.raises(ValueError):
+            O.kmeans_init(10, D)
+
+
+def test_kmeans_single_prototype_is_mean_direction():
+    # Cauchy-Schwarz: over the sphere of radius 4, sum_p <x_p, c> peaks at
+    # c = 4 s / |s| with s = sum_p x_p.
+    X = _sphere_patches(np.random.default_rng(30), 50)
+    for iters in (0, 1, 5):
+        C, a = O.spherical_kmeans(X, 1, iters)
+        s = X.sum(0)
+        if iters:
+            np.testing.assert_allclose(C[0], 4 * s / np.linalg.norm(s), rtol=0, atol=1e-13)
+        assert (a == 0).all()
+
+
+def test_kmeans_objective_monotone_and_on_sphere():
+    X = _sphere_patches(np.random.default_rng(31), 300)
+    prev = -np.inf
+    for iters in range(8):
+        C, a = O.spherical_kmeans(X, 12, iters)
+        np.testing.assert_allclose(np.linalg.norm(C, axis=1), 4.0, rtol=0, atol=1e-12)
+        J = O.kmeans_objective(X, C, a)
+        assert J >= prev - 1e-9, (iters, J, prev)
+        # every vector sits with a nearest centroid
+        S = X @ C.T
+        assert (S[np.arange(len(X)), a] >= S.max(1) - 1e-12).all()
+        prev = J
+
+
+def test_kmeans_reaches_bruteforce_optimum_on_separated_data():
+    # Two well-separated groups of 3 vectors: the best partition over all
+    # 2^6 splits, scored by sum_k 4 |sum of group k| (the objective with each
+    # centroid at its optimum), is what k-means converges to.
+    rng = np.random.default_rng(32)
+    base = _sphere_patches(rng, 2)
+    X = []
+    for g in (0, 1, 0, 1, 1, 0):
+        v = base[g].reshape(16, 9) + 0.01 * rng.random((16, 9))
+        X.append((v / np.linalg.norm(v, axis=-1, keepdims=True)).ravel())
+    X = np.array(X)
+    best = max(sum(4 * np.linalg.norm(X[[i for i in range(6) if (m >> i) & 1 == k]].sum(0)) for k in (0, 1))
+               for m in range(1, 63))
+    C, a = O.spherical_kmeans(X, 2, 10)
+    assert abs(O.kmeans_objective(X, C, a) - best) < 1e-10
+    assert len(set(a[[0, 2, 5]])) == 1 and len(set(a[[1, 3, 4]])) == 1 and a[0] != a[1]
+
+
+def test_kmeans_ties_go_to_lowest_index():
+    X = _sphere_patches(np.random.default_rng(33), 4)
+    C = np.stack([X[1], X[0], X[0], X[1]])
+    assert O.nearest_prototype(X[:2], C).tolist() == [1, 0]
+
+
+def _substituted(D1, pyr):
+    """D1 with every atomic patch replaced by its prototype (Sec. 4.1)."""
+    H, W, _ = D1.shape
+    ny, nx = O.lattice_shape(0, W, H)
+    S = D1.copy()
+    P = pyr.protos[pyr.assign].reshape(ny, nx, 4, 4, 9)
+    for b in range(ny):
+        for a in range(nx):
+            S[4 * b:4 * b + 4, 4 * a:4 * a + 4] = P[b, a]
+    return S
+
+
+@pytest.mark.parametrize("D", [1, 5, 37])
+def test_approx_equals_exact_method_on_substituted_patches(D):
+    # Each patch replaced by its closest prototype, then the exact method:
+    # the same pyramid and matches as the approximate path.
+    rng = np.random.default_rng(34)
+    D1, D2 = rand_desc(rng, 30, 27), rand_desc(rng, 26, 29)
+    prm = O.Params(max_patch=16, prototypes=D, kmeans_iters=4)
+    out, margin, pyr, _ = O.match_descriptors(D1, D2, prm)
+    assert pyr.protos.shape == (D, 144) and pyr.assign.shape == (7 * 6,)
+    ex_prm = O.Params(max_patch=16)
+    out_e, _, pyr_e, _ = O.match_descriptors(_substituted(D1, pyr), D2, ex_prm)
+    for lv in range(pyr.lmax):
+        np.testing.assert_allclose(pyr.Cp[lv], pyr_e.Cp[lv], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(pyr.top, pyr_e.top, rtol=1e-12, atol=1e-14)
+    assert out.shape == out_e.shape
+    np.testing.assert_array_equal(out[:, :4], out_e[:, :4])
+    np.testing.assert_allclose(out[:, 4], out_e[:, 4], rtol=1e-12)
+
+
+def test_approx_with_every_patch_a_prototype_is_the_exact_method():
+    rng = np.random.default_rng(35)
+    D1, D2 = rand_desc(rng, 24, 28), rand_desc(rng, 25, 22)
+    n = 6 * 7
+    out, _, pyr, _ = O.match_descriptors(D1, D2, O.Params(max_patch=16, prototypes=n, kmeans_iters=3))
+    assert pyr.assign.tolist() == list(range(n))
+    out_e, _, pyr_e, _ = O.match_descriptors(D1, D2, O.Params(max_patch=16))
+    np.testing.assert_allclose(pyr.Cp[0], pyr_e.Cp[0], rtol=1e-12)
+    np.testing.assert_array_equal(out[:, :4], out_e[:, :4])
+
+
+def test_gradient_rejects_prototypes():
+    rng = np.random.default_rng(36)
+    D1, D2 = rand_desc(rng, 16, 16), rand_desc(rng, 16, 16)
+    with pytest.raises(ValueError):
+        O.pyramid(D1, D2, O.Params(max_patch=16, prototypes=4), keep_full=True)
