@@ -42,6 +42,7 @@ extern "C" {
 
 #define DM_MAX_LEVELS 16   /* level index l < 16, patch size N = 4 * 2^l   */
 #define DM_MAX_DIM 8192    /* largest supported image width or height      */
+#define DM_MAX_PROTOTYPES 4096  /* largest prototype dictionary (Sec. 4.1) */
 
 typedef enum {
     DM_OK = 0,
@@ -66,12 +67,27 @@ typedef enum {
  * ninth component mu, intensities multiplied by intensity_scale.
  * Rectification exponent lambda (Eq. (11)).  max_patch: pyramid top N_max
  * (power of two >= 4), 0 = the loop bound of Algorithm 1 (N < max(W, H));
- * either way capped at the last level whose patch grid is non-empty. */
+ * either way capped at the last level whose patch grid is non-empty.
+ *
+ * Approximate DeepMatching (Sec. 4.1), matching calls only: with
+ * prototypes = D > 0 the atomic patches of I are clustered by spherical
+ * k-means into D prototypes (centroids kept at the norm 4 of a patch vector,
+ * i.e. its 16 unit pixel descriptors in (dy, dx, channel) order), and each
+ * patch takes the bottom map C'_0 of its nearest prototype, so the bottom
+ * correlation computes and stores D maps instead of one per patch.
+ * Centroid d starts as atomic patch floor((2d+1) n / (2D)) of the n patches
+ * in raster order; kmeans_iters rounds of assignment (largest dot product;
+ * within 1e-11 of the largest, the lowest index) and update (sum of the
+ * members rescaled to norm 4; no members: unchanged), then a final
+ * assignment.  Decisions are those of an FP64 evaluation.  1 <= D <=
+ * min(n, DM_MAX_PROTOTYPES); D = 0 is the exact method. */
 typedef struct {
     float nu1, nu2, nu3, sigmoid_slope, mu, intensity_scale, lambda;
     int32_t max_patch;
     int32_t precision;          /* dm_precision */
-    int32_t reserved[7];        /* must be 0 */
+    int32_t prototypes;         /* D of approximate DeepMatching, 0 = exact     */
+    int32_t kmeans_iters;       /* k-means rounds (prototypes > 0), 0..1000     */
+    int32_t reserved[5];        /* must be 0 */
 } dm_params;
 
 /* One correspondence: atomic patch centre p = (x1, y1) in I, pixel
@@ -100,6 +116,12 @@ typedef struct {
  *   off_desc1/2 descriptors of I and I' (dm_match_images), float32 HWC
  *   off_best    per atomic patch: packed best tuple (uint64)
  *   off_cell    per 4x4 target cell: packed best tuple (uint64)
+ * With prototypes = D > 0, off_cp[0] / off_code[0] hold the D prototype maps
+ * [D][h[1]][w[1]] (patch p's map is that of prototype assign[p]) and
+ *   off_protos  the prototypes, float64 [D][144], (dy, dx, channel) order
+ *   off_assign  prototype of each atomic patch, int32 [gy[0]][gx[0]]
+ *   off_kstat   int32 [2]: assignments settled in FP64 over all k-means
+ *               rounds (between two candidates; over every centroid)
  */
 typedef struct {
     int32_t W1, H1, W2, H2;
@@ -113,11 +135,16 @@ typedef struct {
     uint64_t off_cp[DM_MAX_LEVELS], off_code[DM_MAX_LEVELS], off_u[DM_MAX_LEVELS];
     uint64_t off_top, off_desc1, off_desc2, off_bf1, off_bf2, off_valid;
     uint64_t off_best, off_cell, off_misc;
+    int32_t prototypes;        /* D (0: exact method)                         */
+    int32_t kmeans_chunks;     /* centroid chunks of the k-means FP32 pass     */
+    uint64_t off_protos, off_assign, off_kstat;
+    uint64_t off_proto_img, off_proto_bf, off_kpart;   /* k-means scratch     */
     uint64_t workspace_bytes;
 } dm_plan_info;
 
 /* Fills *p with the defaults: nu1=0, nu2=nu3=1, sigmoid_slope=0.2, mu=0.1,
- * intensity_scale=255, lambda=1.4, max_patch=0, precision=DM_FP32.
+ * intensity_scale=255, lambda=1.4, max_patch=0, precision=DM_FP32,
+ * prototypes=0 (exact), kmeans_iters=10.
  * Host only.  Errors: DM_ERR_INVALID_ARG if p is null. */
 dm_status dm_default_params(dm_params* p);
 
@@ -125,8 +152,10 @@ dm_status dm_default_params(dm_params* p);
  * grids, map sizes (Algorithm 1 with the boundary rule of Sec. 3.2) and the
  * workspace layout, written to *out.  Host only; touches no device.
  * Errors: DM_ERR_INVALID_ARG (null pointer, parameter out of range,
- * max_patch not a power of two >= 4), DM_ERR_SHAPE (W1 or H1 < 4, W2 or
- * H2 < 1, any size above DM_MAX_DIM). */
+ * max_patch not a power of two >= 4, prototypes above the number of atomic
+ * patches), DM_ERR_SHAPE (W1 or H1 < 4, W2 or H2 < 1, any size above
+ * DM_MAX_DIM), DM_ERR_UNSUPPORTED (prototypes with DM_FP64 or with a
+ * single-level pyramid). */
 dm_status dm_plan(const dm_params* prm, int W1, int H1, int W2, int H2, dm_plan_info* out);
 
 /* Per-pixel descriptors of one image (Sec. 3.2, "Pixel descriptor"):
@@ -191,7 +220,8 @@ typedef struct {
 
 /* Plans dm_pyramid_forward / dm_pyramid_backward for a pair of sizes.
  * Host only.  Errors as dm_plan; DM_ERR_UNSUPPORTED if the pyramid has a
- * single level (N_max = 4: no pooled level to route through). */
+ * single level (N_max = 4: no pooled level to route through) or
+ * prototypes != 0 (the gradient is that of the exact method). */
 dm_status dm_plan_grad(const dm_params* prm, int W1, int H1, int W2, int H2, int recompute, dm_grad_plan* out);
 
 /* Forward pyramid of descriptor fields d1 (H1 x W1 x 9) and d2 (H2 x W2 x 9),
@@ -271,7 +301,8 @@ typedef struct {
 
 /* Sizes of a batch of n pairs (1 <= n <= DM_MAX_BATCH).  Host only; reads
  * the sizes in pairs[] only.  Errors: DM_ERR_INVALID_ARG, DM_ERR_SHAPE,
- * DM_ERR_UNSUPPORTED (FP64, or a pair without a pooled level). */
+ * DM_ERR_UNSUPPORTED (FP64, prototypes != 0, or a pair without a pooled
+ * level). */
 dm_status dm_plan_batch(int n, const dm_pair* pairs, const dm_params* prm, int flags, dm_batch_info* out);
 
 /* Matches of every pair: pair k writes its matches (sorted by (y1, x1)) to

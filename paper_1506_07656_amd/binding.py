@@ -30,7 +30,8 @@ class DMError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("nu1", c_float), ("nu2", c_float), ("nu3", c_float), ("sigmoid_slope", c_float),
                 ("mu", c_float), ("intensity_scale", c_float), ("lam", c_float),
-                ("max_patch", c_int32), ("precision", c_int32), ("reserved", c_int32 * 7)]
+                ("max_patch", c_int32), ("precision", c_int32), ("prototypes", c_int32),
+                ("kmeans_iters", c_int32), ("reserved", c_int32 * 5)]
 
 
 class Match(ctypes.Structure):
@@ -50,6 +51,9 @@ class PlanInfo(ctypes.Structure):
                 ("off_top", c_uint64), ("off_desc1", c_uint64), ("off_desc2", c_uint64),
                 ("off_bf1", c_uint64), ("off_bf2", c_uint64), ("off_valid", c_uint64),
                 ("off_best", c_uint64), ("off_cell", c_uint64), ("off_misc", c_uint64),
+                ("prototypes", c_int32), ("kmeans_chunks", c_int32),
+                ("off_protos", c_uint64), ("off_assign", c_uint64), ("off_kstat", c_uint64),
+                ("off_proto_img", c_uint64), ("off_proto_bf", c_uint64), ("off_kpart", c_uint64),
                 ("workspace_bytes", c_uint64)]
 
 
@@ -137,7 +141,8 @@ def _check(status: int):
 
 def params(**kw) -> Params:
     """Library defaults overridden by keyword (nu1, nu2, nu3, sigmoid_slope, mu,
-    intensity_scale, lam, max_patch, precision in {'fp32','bf16','fp64'} or int)."""
+    intensity_scale, lam, max_patch, precision in {'fp32','bf16','fp64'} or int,
+    prototypes, kmeans_iters)."""
     p = Params()
     _check(lib().dm_default_params(ctypes.byref(p)))
     for k, v in kw.items():
@@ -279,6 +284,8 @@ def workspace_views(ws: torch.Tensor, pl: PlanInfo) -> dict:
     levels = []
     for lv in range(pl.lmax):
         shp = (pl.gy[lv], pl.gx[lv], pl.h[lv + 1], pl.w[lv + 1])
+        if lv == 0 and pl.prototypes:   # the D prototype maps
+            shp = (1, pl.prototypes, pl.h[1], pl.w[1])
         n = shp[0] * shp[1] * shp[2] * shp[3]
         d = dict(cp=view(pl.off_cp[lv], n, fdt, shp, fsz), code=view(pl.off_code[lv], n, torch.uint8, shp, 1))
         if lv >= 1:
@@ -291,6 +298,11 @@ def workspace_views(ws: torch.Tensor, pl: PlanInfo) -> dict:
     out["best"] = view(pl.off_best, pl.n_atomic, torch.int64, (pl.n_atomic,), 8)
     out["desc1"] = view(pl.off_desc1, pl.H1 * pl.W1 * 9, fdt, (pl.H1, pl.W1, 9), fsz)
     out["desc2"] = view(pl.off_desc2, pl.H2 * pl.W2 * 9, fdt, (pl.H2, pl.W2, 9), fsz)
+    if pl.prototypes:
+        D = pl.prototypes
+        out["protos"] = view(pl.off_protos, D * 144, torch.float64, (D, 144), 8)
+        out["assign"] = view(pl.off_assign, pl.n_atomic, torch.int32, (pl.gy[0], pl.gx[0]), 4)
+        out["kstat"] = view(pl.off_kstat, 2, torch.int32, (2,), 4)
     return out
 
 

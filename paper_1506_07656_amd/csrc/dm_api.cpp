@@ -34,7 +34,7 @@ inline P* at(void* ws, uint64_t off) {
 // Stages a1..a4 on descriptors d1, d2 (float32) already in device memory.
 dm_status run_match(const float* d1, const float* d2, const dm_plan_info& pi, const dm_params* prm, void* ws,
                     bool have_bf16, dm_match* out, int* n_out, hipStream_t s) {
-    const Geom g = make_geom(pi);
+    Geom g = make_geom(pi);
     const float lam = prm->lambda;
     uint8_t* vt = at<uint8_t>(ws, pi.off_valid);
     DM_LAUNCH("valid_init", -1, launch_valid_init(g, vt, s));
@@ -43,7 +43,49 @@ dm_status run_match(const float* d1, const float* d2, const dm_plan_info& pi, co
     auto code = [&](int l) { return at<uint8_t>(ws, pi.off_code[l]); };
     auto u = [&](int l) { return at<float>(ws, pi.off_u[l]); };
     // a1: bottom correlation + rectification + pooled level 0.
-    if (pi.lmax == 0) {
+    if (pi.prototypes > 0) {
+        // Approximate DeepMatching (Sec. 4.1): the D prototype maps, computed
+        // by the bottom kernels on the prototype image (one row of D atomic
+        // patches); level 1 and the bottom backtracking read patch p's map
+        // through the assignment.
+        const int D = pi.prototypes;
+        const int na = pi.n_atomic;
+        KmArgs km;
+        km.d1 = d1;
+        km.W1 = pi.W1;
+        km.gx0 = pi.gx[0];
+        km.n = na;
+        km.D = D;
+        km.nchunk = pi.kmeans_chunks;
+        km.C64 = at<double>(ws, pi.off_protos);
+        km.img = at<float>(ws, pi.off_proto_img);
+        km.img16 = prm->precision == DM_BF16 ? at<uint16_t>(ws, pi.off_proto_bf) : nullptr;
+        km.assign = at<int>(ws, pi.off_assign);
+        float* part = at<float>(ws, pi.off_kpart);
+        const size_t pn = (size_t)km.nchunk * na;
+        km.pv1 = part;
+        km.pv2 = part + pn;
+        km.pv3 = part + 2 * pn;
+        km.pi1 = reinterpret_cast<int*>(part + 3 * pn);
+        km.pi2 = reinterpret_cast<int*>(part + 4 * pn);
+        km.stat = at<int>(ws, pi.off_kstat);
+        const dm_status st = check_hip(launch_kmeans(km, prm->kmeans_iters, s), "kmeans");
+        if (st != DM_OK) return st;
+        Geom gp = g;   // the prototype image: 4 x 4D pixels, D atomic patches in one row
+        gp.W1 = 4 * D;
+        gp.H1 = 4;
+        gp.gx[0] = D;
+        gp.gy[0] = 1;
+        if (prm->precision == DM_BF16) {
+            uint16_t* b2 = at<uint16_t>(ws, pi.off_bf2);
+            if (!have_bf16) DM_LAUNCH("to_bf16", -1, launch_to_bf16(d2, pi.W2 * pi.H2, b2, s));
+            DM_LAUNCH("corr_pool_bf16", 0, launch_corr_pool_bf16(km.img16, b2, gp, lam, cp(0), code(0), s));
+        } else {
+            DM_LAUNCH("corr_pool_f32", 0, launch_corr_pool_f32(km.img, d2, gp, lam, cp(0), code(0), s));
+        }
+        g.slot0 = km.assign;
+        g.nslot0 = D;
+    } else if (pi.lmax == 0) {
         DM_LAUNCH("corr_top", 0, launch_corr_top<float>(d1, d2, g, lam, top, s));
     } else if (prm->precision == DM_BF16) {
         uint16_t* b1 = at<uint16_t>(ws, pi.off_bf1);
@@ -227,6 +269,8 @@ dm_status dm_default_params(dm_params* p) {
     p->lambda = 1.4f;
     p->max_patch = 0;
     p->precision = DM_FP32;
+    p->prototypes = 0;
+    p->kmeans_iters = 10;
     return DM_OK;
 }
 

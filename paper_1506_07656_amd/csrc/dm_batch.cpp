@@ -121,6 +121,7 @@ dm_status plan_pairs(int n, const dm_pair* pairs, const dm_params* prm, int flag
     dm_status st = check_params(prm);
     if (st != DM_OK) return st;
     if (prm->precision == DM_FP64) return fail(DM_ERR_UNSUPPORTED, "batches run in DM_FP32 or DM_BF16");
+    if (prm->prototypes) return fail(DM_ERR_UNSUPPORTED, "batches run the exact method (prototypes = 0)");
     P.assign(n, PairLayout());
     uint64_t off = 0;
     for (int k = 0; k < n; ++k) {

@@ -20,7 +20,17 @@ struct Geom {
     int gx[DM_MAX_LEVELS], gy[DM_MAX_LEVELS];
     int h[DM_MAX_LEVELS + 1], w[DM_MAX_LEVELS + 1];
     int vstride;  // bytes per validity table (one per level and axis)
+    // Approximate DeepMatching: C'_0 holds nslot0 prototype maps and atomic
+    // patch p reads map slot0[p]; null for the exact method (map p).
+    const int32_t* slot0;
+    int nslot0;
 };
+
+// Map index, in the level l-1 buffer, of child lattice index c of a level-l
+// parent.
+__host__ __device__ inline int child_slot(const Geom& g, int l, int c) {
+    return (l == 1 && g.slot0) ? g.slot0[c] : c;
+}
 
 // Lattice index, at level l-1, of the child of lattice index `a` at level l
 // on the side s in {-1,+1} of one axis (Eq. (5): child centre = parent centre
@@ -159,6 +169,26 @@ JobRec top_grad_job(const float* top, const Geom& g, float* dtop);
 hipError_t launch_group_bot(int kind, const GroupLaunch& gl, hipStream_t s);
 std::vector<JobRec> bot_jobs(bool bf16, const float* gp, const uint8_t* code, const float* d1, const float* d2,
                              const Geom& g, float* part, float* tbuf, void* dense, float* dd1, float* dd2);
+
+// Approximate DeepMatching: spherical k-means of the atomic patches of I
+// (k_kmeans.hip).  d1: FP32 descriptors of I; n = gx0 * gy0 patches; D
+// centroids; C64 [D][144]; img / img16: the prototype image (4 x 4D pixels,
+// 9 floats / 10 bf16 per pixel; img16 may be null); pv*/pi*: [nchunk][n]
+// candidates of the FP32 pass; stat[2]: patches settled in FP64.
+struct KmArgs {
+    const float* d1;
+    int W1, gx0, n, D, nchunk;
+    double* C64;
+    float* img;
+    uint16_t* img16;
+    int* assign;
+    float *pv1, *pv2, *pv3;
+    int *pi1, *pi2;
+    int* stat;
+};
+constexpr int KM_CH = 64;   // centroids per chunk of the FP32 pass
+int kmeans_chunks(int D);
+hipError_t launch_kmeans(const KmArgs& a, int iters, hipStream_t s);
 
 // Opt-in stage timing (dm_timing.cpp); calls may nest.
 void timing_begin(const char* name, int level, hipStream_t s);

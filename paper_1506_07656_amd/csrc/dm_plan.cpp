@@ -48,6 +48,10 @@ dm_status check_params(const dm_params* p) {
         (p->max_patch < 4 || (p->max_patch & (p->max_patch - 1)) || p->max_patch > (4 << (DM_MAX_LEVELS - 1))))
         return fail(DM_ERR_INVALID_ARG, "max_patch must be 0 or a power of two in [4, %d]", 4 << (DM_MAX_LEVELS - 1));
     if (p->precision < DM_FP32 || p->precision > DM_FP64) return fail(DM_ERR_INVALID_ARG, "unknown precision");
+    if (p->prototypes < 0 || p->prototypes > DM_MAX_PROTOTYPES)
+        return fail(DM_ERR_INVALID_ARG, "prototypes must be in [0, %d]", DM_MAX_PROTOTYPES);
+    if (p->kmeans_iters < 0 || p->kmeans_iters > 1000)
+        return fail(DM_ERR_INVALID_ARG, "kmeans_iters must be in [0, 1000]");
     for (int r : p->reserved)
         if (r != 0) return fail(DM_ERR_INVALID_ARG, "reserved fields must be 0");
     return DM_OK;
@@ -108,6 +112,15 @@ dm_status plan_pair(const dm_params* prm, int W1, int H1, int W2, int H2, dm_pla
         if ((cx && cy) || lmax == 0) break;
         --lmax;
     }
+    const int D = prm->prototypes;
+    if (D > 0) {
+        if (prm->precision == DM_FP64)
+            return fail(DM_ERR_UNSUPPORTED, "approximate matching runs in FP32 or BF16");
+        if (D > g0x * g0y)
+            return fail(DM_ERR_INVALID_ARG, "%d prototypes for %d atomic patches", D, g0x * g0y);
+        if (lmax == 0)
+            return fail(DM_ERR_UNSUPPORTED, "approximate matching needs a pooled level (N_max >= 8)");
+    }
     out->lmax = lmax;
     out->N_max = 4 << lmax;
     out->n_atomic = g0x * g0y;
@@ -145,7 +158,8 @@ dm_status plan_pair(const dm_params* prm, int W1, int H1, int W2, int H2, dm_pla
     const int vstride = (int)align256((uint64_t)(glx > gly ? glx : gly));
     out->off_valid = take((uint64_t)(lmax + 1) * 2 * vstride);
     for (int l = 0; l < lmax; ++l) {
-        const uint64_t n = (uint64_t)out->gx[l] * out->gy[l] * out->h[l + 1] * out->w[l + 1];
+        const uint64_t maps = (l == 0 && D > 0) ? (uint64_t)D : (uint64_t)out->gx[l] * out->gy[l];
+        const uint64_t n = maps * out->h[l + 1] * out->w[l + 1];
         out->off_cp[l] = take(n * es);
         out->off_code[l] = take(n);
         if (l >= 1) out->off_u[l] = take(n * es);
@@ -153,6 +167,17 @@ dm_status plan_pair(const dm_params* prm, int W1, int H1, int W2, int H2, dm_pla
     out->off_top = take((uint64_t)out->gx[lmax] * out->gy[lmax] * out->h[lmax] * out->w[lmax] * es);
     out->off_best = take((uint64_t)out->n_atomic * 8);
     out->off_cell = take((uint64_t)((H2 + 3) / 4) * ((W2 + 3) / 4) * 8);
+    if (D > 0) {
+        const uint64_t na = (uint64_t)out->n_atomic;
+        out->prototypes = D;
+        out->kmeans_chunks = kmeans_chunks(D);
+        out->off_protos = take((uint64_t)D * 144 * 8);
+        out->off_assign = take(na * 4);
+        out->off_kstat = take(2 * 4);
+        out->off_proto_img = take((uint64_t)D * 144 * 4);
+        if (prm->precision == DM_BF16) out->off_proto_bf = take((uint64_t)D * 160 * 2);
+        out->off_kpart = take((uint64_t)out->kmeans_chunks * na * 4 * 5);
+    }
     out->workspace_bytes = off;
     return DM_OK;
 }
@@ -163,6 +188,7 @@ dm_status plan_grad(const dm_params* prm, int W1, int H1, int W2, int H2, int re
     dm_status st = plan_pair(prm, W1, H1, W2, H2, &pi);
     if (st != DM_OK) return st;
     if (pi.lmax == 0) return fail(DM_ERR_UNSUPPORTED, "the pyramid has a single level; nothing to route a gradient through");
+    if (prm->prototypes) return fail(DM_ERR_UNSUPPORTED, "the gradient is that of the exact method (prototypes = 0)");
     memset(out, 0, sizeof(*out));
     out->geom = pi;
     out->recompute = recompute ? 1 : 0;

@@ -172,7 +172,7 @@ __device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_pre
             live[u] = true;
 #pragma unroll
             for (int side = 0; side < 4; ++side) vb[u] = max(vb[u], sV[((k * 4 + side) * a.TR + ty) * a.TC + tx]);
-            off[u] = (((size_t)cblk * a.CB + k) * a.h + ry) * a.w + rx;
+            off[u] = ((size_t)child_slot(g, a.l, cblk * a.CB + k) * a.h + ry) * a.w + rx;
             if (vb[u] || !a.is_bottom) {
                 cpv[u] = cp_prev[off[u]];
                 if (a.is_bottom) mv[u] = code_prev[off[u]];
@@ -300,10 +300,11 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
         // One descriptor per array (every array here stays below 2^31 bytes,
         // checked at launch); parents are selected by element offsets.
         const int usz = a.hu * a.wu, csz = a.h * a.w;
-        const int nparent = a.gxp * a.gyp, nchild = a.gxc * a.gyc;
+        const int nparent = a.gxp * a.gyp;
+        const int nmap = (a.l == 1 && g.slot0) ? g.nslot0 : a.gxc * a.gyc;   // maps in the C'_{l-1} buffer
         const __amdgpu_buffer_rsrc_t rsU = rsrc(u_cur, nparent * usz * 4), rsM = rsrc(code_cur, nparent * usz);
-        const __amdgpu_buffer_rsrc_t rsC = rsrc(cp_prev, nchild * csz * 4);
-        const __amdgpu_buffer_rsrc_t rsK = rsrc(code_prev, a.is_bottom ? nchild * csz : 0);
+        const __amdgpu_buffer_rsrc_t rsC = rsrc(cp_prev, nmap * csz * 4);
+        const __amdgpu_buffer_rsrc_t rsK = rsrc(code_prev, a.is_bottom ? nmap * csz : 0);
         // Element offset of each parent's map, or a large negative value for a
         // missing parent: with a lane's row offset added (also large negative
         // when the lane or row has no U_l entry), an entry exists exactly when
@@ -317,7 +318,7 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
             const bool ok = pb >= 0 && pb < a.gyp && pa >= 0 && pa < a.gxp && vxp[pa] && vyp[pb];
             pbase[side] = ok ? (pb * a.gxp + pa) * usz : kNone;
         }
-        const int cbase = c * csz;
+        const int cbase = child_slot(g, a.l, c) * csz;
         uint32_t (*ring)[kBtCols] = sR[wv];
         const int rx = C0 + t;                       // the lane's output column
         const int ux = (C0 >> 1) - 1 + t;            // the lane's U_l column while scattering

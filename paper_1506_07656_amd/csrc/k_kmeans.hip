@@ -1,0 +1,385 @@
+// Approximate DeepMatching (Sec. 4.1): spherical k-means over the atomic
+// patches of I, and the prototypes laid out as a small image (4 rows, 4D
+// columns) whose D atomic patches are the prototypes, so that the bottom
+// correlation kernels compute the D prototype maps C'_0 unchanged.
+//
+// A patch vector is the 16 pixel descriptors of its 4x4 patch in (dy, dx,
+// channel) order (144 values, norm 4).  Centroid d starts as patch
+// floor((2d+1) n / (2D)); each iteration assigns every patch to the centroid
+// with the largest dot product (values within kTie of the largest count as
+// equal, lowest index first), then replaces every centroid that has members
+// by the sum of its members rescaled to norm 4; a final assignment follows.
+//
+// Every decision is the one an FP64 evaluation takes:
+//  * Assignment.  FP32 MFMA dot products of all patches with all centroids;
+//    each patch keeps its two best (value, index) pairs and the best value
+//    after them.  Descriptors and centroids are non-negative and of norm 4,
+//    so a 144-term FP32 dot product (at most 16) is within
+//    gamma_145 * 16 + 16 u < 1.4e-4 of the exact one (u = 2^-24), whatever
+//    the summation order.  With kGap = 5e-4 > 2 * 1.4e-4 + kTie:
+//      v1 - v2 > kGap:  the best centroid is the FP64 answer;
+//      v1 - v3 > kGap:  the answer is one of the two best, decided in FP64;
+//      otherwise:       every centroid is evaluated in FP64.
+//  * Update.  Member sums in FP64, in a fixed order, then the norm and the
+//    rescale in FP64.  Results are deterministic run to run.
+#include <math.h>
+
+#include "dm_group.h"
+
+namespace dm {
+namespace {
+
+constexpr double kTie = 1e-11;     // dot products this close to the largest are equal
+constexpr float kGap = 5e-4f;      // FP32 gap that certifies a decision (see above)
+constexpr int KM_NT = 2;           // patch tiles of 16 per wave in the FP32 pass
+constexpr int KM_PB = 64 * KM_NT;  // patches per block (4 waves)
+constexpr int KM_LD = 148;         // LDS row stride (floats) of a staged centroid
+constexpr int KM_FIX = 256;        // patches per block of the decision kernel
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Element k of the vector of atomic patch p (lattice gx0 wide).
+__device__ inline float patch_elem(const KmArgs& a, int p, int k) {
+    const int b = p / a.gx0, aa = p - b * a.gx0;
+    const int r = k / 36, j = k - r * 36;
+    return a.d1[((size_t)(4 * b + r) * a.W1 + 4 * aa) * 9 + j];
+}
+
+__device__ inline uint16_t bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even (finite inputs)
+    return (uint16_t)(u >> 16);
+}
+
+// Sum over the 64 lanes by a butterfly: every lane ends with the same value
+// (each pairwise sum is computed identically on both lanes of the pair).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// Writes element k of centroid d: the FP64 value, and its FP32 and BF16 forms
+// at pixel (row k / 36, column 4d + (k % 36) / 9) of the prototype image.
+__device__ inline void put_centroid(const KmArgs& a, int d, int k, double v) {
+    a.C64[(size_t)d * 144 + k] = v;
+    const int r = k / 36, j = k - r * 36;
+    a.img[(size_t)r * 36 * a.D + 36 * d + j] = (float)v;
+    if (a.img16) {
+        const int dx = j / 9, c = j - dx * 9;
+        a.img16[((size_t)r * 4 * a.D + 4 * d + dx) * 10 + c] = bf16_rne((float)v);
+    }
+}
+
+// One wave per centroid: the starting patch rescaled to norm 4.
+__global__ __launch_bounds__(64) void k_km_init(KmArgs a) {
+    const int d = blockIdx.x, lane = threadIdx.x;
+    if (d == 0 && lane < 2) a.stat[lane] = 0;
+    const int p = (int)(((2ll * d + 1) * a.n) / (2ll * a.D));
+    double v[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int k = lane + 64 * i;
+        v[i] = k < 144 ? (double)patch_elem(a, p, k) : 0.0;
+    }
+    const double n2 = wave_sum(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const double sc = n2 > 0.0 ? 4.0 / sqrt(n2) : 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int k = lane + 64 * i;
+        if (k < 144) put_centroid(a, d, k, v[i] * sc);
+    }
+    if (a.img16 && lane < 16) {   // the padding channel of the prototype's 16 pixels
+        const int r = lane >> 2, dx = lane & 3;
+        a.img16[((size_t)r * 4 * a.D + 4 * d + dx) * 10 + 9] = 0;
+    }
+}
+
+// Best two (value, index) pairs and the best value after them.
+struct Top3 {
+    float v1, v2, v3;
+    int i1, i2;
+};
+
+__device__ inline void push(Top3& s, float v, int d) {
+    if (v > s.v1) {
+        s.v3 = s.v2;
+        s.v2 = s.v1;
+        s.i2 = s.i1;
+        s.v1 = v;
+        s.i1 = d;
+    } else if (v > s.v2) {
+        s.v3 = s.v2;
+        s.v2 = v;
+        s.i2 = d;
+    } else if (v > s.v3) {
+        s.v3 = v;
+    }
+}
+
+__device__ inline void merge(Top3& s, const Top3& o) {
+    push(s, o.v1, o.i1);
+    push(s, o.v2, o.i2);
+    s.v3 = fmaxf(s.v3, o.v3);
+}
+
+__device__ inline Top3 shfl_xor_top3(const Top3& s, int m) {
+    Top3 o;
+    o.v1 = __shfl_xor(s.v1, m);
+    o.v2 = __shfl_xor(s.v2, m);
+    o.v3 = __shfl_xor(s.v3, m);
+    o.i1 = __shfl_xor(s.i1, m);
+    o.i2 = __shfl_xor(s.i2, m);
+    return o;
+}
+
+// FP32 pass: block (patch block, centroid chunk of KM_CH).  The chunk's
+// centroids are staged in LDS; each wave keeps KM_NT tiles of 16 patches in
+// registers as the B operand of v_mfma_f32_16x16x4f32 (K = 144 split so that
+// the 16-lane group g of a wave owns the 36 values of patch row g, one
+// contiguous run in both layouts) and takes the centroids 16 at a time as the
+// A operand.  Lane (g, n) receives centroids 4g..4g+3 of the tile for patch
+// n and folds them into its running Top3.
+__global__ __launch_bounds__(256) void k_km_assign(KmArgs a) {
+    __shared__ __align__(16) float sC[KM_CH * KM_LD];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n = lane & 15, grp = lane >> 4;
+    const int chunk = blockIdx.y, d0 = chunk * KM_CH;
+    const int nd = min(KM_CH, a.D - d0);
+    for (int e = tid; e < KM_CH * 144; e += 256) {
+        const int i = e / 144, k = e - i * 144;
+        const int r = k / 36, j = k - r * 36;
+        sC[i * KM_LD + k] = i < nd ? a.img[(size_t)r * 36 * a.D + 36 * (d0 + i) + j] : 0.f;
+    }
+    float fb[KM_NT][36];
+    int pp[KM_NT];
+#pragma unroll
+    for (int nt = 0; nt < KM_NT; ++nt) {
+        const int p = blockIdx.x * KM_PB + wave * 16 * KM_NT + nt * 16 + n;
+        pp[nt] = p;
+        if (p < a.n) {
+            const int b = p / a.gx0, aa = p - b * a.gx0;
+            const float* src = a.d1 + ((size_t)(4 * b + grp) * a.W1 + 4 * aa) * 9;
+#pragma unroll
+            for (int t = 0; t < 36; ++t) fb[nt][t] = src[t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < 36; ++t) fb[nt][t] = 0.f;
+        }
+    }
+    __syncthreads();
+    Top3 st[KM_NT];
+#pragma unroll
+    for (int nt = 0; nt < KM_NT; ++nt) st[nt] = Top3{-INFINITY, -INFINITY, -INFINITY, 0x7fffffff, 0x7fffffff};
+    for (int ct = 0; ct * 16 < nd; ++ct) {
+        const float* src = sC + (ct * 16 + n) * KM_LD + grp * 36;
+        f4 acc[KM_NT];
+#pragma unroll
+        for (int nt = 0; nt < KM_NT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 36; ++t) {
+            const float fa = src[t];
+#pragma unroll
+            for (int nt = 0; nt < KM_NT; ++nt)
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa, fb[nt][t], acc[nt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int nt = 0; nt < KM_NT; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = ct * 16 + 4 * grp + r;
+                if (i < nd) push(st[nt], acc[nt][r], d0 + i);
+            }
+    }
+#pragma unroll
+    for (int nt = 0; nt < KM_NT; ++nt) {
+        merge(st[nt], shfl_xor_top3(st[nt], 16));
+        merge(st[nt], shfl_xor_top3(st[nt], 32));
+        const int p = pp[nt];
+        if (grp == 0 && p < a.n) {
+            const size_t o = (size_t)chunk * a.n + p;
+            a.pv1[o] = st[nt].v1;
+            a.pv2[o] = st[nt].v2;
+            a.pv3[o] = st[nt].v3;
+            a.pi1[o] = st[nt].i1;
+            a.pi2[o] = st[nt].i2;
+        }
+    }
+}
+
+// Decisions: merge the chunks' Top3 of each patch (fixed order), keep
+// certified answers, and settle the others in FP64 (two candidates: one wave
+// per patch; more: the whole block per patch, over every centroid).
+__global__ __launch_bounds__(KM_FIX) void k_km_fix(KmArgs a) {
+    __shared__ int sP2[KM_FIX], sA2[KM_FIX], sB2[KM_FIX], sP3[KM_FIX];
+    __shared__ int sN2, sN3;
+    __shared__ double sDot[DM_MAX_PROTOTYPES];
+    __shared__ double sRed[KM_FIX / 64];
+    __shared__ int sRedI[KM_FIX / 64];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (tid == 0) sN2 = sN3 = 0;
+    __syncthreads();
+    const int p = blockIdx.x * KM_FIX + tid;
+    if (p < a.n) {
+        Top3 s{a.pv1[p], a.pv2[p], a.pv3[p], a.pi1[p], a.pi2[p]};
+        for (int c = 1; c < a.nchunk; ++c) {
+            const size_t o = (size_t)c * a.n + p;
+            merge(s, Top3{a.pv1[o], a.pv2[o], a.pv3[o], a.pi1[o], a.pi2[o]});
+        }
+        if (s.v1 - s.v2 > kGap) {
+            a.assign[p] = s.i1;
+        } else if (s.v1 - s.v3 > kGap) {
+            const int e = atomicAdd(&sN2, 1);
+            sP2[e] = p;
+            sA2[e] = s.i1;
+            sB2[e] = s.i2;
+        } else {
+            sP3[atomicAdd(&sN3, 1)] = p;
+        }
+    }
+    __syncthreads();
+    const int n2 = sN2, n3 = sN3;
+    // Two candidates: lanes split the 144 terms, a butterfly sums them.
+    for (int e = wave; e < n2; e += KM_FIX / 64) {
+        const int q = sP2[e], ia = sA2[e], ib = sB2[e];
+        double ta = 0.0, tb = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int k = lane + 64 * i;
+            if (k < 144) {
+                const double x = patch_elem(a, q, k);
+                ta = fma(x, a.C64[(size_t)ia * 144 + k], ta);
+                tb = fma(x, a.C64[(size_t)ib * 144 + k], tb);
+            }
+        }
+        const double da = wave_sum(ta), db = wave_sum(tb);
+        const double mx = fmax(da, db);
+        const bool oka = da >= mx - kTie, okb = db >= mx - kTie;
+        const int win = (oka && okb) ? min(ia, ib) : (oka ? ia : ib);
+        if (lane == 0) a.assign[q] = win;
+    }
+    // Three or more candidates: every centroid, waves take every 4th.
+    for (int e = 0; e < n3; ++e) {
+        const int q = sP3[e];
+        double x[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int k = lane + 64 * i;
+            x[i] = k < 144 ? (double)patch_elem(a, q, k) : 0.0;
+        }
+        for (int d = wave; d < a.D; d += KM_FIX / 64) {
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int k = lane + 64 * i;
+                if (k < 144) t = fma(x[i], a.C64[(size_t)d * 144 + k], t);
+            }
+            t = wave_sum(t);
+            if (lane == 0) sDot[d] = t;
+        }
+        __syncthreads();
+        double mx = -INFINITY;
+        for (int d = tid; d < a.D; d += KM_FIX) mx = fmax(mx, sDot[d]);
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) mx = fmax(mx, __shfl_xor(mx, m));
+        if (lane == 0) sRed[wave] = mx;
+        __syncthreads();
+        mx = sRed[0];
+        for (int w = 1; w < KM_FIX / 64; ++w) mx = fmax(mx, sRed[w]);
+        int first = 0x7fffffff;
+        for (int d = tid; d < a.D; d += KM_FIX)
+            if (sDot[d] >= mx - kTie) first = min(first, d);
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) first = min(first, __shfl_xor(first, m));
+        if (lane == 0) sRedI[wave] = first;
+        __syncthreads();
+        if (tid == 0) {
+            int f = sRedI[0];
+            for (int w = 1; w < KM_FIX / 64; ++w) f = min(f, sRedI[w]);
+            a.assign[q] = f < a.D ? f : 0;   // no candidate only with non-finite inputs
+        }
+        __syncthreads();   // sDot and the reduction slots are reused by the next patch
+    }
+    if (tid == 0 && (n2 || n3)) {
+        atomicAdd(&a.stat[0], n2);
+        atomicAdd(&a.stat[1], n3);
+    }
+}
+
+// One block per centroid: the sum of its members (each wave scans a quarter
+// of the patches in order; the quarters are added in order), then the
+// rescale to norm 4.  A centroid without members keeps its value.
+__global__ __launch_bounds__(256) void k_km_update(KmArgs a) {
+    __shared__ double sPart[4][144];
+    const int d = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int per = (a.n + 3) / 4, p0 = wave * per, p1 = min(a.n, p0 + per);
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int base = p0; base < p1; base += 64) {
+        const int q = base + lane;
+        unsigned long long m = __ballot(q < p1 && a.assign[q] == d);
+        while (m) {
+            const int j = __ffsll((long long)m) - 1;
+            m &= m - 1;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int k = lane + 64 * i;
+                if (k < 144) s[i] += (double)patch_elem(a, base + j, k);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int k = lane + 64 * i;
+        if (k < 144) sPart[wave][k] = s[i];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    double t[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int k = lane + 64 * i;
+        t[i] = k < 144 ? ((sPart[0][k] + sPart[1][k]) + sPart[2][k]) + sPart[3][k] : 0.0;
+    }
+    const double n2 = wave_sum(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    if (!(n2 > 0.0)) return;
+    const double sc = 4.0 / sqrt(n2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int k = lane + 64 * i;
+        if (k < 144) put_centroid(a, d, k, t[i] * sc);
+    }
+}
+
+}  // namespace
+
+int kmeans_chunks(int D) { return (D + KM_CH - 1) / KM_CH; }
+
+hipError_t launch_kmeans(const KmArgs& a, int iters, hipStream_t s) {
+    if (a.D < 1 || a.D > DM_MAX_PROTOTYPES || a.D > a.n || a.nchunk != kmeans_chunks(a.D))
+        return hipErrorInvalidValue;
+    const dim3 g_assign((a.n + KM_PB - 1) / KM_PB, a.nchunk), g_fix((a.n + KM_FIX - 1) / KM_FIX);
+    timing_begin("kmeans_init", 0, s);
+    hipLaunchKernelGGL(k_km_init, dim3(a.D), dim3(64), 0, s, a);
+    timing_end(s);
+    hipError_t e = hipGetLastError();
+    for (int it = 0; it <= iters && e == hipSuccess; ++it) {
+        timing_begin("kmeans_assign", 0, s);
+        hipLaunchKernelGGL(k_km_assign, g_assign, dim3(256), 0, s, a);
+        timing_end(s);
+        timing_begin("kmeans_fix", 0, s);
+        hipLaunchKernelGGL(k_km_fix, g_fix, dim3(KM_FIX), 0, s, a);
+        timing_end(s);
+        if (it < iters) {
+            timing_begin("kmeans_update", 0, s);
+            hipLaunchKernelGGL(k_km_update, dim3(a.D), dim3(256), 0, s, a);
+            timing_end(s);
+        }
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+}  // namespace dm

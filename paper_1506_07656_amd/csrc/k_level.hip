@@ -70,8 +70,9 @@ struct ParentLDS {
 };
 
 template <typename T>
-__device__ inline void load_parents(const LevelArgs& a, int pbase, const uint8_t* vxp, const uint8_t* vyp,
-                                    const uint8_t* vxc, const uint8_t* vyc, const T* prev, ParentLDS<T>* sp) {
+__device__ inline void load_parents(const LevelArgs& a, const Geom& g, int pbase, const uint8_t* vxp,
+                                    const uint8_t* vyp, const uint8_t* vxc, const uint8_t* vyc, const T* prev,
+                                    ParentLDS<T>* sp) {
     const size_t hw = (size_t)a.h * a.w;
     for (int k = threadIdx.x; k < a.PB; k += blockDim.x) {
         const Parent<T> pi = parent_info<T>(a, pbase + k, vxp, vyp, vxc, vyc);
@@ -81,7 +82,9 @@ __device__ inline void load_parents(const LevelArgs& a, int pbase, const uint8_t
 #pragma unroll
             for (int kx = 0; kx < 2; ++kx)
                 r.cmap[2 * ky + kx] =
-                    (pi.cb[ky] >= 0 && pi.ca[kx] >= 0) ? prev + (size_t)(pi.cb[ky] * a.gxc + pi.ca[kx]) * hw : nullptr;
+                    (pi.cb[ky] >= 0 && pi.ca[kx] >= 0)
+                        ? prev + (size_t)child_slot(g, a.l, pi.cb[ky] * a.gxc + pi.ca[kx]) * hw
+                        : nullptr;
         r.inv = pi.inv;
         r.valid = pi.valid;
         sp[k] = r;
@@ -118,7 +121,7 @@ __device__ inline void level_pool_body(const LevelArgs& a, const T* __restrict__
     const int ct = rest / a.n_rt, R0 = (rest - ct * a.n_rt) * a.TRo, C0 = ct * a.TCo;
     const uint8_t *vxp = vtab(vt, g, a.l, 0), *vyp = vtab(vt, g, a.l, 1);
     const uint8_t *vxc = vtab(vt, g, a.l - 1, 0), *vyc = vtab(vt, g, a.l - 1, 1);
-    load_parents<T>(a, pblk * a.PB, vxp, vyp, vxc, vyc, prev, sp);
+    load_parents<T>(a, g, pblk * a.PB, vxp, vyp, vxc, vyc, prev, sp);
     __syncthreads();
     const int RW = 2 * a.TCo + 1, RA = (2 * a.TRo + 1) * RW, total = a.PB * RA;
     // Phase 1: stage max(A, 0) on the pooling footprint; 4 elements per
@@ -305,7 +308,8 @@ __device__ inline void level_stream_body(const StreamArgs& a, const float* __res
     for (int ky = 0; ky < 2; ++ky)
 #pragma unroll
         for (int kx = 0; kx < 2; ++kx)
-            cmap[2 * ky + kx] = (ey[ky] >= 0 && ex[kx] >= 0) ? prev + (size_t)(ey[ky] * a.gxc + ex[kx]) * hw : nullptr;
+            cmap[2 * ky + kx] =
+                (ey[ky] >= 0 && ex[kx] >= 0) ? prev + (size_t)child_slot(g, a.l, ey[ky] * a.gxc + ex[kx]) * hw : nullptr;
     const float inv = 1.f / float(nx * ny);
     const int R0 = band * a.TRo, R1 = min(R0 + a.TRo, a.hp);
     const int C0 = ct * kStreamCols, ncol = min(kStreamCols, a.wp - C0);
@@ -352,7 +356,7 @@ __device__ inline void level_top_body(const LevelArgs& a, const T* __restrict__ 
     const int ct = rest / a.n_rt, R0 = (rest - ct * a.n_rt) * a.TRo, C0 = ct * a.TCo;
     const uint8_t *vxp = vtab(vt, g, a.l, 0), *vyp = vtab(vt, g, a.l, 1);
     const uint8_t *vxc = vtab(vt, g, a.l - 1, 0), *vyc = vtab(vt, g, a.l - 1, 1);
-    load_parents<T>(a, pblk * a.PB, vxp, vyp, vxc, vyc, prev, sp);
+    load_parents<T>(a, g, pblk * a.PB, vxp, vyp, vxc, vyc, prev, sp);
     __syncthreads();
     for (int e = threadIdx.x; e < a.PB * a.TRo * a.TCo; e += 256) {
         const int k = fdiv(e, a.f_tile), rem = e - k * (a.TRo * a.TCo);

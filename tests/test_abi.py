@@ -42,6 +42,7 @@ def test_default_params():
     assert abs(p.nu1) < 1e-9 and p.nu2 == 1 and p.nu3 == 1 and abs(p.sigmoid_slope - 0.2) < 1e-7
     assert abs(p.mu - 0.1) < 1e-7 and p.intensity_scale == 255 and abs(p.lam - 1.4) < 1e-7
     assert p.max_patch == 0 and p.precision == 0
+    assert p.prototypes == 0 and p.kmeans_iters == 10
 
 
 @pytest.mark.parametrize("W,H,W2,H2,mp", [(64, 64, 64, 64, 32), (256, 192, 256, 192, 64), (512, 256, 512, 256, 0),
@@ -81,6 +82,41 @@ def test_plan_rejects_bad_shapes():
     p.reserved[3] = 1
     with pytest.raises(dm.DMError):
         dm.plan(64, 64, 64, 64, p)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_plan_approximate_layout(prec):
+    ex = dm.plan(512, 256, 512, 256, dm.params(precision=prec))
+    pl = dm.plan(512, 256, 512, 256, dm.params(precision=prec, prototypes=1024))
+    assert pl.prototypes == 1024 and pl.kmeans_chunks == 16 and ex.prototypes == 0
+    assert pl.lmax == ex.lmax and pl.n_atomic == ex.n_atomic == 128 * 64
+    # C'_0 holds D maps instead of one per atomic patch
+    assert pl.off_code[0] - pl.off_cp[0] == 1024 * pl.h[1] * pl.w[1] * 4
+    assert ex.off_code[0] - ex.off_cp[0] == 8192 * ex.h[1] * ex.w[1] * 4
+    assert pl.workspace_bytes < ex.workspace_bytes
+    offs = [pl.off_protos, pl.off_assign, pl.off_kstat, pl.off_proto_img, pl.off_kpart]
+    assert all(o % 256 == 0 and o < pl.workspace_bytes for o in offs)
+    assert (pl.off_proto_bf != 0) == (prec == "bf16")
+    assert pl.workspace_bytes >= pl.off_kpart + 16 * 8192 * 20
+
+
+def test_plan_approximate_errors():
+    with pytest.raises(dm.DMError) as e:                          # more prototypes than patches
+        dm.plan(64, 64, 64, 64, dm.params(prototypes=257))
+    assert e.value.status == -1
+    dm.plan(64, 64, 64, 64, dm.params(prototypes=256))
+    for kw in (dict(prototypes=-1), dict(prototypes=4097), dict(prototypes=8, kmeans_iters=-1)):
+        with pytest.raises(dm.DMError) as e:
+            dm.plan(64, 64, 64, 64, dm.params(**kw))
+        assert e.value.status == -1
+    for args, kw in (((64, 64, 64, 64), dict(prototypes=8, precision="fp64")),      # FP64
+                     ((4, 4, 4, 4), dict(prototypes=1))):                           # no pooled level
+        with pytest.raises(dm.DMError) as e:
+            dm.plan(*args, dm.params(**kw))
+        assert e.value.status == -5
+    with pytest.raises(dm.DMError) as e:                          # the gradient is the exact method's
+        dm.plan_grad(64, 64, 64, 64, dm.params(prototypes=8))
+    assert e.value.status == -5
 
 
 def _call_match(ws_bytes, capacity, ws=0x10000, out=0x20000, n_out=0x30000, d1=0x40000, d2=0x50000, prm=None):
@@ -160,7 +196,8 @@ def test_plan_batch_layout_and_errors():
     assert info.n_pairs == 3 and info.workspace_bytes >= ws_sum
     assert info_b.workspace_bytes >= ws_sum + grad_sum and info_b.n_launches > info.n_launches
     bad = [(0, sizes, prm, -1), (257, sizes * 86, prm, -1), (3, sizes, dm.params(precision="fp64"), -5),
-           (1, [(4, 4, 4, 4)], prm, -5), (1, [(3, 64, 64, 64)], prm, -2)]
+           (1, [(4, 4, 4, 4)], prm, -5), (1, [(3, 64, 64, 64)], prm, -2),
+           (1, sizes, dm.params(prototypes=16), -5)]
     for n, sz, p, want in bad:
         P = _pairs(sz[:max(n, 1)])
         assert L.dm_plan_batch(n, P, ctypes.byref(p), 0, ctypes.byref(info)) == want, (n, want)
