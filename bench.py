@@ -11,6 +11,10 @@ Prints one JSON line.  Stage times come from HIP events the library records
 on the launch stream around each kernel (dm_timing_*), in a second pass of
 the same steps right after the timed one.
 
+The "approx" entry is approximate DeepMatching (Sec. 4.1) on the same pair
+with D = 1024 and 64 prototypes: throughput, k-means time, workspace size and
+agreement with the exact path's matches.
+
 The "batch" entry is the uneven-batch workload: 32 pairs with W ~ U{128..621},
 H ~ U{96..188} (half of a 1242x375 driving-frame shape), BF16 correlation,
 FP32 pyramid, forward plus backward of the top loss, every stage one
@@ -47,10 +51,13 @@ def stage_work(pl, name: str, level: int, precision: str):
     correlation on the matrix cores when it is the bound, HBM bytes otherwise."""
     gx, gy, h, w = list(pl.gx), list(pl.gy), list(pl.h), list(pl.w)
     L = pl.lmax
-    npat = lambda l: gx[l] * gy[l]
+    # maps stored at level 0: one per atomic patch, or one per prototype
+    npat = lambda l: (pl.prototypes or gx[0] * gy[0]) if l == 0 else gx[l] * gy[l]
+    if name == "kmeans_assign":   # FP32 MFMA dot products of every patch with every centroid
+        return "mfma", 2.0 * pl.n_atomic * pl.prototypes * 144, "FLOP"
     if name.startswith("corr_pool"):
-        flops = 2.0 * pl.n_atomic * pl.H2 * pl.W2 * 144
-        out_bytes = pl.n_atomic * h[1] * w[1] * 5.0
+        flops = 2.0 * npat(0) * pl.H2 * pl.W2 * 144
+        out_bytes = npat(0) * h[1] * w[1] * 5.0
         if precision == "fp32":
             return "mfma", flops, "FLOP"
         return "hbm", out_bytes, "B"
@@ -76,7 +83,7 @@ def roofline_of(stages, pl, precision):
         avg_ms = total / count
         if unit == "FLOP":
             ach = amount / (avg_ms * 1e-3) / 1e12
-            peak = PEAKS_TFLOPS[precision]
+            peak = PEAKS_TFLOPS["fp32" if name == "kmeans_assign" else precision]
             u = "TFLOP/s"
         else:
             ach = amount / (avg_ms * 1e-3) / 1e9
@@ -89,10 +96,10 @@ def roofline_of(stages, pl, precision):
     return rows
 
 
-def time_path(dm, torch, img1, img2, precision, steps, warmup):
+def time_path(dm, torch, img1, img2, precision, steps, warmup, **kw):
     W1, H1 = img1.shape[1], img1.shape[0]
     W2, H2 = img2.shape[1], img2.shape[0]
-    m = dm.Matcher(W1, H1, W2, H2, dm.params(precision=precision))
+    m = dm.Matcher(W1, H1, W2, H2, dm.params(precision=precision, **kw))
     for _ in range(warmup):
         m.run_images(img1, img2)
     torch.cuda.synchronize()
@@ -263,6 +270,36 @@ def batch_bench(dm, torch, steps):
     return res
 
 
+def approx_bench(dm, torch, img1, img2, exact_matches, exact_plan, steps, warmup):
+    """Approximate DeepMatching (Sec. 4.1) on the same pair: D prototypes from
+    10 rounds of spherical k-means, BF16 correlation of the D prototype maps."""
+    import numpy as np
+    res = {}
+    for D in (1024, 64):
+        dt, matches, stages, pl = time_path(dm, torch, img1, img2, "bf16", steps, warmup, prototypes=D)
+        m = dm.Matcher(img1.shape[1], img1.shape[0], img2.shape[1], img2.shape[0],
+                       dm.params(precision="bf16", prototypes=D))
+        m.run_images(img1, img2)
+        kstat = dm.workspace_views(m.ws, m.plan)["kstat"].cpu().numpy()
+        km = [(n, l, c, t) for n, l, c, t in stages if n.startswith("kmeans")]
+        km_ms = sum(t for _, _, _, t in km) / steps
+        rows = roofline_of(stages, pl, "bf16")
+        res[f"D{D}"] = dict(
+            pairs_s=round(1.0 / dt, 3), ms_per_step=round(dt * 1e3, 4), matches=int(len(matches)),
+            exact_matches_within_1px=round(within_1px(matches, exact_matches), 5),
+            kmeans_ms=round(km_ms, 4),
+            kmeans_assign=next(({k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items() if k != "work"}
+                                for r in rows if r["kernel"] == "kmeans_assign_l0"), None),
+            settled_in_fp64=[int(kstat[0]), int(kstat[1])],
+            workspace_mb=round(pl.workspace_bytes / 2**20, 1),
+            top_kernels=[(r["kernel"], round(r["avg_ms"] * r["launches"] / steps, 4)) for r in rows[:6]])
+        del m
+    res["exact_workspace_mb"] = round(exact_plan.workspace_bytes / 2**20, 1)
+    res["workload"] = ("the same 512x256 pair; 10 k-means rounds over its 8192 atomic patches; "
+                       "BF16 correlation of the D prototype maps, FP32 pyramid")
+    return res
+
+
 def oracle_agreement(matches):
     """Fraction of the stored oracle matches of the pair reproduced within 1 px."""
     import numpy as np
@@ -306,8 +343,9 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the run, copy 1 GiB device to device (calibrates HBM byte counters)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-pair uneven batch")
-    ap.add_argument("--only", choices=("all", "fwd_bf16", "fwd_bwd_bf16"), default="all",
-                    help="fwd_bf16 / fwd_bwd_bf16: run only that pass (short profiler runs); prints no JSON line")
+    ap.add_argument("--no-approx", action="store_true", help="skip approximate DeepMatching")
+    ap.add_argument("--only", choices=("all", "fwd_bf16", "fwd_bwd_bf16", "approx1024", "approx64"), default="all",
+                    help="run only that pass (short profiler runs); prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the matcher has no multi-GPU path, "
@@ -325,6 +363,11 @@ def main():
         if args.copy_probe:
             copy_probe(torch)
         print(f"bf16 forward: {dt * 1e3:.3f} ms/pair", flush=True)
+        return
+    if args.only.startswith("approx"):
+        D = int(args.only[len("approx"):])
+        dt, _, _, _ = time_path(dm, torch, img1, img2, "bf16", args.steps, args.warmup, prototypes=D)
+        print(f"approximate (D={D}) bf16 forward: {dt * 1e3:.3f} ms/pair", flush=True)
         return
     if args.only == "fwd_bwd_bf16":
         d1, d2 = dm.descriptors(img1), dm.descriptors(img2)
@@ -393,6 +436,8 @@ def main():
         "kernels_fp32": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items() if k != "work"}
                          for r in rows32[:4]],
     }
+    if not args.no_approx:
+        out["approx"] = approx_bench(dm, torch, img1, img2, head["matches"], head["plan"], args.steps, args.warmup)
     if not args.no_batch:
         out["batch"] = batch_bench(dm, torch, max(3, args.steps // 2))
     if not args.no_cpu_baseline:

@@ -57,17 +57,13 @@ dm_status run_match(const float* d1, const float* d2, const dm_plan_info& pi, co
         km.n = na;
         km.D = D;
         km.nchunk = pi.kmeans_chunks;
+        km.nsplit = kmeans_update_splits(D);
         km.C64 = at<double>(ws, pi.off_protos);
         km.img = at<float>(ws, pi.off_proto_img);
         km.img16 = prm->precision == DM_BF16 ? at<uint16_t>(ws, pi.off_proto_bf) : nullptr;
         km.assign = at<int>(ws, pi.off_assign);
-        float* part = at<float>(ws, pi.off_kpart);
-        const size_t pn = (size_t)km.nchunk * na;
-        km.pv1 = part;
-        km.pv2 = part + pn;
-        km.pv3 = part + 2 * pn;
-        km.pi1 = reinterpret_cast<int*>(part + 3 * pn);
-        km.pi2 = reinterpret_cast<int*>(part + 4 * pn);
+        km.part = at<km_f4>(ws, pi.off_kpart);
+        km.upd = at<double>(ws, pi.off_kpart + ((uint64_t)km.nchunk * na * 16 + 255) / 256 * 256);
         km.stat = at<int>(ws, pi.off_kstat);
         const dm_status st = check_hip(launch_kmeans(km, prm->kmeans_iters, s), "kmeans");
         if (st != DM_OK) return st;

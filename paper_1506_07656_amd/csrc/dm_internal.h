@@ -174,20 +174,23 @@ std::vector<JobRec> bot_jobs(bool bf16, const float* gp, const uint8_t* code, co
 // (k_kmeans.hip).  d1: FP32 descriptors of I; n = gx0 * gy0 patches; D
 // centroids; C64 [D][144]; img / img16: the prototype image (4 x 4D pixels,
 // 9 floats / 10 bf16 per pixel; img16 may be null); pv*/pi*: [nchunk][n]
-// candidates of the FP32 pass; stat[2]: patches settled in FP64.
+// candidates of the FP32 pass (one 16-byte record per chunk and patch);
+// upd: [nsplit][D][144] partial member sums; stat[2]: patches settled in FP64.
+typedef float km_f4 __attribute__((ext_vector_type(4)));
 struct KmArgs {
     const float* d1;
-    int W1, gx0, n, D, nchunk;
+    int W1, gx0, n, D, nchunk, nsplit;
     double* C64;
     float* img;
     uint16_t* img16;
     int* assign;
-    float *pv1, *pv2, *pv3;
-    int *pi1, *pi2;
+    km_f4* part;
+    double* upd;
     int* stat;
 };
 constexpr int KM_CH = 64;   // centroids per chunk of the FP32 pass
 int kmeans_chunks(int D);
+int kmeans_update_splits(int D);   // patch segments of the centroid update
 hipError_t launch_kmeans(const KmArgs& a, int iters, hipStream_t s);
 
 // Opt-in stage timing (dm_timing.cpp); calls may nest.

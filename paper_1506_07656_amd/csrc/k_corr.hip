@@ -42,7 +42,19 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 struct PoolArgs {
     int natom, n0x, W1, W2, H2, h1, w1;
     int n_ptiles, n_steps;
+    int n_seg, seg_steps;   // column segments of n_steps / n_seg steps (few patches: more blocks)
 };
+
+// Steps [s_begin, s_end) a block computes and the first one it stores: a
+// segment after the first starts one step early, so that the carry (the odd
+// column left of its first pooled column) is computed rather than unknown.
+struct StepRange {
+    int s_begin, s_out, s_end;
+};
+__device__ inline StepRange step_range(const PoolArgs& a, int seg) {
+    const int s0 = seg * a.seg_steps;
+    return StepRange{s0 > 0 ? s0 - 1 : 0, s0, min(a.n_steps, s0 + a.seg_steps)};
+}
 
 // Lane n of each 16-lane row receives v from lane n-1; lane 0 receives `first`.
 __device__ inline float shift_in(float v, float first) {
@@ -79,7 +91,7 @@ __device__ inline uint32_t bf16x2_scale16(uint32_t u) {
 // One x-step of the sweep for both precisions.  Engine supplies the MFMA chain
 // for an N-tile (E or O) of all MT M-tiles.
 template <typename Engine>
-__device__ inline void sweep_band(const Engine& eng, const PoolArgs& a, int pt, int R0, float lam,
+__device__ inline void sweep_band(const Engine& eng, const PoolArgs& a, int pt, int R0, int seg, float lam,
                                   float* __restrict__ cp, uint8_t* __restrict__ code,
                                   float (*carry)[16 * MT]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -91,8 +103,10 @@ __device__ inline void sweep_band(const Engine& eng, const PoolArgs& a, int pt, 
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int j = 0; j < 4; ++j) obase[mt][j] = (size_t)(pbase + mt * 16 + 4 * grp + j) * a.h1 * a.w1;
-    for (int step = 0; step < a.n_steps; ++step) {
+    const StepRange sr = step_range(a, seg);
+    for (int step = sr.s_begin; step < sr.s_end; ++step) {
         const int C0 = 16 * step;
+        const bool store = step >= sr.s_out;
         __syncthreads();                         // previous tile fully consumed
         eng.load_tile(a, R0, C0);
         __syncthreads();
@@ -113,7 +127,7 @@ __device__ inline void sweep_band(const Engine& eng, const PoolArgs& a, int pt, 
                     const int lp = mt * 16 + 4 * grp + j;
                     const float E = (y_ok && e_ok) ? fmaxf(accE[mt][j], 0.f) : -1.f;
                     const float O = (y_ok && o_ok) ? fmaxf(accO[mt][j], 0.f) : -1.f;
-                    const float cin = step ? carry[ia][lp] : -1.f;   // O of column C0-1
+                    const float cin = step > sr.s_begin ? carry[ia][lp] : -1.f;   // O of column C0-1
                     const float L = shift_in(O, cin);
                     if (n == 15) carry[ia][lp] = O;
                     // row maximum, first in order mx = -1, 0, +1
@@ -141,7 +155,7 @@ __device__ inline void sweep_band(const Engine& eng, const PoolArgs& a, int pt, 
                                 bc = 6 + rk;
                             }
                             const int r = R0 + ia / 2 - 1, jp = pbase + lp;
-                            if (r < a.h1 && c < a.w1 && jp < a.natom) {
+                            if (store && r < a.h1 && c < a.w1 && jp < a.natom) {
                                 const size_t o = obase[mt][j] + (uint32_t)(r * a.w1 + c);
                                 cp[o] = rect_pow(bv, lam);
                                 code[o] = (uint8_t)bc;
@@ -267,7 +281,7 @@ __device__ __forceinline__ void row_keys(const EngineBF16& eng, const EngineBF16
 }
 
 __device__ inline void sweep_band_bf16(const bf8* fa, uint32_t* sD2, uint32_t* sD2O, const uint32_t* __restrict__ d2,
-                                       const PoolArgs& a, int pt, int R0, float lam, float* __restrict__ cp,
+                                       const PoolArgs& a, int pt, int R0, int seg, float lam, float* __restrict__ cp,
                                        uint8_t* __restrict__ code, float (*carry)[16 * MT], float* dummy) {
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = lane & 15, grp = lane >> 4;
@@ -310,8 +324,9 @@ __device__ inline void sweep_band_bf16(const bf8* fa, uint32_t* sD2, uint32_t* s
             ob[mt][j] = ok ? lp * mapsz : (uint32_t)kOOB;
             ob4[mt][j] = ok ? lp * mapsz * 4 : (uint32_t)kOOB;
         }
-    fetch(0);
-    for (int step = 0; step < a.n_steps; ++step) {
+    const StepRange sr = step_range(a, seg);
+    fetch(16 * sr.s_begin);
+    for (int step = sr.s_begin; step < sr.s_end; ++step) {
         const int C0 = 16 * step;
         __syncthreads();                         // previous tile fully consumed
 #pragma unroll
@@ -321,7 +336,7 @@ __device__ inline void sweep_band_bf16(const bf8* fa, uint32_t* sD2, uint32_t* s
             if (idx >= 5 && idx < TILE_N) sD2O[idx - 5] = tv[it];   // the same tile one pixel to the left
         }
         __syncthreads();
-        if (step + 1 < a.n_steps) fetch(C0 + 16);
+        if (step + 1 < sr.s_end) fetch(C0 + 16);
         // Even and odd columns read separate copies, so that both fragments
         // load straight into aligned registers (a pixel is 5 words; reading
         // the odd fragment from the even copy would need register moves).
@@ -352,7 +367,7 @@ __device__ inline void sweep_band_bf16(const bf8* fa, uint32_t* sD2, uint32_t* s
                     fin[mt][j] = max(best[mt][j], rk[mt][j] - 6u);   // my = +1 finishes pooled row r
                     best[mt][j] = rk[mt][j];                         // my = -1 of pooled row r + 1
                 }
-            if (r < a.h1 && c < a.w1) {
+            if (step >= sr.s_out && r < a.h1 && c < a.w1) {
                 const uint32_t rc = (uint32_t)(r * a.w1 + c);
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
@@ -375,7 +390,8 @@ __device__ inline void corr_f32_body(const float* __restrict__ d1, const float* 
                                      float lam, float* __restrict__ cp, uint8_t* __restrict__ code, int bid) {
     __shared__ float sD2[D2R * D2C * 9];
     __shared__ float sCarry[WAVES][ARS][16 * MT];
-    const int pt = bid % a.n_ptiles, R0 = (bid / a.n_ptiles) * TR;
+    const int pt = bid % a.n_ptiles, rest = bid / a.n_ptiles;
+    const int seg = rest % a.n_seg, R0 = (rest / a.n_seg) * TR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n = lane & 15, grp = lane >> 4;
     // Patch fragments: lane (n, grp) holds row grp of the 4x4 patch of patch
@@ -395,7 +411,7 @@ __device__ inline void corr_f32_body(const float* __restrict__ d1, const float* 
         }
     }
     EngineF32 eng{fa, sD2, d2};
-    sweep_band(eng, a, pt, R0, lam, cp, code, sCarry[wave]);
+    sweep_band(eng, a, pt, R0, seg, lam, cp, code, sCarry[wave]);
 }
 
 // BF16 variant: descriptors stored as H x W x 10 bf16 (9 channels + a zero),
@@ -408,7 +424,8 @@ __device__ inline void corr_bf16_body(const uint16_t* __restrict__ d1, const uin
     __shared__ __align__(16) uint32_t sD2O[D2R * D2C * 5];
     __shared__ float sCarry[WAVES][ARS][16 * MT];
     __shared__ float sDummy[WAVES][64 + 16 * MT];   // carry writes of lanes other than the row's last
-    const int pt = bid % a.n_ptiles, R0 = (bid / a.n_ptiles) * TR;
+    const int pt = bid % a.n_ptiles, rest = bid / a.n_ptiles;
+    const int seg = rest % a.n_seg, R0 = (rest / a.n_seg) * TR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n = lane & 15, grp = lane >> 4;
     bf8 fa[MT * 5];
@@ -430,7 +447,7 @@ __device__ inline void corr_bf16_body(const uint16_t* __restrict__ d1, const uin
 #pragma unroll
         for (int s = 0; s < 5; ++s) fa[mt * 5 + s] = load_bf8(tmp + 4 * s);
     }
-    sweep_band_bf16(fa, sD2, sD2O, (const uint32_t*)d2, a, pt, R0, lam, cp, code, sCarry[wave], sDummy[wave]);
+    sweep_band_bf16(fa, sD2, sD2O, (const uint32_t*)d2, a, pt, R0, seg, lam, cp, code, sCarry[wave], sDummy[wave]);
 }
 
 __global__ __launch_bounds__(256, 2) void k_corr_pool_f32(const float* __restrict__ d1,
@@ -467,7 +484,9 @@ struct CorrBF16Job {
     }
 };
 
-PoolArgs make_pool_args(const Geom& g, int& nblocks) {
+// split: allow column segments (single-pair launches; a grouped launch over
+// many pairs has blocks enough without the extra step a segment costs).
+PoolArgs make_pool_args(const Geom& g, int& nblocks, bool split) {
     PoolArgs a;
     a.natom = g.gx[0] * g.gy[0];
     a.n0x = g.gx[0];
@@ -478,7 +497,13 @@ PoolArgs make_pool_args(const Geom& g, int& nblocks) {
     a.w1 = g.w[1];
     a.n_ptiles = (a.natom + PT - 1) / PT;
     a.n_steps = (a.w1 + 15) / 16;
-    nblocks = a.n_ptiles * ((a.h1 + TR - 1) / TR);
+    // Few patches (prototype maps, small images): split the sweep into
+    // column segments until about 1024 blocks exist.
+    const int base = a.n_ptiles * ((a.h1 + TR - 1) / TR);
+    const int want = split ? (1024 + base - 1) / base : 1;
+    a.seg_steps = (a.n_steps + (want < a.n_steps ? want : a.n_steps) - 1) / (want < a.n_steps ? want : a.n_steps);
+    a.n_seg = (a.n_steps + a.seg_steps - 1) / a.seg_steps;
+    nblocks = base * a.n_seg;
     return a;
 }
 
@@ -550,7 +575,7 @@ __global__ void k_corr_pool_ref(const T* __restrict__ d1, const T* __restrict__ 
 hipError_t launch_corr_pool_f32(const float* d1, const float* d2, const Geom& g, float lam, float* cp,
                                 uint8_t* code, hipStream_t s) {
     int nb;
-    const PoolArgs a = make_pool_args(g, nb);
+    const PoolArgs a = make_pool_args(g, nb, true);
     hipLaunchKernelGGL(k_corr_pool_f32, dim3(nb), dim3(256), 0, s, d1, d2, a, lam, cp, code);
     return hipGetLastError();
 }
@@ -558,14 +583,14 @@ hipError_t launch_corr_pool_f32(const float* d1, const float* d2, const Geom& g,
 hipError_t launch_corr_pool_bf16(const uint16_t* d1, const uint16_t* d2, const Geom& g, float lam, float* cp,
                                  uint8_t* code, hipStream_t s) {
     int nb;
-    const PoolArgs a = make_pool_args(g, nb);
+    const PoolArgs a = make_pool_args(g, nb, true);
     hipLaunchKernelGGL(k_corr_pool_bf16, dim3(nb), dim3(256), 0, s, d1, d2, a, lam, cp, code);
     return hipGetLastError();
 }
 
 JobRec corr_job(bool bf16, const void* d1, const void* d2, const Geom& g, float lam, float* cp, uint8_t* code) {
     int nb;
-    const PoolArgs a = make_pool_args(g, nb);
+    const PoolArgs a = make_pool_args(g, nb, false);
     JobRec r;
     if (bf16) r.set(JK_CORR_BF16, nb, 0, CorrBF16Job{(const uint16_t*)d1, (const uint16_t*)d2, a, lam, cp, code});
     else r.set(JK_CORR_F32, nb, 0, CorrF32Job{(const float*)d1, (const float*)d2, a, lam, cp, code});

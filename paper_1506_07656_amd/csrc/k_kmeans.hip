@@ -123,6 +123,17 @@ __device__ inline void merge(Top3& s, const Top3& o) {
     s.v3 = fmaxf(s.v3, o.v3);
 }
 
+// A chunk's Top3 as one 16-byte record: the three values and both indices
+// (below 2^16; 0xFFFF = none) in the fourth word.
+__device__ inline f4 pack(const Top3& s) {
+    const uint32_t i = (uint32_t)min(s.i1, 0xFFFF) | ((uint32_t)min(s.i2, 0xFFFF) << 16);
+    return f4{s.v1, s.v2, s.v3, __uint_as_float(i)};
+}
+__device__ inline Top3 unpack(const f4 r) {
+    const uint32_t i = __float_as_uint(r[3]);
+    return Top3{r[0], r[1], r[2], (int)(i & 0xFFFF), (int)(i >> 16)};
+}
+
 __device__ inline Top3 shfl_xor_top3(const Top3& s, int m) {
     Top3 o;
     o.v1 = __shfl_xor(s.v1, m);
@@ -147,10 +158,12 @@ __global__ __launch_bounds__(256) void k_km_assign(KmArgs a) {
     const int n = lane & 15, grp = lane >> 4;
     const int chunk = blockIdx.y, d0 = chunk * KM_CH;
     const int nd = min(KM_CH, a.D - d0);
-    for (int e = tid; e < KM_CH * 144; e += 256) {
-        const int i = e / 144, k = e - i * 144;
-        const int r = k / 36, j = k - r * 36;
-        sC[i * KM_LD + k] = i < nd ? a.img[(size_t)r * 36 * a.D + 36 * (d0 + i) + j] : 0.f;
+    // 16-byte pieces: centroid i, patch row r, piece v (9 per row of 36 floats)
+    for (int e = tid; e < KM_CH * 36; e += 256) {
+        const int i = e / 36, rv = e - i * 36, r = rv / 9, v = rv - r * 9;
+        f4 x = f4{0.f, 0.f, 0.f, 0.f};
+        if (i < nd) x = *(const f4*)(a.img + (size_t)r * 36 * a.D + 36 * (d0 + i) + 4 * v);
+        *(f4*)(sC + i * KM_LD + 36 * r + 4 * v) = x;
     }
     float fb[KM_NT][36];
     int pp[KM_NT];
@@ -197,14 +210,7 @@ __global__ __launch_bounds__(256) void k_km_assign(KmArgs a) {
         merge(st[nt], shfl_xor_top3(st[nt], 16));
         merge(st[nt], shfl_xor_top3(st[nt], 32));
         const int p = pp[nt];
-        if (grp == 0 && p < a.n) {
-            const size_t o = (size_t)chunk * a.n + p;
-            a.pv1[o] = st[nt].v1;
-            a.pv2[o] = st[nt].v2;
-            a.pv3[o] = st[nt].v3;
-            a.pi1[o] = st[nt].i1;
-            a.pi2[o] = st[nt].i2;
-        }
+        if (grp == 0 && p < a.n) a.part[(size_t)chunk * a.n + p] = pack(st[nt]);
     }
 }
 
@@ -223,10 +229,15 @@ __global__ __launch_bounds__(KM_FIX) void k_km_fix(KmArgs a) {
     __syncthreads();
     const int p = blockIdx.x * KM_FIX + tid;
     if (p < a.n) {
-        Top3 s{a.pv1[p], a.pv2[p], a.pv3[p], a.pi1[p], a.pi2[p]};
-        for (int c = 1; c < a.nchunk; ++c) {
-            const size_t o = (size_t)c * a.n + p;
-            merge(s, Top3{a.pv1[o], a.pv2[o], a.pv3[o], a.pi1[o], a.pi2[o]});
+        Top3 s = unpack(a.part[p]);
+        for (int c0 = 1; c0 < a.nchunk; c0 += 4) {   // four chunks' loads in flight, merged in order
+            f4 r[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (c0 + u < a.nchunk) r[u] = a.part[(size_t)(c0 + u) * a.n + p];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (c0 + u < a.nchunk) merge(s, unpack(r[u]));
         }
         if (s.v1 - s.v2 > kGap) {
             a.assign[p] = s.i1;
@@ -308,25 +319,53 @@ __global__ __launch_bounds__(KM_FIX) void k_km_fix(KmArgs a) {
     }
 }
 
-// One block per centroid: the sum of its members (each wave scans a quarter
-// of the patches in order; the quarters are added in order), then the
-// rescale to norm 4.  A centroid without members keeps its value.
+// Centroid update, pass 1: block (centroid d, patch segment) sums the
+// members of d in its segment (each wave a quarter of it, members in order)
+// and writes the partial sum of the segment.
 __global__ __launch_bounds__(256) void k_km_update(KmArgs a) {
     __shared__ double sPart[4][144];
-    const int d = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    const int d = blockIdx.x, seg = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int per = (a.n + 3) / 4, p0 = wave * per, p1 = min(a.n, p0 + per);
+    const int per_seg = (a.n + a.nsplit - 1) / a.nsplit;
+    const int q0 = seg * per_seg, q1 = min(a.n, q0 + per_seg);
+    const int per = (q1 - q0 + 3) / 4, p0 = q0 + wave * per, p1 = min(q1, p0 + per);
     double s[3] = {0.0, 0.0, 0.0};
-    for (int base = p0; base < p1; base += 64) {
-        const int q = base + lane;
-        unsigned long long m = __ballot(q < p1 && a.assign[q] == d);
-        while (m) {
-            const int j = __ffsll((long long)m) - 1;
-            m &= m - 1;
+    constexpr int AHEAD = 8;   // assignment loads in flight
+    for (int b0 = p0; b0 < p1; b0 += 64 * AHEAD) {
+        int av[AHEAD];
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const int k = lane + 64 * i;
-                if (k < 144) s[i] += (double)patch_elem(a, base + j, k);
+        for (int u = 0; u < AHEAD; ++u) {
+            const int q = b0 + 64 * u + lane;
+            av[u] = q < p1 ? a.assign[q] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < AHEAD; ++u) {
+            const int base = b0 + 64 * u;
+            unsigned long long m = __ballot(av[u] == d);
+            while (m) {   // members in order, four rows' loads in flight
+                int j[4];
+                int cnt = 0;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    j[w] = m ? __ffsll((long long)m) - 1 : -1;
+                    if (m) {
+                        m &= m - 1;
+                        ++cnt;
+                    }
+                }
+                float x[4][3];
+#pragma unroll
+                for (int w = 0; w < 4; ++w)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const int k = lane + 64 * i;
+                        x[w][i] = (w < cnt && k < 144) ? patch_elem(a, base + j[w], k) : 0.f;
+                    }
+#pragma unroll
+                for (int w = 0; w < 4; ++w)
+                    if (w < cnt)
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) s[i] += (double)x[w][i];
             }
         }
     }
@@ -336,12 +375,31 @@ __global__ __launch_bounds__(256) void k_km_update(KmArgs a) {
         if (k < 144) sPart[wave][k] = s[i];
     }
     __syncthreads();
-    if (wave != 0) return;
+    if (tid < 144)
+        a.upd[((size_t)seg * a.D + d) * 144 + tid] =
+            ((sPart[0][tid] + sPart[1][tid]) + sPart[2][tid]) + sPart[3][tid];
+}
+
+// Pass 2, one wave per centroid: the segments' sums added in order, then the
+// rescale to norm 4.  A centroid without members keeps its value.
+__global__ __launch_bounds__(64) void k_km_norm(KmArgs a) {
+    const int d = blockIdx.x, lane = threadIdx.x;
     double t[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const int k = lane + 64 * i;
-        t[i] = k < 144 ? ((sPart[0][k] + sPart[1][k]) + sPart[2][k]) + sPart[3][k] : 0.0;
+        double v = 0.0;
+        if (k < 144)
+            for (int s0 = 0; s0 < a.nsplit; s0 += 4) {   // four segments' loads in flight, added in order
+                double r[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    r[u] = s0 + u < a.nsplit ? a.upd[((size_t)(s0 + u) * a.D + d) * 144 + k] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (s0 + u < a.nsplit) v += r[u];
+            }
+        t[i] = v;
     }
     const double n2 = wave_sum(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
     if (!(n2 > 0.0)) return;
@@ -357,8 +415,14 @@ __global__ __launch_bounds__(256) void k_km_update(KmArgs a) {
 
 int kmeans_chunks(int D) { return (D + KM_CH - 1) / KM_CH; }
 
+int kmeans_update_splits(int D) {
+    const int s = (2048 + D - 1) / D;
+    return s < 1 ? 1 : (s > 16 ? 16 : s);
+}
+
 hipError_t launch_kmeans(const KmArgs& a, int iters, hipStream_t s) {
-    if (a.D < 1 || a.D > DM_MAX_PROTOTYPES || a.D > a.n || a.nchunk != kmeans_chunks(a.D))
+    if (a.D < 1 || a.D > DM_MAX_PROTOTYPES || a.D > a.n || a.nchunk != kmeans_chunks(a.D) ||
+        a.nsplit != kmeans_update_splits(a.D))
         return hipErrorInvalidValue;
     const dim3 g_assign((a.n + KM_PB - 1) / KM_PB, a.nchunk), g_fix((a.n + KM_FIX - 1) / KM_FIX);
     timing_begin("kmeans_init", 0, s);
@@ -374,7 +438,10 @@ hipError_t launch_kmeans(const KmArgs& a, int iters, hipStream_t s) {
         timing_end(s);
         if (it < iters) {
             timing_begin("kmeans_update", 0, s);
-            hipLaunchKernelGGL(k_km_update, dim3(a.D), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(k_km_update, dim3(a.D, a.nsplit), dim3(256), 0, s, a);
+            timing_end(s);
+            timing_begin("kmeans_norm", 0, s);
+            hipLaunchKernelGGL(k_km_norm, dim3(a.D), dim3(64), 0, s, a);
             timing_end(s);
         }
         e = hipGetLastError();
