@@ -63,7 +63,10 @@ dm_status run_match(const float* d1, const float* d2, const dm_plan_info& pi, co
         km.img16 = prm->precision == DM_BF16 ? at<uint16_t>(ws, pi.off_proto_bf) : nullptr;
         km.assign = at<int>(ws, pi.off_assign);
         km.part = at<km_f4>(ws, pi.off_kpart);
-        km.upd = at<double>(ws, pi.off_kpart + ((uint64_t)km.nchunk * na * 16 + 255) / 256 * 256);
+        km.upd = at<double>(ws, pi.off_kpart + km_upd_off(D, na));
+        km.hash = at<unsigned long long>(ws, pi.off_kpart + km_hash_off(D, na));
+        km.shadow = at<int>(ws, pi.off_kpart + km_shadow_off(D, na));
+        km.C64T = at<double>(ws, pi.off_kpart + km_c64t_off(D, na));
         km.stat = at<int>(ws, pi.off_kstat);
         const dm_status st = check_hip(launch_kmeans(km, prm->kmeans_iters, s), "kmeans");
         if (st != DM_OK) return st;

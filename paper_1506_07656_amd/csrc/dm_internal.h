@@ -175,22 +175,36 @@ std::vector<JobRec> bot_jobs(bool bf16, const float* gp, const uint8_t* code, co
 // centroids; C64 [D][144]; img / img16: the prototype image (4 x 4D pixels,
 // 9 floats / 10 bf16 per pixel; img16 may be null); pv*/pi*: [nchunk][n]
 // candidates of the FP32 pass (one 16-byte record per chunk and patch);
-// upd: [nsplit][D][144] partial member sums; stat[2]: patches settled in FP64.
+// C64T: [144][D] copy of C64; upd: [nsplit][D][144] partial member sums;
+// hash[D]: order-independent hash
+// of each centroid's FP64 values; shadow[D]: 1 if the centroid equals one of
+// lower index (it can never be chosen); stat[2]: patches settled in FP64.
 typedef float km_f4 __attribute__((ext_vector_type(4)));
 struct KmArgs {
     const float* d1;
     int W1, gx0, n, D, nchunk, nsplit;
-    double* C64;
+    double *C64, *C64T;   // [D][144] and its k-major copy [144][D]
     float* img;
     uint16_t* img16;
     int* assign;
     km_f4* part;
     double* upd;
+    unsigned long long* hash;
+    int* shadow;
     int* stat;
 };
 constexpr int KM_CH = 64;   // centroids per chunk of the FP32 pass
 int kmeans_chunks(int D);
 int kmeans_update_splits(int D);   // patch segments of the centroid update
+// Byte offsets inside the k-means scratch region (plan.off_kpart).
+inline uint64_t km_align(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+inline uint64_t km_upd_off(int D, int n) { return km_align((uint64_t)kmeans_chunks(D) * n * 16); }
+inline uint64_t km_hash_off(int D, int n) {
+    return km_upd_off(D, n) + km_align((uint64_t)kmeans_update_splits(D) * D * 144 * 8);
+}
+inline uint64_t km_shadow_off(int D, int n) { return km_hash_off(D, n) + km_align((uint64_t)D * 8); }
+inline uint64_t km_c64t_off(int D, int n) { return km_shadow_off(D, n) + km_align((uint64_t)D * 4); }
+inline uint64_t km_scratch_bytes(int D, int n) { return km_c64t_off(D, n) + (uint64_t)D * 144 * 8; }
 hipError_t launch_kmeans(const KmArgs& a, int iters, hipStream_t s);
 
 // Opt-in stage timing (dm_timing.cpp); calls may nest.

@@ -176,10 +176,7 @@ dm_status plan_pair(const dm_params* prm, int W1, int H1, int W2, int H2, dm_pla
         out->off_kstat = take(2 * 4);
         out->off_proto_img = take((uint64_t)D * 144 * 4);
         if (prm->precision == DM_BF16) out->off_proto_bf = take((uint64_t)D * 160 * 2);
-        // candidates of the FP32 pass (16 B per chunk and patch), then the
-        // update's partial sums
-        out->off_kpart = take(align256((uint64_t)out->kmeans_chunks * na * 16) +
-                              (uint64_t)kmeans_update_splits(D) * D * 144 * 8);
+        out->off_kpart = take(km_scratch_bytes(D, (int)na));
     }
     out->workspace_bytes = off;
     return DM_OK;

@@ -34,7 +34,8 @@ constexpr float kGap = 5e-4f;      // FP32 gap that certifies a decision (see ab
 constexpr int KM_NT = 2;           // patch tiles of 16 per wave in the FP32 pass
 constexpr int KM_PB = 64 * KM_NT;  // patches per block (4 waves)
 constexpr int KM_LD = 148;         // LDS row stride (floats) of a staged centroid
-constexpr int KM_FIX = 256;        // patches per block of the decision kernel
+constexpr int KM_FIX = 64;         // patches per block of the decision kernel (one wave)
+constexpr int KM_G3 = 16;          // patches per group of the all-centroid FP64 path
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -59,10 +60,29 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// Order-independent hash of a centroid: the XOR over its elements of a
+// mixed (value bits, element index), reduced over the wave.
+__device__ inline unsigned long long elem_hash(double v, int k) {
+    unsigned long long z = (unsigned long long)__double_as_longlong(v) ^ (0x9E3779B97F4A7C15ull * (k + 1));
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ inline unsigned long long wave_xor(unsigned long long h) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)h, m), hi = __shfl_xor((uint32_t)(h >> 32), m);
+        h ^= ((unsigned long long)hi << 32) | lo;
+    }
+    return h;
+}
+
 // Writes element k of centroid d: the FP64 value, and its FP32 and BF16 forms
 // at pixel (row k / 36, column 4d + (k % 36) / 9) of the prototype image.
 __device__ inline void put_centroid(const KmArgs& a, int d, int k, double v) {
     a.C64[(size_t)d * 144 + k] = v;
+    a.C64T[(size_t)k * a.D + d] = v;
     const int r = k / 36, j = k - r * 36;
     a.img[(size_t)r * 36 * a.D + 36 * d + j] = (float)v;
     if (a.img16) {
@@ -84,15 +104,49 @@ __global__ __launch_bounds__(64) void k_km_init(KmArgs a) {
     }
     const double n2 = wave_sum(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     const double sc = n2 > 0.0 ? 4.0 / sqrt(n2) : 0.0;
+    unsigned long long h = 0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const int k = lane + 64 * i;
-        if (k < 144) put_centroid(a, d, k, v[i] * sc);
+        if (k < 144) {
+            put_centroid(a, d, k, v[i] * sc);
+            h ^= elem_hash(v[i] * sc, k);
+        }
     }
+    h = wave_xor(h);
+    if (lane == 0) a.hash[d] = h;
     if (a.img16 && lane < 16) {   // the padding channel of the prototype's 16 pixels
         const int r = lane >> 2, dx = lane & 3;
         a.img16[((size_t)r * 4 * a.D + 4 * d + dx) * 10 + 9] = 0;
     }
+}
+
+// Shadowed centroids: d is shadowed when it equals (all 144 FP64 values) a
+// centroid of lower index.  Its dot products then equal that centroid's in
+// any evaluation, so the tie rule never chooses it: both assignment paths
+// skip it.  Hashes are compared first; equal hashes are confirmed element by
+// element.
+__global__ __launch_bounds__(256) void k_km_shadow(KmArgs a) {
+    const int d = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (d >= a.D) return;
+    const unsigned long long h = a.hash[d];
+    bool sh = false;   // uniform over the wave
+    for (int e0 = 0; e0 < d && !sh; e0 += 64) {
+        const int e = e0 + lane;
+        unsigned long long m = __ballot(e < d && a.hash[e] == h);
+        while (m && !sh) {
+            const int ee = e0 + __ffsll((long long)m) - 1;
+            m &= m - 1;
+            bool diff = false;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int k = lane + 64 * i;
+                if (k < 144) diff |= a.C64[(size_t)ee * 144 + k] != a.C64[(size_t)d * 144 + k];
+            }
+            sh = __ballot(diff) == 0ull;
+        }
+    }
+    if (lane == 0) a.shadow[d] = sh ? 1 : 0;
 }
 
 // Best two (value, index) pairs and the best value after them.
@@ -153,6 +207,7 @@ __device__ inline Top3 shfl_xor_top3(const Top3& s, int m) {
 // n and folds them into its running Top3.
 __global__ __launch_bounds__(256) void k_km_assign(KmArgs a) {
     __shared__ __align__(16) float sC[KM_CH * KM_LD];
+    __shared__ int sSh[KM_CH];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = lane & 15, grp = lane >> 4;
@@ -165,6 +220,7 @@ __global__ __launch_bounds__(256) void k_km_assign(KmArgs a) {
         if (i < nd) x = *(const f4*)(a.img + (size_t)r * 36 * a.D + 36 * (d0 + i) + 4 * v);
         *(f4*)(sC + i * KM_LD + 36 * r + 4 * v) = x;
     }
+    if (tid < KM_CH) sSh[tid] = tid < nd ? a.shadow[d0 + tid] : 1;
     float fb[KM_NT][36];
     int pp[KM_NT];
 #pragma unroll
@@ -202,7 +258,7 @@ __global__ __launch_bounds__(256) void k_km_assign(KmArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = ct * 16 + 4 * grp + r;
-                if (i < nd) push(st[nt], acc[nt][r], d0 + i);
+                if (!sSh[i]) push(st[nt], acc[nt][r], d0 + i);   // i >= nd is marked shadowed
             }
     }
 #pragma unroll
@@ -214,15 +270,31 @@ __global__ __launch_bounds__(256) void k_km_assign(KmArgs a) {
     }
 }
 
+// Dot products of centroid d with the KM_G3 rows of sX, FP64 FMAs in k
+// order; the centroid's column is read KM_KB values at a time so that the
+// loads are in flight together.
+constexpr int KM_KB = 24;
+__device__ inline void dots_g3(const KmArgs& a, int d, const double (*sX)[144], double (&t)[KM_G3]) {
+    for (int k0 = 0; k0 < 144; k0 += KM_KB) {
+        double c[KM_KB];
+#pragma unroll
+        for (int u = 0; u < KM_KB; ++u) c[u] = a.C64T[(size_t)(k0 + u) * a.D + d];
+#pragma unroll
+        for (int u = 0; u < KM_KB; ++u)
+#pragma unroll
+            for (int j = 0; j < KM_G3; ++j) t[j] = fma(sX[j][k0 + u], c[u], t[j]);
+    }
+}
+
 // Decisions: merge the chunks' Top3 of each patch (fixed order), keep
 // certified answers, and settle the others in FP64 (two candidates: one wave
 // per patch; more: the whole block per patch, over every centroid).
 __global__ __launch_bounds__(KM_FIX) void k_km_fix(KmArgs a) {
     __shared__ int sP2[KM_FIX], sA2[KM_FIX], sB2[KM_FIX], sP3[KM_FIX];
     __shared__ int sN2, sN3;
-    __shared__ double sDot[DM_MAX_PROTOTYPES];
-    __shared__ double sRed[KM_FIX / 64];
-    __shared__ int sRedI[KM_FIX / 64];
+    __shared__ double sX[KM_G3][144];
+    __shared__ double sRed[KM_G3][KM_FIX / 64];
+    __shared__ int sRedI[KM_G3][KM_FIX / 64];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (tid == 0) sN2 = sN3 = 0;
@@ -271,47 +343,71 @@ __global__ __launch_bounds__(KM_FIX) void k_km_fix(KmArgs a) {
         const int win = (oka && okb) ? min(ia, ib) : (oka ? ia : ib);
         if (lane == 0) a.assign[q] = win;
     }
-    // Three or more candidates: every centroid, waves take every 4th.
-    for (int e = 0; e < n3; ++e) {
-        const int q = sP3[e];
-        double x[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const int k = lane + 64 * i;
-            x[i] = k < 144 ? (double)patch_elem(a, q, k) : 0.0;
-        }
-        for (int d = wave; d < a.D; d += KM_FIX / 64) {
-            double t = 0.0;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const int k = lane + 64 * i;
-                if (k < 144) t = fma(x[i], a.C64[(size_t)d * 144 + k], t);
-            }
-            t = wave_sum(t);
-            if (lane == 0) sDot[d] = t;
+    // Three or more candidates: up to KM_G3 patches at a time against every
+    // centroid.  Thread t takes centroids t, t + KM_FIX, ... from the k-major
+    // copy (coalesced), each element serving every patch of the group (FP64
+    // FMAs in k order).  Pass 1 finds each patch's largest dot product, pass 2
+    // the lowest index within kTie of it; shadowed centroids are skipped.
+    for (int g0 = 0; g0 < n3; g0 += KM_G3) {
+        const int ng = min(KM_G3, n3 - g0);
+        __syncthreads();   // the previous group's rows and slots are consumed
+        for (int e = tid; e < KM_G3 * 144; e += KM_FIX) {
+            const int j = e / 144, k = e - j * 144;
+            sX[j][k] = j < ng ? (double)patch_elem(a, sP3[g0 + j], k) : 0.0;
         }
         __syncthreads();
-        double mx = -INFINITY;
-        for (int d = tid; d < a.D; d += KM_FIX) mx = fmax(mx, sDot[d]);
+        double mx[KM_G3];
 #pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) mx = fmax(mx, __shfl_xor(mx, m));
-        if (lane == 0) sRed[wave] = mx;
-        __syncthreads();
-        mx = sRed[0];
-        for (int w = 1; w < KM_FIX / 64; ++w) mx = fmax(mx, sRed[w]);
-        int first = 0x7fffffff;
-        for (int d = tid; d < a.D; d += KM_FIX)
-            if (sDot[d] >= mx - kTie) first = min(first, d);
+        for (int j = 0; j < KM_G3; ++j) mx[j] = -INFINITY;
+        for (int d = tid; d < a.D; d += KM_FIX) {
+            if (a.shadow[d]) continue;
+            double t[KM_G3];
 #pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) first = min(first, __shfl_xor(first, m));
-        if (lane == 0) sRedI[wave] = first;
-        __syncthreads();
-        if (tid == 0) {
-            int f = sRedI[0];
-            for (int w = 1; w < KM_FIX / 64; ++w) f = min(f, sRedI[w]);
-            a.assign[q] = f < a.D ? f : 0;   // no candidate only with non-finite inputs
+            for (int j = 0; j < KM_G3; ++j) t[j] = 0.0;
+            dots_g3(a, d, sX, t);
+#pragma unroll
+            for (int j = 0; j < KM_G3; ++j) mx[j] = fmax(mx[j], t[j]);
         }
-        __syncthreads();   // sDot and the reduction slots are reused by the next patch
+#pragma unroll
+        for (int j = 0; j < KM_G3; ++j) {
+            double v = mx[j];
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m));
+            if (lane == 0) sRed[j][wave] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < KM_G3; ++j) {
+            double v = sRed[j][0];
+            for (int w = 1; w < KM_FIX / 64; ++w) v = fmax(v, sRed[j][w]);
+            mx[j] = v;
+        }
+        int first[KM_G3];
+#pragma unroll
+        for (int j = 0; j < KM_G3; ++j) first[j] = 0x7fffffff;
+        for (int d = tid; d < a.D; d += KM_FIX) {   // ascending: a thread's first hit is its lowest
+            if (a.shadow[d]) continue;
+            double t[KM_G3];
+#pragma unroll
+            for (int j = 0; j < KM_G3; ++j) t[j] = 0.0;
+            dots_g3(a, d, sX, t);
+#pragma unroll
+            for (int j = 0; j < KM_G3; ++j)
+                if (first[j] == 0x7fffffff && t[j] >= mx[j] - kTie) first[j] = d;
+        }
+#pragma unroll
+        for (int j = 0; j < KM_G3; ++j) {
+            int f = first[j];
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) f = min(f, __shfl_xor(f, m));
+            if (lane == 0) sRedI[j][wave] = f;
+        }
+        __syncthreads();
+        if (tid < ng) {
+            int f = sRedI[tid][0];
+            for (int w = 1; w < KM_FIX / 64; ++w) f = min(f, sRedI[tid][w]);
+            a.assign[sP3[g0 + tid]] = f < a.D ? f : 0;   // no candidate only with non-finite inputs
+        }
     }
     if (tid == 0 && (n2 || n3)) {
         atomicAdd(&a.stat[0], n2);
@@ -404,11 +500,17 @@ __global__ __launch_bounds__(64) void k_km_norm(KmArgs a) {
     const double n2 = wave_sum(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
     if (!(n2 > 0.0)) return;
     const double sc = 4.0 / sqrt(n2);
+    unsigned long long h = 0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const int k = lane + 64 * i;
-        if (k < 144) put_centroid(a, d, k, t[i] * sc);
+        if (k < 144) {
+            put_centroid(a, d, k, t[i] * sc);
+            h ^= elem_hash(t[i] * sc, k);
+        }
     }
+    h = wave_xor(h);
+    if (lane == 0) a.hash[d] = h;
 }
 
 }  // namespace
@@ -425,8 +527,12 @@ hipError_t launch_kmeans(const KmArgs& a, int iters, hipStream_t s) {
         a.nsplit != kmeans_update_splits(a.D))
         return hipErrorInvalidValue;
     const dim3 g_assign((a.n + KM_PB - 1) / KM_PB, a.nchunk), g_fix((a.n + KM_FIX - 1) / KM_FIX);
+    const dim3 g_shadow((a.D + 3) / 4);
     timing_begin("kmeans_init", 0, s);
     hipLaunchKernelGGL(k_km_init, dim3(a.D), dim3(64), 0, s, a);
+    timing_end(s);
+    timing_begin("kmeans_shadow", 0, s);
+    hipLaunchKernelGGL(k_km_shadow, g_shadow, dim3(256), 0, s, a);
     timing_end(s);
     hipError_t e = hipGetLastError();
     for (int it = 0; it <= iters && e == hipSuccess; ++it) {
@@ -442,6 +548,9 @@ hipError_t launch_kmeans(const KmArgs& a, int iters, hipStream_t s) {
             timing_end(s);
             timing_begin("kmeans_norm", 0, s);
             hipLaunchKernelGGL(k_km_norm, dim3(a.D), dim3(64), 0, s, a);
+            timing_end(s);
+            timing_begin("kmeans_shadow", 0, s);
+            hipLaunchKernelGGL(k_km_shadow, g_shadow, dim3(256), 0, s, a);
             timing_end(s);
         }
         e = hipGetLastError();
