@@ -78,6 +78,31 @@ library takes the same ones):
      above is computed per patch as in the exact method (parents whose
      children have the same prototypes get equal maps; sharing them would
      save work but changes no value).
+ R20 Scale and rotation invariant DM (Sec. 4.2, Algorithm 2): sigma takes
+     half steps k/2, k in -4..4, and theta eighth turns r pi/4, r in 0..7 (the
+     paper's grid).  The factors 2^(|k|/2) and the cosines and sines are
+     exact table values (powers of two times sqrt(2), and 0, +-1,
+     +-sqrt(1/2)), so every geometric quantity below is reproducible.
+ R21 "I downsized by s" and "R_-theta * I' downsized by s" are one bilinear
+     resampling each: output pixel (u, v) of the rotated canvas maps to
+     q = R_theta((u, v) - c_out) + c_in in the downsized image, and q to
+     s (q + 0.5) - 0.5 in the original (pixel centres aligned); neighbours
+     outside the original count as 0.  The downsized image is
+     floor(W/s) x floor(H/s) with centre c_in = ((W_s - 1)/2, (H_s - 1)/2);
+     the rotated canvas is the bounding box ceil(W_s |cos| + H_s |sin|) x
+     ceil(W_s |sin| + H_s |cos|) with centre c_out likewise; R_theta is
+     [[cos, -sin], [sin, cos]] on (x, y) with y down.  No smoothing before
+     the resampling.
+ R22 Rectification: a run's tuple (p, p', s) maps to
+     P = s1 (p + 0.5) - 0.5 and T = s2 (R_theta(p' - c_out) + c_in + 0.5) - 0.5,
+     evaluated in FP64 in that order and rounded to the nearest pixel
+     (floor(x + 0.5)); tuples whose T falls outside I' are dropped.  A run
+     whose downsized I holds no atomic patch contributes nothing.
+ R23 The union M' keeps the highest score of equal (P, T).  Reciprocal
+     verification uses the fixed 4x4 cells of P in I and of T in I':
+     BestAt(cell of P) is the best score, ties to the smallest (T_y, T_x), then
+     the smallest (P_y, P_x); BestAt'(cell of T) as in R12.  The matches come
+     out ordered by the source cell (row-major), at most one per cell.
 
 Parity of the descriptor against the paper itself is unpinned (R10 fills in
 details the paper does not give); it is pinned only by its invariants.
@@ -609,6 +634,140 @@ def match_descriptors(D1: np.ndarray, D2: np.ndarray, prm: Params = Params()):
 def match(img1: np.ndarray, img2: np.ndarray, prm: Params = Params()):
     """Images -> quasi-dense reciprocal matches [x1, y1, x2, y2, score]."""
     return match_descriptors(descriptors(img1, prm), descriptors(img2, prm), prm)
+
+
+# ----------------------------------------------------------------------------
+# Scale and rotation invariant DeepMatching (Sec. 4.2, Algorithm 2, R20-R23)
+# ----------------------------------------------------------------------------
+
+SQRT_HALF = 0.7071067811865476          # the double nearest to sqrt(1/2)
+ROTATIONS = [(1.0, 0.0), (SQRT_HALF, SQRT_HALF), (0.0, 1.0), (-SQRT_HALF, SQRT_HALF),
+             (-1.0, 0.0), (-SQRT_HALF, -SQRT_HALF), (0.0, -1.0), (SQRT_HALF, -SQRT_HALF)]   # (cos, sin) of r pi/4
+
+
+def scale_factor(k: int) -> float:
+    """2^(|k|/2) from exact operations (R20)."""
+    k = abs(int(k))
+    f = float(2 ** (k // 2))
+    return f * math.sqrt(2.0) if k % 2 else f
+
+
+def scale_pair(k: int):
+    """(s1, s2) of Algorithm 2 for sigma = k/2: max(1, 2^sigma), max(1, 2^-sigma)."""
+    return (scale_factor(k), 1.0) if k > 0 else (1.0, scale_factor(k))
+
+
+def resampled_geometry(W: int, H: int, s: float, r: int):
+    """Sizes and centres of the image downsized by s and rotated by -r pi/4
+    (R21): (W_s, H_s, W_r, H_r, c_in, c_out)."""
+    Ws, Hs = int(math.floor(W / s)), int(math.floor(H / s))
+    c, sn = ROTATIONS[r]
+    Wr = int(math.ceil(Ws * abs(c) + Hs * abs(sn)))
+    Hr = int(math.ceil(Ws * abs(sn) + Hs * abs(c)))
+    return Ws, Hs, Wr, Hr, ((Ws - 1) / 2.0, (Hs - 1) / 2.0), ((Wr - 1) / 2.0, (Hr - 1) / 2.0)
+
+
+def canvas_to_source(u, v, s: float, r: int, cin, cout):
+    """The composed map of R21 / R22: canvas pixel -> position in the
+    original image, evaluated in this order."""
+    c, sn = ROTATIONS[r]
+    du, dv = u - cout[0], v - cout[1]
+    qx = (c * du - sn * dv) + cin[0]
+    qy = (sn * du + c * dv) + cin[1]
+    return s * (qx + 0.5) - 0.5, s * (qy + 0.5) - 0.5
+
+
+def resample(img: np.ndarray, s: float, r: int) -> np.ndarray:
+    """img downsized by s and rotated by -r pi/4: one bilinear resampling,
+    zero outside (R21)."""
+    H, W = img.shape
+    Ws, Hs, Wr, Hr, cin, cout = resampled_geometry(W, H, s, r)
+    v, u = np.meshgrid(np.arange(Hr, dtype=np.float64), np.arange(Wr, dtype=np.float64), indexing="ij")
+    x, y = canvas_to_source(u, v, s, r, cin, cout)
+    x0, y0 = np.floor(x), np.floor(y)
+    fx, fy = x - x0, y - y0
+    x0, y0 = x0.astype(np.int64), y0.astype(np.int64)
+    pad = np.zeros((H + 2, W + 2))
+    pad[1:H + 1, 1:W + 1] = img
+    out = np.zeros((Hr, Wr))
+    for dy, wy in ((0, 1 - fy), (1, fy)):
+        for dx, wx in ((0, 1 - fx), (1, fx)):
+            yy, xx = y0 + dy, x0 + dx
+            inside = (yy >= -1) & (yy <= H) & (xx >= -1) & (xx <= W)
+            val = np.where(inside, pad[np.clip(yy + 1, 0, H + 1), np.clip(xx + 1, 0, W + 1)], 0.0)
+            out += wy * wx * val
+    return out
+
+
+def round_half_up(x):
+    return np.floor(np.asarray(x, dtype=np.float64) + 0.5).astype(np.int64)
+
+
+def invariant_match(img1: np.ndarray, img2: np.ndarray, prm: Params = Params(), scales=range(-4, 5),
+                    rotations=range(8)):
+    """Algorithm 2: DM on every (sigma = k/2, theta = r pi/4) version of the
+    pair, raw atomic correspondences rectified to the input images, their
+    union, then one reciprocal verification (R20-R23).  Returns an (n, 5)
+    array [x1, y1, x2, y2, score] ordered by source cell, and per-match
+    margins (smallest decision gap, as in `reciprocal`)."""
+    H1, W1 = img1.shape
+    H2, W2 = img2.shape
+    Px, Py, Tx, Ty, S, Mg = [], [], [], [], [], []
+    for k in scales:
+        s1, s2 = scale_pair(k)
+        Ws1, Hs1, _, _, _, _ = resampled_geometry(W1, H1, s1, 0)
+        if Ws1 < 4 or Hs1 < 4:
+            continue                                      # no atomic patch (R22)
+        D1 = descriptors(resample(img1, s1, 0), prm)
+        for r in rotations:
+            I2 = resample(img2, s2, r)
+            M = backtrack(pyramid(D1, descriptors(I2, prm), prm))
+            _, _, _, _, cin, cout = resampled_geometry(W2, H2, s2, r)
+            px = round_half_up(s1 * ((2.0 + 4.0 * M["a"]) + 0.5) - 0.5)
+            py = round_half_up(s1 * ((2.0 + 4.0 * M["b"]) + 0.5) - 0.5)
+            tx, ty = canvas_to_source(M["qx"].astype(np.float64), M["qy"].astype(np.float64), s2, r, cin, cout)
+            tx, ty = round_half_up(tx), round_half_up(ty)
+            ok = (tx >= 0) & (tx < W2) & (ty >= 0) & (ty < H2)
+            for L, v in ((Px, px), (Py, py), (Tx, tx), (Ty, ty), (S, M["s"]), (Mg, M["margin"])):
+                L.append(v[ok])
+    if not S or sum(len(v) for v in S) == 0:
+        return np.zeros((0, 5)), np.zeros(0)
+    px, py, tx, ty, s, mg = (np.concatenate(L) for L in (Px, Py, Tx, Ty, S, Mg))
+    # Union: equal (P, T) keep the highest score (R23).
+    pid, tid = py * W1 + px, ty * W2 + tx
+    keep, gap = _dedup_max(pid * (W2 * H2) + tid, s)
+    px, py, tx, ty, s, pid, tid = px[keep], py[keep], tx[keep], ty[keep], s[keep], pid[keep], tid[keep]
+    mg = np.minimum(mg[keep], risky(gap))
+    n = len(s)
+    # BestAt per source cell: best score, ties -> smallest T, then smallest P.
+    cw1, cw2 = (W1 + 3) // 4, (W2 + 3) // 4
+    scell = (py // 4) * cw1 + px // 4
+    o1 = np.lexsort((pid, tid, -s, scell))
+    f1 = np.ones(n, dtype=bool)
+    f1[1:] = scell[o1][1:] != scell[o1][:-1]
+    best_p = o1[f1]
+    gap_p = np.full(n, np.inf)
+    st = np.flatnonzero(f1)
+    two = np.append(st[1:], n) - st > 1
+    gap_p[best_p[two]] = s[o1[st[two]]] - s[o1[st[two] + 1]]
+    # BestAt' per target cell (R12): ties -> smallest (P_y, P_x, T_y, T_x).
+    tcell = (ty // 4) * cw2 + tx // 4
+    o2 = np.lexsort((tid, pid, -s, tcell))
+    f2 = np.ones(n, dtype=bool)
+    f2[1:] = tcell[o2][1:] != tcell[o2][:-1]
+    best_c = o2[f2]
+    gap_c = np.full(n, np.inf)
+    st = np.flatnonzero(f2)
+    two = np.append(st[1:], n) - st > 1
+    gap_c[best_c[two]] = s[o2[st[two]]] - s[o2[st[two] + 1]]
+    is_p = np.zeros(n, dtype=bool)
+    is_p[best_p] = True
+    is_c = np.zeros(n, dtype=bool)
+    is_c[best_c] = True
+    sel = np.flatnonzero(is_p & is_c)
+    sel = sel[np.argsort(scell[sel], kind="stable")]
+    out = np.stack([px[sel], py[sel], tx[sel], ty[sel], s[sel]], axis=1).astype(np.float64)
+    return out, np.minimum(mg[sel], risky(np.minimum(gap_p[sel], gap_c[sel])))
 
 
 # ----------------------------------------------------------------------------

@@ -613,3 +613,71 @@ def test_gradient_rejects_prototypes():
     D1, D2 = rand_desc(rng, 16, 16), rand_desc(rng, 16, 16)
     with pytest.raises(ValueError):
         O.pyramid(D1, D2, O.Params(max_patch=16, prototypes=4), keep_full=True)
+
+
+# ---------------------------------------------------------------- scale and rotation invariance (Sec. 4.2)
+
+def test_scale_and_rotation_tables():
+    assert [O.scale_factor(k) for k in range(5)] == [1.0, math.sqrt(2.0), 2.0, 2 * math.sqrt(2.0), 4.0]
+    assert O.scale_pair(3) == (O.scale_factor(3), 1.0) and O.scale_pair(-2) == (1.0, 2.0) and O.scale_pair(0) == (1.0, 1.0)
+    for r, (c, s) in enumerate(O.ROTATIONS):
+        assert abs(c - math.cos(r * math.pi / 4)) < 1e-15 and abs(s - math.sin(r * math.pi / 4)) < 1e-15
+
+
+def test_resample_identity_quarter_turns_and_halving():
+    rng = np.random.default_rng(40)
+    img = rng.random((23, 30))
+    np.testing.assert_array_equal(O.resample(img, 1.0, 0), img)
+    for r, k in ((2, 1), (4, 2), (6, 3)):
+        np.testing.assert_allclose(O.resample(img, 1.0, r), np.rot90(img, k), rtol=0, atol=1e-15)
+    box = img[:22, :30].reshape(11, 2, 15, 2).mean(axis=(1, 3))
+    np.testing.assert_allclose(O.resample(img, 2.0, 0), box, rtol=0, atol=1e-15)
+
+
+def test_resample_eighth_turn_of_a_ramp():
+    # Bilinear sampling reproduces a linear function exactly: inside the
+    # source, the rotated canvas holds the x coordinate of the mapped point.
+    H, W = 20, 26
+    img = np.tile(np.arange(W, dtype=np.float64), (H, 1))
+    out = O.resample(img, 1.0, 1)
+    Ws, Hs, Wr, Hr, cin, cout = O.resampled_geometry(W, H, 1.0, 1)
+    assert (Wr, Hr) == (math.ceil(46 * O.SQRT_HALF), math.ceil(46 * O.SQRT_HALF))
+    v, u = np.meshgrid(np.arange(Hr, dtype=float), np.arange(Wr, dtype=float), indexing="ij")
+    x, y = O.canvas_to_source(u, v, 1.0, 1, cin, cout)
+    inside = (x >= 0) & (x <= W - 1) & (y >= 0) & (y <= H - 1)
+    assert inside.sum() > 300
+    np.testing.assert_allclose(out[inside], x[inside], rtol=0, atol=1e-12)
+    assert (out[(x < -1) | (x > W) | (y < -1) | (y > H)] == 0).all()
+
+
+def test_invariant_single_run_is_the_exact_method():
+    p = synth.make_pair("c1")
+    prm = O.Params(max_patch=32)
+    out, margin = O.invariant_match(p["img1"], p["img2"], prm, scales=[0], rotations=[0])
+    ref, rmargin, _, _ = O.match(p["img1"], p["img2"], prm)
+    np.testing.assert_array_equal(out, ref)
+    np.testing.assert_array_equal(margin, rmargin)
+
+
+def test_invariant_recovers_a_quarter_turn():
+    img1 = synth.make_pair("c1")["img1"].astype(np.float64)
+    img2 = np.rot90(img1, -1).copy()            # I' = I turned a quarter: the r = 2 run sees I against I
+    prm = O.Params(max_patch=32)
+    out, _ = O.invariant_match(img1, img2, prm, scales=[0], rotations=[0, 2])
+    H, W = img1.shape
+    x1, y1, x2, y2 = (out[:, i].astype(int) for i in range(4))
+    # pixel (x, y) of I sits at (H - 1 - y, x) in I'
+    ok = (x2 == H - 1 - y1) & (y2 == x1)
+    assert len(out) > 150 and ok.mean() > 0.95
+    assert len(np.unique(out[:, 2:4] // 4, axis=0)) == len(out)
+    out0, _ = O.invariant_match(img1, img2, prm, scales=[0], rotations=[0])
+    assert ((out0[:, 2] == H - 1 - out0[:, 1]) & (out0[:, 3] == out0[:, 0])).mean() < 0.2
+
+
+def test_invariant_recovers_a_halving():
+    img1 = synth.make_pair("c1")["img1"].astype(np.float64)
+    img2 = O.resample(img1, 2.0, 0)              # I' = I at half size: the sigma = 1 run sees I' against I'
+    out, _ = O.invariant_match(img1, img2, O.Params(max_patch=16), scales=[0, 2], rotations=[0])
+    x1, y1, x2, y2 = (out[:, i].astype(int) for i in range(4))
+    ok = (x1 == 2 * x2 + 1) & (y1 == 2 * y2 + 1)   # P = 2 (p + 0.5) - 0.5 rounded, T = p
+    assert len(out) > 40 and ok.mean() > 0.9
