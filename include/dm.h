@@ -189,6 +189,54 @@ dm_status dm_match_images(const float* img1, int W1, int H1, int ld1,
                           dm_match* out, int capacity, int* n_out, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Scale and rotation invariant matching (Sec. 4.2, Algorithm 2).
+ *
+ * DeepMatching runs on every selected version of the pair: sigma = k/2 for
+ * the set bits k + 4 of scales_mask (k in -4..4; I is downsized by
+ * max(1, 2^sigma), I' by max(1, 2^-sigma)) and theta = r pi/4 for the set
+ * bits r of rotations_mask (r in 0..7; I' is rotated by -theta).  A
+ * downsized or rotated image is one bilinear resampling of the input
+ * (pixel centres aligned, zero outside; the rotated image is the bounding
+ * box of the turned one).  Every run's raw atomic correspondences
+ * (Eq. (15)) are mapped back to the input images, P = s1 (p + 1/2) - 1/2
+ * and T = s2 (R_theta (p' - c_out) + c_in + 1/2) - 1/2 in FP64 rounded to
+ * the nearest pixel (tuples whose T leaves I' are dropped), and one
+ * reciprocal verification (Eq. (16)) runs over their union with the fixed
+ * 4x4 cells of P in I and of T in I'.  At most one match per source cell,
+ * in row-major order of the source cells; max_matches = ceil(W1/4) *
+ * ceil(H1/4).  The paper's grid is scales_mask = 0x1FF, rotations_mask =
+ * 0xFF (72 runs); scales_mask = 0x10, rotations_mask = 1 is the plain
+ * method.  Runs go one after the other on the stream, reusing the
+ * workspace.  Precisions DM_FP32 and DM_BF16; prototypes must be 0.
+ * --------------------------------------------------------------------------- */
+#define DM_INV_MAX_RUNS 72
+
+typedef struct {
+    int32_t n_runs;            /* runs with at least one atomic patch         */
+    int32_t max_matches;       /* ceil(W1/4) * ceil(H1/4)                       */
+    int32_t run_k[DM_INV_MAX_RUNS], run_r[DM_INV_MAX_RUNS];   /* sigma = k/2, theta = r pi/4 */
+    int32_t run_W1[DM_INV_MAX_RUNS], run_H1[DM_INV_MAX_RUNS]; /* downsized I                 */
+    int32_t run_W2[DM_INV_MAX_RUNS], run_H2[DM_INV_MAX_RUNS]; /* downsized, turned I'        */
+    uint64_t off_best, off_cell, off_img1, off_img2, off_run;  /* workspace layout            */
+    uint64_t workspace_bytes;
+} dm_invariant_info;
+
+/* Plans the runs of an invariant match (host only).  Errors: those of
+ * dm_plan for any run, DM_ERR_INVALID_ARG (empty or out-of-range masks),
+ * DM_ERR_UNSUPPORTED (DM_FP64, prototypes != 0). */
+dm_status dm_plan_invariant(const dm_params* prm, int W1, int H1, int W2, int H2, uint32_t scales_mask,
+                            uint32_t rotations_mask, dm_invariant_info* out);
+
+/* Invariant matches of two images (device buffers, as dm_match_images).
+ * Writes the matches to out[0 .. *n_out) and their count to the DEVICE int
+ * n_out.  Errors: those of dm_plan_invariant, DM_ERR_WORKSPACE,
+ * DM_ERR_CAPACITY (capacity < info.max_matches), DM_ERR_HIP. */
+dm_status dm_match_invariant(const float* img1, int W1, int H1, int ld1, const float* img2, int W2, int H2,
+                             int ld2, const dm_params* prm, uint32_t scales_mask, uint32_t rotations_mask,
+                             void* ws, size_t ws_bytes, dm_match* out, int capacity, int* n_out,
+                             hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Gradient of a loss on the top-level maps (no counterpart in the paper).
  *
  * dm_pyramid_forward computes the pyramid of two descriptor fields (Eqs.

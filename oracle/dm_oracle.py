@@ -720,6 +720,8 @@ def invariant_match(img1: np.ndarray, img2: np.ndarray, prm: Params = Params(), 
             continue                                      # no atomic patch (R22)
         D1 = descriptors(resample(img1, s1, 0), prm)
         for r in rotations:
+            if min(resampled_geometry(W2, H2, s2, r)[2:4]) < 1:
+                continue                                  # an empty image: nothing to add
             I2 = resample(img2, s2, r)
             M = backtrack(pyramid(D1, descriptors(I2, prm), prm))
             _, _, _, _, cin, cout = resampled_geometry(W2, H2, s2, r)

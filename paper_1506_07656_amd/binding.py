@@ -65,6 +65,18 @@ class GradPlan(ctypes.Structure):
                 ("off_g", c_uint64 * 2), ("off_part", c_uint64), ("off_t", c_uint64), ("off_dense", c_uint64)]
 
 
+DM_INV_MAX_RUNS = 72
+
+
+class InvariantInfo(ctypes.Structure):
+    _fields_ = [("n_runs", c_int32), ("max_matches", c_int32),
+                ("run_k", c_int32 * DM_INV_MAX_RUNS), ("run_r", c_int32 * DM_INV_MAX_RUNS),
+                ("run_W1", c_int32 * DM_INV_MAX_RUNS), ("run_H1", c_int32 * DM_INV_MAX_RUNS),
+                ("run_W2", c_int32 * DM_INV_MAX_RUNS), ("run_H2", c_int32 * DM_INV_MAX_RUNS),
+                ("off_best", c_uint64), ("off_cell", c_uint64), ("off_img1", c_uint64), ("off_img2", c_uint64),
+                ("off_run", c_uint64), ("workspace_bytes", c_uint64)]
+
+
 class StageTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 40), ("level", c_int32), ("count", c_int32), ("total_ms", ctypes.c_double)]
 
@@ -109,6 +121,11 @@ SIGNATURES = {
                                POINTER(c_int32), c_void_p, c_void_p]),
     "dm_batch_tiles_get": (c_int, [c_void_p, POINTER(BatchTiles)]),
     "dm_batch_release": (c_int, [c_void_p]),
+    "dm_plan_invariant": (c_int, [POINTER(Params), c_int, c_int, c_int, c_int, ctypes.c_uint32, ctypes.c_uint32,
+                                  POINTER(InvariantInfo)]),
+    "dm_match_invariant": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_int, c_int, POINTER(Params),
+                                   ctypes.c_uint32, ctypes.c_uint32, c_void_p, c_size_t, c_void_p, c_int, c_void_p,
+                                   c_void_p]),
     "dm_timing_enable": (c_int, [c_int]),
     "dm_timing_read": (c_int, [POINTER(StageTime), c_int, POINTER(c_int)]),
     "dm_status_string": (c_char_p, [c_int]),
@@ -238,6 +255,39 @@ def match_images(img1: torch.Tensor, img2: torch.Tensor, prm: Params | None = No
                                  pl.max_matches, c_void_p(n_out.data_ptr()), _stream()))
     m = _matches_tensor(buf, int(n_out.item()))
     return (m, ws, pl) if return_state else m
+
+
+def plan_invariant(W1: int, H1: int, W2: int, H2: int, prm: Params | None = None, scales_mask: int = 0x1FF,
+                   rotations_mask: int = 0xFF) -> InvariantInfo:
+    prm = prm or params()
+    out = InvariantInfo()
+    _check(lib().dm_plan_invariant(ctypes.byref(prm), W1, H1, W2, H2, ctypes.c_uint32(scales_mask),
+                                   ctypes.c_uint32(rotations_mask), ctypes.byref(out)))
+    return out
+
+
+def match_invariant(img1: torch.Tensor, img2: torch.Tensor, prm: Params | None = None, scales_mask: int = 0x1FF,
+                    rotations_mask: int = 0xFF, ws: torch.Tensor | None = None, return_state: bool = False):
+    """Scale and rotation invariant matches (Sec. 4.2) of two H x W float32
+    images: sigma = k/2 for the set bits k + 4 of scales_mask, theta = r pi/4
+    for the set bits r of rotations_mask.  Returns (n x 5: x1, y1, x2, y2,
+    score), ordered by source cell."""
+    prm = prm or params()
+    img1 = _dev(img1, torch.float32, 2, "img1")
+    img2 = _dev(img2, torch.float32, 2, "img2")
+    H1, W1 = img1.shape
+    H2, W2 = img2.shape
+    info = plan_invariant(W1, H1, W2, H2, prm, scales_mask, rotations_mask)
+    ws = torch.empty(int(info.workspace_bytes), dtype=torch.uint8, device=img1.device) if ws is None else ws
+    buf = torch.empty((info.max_matches, 5), dtype=torch.int32, device=img1.device)
+    n_out = torch.zeros(1, dtype=torch.int32, device=img1.device)
+    _check(lib().dm_match_invariant(c_void_p(img1.data_ptr()), W1, H1, img1.stride(0),
+                                    c_void_p(img2.data_ptr()), W2, H2, img2.stride(0), ctypes.byref(prm),
+                                    ctypes.c_uint32(scales_mask), ctypes.c_uint32(rotations_mask),
+                                    c_void_p(ws.data_ptr()), ws.numel(), c_void_p(buf.data_ptr()),
+                                    info.max_matches, c_void_p(n_out.data_ptr()), _stream()))
+    m = _matches_tensor(buf, int(n_out.item()))
+    return (m, ws, info) if return_state else m
 
 
 class Matcher:

@@ -31,10 +31,17 @@ inline P* at(void* ws, uint64_t off) {
         if (st_ != DM_OK) return st_;                                 \
     } while (0)
 
+}  // namespace
+
 // Stages a1..a4 on descriptors d1, d2 (float32) already in device memory.
-dm_status run_match(const float* d1, const float* d2, const dm_plan_info& pi, const dm_params* prm, void* ws,
-                    bool have_bf16, dm_match* out, int* n_out, hipStream_t s) {
+// With rect (a run of invariant matching), the bottom step reduces into the
+// shared tables rbest / rcell through the run's map and nothing is
+// finalised here.
+dm_status dm::run_match(const float* d1, const float* d2, const dm_plan_info& pi, const dm_params* prm, void* ws,
+                        bool have_bf16, dm_match* out, int* n_out, hipStream_t s, const RectMap* rect,
+                        uint64_t* rbest, uint64_t* rcell) {
     Geom g = make_geom(pi);
+    if (rect) g.rect = *rect;
     const float lam = prm->lambda;
     uint8_t* vt = at<uint8_t>(ws, pi.off_valid);
     DM_LAUNCH("valid_init", -1, launch_valid_init(g, vt, s));
@@ -102,10 +109,12 @@ dm_status run_match(const float* d1, const float* d2, const dm_plan_info& pi, co
         DM_LAUNCH("level", l, launch_level<float>(l, cp(l - 1), vt, g, lam, l < pi.lmax ? cp(l) : nullptr,
                                                   l < pi.lmax ? code(l) : nullptr, top, s));
     // a3 + a4: backtracking, bottom reduction, reciprocal check, compaction.
-    uint64_t* best = at<uint64_t>(ws, pi.off_best);
-    uint64_t* cell = at<uint64_t>(ws, pi.off_cell);
-    DM_LAUNCH("fill", -1, launch_fill_u64(best, (size_t)pi.n_atomic, 0, s));
-    DM_LAUNCH("fill", -1, launch_fill_u64(cell, (size_t)((pi.H2 + 3) / 4) * ((pi.W2 + 3) / 4), 0, s));
+    uint64_t* best = rect ? rbest : at<uint64_t>(ws, pi.off_best);
+    uint64_t* cell = rect ? rcell : at<uint64_t>(ws, pi.off_cell);
+    if (!rect) {
+        DM_LAUNCH("fill", -1, launch_fill_u64(best, (size_t)pi.n_atomic, 0, s));
+        DM_LAUNCH("fill", -1, launch_fill_u64(cell, (size_t)((pi.H2 + 3) / 4) * ((pi.W2 + 3) / 4), 0, s));
+    }
     if (pi.lmax == 0) {
         DM_LAUNCH("top_reduce", 0, launch_top_reduce<float>(top, g, best, cell, s));
     } else {
@@ -115,9 +124,11 @@ dm_status run_match(const float* d1, const float* d2, const dm_plan_info& pi, co
                                               l < pi.lmax ? code(l) : nullptr, top, vt, g,
                                               l >= 2 ? u(l - 1) : nullptr, best, cell, s));
     }
-    DM_LAUNCH("finalize", -1, launch_finalize(best, cell, g, out, n_out, s));
+    if (!rect) DM_LAUNCH("finalize", -1, launch_finalize(best, cell, g, out, n_out, s));
     return DM_OK;
 }
+
+namespace {
 
 dm_status check_ws(const dm_plan_info& pi, void* ws, size_t ws_bytes) {
     if (!ws) return fail(DM_ERR_INVALID_ARG, "workspace is null");

@@ -12,6 +12,39 @@
 
 namespace dm {
 
+// Scale and rotation invariant matching (Sec. 4.2): how one run's atomic
+// tuples map back to the input images, and the tables shared by all runs
+// (per 4x4 cell of I and of I').  on = 0: plain matching.
+struct RectMap {
+    int on;
+    int W1o, H1o, W2o, H2o, cw1, cw2;     // input images and their cells per row
+    double s1, s2, c, sn;                 // scales of I and I', cos and sin of theta
+    double cinx, ciny, coutx, couty;      // centres of the downsized I' and of the turned canvas
+};
+
+// Rectified source pixel of atomic patch (a, b) of a run: s1 (p + 1/2) - 1/2,
+// rounded to the nearest pixel; FP64 in this order, no contraction.
+__host__ __device__ inline void rect_source(const RectMap& m, int a, int b, int& px, int& py) {
+#pragma clang fp contract(off)
+    const double x = m.s1 * ((2.0 + 4.0 * a) + 0.5) - 0.5;
+    const double y = m.s1 * ((2.0 + 4.0 * b) + 0.5) - 0.5;
+    px = (int)floor(x + 0.5);
+    py = (int)floor(y + 0.5);
+}
+
+// Rectified target pixel of canvas pixel (u, v): s2 (R_theta((u, v) - c_out)
+// + c_in + 1/2) - 1/2, rounded; false if it lies outside I'.
+__host__ __device__ inline bool rect_target(const RectMap& m, int u, int v, int& tx, int& ty) {
+#pragma clang fp contract(off)
+    const double du = (double)u - m.coutx, dv = (double)v - m.couty;
+    const double qx = (m.c * du - m.sn * dv) + m.cinx;
+    const double qy = (m.sn * du + m.c * dv) + m.ciny;
+    const double x = m.s2 * (qx + 0.5) - 0.5, y = m.s2 * (qy + 0.5) - 0.5;
+    tx = (int)floor(x + 0.5);
+    ty = (int)floor(y + 0.5);
+    return tx >= 0 && tx < m.W2o && ty >= 0 && ty < m.H2o;
+}
+
 // Geometry of one pair as the kernels see it (passed by value).
 // Level l lattice: gx[l] x gy[l] centres; maps of C_l: h[l] x w[l].
 struct Geom {
@@ -24,6 +57,7 @@ struct Geom {
     // patch p reads map slot0[p]; null for the exact method (map p).
     const int32_t* slot0;
     int nslot0;
+    RectMap rect;   // invariant matching: the run's map back to the input images
 };
 
 // Map index, in the level l-1 buffer, of child lattice index c of a level-l
@@ -207,6 +241,12 @@ inline uint64_t km_c64t_off(int D, int n) { return km_shadow_off(D, n) + km_alig
 inline uint64_t km_scratch_bytes(int D, int n) { return km_c64t_off(D, n) + (uint64_t)D * 144 * 8; }
 hipError_t launch_kmeans(const KmArgs& a, int iters, hipStream_t s);
 
+// Stages a1..a4 of one pair on descriptors in device memory (dm_api.cpp);
+// with rect, a run of invariant matching reducing into rbest / rcell.
+dm_status run_match(const float* d1, const float* d2, const dm_plan_info& pi, const dm_params* prm, void* ws,
+                    bool have_bf16, dm_match* out, int* n_out, hipStream_t s, const RectMap* rect = nullptr,
+                    uint64_t* rbest = nullptr, uint64_t* rcell = nullptr);
+
 // Opt-in stage timing (dm_timing.cpp); calls may nest.
 void timing_begin(const char* name, int level, hipStream_t s);
 void timing_end(hipStream_t s);
@@ -254,5 +294,12 @@ hipError_t launch_top_reduce(const T* top, const Geom& g, uint64_t* best, uint64
                              hipStream_t s);
 hipError_t launch_finalize(const uint64_t* best, const uint64_t* cell, const Geom& g,
                            dm_match* out, int* n_out, hipStream_t s);
+// Invariant matching: reciprocal check over the shared tables of all runs.
+hipError_t launch_finalize_rect(const uint64_t* best, const uint64_t* cell, const RectMap& m, dm_match* out,
+                                int* n_out, hipStream_t s);
+// One bilinear resampling (zero outside): canvas pixel (u, v) of dst (Wr x Hr)
+// reads src at s (R((u, v) - c_out) + c_in + 1/2) - 1/2, R = [[c, -sn], [sn, c]].
+hipError_t launch_resample(const float* src, int W, int H, int ld, float* dst, int Wr, int Hr, double s, double c,
+                           double sn, double cinx, double ciny, double coutx, double couty, hipStream_t st);
 
 }  // namespace dm

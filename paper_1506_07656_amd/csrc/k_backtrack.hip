@@ -45,6 +45,9 @@ __device__ inline int xcd_block(int nblocks) {
     return (blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
+// RECT: a run of invariant matching; the bottom step maps each tuple back to
+// the input images and reduces into the tables shared by all runs.
+template <bool RECT>
 __device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_prev,
                                const uint8_t* __restrict__ code_prev, const float* __restrict__ u_cur,
                                const uint8_t* __restrict__ code_cur, const float* __restrict__ top,
@@ -193,16 +196,34 @@ __device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_pre
             const float uu = cpv[u] + dec(vb[u]);
             const int xy = 2 * ry + mv[u] / 3 - 1, xx = 2 * rx + mv[u] % 3 - 1;
             const unsigned long long hi = (unsigned long long)__float_as_uint(uu) << 32;
-            atomicMax(&sBest[k], hi | (0xFFFFFFFFull - (uint32_t)(xy * a.W2 + xx)));
-            const unsigned long long kc = hi | (0xFFFFFFFFull - (uint32_t)(c * 16 + (xy & 3) * 4 + (xx & 3)));
-            atomicMax(&sCell[((xy >> 2) - cyb) * a.ncx + ((xx >> 2) - cxb)], kc);
+            if constexpr (RECT) {
+                int qx, qy, px, py;
+                if (rect_target(g.rect, xx, xy, qx, qy)) {
+                    rect_source(g.rect, c % a.gxc, c / a.gxc, px, py);
+                    atomicMax(&sBest[k], hi | (0xFFFFFFFFull - (uint32_t)(qy * g.rect.W2o + qx)));
+                    atomicMax(&cell[(size_t)(qy >> 2) * g.rect.cw2 + (qx >> 2)],
+                              hi | (0xFFFFFFFFull - (uint32_t)((py * g.rect.W1o + px) * 16 + (qy & 3) * 4 + (qx & 3))));
+                }
+            } else {
+                atomicMax(&sBest[k], hi | (0xFFFFFFFFull - (uint32_t)(xy * a.W2 + xx)));
+                const unsigned long long kc = hi | (0xFFFFFFFFull - (uint32_t)(c * 16 + (xy & 3) * 4 + (xx & 3)));
+                atomicMax(&sCell[((xy >> 2) - cyb) * a.ncx + ((xx >> 2) - cxb)], kc);
+            }
         }
     }
     if (a.is_bottom) {
         __syncthreads();
         for (int e = tid; e < a.CB; e += 256) {
             const int c = cblk * a.CB + e;
-            if (c < a.gxc * a.gyc && sBest[e]) atomicMax(&best[c], sBest[e]);
+            if (c < a.gxc * a.gyc && sBest[e]) {
+                int slot = c;
+                if constexpr (RECT) {
+                    int px, py;
+                    rect_source(g.rect, c % a.gxc, c / a.gxc, px, py);
+                    slot = (py >> 2) * g.rect.cw1 + (px >> 2);
+                }
+                atomicMax(&best[slot], sBest[e]);
+            }
         }
         for (int e = tid; e < a.ncy * a.ncx; e += 256) {
             const unsigned long long v = sCell[e];
@@ -261,6 +282,7 @@ __device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, int nbytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, nbytes, 0x00020000);
 }
 
+template <bool RECT>
 __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __restrict__ cp_prev,
                                       const uint8_t* __restrict__ code_prev, const float* __restrict__ u_cur,
                                       const uint8_t* __restrict__ code_cur, const uint8_t* __restrict__ vt,
@@ -295,6 +317,15 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
         live = vxc[ca] && vyc[cb];
     }
     unsigned long long mybest = 0ull;
+    int pidx = 0, scell = c;   // invariant runs: the rectified source pixel and its cell
+    if constexpr (RECT) {
+        if (live) {
+            int px, py;
+            rect_source(g.rect, ca, cb, px, py);
+            pidx = py * g.rect.W1o + px;
+            scell = (py >> 2) * g.rect.cw1 + (px >> 2);
+        }
+    }
     if (live) {
         const uint8_t *vxp = vtab(vt, g, a.l, 0), *vyp = vtab(vt, g, a.l, 1);
         // One descriptor per array (every array here stays below 2^31 bytes,
@@ -377,10 +408,21 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
                     const int mm = o.cm[dy];
                     const int xy = 2 * ry + code_my(mm) - 1, xx = 2 * rx + code_mx(mm) - 1;
                     const unsigned long long hi = (unsigned long long)__float_as_uint(uu) << 32;
-                    const unsigned long long kb = hi | (0xFFFFFFFFull - (uint32_t)(xy * a.W2 + xx));
-                    mybest = kb > mybest ? kb : mybest;
-                    const unsigned long long kc = hi | (0xFFFFFFFFull - (uint32_t)(c * 16 + (xy & 3) * 4 + (xx & 3)));
-                    atomicMax(&sCell[((xy >> 2) - cyb) * NCX + ((xx >> 2) - cxb)], kc);
+                    if constexpr (RECT) {
+                        int qx, qy;
+                        if (rect_target(g.rect, xx, xy, qx, qy)) {
+                            const unsigned long long kb = hi | (0xFFFFFFFFull - (uint32_t)(qy * g.rect.W2o + qx));
+                            mybest = kb > mybest ? kb : mybest;
+                            atomicMax(&cell[(size_t)(qy >> 2) * g.rect.cw2 + (qx >> 2)],
+                                      hi | (0xFFFFFFFFull - (uint32_t)(pidx * 16 + (qy & 3) * 4 + (qx & 3))));
+                        }
+                    } else {
+                        const unsigned long long kb = hi | (0xFFFFFFFFull - (uint32_t)(xy * a.W2 + xx));
+                        mybest = kb > mybest ? kb : mybest;
+                        const unsigned long long kc =
+                            hi | (0xFFFFFFFFull - (uint32_t)(c * 16 + (xy & 3) * 4 + (xx & 3)));
+                        atomicMax(&sCell[((xy >> 2) - cyb) * NCX + ((xx >> 2) - cxb)], kc);
+                    }
                 }
             }
         };
@@ -427,7 +469,7 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
         const unsigned long long o = ((unsigned long long)hi << 32) | lo;
         mybest = o > mybest ? o : mybest;
     }
-    if (live && t == 0 && mybest) atomicMax(&best[c], mybest);
+    if (live && t == 0 && mybest) atomicMax(&best[scell], mybest);
     __syncthreads();
     for (int e = tid; e < ncy * NCX; e += 64 * kBtWaves) {
         const unsigned long long v = sCell[e];
@@ -438,6 +480,7 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
 }
 
 // A pyramid whose top is the bottom level: M' = every (p, q) of C_top.
+template <bool RECT>
 __device__ inline void top_reduce_body(const float* __restrict__ top, const Geom& g,
                                        unsigned long long* __restrict__ best, unsigned long long* __restrict__ cell,
                                        int bid) {
@@ -447,6 +490,15 @@ __device__ inline void top_reduce_body(const float* __restrict__ top, const Geom
     const int xx = i % g.W2, xy = (i / g.W2) % g.H2;
     const int c = i / ((size_t)g.W2 * g.H2);
     const unsigned long long hi = (unsigned long long)__float_as_uint(top[i]) << 32;
+    if constexpr (RECT) {
+        int qx, qy, px, py;
+        if (!rect_target(g.rect, xx, xy, qx, qy)) return;
+        rect_source(g.rect, c % g.gx[0], c / g.gx[0], px, py);
+        atomicMax(&best[(py >> 2) * g.rect.cw1 + (px >> 2)], hi | (0xFFFFFFFFull - (uint32_t)(qy * g.rect.W2o + qx)));
+        atomicMax(&cell[(size_t)(qy >> 2) * g.rect.cw2 + (qx >> 2)],
+                  hi | (0xFFFFFFFFull - (uint32_t)((py * g.rect.W1o + px) * 16 + (qy & 3) * 4 + (qx & 3))));
+        return;
+    }
     atomicMax(&best[c], hi | (0xFFFFFFFFull - (uint32_t)(xy * g.W2 + xx)));
     atomicMax(&cell[(size_t)(xy >> 2) * ((g.W2 + 3) / 4) + (xx >> 2)],
               hi | (0xFFFFFFFFull - (uint32_t)(c * 16 + (xy & 3) * 4 + (xx & 3))));
@@ -533,6 +585,7 @@ __device__ inline void valid_body(const Geom& g, uint8_t* __restrict__ vt) {
     }
 }
 
+template <bool RECT>
 __global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __restrict__ cp_prev,
                                                    const uint8_t* __restrict__ code_prev,
                                                    const float* __restrict__ u_cur,
@@ -543,9 +596,10 @@ __global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __rest
                                                    unsigned long long* __restrict__ cell, int nblocks) {
     const int bid = xcd_block(nblocks);
     if (bid >= nblocks) return;
-    bt_body(a, cp_prev, code_prev, u_cur, code_cur, top, vt, g, u_prev, best, cell, bid);
+    bt_body<RECT>(a, cp_prev, code_prev, u_cur, code_cur, top, vt, g, u_prev, best, cell, bid);
 }
 
+template <bool RECT>
 __global__ __launch_bounds__(64 * kBtWaves) void k_backtrack_stream(
     BtStreamArgs a, const float* __restrict__ cp_prev, const uint8_t* __restrict__ code_prev,
     const float* __restrict__ u_cur, const uint8_t* __restrict__ code_cur, const uint8_t* __restrict__ vt, Geom g,
@@ -553,12 +607,13 @@ __global__ __launch_bounds__(64 * kBtWaves) void k_backtrack_stream(
     int nblocks) {
     const int bid = xcd_block(nblocks);
     if (bid >= nblocks) return;
-    bt_stream_body(a, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, best, cell, bid);
+    bt_stream_body<RECT>(a, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, best, cell, bid);
 }
 
+template <bool RECT>
 __global__ void k_top_reduce(const float* __restrict__ top, Geom g, unsigned long long* __restrict__ best,
                              unsigned long long* __restrict__ cell) {
-    top_reduce_body(top, g, best, cell, blockIdx.x);
+    top_reduce_body<RECT>(top, g, best, cell, blockIdx.x);
 }
 
 __global__ __launch_bounds__(1024) void k_finalize(const unsigned long long* __restrict__ best,
@@ -583,7 +638,8 @@ struct BtJob {
     float* u_prev;
     unsigned long long *best, *cell;
     static __device__ void run(const BtJob& j, int v) {
-        bt_body(j.a, j.cp_prev, j.code_prev, j.u_cur, j.code_cur, j.top, j.vt, j.g, j.u_prev, j.best, j.cell, v);
+        bt_body<false>(j.a, j.cp_prev, j.code_prev, j.u_cur, j.code_cur, j.top, j.vt, j.g, j.u_prev, j.best, j.cell,
+                       v);
     }
 };
 
@@ -598,7 +654,8 @@ struct BtStreamJob {
     float* u_prev;
     unsigned long long *best, *cell;
     static __device__ void run(const BtStreamJob& j, int v) {
-        bt_stream_body(j.a, j.cp_prev, j.code_prev, j.u_cur, j.code_cur, j.vt, j.g, j.u_prev, j.best, j.cell, v);
+        bt_stream_body<false>(j.a, j.cp_prev, j.code_prev, j.u_cur, j.code_cur, j.vt, j.g, j.u_prev, j.best, j.cell,
+                              v);
     }
 };
 
@@ -606,7 +663,7 @@ struct TopReduceJob {
     const float* top;
     Geom g;
     unsigned long long *best, *cell;
-    static __device__ void run(const TopReduceJob& j, int v) { top_reduce_body(j.top, j.g, j.best, j.cell, v); }
+    static __device__ void run(const TopReduceJob& j, int v) { top_reduce_body<false>(j.top, j.g, j.best, j.cell, v); }
 };
 
 struct FinalizeJob {
@@ -711,17 +768,26 @@ hipError_t launch_backtrack<float>(int l, const float* cp_prev, const uint8_t* c
     if (use_bt_stream(l, g)) {
         int nb;
         const BtStreamArgs b = make_bt_stream_args(l, g, kBtTR, nb);
-        hipLaunchKernelGGL(k_backtrack_stream, dim3(((nb + 7) / 8) * 8), dim3(64 * kBtWaves), 0, s, b, cp_prev,
-                           code_prev, u_cur, code_cur, vt, g, u_prev, (unsigned long long*)best,
-                           (unsigned long long*)cell, nb);
+        if (g.rect.on)
+            hipLaunchKernelGGL(k_backtrack_stream<true>, dim3(((nb + 7) / 8) * 8), dim3(64 * kBtWaves), 0, s, b,
+                               cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, (unsigned long long*)best,
+                               (unsigned long long*)cell, nb);
+        else
+            hipLaunchKernelGGL(k_backtrack_stream<false>, dim3(((nb + 7) / 8) * 8), dim3(64 * kBtWaves), 0, s, b,
+                               cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, (unsigned long long*)best,
+                               (unsigned long long*)cell, nb);
         return hipGetLastError();
     }
     int nblocks;
     size_t smem;
     const BtArgs a = make_bt_args(l, g, nblocks, smem);
     const dim3 grid(((nblocks + 7) / 8) * 8);
-    hipLaunchKernelGGL(k_backtrack, grid, dim3(256), smem, s, a, cp_prev, code_prev, u_cur, code_cur, top, vt, g,
-                       u_prev, (unsigned long long*)best, (unsigned long long*)cell, nblocks);
+    if (g.rect.on)
+        hipLaunchKernelGGL(k_backtrack<true>, grid, dim3(256), smem, s, a, cp_prev, code_prev, u_cur, code_cur, top,
+                           vt, g, u_prev, (unsigned long long*)best, (unsigned long long*)cell, nblocks);
+    else
+        hipLaunchKernelGGL(k_backtrack<false>, grid, dim3(256), smem, s, a, cp_prev, code_prev, u_cur, code_cur, top,
+                           vt, g, u_prev, (unsigned long long*)best, (unsigned long long*)cell, nblocks);
     return hipGetLastError();
 }
 
@@ -786,8 +852,12 @@ template <>
 hipError_t launch_top_reduce<float>(const float* top, const Geom& g, uint64_t* best, uint64_t* cell,
                                     hipStream_t s) {
     const size_t n = (size_t)g.gx[0] * g.gy[0] * g.H2 * g.W2;
-    hipLaunchKernelGGL(k_top_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, top, g,
-                       (unsigned long long*)best, (unsigned long long*)cell);
+    if (g.rect.on)
+        hipLaunchKernelGGL(k_top_reduce<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, top, g,
+                           (unsigned long long*)best, (unsigned long long*)cell);
+    else
+        hipLaunchKernelGGL(k_top_reduce<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, top, g,
+                           (unsigned long long*)best, (unsigned long long*)cell);
     return hipGetLastError();
 }
 

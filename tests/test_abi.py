@@ -232,3 +232,28 @@ def test_match_batch_validation_before_any_launch():
     t = B.BatchTiles()
     assert L.dm_batch_tiles_get(ctypes.c_void_p(0x100000), ctypes.byref(t)) == -1
     assert L.dm_batch_release(ctypes.c_void_p(0x100000)) == 0
+
+
+def test_plan_invariant_runs_and_errors():
+    info = dm.plan_invariant(64, 48, 64, 48, dm.params())
+    assert info.n_runs == 72 and info.max_matches == 16 * 12
+    k = [info.run_k[i] for i in range(72)]
+    r = [info.run_r[i] for i in range(72)]
+    assert k == [kk for kk in range(-4, 5) for _ in range(8)] and r == list(range(8)) * 9
+    for i in range(72):
+        s1, s2 = O.scale_pair(k[i])
+        Ws, Hs, _, _, _, _ = O.resampled_geometry(64, 48, s1, 0)
+        _, _, Wr, Hr, _, _ = O.resampled_geometry(64, 48, s2, r[i])
+        assert (info.run_W1[i], info.run_H1[i], info.run_W2[i], info.run_H2[i]) == (Ws, Hs, Wr, Hr)
+    offs = [info.off_best, info.off_cell, info.off_img1, info.off_img2, info.off_run]
+    assert all(o % 256 == 0 for o in offs) and info.workspace_bytes > info.off_run
+    one = dm.plan_invariant(64, 48, 64, 48, dm.params(), 0x10, 0x1)
+    assert one.n_runs == 1 and (one.run_W1[0], one.run_W2[0]) == (64, 64)
+    # image 1 too small once downsized: those runs are left out
+    small = dm.plan_invariant(12, 12, 64, 48, dm.params(), 0x1FF, 0x1)
+    assert small.n_runs == 8          # k = 4 leaves a 3x3 image 1
+    for kw, args, want in ((dict(), (0, 0xFF), -1), (dict(), (0x200, 0xFF), -1), (dict(), (0x1FF, 0x100), -1),
+                           (dict(precision="fp64"), (0x1FF, 0xFF), -5), (dict(prototypes=8), (0x1FF, 0xFF), -5)):
+        with pytest.raises(dm.DMError) as e:
+            dm.plan_invariant(64, 48, 64, 48, dm.params(**kw), *args)
+        assert e.value.status == want

@@ -1,0 +1,111 @@
+"""Scale and rotation invariant matching (Sec. 4.2, Algorithm 2) on the GPU
+against the FP64 oracle.  The geometry (resampled sizes, rectified
+coordinates) is exact on both sides; pixel values and scores follow the
+plain method's FP32 tolerances."""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1506_07656_amd as dm
+import synth
+from oracle import dm_oracle as O
+from tests.helpers import compare_matches, within_px
+
+pytestmark = pytest.mark.gpu
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def masks(scales, rotations):
+    return sum(1 << (k + 4) for k in scales), sum(1 << r for r in rotations)
+
+
+def report(name, r):
+    print(f"{name}: ref {r['n_ref']} gpu {r['n_gpu']} near-ties {r['near_ties']} missing {len(r['missing'])} "
+          f"moved {len(r['moved'])} bad-score {len(r['bad_score'])} extra {len(r['extra'])} "
+          f"worst rel {r['worst_rel']:.2e}", flush=True)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_inv(key, scales, rotations, mp):
+    i1, i2 = IMAGES[key]()
+    f1, f2 = i1.astype(np.float32).astype(np.float64), i2.astype(np.float32).astype(np.float64)
+    return O.invariant_match(f1, f2, O.Params(max_patch=mp), scales=scales, rotations=rotations)
+
+
+def _c1():
+    p = synth.make_pair("c1")
+    return p["img1"], p["img2"]
+
+
+def _small():
+    rng = np.random.default_rng(4501)
+    a = synth.blurred_noise(rng, 40, 48)
+    b = np.rot90(a, -1) + 0.01 * rng.standard_normal((48, 40))
+    return a, b
+
+
+def _turned():
+    img1 = synth.make_pair("c1")["img1"]
+    return img1, np.rot90(img1, -1).copy()
+
+
+IMAGES = {"c1": _c1, "small": _small, "turned": _turned}
+
+
+def test_single_identity_run_is_the_plain_method():
+    i1, i2 = _c1()
+    prm = dm.params(max_patch=32)
+    m = dm.match_invariant(cuda(i1), cuda(i2), prm, 0x10, 0x1).cpu().numpy()
+    ref = dm.match_images(cuda(i1), cuda(i2), prm).cpu().numpy()
+    np.testing.assert_array_equal(m, ref)
+
+
+@pytest.mark.parametrize("key,scales,rotations,mp", [
+    ("c1", (-2, 0, 1), (0, 1, 2), 32),
+    ("c1", (0, 3), (5, 7), 32),
+    ("small", tuple(range(-4, 5)), tuple(range(8)), 16),
+])
+def test_invariant_matches_oracle(key, scales, rotations, mp):
+    i1, i2 = IMAGES[key]()
+    ref, margin = oracle_inv(key, scales, rotations, mp)
+    sm, rm = masks(scales, rotations)
+    m = dm.match_invariant(cuda(i1), cuda(i2), dm.params(max_patch=mp), sm, rm).cpu().numpy()
+    r = compare_matches(m, ref, margin, tie=1e-4, score_rtol=2e-5)
+    report(f"{key} {scales} {rotations}", r)
+    assert not r["missing"] and not r["moved"] and not r["bad_score"]
+    assert len(r["extra"]) <= max(2, r["near_ties"])
+    cells = (m[:, 1] // 4) * ((i1.shape[1] + 3) // 4) + m[:, 0] // 4
+    assert (np.diff(cells) > 0).all()                             # ordered by source cell, one per cell
+    assert len(np.unique(m[:, 2:4] // 4, axis=0)) == len(m)        # one per target cell
+
+
+def test_quarter_turn_recovered():
+    img1, img2 = _turned()
+    H = img1.shape[0]
+    m = dm.match_invariant(cuda(img1), cuda(img2), dm.params(max_patch=32), 0x10, 0xFF).cpu().numpy()
+    ok = (m[:, 2] == H - 1 - m[:, 1]) & (m[:, 3] == m[:, 0])
+    print(f"turned: {len(m)} matches, {ok.mean():.3f} at the true position", flush=True)
+    assert len(m) > 150 and ok.mean() > 0.95
+
+
+def test_invariant_bf16_close_to_oracle():
+    i1, i2 = _c1()
+    scales, rotations = (-2, 0, 1), (0, 1, 2)
+    ref, _ = oracle_inv("c1", scales, rotations, 32)
+    sm, rm = masks(scales, rotations)
+    m = dm.match_invariant(cuda(i1), cuda(i2), dm.params(max_patch=32, precision="bf16"), sm, rm).cpu().numpy()
+    frac = within_px(m, ref, 1.0)
+    print(f"c1 bf16 invariant: {len(m)} matches, {frac:.4f} of oracle matches within 1 px", flush=True)
+    assert frac >= 0.97
+
+
+def test_invariant_deterministic():
+    i1, i2 = _c1()
+    a = dm.match_invariant(cuda(i1), cuda(i2), dm.params(max_patch=32), 0x1FF, 0xFF)
+    b = dm.match_invariant(cuda(i1), cuda(i2), dm.params(max_patch=32), 0x1FF, 0xFF)
+    assert torch.equal(a, b)
