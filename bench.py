@@ -15,6 +15,11 @@ The "approx" entry is approximate DeepMatching (Sec. 4.1) on the same pair
 with D = 1024 and 64 prototypes: throughput, k-means time, workspace size and
 agreement with the exact path's matches.
 
+The "invariant" entry is scale and rotation invariant DeepMatching (Sec. 4.2,
+Algorithm 2) on the same pair: the paper's grid of 9 scales x 8 rotations (72
+runs of the pipeline on resampled pairs, one reciprocal check over their
+union), BF16 correlation.
+
 The "batch" entry is the uneven-batch workload: 32 pairs with W ~ U{128..621},
 H ~ U{96..188} (half of a 1242x375 driving-frame shape), BF16 correlation,
 FP32 pyramid, forward plus backward of the top loss, every stage one
@@ -300,6 +305,39 @@ def approx_bench(dm, torch, img1, img2, exact_matches, exact_plan, steps, warmup
     return res
 
 
+def invariant_bench(dm, torch, img1, img2, plain_ms, steps, warmup):
+    """Algorithm 2 on the pair: the full 9 x 8 grid, and per-stage times."""
+    prm = dm.params(precision="bf16")
+    info = dm.plan_invariant(img1.shape[1], img1.shape[0], img2.shape[1], img2.shape[0], prm)
+    ws = torch.empty(int(info.workspace_bytes), dtype=torch.uint8, device="cuda")
+    run = lambda: dm.match_invariant(img1, img2, prm, ws=ws)
+    for _ in range(warmup):
+        m = run()
+    torch.cuda.synchronize()
+    n = max(2, steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(n):
+        m = run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / n
+    dm.timing_enable(True)
+    run()
+    torch.cuda.synchronize()
+    stages = dm.timing_read()
+    dm.timing_enable(False)
+    per = {}
+    for name, level, count, total in stages:
+        key = name if level < 0 else f"{name}_l{level}"
+        per[key] = per.get(key, 0.0) + total
+    top = sorted(per.items(), key=lambda kv: -kv[1])[:6]
+    return dict(pairs_s=round(1.0 / dt, 3), ms_per_step=round(dt * 1e3, 3), runs=int(info.n_runs),
+                matches=int(len(m)), vs_plain=round(dt * 1e3 / plain_ms, 1),
+                workspace_mb=round(info.workspace_bytes / 2**20, 1),
+                top_stages_ms=[(k, round(v, 3)) for k, v in top],
+                workload="the same 512x256 pair; sigma = -2..2 step 1/2, theta = 0..7 pi/4 (72 runs); "
+                         "BF16 correlation, FP32 pyramid")
+
+
 def oracle_agreement(matches):
     """Fraction of the stored oracle matches of the pair reproduced within 1 px."""
     import numpy as np
@@ -344,7 +382,9 @@ def main():
                     help="after the run, copy 1 GiB device to device (calibrates HBM byte counters)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-pair uneven batch")
     ap.add_argument("--no-approx", action="store_true", help="skip approximate DeepMatching")
-    ap.add_argument("--only", choices=("all", "fwd_bf16", "fwd_bwd_bf16", "approx1024", "approx64"), default="all",
+    ap.add_argument("--no-invariant", action="store_true", help="skip scale and rotation invariant DeepMatching")
+    ap.add_argument("--only", choices=("all", "fwd_bf16", "fwd_bwd_bf16", "approx1024", "approx64", "invariant"),
+                    default="all",
                     help="run only that pass (short profiler runs); prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -363,6 +403,17 @@ def main():
         if args.copy_probe:
             copy_probe(torch)
         print(f"bf16 forward: {dt * 1e3:.3f} ms/pair", flush=True)
+        return
+    if args.only == "invariant":
+        prm = dm.params(precision="bf16")
+        for _ in range(args.warmup):
+            dm.match_invariant(img1, img2, prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dm.match_invariant(img1, img2, prm)
+        torch.cuda.synchronize()
+        print(f"invariant (72 runs) bf16: {(time.perf_counter() - t0) / args.steps * 1e3:.3f} ms/pair", flush=True)
         return
     if args.only.startswith("approx"):
         D = int(args.only[len("approx"):])
@@ -438,6 +489,8 @@ def main():
     }
     if not args.no_approx:
         out["approx"] = approx_bench(dm, torch, img1, img2, head["matches"], head["plan"], args.steps, args.warmup)
+    if not args.no_invariant:
+        out["invariant"] = invariant_bench(dm, torch, img1, img2, head["ms"], args.steps, args.warmup)
     if not args.no_batch:
         out["batch"] = batch_bench(dm, torch, max(3, args.steps // 2))
     if not args.no_cpu_baseline:
