@@ -328,14 +328,15 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
     }
     if (live) {
         const uint8_t *vxp = vtab(vt, g, a.l, 0), *vyp = vtab(vt, g, a.l, 1);
-        // One descriptor per array (every array here stays below 2^31 bytes,
-        // checked at launch); parents are selected by element offsets.
+        // One descriptor per parent array (below 2^31 bytes, checked at
+        // launch; parents are selected by element offsets) and one over this
+        // child's own map of C'_{l-1}.
         const int usz = a.hu * a.wu, csz = a.h * a.w;
         const int nparent = a.gxp * a.gyp;
-        const int nmap = (a.l == 1 && g.slot0) ? g.nslot0 : a.gxc * a.gyc;   // maps in the C'_{l-1} buffer
         const __amdgpu_buffer_rsrc_t rsU = rsrc(u_cur, nparent * usz * 4), rsM = rsrc(code_cur, nparent * usz);
-        const __amdgpu_buffer_rsrc_t rsC = rsrc(cp_prev, nmap * csz * 4);
-        const __amdgpu_buffer_rsrc_t rsK = rsrc(code_prev, a.is_bottom ? nmap * csz : 0);
+        const size_t cmap = (size_t)child_slot(g, a.l, c) * csz;
+        const __amdgpu_buffer_rsrc_t rsC = rsrc(cp_prev + cmap, csz * 4);
+        const __amdgpu_buffer_rsrc_t rsK = rsrc(code_prev + cmap, a.is_bottom ? csz : 0);
         // Element offset of each parent's map, or a large negative value for a
         // missing parent: with a lane's row offset added (also large negative
         // when the lane or row has no U_l entry), an entry exists exactly when
@@ -349,7 +350,6 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
             const bool ok = pb >= 0 && pb < a.gyp && pa >= 0 && pa < a.gxp && vxp[pa] && vyp[pb];
             pbase[side] = ok ? (pb * a.gxp + pa) * usz : kNone;
         }
-        const int cbase = child_slot(g, a.l, c) * csz;
         uint32_t (*ring)[kBtCols] = sR[wv];
         const int rx = C0 + t;                       // the lane's output column
         const int ux = (C0 >> 1) - 1 + t;            // the lane's U_l column while scattering
@@ -389,7 +389,7 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
                 const int ry = 2 * rp - 2 + dy;
                 const bool rok = ry >= R0 && ry < R1;                          // uniform
                 o.vb[dy] = (rok && lane_o) ? atomicExch(&ring[ry & (kBtRing - 1)][t], 0u) : 0u;
-                const int off = cbase + ry * a.w + rx;   // element offset, used only where a tuple arrived
+                const int off = ry * a.w + rx;   // element offset in the child's map, used only where a tuple arrived
                 o.cv[dy] = __uint_as_float(
                     __builtin_amdgcn_raw_buffer_load_b32(rsC, o.vb[dy] ? off * 4 : kOOB, 0, 0));
                 o.cm[dy] = __builtin_amdgcn_raw_buffer_load_b8(rsK, o.vb[dy] ? off : kOOB, 0, 0);
@@ -728,11 +728,11 @@ BtArgs make_bt_args(int l, const Geom& g, int& nblocks, size_t& smem) {
 }
 
 // The streaming form serves every step below the top whose child maps are at
-// least 32 columns wide and whose arrays stay below 2^31 bytes (buffer offsets).
+// least 32 columns wide and whose parent arrays (U_l) stay below 2^31 bytes
+// (buffer offsets; a child's map has a descriptor of its own).
 bool use_bt_stream(int l, const Geom& g) {
     if (l == g.lmax || g.w[l] < 32) return false;
-    return (double)g.gx[l] * g.gy[l] * g.h[l + 1] * g.w[l + 1] * 4 < 2.0e9 &&
-           (double)g.gx[l - 1] * g.gy[l - 1] * g.h[l] * g.w[l] * 4 < 2.0e9;
+    return (double)g.gx[l] * g.gy[l] * g.h[l + 1] * g.w[l + 1] * 4 < 2.0e9;
 }
 
 // Streaming form with bands of tr rows (even, at most kBtMaxTR).
