@@ -257,3 +257,27 @@ def test_plan_invariant_runs_and_errors():
         with pytest.raises(dm.DMError) as e:
             dm.plan_invariant(64, 48, 64, 48, dm.params(**kw), *args)
         assert e.value.status == want
+
+
+def test_match_invariant_validation_before_any_launch():
+    """Fake device addresses: every call below fails on the host."""
+    L = dm.lib()
+    info = dm.plan_invariant(64, 48, 64, 48, dm.params(), 0x1FF, 0xFF)
+    need, cap = info.workspace_bytes, info.max_matches
+
+    def call(prm=None, smask=0x1FF, rmask=0xFF, ws=0x100000, nbytes=need, out=0x200000, capacity=cap,
+             n_out=0x300000, img1=0x1000, img2=0x2000, ld1=64, ld2=64):
+        prm = prm or dm.params()
+        return L.dm_match_invariant(ctypes.c_void_p(img1), 64, 48, ld1, ctypes.c_void_p(img2), 64, 48, ld2,
+                                    ctypes.byref(prm), smask, rmask, ctypes.c_void_p(ws), nbytes,
+                                    ctypes.c_void_p(out), capacity, ctypes.c_void_p(n_out), None)
+
+    assert call(nbytes=need - 1) == -3
+    assert call(capacity=cap - 1) == -4
+    assert call(ws=0x100010) == -1 and call(ws=0) == -1
+    assert call(img1=0) == -1 and call(out=0) == -1 and call(n_out=0) == -1
+    assert call(ld1=63) == -2
+    assert call(smask=0) == -1 and call(rmask=0x100) == -1
+    assert call(prm=dm.params(precision="fp64")) == -5
+    assert call(prm=dm.params(prototypes=4)) == -5
+    assert b"prototypes" in L.dm_last_error()

@@ -153,3 +153,22 @@ def test_approx_512x256_bench_configuration():
             _, ref, _, _ = load_golden("c3")
             print(f"c3 D=1024: {len(m)} matches; {within_px(m, ref, 1.0):.4f} of the exact method's within 1 px",
                   flush=True)
+
+
+def test_approx_uneven_crops():
+    """I 310x150, I' 300x156 (crops of the 512x256 pair): level maps 150, 75,
+    38, ... wide, 2849 atomic patches, D = 333 (not a multiple of the
+    64-centroid chunks)."""
+    from tests.test_gpu_parity import odd_case
+    o = odd_case()
+    D1, D2 = f32(o["D1"]), f32(o["D2"])
+    prm = O.Params(prototypes=333, kmeans_iters=6)
+    out, margin, pyr, _ = O.match_descriptors(D1, D2, prm)
+    gpu, views, pl = run_gpu(D1, D2, prototypes=333, kmeans_iters=6)
+    assert pl.lmax == pyr.lmax and pl.n_atomic == 77 * 37
+    check_kmeans(views, pyr, "odd D=333")
+    r = compare_matches(gpu, out, margin)
+    print(f"odd D=333: ref {r['n_ref']} gpu {r['n_gpu']} near-ties {r['near_ties']} missing {len(r['missing'])} "
+          f"moved {len(r['moved'])} bad-score {len(r['bad_score'])} extra {len(r['extra'])}", flush=True)
+    assert not r["missing"] and not r["moved"] and not r["bad_score"]
+    assert len(r["extra"]) <= r["near_ties"]

@@ -109,3 +109,41 @@ def test_invariant_deterministic():
     a = dm.match_invariant(cuda(i1), cuda(i2), dm.params(max_patch=32), 0x1FF, 0xFF)
     b = dm.match_invariant(cuda(i1), cuda(i2), dm.params(max_patch=32), 0x1FF, 0xFF)
     assert torch.equal(a, b)
+
+
+def _ragged():
+    rng = np.random.default_rng(4502)
+    a = synth.blurred_noise(rng, 37, 53)
+    b = synth.blurred_noise(rng, 45, 29)
+    return a, b
+
+
+IMAGES["ragged"] = _ragged
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_invariant_ragged_sizes(prec):
+    """I 53x37 and I' 29x45 (odd, non-square): turned canvases of odd size,
+    downsized images of 37, 26, 18, 13, 9 pixels."""
+    i1, i2 = _ragged()
+    scales, rotations = (-3, -1, 0, 2, 4), (0, 1, 3, 6)
+    ref, margin = oracle_inv("ragged", scales, rotations, 0)
+    sm, rm = masks(scales, rotations)
+    m = dm.match_invariant(cuda(i1), cuda(i2), dm.params(precision=prec), sm, rm).cpu().numpy()
+    if prec == "fp32":
+        r = compare_matches(m, ref, margin, tie=1e-4, score_rtol=2e-5)
+        report("ragged", r)
+        assert not r["missing"] and not r["moved"] and not r["bad_score"]
+        assert len(r["extra"]) <= max(2, r["near_ties"])
+    else:
+        frac = within_px(m, ref, 1.0)
+        print(f"ragged bf16: {len(m)} matches, {frac:.4f} of oracle matches within 1 px", flush=True)
+        assert frac >= 0.95
+
+
+def test_single_identity_run_is_the_plain_method_bf16():
+    i1, i2 = _c1()
+    prm = dm.params(max_patch=32, precision="bf16")
+    m = dm.match_invariant(cuda(i1), cuda(i2), prm, 0x10, 0x1).cpu().numpy()
+    ref = dm.match_images(cuda(i1), cuda(i2), prm).cpu().numpy()
+    np.testing.assert_array_equal(m, ref)
