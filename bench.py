@@ -180,9 +180,58 @@ def cpu_baseline(pair, cw=384, ch=192):
     O.match(c1, c2, O.Params())
     t = time.perf_counter() - t0
     scale = (W * H) ** 2 / (cw * ch) ** 2
+    # The 64x64 pair in full, with every thread and with one (the paper's
+    # CPU timings are for one core).
+    import synth
+    small = synth.make_pair("c1")
+    t1 = time.perf_counter()
+    O.match(small["img1"], small["img2"], O.Params(max_patch=32))
+    t_small = time.perf_counter() - t1
+    t_small_1 = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            O.match(small["img1"], small["img2"], O.Params(max_patch=32))
+            t_small_1 = round(time.perf_counter() - t1, 3)
+    except Exception:
+        pass
     return dict(value=1.0 / (t * scale), unit="pairs/s", cores=int(cores), kind="oracle",
                 sample=f"oracle (FP64 NumPy) descriptors-to-matches on the central {cw}x{ch} crop of the {W}x{H} "
-                       f"pair: {t:.1f} s, scaled by the O(LL') cost ratio {scale:.0f} to a full pair")
+                       f"pair: {t:.1f} s, scaled by the O(LL') cost ratio {scale:.0f} to a full pair",
+                c1_64x64_s=round(t_small, 3), c1_64x64_s_one_thread=t_small_1, host=host_info())
+
+
+def host_info():
+    """CPU model, logical CPUs and memory of the host the oracle ran on."""
+    model, mem_gb = None, None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    mem_gb = round(int(line.split()[1]) / 2**20, 1)
+                    break
+    except OSError:
+        pass
+    return dict(cpu_model=model, cpu_count=os.cpu_count(), mem_gb=mem_gb)
+
+
+def small_pairs(dm, torch, steps):
+    """GPU throughput on the 64x64 and 256x192 pairs (BF16 correlation)."""
+    import synth
+    res = {}
+    for name, mp in (("c1", 32), ("c2", 64)):
+        p = synth.make_pair(name)
+        i1, i2 = torch.from_numpy(p["img1"]).cuda(), torch.from_numpy(p["img2"]).cuda()
+        dt, _, _, _ = time_path(dm, torch, i1, i2, "bf16", steps, 3, max_patch=mp)
+        res[name] = dict(size=f"{p['img1'].shape[1]}x{p['img1'].shape[0]}", pairs_s=round(1.0 / dt, 1),
+                         ms_per_step=round(dt * 1e3, 4))
+    return res
 
 
 def pair_work(pl):
@@ -487,6 +536,7 @@ def main():
         "kernels_fp32": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items() if k != "work"}
                          for r in rows32[:4]],
     }
+    out["small_pairs"] = small_pairs(dm, torch, args.steps)
     if not args.no_approx:
         out["approx"] = approx_bench(dm, torch, img1, img2, head["matches"], head["plan"], args.steps, args.warmup)
     if not args.no_invariant:

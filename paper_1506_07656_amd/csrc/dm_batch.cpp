@@ -44,6 +44,7 @@ hipError_t launch_group(int kind, const GroupLaunch& gl, hipStream_t s) {
         case JK_FILL:
         case JK_BT:
         case JK_BT_STREAM:
+        case JK_BT_STREAM64:
         case JK_TOP_REDUCE:
         case JK_FINALIZE:
             return launch_group_bt(kind, gl, s);
@@ -74,6 +75,7 @@ int default_res(int kind) {
         case JK_LEVEL_STREAM_VEC:
         case JK_LEVEL_STREAM:
         case JK_BT_STREAM:
+        case JK_BT_STREAM64:
         case JK_BWD_LEVEL_STREAM:
             return 6;
         case JK_VALID:
@@ -371,7 +373,7 @@ dm_status autotune(Schedule& S, int n, const dm_pair* pairs, const dm_params* pr
     dm_status st = rebuild();
     if (st != DM_OK) return st;
     if ((st = run(S, ws, s, false)) != DM_OK) return st;   // every stage's inputs in place
-    const std::vector<int> lev = {JK_LEVEL_STREAM_VEC, JK_LEVEL_STREAM}, bt = {JK_BT_STREAM};
+    const std::vector<int> lev = {JK_LEVEL_STREAM_VEC, JK_LEVEL_STREAM}, bt = {JK_BT_STREAM, JK_BT_STREAM64};
     const int reps = 3;
     // band heights (job tables change)
     {

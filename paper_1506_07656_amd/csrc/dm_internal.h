@@ -158,6 +158,7 @@ enum JobKind : int {
     JK_TG_F32,
     JK_DD1_REDUCE,
     JK_COL2IM,
+    JK_BT_STREAM64,
     JK_COUNT
 };
 

@@ -236,7 +236,9 @@ __device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_pre
 
 // Row-streaming form of k_backtrack below the top, for child maps at least
 // 32 columns wide.  One wave owns a child c, a band of TR rows of its pooled
-// grid and 64 columns (one per lane).  It walks down the rows of U_l of the
+// grid and 60 columns (one per lane; the parents' entries that can reach
+// them span 32 columns, so each lane loads and scatters two of the four
+// parents at once).  It walks down the rows of U_l of the
 // child's (up to 4) parents.  Each U_l entry of parent P_i = c - 2^l o_i
 // reaches V_l(P_i, x) at x = 2r' + m, hence the child's candidate at
 // r = x + o_i, so the entry goes straight (max on collision, packed keys) into
@@ -250,11 +252,14 @@ __device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_pre
 // one step ahead of their use.
 // At the bottom the 4 waves of a block (4 children, same rows and columns)
 // share the cell-table window; BestAt(c) is reduced within the wave.
-constexpr int kBtCols = 64;
+constexpr int kBtCols = 64;    // lanes per wave: width of the candidate ring
+// Output columns per wave: 60 (the parents' U_l entries that reach them span
+// 32 columns, so the 64 lanes load and scatter two sides at once) or 64 (34
+// columns: one side at a time, fewer waves when the map is 64 k wide).
 constexpr int kBtWaves = 4;
 constexpr int kBtRing = 8;     // live candidate rows 2r'-2 .. 2r'+2 (5), rounded up to a power of two
 constexpr int kBtMaxTR = 64;   // tallest band (sizes the cell window in LDS)
-constexpr int kBtTR = 32;      // band of the single-pair launch
+constexpr int kBtTR = 64;      // band of the single-pair launch
 constexpr int kOOB = 0x7ffffff0;   // buffer byte offset past any map (element offsets stay < 2^29)
 
 struct BtStreamArgs {
@@ -264,6 +269,7 @@ struct BtStreamArgs {
     int is_bottom;
     int TR, n_band, n_ct, n_cgrp;
     int W2, cw;
+    int tile;   // output columns per wave (60 or 64)
 };
 
 // Window offsets of an argmax code k = 3 m_y + m_x (m in 0..2): 2-bit fields
@@ -282,7 +288,7 @@ __device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, int nbytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, nbytes, 0x00020000);
 }
 
-template <bool RECT>
+template <bool RECT, int TILE>
 __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __restrict__ cp_prev,
                                       const uint8_t* __restrict__ code_prev, const float* __restrict__ u_cur,
                                       const uint8_t* __restrict__ code_cur, const uint8_t* __restrict__ vt,
@@ -297,7 +303,7 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
     const int tid = threadIdx.x, t = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index: uniform
     const int R0 = band * a.TR, R1 = min(R0 + a.TR, a.h);
-    const int C0 = ct * kBtCols, Cend = min(C0 + kBtCols, a.w);
+    const int C0 = ct * TILE, Cend = min(C0 + TILE, a.w);
     const int ncy = a.TR / 2 + 2;
     const int cyb = (2 * R0 - 1) >> 2, cxb = (2 * C0 - 1) >> 2;   // floor division by 4
     {
@@ -352,35 +358,53 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
         }
         uint32_t (*ring)[kBtCols] = sR[wv];
         const int rx = C0 + t;                       // the lane's output column
-        const int ux = (C0 >> 1) - 1 + t;            // the lane's U_l column while scattering
-        const bool lane_u = t < NCX && ux >= 0 && ux < a.wu;
-        const bool lane_o = rx < Cend;
+        // While scattering, TILE = 60: lane t serves U_l column ux of the
+        // sides 2p + h (h = t / 32) in the passes p = 0, 1 (output columns
+        // [C0, C0 + 60) are reached only from columns C0/2 - 1 .. C0/2 + 30);
+        // TILE = 64: lane t < 34 serves column ux of every side.
+        constexpr int NP = TILE == 60 ? 2 : 4;       // passes (sides per lane)
+        const int h = t >> 5;
+        const int ux = (C0 >> 1) - 1 + (TILE == 60 ? (t & 31) : t);
+        const bool lane_u = (TILE == 60 || t < TILE / 2 + 2) && ux >= 0 && ux < a.wu;
+        const bool lane_o = t < TILE && rx < Cend;
+        // Parent map offset of pass p for this lane; o_i of Eq. (5) along y
+        // for the lane's sides (TILE = 60; along x it is fixed per pass).
+        int pbl[NP];
+        if constexpr (TILE == 60) {
+            pbl[0] = h ? pbase[1] : pbase[0];
+            pbl[1] = h ? pbase[3] : pbase[2];
+        } else {
+#pragma unroll
+            for (int p = 0; p < NP; ++p) pbl[p] = pbase[p];
+        }
+        const int sy_l = h ? 1 : -1;
         const int rp0 = (R0 - 1) >> 1, rp1 = ((R1 - 1) >> 1) + 1;
 
-        struct UBuf { float u[4]; int m[4]; };
+        struct UBuf { float u[NP]; int m[NP]; };
         struct OBuf { uint32_t vb[2]; float cv[2]; int cm[2]; };
         auto load_u = [&](int rp, UBuf& st) {
             const bool rok = lane_u && rp >= 0 && rp < a.hu;
             const int roff = rok ? rp * a.wu + ux : kNone;
 #pragma unroll
-            for (int side = 0; side < 4; ++side) {
-                const int off = pbase[side] + roff;   // >= 0 exactly for an existing entry
+            for (int p = 0; p < NP; ++p) {
+                const int off = pbl[p] + roff;   // >= 0 exactly for an existing entry
                 const bool ok = off >= 0;
                 const float v =
                     __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsU, ok ? off * 4 : kOOB, 0, 0));
-                st.m[side] = __builtin_amdgcn_raw_buffer_load_b8(rsM, ok ? off : kOOB, 0, 0);
-                st.u[side] = ok ? v : -1.f;
+                st.m[p] = __builtin_amdgcn_raw_buffer_load_b8(rsM, ok ? off : kOOB, 0, 0);
+                st.u[p] = ok ? v : -1.f;
             }
         };
         auto scatter = [&](int rp, const UBuf& st) {
 #pragma unroll
-            for (int side = 0; side < 4; ++side) {
-                const int sx = (side & 2) ? 1 : -1, sy = (side & 1) ? 1 : -1;
-                const int ry = 2 * rp + code_my(st.m[side]) - 1 + sy, rxx = 2 * ux + code_mx(st.m[side]) - 1 + sx;
+            for (int p = 0; p < NP; ++p) {
+                const int sx = TILE == 60 ? (p ? 1 : -1) : ((p & 2) ? 1 : -1);   // side 2p + h, or p
+                const int sy = TILE == 60 ? sy_l : ((p & 1) ? 1 : -1);
+                const int ry = 2 * rp + code_my(st.m[p]) - 1 + sy, rxx = 2 * ux + code_mx(st.m[p]) - 1 + sx;
                 // an entry (U = -inf: unreached; -1: no parent or column) whose target is in the tile
-                const bool act = st.u[side] >= 0.f && (unsigned)(ry - R0) < (unsigned)(R1 - R0) &&
+                const bool act = st.u[p] >= 0.f && (unsigned)(ry - R0) < (unsigned)(R1 - R0) &&
                                  (unsigned)(rxx - C0) < (unsigned)(Cend - C0);
-                if (act) atomicMax(&ring[ry & (kBtRing - 1)][rxx - C0], enc(st.u[side]));
+                if (act) atomicMax(&ring[ry & (kBtRing - 1)][rxx - C0], enc(st.u[p]));
             }
         };
         auto collect = [&](int rp, OBuf& o) {
@@ -599,7 +623,7 @@ __global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __rest
     bt_body<RECT>(a, cp_prev, code_prev, u_cur, code_cur, top, vt, g, u_prev, best, cell, bid);
 }
 
-template <bool RECT>
+template <bool RECT, int TILE>
 __global__ __launch_bounds__(64 * kBtWaves) void k_backtrack_stream(
     BtStreamArgs a, const float* __restrict__ cp_prev, const uint8_t* __restrict__ code_prev,
     const float* __restrict__ u_cur, const uint8_t* __restrict__ code_cur, const uint8_t* __restrict__ vt, Geom g,
@@ -607,7 +631,7 @@ __global__ __launch_bounds__(64 * kBtWaves) void k_backtrack_stream(
     int nblocks) {
     const int bid = xcd_block(nblocks);
     if (bid >= nblocks) return;
-    bt_stream_body<RECT>(a, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, best, cell, bid);
+    bt_stream_body<RECT, TILE>(a, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, best, cell, bid);
 }
 
 template <bool RECT>
@@ -643,6 +667,7 @@ struct BtJob {
     }
 };
 
+template <int TILE>
 struct BtStreamJob {
     BtStreamArgs a;
     const float* cp_prev;
@@ -654,8 +679,8 @@ struct BtStreamJob {
     float* u_prev;
     unsigned long long *best, *cell;
     static __device__ void run(const BtStreamJob& j, int v) {
-        bt_stream_body<false>(j.a, j.cp_prev, j.code_prev, j.u_cur, j.code_cur, j.vt, j.g, j.u_prev, j.best, j.cell,
-                              v);
+        bt_stream_body<false, TILE>(j.a, j.cp_prev, j.code_prev, j.u_cur, j.code_cur, j.vt, j.g, j.u_prev, j.best,
+                                    j.cell, v);
     }
 };
 
@@ -735,6 +760,15 @@ bool use_bt_stream(int l, const Geom& g) {
     return (double)g.gx[l] * g.gy[l] * g.h[l + 1] * g.w[l + 1] * 4 < 2.0e9;
 }
 
+// Output columns per wave for child maps w wide: the form with the shorter
+// time per row of the map (a 60-column wave takes about 0.76 of a 64-column
+// wave's time, measured at 512x256, but more waves are needed when
+// ceil(w / 60) > ceil(w / 64)).
+int bt_tile(int w) {
+    const int n60 = (w + 59) / 60, n64 = (w + 63) / 64;
+    return n60 * 76 <= n64 * 100 ? 60 : 64;
+}
+
 // Streaming form with bands of tr rows (even, at most kBtMaxTR).
 BtStreamArgs make_bt_stream_args(int l, const Geom& g, int tr, int& nblocks) {
     BtStreamArgs b;
@@ -751,7 +785,8 @@ BtStreamArgs make_bt_stream_args(int l, const Geom& g, int tr, int& nblocks) {
     tr = tr < 2 ? 2 : (tr > kBtMaxTR ? kBtMaxTR : tr & ~1);
     b.TR = b.h < tr ? ((b.h + 1) & ~1) : tr;
     b.n_band = (b.h + b.TR - 1) / b.TR;
-    b.n_ct = (b.w + kBtCols - 1) / kBtCols;
+    b.tile = bt_tile(b.w);
+    b.n_ct = (b.w + b.tile - 1) / b.tile;
     b.n_cgrp = (b.gxc * b.gyc + kBtWaves - 1) / kBtWaves;
     b.W2 = g.W2;
     b.cw = (g.W2 + 3) / 4;
@@ -768,14 +803,21 @@ hipError_t launch_backtrack<float>(int l, const float* cp_prev, const uint8_t* c
     if (use_bt_stream(l, g)) {
         int nb;
         const BtStreamArgs b = make_bt_stream_args(l, g, kBtTR, nb);
-        if (g.rect.on)
-            hipLaunchKernelGGL(k_backtrack_stream<true>, dim3(((nb + 7) / 8) * 8), dim3(64 * kBtWaves), 0, s, b,
-                               cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, (unsigned long long*)best,
-                               (unsigned long long*)cell, nb);
+        auto* b64 = (unsigned long long*)best;
+        auto* c64 = (unsigned long long*)cell;
+        const dim3 grid(((nb + 7) / 8) * 8), block(64 * kBtWaves);
+        if (g.rect.on && b.tile == 60)
+            hipLaunchKernelGGL((k_backtrack_stream<true, 60>), grid, block, 0, s, b, cp_prev, code_prev, u_cur,
+                               code_cur, vt, g, u_prev, b64, c64, nb);
+        else if (g.rect.on)
+            hipLaunchKernelGGL((k_backtrack_stream<true, 64>), grid, block, 0, s, b, cp_prev, code_prev, u_cur,
+                               code_cur, vt, g, u_prev, b64, c64, nb);
+        else if (b.tile == 60)
+            hipLaunchKernelGGL((k_backtrack_stream<false, 60>), grid, block, 0, s, b, cp_prev, code_prev, u_cur,
+                               code_cur, vt, g, u_prev, b64, c64, nb);
         else
-            hipLaunchKernelGGL(k_backtrack_stream<false>, dim3(((nb + 7) / 8) * 8), dim3(64 * kBtWaves), 0, s, b,
-                               cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, (unsigned long long*)best,
-                               (unsigned long long*)cell, nb);
+            hipLaunchKernelGGL((k_backtrack_stream<false, 64>), grid, block, 0, s, b, cp_prev, code_prev, u_cur,
+                               code_cur, vt, g, u_prev, b64, c64, nb);
         return hipGetLastError();
     }
     int nblocks;
@@ -800,7 +842,11 @@ JobRec bt_job(int l, const float* cp_prev, const uint8_t* code_prev, const float
     if (use_bt_stream(l, g)) {
         int nb;
         const BtStreamArgs b = make_bt_stream_args(l, g, tr, nb);
-        r.set(JK_BT_STREAM, nb, 0, BtStreamJob{b, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, b64, c64});
+        if (b.tile == 60)
+            r.set(JK_BT_STREAM, nb, 0, BtStreamJob<60>{b, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, b64, c64});
+        else
+            r.set(JK_BT_STREAM64, nb, 0,
+                  BtStreamJob<64>{b, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, b64, c64});
         return r;
     }
     int nb;
@@ -839,7 +885,8 @@ JobRec valid_job(const Geom& g, uint8_t* vt) {
 hipError_t launch_group_bt(int kind, const GroupLaunch& gl, hipStream_t s) {
     switch (kind) {
         case JK_BT: return launch_grouped<BtJob, 256, 1>(gl, s);
-        case JK_BT_STREAM: return launch_grouped<BtStreamJob, 64 * kBtWaves, 1>(gl, s);
+        case JK_BT_STREAM: return launch_grouped<BtStreamJob<60>, 64 * kBtWaves, 1>(gl, s);
+        case JK_BT_STREAM64: return launch_grouped<BtStreamJob<64>, 64 * kBtWaves, 1>(gl, s);
         case JK_TOP_REDUCE: return launch_grouped<TopReduceJob, 256, 1>(gl, s);
         case JK_FINALIZE: return launch_grouped<FinalizeJob, 1024, 1>(gl, s);
         case JK_FILL: return launch_grouped<FillJob, 256, 1>(gl, s);
