@@ -411,7 +411,7 @@ BwStreamArgs make_bwd_stream_args(int l, const Geom& g, int& nblocks) {
     b.w = g.w[l];
     b.hu = g.h[l + 1];
     b.wu = g.w[l + 1];
-    b.TR = b.h < 32 ? ((b.h + 1) & ~1) : 32;
+    b.TR = b.h < 64 ? ((b.h + 1) & ~1) : 64;
     b.n_band = (b.h + b.TR - 1) / b.TR;
     b.n_ct = (b.w + kBwCols - 1) / kBwCols;
     b.n_cgrp = (b.gxc * b.gyc + kBwWaves - 1) / kBwWaves;
