@@ -37,6 +37,7 @@ hipError_t launch_group(int kind, const GroupLaunch& gl, hipStream_t s) {
             return launch_group_corr(kind, gl, s);
         case JK_LEVEL_STREAM_VEC:
         case JK_LEVEL_STREAM:
+        case JK_LEVEL_NARROW:
         case JK_LEVEL_POOL:
         case JK_LEVEL_TOP:
             return launch_group_level(kind, gl, s);
@@ -74,6 +75,7 @@ int default_res(int kind) {
             return 2;
         case JK_LEVEL_STREAM_VEC:
         case JK_LEVEL_STREAM:
+        case JK_LEVEL_NARROW:
         case JK_BT_STREAM:
         case JK_BT_STREAM64:
         case JK_BWD_LEVEL_STREAM:
@@ -373,7 +375,7 @@ dm_status autotune(Schedule& S, int n, const dm_pair* pairs, const dm_params* pr
     dm_status st = rebuild();
     if (st != DM_OK) return st;
     if ((st = run(S, ws, s, false)) != DM_OK) return st;   // every stage's inputs in place
-    const std::vector<int> lev = {JK_LEVEL_STREAM_VEC, JK_LEVEL_STREAM}, bt = {JK_BT_STREAM, JK_BT_STREAM64};
+    const std::vector<int> lev = {JK_LEVEL_STREAM_VEC, JK_LEVEL_STREAM, JK_LEVEL_NARROW}, bt = {JK_BT_STREAM, JK_BT_STREAM64};
     const int reps = 3;
     // band heights (job tables change)
     {

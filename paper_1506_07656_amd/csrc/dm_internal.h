@@ -159,6 +159,7 @@ enum JobKind : int {
     JK_DD1_REDUCE,
     JK_COL2IM,
     JK_BT_STREAM64,
+    JK_LEVEL_NARROW,
     JK_COUNT
 };
 

@@ -194,6 +194,7 @@ struct StreamArgs {
     int h, w, hp, wp;
     int TRo, n_band, n_ct, n_items;
     int vec;                         // w % 4 == 0: 16-byte child row segments
+    int narrow;                      // pooled maps <= 64 wide (and vec): two bands per wave
 };
 
 // Child values of one A row for a lane: v[k][j] for its 4 columns, hv[k] for
@@ -278,7 +279,116 @@ __device__ inline void pool_row(const StreamArgs& a, const RowBuf& b, float inv,
     }
 }
 
-template <bool VEC>
+// Narrow maps (at most 64 pooled columns, w % 4 == 0): the two half-waves
+// walk two bands of the same parent, lane tt = t % 32 owning the A columns
+// 4 tt - 1 .. 4 tt + 3.  Rows differ between the halves, so each child has a
+// descriptor over its whole map and a lane's offset is kOOB wherever its row
+// or columns fall outside (w % 4 == 0 keeps every 8- and 16-byte piece
+// wholly inside or outside a row).  Same sums, same comparisons: the values
+// equal those of the 64-lane form.
+__device__ inline void load_row_narrow(const StreamArgs& a, const __amdgpu_buffer_rsrc_t rs[4], const bool ex[4],
+                                       int y, int tt, RowBuf& b) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int yy = y + 2 * (k >> 1) - 1, dx = 2 * (k & 1) - 1;
+        const bool rok = ex[k] && yy >= 0 && yy < a.h;
+        const int rowb = yy * a.w;
+        const int s0 = 4 * tt - 1 + dx;   // -2 .. 125
+        if (k & 1) {   // s0 = 4 tt: 16 bytes inside or outside the row
+            const auto f = __builtin_amdgcn_raw_buffer_load_b128(rs[k], rok && s0 < a.w ? (rowb + s0) * 4 : kOOB, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b.v[k][j] = __uint_as_float(f[j]);
+        } else {       // s0 = 4 tt - 2: two 8-byte halves
+            const auto f0 = __builtin_amdgcn_raw_buffer_load_b64(
+                rs[k], rok && s0 >= 0 && s0 < a.w ? (rowb + s0) * 4 : kOOB, 0, 0);
+            const auto f1 =
+                __builtin_amdgcn_raw_buffer_load_b64(rs[k], rok && s0 + 2 < a.w ? (rowb + s0 + 2) * 4 : kOOB, 0, 0);
+            b.v[k][0] = __uint_as_float(f0[0]);
+            b.v[k][1] = __uint_as_float(f0[1]);
+            b.v[k][2] = __uint_as_float(f1[0]);
+            b.v[k][3] = __uint_as_float(f1[1]);
+        }
+        const int hx = 4 * 32 - 1 + dx;   // the halo column of the half-wave
+        b.hv[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs[k], rok && hx < a.w ? (rowb + hx) * 4 : kOOB,
+                                                                        0, 0));
+    }
+}
+
+__device__ inline void pool_row_narrow(const StreamArgs& a, const RowBuf& b, float inv, int y, int tt, float hv[2],
+                                       int hk[2]) {
+    const bool yin = y >= 0 && y < a.h;
+    float av[5];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float s = (((0.f + b.v[0][j]) + b.v[1][j]) + b.v[2][j]) + b.v[3][j];
+        const float m = s * inv;
+        const int x = 4 * tt - 1 + j;
+        av[j] = (yin && x >= 0 && x < a.w) ? fmaxf(m, 0.f) : -1.f;
+    }
+    {
+        const float s = (((0.f + b.hv[0]) + b.hv[1]) + b.hv[2]) + b.hv[3];
+        const float m = s * inv;
+        const float halo = (yin && 4 * 32 - 1 < a.w) ? fmaxf(m, 0.f) : -1.f;
+        const float nb = __shfl_down(av[0], 1);
+        av[4] = tt == 31 ? halo : nb;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const float v0 = av[2 * q], v1 = av[2 * q + 1], v2 = av[2 * q + 2];
+        float best = v0;
+        int k = 0;
+        if (v1 > best) { best = v1; k = 1; }
+        if (v2 > best) { best = v2; k = 2; }
+        hv[q] = best;
+        hk[q] = k;
+    }
+}
+
+__device__ inline void level_narrow_body(const StreamArgs& a, const float* __restrict__ prev, const float* const cmap[4],
+                                         float inv, int P, int band2, int t, float lam, float* __restrict__ cp,
+                                         uint8_t* __restrict__ code) {
+    const int tt = t & 31, hh = t >> 5;
+    const int R0 = (2 * band2 + hh) * a.TRo, R1 = min(R0 + a.TRo, a.hp);   // this half's band (may be empty)
+    __amdgpu_buffer_rsrc_t rs[4];
+    bool ex[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        ex[k] = cmap[k] != nullptr;
+        rs[k] = row_rsrc(ex[k] ? cmap[k] : prev, ex[k] ? a.h * a.w * 4 : 0);
+    }
+    RowBuf b0, b1;
+    float pv[2], hv[2];
+    int pk[2], hk[2];
+    load_row_narrow(a, rs, ex, 2 * R0 - 1, tt, b0);
+    load_row_narrow(a, rs, ex, 2 * R0, tt, b1);
+    pool_row_narrow(a, b0, inv, 2 * R0 - 1, tt, pv, pk);
+    for (int i = 0; i < a.TRo; ++i) {   // the same count in both halves
+        const int r = R0 + i;
+        load_row_narrow(a, rs, ex, 2 * r + 1, tt, b0);
+        float best[2];
+        int bk[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) { best[q] = pv[q]; bk[q] = pk[q]; }
+        pool_row_narrow(a, b1, inv, 2 * r, tt, hv, hk);
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (hv[q] > best[q]) { best[q] = hv[q]; bk[q] = 3 + hk[q]; }
+        load_row_narrow(a, rs, ex, 2 * r + 2, tt, b1);
+        pool_row_narrow(a, b0, inv, 2 * r + 1, tt, pv, pk);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (pv[q] > best[q]) { best[q] = pv[q]; bk[q] = 6 + pk[q]; }
+            const int u = 2 * tt + q;
+            if (r < R1 && u < a.wp) {
+                const size_t o = ((size_t)P * a.hp + r) * a.wp + u;
+                cp[o] = rect_pow(best[q], lam);
+                code[o] = (uint8_t)bk[q];
+            }
+        }
+    }
+}
+
+template <bool VEC, bool NARROW>
 __device__ inline void level_stream_body(const StreamArgs& a, const float* __restrict__ prev,
                                          const uint8_t* __restrict__ vt, const Geom& g, float lam,
                                          float* __restrict__ cp, uint8_t* __restrict__ code, int bid) {
@@ -311,6 +421,10 @@ __device__ inline void level_stream_body(const StreamArgs& a, const float* __res
             cmap[2 * ky + kx] =
                 (ey[ky] >= 0 && ex[kx] >= 0) ? prev + (size_t)child_slot(g, a.l, ey[ky] * a.gxc + ex[kx]) * hw : nullptr;
     const float inv = 1.f / float(nx * ny);
+    if constexpr (NARROW) {
+        level_narrow_body(a, prev, cmap, inv, P, band, t, lam, cp, code);
+        return;
+    }
     const int R0 = band * a.TRo, R1 = min(R0 + a.TRo, a.hp);
     const int C0 = ct * kStreamCols, ncol = min(kStreamCols, a.wp - C0);
     const int X0 = 2 * C0 - 1;
@@ -379,14 +493,14 @@ __global__ __launch_bounds__(256) void k_level_pool(LevelArgs a, const T* __rest
     level_pool_body<T>(a, prev, vt, g, lam, cp, code, bid);
 }
 
-template <bool VEC>
+template <bool VEC, bool NARROW>
 __global__ __launch_bounds__(64 * kStreamWaves) void k_level_stream(StreamArgs a, const float* __restrict__ prev,
                                                                      const uint8_t* __restrict__ vt, Geom g, float lam,
                                                                      float* __restrict__ cp,
                                                                      uint8_t* __restrict__ code, int nblocks) {
     const int bid = xcd_block(nblocks);
     if (bid >= nblocks) return;
-    level_stream_body<VEC>(a, prev, vt, g, lam, cp, code, bid);
+    level_stream_body<VEC, NARROW>(a, prev, vt, g, lam, cp, code, bid);
 }
 
 template <typename T>
@@ -423,7 +537,7 @@ struct LevelTopJob {
     }
 };
 
-template <bool VEC>
+template <bool VEC, bool NARROW>
 struct LevelStreamJob {
     StreamArgs a;
     const float* prev;
@@ -433,7 +547,7 @@ struct LevelStreamJob {
     float* cp;
     uint8_t* code;
     static __device__ void run(const LevelStreamJob& j, int v) {
-        level_stream_body<VEC>(j.a, j.prev, j.vt, j.g, j.lam, j.cp, j.code, v);
+        level_stream_body<VEC, NARROW>(j.a, j.prev, j.vt, j.g, j.lam, j.cp, j.code, v);
     }
 };
 
@@ -487,8 +601,15 @@ StreamArgs make_stream_args(int l, const Geom& g, int tro, int& nblocks) {
     b.TRo = b.hp < tro ? b.hp : tro;
     b.n_band = (b.hp + b.TRo - 1) / b.TRo;
     b.n_ct = (b.wp + kStreamCols - 1) / kStreamCols;
-    b.n_items = b.gx * b.gy * b.n_ct * b.n_band;
     b.vec = (b.w % 4) == 0;
+    // Narrow maps: one wave walks two bands (pairs of bands per item); each
+    // child's descriptor spans its whole map, whose byte size must fit an int.
+    b.narrow = b.vec && b.wp <= kStreamCols / 2 && (double)b.h * b.w * 4 < 2.0e9;
+    if (b.narrow) {   // pairs of bands of at most tro rows, the rows split evenly over the two halves
+        b.n_band = (b.hp + 2 * b.TRo - 1) / (2 * b.TRo);
+        b.TRo = (b.hp + 2 * b.n_band - 1) / (2 * b.n_band);
+    }
+    b.n_items = b.gx * b.gy * b.n_ct * b.n_band;
     nblocks = (b.n_items + kStreamWaves - 1) / kStreamWaves;
     return b;
 }
@@ -505,8 +626,9 @@ JobRec level_job(int l, const float* prev, const uint8_t* vt, const Geom& g, flo
     if (use_stream(l, g)) {
         int nb;
         const StreamArgs b = make_stream_args(l, g, tro, nb);
-        if (b.vec) r.set(JK_LEVEL_STREAM_VEC, nb, 0, LevelStreamJob<true>{b, prev, vt, g, lam, cp, code});
-        else r.set(JK_LEVEL_STREAM, nb, 0, LevelStreamJob<false>{b, prev, vt, g, lam, cp, code});
+        if (b.narrow) r.set(JK_LEVEL_NARROW, nb, 0, LevelStreamJob<true, true>{b, prev, vt, g, lam, cp, code});
+        else if (b.vec) r.set(JK_LEVEL_STREAM_VEC, nb, 0, LevelStreamJob<true, false>{b, prev, vt, g, lam, cp, code});
+        else r.set(JK_LEVEL_STREAM, nb, 0, LevelStreamJob<false, false>{b, prev, vt, g, lam, cp, code});
         return r;
     }
     int nb;
@@ -519,8 +641,9 @@ JobRec level_job(int l, const float* prev, const uint8_t* vt, const Geom& g, flo
 
 hipError_t launch_group_level(int kind, const GroupLaunch& gl, hipStream_t s) {
     switch (kind) {
-        case JK_LEVEL_STREAM_VEC: return launch_grouped<LevelStreamJob<true>, 64 * kStreamWaves, 1>(gl, s);
-        case JK_LEVEL_STREAM: return launch_grouped<LevelStreamJob<false>, 64 * kStreamWaves, 1>(gl, s);
+        case JK_LEVEL_STREAM_VEC: return launch_grouped<LevelStreamJob<true, false>, 64 * kStreamWaves, 1>(gl, s);
+        case JK_LEVEL_STREAM: return launch_grouped<LevelStreamJob<false, false>, 64 * kStreamWaves, 1>(gl, s);
+        case JK_LEVEL_NARROW: return launch_grouped<LevelStreamJob<true, true>, 64 * kStreamWaves, 1>(gl, s);
         case JK_LEVEL_POOL: return launch_grouped<LevelPoolJob, 256, 1>(gl, s);
         case JK_LEVEL_TOP: return launch_grouped<LevelTopJob, 256, 1>(gl, s);
         default: return hipErrorInvalidValue;
@@ -536,12 +659,15 @@ hipError_t launch_level(int l, const T* prev, const uint8_t* vt, const Geom& g, 
         const float* pf = reinterpret_cast<const float*>(prev);
         float* cf = reinterpret_cast<float*>(cp);
         const dim3 grid(((nb + 7) / 8) * 8);
-        if (b.vec)
-            hipLaunchKernelGGL(k_level_stream<true>, grid, dim3(64 * kStreamWaves), 0, s, b, pf, vt, g, (float)lam, cf,
-                               code, nb);
+        if (b.narrow)
+            hipLaunchKernelGGL((k_level_stream<true, true>), grid, dim3(64 * kStreamWaves), 0, s, b, pf, vt, g,
+                               (float)lam, cf, code, nb);
+        else if (b.vec)
+            hipLaunchKernelGGL((k_level_stream<true, false>), grid, dim3(64 * kStreamWaves), 0, s, b, pf, vt, g,
+                               (float)lam, cf, code, nb);
         else
-            hipLaunchKernelGGL(k_level_stream<false>, grid, dim3(64 * kStreamWaves), 0, s, b, pf, vt, g, (float)lam,
-                               cf, code, nb);
+            hipLaunchKernelGGL((k_level_stream<false, false>), grid, dim3(64 * kStreamWaves), 0, s, b, pf, vt, g,
+                               (float)lam, cf, code, nb);
         return hipGetLastError();
     }
     int nblocks;

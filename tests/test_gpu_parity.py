@@ -79,11 +79,28 @@ def odd_case():
     return o
 
 
+@functools.lru_cache(maxsize=None)
+def narrow_case():
+    """Crops I 168x120 and I' 200x148: level 1 maps are 100 wide (a multiple
+    of 4) and pool to 50 x 37, the narrow streaming form whose half-waves
+    walk bands of 10 rows, the last one ragged (7 rows)."""
+    p = synth.make_pair("c3")
+    i1 = np.ascontiguousarray(p["img1"][60:180, 100:268])
+    i2 = np.ascontiguousarray(p["img2"][50:198, 90:290])
+    o = oracle_from_desc(O.descriptors(i1), O.descriptors(i2))
+    o["img1"], o["img2"] = i1, i2
+    return o
+
+
 def case(name):
-    return (odd_case(), 0) if name == "odd" else (oracle_pair(name), synth.CONFIG_NMAX[name])
+    if name == "odd":
+        return odd_case(), 0
+    if name == "narrow":
+        return narrow_case(), 0
+    return oracle_pair(name), synth.CONFIG_NMAX[name]
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "odd"])
+@pytest.mark.parametrize("name", ["c1", "c2", "odd", "narrow"])
 def test_pyramid_levels_match_oracle(name):
     o, mp = case(name)
     pyr = o["pyr"]
@@ -117,7 +134,7 @@ def test_pyramid_levels_match_oracle(name):
     np.testing.assert_allclose(views["top"].cpu().numpy()[G], pyr.top[G], rtol=1e-5, atol=1e-7)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "odd"])
+@pytest.mark.parametrize("name", ["c1", "c2", "odd", "narrow"])
 def test_matches_fp32_match_oracle(name):
     o, mp = case(name)
     gpu, _, _ = run_desc(o["D1"], o["D2"], max_patch=mp)
