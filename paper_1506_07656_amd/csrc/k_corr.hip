@@ -199,8 +199,16 @@ struct EngineF32 {
     }
 };
 
+// The lane's run of target words at A-row ia starts at pixel 2n (even
+// column) and, one pixel (5 words) on, at pixel 2n + 1 (odd column).  The even
+// MFMAs take run words 0..19 as quads {0-3} ... {16-19} against patch words in
+// the same order (fa).  The odd run is words 5..24: three of its quads are the
+// even run's {8-11}, {12-15}, {16-19}, reused as they are, and two more are
+// loaded, {5, 6, 7, 20} and {21-24}; faO holds the patch words in that order
+// (run word w pairs with patch word w - 5).
 struct EngineBF16 {
     const bf8* fa;     // [MT][5]
+    const bf8* faO;    // [MT][5], K order of the odd run
     uint32_t* sD2;     // [D2R][D2C][5] bf16 pairs
     const uint32_t* d2;
     __device__ void load_tile(const PoolArgs& a, int R0, int C0) const {
@@ -211,18 +219,36 @@ struct EngineBF16 {
             sD2[e] = (y >= 0 && y < a.H2 && x >= 0 && x < a.W2) ? d2[((size_t)y * a.W2 + x) * 5 + pr] : 0u;
         }
     }
-    __device__ void mfma_row(int ia, int col, f4* acc) const {
-        const int grp = (threadIdx.x & 63) >> 4;
-        const uint32_t* bs = sD2 + ((ia + grp) * D2C + col) * 5;
-        bf8 fb[5];
+    // Even (accE) and odd (accO) columns of A-row ia for the lane's patches.
+    __device__ void mfma_row(int ia, f4* accE, f4* accO) const {
+        const int grp = (threadIdx.x & 63) >> 4, n = threadIdx.x & 15;
+        const uint32_t* bs = sD2 + ((ia + grp) * D2C + 2 * n) * 5;
+        bf8 fb[7];
 #pragma unroll
         for (int s = 0; s < 5; ++s) fb[s] = load_bf8(bs + 4 * s);
+        {
+            union {
+                uint32_t u[4];
+                bf8 v;
+            } x;
+            x.u[0] = bs[5];
+            x.u[1] = bs[6];
+            x.u[2] = bs[7];
+            x.u[3] = bs[20];
+            fb[5] = x.v;
+        }
+        fb[6] = load_bf8(bs + 21);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             f4 r = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < 5; ++s) r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[mt * 5 + s], fb[s], r, 0, 0, 0);
-            acc[mt] = r;
+            accE[mt] = r;
+            f4 q = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 5; ++s)
+                q = __builtin_amdgcn_mfma_f32_16x16x32_bf16(faO[mt * 5 + s], fb[s + 2], q, 0, 0, 0);
+            accO[mt] = q;
         }
     }
 };
@@ -254,33 +280,37 @@ __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t nbytes
 
 // Keys of A-row ia of the step for this lane's 4 * MT patches: the row
 // maximum over the window columns k = 0, 1, 2 (odd column left of the lane's
-// pooled column, even column, odd column), each carrying 15 - k.
-__device__ __forceinline__ void row_keys(const EngineBF16& eng, const EngineBF16& engO, const PoolArgs& a, int R0,
-                                         int ia, int n,
-                                         uint32_t me, uint32_t mo, const float* cr, float* cw,
+// pooled column, even column, odd column), each carrying bits - k, where
+// bits = 15 - 3 (my + 1) places the row in the window.  The carry (keys of
+// the odd column left of the step) moves through LDS 4 values at a time.
+__device__ __forceinline__ void row_keys(const EngineBF16& eng, const PoolArgs& a, int R0, int ia, int n,
+                                         uint32_t me, uint32_t mo, uint32_t bits, const float* cr, float* cw,
                                          uint32_t (&rk)[MT][4]) {
     const int y = 2 * R0 - 1 + ia;
     const bool y_ok = y >= 0 && y < a.H2;
     const uint32_t mE = y_ok ? me : 0u, mO = y_ok ? mo : 0u;
     const int lo = 0x00800000;   // bits of 2^-126; as signed integers, floats below it (negatives too) are smaller
     f4 accE[MT], accO[MT];
-    eng.mfma_row(ia, 2 * n, accE);
-    engO.mfma_row(ia, 2 * n, accO);   // column 2n + 1 of the tile
+    eng.mfma_row(ia, accE, accO);
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt) {
+        const f4 cin = *reinterpret_cast<const f4*>(__builtin_assume_aligned(cr + mt * 16, 16));   // O of column C0-1
+        f4 kout;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const uint32_t kE = ((uint32_t)max(__float_as_int(accE[mt][j]), lo) & mE) | 14u;   // k = 1
-            const uint32_t kO = ((uint32_t)max(__float_as_int(accO[mt][j]), lo) & mO) | 13u;   // k = 2
-            const uint32_t cin = __float_as_uint(cr[mt * 16 + j]);                           // O of column C0-1
+            const uint32_t kE = ((uint32_t)max(__float_as_int(accE[mt][j]), lo) & mE) | (bits - 1u);   // k = 1
+            const uint32_t kO = ((uint32_t)max(__float_as_int(accO[mt][j]), lo) & mO) | (bits - 2u);   // k = 2
             const uint32_t kL =
-                (uint32_t)__builtin_amdgcn_update_dpp((int)cin, (int)kO, 0x111, 0xF, 0xF, false) | 15u;   // k = 0
-            cw[mt * 16 + j] = __uint_as_float(kO);
+                ((uint32_t)__builtin_amdgcn_update_dpp((int)__float_as_uint(cin[j]), (int)kO, 0x111, 0xF, 0xF, false) &
+                 ~15u) | bits;                                                                          // k = 0
+            kout[j] = __uint_as_float(kO);
             rk[mt][j] = max(max(kL, kE), kO);
         }
+        *reinterpret_cast<f4*>(__builtin_assume_aligned(cw + mt * 16, 16)) = kout;
+    }
 }
 
-__device__ inline void sweep_band_bf16(const bf8* fa, uint32_t* sD2, uint32_t* sD2O, const uint32_t* __restrict__ d2,
+__device__ inline void sweep_band_bf16(const bf8* fa, const bf8* faO, uint32_t* sD2, const uint32_t* __restrict__ d2,
                                        const PoolArgs& a, int pt, int R0, int seg, float lam, float* __restrict__ cp,
                                        uint8_t* __restrict__ code, float (*carry)[16 * MT], float* dummy) {
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -308,12 +338,15 @@ __device__ inline void sweep_band_bf16(const bf8* fa, uint32_t* sD2, uint32_t* s
     // Carry (key of the odd column left of the step) starts as "outside".
 #pragma unroll
     for (int e = lane; e < ARS * 16 * MT; e += 64) (&carry[0][0])[e] = 0.f;
-    // Lanes other than n = 15 write their carry into a private dummy slot.
-    float* const cw0 = n == 15 ? &carry[0][4 * grp] : dummy + lane;
+    // Lanes other than n = 15 write their carry into a private dummy slot
+    // (16-byte aligned, 4 words per lane and M-tile).
+    float* const cw0 = n == 15 ? &carry[0][4 * grp] : dummy + 4 * lane;
     const int cstep = n == 15 ? 16 * MT : 0;
-    // Output offsets (pooled row 0, column 0) of this lane's 4 * MT patches,
-    // in bytes for the codes and for the values; patches past natom get
-    // offsets past the end of the buffers, so their stores are dropped.
+    // Output offsets (pooled row 0, column n) of this lane's 4 * MT patches,
+    // in bytes for the codes and for the values; the row and step part of an
+    // offset is uniform and goes into the instruction's scalar offset.
+    // Patches past natom get offsets past the end of the buffers, so their
+    // stores are dropped.
     uint32_t ob[MT][4], ob4[MT][4];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -321,8 +354,8 @@ __device__ inline void sweep_band_bf16(const bf8* fa, uint32_t* sD2, uint32_t* s
         for (int j = 0; j < 4; ++j) {
             const uint32_t lp = mt * 16 + 4 * grp + j;
             const bool ok = lp * mapsz < nmap;
-            ob[mt][j] = ok ? lp * mapsz : (uint32_t)kOOB;
-            ob4[mt][j] = ok ? lp * mapsz * 4 : (uint32_t)kOOB;
+            ob[mt][j] = ok ? lp * mapsz + n : (uint32_t)kOOB;
+            ob4[mt][j] = ok ? (lp * mapsz + n) * 4 : (uint32_t)kOOB;
         }
     const StepRange sr = step_range(a, seg);
     fetch(16 * sr.s_begin);
@@ -333,42 +366,38 @@ __device__ inline void sweep_band_bf16(const bf8* fa, uint32_t* sD2, uint32_t* s
         for (int it = 0; it < TILE_PER_T; ++it) {
             const int idx = tid + 256 * it;
             if (idx < TILE_N) sD2[idx] = tv[it];
-            if (idx >= 5 && idx < TILE_N) sD2O[idx - 5] = tv[it];   // the same tile one pixel to the left
         }
         __syncthreads();
         if (step + 1 < sr.s_end) fetch(C0 + 16);
-        // Even and odd columns read separate copies, so that both fragments
-        // load straight into aligned registers (a pixel is 5 words; reading
-        // the odd fragment from the even copy would need register moves).
-        const EngineBF16 eng{fa, sD2, d2}, engO{fa, sD2O, d2};
+        const EngineBF16 eng{fa, faO, sD2, d2};
         const int c = C0 + n;
         const uint32_t me = 2 * c < a.W2 ? ~15u : 0u, mo = 2 * c + 1 < a.W2 ? ~15u : 0u;
         uint32_t best[MT][4], rk[MT][4];
-        row_keys(eng, engO, a, R0, 0, n, me, mo, carry[0] + 4 * grp, cw0, rk);
+        row_keys(eng, a, R0, 0, n, me, mo, 15u, carry[0] + 4 * grp, cw0, rk);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int j = 0; j < 4; ++j) best[mt][j] = rk[mt][j];   // my = -1 of pooled row R0
         for (int pr = 0; pr < TR; ++pr) {
             const int r = R0 + pr;
-            row_keys(eng, engO, a, R0, 2 * pr + 1, n, me, mo, carry[2 * pr + 1] + 4 * grp, cw0 + (2 * pr + 1) * cstep,
+            row_keys(eng, a, R0, 2 * pr + 1, n, me, mo, 12u, carry[2 * pr + 1] + 4 * grp, cw0 + (2 * pr + 1) * cstep,
                      rk);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) best[mt][j] = max(best[mt][j], rk[mt][j] - 3u);   // my = 0
-            row_keys(eng, engO, a, R0, 2 * pr + 2, n, me, mo, carry[2 * pr + 2] + 4 * grp, cw0 + (2 * pr + 2) * cstep,
+                for (int j = 0; j < 4; ++j) best[mt][j] = max(best[mt][j], rk[mt][j]);   // my = 0
+            row_keys(eng, a, R0, 2 * pr + 2, n, me, mo, 9u, carry[2 * pr + 2] + 4 * grp, cw0 + (2 * pr + 2) * cstep,
                      rk);
             uint32_t fin[MT][4];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    fin[mt][j] = max(best[mt][j], rk[mt][j] - 6u);   // my = +1 finishes pooled row r
-                    best[mt][j] = rk[mt][j];                         // my = -1 of pooled row r + 1
+                    fin[mt][j] = max(best[mt][j], rk[mt][j]);   // my = +1 finishes pooled row r
+                    best[mt][j] = rk[mt][j] + 6u;               // the same keys as my = -1 of pooled row r + 1
                 }
             if (step >= sr.s_out && r < a.h1 && c < a.w1) {
-                const uint32_t rc = (uint32_t)(r * a.w1 + c);
+                const int rc = __builtin_amdgcn_readfirstlane(r * a.w1 + C0);   // uniform part of the offsets
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -377,9 +406,9 @@ __device__ inline void sweep_band_bf16(const bf8* fa, uint32_t* sD2, uint32_t* s
                             // the kept value is >= 2^-126 > 0: the power needs no test for 0
                             __float_as_uint(__builtin_amdgcn_exp2f(lam * __builtin_amdgcn_logf(
                                 __uint_as_float(fin[mt][j] & ~15u)))), rsC,
-                            (int)(ob4[mt][j] + 4 * rc), 0, 0);
+                            (int)ob4[mt][j], 4 * rc, 0);
                         __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(15u - (fin[mt][j] & 15u)), rsK,
-                                                             (int)(ob[mt][j] + rc), 0, 0);
+                                                             (int)ob[mt][j], rc, 0);
                     }
             }
         }
@@ -421,14 +450,13 @@ __device__ inline void corr_bf16_body(const uint16_t* __restrict__ d1, const uin
                                       const PoolArgs& a, float lam, float* __restrict__ cp,
                                       uint8_t* __restrict__ code, int bid) {
     __shared__ __align__(16) uint32_t sD2[D2R * D2C * 5];
-    __shared__ __align__(16) uint32_t sD2O[D2R * D2C * 5];
-    __shared__ float sCarry[WAVES][ARS][16 * MT];
-    __shared__ float sDummy[WAVES][64 + 16 * MT];   // carry writes of lanes other than the row's last
+    __shared__ __align__(16) float sCarry[WAVES][ARS][16 * MT];
+    __shared__ __align__(16) float sDummy[WAVES][4 * 64 + 16 * MT];   // carry writes of lanes other than the row's last
     const int pt = bid % a.n_ptiles, rest = bid / a.n_ptiles;
     const int seg = rest % a.n_seg, R0 = (rest / a.n_seg) * TR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n = lane & 15, grp = lane >> 4;
-    bf8 fa[MT * 5];
+    bf8 fa[MT * 5], faO[MT * 5];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int j = pt * PT + wave * 16 * MT + mt * 16 + n;
@@ -446,8 +474,17 @@ __device__ inline void corr_bf16_body(const uint16_t* __restrict__ d1, const uin
         for (int t = 0; t < 20; ++t) tmp[t] = bf16x2_scale16(tmp[t]);   // the 1/16 of Eq. (3)
 #pragma unroll
         for (int s = 0; s < 5; ++s) fa[mt * 5 + s] = load_bf8(tmp + 4 * s);
+        // The odd run's K order: patch words {3-6}, {7-10}, {11-14}, {0, 1, 2, 15}, {16-19}.
+        faO[mt * 5 + 0] = load_bf8(tmp + 3);
+        faO[mt * 5 + 1] = load_bf8(tmp + 7);
+        faO[mt * 5 + 2] = load_bf8(tmp + 11);
+        {
+            const uint32_t q[4] = {tmp[0], tmp[1], tmp[2], tmp[15]};
+            faO[mt * 5 + 3] = load_bf8(q);
+        }
+        faO[mt * 5 + 4] = load_bf8(tmp + 16);
     }
-    sweep_band_bf16(fa, sD2, sD2O, (const uint32_t*)d2, a, pt, R0, seg, lam, cp, code, sCarry[wave], sDummy[wave]);
+    sweep_band_bf16(fa, faO, sD2, (const uint32_t*)d2, a, pt, R0, seg, lam, cp, code, sCarry[wave], sDummy[wave]);
 }
 
 __global__ __launch_bounds__(256, 2) void k_corr_pool_f32(const float* __restrict__ d1,

@@ -203,6 +203,53 @@ def test_bf16_agreement(name):
     assert frac >= 0.99
 
 
+def bf16_round(a):
+    """Round to the nearest bfloat16 (ties to even), kept as float64: the
+    values a BF16 operand holds exactly."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@functools.lru_cache(maxsize=None)
+def bf16_operand_case(name):
+    o = oracle_pair(name)
+    return oracle_from_desc(bf16_round(o["D1"]), bf16_round(o["D2"]), synth.CONFIG_NMAX[name])
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_bf16_pyramid_equals_oracle_on_bf16_operands(name):
+    """The BF16 path on descriptors that BF16 holds exactly against the FP64
+    oracle on the same values, element by element.  Products of BF16 values
+    are exact in FP32 and the descriptors are non-negative, so the level-0
+    correlation differs from the oracle's only by FP32 accumulation over
+    K = 160 (about 1e-5 relative at worst) and the 4 mantissa bits the
+    pooling keys drop (2^-19), raised to lambda; the upper levels add FP32
+    rounding.  Codes are compared where the oracle's margin exceeds that."""
+    o = bf16_operand_case(name)
+    pyr = o["pyr"]
+    gpu, views, pl = run_desc(o["D1"], o["D2"], max_patch=synth.CONFIG_NMAX[name], precision="bf16")
+    assert pl.lmax == pyr.lmax
+    tie = 5e-5
+    for lv in range(pyr.lmax):
+        G = pyr.G[lv]
+        cp = views["levels"][lv]["cp"].cpu().numpy()[G]
+        code = views["levels"][lv]["code"].cpu().numpy()[G]
+        ref = pyr.Cp[lv][G]
+        print(f"{name} bf16 level {lv}: max rel err {np.max(np.abs(cp - ref) / np.maximum(ref, 1e-30)):.3e}",
+              flush=True)
+        np.testing.assert_allclose(cp, ref, rtol=3e-5, atol=1e-7, err_msg=f"level {lv}")
+        clear = pyr.gap[lv][G] > tie * (1 + ref)
+        mism = (code != pyr.code[lv][G]) & clear
+        assert mism.sum() == 0, f"level {lv}: {mism.sum()} codes differ away from near-ties"
+    G = pyr.G[pyr.lmax]
+    np.testing.assert_allclose(views["top"].cpu().numpy()[G], pyr.top[G], rtol=3e-5, atol=1e-7)
+    r = compare_matches(gpu, o["out"], o["margin"], tie=tie, score_rtol=3e-5)
+    report(f"{name} bf16 operands", r)
+    assert not r["missing"] and not r["moved"] and not r["bad_score"]
+    assert len(r["extra"]) <= r["near_ties"]
+
+
 def load_golden(name):
     import os
     from tests.golden.make_golden import image_hash, path_of
