@@ -46,6 +46,8 @@ hipError_t launch_group(int kind, const GroupLaunch& gl, hipStream_t s) {
         case JK_BT:
         case JK_BT_STREAM:
         case JK_BT_STREAM64:
+        case JK_BT_STREAM_BOT:
+        case JK_BT_STREAM64_BOT:
         case JK_TOP_REDUCE:
         case JK_FINALIZE:
             return launch_group_bt(kind, gl, s);
@@ -78,6 +80,8 @@ int default_res(int kind) {
         case JK_LEVEL_NARROW:
         case JK_BT_STREAM:
         case JK_BT_STREAM64:
+        case JK_BT_STREAM_BOT:
+        case JK_BT_STREAM64_BOT:
         case JK_BWD_LEVEL_STREAM:
             return 6;
         case JK_VALID:
@@ -375,7 +379,8 @@ dm_status autotune(Schedule& S, int n, const dm_pair* pairs, const dm_params* pr
     dm_status st = rebuild();
     if (st != DM_OK) return st;
     if ((st = run(S, ws, s, false)) != DM_OK) return st;   // every stage's inputs in place
-    const std::vector<int> lev = {JK_LEVEL_STREAM_VEC, JK_LEVEL_STREAM, JK_LEVEL_NARROW}, bt = {JK_BT_STREAM, JK_BT_STREAM64};
+    const std::vector<int> lev = {JK_LEVEL_STREAM_VEC, JK_LEVEL_STREAM, JK_LEVEL_NARROW},
+                           bt = {JK_BT_STREAM, JK_BT_STREAM64, JK_BT_STREAM_BOT, JK_BT_STREAM64_BOT};
     const int reps = 3;
     // band heights (job tables change)
     {

@@ -160,6 +160,8 @@ enum JobKind : int {
     JK_COL2IM,
     JK_BT_STREAM64,
     JK_LEVEL_NARROW,
+    JK_BT_STREAM_BOT,     // the streaming backtracking's bottom level (the key tables), per tile width
+    JK_BT_STREAM64_BOT,
     JK_COUNT
 };
 

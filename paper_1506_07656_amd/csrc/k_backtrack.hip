@@ -288,7 +288,7 @@ __device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, int nbytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, nbytes, 0x00020000);
 }
 
-template <bool RECT, int TILE>
+template <bool RECT, int TILE, bool BOTTOM>
 __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __restrict__ cp_prev,
                                       const uint8_t* __restrict__ code_prev, const float* __restrict__ u_cur,
                                       const uint8_t* __restrict__ code_cur, const uint8_t* __restrict__ vt,
@@ -309,7 +309,7 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
     {
         uint32_t* flat = &sR[0][0][0];
         for (int e = tid; e < kBtWaves * kBtRing * kBtCols; e += 64 * kBtWaves) flat[e] = 0u;
-        if (a.is_bottom)
+        if constexpr (BOTTOM)
             for (int e = tid; e < ncy * NCX; e += 64 * kBtWaves) sCell[e] = 0ull;
     }
     __syncthreads();
@@ -342,7 +342,7 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
         const __amdgpu_buffer_rsrc_t rsU = rsrc(u_cur, nparent * usz * 4), rsM = rsrc(code_cur, nparent * usz);
         const size_t cmap = (size_t)child_slot(g, a.l, c) * csz;
         const __amdgpu_buffer_rsrc_t rsC = rsrc(cp_prev + cmap, csz * 4);
-        const __amdgpu_buffer_rsrc_t rsK = rsrc(code_prev + cmap, a.is_bottom ? csz : 0);
+        const __amdgpu_buffer_rsrc_t rsK = rsrc(code_prev + cmap, BOTTOM ? csz : 0);
         // Element offset of each parent's map, or a large negative value for a
         // missing parent: with a lane's row offset added (also large negative
         // when the lane or row has no U_l entry), an entry exists exactly when
@@ -425,7 +425,7 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
                 const int ry = 2 * rp - 2 + dy;
                 if (ry < R0 || ry >= R1 || !lane_o) continue;
                 const uint32_t vb = o.vb[dy];
-                if (!a.is_bottom) {
+                if constexpr (!BOTTOM) {
                     u_prev[((size_t)c * a.h + ry) * a.w + rx] = vb ? o.cv[dy] + dec(vb) : -INFINITY;
                 } else if (vb) {
                     const float uu = o.cv[dy] + dec(vb);
@@ -486,7 +486,7 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
             ++rp;
         }
     }
-    if (!a.is_bottom) return;
+    if constexpr (!BOTTOM) return;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         const uint32_t lo = __shfl_xor((uint32_t)mybest, d), hi = __shfl_xor((uint32_t)(mybest >> 32), d);
@@ -623,7 +623,7 @@ __global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __rest
     bt_body<RECT>(a, cp_prev, code_prev, u_cur, code_cur, top, vt, g, u_prev, best, cell, bid);
 }
 
-template <bool RECT, int TILE>
+template <bool RECT, int TILE, bool BOTTOM>
 __global__ __launch_bounds__(64 * kBtWaves) void k_backtrack_stream(
     BtStreamArgs a, const float* __restrict__ cp_prev, const uint8_t* __restrict__ code_prev,
     const float* __restrict__ u_cur, const uint8_t* __restrict__ code_cur, const uint8_t* __restrict__ vt, Geom g,
@@ -631,7 +631,7 @@ __global__ __launch_bounds__(64 * kBtWaves) void k_backtrack_stream(
     int nblocks) {
     const int bid = xcd_block(nblocks);
     if (bid >= nblocks) return;
-    bt_stream_body<RECT, TILE>(a, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, best, cell, bid);
+    bt_stream_body<RECT, TILE, BOTTOM>(a, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, best, cell, bid);
 }
 
 template <bool RECT>
@@ -667,7 +667,7 @@ struct BtJob {
     }
 };
 
-template <int TILE>
+template <int TILE, bool BOTTOM>
 struct BtStreamJob {
     BtStreamArgs a;
     const float* cp_prev;
@@ -679,8 +679,8 @@ struct BtStreamJob {
     float* u_prev;
     unsigned long long *best, *cell;
     static __device__ void run(const BtStreamJob& j, int v) {
-        bt_stream_body<false, TILE>(j.a, j.cp_prev, j.code_prev, j.u_cur, j.code_cur, j.vt, j.g, j.u_prev, j.best,
-                                    j.cell, v);
+        bt_stream_body<false, TILE, BOTTOM>(j.a, j.cp_prev, j.code_prev, j.u_cur, j.code_cur, j.vt, j.g, j.u_prev,
+                                            j.best, j.cell, v);
     }
 };
 
@@ -806,18 +806,20 @@ hipError_t launch_backtrack<float>(int l, const float* cp_prev, const uint8_t* c
         auto* b64 = (unsigned long long*)best;
         auto* c64 = (unsigned long long*)cell;
         const dim3 grid(((nb + 7) / 8) * 8), block(64 * kBtWaves);
-        if (g.rect.on && b.tile == 60)
-            hipLaunchKernelGGL((k_backtrack_stream<true, 60>), grid, block, 0, s, b, cp_prev, code_prev, u_cur,
-                               code_cur, vt, g, u_prev, b64, c64, nb);
-        else if (g.rect.on)
-            hipLaunchKernelGGL((k_backtrack_stream<true, 64>), grid, block, 0, s, b, cp_prev, code_prev, u_cur,
-                               code_cur, vt, g, u_prev, b64, c64, nb);
-        else if (b.tile == 60)
-            hipLaunchKernelGGL((k_backtrack_stream<false, 60>), grid, block, 0, s, b, cp_prev, code_prev, u_cur,
-                               code_cur, vt, g, u_prev, b64, c64, nb);
-        else
-            hipLaunchKernelGGL((k_backtrack_stream<false, 64>), grid, block, 0, s, b, cp_prev, code_prev, u_cur,
-                               code_cur, vt, g, u_prev, b64, c64, nb);
+#define DM_BT_STREAM(R, T, B)                                                                                   \
+    hipLaunchKernelGGL((k_backtrack_stream<R, T, B>), grid, block, 0, s, b, cp_prev, code_prev, u_cur, code_cur, \
+                       vt, g, u_prev, b64, c64, nb)
+        // The rectified (invariant) form differs from the plain one at the bottom level only.
+        if (b.is_bottom) {
+            if (g.rect.on && b.tile == 60) DM_BT_STREAM(true, 60, true);
+            else if (g.rect.on) DM_BT_STREAM(true, 64, true);
+            else if (b.tile == 60) DM_BT_STREAM(false, 60, true);
+            else DM_BT_STREAM(false, 64, true);
+        } else {
+            if (b.tile == 60) DM_BT_STREAM(false, 60, false);
+            else DM_BT_STREAM(false, 64, false);
+        }
+#undef DM_BT_STREAM
         return hipGetLastError();
     }
     int nblocks;
@@ -842,11 +844,18 @@ JobRec bt_job(int l, const float* cp_prev, const uint8_t* code_prev, const float
     if (use_bt_stream(l, g)) {
         int nb;
         const BtStreamArgs b = make_bt_stream_args(l, g, tr, nb);
-        if (b.tile == 60)
-            r.set(JK_BT_STREAM, nb, 0, BtStreamJob<60>{b, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, b64, c64});
+        if (b.tile == 60 && b.is_bottom)
+            r.set(JK_BT_STREAM_BOT, nb, 0,
+                  BtStreamJob<60, true>{b, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, b64, c64});
+        else if (b.tile == 60)
+            r.set(JK_BT_STREAM, nb, 0,
+                  BtStreamJob<60, false>{b, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, b64, c64});
+        else if (b.is_bottom)
+            r.set(JK_BT_STREAM64_BOT, nb, 0,
+                  BtStreamJob<64, true>{b, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, b64, c64});
         else
             r.set(JK_BT_STREAM64, nb, 0,
-                  BtStreamJob<64>{b, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, b64, c64});
+                  BtStreamJob<64, false>{b, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, b64, c64});
         return r;
     }
     int nb;
@@ -885,8 +894,10 @@ JobRec valid_job(const Geom& g, uint8_t* vt) {
 hipError_t launch_group_bt(int kind, const GroupLaunch& gl, hipStream_t s) {
     switch (kind) {
         case JK_BT: return launch_grouped<BtJob, 256, 1>(gl, s);
-        case JK_BT_STREAM: return launch_grouped<BtStreamJob<60>, 64 * kBtWaves, 1>(gl, s);
-        case JK_BT_STREAM64: return launch_grouped<BtStreamJob<64>, 64 * kBtWaves, 1>(gl, s);
+        case JK_BT_STREAM: return launch_grouped<BtStreamJob<60, false>, 64 * kBtWaves, 1>(gl, s);
+        case JK_BT_STREAM64: return launch_grouped<BtStreamJob<64, false>, 64 * kBtWaves, 1>(gl, s);
+        case JK_BT_STREAM_BOT: return launch_grouped<BtStreamJob<60, true>, 64 * kBtWaves, 1>(gl, s);
+        case JK_BT_STREAM64_BOT: return launch_grouped<BtStreamJob<64, true>, 64 * kBtWaves, 1>(gl, s);
         case JK_TOP_REDUCE: return launch_grouped<TopReduceJob, 256, 1>(gl, s);
         case JK_FINALIZE: return launch_grouped<FinalizeJob, 1024, 1>(gl, s);
         case JK_FILL: return launch_grouped<FillJob, 256, 1>(gl, s);
