@@ -213,11 +213,11 @@ def bf16_round(a):
 
 @functools.lru_cache(maxsize=None)
 def bf16_operand_case(name):
-    o = oracle_pair(name)
-    return oracle_from_desc(bf16_round(o["D1"]), bf16_round(o["D2"]), synth.CONFIG_NMAX[name])
+    o, mp = case(name)
+    return oracle_from_desc(bf16_round(o["D1"]), bf16_round(o["D2"]), mp), mp
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
+@pytest.mark.parametrize("name", ["c1", "c2", "odd", "narrow"])
 def test_bf16_pyramid_equals_oracle_on_bf16_operands(name):
     """The BF16 path on descriptors that BF16 holds exactly against the FP64
     oracle on the same values, element by element.  Products of BF16 values
@@ -225,10 +225,12 @@ def test_bf16_pyramid_equals_oracle_on_bf16_operands(name):
     correlation differs from the oracle's only by FP32 accumulation over
     K = 160 (about 1e-5 relative at worst) and the 4 mantissa bits the
     pooling keys drop (2^-19), raised to lambda; the upper levels add FP32
-    rounding.  Codes are compared where the oracle's margin exceeds that."""
-    o = bf16_operand_case(name)
+    rounding.  Codes are compared where the oracle's margin exceeds that.
+    The odd and narrow crops pool to 150 x 78 and 100 x 74 entries, so the
+    bottom kernel's last 16-column step and last 8-row band are partial."""
+    o, mp = bf16_operand_case(name)
     pyr = o["pyr"]
-    gpu, views, pl = run_desc(o["D1"], o["D2"], max_patch=synth.CONFIG_NMAX[name], precision="bf16")
+    gpu, views, pl = run_desc(o["D1"], o["D2"], max_patch=mp, precision="bf16")
     assert pl.lmax == pyr.lmax
     tie = 5e-5
     for lv in range(pyr.lmax):
