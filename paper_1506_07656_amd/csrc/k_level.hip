@@ -194,7 +194,8 @@ struct StreamArgs {
     int h, w, hp, wp;
     int TRo, n_band, n_ct, n_items;
     int vec;                         // w % 4 == 0: 16-byte child row segments
-    int narrow;                      // pooled maps <= 64 wide (and vec): two bands per wave
+    int narrow;                      // pooled maps <= 64 wide (and vec): several bands per wave
+    int lgl;                         // narrow: log2 of the lanes per band (the wave walks 64 >> lgl bands)
 };
 
 // Child values of one A row for a lane: v[k][j] for its 4 columns, hv[k] for
@@ -279,15 +280,16 @@ __device__ inline void pool_row(const StreamArgs& a, const RowBuf& b, float inv,
     }
 }
 
-// Narrow maps (at most 64 pooled columns, w % 4 == 0): the two half-waves
-// walk two bands of the same parent, lane tt = t % 32 owning the A columns
-// 4 tt - 1 .. 4 tt + 3.  Rows differ between the halves, so each child has a
+// Narrow maps (at most 64 pooled columns, w % 4 == 0): the wave splits into
+// groups of L = 2^lgl lanes (L >= half the pooled width), each walking its
+// own band of the same parent, lane tt = t % L owning the A columns
+// 4 tt - 1 .. 4 tt + 3.  Rows differ between the groups, so each child has a
 // descriptor over its whole map and a lane's offset is kOOB wherever its row
 // or columns fall outside (w % 4 == 0 keeps every 8- and 16-byte piece
 // wholly inside or outside a row).  Same sums, same comparisons: the values
 // equal those of the 64-lane form.
 __device__ inline void load_row_narrow(const StreamArgs& a, const __amdgpu_buffer_rsrc_t rs[4], const bool ex[4],
-                                       int y, int tt, RowBuf& b) {
+                                       int y, int tt, int L, RowBuf& b) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int yy = y + 2 * (k >> 1) - 1, dx = 2 * (k & 1) - 1;
@@ -308,14 +310,14 @@ __device__ inline void load_row_narrow(const StreamArgs& a, const __amdgpu_buffe
             b.v[k][2] = __uint_as_float(f1[0]);
             b.v[k][3] = __uint_as_float(f1[1]);
         }
-        const int hx = 4 * 32 - 1 + dx;   // the halo column of the half-wave
+        const int hx = 4 * L - 1 + dx;   // the halo column of the group
         b.hv[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs[k], rok && hx < a.w ? (rowb + hx) * 4 : kOOB,
                                                                         0, 0));
     }
 }
 
-__device__ inline void pool_row_narrow(const StreamArgs& a, const RowBuf& b, float inv, int y, int tt, float hv[2],
-                                       int hk[2]) {
+__device__ inline void pool_row_narrow(const StreamArgs& a, const RowBuf& b, float inv, int y, int tt, int L,
+                                       float hv[2], int hk[2]) {
     const bool yin = y >= 0 && y < a.h;
     float av[5];
 #pragma unroll
@@ -328,9 +330,9 @@ __device__ inline void pool_row_narrow(const StreamArgs& a, const RowBuf& b, flo
     {
         const float s = (((0.f + b.hv[0]) + b.hv[1]) + b.hv[2]) + b.hv[3];
         const float m = s * inv;
-        const float halo = (yin && 4 * 32 - 1 < a.w) ? fmaxf(m, 0.f) : -1.f;
+        const float halo = (yin && 4 * L - 1 < a.w) ? fmaxf(m, 0.f) : -1.f;
         const float nb = __shfl_down(av[0], 1);
-        av[4] = tt == 31 ? halo : nb;
+        av[4] = tt == L - 1 ? halo : nb;
     }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -347,8 +349,8 @@ __device__ inline void pool_row_narrow(const StreamArgs& a, const RowBuf& b, flo
 __device__ inline void level_narrow_body(const StreamArgs& a, const float* __restrict__ prev, const float* const cmap[4],
                                          float inv, int P, int band2, int t, float lam, float* __restrict__ cp,
                                          uint8_t* __restrict__ code) {
-    const int tt = t & 31, hh = t >> 5;
-    const int R0 = (2 * band2 + hh) * a.TRo, R1 = min(R0 + a.TRo, a.hp);   // this half's band (may be empty)
+    const int L = 1 << a.lgl, tt = t & (L - 1), hh = t >> a.lgl;
+    const int R0 = ((64 >> a.lgl) * band2 + hh) * a.TRo, R1 = min(R0 + a.TRo, a.hp);   // this group's band (may be empty)
     __amdgpu_buffer_rsrc_t rs[4];
     bool ex[4];
 #pragma unroll
@@ -359,22 +361,22 @@ __device__ inline void level_narrow_body(const StreamArgs& a, const float* __res
     RowBuf b0, b1;
     float pv[2], hv[2];
     int pk[2], hk[2];
-    load_row_narrow(a, rs, ex, 2 * R0 - 1, tt, b0);
-    load_row_narrow(a, rs, ex, 2 * R0, tt, b1);
-    pool_row_narrow(a, b0, inv, 2 * R0 - 1, tt, pv, pk);
-    for (int i = 0; i < a.TRo; ++i) {   // the same count in both halves
+    load_row_narrow(a, rs, ex, 2 * R0 - 1, tt, L, b0);
+    load_row_narrow(a, rs, ex, 2 * R0, tt, L, b1);
+    pool_row_narrow(a, b0, inv, 2 * R0 - 1, tt, L, pv, pk);
+    for (int i = 0; i < a.TRo; ++i) {   // the same count in every group
         const int r = R0 + i;
-        load_row_narrow(a, rs, ex, 2 * r + 1, tt, b0);
+        load_row_narrow(a, rs, ex, 2 * r + 1, tt, L, b0);
         float best[2];
         int bk[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) { best[q] = pv[q]; bk[q] = pk[q]; }
-        pool_row_narrow(a, b1, inv, 2 * r, tt, hv, hk);
+        pool_row_narrow(a, b1, inv, 2 * r, tt, L, hv, hk);
 #pragma unroll
         for (int q = 0; q < 2; ++q)
             if (hv[q] > best[q]) { best[q] = hv[q]; bk[q] = 3 + hk[q]; }
-        load_row_narrow(a, rs, ex, 2 * r + 2, tt, b1);
-        pool_row_narrow(a, b0, inv, 2 * r + 1, tt, pv, pk);
+        load_row_narrow(a, rs, ex, 2 * r + 2, tt, L, b1);
+        pool_row_narrow(a, b0, inv, 2 * r + 1, tt, L, pv, pk);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             if (pv[q] > best[q]) { best[q] = pv[q]; bk[q] = 6 + pk[q]; }
@@ -602,12 +604,16 @@ StreamArgs make_stream_args(int l, const Geom& g, int tro, int& nblocks) {
     b.n_band = (b.hp + b.TRo - 1) / b.TRo;
     b.n_ct = (b.wp + kStreamCols - 1) / kStreamCols;
     b.vec = (b.w % 4) == 0;
-    // Narrow maps: one wave walks two bands (pairs of bands per item); each
-    // child's descriptor spans its whole map, whose byte size must fit an int.
+    // Narrow maps: one wave walks G = 64 / L bands (groups of bands per
+    // item); each child's descriptor spans its whole map, whose byte size
+    // must fit an int.
     b.narrow = b.vec && b.wp <= kStreamCols / 2 && (double)b.h * b.w * 4 < 2.0e9;
-    if (b.narrow) {   // pairs of bands of at most tro rows, the rows split evenly over the two halves
-        b.n_band = (b.hp + 2 * b.TRo - 1) / (2 * b.TRo);
-        b.TRo = (b.hp + 2 * b.n_band - 1) / (2 * b.n_band);
+    b.lgl = 5;
+    if (b.narrow) {   // groups of G bands of at most tro rows, the rows split evenly over the groups
+        while (b.lgl > 0 && 2 * (1 << (b.lgl - 1)) >= b.wp) --b.lgl;   // smallest L with 2 L >= wp
+        const int G = 64 >> b.lgl;
+        b.n_band = (b.hp + G * b.TRo - 1) / (G * b.TRo);
+        b.TRo = (b.hp + G * b.n_band - 1) / (G * b.n_band);
     }
     b.n_items = b.gx * b.gy * b.n_ct * b.n_band;
     nblocks = (b.n_items + kStreamWaves - 1) / kStreamWaves;
@@ -615,8 +621,12 @@ StreamArgs make_stream_args(int l, const Geom& g, int tro, int& nblocks) {
 }
 
 // The streaming form serves FP32 levels below the top whose pooled maps are
-// at least 32 columns wide.
-inline bool use_stream(int l, const Geom& g) { return l < g.lmax && g.w[l + 1] >= 32; }
+// at least 32 columns wide, or at least 16 wide with maps a multiple of 4
+// wide (the narrow form; on smaller maps a wave has too little to do and the
+// tiled form is as fast).
+inline bool use_stream(int l, const Geom& g) {
+    return l < g.lmax && (g.w[l + 1] >= 32 || (g.w[l + 1] >= 16 && g.w[l] % 4 == 0));
+}
 
 }  // namespace
 
