@@ -532,45 +532,65 @@ __device__ inline void top_reduce_body(const float* __restrict__ top, const Geom
 __device__ inline void finalize_body(const unsigned long long* __restrict__ best,
                                      const unsigned long long* __restrict__ cell, const Geom& g,
                                      dm_match* __restrict__ out, int* __restrict__ n_out) {
+    // kFinChunks passes of 1024 patches at a time: their BestAt keys are
+    // loaded together, then the BestAt' entries they name, and only then are
+    // the winners compacted pass by pass (two memory round trips per group
+    // of passes instead of two per pass).
+    constexpr int kFinChunks = 8;
     __shared__ int wsum[16];
     __shared__ int base;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int gx0 = g.gx[0], natom = g.gx[0] * g.gy[0], cw = (g.W2 + 3) / 4;
     if (tid == 0) base = 0;
     __syncthreads();
-    for (int start = 0; start < natom; start += 1024) {
-        const int j = start + tid;
-        int flag = 0;
-        dm_match m;
-        if (j < natom) {
-            const unsigned long long key = best[j];
-            if (key) {
-                const uint32_t xi = 0xFFFFFFFFu - (uint32_t)key;
+    for (int start = 0; start < natom; start += 1024 * kFinChunks) {
+        unsigned long long key[kFinChunks], cv[kFinChunks];
+#pragma unroll
+        for (int c = 0; c < kFinChunks; ++c) {
+            const int j = start + c * 1024 + tid;
+            key[c] = j < natom ? best[j] : 0ull;
+        }
+#pragma unroll
+        for (int c = 0; c < kFinChunks; ++c) {
+            cv[c] = 0ull;
+            if (key[c]) {
+                const uint32_t xi = 0xFFFFFFFFu - (uint32_t)key[c];
                 const int xy = xi / g.W2, xx = xi % g.W2;
-                const unsigned long long expect =
-                    (key & 0xFFFFFFFF00000000ull) | (0xFFFFFFFFull - (uint32_t)(j * 16 + (xy & 3) * 4 + (xx & 3)));
-                flag = cell[(size_t)(xy >> 2) * cw + (xx >> 2)] == expect;
+                cv[c] = cell[(size_t)(xy >> 2) * cw + (xx >> 2)];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kFinChunks; ++c) {
+            const int j = start + c * 1024 + tid;
+            int flag = 0;
+            dm_match m;
+            if (key[c]) {
+                const uint32_t xi = 0xFFFFFFFFu - (uint32_t)key[c];
+                const int xy = xi / g.W2, xx = xi % g.W2;
+                const unsigned long long expect = (key[c] & 0xFFFFFFFF00000000ull) |
+                                                  (0xFFFFFFFFull - (uint32_t)(j * 16 + (xy & 3) * 4 + (xx & 3)));
+                flag = cv[c] == expect;
                 m.x1 = 2 + 4 * (j % gx0);
                 m.y1 = 2 + 4 * (j / gx0);
                 m.x2 = xx;
                 m.y2 = xy;
-                m.score = __uint_as_float((uint32_t)(key >> 32));
+                m.score = __uint_as_float((uint32_t)(key[c] >> 32));
             }
+            const unsigned long long mask = __ballot(flag);
+            const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+            if (lane == 0) wsum[wave] = __popcll(mask);
+            __syncthreads();
+            int off = base;
+            for (int w = 0; w < wave; ++w) off += wsum[w];
+            if (flag) out[off + rank] = m;
+            __syncthreads();
+            if (tid == 0) {
+                int tot = 0;
+                for (int w = 0; w < 16; ++w) tot += wsum[w];
+                base += tot;
+            }
+            __syncthreads();
         }
-        const unsigned long long mask = __ballot(flag);
-        const int rank = __popcll(mask & ((1ull << lane) - 1ull));
-        if (lane == 0) wsum[wave] = __popcll(mask);
-        __syncthreads();
-        int off = base;
-        for (int w = 0; w < wave; ++w) off += wsum[w];
-        if (flag) out[off + rank] = m;
-        __syncthreads();
-        if (tid == 0) {
-            int tot = 0;
-            for (int w = 0; w < 16; ++w) tot += wsum[w];
-            base += tot;
-        }
-        __syncthreads();
     }
     if (tid == 0) *n_out = base;
 }
