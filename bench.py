@@ -42,12 +42,13 @@ HBM_PEAK_GBS = 8000.0
 # profiles/bf16_forward_512x256_hbm_bytes.md.  Only valid for the 512x256
 # pair; a kernel changed since then must be dropped from this table.
 MEASURED_TRAFFIC_512x256 = {
-    "corr_pool_bf16_l0": 43.0e6 + 1611.3e6,
-    "level_l1": 2326.9e6 + 338.0e6,
-    "level_l2": 570.6e6 + 90.6e6,
-    "level_l3": 134.3e6 + 21.5e6,
-    "backtrack_l1": 1746.3e6 + 45.3e6,
-    "backtrack_l2": 414.2e6 + 268.4e6,
+    "corr_pool_bf16_l0": 43.5e6 + 1611.1e6,
+    "level_l1": 2328.0e6 + 338.1e6,
+    "level_l2": 561.2e6 + 89.2e6,
+    "level_l3": 150.0e6 + 23.1e6,
+    "level_l4": 31.6e6 + 5.2e6,
+    "backtrack_l1": 1747.7e6 + 45.3e6,
+    "backtrack_l2": 413.9e6 + 268.4e6,
 }
 PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
 
