@@ -82,8 +82,8 @@ def odd_case():
 @functools.lru_cache(maxsize=None)
 def narrow_case():
     """Crops I 168x120 and I' 200x148: level 1 maps are 100 wide (a multiple
-    of 4) and pool to 50 x 37, the narrow streaming form whose half-waves
-    walk bands of 10 rows, the last one ragged (7 rows)."""
+    of 4) and pool to 50 x 37, the narrow streaming form whose two lane
+    groups walk bands of 10 rows, the last one ragged (7 rows)."""
     p = synth.make_pair("c3")
     i1 = np.ascontiguousarray(p["img1"][60:180, 100:268])
     i2 = np.ascontiguousarray(p["img2"][50:198, 90:290])
