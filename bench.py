@@ -389,14 +389,37 @@ def invariant_bench(dm, torch, img1, img2, plain_ms, steps, warmup):
                          "BF16 correlation, FP32 pyramid")
 
 
-def oracle_agreement(matches):
-    """Fraction of the stored oracle matches of the pair reproduced within 1 px."""
+def _stored_oracle_matches():
     import numpy as np
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "c3_oracle.npz")
-    if not os.path.exists(path):
+    return np.load(path)["matches"] if os.path.exists(path) else None
+
+
+def oracle_agreement(matches):
+    """Fraction of the stored oracle matches of the pair reproduced within 1 px."""
+    ref = _stored_oracle_matches()
+    return None if ref is None else round(within_1px(matches, ref), 5)
+
+
+def oracle_score_error(matches):
+    """Relative score error against the stored oracle matches, over the matches
+    whose source and target pixels both equal the oracle's (and how many of the
+    oracle's matches that is)."""
+    import numpy as np
+    ref = _stored_oracle_matches()
+    if ref is None:
         return None
-    ref = np.load(path)["matches"]
-    return round(within_1px(matches, ref), 5)
+    g = {(int(r[0]), int(r[1])): r for r in matches}
+    rel = []
+    for r in ref:
+        q = g.get((int(r[0]), int(r[1])))
+        if q is not None and int(q[2]) == int(r[2]) and int(q[3]) == int(r[3]):
+            rel.append(abs(float(q[4]) - float(r[4])) / abs(float(r[4])))
+    if not rel:
+        return {"same_coordinates": 0.0}
+    rel = np.array(rel)
+    return {"same_coordinates": round(len(rel) / len(ref), 5), "max": float("%.3g" % rel.max()),
+            "median": float("%.3g" % np.median(rel))}
 
 
 def copy_probe(torch):
@@ -516,10 +539,12 @@ def main():
                    "global_batch": 1, "parallelism": "single GPU"},
         "fp32": {"pairs_s": round(res["fp32"]["pairs_s"], 3), "ms_per_step": round(res["fp32"]["ms"], 4),
                  "matches": int(len(res["fp32"]["matches"])),
-                 "oracle_matches_within_1px": oracle_agreement(res["fp32"]["matches"])},
+                 "oracle_matches_within_1px": oracle_agreement(res["fp32"]["matches"]),
+                 "oracle_score_rel_err": oracle_score_error(res["fp32"]["matches"])},
         "bf16": {"pairs_s": round(head["pairs_s"], 3), "ms_per_step": round(head["ms"], 4),
                  "matches": int(len(head["matches"])), "within_1px_of_fp32": round(agree, 5),
-                 "oracle_matches_within_1px": oracle_agreement(head["matches"])},
+                 "oracle_matches_within_1px": oracle_agreement(head["matches"]),
+                 "oracle_score_rel_err": oracle_score_error(head["matches"])},
         "fwd_bwd": {k: {kk: vv for kk, vv in v.items() if kk != "stages"} for k, v in fb.items()},
         "fwd_bwd_top_kernels_bf16": sorted([(n + ("" if l < 0 else "_l%d" % l), round(t / c, 4))
                                             for n, l, c, t in fb["bf16"]["stages"]], key=lambda x: -x[1])[:6],
