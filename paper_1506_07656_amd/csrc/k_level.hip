@@ -214,7 +214,6 @@ __device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const float* row, int nbytes) 
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(row), (short)0, nbytes, 0x00020000);
 }
 
-template <bool VEC>
 __device__ inline void load_row(const StreamArgs& a, const float* prev, const float* const cmap[4], int y, int X0,
                                 int t, RowBuf& b) {
 #pragma unroll
@@ -226,24 +225,17 @@ __device__ inline void load_row(const StreamArgs& a, const float* prev, const fl
         // kOOB (a byte offset past any row), so that each load is in or out of
         // range on its own whatever the compiler folds into immediate offsets.
         const int s0 = X0 + 4 * t + dx;   // >= -2
-        if constexpr (VEC) {
-            if (k & 1) {   // s0 = 2 C0 + 4t >= 0: 16-byte aligned, entirely inside or outside the row
-                const auto f = __builtin_amdgcn_raw_buffer_load_b128(rs, s0 * 4, 0, 0);
+        if (k & 1) {   // s0 = 2 C0 + 4t >= 0: 16-byte aligned, entirely inside or outside the row
+            const auto f = __builtin_amdgcn_raw_buffer_load_b128(rs, s0 * 4, 0, 0);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) b.v[k][j] = __uint_as_float(f[j]);
-            } else {       // s0 = 2 C0 + 4t - 2: two 8-byte halves, each inside or outside
-                const auto f0 = __builtin_amdgcn_raw_buffer_load_b64(rs, s0 >= 0 ? s0 * 4 : kOOB, 0, 0);
-                const auto f1 = __builtin_amdgcn_raw_buffer_load_b64(rs, s0 * 4 + 8, 0, 0);
-                b.v[k][0] = __uint_as_float(f0[0]);
-                b.v[k][1] = __uint_as_float(f0[1]);
-                b.v[k][2] = __uint_as_float(f1[0]);
-                b.v[k][3] = __uint_as_float(f1[1]);
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                b.v[k][j] = __uint_as_float(
-                    __builtin_amdgcn_raw_buffer_load_b32(rs, s0 + j >= 0 ? (s0 + j) * 4 : kOOB, 0, 0));
+            for (int j = 0; j < 4; ++j) b.v[k][j] = __uint_as_float(f[j]);
+        } else {       // s0 = 2 C0 + 4t - 2: two 8-byte halves, each inside or outside
+            const auto f0 = __builtin_amdgcn_raw_buffer_load_b64(rs, s0 >= 0 ? s0 * 4 : kOOB, 0, 0);
+            const auto f1 = __builtin_amdgcn_raw_buffer_load_b64(rs, s0 * 4 + 8, 0, 0);
+            b.v[k][0] = __uint_as_float(f0[0]);
+            b.v[k][1] = __uint_as_float(f0[1]);
+            b.v[k][2] = __uint_as_float(f1[0]);
+            b.v[k][3] = __uint_as_float(f1[1]);
         }
         b.hv[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (X0 + 4 * 64 + dx) * 4, 0, 0));
     }
@@ -390,8 +382,113 @@ __device__ inline void level_narrow_body(const StreamArgs& a, const float* __res
     }
 }
 
+// Maps whose width is not a multiple of 4 (rows not 16-byte aligned): lane t
+// holds the A columns X0 + 64 j + t, j = 0..3, so that every child load
+// instruction reads 64 consecutive floats.  A pooling window's outer columns
+// come from the neighbouring lanes (lane 63's right neighbour is lane 0 of
+// the next block, or the halo column X0 + 256), and the lanes of odd t, which
+// hold the even (centre) columns 2u, produce pooled column u.  Same sums,
+// same comparisons as the 4-columns-per-lane form.
+struct CoBuf {
+    float v[4][4];   // [child][block]
+    float hv[4];     // halo column, per child
+};
+
+__device__ inline void load_row_co(const StreamArgs& a, const float* prev, const float* const cmap[4], int y, int X0,
+                                   int t, CoBuf& b) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int yy = y + 2 * (k >> 1) - 1, dx = 2 * (k & 1) - 1;
+        const bool rok = cmap[k] != nullptr && yy >= 0 && yy < a.h;     // uniform over the wave
+        const __amdgpu_buffer_rsrc_t rs = row_rsrc(rok ? cmap[k] + (size_t)yy * a.w : prev, rok ? a.w * 4 : 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = X0 + 64 * j + t + dx;   // >= -2; right of the row: past the descriptor's size
+            b.v[k][j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, c >= 0 ? c * 4 : kOOB, 0, 0));
+        }
+        b.hv[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (X0 + 256 + dx) * 4, 0, 0));
+    }
+}
+
+// Horizontal first maxima (value, mx code 0..2) of the windows centred on the
+// lane's four columns (meaningful on lanes of odd t).
+__device__ inline void pool_row_co(const StreamArgs& a, const CoBuf& b, float inv, int y, int X0, int t, float hv[4],
+                                   int hk[4]) {
+    const bool yin = y >= 0 && y < a.h;
+    float av[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float s = (((0.f + b.v[0][j]) + b.v[1][j]) + b.v[2][j]) + b.v[3][j];
+        const float m = s * inv;
+        const int x = X0 + 64 * j + t;
+        av[j] = (yin && x >= 0 && x < a.w) ? fmaxf(m, 0.f) : -1.f;
+    }
+    float halo;
+    {
+        const float s = (((0.f + b.hv[0]) + b.hv[1]) + b.hv[2]) + b.hv[3];
+        const float m = s * inv;
+        halo = (yin && X0 + 256 < a.w) ? fmaxf(m, 0.f) : -1.f;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        // wave_shr:1 gives lane t the value of lane t - 1 (lane 0: unused);
+        // wave_shl:1 gives lane t that of lane t + 1, and lane 63, which has
+        // no source lane, keeps the old operand: the next block's lane 0.
+        const float nxt = j < 3 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av[j < 3 ? j + 1 : j]), 0))
+                                : halo;
+        const float v0 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(av[j]), 0x138, 0xF, 0xF, false));
+        const float v2 =
+            __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(nxt), __float_as_int(av[j]), 0x130, 0xF, 0xF, false));
+        const float v1 = av[j];
+        float best = v0;
+        int k = 0;
+        if (v1 > best) { best = v1; k = 1; }
+        if (v2 > best) { best = v2; k = 2; }
+        hv[j] = best;
+        hk[j] = k;
+    }
+}
+
+__device__ __forceinline__ void level_coalesced_body(const StreamArgs& a, const float* __restrict__ prev,
+                                            const float* const cmap[4], float inv, int P, int band, int ct, int t,
+                                            float lam, float* __restrict__ cp, uint8_t* __restrict__ code) {
+    const int R0 = band * a.TRo, R1 = min(R0 + a.TRo, a.hp);
+    const int C0 = ct * kStreamCols, ncol = min(kStreamCols, a.wp - C0);
+    const int X0 = 2 * C0 - 1;
+    CoBuf b0, b1;
+    float pv[4], hv[4];
+    int pk[4], hk[4];
+    load_row_co(a, prev, cmap, 2 * R0 - 1, X0, t, b0);
+    load_row_co(a, prev, cmap, 2 * R0, X0, t, b1);
+    pool_row_co(a, b0, inv, 2 * R0 - 1, X0, t, pv, pk);
+    for (int r = R0; r < R1; ++r) {
+        // b1 holds row 2r
+        load_row_co(a, prev, cmap, 2 * r + 1, X0, t, b0);
+        float best[4];
+        int bk[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { best[j] = pv[j]; bk[j] = pk[j]; }
+        pool_row_co(a, b1, inv, 2 * r, X0, t, hv, hk);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (hv[j] > best[j]) { best[j] = hv[j]; bk[j] = 3 + hk[j]; }
+        load_row_co(a, prev, cmap, 2 * r + 2, X0, t, b1);   // row 2R1 is in range or masked
+        pool_row_co(a, b0, inv, 2 * r + 1, X0, t, pv, pk);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (pv[j] > best[j]) { best[j] = pv[j]; bk[j] = 6 + pk[j]; }
+            const int u = 32 * j + (t >> 1);   // lane t = 2i + 1 holds centre column 2 (C0 + 32 j + i)
+            if ((t & 1) && u < ncol) {
+                const size_t o = ((size_t)P * a.hp + r) * a.wp + C0 + u;
+                cp[o] = rect_pow(best[j], lam);
+                code[o] = (uint8_t)bk[j];
+            }
+        }
+    }
+}
+
 template <bool VEC, bool NARROW>
-__device__ inline void level_stream_body(const StreamArgs& a, const float* __restrict__ prev,
+__device__ __forceinline__ void level_stream_body(const StreamArgs& a, const float* __restrict__ prev,
                                          const uint8_t* __restrict__ vt, const Geom& g, float lam,
                                          float* __restrict__ cp, uint8_t* __restrict__ code, int bid) {
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), t = threadIdx.x & 63;   // wave index: uniform
@@ -427,6 +524,10 @@ __device__ inline void level_stream_body(const StreamArgs& a, const float* __res
         level_narrow_body(a, prev, cmap, inv, P, band, t, lam, cp, code);
         return;
     }
+    if constexpr (!VEC) {
+        level_coalesced_body(a, prev, cmap, inv, P, band, ct, t, lam, cp, code);
+        return;
+    }
     const int R0 = band * a.TRo, R1 = min(R0 + a.TRo, a.hp);
     const int C0 = ct * kStreamCols, ncol = min(kStreamCols, a.wp - C0);
     const int X0 = 2 * C0 - 1;
@@ -434,12 +535,12 @@ __device__ inline void level_stream_body(const StreamArgs& a, const float* __res
     RowBuf b0, b1;
     float pv[2], hv[2];
     int pk[2], hk[2];
-    load_row<VEC>(a, prev, cmap, 2 * R0 - 1, X0, t, b0);
-    load_row<VEC>(a, prev, cmap, 2 * R0, X0, t, b1);
+    load_row(a, prev, cmap, 2 * R0 - 1, X0, t, b0);
+    load_row(a, prev, cmap, 2 * R0, X0, t, b1);
     pool_row(a, b0, inv, 2 * R0 - 1, X0, t, pv, pk);
     for (int r = R0; r < R1; ++r) {
         // b1 holds row 2r
-        load_row<VEC>(a, prev, cmap, 2 * r + 1, X0, t, b0);
+        load_row(a, prev, cmap, 2 * r + 1, X0, t, b0);
         float best[2];
         int bk[2];
 #pragma unroll
@@ -448,7 +549,7 @@ __device__ inline void level_stream_body(const StreamArgs& a, const float* __res
 #pragma unroll
         for (int q = 0; q < 2; ++q)
             if (hv[q] > best[q]) { best[q] = hv[q]; bk[q] = 3 + hk[q]; }
-        load_row<VEC>(a, prev, cmap, 2 * r + 2, X0, t, b1);   // row 2R1 is in range or masked
+        load_row(a, prev, cmap, 2 * r + 2, X0, t, b1);   // row 2R1 is in range or masked
         pool_row(a, b0, inv, 2 * r + 1, X0, t, pv, pk);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
