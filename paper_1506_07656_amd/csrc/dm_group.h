@@ -1,10 +1,11 @@
 // Persistent grouped launches: one kernel launch runs the blocks of many
 // jobs (one job = one stage of one image pair, with that pair's own sizes and
 // buffers).  Job j owns the virtual blocks [start[j], start[j + 1]); a fixed
-// grid of resident blocks walks them.  The hardware deals blocks to the 8
-// XCDs round-robin, so block b stays on XCD b % 8; each XCD is given one
-// contiguous range of virtual blocks (neighbouring tiles of one pair share
-// its L2), which its blocks take in turn.
+// grid of resident blocks walks them, block b taking b, b + grid, ...  The
+// hardware deals blocks to the 8 XCDs round-robin, so every XCD gets a share
+// of every job: pairs of different sizes have blocks of different cost, and
+// one contiguous range of virtual blocks per XCD (which kept neighbouring
+// tiles of a pair on one L2) left the XCDs with uneven work.
 #pragma once
 
 #include "dm_internal.h"
@@ -27,11 +28,7 @@ __device__ inline int group_find(const int* __restrict__ start, int njobs, int v
 template <class Job, int NT, int MINB>
 __global__ __launch_bounds__(NT, MINB) void k_grouped(const Job* __restrict__ jobs, const int* __restrict__ start,
                                                      int njobs, int total) {
-    const int per_xcd = gridDim.x >> 3;
-    const int x = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int chunk = (total + 7) >> 3;
-    const int vbeg = x * chunk, vend = min(vbeg + chunk, total);
-    for (int v = vbeg + slot; v < vend; v += per_xcd) {
+    for (int v = blockIdx.x; v < total; v += gridDim.x) {
         const int j = __builtin_amdgcn_readfirstlane(group_find(start, njobs, v));
         Job::run(jobs[j], v - start[j]);
         __syncthreads();   // LDS of one virtual block is free before the next one starts
