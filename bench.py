@@ -457,7 +457,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-pair uneven batch")
     ap.add_argument("--no-approx", action="store_true", help="skip approximate DeepMatching")
     ap.add_argument("--no-invariant", action="store_true", help="skip scale and rotation invariant DeepMatching")
-    ap.add_argument("--only", choices=("all", "fwd_bf16", "fwd_bwd_bf16", "approx1024", "approx64", "invariant"),
+    ap.add_argument("--only", choices=("all", "fwd_bf16", "fwd_bwd_bf16", "approx1024", "approx64", "invariant",
+                                       "batch_fwd"),
                     default="all",
                     help="run only that pass (short profiler runs); prints no JSON line")
     args = ap.parse_args()
@@ -493,6 +494,23 @@ def main():
         D = int(args.only[len("approx"):])
         dt, _, _, _ = time_path(dm, torch, img1, img2, "bf16", args.steps, args.warmup, prototypes=D)
         print(f"approximate (D={D}) bf16 forward: {dt * 1e3:.3f} ms/pair", flush=True)
+        return
+    if args.only == "batch_fwd":   # the 32-pair uneven batch, forward only, autotuned, one graph replay per step
+        import synth
+        pairs = synth.make_batch(32)
+        sizes = [(p["img1"].shape[1], p["img1"].shape[0], p["img2"].shape[1], p["img2"].shape[0]) for p in pairs]
+        F = dm.Batch(sizes, dm.params(precision="bf16"), bwd=False, graph=True, autotune=True)
+        F.set_images([torch.from_numpy(p["img1"]).cuda() for p in pairs],
+                     [torch.from_numpy(p["img2"]).cuda() for p in pairs])
+        for _ in range(max(1, args.warmup)):
+            F.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            F.run()
+        torch.cuda.synchronize()
+        print(f"batch of 32 forward: {(time.perf_counter() - t0) / args.steps * 1e3:.3f} ms", flush=True)
+        F.release()
         return
     if args.only == "fwd_bwd_bf16":
         d1, d2 = dm.descriptors(img1), dm.descriptors(img2)
