@@ -24,7 +24,6 @@ __device__ inline int group_find(const int* __restrict__ start, int njobs, int v
 }
 
 // Job must provide: static __device__ void run(const Job&, int block).
-// The grid size is a multiple of 8.
 template <class Job, int NT, int MINB>
 __global__ __launch_bounds__(NT, MINB) void k_grouped(const Job* __restrict__ jobs, const int* __restrict__ start,
                                                      int njobs, int total) {
