@@ -92,15 +92,34 @@ def narrow_case():
     return o
 
 
+@functools.lru_cache(maxsize=None)
+def wide_case(w2):
+    """I 96x72 against I' w2 x 72, I a window of I' before a smooth warp of up
+    to 10 px: level 1 maps are w2 / 2 wide and pool to w2 / 4 columns, so the
+    streaming level form runs a second column tile; at w2 = 540 (maps 270
+    wide, not a multiple of 4) that is the coalesced form, also at level 2
+    (135 wide), and at w2 = 544 the 4-columns-per-lane form."""
+    rng = np.random.default_rng(707)
+    big = synth.blurred_noise(rng, 72, w2)
+    field = synth.smooth_field(rng, 72, w2, 10.0)
+    i2 = np.ascontiguousarray(synth.warp_bilinear(big, field))
+    i1 = np.ascontiguousarray(big[:, 200:296])
+    o = oracle_from_desc(O.descriptors(i1), O.descriptors(i2))
+    o["img1"], o["img2"] = i1, i2
+    return o
+
+
 def case(name):
     if name == "odd":
         return odd_case(), 0
     if name == "narrow":
         return narrow_case(), 0
+    if name.startswith("wide"):
+        return wide_case(int(name[4:])), 0
     return oracle_pair(name), synth.CONFIG_NMAX[name]
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "odd", "narrow"])
+@pytest.mark.parametrize("name", ["c1", "c2", "odd", "narrow", "wide540", "wide544"])
 def test_pyramid_levels_match_oracle(name):
     o, mp = case(name)
     pyr = o["pyr"]
@@ -134,7 +153,7 @@ def test_pyramid_levels_match_oracle(name):
     np.testing.assert_allclose(views["top"].cpu().numpy()[G], pyr.top[G], rtol=1e-5, atol=1e-7)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "odd", "narrow"])
+@pytest.mark.parametrize("name", ["c1", "c2", "odd", "narrow", "wide540", "wide544"])
 def test_matches_fp32_match_oracle(name):
     o, mp = case(name)
     gpu, _, _ = run_desc(o["D1"], o["D2"], max_patch=mp)
