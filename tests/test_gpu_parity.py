@@ -236,7 +236,7 @@ def bf16_operand_case(name):
     return oracle_from_desc(bf16_round(o["D1"]), bf16_round(o["D2"]), mp), mp
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "odd", "narrow"])
+@pytest.mark.parametrize("name", ["c1", "c2", "odd", "narrow", "wide540"])
 def test_bf16_pyramid_equals_oracle_on_bf16_operands(name):
     """The BF16 path on descriptors that BF16 holds exactly against the FP64
     oracle on the same values, element by element.  Products of BF16 values
