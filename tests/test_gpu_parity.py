@@ -153,6 +153,43 @@ def test_pyramid_levels_match_oracle(name):
     np.testing.assert_allclose(views["top"].cpu().numpy()[G], pyr.top[G], rtol=1e-5, atol=1e-7)
 
 
+def random_shape_case(seed):
+    """Seeded sizes, I in [40, 140] x [32, 96], I' in [60, 300] x [40, 160]:
+    crops of one blurred-noise image, I' warped by up to 6 px, so that level
+    maps of every width class occur (not a multiple of 4, narrow, tiled)."""
+    rng = np.random.default_rng(9000 + seed)
+    W1, H1 = int(rng.integers(40, 141)), int(rng.integers(32, 97))
+    W2, H2 = int(rng.integers(60, 301)), int(rng.integers(40, 161))
+    Wb, Hb = max(W1, W2) + 16, max(H1, H2) + 16
+    base = synth.blurred_noise(rng, Hb, Wb)
+    warped = synth.warp_bilinear(base, synth.smooth_field(rng, Hb, Wb, 6.0))
+    i1 = np.ascontiguousarray(base[4:4 + H1, 6:6 + W1])
+    i2 = np.ascontiguousarray(warped[7:7 + H2, 3:3 + W2])
+    return oracle_from_desc(O.descriptors(i1), O.descriptors(i2))
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_shapes_match_oracle(seed):
+    o = random_shape_case(seed)
+    pyr = o["pyr"]
+    gpu, views, pl = run_desc(o["D1"], o["D2"])
+    assert pl.lmax == pyr.lmax
+    for lv in range(pyr.lmax):
+        G = pyr.G[lv]
+        cp = views["levels"][lv]["cp"].cpu().numpy()[G]
+        code = views["levels"][lv]["code"].cpu().numpy()[G]
+        ref = pyr.Cp[lv][G]
+        np.testing.assert_allclose(cp, ref, rtol=1e-5, atol=1e-7, err_msg=f"seed {seed} level {lv}")
+        clear = pyr.gap[lv][G] > FP32_TIE * (1 + ref)
+        assert ((code != pyr.code[lv][G]) & clear).sum() == 0, f"seed {seed} level {lv}: codes differ"
+    G = pyr.G[pyr.lmax]
+    np.testing.assert_allclose(views["top"].cpu().numpy()[G], pyr.top[G], rtol=1e-5, atol=1e-7)
+    r = compare_matches(gpu, o["out"], o["margin"])
+    report(f"random shape {seed} {o['D1'].shape[:2]} {o['D2'].shape[:2]}", r)
+    assert not r["missing"] and not r["moved"] and not r["bad_score"]
+    assert len(r["extra"]) <= r["near_ties"]
+
+
 @pytest.mark.parametrize("name", ["c1", "c2", "odd", "narrow", "wide540", "wide544"])
 def test_matches_fp32_match_oracle(name):
     o, mp = case(name)
