@@ -116,6 +116,8 @@ def case(name):
         return narrow_case(), 0
     if name.startswith("wide"):
         return wide_case(int(name[4:])), 0
+    if name.startswith("random"):
+        return random_shape_case(int(name[6:])), 0
     return oracle_pair(name), synth.CONFIG_NMAX[name]
 
 
@@ -273,7 +275,7 @@ def bf16_operand_case(name):
     return oracle_from_desc(bf16_round(o["D1"]), bf16_round(o["D2"]), mp), mp
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "odd", "narrow", "wide540"])
+@pytest.mark.parametrize("name", ["c1", "c2", "odd", "narrow", "wide540"] + [f"random{k}" for k in range(5)])
 def test_bf16_pyramid_equals_oracle_on_bf16_operands(name):
     """The BF16 path on descriptors that BF16 holds exactly against the FP64
     oracle on the same values, element by element.  Products of BF16 values
