@@ -28,9 +28,11 @@
 namespace dm {
 namespace {
 
-constexpr int MT = 2;                // M-tiles (16 patches) per wave
+constexpr int MT = 2;                // BF16: M-tiles (16 patches) per wave
+constexpr int MF = 1;                // FP32: M-tiles per wave (its register budget allows three waves per SIMD)
 constexpr int WAVES = 4;
-constexpr int PT = 16 * MT * WAVES;  // patches per block
+constexpr int PT = 16 * MT * WAVES;  // BF16: patches per block
+constexpr int PF = 16 * MF * WAVES;  // FP32: patches per block
 constexpr int TR = 8;                // pooled rows per band
 constexpr int ARS = 2 * TR + 1;      // A-rows per band
 constexpr int D2R = 2 * TR + 4;      // target tile rows (A-rows + patch height - 1)
@@ -88,19 +90,19 @@ __device__ inline uint32_t bf16x2_scale16(uint32_t u) {
     return r;
 }
 
-// One x-step of the sweep for both precisions.  Engine supplies the MFMA chain
-// for an N-tile (E or O) of all MT M-tiles.
+// One x-step of the FP32 sweep.  Engine supplies the MFMA chain for an N-tile
+// (E or O) of all MF M-tiles.
 template <typename Engine>
 __device__ inline void sweep_band(const Engine& eng, const PoolArgs& a, int pt, int R0, int seg, float lam,
                                   float* __restrict__ cp, uint8_t* __restrict__ code,
-                                  float (*carry)[16 * MT]) {
+                                  float (*carry)[16 * MF]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = lane & 15, grp = lane >> 4;
-    const int pbase = pt * PT + wave * 16 * MT;
-    // Output offsets of this lane's 4*MT patches (a patch map is h1 x w1).
-    size_t obase[MT][4];
+    const int pbase = pt * PF + wave * 16 * MF;
+    // Output offsets of this lane's 4*MF patches (a patch map is h1 x w1).
+    size_t obase[MF][4];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MF; ++mt)
 #pragma unroll
         for (int j = 0; j < 4; ++j) obase[mt][j] = (size_t)(pbase + mt * 16 + 4 * grp + j) * a.h1 * a.w1;
     const StepRange sr = step_range(a, seg);
@@ -112,16 +114,16 @@ __device__ inline void sweep_band(const Engine& eng, const PoolArgs& a, int pt, 
         __syncthreads();
         const int c = C0 + n;
         const bool e_ok = 2 * c < a.W2, o_ok = 2 * c + 1 < a.W2;
-        float best[MT][4];
-        int bk[MT][4];
+        float best[MF][4];
+        int bk[MF][4];
         for (int ia = 0; ia < ARS; ++ia) {
             const int y = 2 * R0 - 1 + ia;
             const bool y_ok = y >= 0 && y < a.H2;
-            f4 accE[MT], accO[MT];
+            f4 accE[MF], accO[MF];
             eng.mfma_row(ia, 2 * n, accE);
             eng.mfma_row(ia, 2 * n + 1, accO);
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
+            for (int mt = 0; mt < MF; ++mt) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int lp = mt * 16 + 4 * grp + j;
@@ -171,7 +173,7 @@ __device__ inline void sweep_band(const Engine& eng, const PoolArgs& a, int pt, 
 }
 
 struct EngineF32 {
-    const float* fa;   // [MT][36] patch fragments (registers of the caller)
+    const float* fa;   // [MF][36] patch fragments (registers of the caller)
     float* sD2;        // [D2R][D2C][9]
     const float* d2;
     __device__ void load_tile(const PoolArgs& a, int R0, int C0) const {
@@ -190,7 +192,7 @@ struct EngineF32 {
 #pragma unroll
         for (int t = 0; t < 36; ++t) fb[t] = bs[t];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
+        for (int mt = 0; mt < MF; ++mt) {
             f4 r = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int t = 0; t < 36; ++t) r = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[mt * 36 + t], fb[t], r, 0, 0, 0);
@@ -418,17 +420,17 @@ __device__ inline void sweep_band_bf16(const bf8* fa, const bf8* faO, uint32_t* 
 __device__ inline void corr_f32_body(const float* __restrict__ d1, const float* __restrict__ d2, const PoolArgs& a,
                                      float lam, float* __restrict__ cp, uint8_t* __restrict__ code, int bid) {
     __shared__ float sD2[D2R * D2C * 9];
-    __shared__ float sCarry[WAVES][ARS][16 * MT];
+    __shared__ float sCarry[WAVES][ARS][16 * MF];
     const int pt = bid % a.n_ptiles, rest = bid / a.n_ptiles;
     const int seg = rest % a.n_seg, R0 = (rest / a.n_seg) * TR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n = lane & 15, grp = lane >> 4;
     // Patch fragments: lane (n, grp) holds row grp of the 4x4 patch of patch
     // pbase + 16 mt + n: 4 pixels x 9 channels, contiguous in D1.
-    float fa[MT * 36];
+    float fa[MF * 36];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-        const int j = pt * PT + wave * 16 * MT + mt * 16 + n;
+    for (int mt = 0; mt < MF; ++mt) {
+        const int j = pt * PF + wave * 16 * MF + mt * 16 + n;
         if (j < a.natom) {
             const int b = j / a.n0x, aa = j - b * a.n0x;
             const float* src = d1 + ((size_t)(4 * b + grp) * a.W1 + 4 * aa) * 9;
@@ -523,7 +525,7 @@ struct CorrBF16Job {
 
 // split: allow column segments (single-pair launches; a grouped launch over
 // many pairs has blocks enough without the extra step a segment costs).
-PoolArgs make_pool_args(const Geom& g, int& nblocks, bool split) {
+PoolArgs make_pool_args(const Geom& g, int& nblocks, bool split, bool bf16) {
     PoolArgs a;
     a.natom = g.gx[0] * g.gy[0];
     a.n0x = g.gx[0];
@@ -532,7 +534,7 @@ PoolArgs make_pool_args(const Geom& g, int& nblocks, bool split) {
     a.H2 = g.H2;
     a.h1 = g.h[1];
     a.w1 = g.w[1];
-    a.n_ptiles = (a.natom + PT - 1) / PT;
+    a.n_ptiles = (a.natom + (bf16 ? PT : PF) - 1) / (bf16 ? PT : PF);
     a.n_steps = (a.w1 + 15) / 16;
     // Few patches (prototype maps, small images): split the sweep into
     // column segments until about 1024 blocks exist.
@@ -612,7 +614,7 @@ __global__ void k_corr_pool_ref(const T* __restrict__ d1, const T* __restrict__ 
 hipError_t launch_corr_pool_f32(const float* d1, const float* d2, const Geom& g, float lam, float* cp,
                                 uint8_t* code, hipStream_t s) {
     int nb;
-    const PoolArgs a = make_pool_args(g, nb, true);
+    const PoolArgs a = make_pool_args(g, nb, true, false);
     hipLaunchKernelGGL(k_corr_pool_f32, dim3(nb), dim3(256), 0, s, d1, d2, a, lam, cp, code);
     return hipGetLastError();
 }
@@ -620,14 +622,14 @@ hipError_t launch_corr_pool_f32(const float* d1, const float* d2, const Geom& g,
 hipError_t launch_corr_pool_bf16(const uint16_t* d1, const uint16_t* d2, const Geom& g, float lam, float* cp,
                                  uint8_t* code, hipStream_t s) {
     int nb;
-    const PoolArgs a = make_pool_args(g, nb, true);
+    const PoolArgs a = make_pool_args(g, nb, true, true);
     hipLaunchKernelGGL(k_corr_pool_bf16, dim3(nb), dim3(256), 0, s, d1, d2, a, lam, cp, code);
     return hipGetLastError();
 }
 
 JobRec corr_job(bool bf16, const void* d1, const void* d2, const Geom& g, float lam, float* cp, uint8_t* code) {
     int nb;
-    const PoolArgs a = make_pool_args(g, nb, false);
+    const PoolArgs a = make_pool_args(g, nb, false, bf16);
     JobRec r;
     if (bf16) r.set(JK_CORR_BF16, nb, 0, CorrBF16Job{(const uint16_t*)d1, (const uint16_t*)d2, a, lam, cp, code});
     else r.set(JK_CORR_F32, nb, 0, CorrF32Job{(const float*)d1, (const float*)d2, a, lam, cp, code});
