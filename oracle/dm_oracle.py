@@ -782,11 +782,25 @@ def top_loss(pyr: Pyramid) -> float:
     return float(t.reshape(len(t), -1).max(1).sum())
 
 
-def pyramid_backward(D1: np.ndarray, D2: np.ndarray, pyr: Pyramid):
+def pyramid_backward(D1: np.ndarray, D2: np.ndarray, pyr: Pyramid, tie: float | None = None):
     """dL/dD1, dL/dD2 for the loss of `top_loss`, by hand-written adjoints of
     rectification, shift-average, max-pool/subsample (routed to the stored
     argmax) and the bottom correlation.  `pyr` must come from
-    pyramid(..., keep_full=True)."""
+    pyramid(..., keep_full=True).
+
+    With `tie` set, also returns two boolean masks shaped like D1 and D2: the
+    coordinates whose gradient passes a decision that a less precise
+    evaluation may take the other way (R14), and the list of those decisions
+    as (level, b, a, y, x): the pooled cell (y, x) of patch (b, a) at a level
+    below the top, or the top map's first maximum (y, x) at level lmax.  A decision is the top map's
+    maximum or a pooling argmax that carries gradient, and it is at risk when
+    a runner-up lies within tie * (1 + value) of the winner (exact ties
+    included, since an ulp of difference upstream can split them); every
+    candidate within that distance may then receive the gradient.  The flag
+    travels down the same adjoints as the gradient: rectification keeps the
+    position, the shifted average sends it to each child position, a pooled
+    cell sends it to its routed position, and the bottom correlation to the
+    16 pixels of patch p in D1 and the 4x4 support of position q in D2."""
     if pyr.assign is not None:
         raise ValueError("the gradient is defined for the exact method only (no prototypes)")
     W, H, lmax, lam = pyr.W, pyr.H, pyr.lmax, pyr.lam
@@ -797,6 +811,21 @@ def pyramid_backward(D1: np.ndarray, D2: np.ndarray, pyr: Pyramid):
     dC = np.zeros_like(top)
     bb, aa = np.nonzero(G)
     dC.reshape(top.shape[0], top.shape[1], -1)[bb, aa, am[bb, aa]] = 1.0
+    flag = None
+    if tie is not None:
+        unstable, tvid = pooling_stability(pyr, tie)
+        mx = flat.max(-1, keepdims=True)
+        near = (flat >= mx - tie * (1.0 + np.abs(mx))) & (mx > 0)
+        if lmax == 0:   # the top is the bottom: distinct correlations
+            at_risk = near.sum(-1) >= 2
+        else:
+            tv = tvid.reshape(flat.shape)
+            winner = np.take_along_axis(tv, am[..., None], axis=-1)
+            at_risk = (near & ((flat < mx) | (tv != winner))).any(-1)
+        flag = (near & at_risk[..., None]).reshape(top.shape)
+        w_top = top.shape[-1]
+        decisions = [(lmax, int(b), int(a), int(am[b, a] // w_top), int(am[b, a] % w_top))
+                     for b, a in zip(*np.nonzero(at_risk & G))]
     for lv in range(lmax, 0, -1):
         A = pyr.A[lv]
         dA = np.where(A > 0, dC * lam * np.where(A > 0, A, 1.0) ** (lam - 1.0), 0.0)
@@ -814,14 +843,23 @@ def pyramid_backward(D1: np.ndarray, D2: np.ndarray, pyr: Pyramid):
             ok &= pyr.G[lv - 1][cb, ca] & pyr.G[lv]
             cnt += ok
             links.append((ox, oy, cb, ca, ok))
+        fCp = np.zeros((ny, nx, h + 2, w + 2), dtype=bool) if flag is not None else None
         for ox, oy, cb, ca, ok in links:
             pb, pa = np.nonzero(ok)
             contrib = dA[pb, pa] / cnt[pb, pa][:, None, None]
             dCp[cb[pb, pa], ca[pb, pa], 1 + oy:1 + oy + h, 1 + ox:1 + ox + w] += contrib
+            if flag is not None:
+                fCp[cb[pb, pa], ca[pb, pa], 1 + oy:1 + oy + h, 1 + ox:1 + ox + w] |= flag[pb, pa]
         dCp = dCp[:, :, 1:1 + h, 1:1 + w]
+        if flag is not None:
+            fCp = fCp[:, :, 1:1 + h, 1:1 + w]
         if lv == 1:
             break   # dCp is the gradient of the pooled bottom maps C'_0
         dC = unpool_adjoint(dCp, pyr.code[lv - 1], pyr.h[lv - 1], pyr.w[lv - 1])
+        if flag is not None:
+            below = rectify(np.nan_to_num(pyr.A[lv - 1], nan=0.0), lam)
+            flag, risky = unpool_flag(fCp, dCp, pyr.code[lv - 1], pyr.Cp[lv - 1], unstable[lv - 1], below, tie)
+            decisions += [(lv - 1, *map(int, t)) for t in zip(*np.nonzero(risky))]
     # adjoint of the bottom correlation, Eq. (3), over chunks of patch rows
     # (the bottom maps are full resolution; a chunk at a time bounds memory)
     Hh, Ww, C = D1.shape
@@ -832,6 +870,9 @@ def pyramid_backward(D1: np.ndarray, D2: np.ndarray, pyr: Pyramid):
     D2p[2:2 + H2, 2:2 + W2] = D2
     dD1 = np.zeros_like(D1, dtype=np.float64)
     dD2p = np.zeros_like(D2p)
+    if flag is not None:
+        f1 = np.zeros(D1.shape, dtype=bool)
+        f2p = np.zeros(D2p.shape, dtype=bool)
     chunk = ny0 if pyr.A[0] is not None else 4
     for r0 in range(0, ny0, chunk):
         rows = np.arange(r0, min(ny0, r0 + chunk))
@@ -841,13 +882,131 @@ def pyramid_backward(D1: np.ndarray, D2: np.ndarray, pyr: Pyramid):
         dA0 = np.where(A0 > 0, dC0 * lam * np.where(A0 > 0, A0, 1.0) ** (lam - 1.0), 0.0)
         g = dA0.reshape(len(rows) * nx0, H2 * W2) / 16.0
         cy = 2 + 4 * rows
+        if flag is not None:
+            if lmax == 0:
+                fl0 = flag[rows]
+            else:
+                fl0, risky = unpool_flag(fCp[rows], dCp[rows], pyr.code[0][rows], pyr.Cp[0][rows],
+                                         unstable[0][rows], rectify(A0, lam), tie)
+                decisions += [(0, int(b) + r0, *map(int, t)) for b, *t in zip(*np.nonzero(risky))]
+            # patch p: its 16 pixels in D1; position q: the 4x4 support q + delta in D2
+            hit = fl0.any(axis=(-2, -1))
+            anyq = fl0.any(axis=(0, 1))
+            for dy in (-2, -1, 0, 1):
+                for dx in (-2, -1, 0, 1):
+                    f1[np.ix_(cy + dy, cx + dx)] |= hit[..., None]
+                    f2p[2 + dy:2 + dy + H2, 2 + dx:2 + dx + W2] |= anyq[..., None]
         for dy in (-2, -1, 0, 1):
             for dx in (-2, -1, 0, 1):
                 S = D2p[2 + dy:2 + dy + H2, 2 + dx:2 + dx + W2].reshape(-1, C)
                 P = D1[np.ix_(cy + dy, cx + dx)].reshape(-1, C)
                 dD1[np.ix_(cy + dy, cx + dx)] += (g @ S).reshape(len(rows), nx0, C)
                 dD2p[2 + dy:2 + dy + H2, 2 + dx:2 + dx + W2] += (g.T @ P).reshape(H2, W2, C)
+    if flag is not None:
+        return dD1, dD2p[2:2 + H2, 2:2 + W2], f1, f2p[2:2 + H2, 2:2 + W2], decisions
     return dD1, dD2p[2:2 + H2, 2:2 + W2]
+
+
+def _mix64(h: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """One step of a 64-bit hash chain (the splitmix64 finaliser of h + v)."""
+    with np.errstate(over="ignore"):
+        z = h + v.astype(np.uint64) + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def _value_ids(pyr: Pyramid, lv: int, pid_below: np.ndarray) -> np.ndarray:
+    """Provenance of every value of C_lv (lv >= 1): a hash of the identities
+    of the pooled child values it averages (Eq. (12)), -1 for a read outside
+    the child's map, nothing for a missing child.  Equal ids mean the same
+    child values added in the same order, hence bitwise equal results in any
+    deterministic evaluation; ids are non-negative."""
+    W, H = pyr.W, pyr.H
+    h, w = pyr.h[lv], pyr.w[lv]
+    cy, cx = lattice_centres(lv, W, H)
+    CY, CX = np.meshgrid(cy, cx, indexing="ij")
+    vid = np.zeros(CY.shape + (h, w), dtype=np.uint64)
+    for ox, oy in OFFSETS:
+        cb, ca, ok = lattice_index(lv - 1, W, H, CY + (2 ** lv) * oy, CX + (2 ** lv) * ox)
+        ok &= pyr.G[lv - 1][cb, ca]
+        pad = np.full(pid_below.shape[:-2] + (h + 2, w + 2), -1, dtype=np.int64)
+        pad[..., 1:1 + h, 1:1 + w] = pid_below
+        child = pad[cb, ca, 1 + oy:1 + oy + h, 1 + ox:1 + ox + w]
+        vid = np.where(ok[..., None, None], _mix64(vid, child), vid)
+    return (vid >> np.uint64(1)).astype(np.int64)
+
+
+def pooling_stability(pyr: Pyramid, tie: float):
+    """The decisions a less precise evaluation may take differently (R14).
+
+    Returns (unstable, top_vid): per level l < lmax, the pooled cells whose
+    argmax (Eq. (9)) is at risk, and the provenance ids of the top map.  A
+    decision with a positive best value is at risk when a runner-up lies
+    within tie * (1 + best) of it, unless the runner-up is an exact tie whose
+    value has the same provenance as the winner's (`_value_ids`: the same
+    stable child values, which every evaluation adds alike).  At level 0
+    every exact tie counts, its candidates being distinct correlations.  A
+    pooled cell passes on the provenance of its source position when its
+    decision is stable, and an identity of its own otherwise."""
+    out = []
+    pid = None
+    for lv in range(pyr.lmax + 1):
+        vid = None if lv == 0 else _value_ids(pyr, lv, pid)
+        if lv == pyr.lmax:
+            return out, vid
+        best, code = pyr.Cp[lv], pyr.code[lv]
+        thr = tie * (1.0 + np.abs(best))
+        h, w = best.shape[-2:]
+        ry, rx = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+        sy, sx = 2 * ry + code // 3 - 1, 2 * rx + code % 3 - 1
+        if lv == 0:
+            unstable = (pyr.gap[lv] <= thr) & (best > 0)
+            src = (sy * pyr.w[0] + sx).astype(np.int64)
+        else:
+            C = rectify(np.nan_to_num(pyr.A[lv], nan=0.0), pyr.lam)
+            hp, wp = C.shape[-2:]
+            Cpad = np.full(C.shape[:-2] + (hp + 3, wp + 3), -np.inf)
+            Cpad[..., 1:1 + hp, 1:1 + wp] = C
+            Vpad = np.full(C.shape[:-2] + (hp + 3, wp + 3), -1, dtype=np.int64)
+            Vpad[..., 1:1 + hp, 1:1 + wp] = vid
+            src = np.take_along_axis(vid.reshape(vid.shape[:-2] + (-1,)),
+                                     (sy * wp + sx).reshape(code.shape[:-2] + (-1,)).astype(np.int64),
+                                     axis=-1).reshape(code.shape)
+            unstable = np.zeros(best.shape, dtype=bool)
+            for my in (-1, 0, 1):
+                for mx in (-1, 0, 1):
+                    v = Cpad[..., 1 + my:1 + my + 2 * h:2, 1 + mx:1 + mx + 2 * w:2]
+                    vv = Vpad[..., 1 + my:1 + my + 2 * h:2, 1 + mx:1 + mx + 2 * w:2]
+                    unstable |= (v < best) & (v >= best - thr)
+                    unstable |= (v == best) & (vv != src)
+            unstable &= best > 0
+        out.append(unstable)
+        marker = -2 - np.arange(best.size, dtype=np.int64).reshape(best.shape)
+        pid = np.where(unstable, marker, src)
+
+
+def unpool_flag(fCp: np.ndarray, dCp: np.ndarray, code: np.ndarray, best: np.ndarray, unstable: np.ndarray,
+                C: np.ndarray, tie: float) -> np.ndarray:
+    """The near-tie flag of `pyramid_backward` through S o P (Eqs. (8)-(9)):
+    a flagged pooled cell flags its routed position; an unstable cell
+    (`pooling_stability`) that carries gradient or a flag flags every
+    position of its window within tie * (1 + best) of the best (C: the map
+    below the pooling).  Returns the flags of that map and the mask of the
+    unstable cells that carry gradient or a flag."""
+    h, w = fCp.shape[-2:]
+    hp, wp = C.shape[-2:]
+    out = unpool_adjoint(fCp.astype(np.float64), code, hp, wp) > 0
+    thr = best - tie * (1.0 + np.abs(best))
+    risky = (fCp | (dCp != 0)) & unstable
+    Cpad = np.full(C.shape[:-2] + (hp + 3, wp + 3), -np.inf)
+    Cpad[..., 1:1 + hp, 1:1 + wp] = C
+    opad = np.zeros(Cpad.shape, dtype=bool)
+    for my in (-1, 0, 1):
+        for mx in (-1, 0, 1):
+            v = Cpad[..., 1 + my:1 + my + 2 * h:2, 1 + mx:1 + mx + 2 * w:2]
+            opad[..., 1 + my:1 + my + 2 * h:2, 1 + mx:1 + mx + 2 * w:2] |= risky & (v >= thr)
+    return out | opad[..., 1:1 + hp, 1:1 + wp], risky
 
 
 def unpool_adjoint(dCp: np.ndarray, code: np.ndarray, hp: int, wp: int) -> np.ndarray:

@@ -344,6 +344,20 @@ def test_translation_recovered(noise):
     assert len(np.unique(out[:, 2:4] // 4, axis=0)) == len(out)
 
 
+def test_warped_pair_recovers_the_ground_truth_field():
+    """End to end on the 256x192 warped pair c2: the oracle's matches follow
+    the true displacement field (the inverse of the smooth warp that made
+    I') to within 1 px, except in the periodic rectangle, where the texture
+    repeats every 8 px, and near the borders."""
+    from tests.helpers import GT_WITHIN_1PX_ALL, GT_WITHIN_1PX_CLEAR, ground_truth_agreement, oracle_pair
+    o = oracle_pair("c2")
+    frac_all, frac_clear, n_clear = ground_truth_agreement(o["out"], o["pair"])
+    print(f"c2 oracle: {len(o['out'])} matches, {frac_all:.4f} within 1 px of the true field, "
+          f"{frac_clear:.4f} of the {n_clear} away from the periodic rectangle and the borders")
+    assert n_clear > 1000
+    assert frac_clear >= GT_WITHIN_1PX_CLEAR and frac_all >= GT_WITHIN_1PX_ALL
+
+
 # ---------------------------------------------------------------- backtracking
 
 def _enumerate(pyr, lv, b, a, qy, qx, s, path, out):
@@ -493,6 +507,139 @@ def test_gradient_matches_autograd_reexpression():
     L.backward()
     np.testing.assert_allclose(g1, t1.grad.numpy(), rtol=1e-10, atol=1e-13)
     np.testing.assert_allclose(g2, t2.grad.numpy(), rtol=1e-10, atol=1e-13)
+
+
+def _c4_sub_pair():
+    p = synth.make_pair("c4")
+    D1, D2 = O.descriptors(p["img1"]), O.descriptors(p["img2"])
+    return np.ascontiguousarray(D1[72:120, 104:152]), np.ascontiguousarray(D2[72:120, 104:152])
+
+
+def test_gradient_flags_cover_every_alternative_route():
+    """The near-tie flags of pyramid_backward (R14): forcing any flagged
+    decision (a pooling argmax, or the top map's maximum) to any other
+    candidate within the tie changes the gradient only at flagged
+    coordinates.  A generous tie makes decisions at every level risky."""
+    D1, D2 = _c4_sub_pair()
+    tie = 1e-3
+    pyr = O.pyramid(D1, D2, O.Params(max_patch=64), keep_full=True)
+    g1, g2, f1, f2, dec = O.pyramid_backward(D1, D2, pyr, tie=tie)
+    ref1, ref2 = O.pyramid_backward(D1, D2, pyr)
+    np.testing.assert_array_equal(g1, ref1)
+    np.testing.assert_array_equal(g2, ref2)
+    levels = {d[0] for d in dec}
+    assert levels == set(range(pyr.lmax + 1)), levels
+    assert f1.mean() < 0.95 and f2.mean() < 0.95
+    gmax = max(np.abs(g1).max(), np.abs(g2).max())
+    flips = changed = 0
+
+    def check():
+        nonlocal flips, changed
+        h1, h2 = O.pyramid_backward(D1, D2, pyr)
+        for g, h, f in ((g1, h1, f1), (g2, h2, f2)):
+            moved = np.abs(h - g) > 1e-12 * gmax
+            changed += int(moved.any())
+            assert not (moved & ~f).any(), "an alternative route reaches unflagged coordinates"
+        flips += 1
+
+    for lv, b, a, y, x in dec:
+        if lv == pyr.lmax:
+            top = pyr.top[b, a]
+            m = top[y, x]
+            for k in np.flatnonzero(top.reshape(-1) >= m - tie * (1 + m)):
+                qy, qx = divmod(int(k), top.shape[1])
+                if (qy, qx) == (y, x):
+                    continue
+                old = top[qy, qx]
+                top[qy, qx] = np.nextafter(m, np.inf) if (qy, qx) > (y, x) else m
+                check()
+                top[qy, qx] = old
+            continue
+        code = pyr.code[lv]
+        k0, best = int(code[b, a, y, x]), pyr.Cp[lv][b, a, y, x]
+        A = pyr.A[lv][b, a] if lv else O.bottom_scores(D1, D2, np.array([b]))[0, a]
+        C = O.rectify(A, pyr.lam)
+        for k in range(9):
+            yy, xx = 2 * y + k // 3 - 1, 2 * x + k % 3 - 1
+            if k == k0 or not (0 <= yy < C.shape[0] and 0 <= xx < C.shape[1]) or C[yy, xx] < best - tie * (1 + best):
+                continue
+            code[b, a, y, x] = k
+            check()
+            code[b, a, y, x] = k0
+    assert flips >= 50 and changed >= 50, (flips, changed)
+
+
+def test_pooling_stability_bruteforce_provenance():
+    """pooling_stability against a brute force: every value of every map is
+    given the explicit tree of the child values it averages (a stable pooled
+    cell passes on its source's tree, an unstable one a leaf of its own), and
+    equal trees are interned to one id by an exact dictionary.  A decision is
+    unstable iff a runner-up lies within the tie with a lower value, or
+    equals the winner with a different tree (level 0: any equal value)."""
+    D1, D2 = _c4_sub_pair()
+    pyr = O.pyramid(D1, D2, O.Params(max_patch=64), keep_full=True)
+    W, H = pyr.W, pyr.H
+    for tie in (2e-5, 1e-3):
+        unstable, top_vid = O.pooling_stability(pyr, tie)
+        intern = {}
+        pid = {}          # (lv, b, a, y, x) of a pooled cell -> tree id of its value
+        for lv in range(pyr.lmax + 1):
+            ny, nx = O.lattice_shape(lv, W, H)
+            h, w = pyr.h[lv], pyr.w[lv]
+            vid = {}
+            if lv >= 1:
+                for b in range(ny):
+                    for a in range(nx):
+                        if not pyr.G[lv][b, a]:
+                            continue
+                        kids = []
+                        for ox, oy in O.OFFSETS:
+                            cb, ca, ok = O.lattice_index(lv - 1, W, H, 4 * b + (2 ** lv) * oy, 4 * a + (2 ** lv) * ox)
+                            kids.append((bool(ok and pyr.G[lv - 1][cb, ca]), int(cb), int(ca), ox, oy))
+                        for y in range(h):
+                            for x in range(w):
+                                t = tuple(("out",) if not (0 <= y + oy < h and 0 <= x + ox < w)
+                                          else pid[(lv - 1, cb, ca, y + oy, x + ox)]
+                                          for ok, cb, ca, ox, oy in kids if ok)
+                                vid[(b, a, y, x)] = intern.setdefault(t, len(intern))
+            if lv == pyr.lmax:
+                # the vectorised ids induce the same partition of every top map
+                for b in range(ny):
+                    for a in range(nx):
+                        if pyr.G[lv][b, a]:
+                            mine = np.array([[vid[(b, a, y, x)] for x in range(w)] for y in range(h)])
+                            _, inv1 = np.unique(mine, return_inverse=True)
+                            _, inv2 = np.unique(top_vid[b, a], return_inverse=True)
+                            assert len(set(zip(inv1.ravel(), inv2.ravel()))) == len(set(inv1.ravel()))
+                            assert len(set(inv1.ravel())) == len(set(inv2.ravel()))
+                break
+            C = O.rectify(pyr.A[lv] if lv else O.bottom_scores(D1, D2), pyr.lam)
+            hp, wp = pyr.h[lv + 1], pyr.w[lv + 1]
+            n_unstable = 0
+            for b in range(ny):
+                for a in range(nx):
+                    if not pyr.G[lv][b, a]:
+                        continue
+                    for y in range(hp):
+                        for x in range(wp):
+                            k0 = int(pyr.code[lv][b, a, y, x])
+                            sy, sx = 2 * y + k0 // 3 - 1, 2 * x + k0 % 3 - 1
+                            best = C[b, a, sy, sx]
+                            bad = False
+                            for k in range(9):
+                                yy, xx = 2 * y + k // 3 - 1, 2 * x + k % 3 - 1
+                                if k == k0 or not (0 <= yy < h and 0 <= xx < w) or best <= 0:
+                                    continue
+                                v = C[b, a, yy, xx]
+                                if best - tie * (1 + best) <= v < best:
+                                    bad = True
+                                elif v == best and (lv == 0 or vid[(b, a, yy, xx)] != vid[(b, a, sy, sx)]):
+                                    bad = True
+                            assert bad == bool(unstable[lv][b, a, y, x]), (tie, lv, b, a, y, x)
+                            n_unstable += bad
+                            pid[(lv, b, a, y, x)] = (("u", lv, b, a, y, x) if bad else
+                                                     (("c0", b, a, sy, sx) if lv == 0 else vid[(b, a, sy, sx)]))
+            assert n_unstable > 0 or tie < 1e-4
 
 
 # ---------------------------------------------------------------- approximate DeepMatching (Sec. 4.1)
