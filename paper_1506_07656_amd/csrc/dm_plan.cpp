@@ -189,6 +189,11 @@ dm_status plan_grad(const dm_params* prm, int W1, int H1, int W2, int H2, int re
     if (st != DM_OK) return st;
     if (pi.lmax == 0) return fail(DM_ERR_UNSUPPORTED, "the pyramid has a single level; nothing to route a gradient through");
     if (prm->prototypes) return fail(DM_ERR_UNSUPPORTED, "the gradient is that of the exact method (prototypes = 0)");
+    // The bottom GEMMs address the pooled gradient of 128 patches from one
+    // 32-bit buffer offset.
+    if (prm->precision != DM_FP64 && (uint64_t)128 * pi.h[1] * pi.w[1] * 4 >= (uint64_t(1) << 31))
+        return fail(DM_ERR_SHAPE, "image 2 is %dx%d; the gradient supports at most %d pooled positions", W2, H2,
+                    (1 << 31) / 512 - 1);
     memset(out, 0, sizeof(*out));
     out->geom = pi;
     out->recompute = recompute ? 1 : 0;
@@ -217,7 +222,15 @@ dm_status plan_grad(const dm_params* prm, int W1, int H1, int W2, int H2, int re
         out->off_bf1 = take(xo, (uint64_t)W1 * H1 * 10 * 2);
         out->off_bf2 = take(xo, (uint64_t)W2 * H2 * 10 * 2);
     }
-    const uint64_t ng = (uint64_t)pi.gx[0] * pi.gy[0] * pi.h[1] * pi.w[1];  // largest pooled level
+    // Gradients of the pooled maps C'_l, l < lmax, alternate between two
+    // buffers; each holds the largest of them.  Levels above 0 have
+    // ceil(W/4) x ceil(H/4) lattice points against floor(W/4) x floor(H/4)
+    // at level 0, so with tiny maps a coarser level can be the largest.
+    uint64_t ng = 0;
+    for (int l = 0; l < pi.lmax; ++l) {
+        const uint64_t n = (uint64_t)pi.gx[l] * pi.gy[l] * pi.h[l + 1] * pi.w[l + 1];
+        if (n > ng) ng = n;
+    }
     out->off_g[0] = take(xo, ng * es);
     out->off_g[1] = take(xo, ng * es);
     out->off_part = take(xo, (uint64_t)out->nsplit * pi.n_atomic * 144 * es);

@@ -173,6 +173,23 @@ def test_grad_plan_layout_and_errors():
     assert st == -1
 
 
+@pytest.mark.parametrize("W1,H1,W2,H2", [(9, 401, 1, 1), (401, 9, 1, 1), (13, 13, 2, 2), (256, 192, 256, 192),
+                                         (37, 23, 19, 41)])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_grad_plan_holds_every_level_gradient(W1, H1, W2, H2, prec):
+    """The two level-gradient buffers alternate over the pooled maps C'_l,
+    l < lmax, so each must hold the largest, which need not be level 0's: the
+    lattice above level 0 has ceil(W/4) x ceil(H/4) points, level 0
+    floor(W/4) x floor(H/4)."""
+    gp = dm.plan_grad(W1, H1, W2, H2, dm.params(precision=prec))
+    g = gp.geom
+    es = 8 if prec == "fp64" else 4
+    need = max(g.gx[l] * g.gy[l] * g.h[l + 1] * g.w[l + 1] for l in range(g.lmax)) * es
+    # scratch layout: ..., g[0], g[1], part, ...
+    assert gp.off_g[0] < gp.off_g[1] < gp.off_part
+    assert gp.off_g[1] - gp.off_g[0] >= need and gp.off_part - gp.off_g[1] >= need
+
+
 def _pairs(sizes, img=0x1000, dd=None):
     P = (dm.Pair * len(sizes))()
     for k, (a, b, c, d) in enumerate(sizes):
