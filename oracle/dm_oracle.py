@@ -103,6 +103,15 @@ library takes the same ones):
      BestAt(cell of P) is the best score, ties to the smallest (T_y, T_x), then
      the smallest (P_y, P_x); BestAt'(cell of T) as in R12.  The matches come
      out ordered by the source cell (row-major), at most one per cell.
+ R24 DM* entry points (Sec. 3.3 names them only as local maxima over the
+     correlation maps of every level; Table 1's middle configuration pairs
+     them with the current path-sum scoring): the maps are those the method
+     keeps, C_top and the pooled C'_l below it (a pooled cell stands for the
+     position it was pooled from); a local maximum is positive, not below any
+     of its 3 x 3 neighbours inside the map and above those before it in
+     raster order (one maximum per plateau, since pooling repeats values in
+     adjacent cells); an entry starts with its map value, tuples from above
+     and entries merge by max at equal (N, p, p').
 
 Parity of the descriptor against the paper itself is unpinned (R10 fills in
 details the paper does not give); it is pinned only by its invariants.
@@ -134,6 +143,10 @@ class Params:
     # method) and the spherical k-means iterations (R16-R19).
     prototypes: int = 0
     kmeans_iters: int = 10
+    # Entry points of the backtracking (Sec. 3.3, "Merging correspondences"):
+    # 0 = every position of the top level; 1 = the earlier scheme (DM*,
+    # compared in Table 1), local maxima of the maps of every level (R24).
+    entry_points: int = 0
 
 
 # ----------------------------------------------------------------------------
@@ -529,16 +542,22 @@ def _dedup_max(key: np.ndarray, s: np.ndarray):
     return keep, gap
 
 
-def backtrack(pyr: Pyramid, entries=None):
+def backtrack(pyr: Pyramid, entries=None, level_entries=None):
     """M' = B o ... o B (M), Eq. (15), merging equal (N, p, p') by max.
 
     Entry points are all top-level (p, p') (Sec. 3.3, "Merging
-    correspondences").  Returns a dict of arrays over the atomic tuples:
-    b, a (atomic lattice indices of p), qy, qx (pixel p' in I'), s (score),
-    margin (smallest pooling-argmax gap along the tuple's path)."""
+    correspondences"), or the tuples of `level_entries` (a dict level ->
+    (b, a, qy, qx, s, margin) arrays, `dmstar_entries`): those of the top
+    level start the expansion and those of each lower level join the tuples
+    that reach it before equal (N, p, p') merge.  Returns a dict of arrays
+    over the atomic tuples: b, a (atomic lattice indices of p), qy, qx (pixel
+    p' in I'), s (score), margin (smallest decision gap along the tuple's
+    path: pooling argmaxes, and the local-maximum test of its entry)."""
     W, H, lmax = pyr.W, pyr.H, pyr.lmax
     Gt = pyr.G[lmax]
-    if entries is None:
+    if level_entries is not None:
+        b, a, qy, qx, s, margin = (np.asarray(e) for e in level_entries[lmax])
+    elif entries is None:
         bb, aa = np.nonzero(Gt)
         ht, wt = pyr.h[lmax], pyr.w[lmax]
         qy, qx = np.meshgrid(np.arange(ht), np.arange(wt), indexing="ij")
@@ -549,8 +568,9 @@ def backtrack(pyr: Pyramid, entries=None):
         qx = np.tile(qx.ravel(), n)
     else:
         b, a, qy, qx = (np.asarray(e) for e in entries)
-    s = pyr.top[b, a, qy, qx].astype(np.float64)
-    margin = np.full(len(s), np.inf)
+    if level_entries is None:
+        s = pyr.top[b, a, qy, qx].astype(np.float64)
+        margin = np.full(len(s), np.inf)
     for lv in range(lmax, 0, -1):
         h, w = pyr.h[lv], pyr.w[lv]
         cy, cx = lattice_centres(lv, W, H)
@@ -568,12 +588,63 @@ def backtrack(pyr: Pyramid, entries=None):
             out["qx"].append(2 * rx + (k % 3 - 1))
             out["s"].append(s[ok] + pyr.Cp[lv - 1][cb, ca, ry, rx])   # Eq. (14)
             out["m"].append(np.minimum(margin[ok], risky(pyr.gap[lv - 1][cb, ca, ry, rx])))
+        if level_entries is not None:   # the entries of level lv - 1 join before the merge
+            for k, e in zip(("b", "a", "qy", "qx", "s", "m"), level_entries[lv - 1]):
+                out[k].append(np.asarray(e))
         b, a, qy, qx, s, margin = (np.concatenate(out[k]) for k in ("b", "a", "qy", "qx", "s", "m"))
         ny, nx = lattice_shape(lv - 1, W, H)
         key = ((b * nx + a) * pyr.h[lv - 1] + qy) * pyr.w[lv - 1] + qx
         keep, _ = _dedup_max(key, s)
         b, a, qy, qx, s, margin = b[keep], a[keep], qy[keep], qx[keep], s[keep], margin[keep]
     return dict(b=b, a=a, qy=qy, qx=qx, s=s, margin=margin)
+
+
+# ----------------------------------------------------------------------------
+# Entry points of the earlier DeepMatching (DM*, Sec. 3.3 and Table 1): local
+# maxima of the correlation maps of every level, scored by path sums (R24)
+# ----------------------------------------------------------------------------
+
+def local_maxima(M: np.ndarray):
+    """R24: the local maxima of maps M[..., h, w] over their 3 x 3
+    neighbourhoods (positions outside the map take no part): a positive value
+    not below any neighbour and above the neighbours that come before it in
+    raster order, so a plateau of equal values gives one maximum, at its
+    first position.  Returns the mask and the gap to the largest neighbour
+    (the decision's margin; inf without neighbours)."""
+    h, w = M.shape[-2:]
+    P = np.full(M.shape[:-2] + (h + 2, w + 2), -np.inf)
+    P[..., 1:1 + h, 1:1 + w] = M
+    mask = M > 0
+    top2 = np.full(M.shape, -np.inf)
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if dy == 0 and dx == 0:
+                continue
+            v = P[..., 1 + dy:1 + dy + h, 1 + dx:1 + dx + w]
+            mask &= (M > v) if (dy, dx) < (0, 0) else (M >= v)
+            top2 = np.maximum(top2, v)
+    return mask, M - top2
+
+
+def dmstar_entries(pyr: Pyramid):
+    """Entry tuples of every level (R24): the local maxima of the top maps
+    C_top, and of the pooled maps C'_l below the top, where pooled cell r of
+    patch p stands for the node (l, p, 2r + m_l(p, r)) (the position it was
+    pooled from) with score C'_l(p, r).  Returns {level: (b, a, qy, qx, s,
+    margin)}."""
+    out = {}
+    for lv in range(pyr.lmax + 1):
+        M = pyr.top if lv == pyr.lmax else pyr.Cp[lv]
+        mask, gap = local_maxima(np.nan_to_num(M, nan=-np.inf))
+        mask &= pyr.G[lv][..., None, None]
+        b, a, ry, rx = np.nonzero(mask)
+        if lv == pyr.lmax:
+            qy, qx = ry, rx
+        else:
+            k = pyr.code[lv][b, a, ry, rx].astype(np.int64)
+            qy, qx = 2 * ry + (k // 3 - 1), 2 * rx + (k % 3 - 1)
+        out[lv] = (b, a, qy, qx, M[b, a, ry, rx].astype(np.float64), risky(gap[b, a, ry, rx]))
+    return out
 
 
 # ----------------------------------------------------------------------------
@@ -626,7 +697,7 @@ def reciprocal(M: dict, W: int, H: int, W2: int, H2: int):
 def match_descriptors(D1: np.ndarray, D2: np.ndarray, prm: Params = Params()):
     """Descriptors -> pyramid -> backtracking -> reciprocal matches."""
     pyr = pyramid(D1, D2, prm)
-    M = backtrack(pyr)
+    M = backtrack(pyr, level_entries=dmstar_entries(pyr) if prm.entry_points else None)
     out, margin = reciprocal(M, pyr.W, pyr.H, pyr.W2, pyr.H2)
     return out, margin, pyr, M
 
@@ -788,19 +859,18 @@ def pyramid_backward(D1: np.ndarray, D2: np.ndarray, pyr: Pyramid, tie: float | 
     argmax) and the bottom correlation.  `pyr` must come from
     pyramid(..., keep_full=True).
 
-    With `tie` set, also returns two boolean masks shaped like D1 and D2: the
-    coordinates whose gradient passes a decision that a less precise
-    evaluation may take the other way (R14), and the list of those decisions
-    as (level, b, a, y, x): the pooled cell (y, x) of patch (b, a) at a level
-    below the top, or the top map's first maximum (y, x) at level lmax.  A decision is the top map's
-    maximum or a pooling argmax that carries gradient, and it is at risk when
-    a runner-up lies within tie * (1 + value) of the winner (exact ties
-    included, since an ulp of difference upstream can split them); every
-    candidate within that distance may then receive the gradient.  The flag
-    travels down the same adjoints as the gradient: rectification keeps the
-    position, the shifted average sends it to each child position, a pooled
-    cell sends it to its routed position, and the bottom correlation to the
-    16 pixels of patch p in D1 and the 4x4 support of position q in D2."""
+    With `tie` set, also returns R1, R2 shaped like D1 and D2 and the list of
+    risky decisions.  A decision (a pooling argmax that carries gradient, or
+    the top map's maximum) is risky when `pooling_stability` finds that a
+    less precise evaluation may take it the other way (R14); its gradient may
+    then land on any candidate within tie * (1 + value) of the winner.  R is
+    the magnitude of all such gradient, carried down the same adjoints as the
+    gradient itself (absolute values, every candidate of a risky decision
+    receiving the whole magnitude that reaches it), so it bounds how far each
+    coordinate's gradient moves when any set of risky decisions goes another
+    way.  Decisions are listed as (level, b, a, y, x): the pooled cell (y, x)
+    of patch (b, a) at a level below the top, or the top map's first maximum
+    (y, x) at level lmax."""
     if pyr.assign is not None:
         raise ValueError("the gradient is defined for the exact method only (no prototypes)")
     W, H, lmax, lam = pyr.W, pyr.H, pyr.lmax, pyr.lam
@@ -811,7 +881,7 @@ def pyramid_backward(D1: np.ndarray, D2: np.ndarray, pyr: Pyramid, tie: float | 
     dC = np.zeros_like(top)
     bb, aa = np.nonzero(G)
     dC.reshape(top.shape[0], top.shape[1], -1)[bb, aa, am[bb, aa]] = 1.0
-    flag = None
+    risk = None
     if tie is not None:
         unstable, tvid = pooling_stability(pyr, tie)
         mx = flat.max(-1, keepdims=True)
@@ -822,14 +892,15 @@ def pyramid_backward(D1: np.ndarray, D2: np.ndarray, pyr: Pyramid, tie: float | 
             tv = tvid.reshape(flat.shape)
             winner = np.take_along_axis(tv, am[..., None], axis=-1)
             at_risk = (near & ((flat < mx) | (tv != winner))).any(-1)
-        flag = (near & at_risk[..., None]).reshape(top.shape)
+        risk = (near & at_risk[..., None]).reshape(top.shape).astype(np.float64)
         w_top = top.shape[-1]
         decisions = [(lmax, int(b), int(a), int(am[b, a] // w_top), int(am[b, a] % w_top))
                      for b, a in zip(*np.nonzero(at_risk & G))]
     for lv in range(lmax, 0, -1):
         A = pyr.A[lv]
-        dA = np.where(A > 0, dC * lam * np.where(A > 0, A, 1.0) ** (lam - 1.0), 0.0)
-        dA[~pyr.G[lv]] = 0.0
+        fac = np.where(A > 0, lam * np.where(A > 0, A, 1.0) ** (lam - 1.0), 0.0)   # R_lambda'
+        fac[~pyr.G[lv]] = 0.0
+        dA = dC * fac
         # adjoint of the shifted average
         h, w = pyr.h[lv], pyr.w[lv]
         ny, nx = lattice_shape(lv - 1, W, H)
@@ -843,22 +914,25 @@ def pyramid_backward(D1: np.ndarray, D2: np.ndarray, pyr: Pyramid, tie: float | 
             ok &= pyr.G[lv - 1][cb, ca] & pyr.G[lv]
             cnt += ok
             links.append((ox, oy, cb, ca, ok))
-        fCp = np.zeros((ny, nx, h + 2, w + 2), dtype=bool) if flag is not None else None
+        if risk is not None:
+            rA = risk * fac
+            rCp = np.zeros((ny, nx, h + 2, w + 2))
         for ox, oy, cb, ca, ok in links:
             pb, pa = np.nonzero(ok)
             contrib = dA[pb, pa] / cnt[pb, pa][:, None, None]
             dCp[cb[pb, pa], ca[pb, pa], 1 + oy:1 + oy + h, 1 + ox:1 + ox + w] += contrib
-            if flag is not None:
-                fCp[cb[pb, pa], ca[pb, pa], 1 + oy:1 + oy + h, 1 + ox:1 + ox + w] |= flag[pb, pa]
+            if risk is not None:
+                rCp[cb[pb, pa], ca[pb, pa], 1 + oy:1 + oy + h, 1 + ox:1 + ox + w] += \
+                    rA[pb, pa] / cnt[pb, pa][:, None, None]
         dCp = dCp[:, :, 1:1 + h, 1:1 + w]
-        if flag is not None:
-            fCp = fCp[:, :, 1:1 + h, 1:1 + w]
+        if risk is not None:
+            rCp = rCp[:, :, 1:1 + h, 1:1 + w]
         if lv == 1:
             break   # dCp is the gradient of the pooled bottom maps C'_0
         dC = unpool_adjoint(dCp, pyr.code[lv - 1], pyr.h[lv - 1], pyr.w[lv - 1])
-        if flag is not None:
+        if risk is not None:
             below = rectify(np.nan_to_num(pyr.A[lv - 1], nan=0.0), lam)
-            flag, risky = unpool_flag(fCp, dCp, pyr.code[lv - 1], pyr.Cp[lv - 1], unstable[lv - 1], below, tie)
+            risk, risky = unpool_risk(rCp, dCp, pyr.code[lv - 1], pyr.Cp[lv - 1], unstable[lv - 1], below, tie)
             decisions += [(lv - 1, *map(int, t)) for t in zip(*np.nonzero(risky))]
     # adjoint of the bottom correlation, Eq. (3), over chunks of patch rows
     # (the bottom maps are full resolution; a chunk at a time bounds memory)
@@ -870,40 +944,37 @@ def pyramid_backward(D1: np.ndarray, D2: np.ndarray, pyr: Pyramid, tie: float | 
     D2p[2:2 + H2, 2:2 + W2] = D2
     dD1 = np.zeros_like(D1, dtype=np.float64)
     dD2p = np.zeros_like(D2p)
-    if flag is not None:
-        f1 = np.zeros(D1.shape, dtype=bool)
-        f2p = np.zeros(D2p.shape, dtype=bool)
+    if risk is not None:
+        R1 = np.zeros(D1.shape)
+        R2p = np.zeros(D2p.shape)
     chunk = ny0 if pyr.A[0] is not None else 4
     for r0 in range(0, ny0, chunk):
         rows = np.arange(r0, min(ny0, r0 + chunk))
         A0 = pyr.A[0][rows] if pyr.A[0] is not None else bottom_scores(D1, D2, rows)
         # gradient of C_0: the top's own (lmax = 0) or routed through the pool
         dC0 = dC[rows] if lmax == 0 else unpool_adjoint(dCp[rows], pyr.code[0][rows], H2, W2)
-        dA0 = np.where(A0 > 0, dC0 * lam * np.where(A0 > 0, A0, 1.0) ** (lam - 1.0), 0.0)
-        g = dA0.reshape(len(rows) * nx0, H2 * W2) / 16.0
+        fac0 = np.where(A0 > 0, lam * np.where(A0 > 0, A0, 1.0) ** (lam - 1.0), 0.0)
+        g = (dC0 * fac0).reshape(len(rows) * nx0, H2 * W2) / 16.0
         cy = 2 + 4 * rows
-        if flag is not None:
+        if risk is not None:
             if lmax == 0:
-                fl0 = flag[rows]
+                r0map = risk[rows]
             else:
-                fl0, risky = unpool_flag(fCp[rows], dCp[rows], pyr.code[0][rows], pyr.Cp[0][rows],
-                                         unstable[0][rows], rectify(A0, lam), tie)
+                r0map, risky = unpool_risk(rCp[rows], dCp[rows], pyr.code[0][rows], pyr.Cp[0][rows],
+                                           unstable[0][rows], rectify(A0, lam), tie)
                 decisions += [(0, int(b) + r0, *map(int, t)) for b, *t in zip(*np.nonzero(risky))]
-            # patch p: its 16 pixels in D1; position q: the 4x4 support q + delta in D2
-            hit = fl0.any(axis=(-2, -1))
-            anyq = fl0.any(axis=(0, 1))
-            for dy in (-2, -1, 0, 1):
-                for dx in (-2, -1, 0, 1):
-                    f1[np.ix_(cy + dy, cx + dx)] |= hit[..., None]
-                    f2p[2 + dy:2 + dy + H2, 2 + dx:2 + dx + W2] |= anyq[..., None]
+            rg = (r0map * fac0).reshape(len(rows) * nx0, H2 * W2) / 16.0
         for dy in (-2, -1, 0, 1):
             for dx in (-2, -1, 0, 1):
                 S = D2p[2 + dy:2 + dy + H2, 2 + dx:2 + dx + W2].reshape(-1, C)
                 P = D1[np.ix_(cy + dy, cx + dx)].reshape(-1, C)
                 dD1[np.ix_(cy + dy, cx + dx)] += (g @ S).reshape(len(rows), nx0, C)
                 dD2p[2 + dy:2 + dy + H2, 2 + dx:2 + dx + W2] += (g.T @ P).reshape(H2, W2, C)
-    if flag is not None:
-        return dD1, dD2p[2:2 + H2, 2:2 + W2], f1, f2p[2:2 + H2, 2:2 + W2], decisions
+                if risk is not None:
+                    R1[np.ix_(cy + dy, cx + dx)] += (rg @ np.abs(S)).reshape(len(rows), nx0, C)
+                    R2p[2 + dy:2 + dy + H2, 2 + dx:2 + dx + W2] += (rg.T @ np.abs(P)).reshape(H2, W2, C)
+    if risk is not None:
+        return dD1, dD2p[2:2 + H2, 2:2 + W2], R1, R2p[2:2 + H2, 2:2 + W2], decisions
     return dD1, dD2p[2:2 + H2, 2:2 + W2]
 
 
@@ -986,27 +1057,28 @@ def pooling_stability(pyr: Pyramid, tie: float):
         pid = np.where(unstable, marker, src)
 
 
-def unpool_flag(fCp: np.ndarray, dCp: np.ndarray, code: np.ndarray, best: np.ndarray, unstable: np.ndarray,
-                C: np.ndarray, tie: float) -> np.ndarray:
-    """The near-tie flag of `pyramid_backward` through S o P (Eqs. (8)-(9)):
-    a flagged pooled cell flags its routed position; an unstable cell
-    (`pooling_stability`) that carries gradient or a flag flags every
-    position of its window within tie * (1 + best) of the best (C: the map
-    below the pooling).  Returns the flags of that map and the mask of the
-    unstable cells that carry gradient or a flag."""
-    h, w = fCp.shape[-2:]
+def unpool_risk(rCp: np.ndarray, dCp: np.ndarray, code: np.ndarray, best: np.ndarray, unstable: np.ndarray,
+                C: np.ndarray, tie: float):
+    """The risk of `pyramid_backward` through S o P (Eqs. (8)-(9)): a stable
+    cell routes its risk to its argmax position; an unstable cell
+    (`pooling_stability`) that carries gradient or risk sends its whole
+    magnitude |gradient| + risk to every position of its window within
+    tie * (1 + best) of the best (C: the map below the pooling).  Returns the
+    risk of that map and the mask of those unstable cells."""
+    h, w = rCp.shape[-2:]
     hp, wp = C.shape[-2:]
-    out = unpool_adjoint(fCp.astype(np.float64), code, hp, wp) > 0
+    risky = ((rCp > 0) | (dCp != 0)) & unstable
+    out = unpool_adjoint(np.where(risky, 0.0, rCp), code, hp, wp)
+    mag = np.where(risky, np.abs(dCp) + rCp, 0.0)
     thr = best - tie * (1.0 + np.abs(best))
-    risky = (fCp | (dCp != 0)) & unstable
     Cpad = np.full(C.shape[:-2] + (hp + 3, wp + 3), -np.inf)
     Cpad[..., 1:1 + hp, 1:1 + wp] = C
-    opad = np.zeros(Cpad.shape, dtype=bool)
+    opad = np.zeros(Cpad.shape)
     for my in (-1, 0, 1):
         for mx in (-1, 0, 1):
             v = Cpad[..., 1 + my:1 + my + 2 * h:2, 1 + mx:1 + mx + 2 * w:2]
-            opad[..., 1 + my:1 + my + 2 * h:2, 1 + mx:1 + mx + 2 * w:2] |= risky & (v >= thr)
-    return out | opad[..., 1:1 + hp, 1:1 + wp], risky
+            opad[..., 1 + my:1 + my + 2 * h:2, 1 + mx:1 + mx + 2 * w:2] += np.where(v >= thr, mag, 0.0)
+    return out + opad[..., 1:1 + hp, 1:1 + wp], risky
 
 
 def unpool_adjoint(dCp: np.ndarray, code: np.ndarray, hp: int, wp: int) -> np.ndarray:
