@@ -174,6 +174,12 @@ def make_batch(n: int = 32, base_seed: int = 5000, max_disp: float = 30.0):
     return out
 
 
+def make_warp_pair(seed: int, w: int, h: int, max_disp: float = 30.0) -> dict:
+    """One pair of the uneven-batch recipe at a chosen size: c1-style content
+    warped by a smooth field of the given maximum displacement, plus noise."""
+    return _warp_pair(seed, w, h, max_disp, "noise", gain=False)
+
+
 def sub_pair(pair: dict, x0: int, y0: int, w: int, h: int) -> dict:
     """Crop both images of a pair to the same window."""
     return dict(img1=np.ascontiguousarray(pair["img1"][y0:y0 + h, x0:x0 + w]),

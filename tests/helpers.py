@@ -69,3 +69,27 @@ def within_px(gpu: np.ndarray, ref: np.ndarray, px: float = 1.0) -> float:
         if q is not None and max(abs(q[2] - r[2]), abs(q[3] - r[3])) <= px:
             ok += 1
     return ok / max(1, len(ref))
+
+
+# Ground truth of the warped pairs (c2): the oracle's own run puts 97.7 % of
+# its matches outside the periodic rectangle and the borders, and 95.5 % of
+# all its matches, within 1 px of the inverted field; these bounds leave a
+# margin below that run.
+GT_WITHIN_1PX_CLEAR = 0.95
+GT_WITHIN_1PX_ALL = 0.93
+
+
+def ground_truth_agreement(matches: np.ndarray, pair: dict, border: int = 16, margin: int = 8):
+    """Fractions of matches whose p' lies within 1 px (inf-norm) of the true
+    target of p (the pair's inverted displacement field): over all matches,
+    and over those whose p is at least `border` px inside I and `margin` px
+    away from the periodic rectangle (where the texture repeats every 8 px)."""
+    px, py = matches[:, 0], matches[:, 1]
+    qx, qy = pair["flow"](px, py)
+    ok = np.maximum(np.abs(matches[:, 2] - qx), np.abs(matches[:, 3] - qy)) <= 1.0
+    H, W = pair["img1"].shape
+    clear = (px >= border) & (px < W - border) & (py >= border) & (py < H - border)
+    if "periodic_rect" in pair["meta"]:
+        x0, y0, rw, rh = pair["meta"]["periodic_rect"]
+        clear &= ~((px >= x0 - margin) & (px < x0 + rw + margin) & (py >= y0 - margin) & (py < y0 + rh + margin))
+    return float(ok.mean()), float(ok[clear].mean()), int(clear.sum())

@@ -17,14 +17,18 @@ pytestmark = pytest.mark.gpu
 # FP32 against FP64 at 512x256.  An argmax (a pooling code or a top-map
 # maximum) whose candidates are closer than the FP32 rounding can be decided
 # the other way than in FP64 (the near-ties of the matching tests); the path
-# below it then carries its gradient to a neighbouring position, which moves
-# the gradient of the few descriptor entries around that position.  So the
-# sampled coordinates must agree to FP32 rounding except for at most
-# GRAD512_NEAR_TIES of them (0.4 % of the sample), and those few stay within
-# GRAD512_TOL_ALL of the sample's norm.  BF16 operands: within GRAD512_TOL_BF16.
-GRAD512_NEAR_TIES = 16
-GRAD512_TOL_FP32 = 1e-6
-GRAD512_TOL_ALL = 2e-2
+# below it then carries its gradient to another position.  The oracle bounds,
+# per coordinate, how far the gradient can move when such decisions go
+# another way (its near-tie risk R, stored with the sample), so every FP32
+# coordinate must lie within GRAD512_ROUND (relative to the largest entry) +
+# R of the oracle; only few may move beyond rounding at all, and the
+# coordinates the oracle finds out of every near-tie's reach (R below
+# GRAD512_CLEAR of the sample norm) agree within GRAD512_TOL_FP32.  BF16
+# operands: within GRAD512_TOL_BF16 overall.
+GRAD512_ROUND = 2e-6
+GRAD512_CLEAR = 1e-6
+GRAD512_MOVED = 0.02
+GRAD512_TOL_FP32 = 1e-4
 GRAD512_TOL_BF16 = 5e-2
 
 
@@ -171,9 +175,9 @@ def test_autograd_function():
 
 def test_gradient_at_512x256_against_stored_oracle_sample():
     """The gradient at the benchmark's 512x256 size, in the launch
-    configuration the benchmark times, against the FP64 oracle's gradient at
-    the coordinates stored by tests/golden/make_golden.py c3grad (a seeded
-    uniform sample plus the largest entries)."""
+    configuration the benchmark times, against the FP64 oracle's gradient and
+    near-tie risk at the coordinates stored by tests/golden/make_golden.py
+    c3grad (a seeded uniform sample plus the largest entries)."""
     import os
     from tests.golden.make_golden import grad_path_of, image_hash
     path = grad_path_of("c3")
@@ -189,13 +193,22 @@ def test_gradient_at_512x256_against_stored_oracle_sample():
         if prec == "fp32":
             assert abs(L - float(z["loss"])) <= 1e-5 * abs(float(z["loss"]))
         for k, g in (("1", g1), ("2", g2)):
-            got, ref = g.reshape(-1)[z["idx" + k]], z["val" + k]
+            got, ref, R = g.reshape(-1)[z["idx" + k]], z["val" + k], z["risk" + k]
             err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-            keep = np.argsort(-np.abs(got - ref))[GRAD512_NEAR_TIES:]
-            err_rest = float(np.linalg.norm(got[keep] - ref[keep]) / np.linalg.norm(ref[keep]))
-            print(f"512x256 {prec} dD{k}: {len(ref)} coordinates, relative error {err:.2e}, "
-                  f"{err_rest:.2e} without the {GRAD512_NEAR_TIES} largest differences", flush=True)
-            if prec == "fp32":
-                assert err_rest <= GRAD512_TOL_FP32 and err <= GRAD512_TOL_ALL
-            else:
+            if prec != "fp32":
+                print(f"512x256 {prec} dD{k}: {len(ref)} coordinates, relative error {err:.2e}", flush=True)
                 assert err <= GRAD512_TOL_BF16
+                continue
+            dev = np.abs(got - ref)
+            rnd = GRAD512_ROUND * np.abs(ref).max()
+            unexplained = dev > rnd + R * (1 + 1e-3)
+            moved = dev > rnd
+            clear = R <= GRAD512_CLEAR * np.linalg.norm(ref)
+            err_clear = float(np.linalg.norm(got[clear] - ref[clear]) / np.linalg.norm(ref[clear]))
+            print(f"512x256 fp32 dD{k}: {len(ref)} coordinates, relative error {err:.2e}; {int(moved.sum())} moved "
+                  f"beyond rounding (largest {dev.max():.2e}, its oracle risk {R[np.argmax(dev)]:.2e}), "
+                  f"{int(unexplained.sum())} beyond their risk; {int(clear.sum())} out of every near-tie's reach, "
+                  f"relative error {err_clear:.2e} there", flush=True)
+            assert not unexplained.any()
+            assert moved.mean() <= GRAD512_MOVED
+            assert clear.sum() >= 50 and err_clear <= GRAD512_TOL_FP32

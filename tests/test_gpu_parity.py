@@ -210,7 +210,7 @@ def test_match_images_end_to_end_c1():
     o = oracle_pair("c1")
     p = o["pair"]
     m = dm.match_images(cuda(p["img1"]), cuda(p["img2"]), dm.params(max_patch=32)).cpu().numpy()
-    r = compare_matches(m, o["out"], o["margin"], tie=1e-4, score_rtol=2e-5)
+    r = compare_matches(m, o["out"], o["margin"], tie=1e-4)
     report("c1 images", r)
     assert not r["missing"] and not r["moved"] and not r["bad_score"]
     x1, y1 = m[:, 0], m[:, 1]
@@ -259,6 +259,23 @@ def test_bf16_agreement(name):
     frac = within_px(gpu, o["out"], 1.0)
     print(f"{name} bf16: {len(gpu)} matches, {frac:.4f} of oracle matches within 1 px", flush=True)
     assert frac >= 0.99
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_warped_pair_recovers_the_ground_truth_field(prec):
+    """Images in, matches out on the 256x192 warped pair c2: the GPU's
+    matches follow the true displacement field as closely as the oracle's
+    (bounds set from the oracle's run; the oracle test holds it to them)."""
+    from tests.helpers import GT_WITHIN_1PX_ALL, GT_WITHIN_1PX_CLEAR, ground_truth_agreement
+    o = oracle_pair("c2")
+    p = o["pair"]
+    m = dm.match_images(cuda(p["img1"]), cuda(p["img2"]), dm.params(precision=prec, max_patch=64)).cpu().numpy()
+    fa, fc, n = ground_truth_agreement(m, p)
+    ra, rc, _ = ground_truth_agreement(o["out"], p)
+    print(f"c2 {prec}: {len(m)} matches, {fa:.4f} within 1 px of the true field ({fc:.4f} of {n} clear); "
+          f"oracle {ra:.4f} ({rc:.4f})", flush=True)
+    assert fc >= GT_WITHIN_1PX_CLEAR and fa >= GT_WITHIN_1PX_ALL
+    assert fc >= rc - 0.01 and fa >= ra - 0.01
 
 
 def bf16_round(a):
@@ -331,10 +348,10 @@ def test_full_size_512x256_against_stored_oracle(prec):
     m = m.cpu().numpy()
     assert pl.lmax == lmax
     if prec == "fp32":
-        r = compare_matches(m, ref, margin, tie=1e-4, score_rtol=2e-5)
+        r = compare_matches(m, ref, margin, tie=1e-4)
         report("c3 fp32", r)
         assert not r["missing"] and not r["moved"] and not r["bad_score"]
-        assert len(r["extra"]) <= max(3, r["near_ties"])
+        assert len(r["extra"]) <= r["near_ties"]
     else:
         frac = within_px(m, ref, 1.0)
         exact = within_px(m, ref, 0.0)
