@@ -21,6 +21,12 @@
  *    waiting; results are ready once the stream has reached that point.
  *    Arguments are validated on the host before anything is enqueued; on an
  *    error nothing is enqueued and dm_last_error() describes the problem.
+ *  - Output capacity: the match count n_out lives in device memory and is
+ *    written by the enqueued work, so an insufficient capacity is reported
+ *    by DM_ERR_CAPACITY alone (nothing is enqueued, n_out is untouched); the
+ *    required capacity is plan.max_matches (info.max_matches for invariant
+ *    matching), known on the host from dm_plan / dm_plan_invariant before
+ *    any call, and dm_last_error() repeats it.
  *  - The library keeps no state between calls other than the thread-local
  *    error text, the per-stage timing records (when enabled) and, for
  *    dm_match_batch, one cached batch schedule per workspace (job tables,
@@ -87,8 +93,24 @@ typedef struct {
     int32_t precision;          /* dm_precision */
     int32_t prototypes;         /* D of approximate DeepMatching, 0 = exact     */
     int32_t kmeans_iters;       /* k-means rounds (prototypes > 0), 0..1000     */
-    int32_t reserved[5];        /* must be 0 */
+    int32_t entry_points;       /* DM_ENTRIES_TOP or DM_ENTRIES_LOCAL_MAXIMA    */
+    int32_t reserved[4];        /* must be 0 */
 } dm_params;
+
+/* Entry points of the backtracking (Sec. 3.3, "Merging correspondences").
+ * DM_ENTRIES_TOP: every position of every top-level map (the method of the
+ * paper).  DM_ENTRIES_LOCAL_MAXIMA: the earlier scheme compared in Sec. 5
+ * (Table 1, "DM*"), here with the current path-sum scores: the local maxima
+ * of the maps of every level start backtracking paths.  The maps are C_top
+ * and the pooled C'_l below it (a pooled cell stands for the position it was
+ * pooled from, with its value as the entry's score); a local maximum is
+ * positive, not below any of its 3 x 3 neighbours inside the map and above
+ * those before it in raster order (one per plateau).  Tuples from above and
+ * entries merge by max at equal (N, p, p').  Matching entry points only
+ * (dm_match_images / dm_match_descriptors), exact method, N_max >= 8; in the
+ * workspace, bit 4 of a code (off_code[l]) then marks the entries of C'_l. */
+#define DM_ENTRIES_TOP 0
+#define DM_ENTRIES_LOCAL_MAXIMA 1
 
 /* One correspondence: atomic patch centre p = (x1, y1) in I, pixel
  * p' = (x2, y2) in I', score s = the top-level value plus the pooled child
@@ -263,7 +285,7 @@ typedef struct {
     int32_t cp_in_saved[DM_MAX_LEVELS];
     uint64_t off_top;          /* in `saved` */
     uint64_t off_valid, off_bf1, off_bf2, off_g[2], off_part, off_t;  /* in `scratch` */
-    uint64_t off_dense;        /* in `scratch`: dense dA_0 and patch matrix of the bottom GEMMs */
+    uint64_t off_dense;        /* in `scratch`: operands of the bottom GEMMs (D2 im2col, D1 patches) */
 } dm_grad_plan;
 
 /* Plans dm_pyramid_forward / dm_pyramid_backward for a pair of sizes.

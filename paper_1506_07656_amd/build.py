@@ -21,6 +21,9 @@ FLAGS = [
     # Keep the compiler from emitting packed FP32 arithmetic.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     f"-I{INCLUDE}", f"-I{CSRC}",
+    # Bounds-checked standard containers in host code: an index out of range
+    # aborts on the host in the CPU tests rather than corrupting memory.
+    "-D_GLIBCXX_ASSERTIONS",
 ]
 
 

@@ -108,6 +108,12 @@ dm_status dm::run_match(const float* d1, const float* d2, const dm_plan_info& pi
     for (int l = 1; l <= pi.lmax; ++l)
         DM_LAUNCH("level", l, launch_level<float>(l, cp(l - 1), vt, g, lam, l < pi.lmax ? cp(l) : nullptr,
                                                   l < pi.lmax ? code(l) : nullptr, top, s));
+    // DM* entry points: the local maxima of every pooled level (the top's are
+    // tested during its backtracking step).
+    if (prm->entry_points == DM_ENTRIES_LOCAL_MAXIMA) {
+        g.dmstar = 1;
+        for (int l = 0; l < pi.lmax; ++l) DM_LAUNCH("mark_entries", l, launch_mark_entries(l, cp(l), code(l), vt, g, s));
+    }
     // a3 + a4: backtracking, bottom reduction, reciprocal check, compaction.
     uint64_t* best = rect ? rbest : at<uint64_t>(ws, pi.off_best);
     uint64_t* cell = rect ? rcell : at<uint64_t>(ws, pi.off_cell);
@@ -229,6 +235,30 @@ dm_status grad_backward(const T* d1, const T* d2, const dm_grad_plan& gp, const 
 
 }  // namespace
 
+// dm_match_images on the workspace ws (validated here; the caller has
+// cleared the error text).
+dm_status dm::match_images(const float* img1, int W1, int H1, int ld1, const float* img2, int W2, int H2, int ld2,
+                           const dm_params* prm, void* ws, size_t ws_bytes, dm_match* out, int capacity,
+                           int* n_out, hipStream_t stream) {
+    dm_plan_info pi;
+    dm_status st = plan_pair(prm, W1, H1, W2, H2, &pi);
+    if (st != DM_OK) return st;
+    if (!img1 || !img2) return fail(DM_ERR_INVALID_ARG, "image pointer is null");
+    if (ld1 < W1 || ld2 < W2) return fail(DM_ERR_SHAPE, "leading dimension below the width");
+    if ((st = check_ws(pi, ws, ws_bytes)) != DM_OK) return st;
+    if ((st = check_out(pi, out, capacity, n_out)) != DM_OK) return st;
+    if (prm->precision == DM_FP64) return fail(DM_ERR_UNSUPPORTED, "matching runs in FP32 or BF16");
+    const DescParams dp = make_desc_params(prm);
+    float* d1 = at<float>(ws, pi.off_desc1);
+    float* d2 = at<float>(ws, pi.off_desc2);
+    const bool bf = prm->precision == DM_BF16;
+    hipStream_t s = stream;
+    DM_LAUNCH("descriptor", -1,
+              launch_descriptor_pair(img1, W1, H1, ld1, d1, bf ? at<uint16_t>(ws, pi.off_bf1) : nullptr, img2, W2, H2,
+                                     ld2, d2, bf ? at<uint16_t>(ws, pi.off_bf2) : nullptr, dp, s));
+    return run_match(d1, d2, pi, prm, ws, bf, out, n_out, stream);
+}
+
 extern "C" {
 
 dm_status dm_plan_grad(const dm_params* prm, int W1, int H1, int W2, int H2, int recompute, dm_grad_plan* out) {
@@ -321,23 +351,7 @@ dm_status dm_match_images(const float* img1, int W1, int H1, int ld1, const floa
                           const dm_params* prm, void* ws, size_t ws_bytes, dm_match* out, int capacity,
                           int* n_out, hipStream_t stream) {
     clear_error();
-    dm_plan_info pi;
-    dm_status st = plan_pair(prm, W1, H1, W2, H2, &pi);
-    if (st != DM_OK) return st;
-    if (!img1 || !img2) return fail(DM_ERR_INVALID_ARG, "image pointer is null");
-    if (ld1 < W1 || ld2 < W2) return fail(DM_ERR_SHAPE, "leading dimension below the width");
-    if ((st = check_ws(pi, ws, ws_bytes)) != DM_OK) return st;
-    if ((st = check_out(pi, out, capacity, n_out)) != DM_OK) return st;
-    if (prm->precision == DM_FP64) return fail(DM_ERR_UNSUPPORTED, "matching runs in FP32 or BF16");
-    const DescParams dp = make_desc_params(prm);
-    float* d1 = at<float>(ws, pi.off_desc1);
-    float* d2 = at<float>(ws, pi.off_desc2);
-    const bool bf = prm->precision == DM_BF16;
-    hipStream_t s = stream;
-    DM_LAUNCH("descriptor", -1,
-              launch_descriptor_pair(img1, W1, H1, ld1, d1, bf ? at<uint16_t>(ws, pi.off_bf1) : nullptr, img2, W2, H2,
-                                     ld2, d2, bf ? at<uint16_t>(ws, pi.off_bf2) : nullptr, dp, s));
-    return run_match(d1, d2, pi, prm, ws, bf, out, n_out, stream);
+    return match_images(img1, W1, H1, ld1, img2, W2, H2, ld2, prm, ws, ws_bytes, out, capacity, n_out, stream);
 }
 
 const char* dm_status_string(dm_status s) {

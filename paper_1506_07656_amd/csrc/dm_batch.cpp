@@ -15,6 +15,7 @@
 // per CU of each grouped launch, one parameter at a time (each stage can be
 // re-run on its own: it rewrites its outputs from inputs that stay put, and
 // the bottom reduction takes maxima, so a re-run leaves the same values).
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -130,6 +131,7 @@ dm_status plan_pairs(int n, const dm_pair* pairs, const dm_params* prm, int flag
     if (st != DM_OK) return st;
     if (prm->precision == DM_FP64) return fail(DM_ERR_UNSUPPORTED, "batches run in DM_FP32 or DM_BF16");
     if (prm->prototypes) return fail(DM_ERR_UNSUPPORTED, "batches run the exact method (prototypes = 0)");
+    if (prm->entry_points) return fail(DM_ERR_UNSUPPORTED, "batches start from every top-level position");
     P.assign(n, PairLayout());
     uint64_t off = 0;
     for (int k = 0; k < n; ++k) {
@@ -286,16 +288,19 @@ void build(int n, const dm_pair* pairs, const dm_params* prm, int flags, const s
         }
         B.stage("bwd_level", l, J, false);
     }
-    std::vector<std::vector<JobRec>> bot(7);
+    // the stages of bot_jobs, in its order
+    static const char* const names[] = {"bwd_d2col", "bwd_pt", "bwd_dd1_gemm", "bwd_t_gemm", "bwd_dd1_reduce",
+                                        "bwd_col2im"};
+    constexpr size_t nst = sizeof(names) / sizeof(names[0]);
+    std::vector<std::vector<JobRec>> bot(nst);
     for (int k = 0; k < n; ++k) {
         std::vector<JobRec> r = bot_jobs(bf, gbuf(k, 0), code(k, 0), d1(k), d2(k), G[k], at<float>(S(k), P[k].gp.off_part),
                                          at<float>(S(k), P[k].gp.off_t), at<void>(S(k), P[k].gp.off_dense),
                                          pairs[k].dd1, pairs[k].dd2);
-        for (int i = 0; i < 7; ++i) bot[i].push_back(r[i]);
+        if (r.size() != nst) abort();   // bot_jobs and this list must agree
+        for (size_t i = 0; i < nst; ++i) bot[i].push_back(r[i]);
     }
-    static const char* names[7] = {"bwd_da",       "bwd_d2col",      "bwd_pt",    "bwd_dd1_gemm",
-                                   "bwd_t_gemm", "bwd_dd1_reduce", "bwd_col2im"};
-    for (int i = 0; i < 7; ++i) B.stage(names[i], 0, bot[i], false);
+    for (size_t i = 0; i < nst; ++i) B.stage(names[i], 0, bot[i], false);
 }
 
 struct Schedule {

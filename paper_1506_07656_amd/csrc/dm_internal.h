@@ -58,6 +58,7 @@ struct Geom {
     const int32_t* slot0;
     int nslot0;
     RectMap rect;   // invariant matching: the run's map back to the input images
+    int dmstar;     // entry points at the local maxima of every level (bit 4 of the codes marks them)
 };
 
 // Map index, in the level l-1 buffer, of child lattice index c of a level-l
@@ -146,8 +147,6 @@ enum JobKind : int {
     JK_TOP_GRAD,
     JK_BWD_LEVEL,
     JK_BWD_LEVEL_STREAM,
-    JK_BWD_DA_BF16,
-    JK_BWD_DA_F32,
     JK_PATCH_BF16,
     JK_PATCH_F32,
     JK_D2COL_BF16,
@@ -254,6 +253,12 @@ dm_status run_match(const float* d1, const float* d2, const dm_plan_info& pi, co
 // Opt-in stage timing (dm_timing.cpp); calls may nest.
 void timing_begin(const char* name, int level, hipStream_t s);
 void timing_end(hipStream_t s);
+// While suppressed (counted per thread), launches of this thread record no events.
+void timing_suppress(bool on);
+// dm_match_images on a given workspace (validates everything but clears no error text).
+dm_status match_images(const float* img1, int W1, int H1, int ld1, const float* img2, int W2, int H2, int ld2,
+                       const dm_params* prm, void* ws, size_t ws_bytes, dm_match* out, int capacity, int* n_out,
+                       hipStream_t stream);
 
 // Kernel launchers (each returns the launch status).
 hipError_t launch_valid_init(const Geom& g, uint8_t* vt, hipStream_t s);
@@ -276,13 +281,16 @@ template <typename T>
 hipError_t launch_level(int l, const T* prev, const uint8_t* vt, const Geom& g, T lam, T* cp,
                         uint8_t* code, T* top, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s);
+// Marks (bit 4 of the code) the local maxima of the pooled maps C'_l (DM* entry points).
+hipError_t launch_mark_entries(int l, const float* cp, uint8_t* code, const uint8_t* vt, const Geom& g,
+                               hipStream_t s);
 template <typename T>
 hipError_t launch_bwd_level(int l, const T* dtop, const T* top, const T* gp_cur, const uint8_t* code_cur,
                             const T* cp_prev, const uint8_t* vt, const Geom& g, T lam, T* gp_prev, hipStream_t s,
                             bool out16 = false);
 // mode 0: FP32 MFMA, 1: BF16 MFMA operands with FP32 accumulation (then the pooled gradient gp is
 // stored as BF16: the level-1 adjoint writes it with out16), 2: reference kernels (any T)
-// dense: scratch of bwd_dense_bytes() for the dense dA_0 and the patch matrix (modes 0, 1)
+// dense: scratch of bwd_dense_bytes() for the GEMM operands built from D1 and D2 (modes 0, 1)
 template <typename T>
 hipError_t launch_bwd_bottom(int mode, const T* gp, const uint8_t* code, const T* d1, const T* d2, const Geom& g,
                              T* part, T* tbuf, void* dense, T* dd1, T* dd2, hipStream_t s);

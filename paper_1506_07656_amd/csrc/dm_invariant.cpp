@@ -72,6 +72,7 @@ dm_status plan_invariant(const dm_params* prm, int W1, int H1, int W2, int H2, u
     if (st != DM_OK) return st;
     if (prm->precision == DM_FP64) return fail(DM_ERR_UNSUPPORTED, "invariant matching runs in FP32 or BF16");
     if (prm->prototypes) return fail(DM_ERR_UNSUPPORTED, "invariant matching runs the exact method (prototypes = 0)");
+    if (prm->entry_points) return fail(DM_ERR_UNSUPPORTED, "invariant matching starts from every top-level position");
     if (!smask || (smask & ~0x1FFu)) return fail(DM_ERR_INVALID_ARG, "scales_mask must be a non-empty subset of 0x1FF");
     if (!rmask || (rmask & ~0xFFu)) return fail(DM_ERR_INVALID_ARG, "rotations_mask must be a non-empty subset of 0xFF");
     if (W1 < 4 || H1 < 4) return fail(DM_ERR_SHAPE, "image 1 is %dx%d; it must hold one 4x4 patch", W1, H1);

@@ -52,6 +52,8 @@ dm_status check_params(const dm_params* p) {
         return fail(DM_ERR_INVALID_ARG, "prototypes must be in [0, %d]", DM_MAX_PROTOTYPES);
     if (p->kmeans_iters < 0 || p->kmeans_iters > 1000)
         return fail(DM_ERR_INVALID_ARG, "kmeans_iters must be in [0, 1000]");
+    if (p->entry_points != DM_ENTRIES_TOP && p->entry_points != DM_ENTRIES_LOCAL_MAXIMA)
+        return fail(DM_ERR_INVALID_ARG, "entry_points must be DM_ENTRIES_TOP or DM_ENTRIES_LOCAL_MAXIMA");
     for (int r : p->reserved)
         if (r != 0) return fail(DM_ERR_INVALID_ARG, "reserved fields must be 0");
     return DM_OK;
@@ -121,6 +123,10 @@ dm_status plan_pair(const dm_params* prm, int W1, int H1, int W2, int H2, dm_pla
         if (lmax == 0)
             return fail(DM_ERR_UNSUPPORTED, "approximate matching needs a pooled level (N_max >= 8)");
     }
+    if (prm->entry_points == DM_ENTRIES_LOCAL_MAXIMA) {
+        if (D > 0) return fail(DM_ERR_UNSUPPORTED, "local-maxima entry points run the exact method (prototypes = 0)");
+        if (lmax == 0) return fail(DM_ERR_UNSUPPORTED, "local-maxima entry points need a pooled level (N_max >= 8)");
+    }
     out->lmax = lmax;
     out->N_max = 4 << lmax;
     out->n_atomic = g0x * g0y;
@@ -189,6 +195,7 @@ dm_status plan_grad(const dm_params* prm, int W1, int H1, int W2, int H2, int re
     if (st != DM_OK) return st;
     if (pi.lmax == 0) return fail(DM_ERR_UNSUPPORTED, "the pyramid has a single level; nothing to route a gradient through");
     if (prm->prototypes) return fail(DM_ERR_UNSUPPORTED, "the gradient is that of the exact method (prototypes = 0)");
+    if (prm->entry_points) return fail(DM_ERR_UNSUPPORTED, "entry points concern matching, not the gradient");
     // The bottom GEMMs address the pooled gradient of 128 patches from one
     // 32-bit buffer offset.
     if (prm->precision != DM_FP64 && (uint64_t)128 * pi.h[1] * pi.w[1] * 4 >= (uint64_t(1) << 31))

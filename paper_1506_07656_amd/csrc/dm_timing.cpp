@@ -19,6 +19,7 @@ struct Rec {
 
 std::mutex g_mu;
 bool g_on = false;
+thread_local int g_suppressed = 0;   // calls on this thread that must create no events
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 std::vector<int> g_open;
@@ -45,7 +46,10 @@ void recycle_all() {
 
 }  // namespace
 
+void timing_suppress(bool on) { g_suppressed += on ? 1 : -1; }
+
 void timing_begin(const char* name, int level, hipStream_t s) {
+    if (g_suppressed) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) return;
     Rec r{name, level, take_event(), take_event()};
@@ -55,6 +59,7 @@ void timing_begin(const char* name, int level, hipStream_t s) {
 }
 
 void timing_end(hipStream_t s) {
+    if (g_suppressed) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on || g_open.empty()) return;
     const int i = g_open.back();

@@ -45,9 +45,31 @@ __device__ inline int xcd_block(int nblocks) {
     return (blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
+// Local maximum of a map (DM* entry points): positive, not below any 3 x 3
+// neighbour inside the h x w map, above the neighbours before it in raster
+// order (one maximum per plateau).
+__device__ inline bool local_max(const float* __restrict__ m, int h, int w, int y, int x) {
+    const float v = m[(size_t)y * w + x];
+    if (!(v > 0.f)) return false;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int yy = y + dy, xx = x + dx;
+            if ((dy == 0 && dx == 0) || yy < 0 || yy >= h || xx < 0 || xx >= w) continue;
+            const float n = m[(size_t)yy * w + xx];
+            if (dy < 0 || (dy == 0 && dx < 0) ? !(v > n) : !(v >= n)) return false;
+        }
+    return true;
+}
+
+constexpr uint8_t kEntryBit = 0x10;   // DM*: the pooled cell is an entry point (above the 4-bit code)
+
 // RECT: a run of invariant matching; the bottom step maps each tuple back to
 // the input images and reduces into the tables shared by all runs.
-template <bool RECT>
+// DMSTAR: entry points at the local maxima of every level (codes carry
+// kEntryBit): a top position enters only at a local maximum, and a pooled
+// cell marked as an entry starts a tuple with its own value where no tuple
+// arrives from above (one that arrives scores at least as much).
+template <bool RECT, bool DMSTAR = false>
 __device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_prev,
                                const uint8_t* __restrict__ code_prev, const float* __restrict__ u_cur,
                                const uint8_t* __restrict__ code_cur, const float* __restrict__ top,
@@ -105,7 +127,8 @@ __device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_pre
                     const int par = sPar[ks];
                     const int ty = fdiv(rem, a.f_tc);
                     const int qy = R0 + ty - sy, qx = C0 + rem - ty * a.TC - sx;
-                    if (par >= 0 && qy >= 0 && qy < a.h && qx >= 0 && qx < a.w)
+                    if (par >= 0 && qy >= 0 && qy < a.h && qx >= 0 && qx < a.w &&
+                        (!DMSTAR || local_max(top + (size_t)par * a.h * a.w, a.h, a.w, qy, qx)))
                         v[u] = enc(top[((size_t)par * a.h + qy) * a.w + qx]);
                 }
             }
@@ -139,7 +162,7 @@ __device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_pre
                 if (ry < 0 || ry >= a.hu || rx < 0 || rx >= a.wu) continue;
                 const size_t o = ((size_t)par * a.hu + ry) * a.wu + rx;
                 uv[u] = u_cur[o];
-                m[u] = code_cur[o];
+                m[u] = code_cur[o] & (DMSTAR ? 15 : 255);
                 const int qy = 2 * ry + m[u] / 3 - 1, qx = 2 * rx + m[u] % 3 - 1;
                 const int ty = qy - qy0, tx = qx - qx0;   // tile index of r = q + o_i
                 if (ty >= 0 && ty < a.TR && tx >= 0 && tx < a.TC) idx[u] = (ks * a.TR + ty) * a.TC + tx;
@@ -176,7 +199,12 @@ __device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_pre
 #pragma unroll
             for (int side = 0; side < 4; ++side) vb[u] = max(vb[u], sV[((k * 4 + side) * a.TR + ty) * a.TC + tx]);
             off[u] = ((size_t)child_slot(g, a.l, cblk * a.CB + k) * a.h + ry) * a.w + rx;
-            if (vb[u] || !a.is_bottom) {
+            if constexpr (DMSTAR) {
+                const int cm = code_prev[off[u]];
+                if (!vb[u] && (cm & kEntryBit)) vb[u] = enc(0.f);   // an entry: its own value, nothing above
+                mv[u] = cm & 15;
+                if (vb[u] || !a.is_bottom) cpv[u] = cp_prev[off[u]];
+            } else if (vb[u] || !a.is_bottom) {
                 cpv[u] = cp_prev[off[u]];
                 if (a.is_bottom) mv[u] = code_prev[off[u]];
             }
@@ -629,7 +657,7 @@ __device__ inline void valid_body(const Geom& g, uint8_t* __restrict__ vt) {
     }
 }
 
-template <bool RECT>
+template <bool RECT, bool DMSTAR = false>
 __global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __restrict__ cp_prev,
                                                    const uint8_t* __restrict__ code_prev,
                                                    const float* __restrict__ u_cur,
@@ -640,7 +668,21 @@ __global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __rest
                                                    unsigned long long* __restrict__ cell, int nblocks) {
     const int bid = xcd_block(nblocks);
     if (bid >= nblocks) return;
-    bt_body<RECT>(a, cp_prev, code_prev, u_cur, code_cur, top, vt, g, u_prev, best, cell, bid);
+    bt_body<RECT, DMSTAR>(a, cp_prev, code_prev, u_cur, code_cur, top, vt, g, u_prev, best, cell, bid);
+}
+
+// DM* entry points: kEntryBit on the codes of the local maxima of C'_l (maps
+// of existing patches only).
+__global__ void k_mark_entries(const float* __restrict__ cp, uint8_t* __restrict__ code,
+                               const uint8_t* __restrict__ vt, Geom g, int l) {
+    const int h = g.h[l + 1], w = g.w[l + 1];
+    const size_t pm = (size_t)h * w, n = (size_t)g.gx[l] * g.gy[l] * pm;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = (int)(i / pm), r = (int)(i - (size_t)c * pm), y = r / w, x = r - y * w;
+    const int cb = c / g.gx[l], ca = c - cb * g.gx[l];
+    if (!vtab(vt, g, l, 0)[ca] || !vtab(vt, g, l, 1)[cb]) return;
+    if (local_max(cp + (size_t)c * pm, h, w, y, x)) code[i] |= kEntryBit;
 }
 
 template <bool RECT, int TILE, bool BOTTOM>
@@ -820,7 +862,7 @@ template <>
 hipError_t launch_backtrack<float>(int l, const float* cp_prev, const uint8_t* code_prev, const float* u_cur,
                                    const uint8_t* code_cur, const float* top, const uint8_t* vt, const Geom& g,
                                    float* u_prev, uint64_t* best, uint64_t* cell, hipStream_t s) {
-    if (use_bt_stream(l, g)) {
+    if (!g.dmstar && use_bt_stream(l, g)) {
         int nb;
         const BtStreamArgs b = make_bt_stream_args(l, g, kBtTR, nb);
         auto* b64 = (unsigned long long*)best;
@@ -846,7 +888,10 @@ hipError_t launch_backtrack<float>(int l, const float* cp_prev, const uint8_t* c
     size_t smem;
     const BtArgs a = make_bt_args(l, g, nblocks, smem);
     const dim3 grid(((nblocks + 7) / 8) * 8);
-    if (g.rect.on)
+    if (g.dmstar)
+        hipLaunchKernelGGL((k_backtrack<false, true>), grid, dim3(256), smem, s, a, cp_prev, code_prev, u_cur,
+                           code_cur, top, vt, g, u_prev, (unsigned long long*)best, (unsigned long long*)cell, nblocks);
+    else if (g.rect.on)
         hipLaunchKernelGGL(k_backtrack<true>, grid, dim3(256), smem, s, a, cp_prev, code_prev, u_cur, code_cur, top,
                            vt, g, u_prev, (unsigned long long*)best, (unsigned long long*)cell, nblocks);
     else
@@ -950,6 +995,14 @@ hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s) {
     if (!n) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (unsigned long long*)p, n,
                        (unsigned long long)v);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_entries(int l, const float* cp, uint8_t* code, const uint8_t* vt, const Geom& g,
+                               hipStream_t s) {
+    const size_t n = (size_t)g.gx[l] * g.gy[l] * g.h[l + 1] * g.w[l + 1];
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_mark_entries, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cp, code, vt, g, l);
     return hipGetLastError();
 }
 

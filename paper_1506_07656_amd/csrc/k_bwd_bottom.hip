@@ -9,20 +9,27 @@
 //   dD2[y][c]         = 1/16 sum_{dy,dx} T[(d, c)][y - d]               (col2im)
 // Atomic patches do not overlap, so GEMM 1 writes each D1 pixel once.
 //
-// Matrix-core path (FP32 or BF16 operands, FP32 accumulation):
-//  - dA_0 is written once, densely, by a gather over the <= 4 candidates in
-//    a fixed order (deterministic), as a [Pp][Xp] array: target positions on
-//    an H2p x Wp grid (width rounded up to 8, so rows of 8 values are
-//    16-byte aligned, height up to 16, so Xp is a multiple of 128), patches padded to Pp
-//    (a multiple of 128); padding entries are 0, so GEMM tiles never check
-//    bounds.
-//  - GEMM 1 (M = patches, N = 144, K = positions, split over K) and GEMM 2
-//    (M = 144, N = positions, K = patches) read operands that are contiguous
-//    along K: dA_0 rows, the transposed im2col of D2 ([144][Xp], built once)
-//    and the transposed patch matrix of D1 ([144][Pp], built once).  GEMM 2
-//    needs dA_0 along patches: 8 x 8 blocks are transposed in registers on
-//    their way into LDS.  Tiles go through LDS with the next chunk's loads in
-//    flight.  Split partial sums are added in a fixed order.
+// Matrix-core path (FP32 or BF16 operands, FP32 accumulation): dA_0 never
+// goes to memory.  Every GEMM tile stages the pooled cells (g'_0 and codes)
+// its dA_0 block depends on into LDS and gathers the block there: a 2 x 2
+// square of target positions (2t + i, 2u + e) receives only from the pooled
+// cells (t, u), (t, u + 1), (t + 1, u), (t + 1, u + 1), each of which sends
+// its value to the one position its code names, so every dA_0 entry is the
+// sum of at most four staged values, added in the fixed order of (row,
+// column) of the cell (deterministic).  Target positions live on a padded
+// Hp x Wp grid (Wp = W' rounded up to 64, Hp = H' rounded up to 4): padding
+// positions receive nothing (the forward pool never selects a position
+// outside I') and read zero descriptors, so tiles never check bounds.
+//  - GEMM 1 (M = 128 patches, N = 144, K = positions split over blocks): a
+//    K chunk is 2 position rows x CW columns; the im2col operand of D2 is
+//    stored transposed ([144][positions]) in that chunk order, contiguous
+//    along K.
+//  - GEMM 2 (M = 144, N = a tile of 4 position rows x 32 columns, K =
+//    patches): the dA_0 chunk is gathered straight into LDS as
+//    [position][patch]; the transposed patch matrix of D1 ([144][Pp]) is
+//    copied as it is.
+// Loads of the next chunk are in flight during the matrix-core work; split
+// partial sums are added in a fixed order.
 //
 // Reference kernels (thread per output, direct loops) serve the FP64
 // instantiation used by the finite-difference check.
@@ -41,7 +48,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 struct BotArgs {
     int W1, H1, W2, H2, n0x, natom, h1, w1;
-    int Wp, H2p, Xp, Pp;   // padded dense layout (matrix-core path)
+    int Wp, H2p, Xp, Pp;   // padded target grid and patch count (matrix-core path)
 };
 
 // dA_0(p, x) from the pooled gradient and codes of patch p (maps h1 x w1).
@@ -106,189 +113,208 @@ __device__ inline void store8(E* dst, const float v[8]) {
     }
 }
 
-// ---------------------------------------------------------------- dense dA_0
-// Block: one patch x 32 target rows x 256 target columns of the padded grid,
-// accumulated in LDS.  Each pooled entry (ry, rx) sends its gradient to the
-// one position its code names, (2 ry + my, 2 rx + mx); entries with the same
-// parities of ry and rx never name the same position, so the four parity
-// classes are added in four passes, in a fixed order, without atomics
-// (deterministic).  Codes never name positions outside I' (the forward pool
-// never selects one), so the padding of the grid stays 0.  A thread owns a
-// 2 x 2 quad of pooled entries per round; then the tile leaves as rows of 8
-// values (16 bytes in BF16).
-constexpr int DA_ROWS = 32, DA_COLS = 256;
-constexpr int DA_QR = DA_ROWS / 4 + 1, DA_QC = DA_COLS / 4 + 1;   // quads reaching the tile
-constexpr int DA_NQ = DA_QR * DA_QC, DA_ROUNDS = (DA_NQ + 255) / 256;
-constexpr int kOOB = 0x7ffffff0;                                   // buffer byte offset past any map
+constexpr int kPadW = 64, kPadH = 4;   // target grid padding (columns, rows)
+
+// ---------------------------------------------------------------- staging and gather
+constexpr int kOOB = 0x7ffffff0;   // buffer byte offset past any map
 
 __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t nbytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
 }
 
-template <typename E>
-__device__ __forceinline__ void bwd_da_body(const float* __restrict__ gp, const uint8_t* __restrict__ code, const BotArgs& a,
-                                   int nct, E* __restrict__ dA, int bid) {
-    __shared__ __align__(16) float sT[DA_ROWS][DA_COLS];
-    const int tid = threadIdx.x;
-    const int nband = (a.H2p + DA_ROWS - 1) / DA_ROWS;
-    const int ct = bid % nct, rest = bid / nct, band = rest % nband, p = rest / nband;
-    const int Y0 = band * DA_ROWS, X0 = ct * DA_COLS;
-    const int ry0 = Y0 >> 1, rx0 = X0 >> 1;
-    const uint32_t pm = (uint32_t)a.h1 * a.w1;
-    const uint32_t nrec = __builtin_amdgcn_readfirstlane(p < a.natom ? pm : 0u);
-    // BF16 operands come with a BF16 pooled gradient, FP32 with FP32
-    constexpr bool G16 = std::is_same<E, uint16_t>::value;
-    constexpr int gsz = G16 ? 2 : 4;   // bytes per stored gradient entry
-    const auto rsG = buf_rsrc(reinterpret_cast<const char*>(gp) + (size_t)p * pm * gsz, nrec * gsz),
-               rsM = buf_rsrc(code + (size_t)p * pm, nrec);
-    // the quads' gradients and codes, in flight while the tile is cleared
-    float g[DA_ROUNDS][4];
-    int m[DA_ROUNDS][4];
+// Pooled cells of NP patches (from patch p0), pooled rows r0 .. r0 + NR - 1
+// and columns s0 .. s0 + NS - 1, as an LDS image [NP][NR][NS] of values and
+// codes.  Thread t loads cells t, t + 256, ... of that image, so the lanes of
+// a load read consecutive cells of a row (few cache lines per instruction);
+// each cell's offset from (p0, r0, s0) is fixed per block and computed once.
+// Values wait in registers between their loads and their LDS store: BF16
+// values with their codes in one register, FP32 values beside codes packed
+// four to a register.  Cells outside the map or the patch range are 0 (value
+// and code): they add nothing.  One buffer descriptor starts at patch p0;
+// the host keeps 128 x h1 x w1 x 4 bytes below 2^31, so every offset fits.
+template <bool BF16, int NP, int NR, int NS>
+struct Cells {
+    static constexpr int N = NP * NR * NS, PER = (N + 255) / 256;
+    static constexpr int NC = BF16 ? 1 : (PER + 3) / 4;
+    uint32_t off[PER];   // element offset of the cell from (p0, r0, s0)
+    uint32_t rs[PER];    // its row (low byte) and column (next byte); 0xFFFF past the image
+    uint32_t v[PER];
+    uint32_t c[NC];
+    __device__ __forceinline__ void init(const BotArgs& a) {
+        const uint32_t pm = (uint32_t)a.h1 * a.w1;
 #pragma unroll
-    for (int k = 0; k < DA_ROUNDS; ++k) {
-        const int q = tid + 256 * k, qi = q / DA_QC, qj = q - qi * DA_QC;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int ry = ry0 + 2 * qi + (e >> 1), rx = rx0 + 2 * qj + (e & 1);
-            const bool ok = q < DA_NQ && rx < a.w1 && ry < a.h1;
-            const int off = ry * a.w1 + rx;   // used only when ok
-            if constexpr (G16)
-                g[k][e] = __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rsG, ok ? off * 2 : kOOB, 0, 0)
-                                          << 16);
-            else
-                g[k][e] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsG, ok ? off * 4 : kOOB, 0, 0));
-            m[k][e] = __builtin_amdgcn_raw_buffer_load_b8(rsM, ok ? off : kOOB, 0, 0);
+        for (int k = 0; k < PER; ++k) {
+            const int e = threadIdx.x + 256 * k;
+            const int p = e / (NR * NS), q = e - p * (NR * NS), r = q / NS, col = q - r * NS;
+            off[k] = (uint32_t)p * pm + (uint32_t)r * a.w1 + col;
+            rs[k] = e < N ? (uint32_t)(r | (col << 8)) : 0xFFFFu;
         }
     }
-    for (int e = tid; e < DA_ROWS * DA_COLS / 4; e += 256) reinterpret_cast<float4*>(&sT[0][0])[e] = float4{0.f, 0.f, 0.f, 0.f};
+    __device__ __forceinline__ void load(const void* __restrict__ gp, const uint8_t* __restrict__ code,
+                                         const BotArgs& a, int p0, int r0, int s0) {
+        constexpr int es = BF16 ? 2 : 4;
+        const uint32_t pm = (uint32_t)a.h1 * a.w1;
+        // patches of this range that exist (none when p0 is past the last one)
+        const uint32_t np = p0 < a.natom ? (uint32_t)min(NP, a.natom - p0) : 0u;
+        const auto rsG = buf_rsrc(static_cast<const char*>(gp) + (size_t)p0 * pm * es, np * pm * es);
+        const auto rsM = buf_rsrc(code + (size_t)p0 * pm, np * pm);
+        const uint32_t base = (uint32_t)r0 * a.w1 + s0;   // uniform
+        const bool inside = r0 + NR <= a.h1 && s0 + NS <= a.w1;   // uniform: no cell leaves the map
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {   // parity class (ry - ry0) & 1 = e >> 1, (rx - rx0) & 1 = e & 1
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < DA_ROUNDS; ++k) {
-            const int q = tid + 256 * k, qi = q / DA_QC, qj = q - qi * DA_QC;
-            const int my = (m[k][e] * 11) >> 5, mx = m[k][e] - 3 * my;   // code = 3 (my + 1) + (mx + 1), 0..8
-            const int ly = 4 * qi + 2 * (e >> 1) + my - 1, lx = 4 * qj + 2 * (e & 1) + mx - 1;
-            // no two entries of one class meet: an LDS add without return is exactly old + g
-            if (g[k][e] != 0.f && ly >= 0 && ly < DA_ROWS && lx >= 0 && lx < DA_COLS) atomicAdd(&sT[ly][lx], g[k][e]);
+        for (int k = 0; k < PER; ++k) {
+            bool ok = rs[k] != 0xFFFFu;
+            if (!inside) ok = ok && r0 + (int)(rs[k] & 0xFF) < a.h1 && s0 + (int)(rs[k] >> 8) < a.w1;
+            const int o = ok ? (int)(off[k] + base) : kOOB / es;
+            const uint32_t m = __builtin_amdgcn_raw_buffer_load_b8(rsM, o, 0, 0);
+            if constexpr (BF16) {
+                v[k] = ((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rsG, o * 2, 0, 0) << 16) | m;
+            } else {
+                v[k] = __builtin_amdgcn_raw_buffer_load_b32(rsG, o * 4, 0, 0);
+                if (k % 4 == 0) c[k / 4] = m;
+                else c[k / 4] |= m << (8 * (k % 4));
+            }
         }
     }
-    __syncthreads();
-    const int grp = tid & 31, xb = X0 + 8 * grp;
-    if (xb >= a.Wp) return;
+    __device__ __forceinline__ void store(float* __restrict__ sg, uint8_t* __restrict__ sm) const {
 #pragma unroll
-    for (int k = 0; k < DA_ROWS / 8; ++k) {
-        const int row = (tid >> 5) + 8 * k, y = Y0 + row;
-        if (y >= a.H2p) break;
-        const float4 v0 = *reinterpret_cast<const float4*>(&sT[row][8 * grp]);
-        const float4 v1 = *reinterpret_cast<const float4*>(&sT[row][8 * grp + 4]);
-        const float out[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-        store8<E>(dA + (size_t)p * a.Xp + (size_t)y * a.Wp + xb, out);
+        for (int k = 0; k < PER; ++k) {
+            const int e = threadIdx.x + 256 * k;
+            if (k == PER - 1 && e >= N) break;
+            if constexpr (BF16) {
+                sg[e] = __uint_as_float(v[k] & 0xFFFF0000u);
+                sm[e] = (uint8_t)(v[k] & 0xFFu);
+            } else {
+                sg[e] = __uint_as_float(v[k]);
+                sm[e] = (uint8_t)(c[k / 4] >> (8 * (k % 4)));
+            }
+        }
     }
+};
+
+// The 2 x 2 target positions (2t + i, 2u + e), i, e in {0, 1}, from the four
+// pooled cells c[di][dj] = (t + di, u + dj): value g, code m = 3(my+1)+(mx+1);
+// cell (t + di, u + dj) sends to (2(t + di) + my, 2(u + dj) + mx).
+__device__ __forceinline__ void gather_quad(const float g[2][2], const int m[2][2], float o[2][2]) {
+    o[0][0] = m[0][0] == 4 ? g[0][0] : 0.f;
+    o[0][1] = (m[0][0] == 5 ? g[0][0] : 0.f) + (m[0][1] == 3 ? g[0][1] : 0.f);
+    o[1][0] = (m[0][0] == 7 ? g[0][0] : 0.f) + (m[1][0] == 1 ? g[1][0] : 0.f);
+    o[1][1] = (m[0][0] == 8 ? g[0][0] : 0.f) + (m[0][1] == 6 ? g[0][1] : 0.f) + (m[1][0] == 2 ? g[1][0] : 0.f) +
+              (m[1][1] == 0 ? g[1][1] : 0.f);
 }
 
-// Transposed im2col of D2: D2colT[k][x] = D2[x + d_k][c_k] on the padded grid.
-template <typename E>
-__device__ inline void bwd_d2col_body(const float* __restrict__ d2, const BotArgs& a, E* __restrict__ d2colT,
-                                      int bid) {
-    const size_t v = (size_t)bid * 256 + threadIdx.x;   // one group of 8 positions
-    const int gpr = a.Xp / 8;
-    if (v >= (size_t)144 * gpr) return;
-    const int k = v / gpr, x0 = (int)(v - (size_t)k * gpr) * 8;
-    const int y = x0 / a.Wp, xx0 = x0 - y * a.Wp;
-    float out[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) out[q] = (y < a.H2 && xx0 + q < a.W2) ? d2_at(d2, a, y, xx0 + q, k) : 0.f;
-    store8<E>(d2colT + (size_t)k * a.Xp + x0, out);
-}
-
-// Transposed patch matrix of D1: PT[k][p] = D1[p + d_k][c_k] (0 for padding patches).
-template <typename E>
-__device__ inline void bwd_pt_body(const float* __restrict__ d1, const BotArgs& a, E* __restrict__ PT, int bid) {
-    const size_t v = (size_t)bid * 256 + threadIdx.x;
-    const int gpr = a.Pp / 8;
-    if (v >= (size_t)144 * gpr) return;
-    const int k = v / gpr, p0 = (int)(v - (size_t)k * gpr) * 8;
-    float out[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) out[q] = p0 + q < a.natom ? d1_at(d1, a, p0 + q, k) : 0.f;
-    store8<E>(PT + (size_t)k * a.Pp + p0, out);
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+    return (uint32_t)to_bf16(lo) | ((uint32_t)to_bf16(hi) << 16);
 }
 
 // ---------------------------------------------------------------- GEMMs
-constexpr int GK = 64;     // K chunk
-constexpr int G1M = 128;   // GEMM 1: patches per block
-constexpr int G2N = 128;   // GEMM 2: positions per block
-
+// GEMM 1 shapes: 128 patches per block; K chunk = 2 position rows x CW columns.
 template <bool BF16>
-struct Op {
+struct G1 {
     typedef typename std::conditional<BF16, uint16_t, float>::type E;
-    static constexpr int VPR = BF16 ? 8 : 4;     // values per 16-byte vector
-    static constexpr int PAD = BF16 ? 8 : 4;     // LDS row padding (keeps rows 16-byte aligned)
-    static constexpr int CV = GK / VPR;          // vectors per chunk row
+    static constexpr int M = 128;
+    static constexpr int CW = BF16 ? 32 : 16;
+    static constexpr int GK = 2 * CW;
+    static constexpr int NS = CW / 2 + 1;          // pooled columns a chunk reads (2 pooled rows)
+    static constexpr int VPR = BF16 ? 8 : 4;       // values per 16-byte vector
+    static constexpr int PAD = BF16 ? 8 : 4;       // LDS row padding (rows stay 16-byte aligned)
+    static constexpr int CV = GK / VPR;            // vectors per chunk row
+};
+// GEMM 2 shapes: a tile of 4 position rows x 32 columns; K chunk = GK patches.
+template <bool BF16>
+struct G2 {
+    typedef typename std::conditional<BF16, uint16_t, float>::type E;
+    static constexpr int TR = 4, TW = 32, N = TR * TW;
+    static constexpr int GK = BF16 ? 64 : 32;
+    static constexpr int NR = TR / 2 + 1, NS = TW / 2 + 1;
+    static constexpr int VPR = BF16 ? 8 : 4;
+    static constexpr int PAD = BF16 ? 8 : 4;
+    static constexpr int CV = GK / VPR;
 };
 
-// C[M=128 patches][N=144] += A[M][K] * B[N][K]^T over the chunks of one split.
+// Number of GEMM 1 K chunks of a pair and their position -> column map.
+__device__ __host__ inline int g1_chunks(const BotArgs& a, int cw) { return (a.H2p / 2) * (a.Wp / cw); }
+
+// C[M=128 patches][N=144] += dA_0[M][K] * D2col[N][K]^T over the chunks of one split.
 template <bool BF16>
-__device__ __forceinline__ void bwd_gemm1_body(const typename Op<BF16>::E* __restrict__ dA,
-                                      const typename Op<BF16>::E* __restrict__ d2colT, const BotArgs& a, int nsplit,
-                                      float* __restrict__ part, int bid) {
-    typedef Op<BF16> O;
+__device__ __forceinline__ void bwd_gemm1_body(const void* __restrict__ gp, const uint8_t* __restrict__ code,
+                                               const typename G1<BF16>::E* __restrict__ d2colT, const BotArgs& a,
+                                               int nsplit, float* __restrict__ part, int bid) {
+    typedef G1<BF16> O;
     typedef typename O::E E;
-    __shared__ __align__(16) E sA[G1M][GK + O::PAD];
-    __shared__ __align__(16) E sB[144][GK + O::PAD];
-    constexpr int NA = G1M * O::CV / 256, NB = (144 * O::CV + 255) / 256;
-    const int ptiles = a.Pp / G1M;
+    typedef Cells<BF16, O::M, 2, O::NS> C;
+    __shared__ __align__(16) E sA[O::M][O::GK + O::PAD];
+    __shared__ __align__(16) E sB[144][O::GK + O::PAD];
+    __shared__ __align__(16) float sg[C::N];
+    __shared__ __align__(16) uint8_t sm[C::N];
+    constexpr int NB = (144 * O::CV + 255) / 256;
+    const int ptiles = a.Pp / O::M;
     const int split = bid / ptiles, ptile = bid - split * ptiles;
-    const int kper = ((a.Xp / GK + nsplit - 1) / nsplit) * GK;
-    const int k_begin = split * kper, k_end = min(a.Xp, k_begin + kper);
-    const int P0 = ptile * G1M;
+    const int nch = g1_chunks(a, O::CW), njc = a.Wp / O::CW;
+    const int cper = (nch + nsplit - 1) / nsplit;
+    const int c_begin = split * cper, c_end = min(nch, c_begin + cper);
+    const int P0 = ptile * O::M;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
-    // Prefetch registers, filled by unconditional loads (rows of the B chunk
-    // past its 144 are clamped and not stored): they must stay in VGPRs.
-    u32x4 ra[NA], rb[NB];
-    size_t aoff[NA], boff[NB];   // element offsets of each vector's row at chunk start 0
-    int aidx[NA], bidx[NB];   // LDS destinations (element index), -1 = none
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-        const int v = tid + 256 * i, r = v / O::CV, c = v - r * O::CV;
-        aoff[i] = (size_t)(P0 + r) * a.Xp + c * O::VPR;
-        aidx[i] = r * (GK + O::PAD) + c * O::VPR;
-    }
+    // Prefetch registers for the D2col chunk, filled by unconditional loads
+    // (rows past 144 are clamped and not stored) so that they stay in VGPRs.
+    u32x4 rb[NB];
+    size_t boff[NB];
+    int bidx[NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int v = tid + 256 * i, vc = min(v, 144 * O::CV - 1), r = vc / O::CV, c = vc - r * O::CV;
         boff[i] = (size_t)r * a.Xp + c * O::VPR;
-        bidx[i] = v < 144 * O::CV ? r * (GK + O::PAD) + c * O::VPR : -1;
+        bidx[i] = v < 144 * O::CV ? r * (O::GK + O::PAD) + c * O::VPR : -1;
     }
+    C cells;
+    cells.init(a);
     f4 acc[2][9];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 9; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
-    if (k_begin < k_end) {
+    auto load = [&](int c) {
+        const int t = c / njc, j = c - t * njc;
+        cells.load(gp, code, a, P0, t, j * (O::CW / 2));
 #pragma unroll
-        for (int i = 0; i < NA; ++i) ra[i] = *reinterpret_cast<const u32x4*>(dA + aoff[i] + k_begin);
-#pragma unroll
-        for (int i = 0; i < NB; ++i) rb[i] = *reinterpret_cast<const u32x4*>(d2colT + boff[i] + k_begin);
-    }
-    for (int k0 = k_begin; k0 < k_end; k0 += GK) {
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NA; ++i) *reinterpret_cast<u32x4*>(&sA[0][0] + aidx[i]) = ra[i];
+        for (int i = 0; i < NB; ++i) rb[i] = *reinterpret_cast<const u32x4*>(d2colT + boff[i] + (size_t)c * O::GK);
+    };
+    if (c_begin < c_end) load(c_begin);
+    for (int c = c_begin; c < c_end; ++c) {
+        __syncthreads();   // the previous chunk's gather and products are done with the LDS
+        cells.store(sg, sm);
 #pragma unroll
         for (int i = 0; i < NB; ++i)
             if (bidx[i] >= 0) *reinterpret_cast<u32x4*>(&sB[0][0] + bidx[i]) = rb[i];
         __syncthreads();
-        if (k0 + GK < k_end) {   // next chunk in flight during the MFMAs
+        if (c + 1 < c_end) load(c + 1);   // next chunk in flight during the gather and the products
+        // gather: task (patch p, quad u) -> sA[p][i * CW + 2u + e]
+        constexpr int QU = O::CW / 2;
 #pragma unroll
-            for (int i = 0; i < NA; ++i) ra[i] = *reinterpret_cast<const u32x4*>(dA + aoff[i] + k0 + GK);
+        for (int k = 0; k < O::M * QU / 256; ++k) {
+            const int q = tid + 256 * k, p = q / QU, u = q - p * QU;
+            float gv[2][2], o[2][2];
+            int mv[2][2];
 #pragma unroll
-            for (int i = 0; i < NB; ++i) rb[i] = *reinterpret_cast<const u32x4*>(d2colT + boff[i] + k0 + GK);
+            for (int di = 0; di < 2; ++di)
+#pragma unroll
+                for (int dj = 0; dj < 2; ++dj) {
+                    const int e = (p * 2 + di) * O::NS + u + dj;
+                    gv[di][dj] = sg[e];
+                    mv[di][dj] = sm[e];
+                }
+            gather_quad(gv, mv, o);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                if constexpr (BF16)
+                    *reinterpret_cast<uint32_t*>(&sA[p][i * O::CW + 2 * u]) = pack_bf16x2(o[i][0], o[i][1]);
+                else
+                    *reinterpret_cast<float2*>(&sA[p][i * O::CW + 2 * u]) = make_float2(o[i][0], o[i][1]);
+            }
         }
+        __syncthreads();
         if constexpr (BF16) {
 #pragma unroll
-            for (int s = 0; s < GK / 32; ++s) {
+            for (int s = 0; s < O::GK / 32; ++s) {
                 bf8 av[2];
 #pragma unroll
                 for (int mt = 0; mt < 2; ++mt) av[mt] = as_bf8(&sA[wave * 32 + mt * 16 + n][32 * s + 8 * g]);
@@ -302,7 +328,7 @@ __device__ __forceinline__ void bwd_gemm1_body(const typename Op<BF16>::E* __res
             }
         } else {
 #pragma unroll 4
-            for (int t = 0; t < GK / 4; ++t) {
+            for (int t = 0; t < O::GK / 4; ++t) {
                 const float a0 = sA[wave * 32 + n][4 * t + g], a1 = sA[wave * 32 + 16 + n][4 * t + g];
 #pragma unroll
                 for (int nt = 0; nt < 9; ++nt) {
@@ -322,6 +348,38 @@ __device__ __forceinline__ void bwd_gemm1_body(const typename Op<BF16>::E* __res
                 const int p = P0 + wave * 32 + mt * 16 + 4 * g + j;
                 if (p < a.natom) part[((size_t)split * a.natom + p) * 144 + 16 * nt + n] = acc[mt][nt][j];
             }
+}
+
+// Transposed im2col of D2 in GEMM 1's chunk order: column c * GK + i * CW + cc
+// of D2colT[k] is target position (2t + i, j * CW + cc) of chunk c = t * (Wp / CW) + j.
+template <bool BF16>
+__device__ inline void bwd_d2col_body(const float* __restrict__ d2, const BotArgs& a,
+                                      typename G1<BF16>::E* __restrict__ d2colT, int bid) {
+    typedef G1<BF16> O;
+    const size_t v = (size_t)bid * 256 + threadIdx.x;   // one group of 8 positions
+    const int gpr = a.Xp / 8;
+    if (v >= (size_t)144 * gpr) return;
+    const int k = v / gpr, x0 = (int)(v - (size_t)k * gpr) * 8;
+    const int c = x0 / O::GK, w = x0 - c * O::GK, i = w / O::CW, cc = w - i * O::CW;
+    const int njc = a.Wp / O::CW, t = c / njc, j = c - t * njc;
+    const int y = 2 * t + i, xx0 = j * O::CW + cc;
+    float out[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) out[q] = (y < a.H2 && xx0 + q < a.W2) ? d2_at(d2, a, y, xx0 + q, k) : 0.f;
+    store8<typename O::E>(d2colT + (size_t)k * a.Xp + x0, out);
+}
+
+// Transposed patch matrix of D1: PT[k][p] = D1[p + d_k][c_k] (0 for padding patches).
+template <typename E>
+__device__ inline void bwd_pt_body(const float* __restrict__ d1, const BotArgs& a, E* __restrict__ PT, int bid) {
+    const size_t v = (size_t)bid * 256 + threadIdx.x;
+    const int gpr = a.Pp / 8;
+    if (v >= (size_t)144 * gpr) return;
+    const int k = v / gpr, p0 = (int)(v - (size_t)k * gpr) * 8;
+    float out[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) out[q] = p0 + q < a.natom ? d1_at(d1, a, p0 + q, k) : 0.f;
+    store8<E>(PT + (size_t)k * a.Pp + p0, out);
 }
 
 // dD1 (HWC) from the split partials: each pixel belongs to at most one patch.
@@ -344,106 +402,93 @@ __device__ inline void bwd_dd1_reduce_body(const T* __restrict__ part, const Bot
     dd1[i] = v;
 }
 
-// T[M=144][N=128 positions] += PT[M][K] * dA[K][N] over all patch chunks.
-// The dA chunk (64 patches x 128 positions) comes through registers, its
-// 8 x 8 (BF16) or 4 x 4 (FP32) blocks transposed so that LDS holds it as
-// [position][patch]; the PT chunk is copied as it is.
+// T[M=144][N = 4 x 32 positions] += PT[M][K] * dA_0[K][N] over all patch
+// chunks; the dA_0 chunk is gathered into LDS as [position][patch].
 template <bool BF16>
-__device__ __forceinline__ void bwd_gemm2_body(const typename Op<BF16>::E* __restrict__ dA,
-                                      const typename Op<BF16>::E* __restrict__ PT, const BotArgs& a,
-                                      float* __restrict__ tt, int bid) {
-    typedef Op<BF16> O;
+__device__ __forceinline__ void bwd_gemm2_body(const void* __restrict__ gp, const uint8_t* __restrict__ code,
+                                               const typename G2<BF16>::E* __restrict__ PT, const BotArgs& a,
+                                               float* __restrict__ tt, int bid) {
+    typedef G2<BF16> O;
     typedef typename O::E E;
-    __shared__ __align__(16) E sA[144][GK + O::PAD];   // PT chunk [k][patch]
-    __shared__ __align__(16) E sB[G2N][GK + O::PAD];   // dA chunk [position][patch]
-    const int X0 = bid * G2N;
+    typedef Cells<BF16, O::GK, O::NR, O::NS> C;
+    __shared__ __align__(16) E sA[144][O::GK + O::PAD];   // PT chunk [k][patch]
+    __shared__ __align__(16) E sB[O::N][O::GK + O::PAD];  // dA_0 chunk [position][patch]
+    __shared__ __align__(16) float sg[C::N];
+    __shared__ __align__(16) uint8_t sm[C::N];
+    constexpr int NPT = (144 * O::CV + 255) / 256;
+    const int ntw = a.Wp / O::TW;
+    const int tr = bid / ntw, tc = bid - tr * ntw;
+    const int Y0 = tr * O::TR, X0 = tc * O::TW;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
-    // BF16: threads 0..127 take one 8x8 dA block each, threads 128..255 the
-    // PT chunk; FP32: every thread takes two 4x4 dA blocks and part of PT.
-    constexpr int BR = BF16 ? 8 : 4, NBLK = BF16 ? 1 : 2;
-    constexpr int NTH_A = BF16 ? 128 : 256, NTH_P = BF16 ? 128 : 256;   // threads per role
-    constexpr int NPT = (144 * O::CV + NTH_P - 1) / NTH_P;             // PT vectors per thread
-    // Prefetch registers, filled by unconditional loads (PT rows past 144 are
-    // clamped and not stored) so that they stay in VGPRs.
-    u32x4 rd[NBLK][BR];
     u32x4 rp[NPT];
-    const bool loader_a = BF16 ? tid < 128 : true;    // wave-uniform
-    const bool loader_p = BF16 ? tid >= 128 : true;
-    const int tp = BF16 ? tid - 128 : tid;
-    const E* dsrc[NBLK];   // first dA row of this thread's block at chunk start 0
-    int dcol[NBLK], drow[NBLK];
-#pragma unroll
-    for (int b = 0; b < NBLK; ++b) {
-        // patch block fastest: each LDS row gets contiguous stores
-        const int blk = (loader_a ? tid : 0) + NTH_A * b;
-        const int pbn = GK / BR, xb = blk / pbn, pb = blk - xb * pbn;
-        dsrc[b] = dA + (size_t)(BR * pb) * a.Xp + X0 + BR * xb;
-        drow[b] = BR * xb;
-        dcol[b] = BR * pb;
-    }
-    const E* psrc[NPT];
+    size_t poff[NPT];
     int pidx[NPT];
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
-        const int v = (loader_p ? tp : 0) + NTH_P * i, vc = min(v, 144 * O::CV - 1), r = vc / O::CV,
-                  c = vc - r * O::CV;
-        psrc[i] = PT + (size_t)r * a.Pp + c * O::VPR;
-        pidx[i] = v < 144 * O::CV ? r * (GK + O::PAD) + c * O::VPR : -1;
+        const int v = tid + 256 * i, vc = min(v, 144 * O::CV - 1), r = vc / O::CV, c = vc - r * O::CV;
+        poff[i] = (size_t)r * a.Pp + c * O::VPR;
+        pidx[i] = v < 144 * O::CV ? r * (O::GK + O::PAD) + c * O::VPR : -1;
     }
+    C cells;
+    cells.init(a);
     f4 acc[9][2];
 #pragma unroll
     for (int mt = 0; mt < 9; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
-#define DM_G2_LOAD(P0_)                                                                              \
-    do {                                                                                             \
-        if (loader_a) {                                                                              \
-            _Pragma("unroll") for (int b = 0; b < NBLK; ++b)                                         \
-                _Pragma("unroll") for (int i = 0; i < BR; ++i) rd[b][i] =                            \
-                    *reinterpret_cast<const u32x4*>(dsrc[b] + (size_t)((P0_) + i) * a.Xp);           \
-        }                                                                                            \
-        if (loader_p) {                                                                              \
-            _Pragma("unroll") for (int i = 0; i < NPT; ++i) rp[i] =                                  \
-                *reinterpret_cast<const u32x4*>(psrc[i] + (P0_));                                    \
-        }                                                                                            \
-    } while (0)
-    DM_G2_LOAD(0);
-    for (int p0 = 0; p0 < a.Pp; p0 += GK) {
+    auto load = [&](int p0) {
+        cells.load(gp, code, a, p0, Y0 / 2, X0 / 2);
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) rp[i] = *reinterpret_cast<const u32x4*>(PT + poff[i] + p0);
+    };
+    load(0);
+    // chunks past the last patch would add zeros: the walk ends at natom
+    for (int p0 = 0; p0 < a.natom; p0 += O::GK) {
         __syncthreads();
-        if (loader_a) {
+        cells.store(sg, sm);
 #pragma unroll
-            for (int b = 0; b < NBLK; ++b) {
-                if constexpr (BF16) {
-                    // rd[b][i] = 8 bf16 of patch row i (positions 2j, 2j+1 in dword j);
-                    // column q (position) = 8 patches, packed 2 per dword.
+        for (int i = 0; i < NPT; ++i)
+            if (pidx[i] >= 0) *reinterpret_cast<u32x4*>(&sA[0][0] + pidx[i]) = rp[i];
+        __syncthreads();
+        if (p0 + O::GK < a.natom) load(p0 + O::GK);
+        // gather: task (patch group, quad row pair rq, quad column u); BF16
+        // takes two patches per task (one 32-bit store per position)
+        constexpr int PG = BF16 ? 2 : 1, NPG = O::GK / PG, QU = O::TW / 2;
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        u32x4 o;
+        for (int k = 0; k < NPG * (O::TR / 2) * QU / 256; ++k) {
+            const int q = tid + 256 * k;
+            const int pg = q % NPG, rest = q / NPG, u = rest % QU, rq = rest / QU;
+            float o[PG][2][2];
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const uint32_t lo = rd[b][2 * j][q >> 1], hi = rd[b][2 * j + 1][q >> 1];
-                            o[j] = (q & 1) ? ((lo >> 16) | (hi & 0xFFFF0000u)) : ((lo & 0xFFFFu) | (hi << 16));
-                        }
-                        *reinterpret_cast<u32x4*>(&sB[drow[b] + q][dcol[b]]) = o;
+            for (int h = 0; h < PG; ++h) {
+                const int p = pg * PG + h;
+                float gv[2][2];
+                int mv[2][2];
+#pragma unroll
+                for (int di = 0; di < 2; ++di)
+#pragma unroll
+                    for (int dj = 0; dj < 2; ++dj) {
+                        const int e = (p * O::NR + rq + di) * O::NS + u + dj;
+                        gv[di][dj] = sg[e];
+                        mv[di][dj] = sm[e];
                     }
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        *reinterpret_cast<u32x4*>(&sB[drow[b] + q][dcol[b]]) =
-                            u32x4{rd[b][0][q], rd[b][1][q], rd[b][2][q], rd[b][3][q]};
-                }
+                gather_quad(gv, mv, o[h]);
             }
-        }
-        if (loader_p) {
 #pragma unroll
-            for (int i = 0; i < NPT; ++i)
-                if (pidx[i] >= 0) *reinterpret_cast<u32x4*>(&sA[0][0] + pidx[i]) = rp[i];
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int pos = (2 * rq + i) * O::TW + 2 * u + e;
+                    if constexpr (BF16)
+                        *reinterpret_cast<uint32_t*>(&sB[pos][pg * 2]) = pack_bf16x2(o[0][i][e], o[1][i][e]);
+                    else
+                        sB[pos][pg] = o[0][i][e];
+                }
         }
         __syncthreads();
-        if (p0 + GK < a.Pp) DM_G2_LOAD(p0 + GK);
         if constexpr (BF16) {
 #pragma unroll
-            for (int s = 0; s < GK / 32; ++s) {
+            for (int s = 0; s < O::GK / 32; ++s) {
                 bf8 bv[2];
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt) bv[nt] = as_bf8(&sB[wave * 32 + nt * 16 + n][32 * s + 8 * g]);
@@ -457,7 +502,7 @@ __device__ __forceinline__ void bwd_gemm2_body(const typename Op<BF16>::E* __res
             }
         } else {
 #pragma unroll 4
-            for (int t = 0; t < GK / 4; ++t) {
+            for (int t = 0; t < O::GK / 4; ++t) {
                 const float b0 = sB[wave * 32 + n][4 * t + g], b1 = sB[wave * 32 + 16 + n][4 * t + g];
 #pragma unroll
                 for (int mt = 0; mt < 9; ++mt) {
@@ -468,15 +513,16 @@ __device__ __forceinline__ void bwd_gemm2_body(const typename Op<BF16>::E* __res
             }
         }
     }
+    // wave w holds position row Y0 + w, columns X0 .. X0 + 31
 #pragma unroll
     for (int mt = 0; mt < 9; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                tt[(size_t)(16 * mt + 4 * g + j) * a.Xp + X0 + wave * 32 + nt * 16 + n] = acc[mt][nt][j];
+                tt[(size_t)(16 * mt + 4 * g + j) * a.Xp + (size_t)(Y0 + wave) * a.Wp + X0 + nt * 16 + n] =
+                    acc[mt][nt][j];
 }
-#undef DM_G2_LOAD
 
 // dD2[y][c] = 1/16 sum_d T[(d, c)][y - d] on the padded grid (T is zero outside the target).
 __device__ inline void bwd_col2im_body(const float* __restrict__ tt, const BotArgs& a, float* __restrict__ dd2,
@@ -566,33 +612,28 @@ __device__ inline int xcd_block(int nblocks) {
     return (blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
-template <typename E>
-__global__ __launch_bounds__(256) void k_bwd_da(const float* __restrict__ gp, const uint8_t* __restrict__ code,
-                                                BotArgs a, int nct, E* __restrict__ dA, int nblocks) {
-    const int bid = xcd_block(nblocks);
-    if (bid < nblocks) bwd_da_body<E>(gp, code, a, nct, dA, bid);
-}
-template <typename E>
-__global__ __launch_bounds__(256) void k_bwd_d2col(const float* __restrict__ d2, BotArgs a, E* __restrict__ d2colT) {
-    bwd_d2col_body<E>(d2, a, d2colT, blockIdx.x);
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_bwd_d2col(const float* __restrict__ d2, BotArgs a,
+                                                   typename G1<BF16>::E* __restrict__ d2colT) {
+    bwd_d2col_body<BF16>(d2, a, d2colT, blockIdx.x);
 }
 template <typename E>
 __global__ __launch_bounds__(256) void k_bwd_pt(const float* __restrict__ d1, BotArgs a, E* __restrict__ PT) {
     bwd_pt_body<E>(d1, a, PT, blockIdx.x);
 }
 template <bool BF16>
-__global__ __launch_bounds__(256) void k_bwd_gemm1(const typename Op<BF16>::E* __restrict__ dA,
-                                                   const typename Op<BF16>::E* __restrict__ d2colT, BotArgs a,
+__global__ __launch_bounds__(256) void k_bwd_gemm1(const void* __restrict__ gp, const uint8_t* __restrict__ code,
+                                                   const typename G1<BF16>::E* __restrict__ d2colT, BotArgs a,
                                                    int nsplit, float* __restrict__ part, int nblocks) {
     const int bid = xcd_block(nblocks);
-    if (bid < nblocks) bwd_gemm1_body<BF16>(dA, d2colT, a, nsplit, part, bid);
+    if (bid < nblocks) bwd_gemm1_body<BF16>(gp, code, d2colT, a, nsplit, part, bid);
 }
 template <bool BF16>
-__global__ __launch_bounds__(256) void k_bwd_gemm2(const typename Op<BF16>::E* __restrict__ dA,
-                                                   const typename Op<BF16>::E* __restrict__ PT, BotArgs a,
+__global__ __launch_bounds__(256) void k_bwd_gemm2(const void* __restrict__ gp, const uint8_t* __restrict__ code,
+                                                   const typename G2<BF16>::E* __restrict__ PT, BotArgs a,
                                                    float* __restrict__ tt, int nblocks) {
     const int bid = xcd_block(nblocks);
-    if (bid < nblocks) bwd_gemm2_body<BF16>(dA, PT, a, tt, bid);
+    if (bid < nblocks) bwd_gemm2_body<BF16>(gp, code, PT, a, tt, bid);
 }
 template <typename T>
 __global__ __launch_bounds__(256) void k_bwd_dd1_reduce(const T* __restrict__ part, BotArgs a, int nsplit,
@@ -603,21 +644,12 @@ __global__ __launch_bounds__(256) void k_bwd_col2im(const float* __restrict__ tt
     bwd_col2im_body(tt, a, dd2, blockIdx.x);
 }
 
-template <typename E>
-struct DaJob {
-    const float* gp;
-    const uint8_t* code;
-    BotArgs a;
-    int nct;
-    E* dA;
-    static __device__ void run(const DaJob& j, int v) { bwd_da_body<E>(j.gp, j.code, j.a, j.nct, j.dA, v); }
-};
-template <typename E>
+template <bool BF16>
 struct D2colJob {
     const float* d2;
     BotArgs a;
-    E* d2colT;
-    static __device__ void run(const D2colJob& j, int v) { bwd_d2col_body<E>(j.d2, j.a, j.d2colT, v); }
+    typename G1<BF16>::E* d2colT;
+    static __device__ void run(const D2colJob& j, int v) { bwd_d2col_body<BF16>(j.d2, j.a, j.d2colT, v); }
 };
 template <typename E>
 struct PtJob {
@@ -628,18 +660,24 @@ struct PtJob {
 };
 template <bool BF16>
 struct Gemm1Job {
-    const typename Op<BF16>::E *dA, *d2colT;
+    const void* gp;
+    const uint8_t* code;
+    const typename G1<BF16>::E* d2colT;
     BotArgs a;
     int nsplit;
     float* part;
-    static __device__ void run(const Gemm1Job& j, int v) { bwd_gemm1_body<BF16>(j.dA, j.d2colT, j.a, j.nsplit, j.part, v); }
+    static __device__ void run(const Gemm1Job& j, int v) {
+        bwd_gemm1_body<BF16>(j.gp, j.code, j.d2colT, j.a, j.nsplit, j.part, v);
+    }
 };
 template <bool BF16>
 struct Gemm2Job {
-    const typename Op<BF16>::E *dA, *PT;
+    const void* gp;
+    const uint8_t* code;
+    const typename G2<BF16>::E* PT;
     BotArgs a;
     float* tt;
-    static __device__ void run(const Gemm2Job& j, int v) { bwd_gemm2_body<BF16>(j.dA, j.PT, j.a, j.tt, v); }
+    static __device__ void run(const Gemm2Job& j, int v) { bwd_gemm2_body<BF16>(j.gp, j.code, j.PT, j.a, j.tt, v); }
 };
 struct Dd1ReduceJob {
     const float* part;
@@ -665,32 +703,31 @@ BotArgs make_bot(const Geom& g) {
     a.natom = g.gx[0] * g.gy[0];
     a.h1 = g.h[1];
     a.w1 = g.w[1];
-    a.Wp = (g.W2 + 7) & ~7;
-    a.H2p = (g.H2 + 15) & ~15;
+    a.Wp = (g.W2 + kPadW - 1) / kPadW * kPadW;
+    a.H2p = (g.H2 + kPadH - 1) / kPadH * kPadH;
     a.Xp = a.Wp * a.H2p;
-    a.Pp = (a.natom + G1M - 1) / G1M * G1M;
+    a.Pp = (a.natom + G1<true>::M - 1) / G1<true>::M * G1<true>::M;
     return a;
 }
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 inline unsigned g8(int nblocks) { return (unsigned)(((nblocks + 7) / 8) * 8); }
 
-// Byte offsets of dA_0, D2colT and PT inside the dense scratch region.
+// Byte offsets of D2colT and PT inside the operand scratch region.
 struct DenseLayout {
-    size_t da, d2col, pt, total;
+    size_t d2col, pt, total;
 };
 DenseLayout dense_layout(const BotArgs& a, size_t es) {
     DenseLayout d;
-    d.da = 0;
-    d.d2col = align256((size_t)a.Pp * a.Xp * es);
-    d.pt = d.d2col + align256((size_t)144 * a.Xp * es);
+    d.d2col = 0;
+    d.pt = align256((size_t)144 * a.Xp * es);
     d.total = d.pt + align256((size_t)144 * a.Pp * es);
     return d;
 }
 
 struct BotPlan {
     BotArgs a;
-    int ns, nct, da_blocks, d2_blocks, pt_blocks, g1_blocks, g2_blocks, red_blocks, c2i_blocks;
+    int ns, d2_blocks, pt_blocks, g1_blocks, g2_blocks, red_blocks, c2i_blocks;
 };
 
 }  // namespace
@@ -701,11 +738,10 @@ int bwd_nsplit(const Geom& g) {
     // partial sums, which matters when many of them share the GPU in a batch.
     // The count depends on the pair alone, so a batch sums in the same order
     // as the single-pair call.
-    const int natom = g.gx[0] * g.gy[0];
-    const int ptiles = (natom + G1M - 1) / G1M;
-    const int xp = ((g.W2 + 7) & ~7) * ((g.H2 + 15) & ~15);
+    const BotArgs a = make_bot(g);
+    const int ptiles = a.Pp / G1<true>::M;
     int ns = (1024 + ptiles - 1) / ptiles;
-    if (ns > xp / 8192) ns = xp / 8192;
+    if (ns > a.Xp / 8192) ns = a.Xp / 8192;
     if (ns > 64) ns = 64;
     if (ns < 1) ns = 1;
     return ns;
@@ -716,12 +752,10 @@ BotPlan bot_plan(const Geom& g) {
     BotPlan b;
     b.a = make_bot(g);
     b.ns = bwd_nsplit(g);
-    b.nct = (b.a.Wp + DA_COLS - 1) / DA_COLS;
-    b.da_blocks = b.a.Pp * ((b.a.H2p + DA_ROWS - 1) / DA_ROWS) * b.nct;
     b.d2_blocks = (int)(((size_t)144 * (b.a.Xp / 8) + 255) / 256);
     b.pt_blocks = (int)(((size_t)144 * (b.a.Pp / 8) + 255) / 256);
-    b.g1_blocks = (b.a.Pp / G1M) * b.ns;
-    b.g2_blocks = b.a.Xp / G2N;
+    b.g1_blocks = (b.a.Pp / G1<true>::M) * b.ns;
+    b.g2_blocks = (b.a.H2p / G2<true>::TR) * (b.a.Wp / G2<true>::TW);
     b.red_blocks = (int)(((size_t)b.a.H1 * b.a.W1 * 9 + 255) / 256);
     b.c2i_blocks = (int)(((size_t)b.a.H2 * b.a.W2 * 9 + 255) / 256);
     return b;
@@ -737,44 +771,38 @@ size_t bwd_t_bytes(const Geom& g, int precision) {
     return (size_t)144 * make_bot(g).Xp * 4;
 }
 
-// The seven stages of the bottom backward of one pair as job records (FP32
-// storage; bf16 selects BF16 MFMA operands), in launch order.
+// The six stages of the bottom backward of one pair as job records (bf16
+// selects BF16 MFMA operands and a BF16 pooled gradient gp), in launch order.
 std::vector<JobRec> bot_jobs(bool bf16, const float* gp, const uint8_t* code, const float* d1, const float* d2,
                              const Geom& g, float* part, float* tbuf, void* dense, float* dd1, float* dd2) {
     const BotPlan b = bot_plan(g);
     const DenseLayout d = dense_layout(b.a, bf16 ? 2 : 4);
     char* base = static_cast<char*>(dense);
-    std::vector<JobRec> r(7);
+    std::vector<JobRec> r(6);
     if (bf16) {
-        uint16_t* dA = (uint16_t*)(base + d.da);
         uint16_t* dc = (uint16_t*)(base + d.d2col);
         uint16_t* pt = (uint16_t*)(base + d.pt);
-        r[0].set(JK_BWD_DA_BF16, b.da_blocks, 0, DaJob<uint16_t>{gp, code, b.a, b.nct, dA});
-        r[1].set(JK_D2COL_BF16, b.d2_blocks, 0, D2colJob<uint16_t>{d2, b.a, dc});
-        r[2].set(JK_PATCH_BF16, b.pt_blocks, 0, PtJob<uint16_t>{d1, b.a, pt});
-        r[3].set(JK_DD1_BF16, b.g1_blocks, 0, Gemm1Job<true>{dA, dc, b.a, b.ns, part});
-        r[4].set(JK_TG_BF16, b.g2_blocks, 0, Gemm2Job<true>{dA, pt, b.a, tbuf});
+        r[0].set(JK_D2COL_BF16, b.d2_blocks, 0, D2colJob<true>{d2, b.a, dc});
+        r[1].set(JK_PATCH_BF16, b.pt_blocks, 0, PtJob<uint16_t>{d1, b.a, pt});
+        r[2].set(JK_DD1_BF16, b.g1_blocks, 0, Gemm1Job<true>{gp, code, dc, b.a, b.ns, part});
+        r[3].set(JK_TG_BF16, b.g2_blocks, 0, Gemm2Job<true>{gp, code, pt, b.a, tbuf});
     } else {
-        float* dA = (float*)(base + d.da);
         float* dc = (float*)(base + d.d2col);
         float* pt = (float*)(base + d.pt);
-        r[0].set(JK_BWD_DA_F32, b.da_blocks, 0, DaJob<float>{gp, code, b.a, b.nct, dA});
-        r[1].set(JK_D2COL_F32, b.d2_blocks, 0, D2colJob<float>{d2, b.a, dc});
-        r[2].set(JK_PATCH_F32, b.pt_blocks, 0, PtJob<float>{d1, b.a, pt});
-        r[3].set(JK_DD1_F32, b.g1_blocks, 0, Gemm1Job<false>{dA, dc, b.a, b.ns, part});
-        r[4].set(JK_TG_F32, b.g2_blocks, 0, Gemm2Job<false>{dA, pt, b.a, tbuf});
+        r[0].set(JK_D2COL_F32, b.d2_blocks, 0, D2colJob<false>{d2, b.a, dc});
+        r[1].set(JK_PATCH_F32, b.pt_blocks, 0, PtJob<float>{d1, b.a, pt});
+        r[2].set(JK_DD1_F32, b.g1_blocks, 0, Gemm1Job<false>{gp, code, dc, b.a, b.ns, part});
+        r[3].set(JK_TG_F32, b.g2_blocks, 0, Gemm2Job<false>{gp, code, pt, b.a, tbuf});
     }
-    r[5].set(JK_DD1_REDUCE, b.red_blocks, 0, Dd1ReduceJob{part, b.a, b.ns, dd1});
-    r[6].set(JK_COL2IM, b.c2i_blocks, 0, Col2imJob{tbuf, b.a, dd2});
+    r[4].set(JK_DD1_REDUCE, b.red_blocks, 0, Dd1ReduceJob{part, b.a, b.ns, dd1});
+    r[5].set(JK_COL2IM, b.c2i_blocks, 0, Col2imJob{tbuf, b.a, dd2});
     return r;
 }
 
 hipError_t launch_group_bot(int kind, const GroupLaunch& gl, hipStream_t s) {
     switch (kind) {
-        case JK_BWD_DA_BF16: return launch_grouped<DaJob<uint16_t>, 256, 1>(gl, s);
-        case JK_BWD_DA_F32: return launch_grouped<DaJob<float>, 256, 1>(gl, s);
-        case JK_D2COL_BF16: return launch_grouped<D2colJob<uint16_t>, 256, 1>(gl, s);
-        case JK_D2COL_F32: return launch_grouped<D2colJob<float>, 256, 1>(gl, s);
+        case JK_D2COL_BF16: return launch_grouped<D2colJob<true>, 256, 1>(gl, s);
+        case JK_D2COL_F32: return launch_grouped<D2colJob<false>, 256, 1>(gl, s);
         case JK_PATCH_BF16: return launch_grouped<PtJob<uint16_t>, 256, 1>(gl, s);
         case JK_PATCH_F32: return launch_grouped<PtJob<float>, 256, 1>(gl, s);
         case JK_DD1_BF16: return launch_grouped<Gemm1Job<true>, 256, 1>(gl, s);
@@ -812,28 +840,22 @@ hipError_t launch_bwd_bottom(int mode, const T* gp, const uint8_t* code, const T
         const DenseLayout d = dense_layout(a, mode == 1 ? 2 : 4);
         char* base = static_cast<char*>(dense);
         if (mode == 1) {
-            uint16_t* dA = (uint16_t*)(base + d.da);
             uint16_t* dc = (uint16_t*)(base + d.d2col);
             uint16_t* pt = (uint16_t*)(base + d.pt);
-            DM_SUB("bwd_da", k_bwd_da<uint16_t>, dim3(g8(b.da_blocks)), dim3(256), 0, s, gp, code, a, b.nct, dA,
-                   b.da_blocks);
-            DM_SUB("bwd_d2col", k_bwd_d2col<uint16_t>, dim3(b.d2_blocks), dim3(256), 0, s, d2, a, dc);
+            DM_SUB("bwd_d2col", k_bwd_d2col<true>, dim3(b.d2_blocks), dim3(256), 0, s, d2, a, dc);
             DM_SUB("bwd_pt", k_bwd_pt<uint16_t>, dim3(b.pt_blocks), dim3(256), 0, s, d1, a, pt);
-            DM_SUB("bwd_dd1_gemm", k_bwd_gemm1<true>, dim3(g8(b.g1_blocks)), dim3(256), 0, s, dA, dc, a, b.ns, part,
-                   b.g1_blocks);
-            DM_SUB("bwd_t_gemm", k_bwd_gemm2<true>, dim3(g8(b.g2_blocks)), dim3(256), 0, s, dA, pt, a, tbuf,
+            DM_SUB("bwd_dd1_gemm", k_bwd_gemm1<true>, dim3(g8(b.g1_blocks)), dim3(256), 0, s, gp, code, dc, a, b.ns,
+                   part, b.g1_blocks);
+            DM_SUB("bwd_t_gemm", k_bwd_gemm2<true>, dim3(g8(b.g2_blocks)), dim3(256), 0, s, gp, code, pt, a, tbuf,
                    b.g2_blocks);
         } else {
-            float* dA = (float*)(base + d.da);
             float* dc = (float*)(base + d.d2col);
             float* pt = (float*)(base + d.pt);
-            DM_SUB("bwd_da", k_bwd_da<float>, dim3(g8(b.da_blocks)), dim3(256), 0, s, gp, code, a, b.nct, dA,
-                   b.da_blocks);
-            DM_SUB("bwd_d2col", k_bwd_d2col<float>, dim3(b.d2_blocks), dim3(256), 0, s, d2, a, dc);
+            DM_SUB("bwd_d2col", k_bwd_d2col<false>, dim3(b.d2_blocks), dim3(256), 0, s, d2, a, dc);
             DM_SUB("bwd_pt", k_bwd_pt<float>, dim3(b.pt_blocks), dim3(256), 0, s, d1, a, pt);
-            DM_SUB("bwd_dd1_gemm", k_bwd_gemm1<false>, dim3(g8(b.g1_blocks)), dim3(256), 0, s, dA, dc, a, b.ns, part,
-                   b.g1_blocks);
-            DM_SUB("bwd_t_gemm", k_bwd_gemm2<false>, dim3(g8(b.g2_blocks)), dim3(256), 0, s, dA, pt, a, tbuf,
+            DM_SUB("bwd_dd1_gemm", k_bwd_gemm1<false>, dim3(g8(b.g1_blocks)), dim3(256), 0, s, gp, code, dc, a, b.ns,
+                   part, b.g1_blocks);
+            DM_SUB("bwd_t_gemm", k_bwd_gemm2<false>, dim3(g8(b.g2_blocks)), dim3(256), 0, s, gp, code, pt, a, tbuf,
                    b.g2_blocks);
         }
         DM_SUB("bwd_dd1_reduce", k_bwd_dd1_reduce<float>, dim3(b.red_blocks), dim3(256), 0, s, part, a, b.ns, dd1);

@@ -190,6 +190,29 @@ def test_grad_plan_holds_every_level_gradient(W1, H1, W2, H2, prec):
     assert gp.off_g[1] - gp.off_g[0] >= need and gp.off_part - gp.off_g[1] >= need
 
 
+def test_entry_points_validation():
+    """DM* entry points: accepted by the matching plan, rejected with
+    prototypes, without a pooled level, and by the gradient, batch and
+    invariant plans; values other than the two schemes are invalid."""
+    L = dm.lib()
+    pl = dm.plan(64, 64, 64, 64, dm.params(entry_points="local_maxima"))
+    assert pl.lmax == 4
+    for kw, want in ((dict(entry_points=2), -1), (dict(entry_points=-1), -1),
+                     (dict(entry_points=1, prototypes=8), -5), (dict(entry_points=1, max_patch=4), -5)):
+        with pytest.raises(dm.DMError) as e:
+            dm.plan(64, 64, 64, 64, dm.params(**kw))
+        assert e.value.status == want, kw
+    with pytest.raises(dm.DMError) as e:
+        dm.plan_grad(64, 64, 64, 64, dm.params(entry_points=1))
+    assert e.value.status == -5
+    info = B.BatchInfo()
+    assert L.dm_plan_batch(1, _pairs([(64, 64, 64, 64)]), ctypes.byref(dm.params(entry_points=1)), 0,
+                           ctypes.byref(info)) == -5
+    inv = dm.InvariantInfo()
+    assert L.dm_plan_invariant(ctypes.byref(dm.params(entry_points=1)), 64, 64, 64, 64, 0x10, 1,
+                               ctypes.byref(inv)) == -5
+
+
 def _pairs(sizes, img=0x1000, dd=None):
     P = (dm.Pair * len(sizes))()
     for k, (a, b, c, d) in enumerate(sizes):
