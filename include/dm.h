@@ -210,6 +210,24 @@ dm_status dm_match_images(const float* img1, int W1, int H1, int ld1,
                           const dm_params* prm, void* ws, size_t ws_bytes,
                           dm_match* out, int capacity, int* n_out, hipStream_t stream);
 
+/* dm_match_images for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  The workspace is a static device array of
+ * DM_NOALLOC_MAX_BYTES that every GPU the library runs on holds from the
+ * load of the library's code until the process ends; the call allocates
+ * nothing (no hipMalloc, no events: per-stage timing records nothing for
+ * it).  The caller still passes the images and the outputs (as
+ * dm_match_images).  Every call on a GPU shares that GPU's array, so calls
+ * that overlap on one GPU (other streams, other host threads) race; the
+ * array keeps the last call's pyramid.  Errors: those of dm_match_images,
+ * and DM_ERR_WORKSPACE when plan.workspace_bytes exceeds
+ * DM_NOALLOC_MAX_BYTES (pairs up to about 192 x 144). */
+#define DM_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+dm_status dm_match_images_noalloc(const float* img1, int W1, int H1, int ld1,
+                                  const float* img2, int W2, int H2, int ld2,
+                                  const dm_params* prm, dm_match* out, int capacity, int* n_out,
+                                  hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Scale and rotation invariant matching (Sec. 4.2, Algorithm 2).
  *

@@ -34,6 +34,8 @@ class Params(ctypes.Structure):
                 ("kmeans_iters", c_int32), ("entry_points", c_int32), ("reserved", c_int32 * 4)]
 
 
+NOALLOC_MAX_BYTES = 128 << 20   # the static workspace of dm_match_images_noalloc
+
 DM_ENTRIES_TOP = 0
 DM_ENTRIES_LOCAL_MAXIMA = 1
 
@@ -114,6 +116,8 @@ SIGNATURES = {
                                      c_void_p, c_size_t, c_void_p, c_int, c_void_p, c_void_p]),
     "dm_match_images": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_int, c_int,
                                 POINTER(Params), c_void_p, c_size_t, c_void_p, c_int, c_void_p, c_void_p]),
+    "dm_match_images_noalloc": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_int, c_int,
+                                        POINTER(Params), c_void_p, c_int, c_void_p, c_void_p]),
     "dm_plan_grad": (c_int, [POINTER(Params), c_int, c_int, c_int, c_int, c_int, POINTER(GradPlan)]),
     "dm_pyramid_forward": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int, c_int, POINTER(Params), c_int,
                                    c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]),
@@ -261,6 +265,26 @@ def match_images(img1: torch.Tensor, img2: torch.Tensor, prm: Params | None = No
                                  pl.max_matches, c_void_p(n_out.data_ptr()), _stream()))
     m = _matches_tensor(buf, int(n_out.item()))
     return (m, ws, pl) if return_state else m
+
+
+def match_images_noalloc(img1: torch.Tensor, img2: torch.Tensor, prm: Params | None = None) -> torch.Tensor:
+    """match_images for callers that cannot allocate a workspace: the
+    library's static device array of NOALLOC_MAX_BYTES serves as one (pairs
+    whose workspace is larger are rejected).  Only the outputs are allocated
+    here.  Calls that overlap on one GPU share that array and race."""
+    prm = prm or params()
+    img1 = _dev(img1, torch.float32, 2, "img1")
+    img2 = _dev(img2, torch.float32, 2, "img2")
+    H1, W1 = img1.shape
+    H2, W2 = img2.shape
+    pl = plan(W1, H1, W2, H2, prm)
+    buf = torch.empty((pl.max_matches, 5), dtype=torch.int32, device=img1.device)
+    n_out = torch.zeros(1, dtype=torch.int32, device=img1.device)
+    _check(lib().dm_match_images_noalloc(c_void_p(img1.data_ptr()), W1, H1, img1.stride(0),
+                                         c_void_p(img2.data_ptr()), W2, H2, img2.stride(0), ctypes.byref(prm),
+                                         c_void_p(buf.data_ptr()), pl.max_matches, c_void_p(n_out.data_ptr()),
+                                         _stream()))
+    return _matches_tensor(buf, int(n_out.item()))
 
 
 def plan_invariant(W1: int, H1: int, W2: int, H2: int, prm: Params | None = None, scales_mask: int = 0x1FF,

@@ -9,7 +9,6 @@
 
 namespace dm {
 const char* last_error_text();
-void clear_error();
 }  // namespace dm
 
 using namespace dm;

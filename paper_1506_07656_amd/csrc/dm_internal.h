@@ -109,6 +109,7 @@ __device__ inline double rect_pow(double x, double lam) {
 
 // Error reporting (thread-local text read back by dm_last_error).
 dm_status fail(dm_status s, const char* fmt, ...);
+void clear_error();
 dm_status check_hip(hipError_t e, const char* what);
 
 // Host planning (dm_plan.cpp).

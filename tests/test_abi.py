@@ -213,6 +213,24 @@ def test_entry_points_validation():
                                ctypes.byref(inv)) == -5
 
 
+def test_match_images_noalloc_validation_before_any_launch():
+    """The allocation-free entry point checks its arguments and the size of
+    the pair's workspace against its static array on the host, before it
+    touches the device (fake addresses)."""
+    L = dm.lib()
+    prm = dm.params()
+    out, n = ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000)
+    assert L.dm_match_images_noalloc(ctypes.c_void_p(0x1000), 512, 256, 512, ctypes.c_void_p(0x2000), 512, 256,
+                                     512, ctypes.byref(prm), out, 32768, n, None) == -3
+    assert "static array" in L.dm_last_error().decode()
+    assert dm.plan(512, 256, 512, 256, prm).workspace_bytes > dm.NOALLOC_MAX_BYTES
+    assert dm.plan(160, 120, 160, 120, prm).workspace_bytes <= dm.NOALLOC_MAX_BYTES
+    assert L.dm_match_images_noalloc(ctypes.c_void_p(0x1000), 2, 2, 2, ctypes.c_void_p(0x2000), 8, 8, 8,
+                                     ctypes.byref(prm), out, 16, n, None) == -2
+    assert L.dm_match_images_noalloc(ctypes.c_void_p(0x1000), 64, 64, 64, ctypes.c_void_p(0x2000), 64, 64, 64,
+                                     None, out, 256, n, None) == -1
+
+
 def _pairs(sizes, img=0x1000, dd=None):
     P = (dm.Pair * len(sizes))()
     for k, (a, b, c, d) in enumerate(sizes):
