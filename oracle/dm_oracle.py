@@ -604,38 +604,63 @@ def backtrack(pyr: Pyramid, entries=None, level_entries=None):
 # maxima of the correlation maps of every level, scored by path sums (R24)
 # ----------------------------------------------------------------------------
 
-def local_maxima(M: np.ndarray):
+def local_maxima(M: np.ndarray, ids: np.ndarray | None = None):
     """R24: the local maxima of maps M[..., h, w] over their 3 x 3
     neighbourhoods (positions outside the map take no part): a positive value
     not below any neighbour and above the neighbours that come before it in
     raster order, so a plateau of equal values gives one maximum, at its
-    first position.  Returns the mask and the gap to the largest neighbour
-    (the decision's margin; inf without neighbours)."""
+    first position.
+
+    Returns the mask and each decision's margin.  The decision is the
+    conjunction of one comparison per neighbour (and of the value with 0);
+    a comparison's margin is the distance of the two values, except that
+    equal values count as safe (inf) when they have the same identity in
+    `ids` (a copy of one value: any evaluation ties them alike) and as 0
+    otherwise (without `ids` every tie counts as 0).  A maximum changes when
+    any comparison does (the smallest margin); a non-maximum only when every
+    failing comparison does (the largest margin among them)."""
     h, w = M.shape[-2:]
     P = np.full(M.shape[:-2] + (h + 2, w + 2), -np.inf)
     P[..., 1:1 + h, 1:1 + w] = M
+    if ids is not None:
+        Q = np.full(M.shape[:-2] + (h + 2, w + 2), -1, dtype=np.int64)
+        Q[..., 1:1 + h, 1:1 + w] = ids
     mask = M > 0
-    top2 = np.full(M.shape, -np.inf)
+    m_all = np.abs(M)                      # the comparison with 0
+    m_fail = np.where(mask, 0.0, np.abs(M))
     for dy in (-1, 0, 1):
         for dx in (-1, 0, 1):
             if dy == 0 and dx == 0:
                 continue
             v = P[..., 1 + dy:1 + dy + h, 1 + dx:1 + dx + w]
-            mask &= (M > v) if (dy, dx) < (0, 0) else (M >= v)
-            top2 = np.maximum(top2, v)
-    return mask, M - top2
+            ok = (M > v) if (dy, dx) < (0, 0) else (M >= v)
+            mask &= ok
+            d = np.abs(M - v)
+            if ids is None:
+                same = np.zeros(M.shape, dtype=bool)
+            else:
+                same = Q[..., 1 + dy:1 + dy + h, 1 + dx:1 + dx + w] == ids
+            mj = np.where(d > 0, d, np.where(same, np.inf, 0.0))
+            mj = np.where(np.isinf(v), np.inf, mj)   # outside the map: no comparison
+            m_all = np.minimum(m_all, mj)
+            m_fail = np.where(ok, m_fail, np.maximum(m_fail, mj))
+    return mask, np.where(mask, m_all, m_fail)
 
 
-def dmstar_entries(pyr: Pyramid):
+def dmstar_entries(pyr: Pyramid, tie: float = 2e-5):
     """Entry tuples of every level (R24): the local maxima of the top maps
     C_top, and of the pooled maps C'_l below the top, where pooled cell r of
     patch p stands for the node (l, p, 2r + m_l(p, r)) (the position it was
-    pooled from) with score C'_l(p, r).  Returns {level: (b, a, qy, qx, s,
-    margin)}."""
+    pooled from) with score C'_l(p, r).  An entry's margin is that of its
+    local-maximum decision, with the value identities of `pooling_stability`
+    at `tie` (R14) telling copies from values that merely tie.  Returns
+    {level: (b, a, qy, qx, s, margin)}."""
     out = {}
+    _, tvid, pids = pooling_stability(pyr, tie)
     for lv in range(pyr.lmax + 1):
         M = pyr.top if lv == pyr.lmax else pyr.Cp[lv]
-        mask, gap = local_maxima(np.nan_to_num(M, nan=-np.inf))
+        ids = tvid if lv == pyr.lmax else pids[lv]
+        mask, margin = local_maxima(np.nan_to_num(M, nan=-np.inf), ids)
         mask &= pyr.G[lv][..., None, None]
         b, a, ry, rx = np.nonzero(mask)
         if lv == pyr.lmax:
@@ -643,7 +668,7 @@ def dmstar_entries(pyr: Pyramid):
         else:
             k = pyr.code[lv][b, a, ry, rx].astype(np.int64)
             qy, qx = 2 * ry + (k // 3 - 1), 2 * rx + (k % 3 - 1)
-        out[lv] = (b, a, qy, qx, M[b, a, ry, rx].astype(np.float64), risky(gap[b, a, ry, rx]))
+        out[lv] = (b, a, qy, qx, M[b, a, ry, rx].astype(np.float64), margin[b, a, ry, rx])
     return out
 
 
@@ -696,7 +721,9 @@ def reciprocal(M: dict, W: int, H: int, W2: int, H2: int):
 
 def match_descriptors(D1: np.ndarray, D2: np.ndarray, prm: Params = Params()):
     """Descriptors -> pyramid -> backtracking -> reciprocal matches."""
-    pyr = pyramid(D1, D2, prm)
+    # DM* entries need the value identities of pooling_stability, which read
+    # the maps before rectification above level 0
+    pyr = pyramid(D1, D2, prm, keep_full=bool(prm.entry_points), keep_bottom=False)
     M = backtrack(pyr, level_entries=dmstar_entries(pyr) if prm.entry_points else None)
     out, margin = reciprocal(M, pyr.W, pyr.H, pyr.W2, pyr.H2)
     return out, margin, pyr, M
@@ -883,7 +910,7 @@ def pyramid_backward(D1: np.ndarray, D2: np.ndarray, pyr: Pyramid, tie: float | 
     dC.reshape(top.shape[0], top.shape[1], -1)[bb, aa, am[bb, aa]] = 1.0
     risk = None
     if tie is not None:
-        unstable, tvid = pooling_stability(pyr, tie)
+        unstable, tvid, _ = pooling_stability(pyr, tie)
         mx = flat.max(-1, keepdims=True)
         near = (flat >= mx - tie * (1.0 + np.abs(mx))) & (mx > 0)
         if lmax == 0:   # the top is the bottom: distinct correlations
@@ -1011,8 +1038,10 @@ def _value_ids(pyr: Pyramid, lv: int, pid_below: np.ndarray) -> np.ndarray:
 def pooling_stability(pyr: Pyramid, tie: float):
     """The decisions a less precise evaluation may take differently (R14).
 
-    Returns (unstable, top_vid): per level l < lmax, the pooled cells whose
-    argmax (Eq. (9)) is at risk, and the provenance ids of the top map.  A
+    Returns (unstable, top_vid, pids): per level l < lmax, the pooled cells
+    whose argmax (Eq. (9)) is at risk; the provenance ids of the top map; and
+    per level l < lmax the identity of each pooled cell's value (equal ids:
+    bitwise equal values in any evaluation that keeps the stable decisions).  A
     decision with a positive best value is at risk when a runner-up lies
     within tie * (1 + best) of it, unless the runner-up is an exact tie whose
     value has the same provenance as the winner's (`_value_ids`: the same
@@ -1020,12 +1049,12 @@ def pooling_stability(pyr: Pyramid, tie: float):
     every exact tie counts, its candidates being distinct correlations.  A
     pooled cell passes on the provenance of its source position when its
     decision is stable, and an identity of its own otherwise."""
-    out = []
+    out, pids = [], []
     pid = None
     for lv in range(pyr.lmax + 1):
         vid = None if lv == 0 else _value_ids(pyr, lv, pid)
         if lv == pyr.lmax:
-            return out, vid
+            return out, vid, pids
         best, code = pyr.Cp[lv], pyr.code[lv]
         thr = tie * (1.0 + np.abs(best))
         h, w = best.shape[-2:]
@@ -1055,6 +1084,7 @@ def pooling_stability(pyr: Pyramid, tie: float):
         out.append(unstable)
         marker = -2 - np.arange(best.size, dtype=np.int64).reshape(best.shape)
         pid = np.where(unstable, marker, src)
+        pids.append(pid)
 
 
 def unpool_risk(rCp: np.ndarray, dCp: np.ndarray, code: np.ndarray, best: np.ndarray, unstable: np.ndarray,
