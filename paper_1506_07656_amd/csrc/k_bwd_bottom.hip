@@ -26,8 +26,11 @@
 //    along K.
 //  - GEMM 2 (M = 144, N = a tile of 4 position rows x 32 columns, K =
 //    patches): the dA_0 chunk is gathered straight into LDS as
-//    [position][patch]; the transposed patch matrix of D1 ([144][Pp]) is
-//    copied as it is.
+//    [position][patch]; the transposed patch matrix of D1 ([144][Pp], its
+//    columns in the gather's patch order) is copied as it is.
+// The staged cells sit in LDS in a layout that lets a lane read a run of four
+// cells of a row with one 16-byte load, and each gather task turns two such
+// runs (pooled rows t, t + 1) into four quads (16 target positions).
 // Loads of the next chunk are in flight during the matrix-core work; split
 // partial sums are added in a fixed order.
 //
@@ -42,6 +45,7 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 // Native 16-byte vector: copies are plain loads and stores, never memcpy of a
 // struct, so arrays of them stay in registers.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -122,34 +126,43 @@ __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t nbytes
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
 }
 
-// Pooled cells of NP patches (from patch p0), pooled rows r0 .. r0 + NR - 1
-// and columns s0 .. s0 + NS - 1, as an LDS image [NP][NR][NS] of values and
-// codes.  Thread t loads cells t, t + 256, ... of that image, so the lanes of
-// a load read consecutive cells of a row (few cache lines per instruction);
-// each cell's offset from (p0, r0, s0) is fixed per block and computed once.
-// Values wait in registers between their loads and their LDS store: BF16
-// values with their codes in one register, FP32 values beside codes packed
-// four to a register.  Cells outside the map or the patch range are 0 (value
-// and code): they add nothing.  One buffer descriptor starts at patch p0;
-// the host keeps 128 x h1 x w1 x 4 bytes below 2^31, so every offset fits.
-template <bool BF16, int NP, int NR, int NS>
-struct Cells {
-    static constexpr int N = NP * NR * NS, PER = (N + 255) / 256;
-    static constexpr int NC = BF16 ? 1 : (PER + 3) / 4;
-    uint32_t off[PER];   // element offset of the cell from (p0, r0, s0)
-    uint32_t rs[PER];    // its row (low byte) and column (next byte); 0xFFFF past the image
-    uint32_t v[PER];
-    uint32_t c[NC];
-    __device__ __forceinline__ void init(const BotArgs& a) {
-        const uint32_t pm = (uint32_t)a.h1 * a.w1;
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int e = threadIdx.x + 256 * k;
-            const int p = e / (NR * NS), q = e - p * (NR * NS), r = q / NS, col = q - r * NS;
-            off[k] = (uint32_t)p * pm + (uint32_t)r * a.w1 + col;
-            rs[k] = e < N ? (uint32_t)(r | (col << 8)) : 0xFFFFu;
-        }
-    }
+// LDS image of the pooled cells of NP patches (from patch p0), pooled rows
+// r0 .. r0 + NR - 1 and columns s0 .. s0 + NM (NM a multiple of 4).
+//  - main[p][r][0 .. NM): patch stride S with S % 8 == 4, so that lanes
+//    taking consecutive patches read their 16-byte runs of a row on distinct
+//    banks;
+//  - every fourth column c = 4, 8, ..., NM once more as dup[c / 4 - 1][r][p]:
+//    the cell after a lane's run of four, with consecutive patches in
+//    consecutive words.
+// BF16: one word per cell, the value in the high half and the code in the
+// low byte (the staged value is the BF16 gradient itself); FP32: a value word
+// and a code byte at the same index.
+// Loading: thread t keeps column t % NM of the first NM columns; its k-th
+// cell is row (256 / NM) k / NP, patch t / NM + (256 / NM) k % NP, so every
+// offset is the thread's base plus a stride known at compile time, and the
+// lanes of a load read runs of NM neighbouring cells of a row.  Column NM
+// goes to the threads in (row, patch) order.  Values wait in registers between
+// their loads and their LDS store: BF16 values with their codes in one
+// register, FP32 values beside codes packed four to a register.  Cells
+// outside the map or the patch range are 0 (value and code): they add
+// nothing.  One buffer descriptor starts at patch p0; the host keeps
+// 128 x h1 x w1 x 4 bytes below 2^31, so every offset fits.
+template <bool BF16, int NP, int NR, int NM>
+struct CellImage {
+    static_assert(NM % 4 == 0 && 256 % NM == 0, "runs of four cells; whole rows per pass");
+    static constexpr int RPK = 256 / NM;                  // rows of NM cells one pass covers
+    static_assert(NP % RPK == 0, "a pass stays in one pooled row");
+    static constexpr int PM = NP * NR * NM / 256;         // first-NM-column cells per thread
+    static constexpr int NX = NP * NR, PX = (NX + 255) / 256;   // column-NM cells (per thread)
+    static constexpr int CM = BF16 ? 1 : (PM + 3) / 4, CX = BF16 ? 1 : (PX + 3) / 4;
+    static constexpr int S = NR * NM + ((NR * NM) % 8 == 4 ? 0 : 4);
+    static constexpr int D0 = NP * S;                       // start of dup
+    static constexpr int WORDS = D0 + (NM / 4) * NR * NP;   // image words (FP32: as many code bytes)
+    static constexpr int kr(int k) { return RPK * k / NP; }
+    static constexpr int kp(int k) { return RPK * k % NP; }
+    uint32_t vm[PM], vx[PX];   // BF16: value << 16 | code; FP32: value
+    uint32_t cm[CM], cx[CX];   // FP32 codes, four to a word
+
     __device__ __forceinline__ void load(const void* __restrict__ gp, const uint8_t* __restrict__ code,
                                          const BotArgs& a, int p0, int r0, int s0) {
         constexpr int es = BF16 ? 2 : 4;
@@ -158,13 +171,11 @@ struct Cells {
         const uint32_t np = p0 < a.natom ? (uint32_t)min(NP, a.natom - p0) : 0u;
         const auto rsG = buf_rsrc(static_cast<const char*>(gp) + (size_t)p0 * pm * es, np * pm * es);
         const auto rsM = buf_rsrc(code + (size_t)p0 * pm, np * pm);
-        const uint32_t base = (uint32_t)r0 * a.w1 + s0;   // uniform
-        const bool inside = r0 + NR <= a.h1 && s0 + NS <= a.w1;   // uniform: no cell leaves the map
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            bool ok = rs[k] != 0xFFFFu;
-            if (!inside) ok = ok && r0 + (int)(rs[k] & 0xFF) < a.h1 && s0 + (int)(rs[k] >> 8) < a.w1;
-            const int o = ok ? (int)(off[k] + base) : kOOB / es;
+        const int col = threadIdx.x % NM, pt = threadIdx.x / NM;
+        const bool colok = s0 + col < a.w1;
+        const uint32_t o0 = (uint32_t)pt * pm + (uint32_t)r0 * a.w1 + s0 + col;
+        auto put = [&](uint32_t* v, uint32_t* c, int k, bool ok, uint32_t off) {
+            const int o = ok ? (int)off : kOOB / es;
             const uint32_t m = __builtin_amdgcn_raw_buffer_load_b8(rsM, o, 0, 0);
             if constexpr (BF16) {
                 v[k] = ((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rsG, o * 2, 0, 0) << 16) | m;
@@ -173,20 +184,60 @@ struct Cells {
                 if (k % 4 == 0) c[k / 4] = m;
                 else c[k / 4] |= m << (8 * (k % 4));
             }
+        };
+#pragma unroll
+        for (int k = 0; k < PM; ++k)
+            put(vm, cm, k, colok && r0 + kr(k) < a.h1, o0 + (uint32_t)kp(k) * pm + (uint32_t)kr(k) * a.w1);
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+            const int e = threadIdx.x + 256 * k, r = e / NP, p = e - r * NP;
+            put(vx, cx, k, e < NX && s0 + NM < a.w1 && r0 + r < a.h1,
+                (uint32_t)p * pm + (uint32_t)(r0 + r) * a.w1 + s0 + NM);
         }
     }
-    __device__ __forceinline__ void store(float* __restrict__ sg, uint8_t* __restrict__ sm) const {
+    __device__ __forceinline__ void store(uint32_t* __restrict__ img, uint8_t* __restrict__ cimg) const {
+        const int col = threadIdx.x % NM, pt = threadIdx.x / NM;
+        const int mi = pt * S + col;
+        const bool dup = col > 0 && col % 4 == 0;
+        const int di = D0 + (col / 4 - 1) * NR * NP + pt;
+        auto put = [&](int slot, uint32_t v, const uint32_t* c, int k) {
+            img[slot] = v;
+            if constexpr (!BF16) cimg[slot] = (uint8_t)(c[k / 4] >> (8 * (k % 4)));
+        };
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
+        for (int k = 0; k < PM; ++k) {
+            put(mi + kp(k) * S + kr(k) * NM, vm[k], cm, k);
+            if (dup) put(di + kr(k) * NP + kp(k), vm[k], cm, k);
+        }
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
             const int e = threadIdx.x + 256 * k;
-            if (k == PER - 1 && e >= N) break;
-            if constexpr (BF16) {
-                sg[e] = __uint_as_float(v[k] & 0xFFFF0000u);
-                sm[e] = (uint8_t)(v[k] & 0xFFu);
-            } else {
-                sg[e] = __uint_as_float(v[k]);
-                sm[e] = (uint8_t)(c[k / 4] >> (8 * (k % 4)));
+            if (NX % 256 == 0 || e < NX) put(D0 + (NM / 4 - 1) * NR * NP + e, vx[k], cx, k);
+        }
+    }
+    // Cells (r, 4 q4 .. 4 q4 + 4) of patch p: values g and codes m.
+    __device__ static __forceinline__ void run5(const uint32_t* __restrict__ img, const uint8_t* __restrict__ cimg,
+                                                int p, int r, int q4, float g[5], int m[5]) {
+        const int mi = p * S + r * NM + 4 * q4, di = D0 + (q4 * NR + r) * NP + p;
+        const u32x4 w = *reinterpret_cast<const u32x4*>(img + mi);
+        const uint32_t nx = img[di];
+        if constexpr (BF16) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                g[j] = __uint_as_float(w[j] & 0xFFFF0000u);
+                m[j] = (int)(w[j] & 0xFFu);
             }
+            g[4] = __uint_as_float(nx & 0xFFFF0000u);
+            m[4] = (int)(nx & 0xFFu);
+        } else {
+            const uint32_t cw = *reinterpret_cast<const uint32_t*>(cimg + mi);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                g[j] = __uint_as_float(w[j]);
+                m[j] = (int)((cw >> (8 * j)) & 0xFFu);
+            }
+            g[4] = __uint_as_float(nx);
+            m[4] = (int)cimg[di];
         }
     }
 };
@@ -202,8 +253,27 @@ __device__ __forceinline__ void gather_quad(const float g[2][2], const int m[2][
               (m[1][1] == 0 ? g[1][1] : 0.f);
 }
 
+// Four neighbouring quads: pooled rows t, t + 1, cells u0 .. u0 + 4 of each
+// (g0/m0 and g1/m1) -> target rows 2t and 2t + 1, positions 2 u0 .. 2 u0 + 7.
+__device__ __forceinline__ void gather_run(const float g0[5], const int m0[5], const float g1[5], const int m1[5],
+                                           float o[2][8]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float gv[2][2] = {{g0[q], g0[q + 1]}, {g1[q], g1[q + 1]}};
+        const int mv[2][2] = {{m0[q], m0[q + 1]}, {m1[q], m1[q + 1]}};
+        float oq[2][2];
+        gather_quad(gv, mv, oq);
+        o[0][2 * q] = oq[0][0];
+        o[0][2 * q + 1] = oq[0][1];
+        o[1][2 * q] = oq[1][0];
+        o[1][2 * q + 1] = oq[1][1];
+    }
+}
+
+// Round to nearest even, two values to one word (lo in the low half).
 __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
-    return (uint32_t)to_bf16(lo) | ((uint32_t)to_bf16(hi) << 16);
+    const bf2 v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, v);
 }
 
 // ---------------------------------------------------------------- GEMMs
@@ -233,6 +303,9 @@ struct G2 {
 
 // Number of GEMM 1 K chunks of a pair and their position -> column map.
 __device__ __host__ inline int g1_chunks(const BotArgs& a, int cw) { return (a.H2p / 2) * (a.Wp / cw); }
+// K splits of one patch tile that run side by side (the split count is a
+// multiple of it).
+__device__ __host__ inline int g1_group(int nsplit) { return nsplit < 8 ? nsplit : 8; }
 
 // C[M=128 patches][N=144] += dA_0[M][K] * D2col[N][K]^T over the chunks of one split.
 template <bool BF16>
@@ -241,32 +314,34 @@ __device__ __forceinline__ void bwd_gemm1_body(const void* __restrict__ gp, cons
                                                int nsplit, float* __restrict__ part, int bid) {
     typedef G1<BF16> O;
     typedef typename O::E E;
-    typedef Cells<BF16, O::M, 2, O::NS> C;
+    typedef CellImage<BF16, O::M, 2, O::CW / 2> C;
     __shared__ __align__(16) E sA[O::M][O::GK + O::PAD];
     __shared__ __align__(16) E sB[144][O::GK + O::PAD];
-    __shared__ __align__(16) float sg[C::N];
-    __shared__ __align__(16) uint8_t sm[C::N];
+    __shared__ __align__(16) uint32_t img[C::WORDS];
+    __shared__ __align__(16) uint8_t cimg[BF16 ? 16 : C::WORDS];
     constexpr int NB = (144 * O::CV + 255) / 256;
-    const int ptiles = a.Pp / O::M;
-    const int split = bid / ptiles, ptile = bid - split * ptiles;
+    // Block bid = ((sg * ptiles) + ptile) * gs + m runs K split sg * gs + m of
+    // patch tile ptile.  Split s takes the chunks s, s + nsplit, s + 2 nsplit,
+    // ... so the gs splits of one group read neighbouring column strips of
+    // the same pooled rows at the same time: they share the cache lines of
+    // g'_0 and the codes, and the patch tiles beside them share the im2col
+    // operand.  (One split per contiguous K range instead left each line to
+    // be re-read by the same block a chunk later, after the other blocks of
+    // its XCD had pushed it out of L2.)
+    const int ptiles = a.Pp / O::M, gs = g1_group(nsplit);
+    const int m = bid % gs, r = bid / gs, ptile = r % ptiles, split = (r / ptiles) * gs + m;
     const int nch = g1_chunks(a, O::CW), njc = a.Wp / O::CW;
-    const int cper = (nch + nsplit - 1) / nsplit;
-    const int c_begin = split * cper, c_end = min(nch, c_begin + cper);
     const int P0 = ptile * O::M;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
     // Prefetch registers for the D2col chunk, filled by unconditional loads
     // (rows past 144 are clamped and not stored) so that they stay in VGPRs.
+    // Vector i of thread t is row t / CV + i (256 / CV), vector t % CV of it.
+    static_assert(256 % O::CV == 0, "whole rows per pass");
+    constexpr int RB = 256 / O::CV;
     u32x4 rb[NB];
-    size_t boff[NB];
-    int bidx[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        const int v = tid + 256 * i, vc = min(v, 144 * O::CV - 1), r = vc / O::CV, c = vc - r * O::CV;
-        boff[i] = (size_t)r * a.Xp + c * O::VPR;
-        bidx[i] = v < 144 * O::CV ? r * (O::GK + O::PAD) + c * O::VPR : -1;
-    }
+    const E* const bsrc = d2colT + (size_t)(tid / O::CV) * a.Xp + (tid % O::CV) * O::VPR;
+    const int bdst = (tid / O::CV) * (O::GK + O::PAD) + (tid % O::CV) * O::VPR;
     C cells;
-    cells.init(a);
     f4 acc[2][9];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
@@ -276,39 +351,43 @@ __device__ __forceinline__ void bwd_gemm1_body(const void* __restrict__ gp, cons
         const int t = c / njc, j = c - t * njc;
         cells.load(gp, code, a, P0, t, j * (O::CW / 2));
 #pragma unroll
-        for (int i = 0; i < NB; ++i) rb[i] = *reinterpret_cast<const u32x4*>(d2colT + boff[i] + (size_t)c * O::GK);
+        for (int i = 0; i < NB; ++i) {
+            const int r = min(tid / O::CV + i * RB, 143) - tid / O::CV;   // clamped row, relative
+            rb[i] = *reinterpret_cast<const u32x4*>(bsrc + (size_t)r * a.Xp + (size_t)c * O::GK);
+        }
     };
-    if (c_begin < c_end) load(c_begin);
-    for (int c = c_begin; c < c_end; ++c) {
+    if (split < nch) load(split);
+    for (int c = split; c < nch; c += nsplit) {
         __syncthreads();   // the previous chunk's gather and products are done with the LDS
-        cells.store(sg, sm);
+        cells.store(img, cimg);
 #pragma unroll
         for (int i = 0; i < NB; ++i)
-            if (bidx[i] >= 0) *reinterpret_cast<u32x4*>(&sB[0][0] + bidx[i]) = rb[i];
+            if (tid / O::CV + i * RB < 144) *reinterpret_cast<u32x4*>(&sB[0][0] + bdst + i * RB * (O::GK + O::PAD)) = rb[i];
         __syncthreads();
-        if (c + 1 < c_end) load(c + 1);   // next chunk in flight during the gather and the products
-        // gather: task (patch p, quad u) -> sA[p][i * CW + 2u + e]
-        constexpr int QU = O::CW / 2;
+        if (c + nsplit < nch) load(c + nsplit);   // next chunk in flight during the gather and the products
+        // gather: task (patch p, run q4 of four quads) -> sA[p][i * CW + 8 q4 .. + 7];
+        // consecutive lanes take consecutive patches
+        constexpr int NG = O::CW / 8;
 #pragma unroll
-        for (int k = 0; k < O::M * QU / 256; ++k) {
-            const int q = tid + 256 * k, p = q / QU, u = q - p * QU;
-            float gv[2][2], o[2][2];
-            int mv[2][2];
-#pragma unroll
-            for (int di = 0; di < 2; ++di)
-#pragma unroll
-                for (int dj = 0; dj < 2; ++dj) {
-                    const int e = (p * 2 + di) * O::NS + u + dj;
-                    gv[di][dj] = sg[e];
-                    mv[di][dj] = sm[e];
-                }
-            gather_quad(gv, mv, o);
+        for (int k = 0; k < O::M * NG / 256; ++k) {
+            const int q = tid + 256 * k, p = q % O::M, q4 = q / O::M;
+            float g0[5], g1[5], o[2][8];
+            int m0[5], m1[5];
+            C::run5(img, cimg, p, 0, q4, g0, m0);
+            C::run5(img, cimg, p, 1, q4, g1, m1);
+            gather_run(g0, m0, g1, m1, o);
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                if constexpr (BF16)
-                    *reinterpret_cast<uint32_t*>(&sA[p][i * O::CW + 2 * u]) = pack_bf16x2(o[i][0], o[i][1]);
-                else
-                    *reinterpret_cast<float2*>(&sA[p][i * O::CW + 2 * u]) = make_float2(o[i][0], o[i][1]);
+                if constexpr (BF16) {
+                    u32x4 w;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) w[j] = pack_bf16x2(o[i][2 * j], o[i][2 * j + 1]);
+                    *reinterpret_cast<u32x4*>(&sA[p][i * O::CW + 8 * q4]) = w;
+                } else {
+                    *reinterpret_cast<float4*>(&sA[p][i * O::CW + 8 * q4]) = make_float4(o[i][0], o[i][1], o[i][2], o[i][3]);
+                    *reinterpret_cast<float4*>(&sA[p][i * O::CW + 8 * q4 + 4]) =
+                        make_float4(o[i][4], o[i][5], o[i][6], o[i][7]);
+                }
             }
         }
         __syncthreads();
@@ -369,17 +448,24 @@ __device__ inline void bwd_d2col_body(const float* __restrict__ d2, const BotArg
     store8<typename O::E>(d2colT + (size_t)k * a.Xp + x0, out);
 }
 
-// Transposed patch matrix of D1: PT[k][p] = D1[p + d_k][c_k] (0 for padding patches).
+// Transposed patch matrix of D1: PT[k][slot] = D1[p + d_k][c_k] (0 for
+// padding patches).  FP32: slot = p.  BF16: GEMM 2 gathers patches p and
+// p + 32 of a 64-patch chunk into neighbouring slots 2p and 2p + 1, and the
+// columns follow that order.
 template <typename E>
 __device__ inline void bwd_pt_body(const float* __restrict__ d1, const BotArgs& a, E* __restrict__ PT, int bid) {
     const size_t v = (size_t)bid * 256 + threadIdx.x;
     const int gpr = a.Pp / 8;
     if (v >= (size_t)144 * gpr) return;
-    const int k = v / gpr, p0 = (int)(v - (size_t)k * gpr) * 8;
+    const int k = v / gpr, s0 = (int)(v - (size_t)k * gpr) * 8;
     float out[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) out[q] = p0 + q < a.natom ? d1_at(d1, a, p0 + q, k) : 0.f;
-    store8<E>(PT + (size_t)k * a.Pp + p0, out);
+    for (int q = 0; q < 8; ++q) {
+        const int sl = s0 + q;
+        const int p = std::is_same<E, float>::value ? sl : (sl & ~63) + ((sl & 63) >> 1) + 32 * (sl & 1);
+        out[q] = p < a.natom ? d1_at(d1, a, p, k) : 0.f;
+    }
+    store8<E>(PT + (size_t)k * a.Pp + s0, out);
 }
 
 // dD1 (HWC) from the split partials: each pixel belongs to at most one patch.
@@ -410,27 +496,24 @@ __device__ __forceinline__ void bwd_gemm2_body(const void* __restrict__ gp, cons
                                                float* __restrict__ tt, int bid) {
     typedef G2<BF16> O;
     typedef typename O::E E;
-    typedef Cells<BF16, O::GK, O::NR, O::NS> C;
-    __shared__ __align__(16) E sA[144][O::GK + O::PAD];   // PT chunk [k][patch]
-    __shared__ __align__(16) E sB[O::N][O::GK + O::PAD];  // dA_0 chunk [position][patch]
-    __shared__ __align__(16) float sg[C::N];
-    __shared__ __align__(16) uint8_t sm[C::N];
+    typedef CellImage<BF16, O::GK, O::NR, O::TW / 2> C;
+    __shared__ __align__(16) E sA[144][O::GK + O::PAD];   // PT chunk [k][patch slot]
+    __shared__ __align__(16) E sB[O::N][O::GK + O::PAD];  // dA_0 chunk [position][patch slot]
+    __shared__ __align__(16) uint32_t img[C::WORDS];
+    __shared__ __align__(16) uint8_t cimg[BF16 ? 16 : C::WORDS];
     constexpr int NPT = (144 * O::CV + 255) / 256;
     const int ntw = a.Wp / O::TW;
     const int tr = bid / ntw, tc = bid - tr * ntw;
     const int Y0 = tr * O::TR, X0 = tc * O::TW;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = lane & 15, g = lane >> 4;
+    // Vector i of thread t is row t / CV + i (256 / CV), vector t % CV of it
+    // (rows past 144 are clamped and not stored).
+    static_assert(256 % O::CV == 0, "whole rows per pass");
+    constexpr int RB = 256 / O::CV;
     u32x4 rp[NPT];
-    size_t poff[NPT];
-    int pidx[NPT];
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-        const int v = tid + 256 * i, vc = min(v, 144 * O::CV - 1), r = vc / O::CV, c = vc - r * O::CV;
-        poff[i] = (size_t)r * a.Pp + c * O::VPR;
-        pidx[i] = v < 144 * O::CV ? r * (O::GK + O::PAD) + c * O::VPR : -1;
-    }
+    const E* const psrc = PT + (size_t)(tid / O::CV) * a.Pp + (tid % O::CV) * O::VPR;
+    const int pdst = (tid / O::CV) * (O::GK + O::PAD) + (tid % O::CV) * O::VPR;
     C cells;
-    cells.init(a);
     f4 acc[9][2];
 #pragma unroll
     for (int mt = 0; mt < 9; ++mt)
@@ -439,50 +522,48 @@ __device__ __forceinline__ void bwd_gemm2_body(const void* __restrict__ gp, cons
     auto load = [&](int p0) {
         cells.load(gp, code, a, p0, Y0 / 2, X0 / 2);
 #pragma unroll
-        for (int i = 0; i < NPT; ++i) rp[i] = *reinterpret_cast<const u32x4*>(PT + poff[i] + p0);
+        for (int i = 0; i < NPT; ++i) {
+            const int r = min(tid / O::CV + i * RB, 143) - tid / O::CV;   // clamped row, relative
+            rp[i] = *reinterpret_cast<const u32x4*>(psrc + (size_t)r * a.Pp + p0);
+        }
     };
     load(0);
     // chunks past the last patch would add zeros: the walk ends at natom
     for (int p0 = 0; p0 < a.natom; p0 += O::GK) {
         __syncthreads();
-        cells.store(sg, sm);
+        cells.store(img, cimg);
 #pragma unroll
         for (int i = 0; i < NPT; ++i)
-            if (pidx[i] >= 0) *reinterpret_cast<u32x4*>(&sA[0][0] + pidx[i]) = rp[i];
+            if (tid / O::CV + i * RB < 144) *reinterpret_cast<u32x4*>(&sA[0][0] + pdst + i * RB * (O::GK + O::PAD)) = rp[i];
         __syncthreads();
         if (p0 + O::GK < a.natom) load(p0 + O::GK);
-        // gather: task (patch group, quad row pair rq, quad column u); BF16
-        // takes two patches per task (one 32-bit store per position)
-        constexpr int PG = BF16 ? 2 : 1, NPG = O::GK / PG, QU = O::TW / 2;
-#pragma unroll
-        for (int k = 0; k < NPG * (O::TR / 2) * QU / 256; ++k) {
-            const int q = tid + 256 * k;
-            const int pg = q % NPG, rest = q / NPG, u = rest % QU, rq = rest / QU;
-            float o[PG][2][2];
+        // gather: task (patch pair pg, quad row pair rq, run q4 of four quads);
+        // consecutive lanes take consecutive pairs.  BF16 pairs patches pg and
+        // pg + 32 into one 32-bit word per position (patch slot 2 pg + h
+        // holds patch pg + 32 h, the order of the patch matrix's columns),
+        // FP32 takes one patch.
+        constexpr int PG = BF16 ? 2 : 1, NPG = O::GK / PG;
+        static_assert(NPG * (O::TR / 2) * (O::TW / 8) == 256, "one task per thread");
+        {
+            const int pg = tid % NPG, rest = tid / NPG, q4 = rest % (O::TW / 8), rq = rest / (O::TW / 8);
+            float o[PG][2][8];
 #pragma unroll
             for (int h = 0; h < PG; ++h) {
-                const int p = pg * PG + h;
-                float gv[2][2];
-                int mv[2][2];
-#pragma unroll
-                for (int di = 0; di < 2; ++di)
-#pragma unroll
-                    for (int dj = 0; dj < 2; ++dj) {
-                        const int e = (p * O::NR + rq + di) * O::NS + u + dj;
-                        gv[di][dj] = sg[e];
-                        mv[di][dj] = sm[e];
-                    }
-                gather_quad(gv, mv, o[h]);
+                float g0[5], g1[5];
+                int m0[5], m1[5];
+                C::run5(img, cimg, pg + NPG * h, rq, q4, g0, m0);
+                C::run5(img, cimg, pg + NPG * h, rq + 1, q4, g1, m1);
+                gather_run(g0, m0, g1, m1, o[h]);
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    const int pos = (2 * rq + i) * O::TW + 2 * u + e;
+                for (int x = 0; x < 8; ++x) {
+                    const int pos = (2 * rq + i) * O::TW + 8 * q4 + x;
                     if constexpr (BF16)
-                        *reinterpret_cast<uint32_t*>(&sB[pos][pg * 2]) = pack_bf16x2(o[0][i][e], o[1][i][e]);
+                        *reinterpret_cast<uint32_t*>(&sB[pos][2 * pg]) = pack_bf16x2(o[0][i][x], o[1][i][x]);
                     else
-                        sB[pos][pg] = o[0][i][e];
+                        sB[pos][pg] = o[0][i][x];
                 }
         }
         __syncthreads();
@@ -605,8 +686,8 @@ __global__ void k_bwd_col2im_ref(const T* __restrict__ tbuf, BotArgs a, T* __res
 
 // ---------------------------------------------------------------- kernels and jobs
 // Blocks are dealt to the 8 XCDs round-robin; renumber them so that each XCD
-// works through one contiguous range (GEMM 1: the patch tiles of one K split
-// share its slice of the im2col operand in that XCD's L2).
+// works through one contiguous range (GEMM 1: the K splits of a group and the
+// patch tiles beside them run on one XCD and share its L2).
 __device__ inline int xcd_block(int nblocks) {
     const int per = (nblocks + 7) / 8;
     return (blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -622,14 +703,14 @@ __global__ __launch_bounds__(256) void k_bwd_pt(const float* __restrict__ d1, Bo
     bwd_pt_body<E>(d1, a, PT, blockIdx.x);
 }
 template <bool BF16>
-__global__ __launch_bounds__(256) void k_bwd_gemm1(const void* __restrict__ gp, const uint8_t* __restrict__ code,
+__global__ __launch_bounds__(256, 2) void k_bwd_gemm1(const void* __restrict__ gp, const uint8_t* __restrict__ code,
                                                    const typename G1<BF16>::E* __restrict__ d2colT, BotArgs a,
                                                    int nsplit, float* __restrict__ part, int nblocks) {
     const int bid = xcd_block(nblocks);
     if (bid < nblocks) bwd_gemm1_body<BF16>(gp, code, d2colT, a, nsplit, part, bid);
 }
 template <bool BF16>
-__global__ __launch_bounds__(256) void k_bwd_gemm2(const void* __restrict__ gp, const uint8_t* __restrict__ code,
+__global__ __launch_bounds__(256, 2) void k_bwd_gemm2(const void* __restrict__ gp, const uint8_t* __restrict__ code,
                                                    const typename G2<BF16>::E* __restrict__ PT, BotArgs a,
                                                    float* __restrict__ tt, int nblocks) {
     const int bid = xcd_block(nblocks);
@@ -743,6 +824,7 @@ int bwd_nsplit(const Geom& g) {
     int ns = (1024 + ptiles - 1) / ptiles;
     if (ns > a.Xp / 8192) ns = a.Xp / 8192;
     if (ns > 64) ns = 64;
+    if (ns > 8) ns &= ~7;   // whole groups of 8 splits
     if (ns < 1) ns = 1;
     return ns;
 }
@@ -805,10 +887,10 @@ hipError_t launch_group_bot(int kind, const GroupLaunch& gl, hipStream_t s) {
         case JK_D2COL_F32: return launch_grouped<D2colJob<false>, 256, 1>(gl, s);
         case JK_PATCH_BF16: return launch_grouped<PtJob<uint16_t>, 256, 1>(gl, s);
         case JK_PATCH_F32: return launch_grouped<PtJob<float>, 256, 1>(gl, s);
-        case JK_DD1_BF16: return launch_grouped<Gemm1Job<true>, 256, 1>(gl, s);
-        case JK_DD1_F32: return launch_grouped<Gemm1Job<false>, 256, 1>(gl, s);
-        case JK_TG_BF16: return launch_grouped<Gemm2Job<true>, 256, 1>(gl, s);
-        case JK_TG_F32: return launch_grouped<Gemm2Job<false>, 256, 1>(gl, s);
+        case JK_DD1_BF16: return launch_grouped<Gemm1Job<true>, 256, 2>(gl, s);
+        case JK_DD1_F32: return launch_grouped<Gemm1Job<false>, 256, 2>(gl, s);
+        case JK_TG_BF16: return launch_grouped<Gemm2Job<true>, 256, 2>(gl, s);
+        case JK_TG_F32: return launch_grouped<Gemm2Job<false>, 256, 2>(gl, s);
         case JK_DD1_REDUCE: return launch_grouped<Dd1ReduceJob, 256, 1>(gl, s);
         case JK_COL2IM: return launch_grouped<Col2imJob, 256, 1>(gl, s);
         default: return hipErrorInvalidValue;
