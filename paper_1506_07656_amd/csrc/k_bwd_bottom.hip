@@ -53,6 +53,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 struct BotArgs {
     int W1, H1, W2, H2, n0x, natom, h1, w1;
     int Wp, H2p, Xp, Pp;   // padded target grid and patch count (matrix-core path)
+    int pm;                // h1 * w1: cells of one patch's pooled map
 };
 
 // dA_0(p, x) from the pooled gradient and codes of patch p (maps h1 x w1).
@@ -131,78 +132,109 @@ __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t nbytes
 //  - main[p][r][0 .. NM): patch stride S with S % 8 == 4, so that lanes
 //    taking consecutive patches read their 16-byte runs of a row on distinct
 //    banks;
-//  - every fourth column c = 4, 8, ..., NM once more as dup[c / 4 - 1][r][p]:
-//    the cell after a lane's run of four, with consecutive patches in
-//    consecutive words.
+//  - column NM as xcol[r][p] (consecutive patches in consecutive words), and
+//    with DUP the columns 4, 8, ..., NM - 4 once more beside it
+//    (dup[c / 4 - 1][r][p]): the cell after a lane's run of four, read
+//    without conflicts.  Without DUP a lane takes that cell from the lane
+//    that holds the next run (run5_lanes).
 // BF16: one word per cell, the value in the high half and the code in the
 // low byte (the staged value is the BF16 gradient itself); FP32: a value word
 // and a code byte at the same index.
-// Loading: thread t keeps column t % NM of the first NM columns; its k-th
-// cell is row (256 / NM) k / NP, patch t / NM + (256 / NM) k % NP, so every
-// offset is the thread's base plus a stride known at compile time, and the
-// lanes of a load read runs of NM neighbouring cells of a row.  Column NM
-// goes to the threads in (row, patch) order.  Values wait in registers between
-// their loads and their LDS store: BF16 values with their codes in one
-// register, FP32 values beside codes packed four to a register.  Cells
-// outside the map or the patch range are 0 (value and code): they add
-// nothing.  One buffer descriptor starts at patch p0; the host keeps
-// 128 x h1 x w1 x 4 bytes below 2^31, so every offset fits.
-template <bool BF16, int NP, int NR, int NM>
+// Loading: thread t keeps column t % NM of the first NM columns, and u =
+// t / NM picks its first (patch, row); its k-th cell is u + (256 / NM) k in
+// (patch, row) order for two rows (row fastest: the lanes of a store then
+// cover 32 banks) and in (row, patch) order otherwise, so every offset is the
+// thread's base plus a stride known at compile time, and the lanes of a load
+// read runs of NM neighbouring cells of a row.  Column NM goes to the threads
+// in (row, patch) order.  Values wait in registers between their loads and
+// their LDS store: BF16 values with their codes in one register, FP32 values
+// beside codes packed four to a register.  Cells outside the map or the patch
+// range are 0 (value and code): they add nothing.  One buffer descriptor
+// starts at patch p0; the host keeps 128 x h1 x w1 x 4 bytes below 2^31, so
+// every offset fits.
+template <bool BF16, int NP, int NR, int NM, bool DUP>
 struct CellImage {
     static_assert(NM % 4 == 0 && 256 % NM == 0, "runs of four cells; whole rows per pass");
     static constexpr int RPK = 256 / NM;                  // rows of NM cells one pass covers
-    static_assert(NP % RPK == 0, "a pass stays in one pooled row");
+    static constexpr bool RFAST = NR == 2;
+    static_assert(RFAST ? RPK % 2 == 0 : NP % RPK == 0, "a thread keeps its row");
     static constexpr int PM = NP * NR * NM / 256;         // first-NM-column cells per thread
     static constexpr int NX = NP * NR, PX = (NX + 255) / 256;   // column-NM cells (per thread)
-    static constexpr int CM = BF16 ? 1 : (PM + 3) / 4, CX = BF16 ? 1 : (PX + 3) / 4;
+    static constexpr int CM = BF16 ? PM : (PM + 3) / 4, CX = BF16 ? PX : (PX + 3) / 4;
     static constexpr int S = NR * NM + ((NR * NM) % 8 == 4 ? 0 : 4);
-    static constexpr int D0 = NP * S;                       // start of dup
-    static constexpr int WORDS = D0 + (NM / 4) * NR * NP;   // image words (FP32: as many code bytes)
-    static constexpr int kr(int k) { return RPK * k / NP; }
-    static constexpr int kp(int k) { return RPK * k % NP; }
-    uint32_t vm[PM], vx[PX];   // BF16: value << 16 | code; FP32: value
-    uint32_t cm[CM], cx[CX];   // FP32 codes, four to a word
+    static constexpr int D0 = NP * S;                              // start of dup
+    static constexpr int X0 = D0 + (DUP ? (NM / 4 - 1) * NR * NP : 0);   // start of xcol
+    static constexpr int WORDS = X0 + NR * NP;            // image words (FP32: as many code bytes)
+    // row and patch of cell k of a thread, beyond those of its first cell
+    static constexpr int kr(int k) { return RFAST ? 0 : RPK * k / NP; }
+    static constexpr int kp(int k) { return RFAST ? RPK / 2 * k : RPK * k % NP; }
+    __device__ static __forceinline__ int row0() { return RFAST ? (int)(threadIdx.x / NM) % 2 : 0; }
+    __device__ static __forceinline__ int patch0() {
+        return RFAST ? (int)(threadIdx.x / NM) / 2 : (int)(threadIdx.x / NM);
+    }
+    uint32_t vm[PM], vx[PX];   // values (BF16: the 16 bits)
+    uint32_t cm[CM], cx[CX];   // codes (BF16: one per register; FP32: four to a word)
 
     __device__ __forceinline__ void load(const void* __restrict__ gp, const uint8_t* __restrict__ code,
                                          const BotArgs& a, int p0, int r0, int s0) {
         constexpr int es = BF16 ? 2 : 4;
-        const uint32_t pm = (uint32_t)a.h1 * a.w1;
+        const uint32_t pm = (uint32_t)a.pm;
         // patches of this range that exist (none when p0 is past the last one)
         const uint32_t np = p0 < a.natom ? (uint32_t)min(NP, a.natom - p0) : 0u;
         const auto rsG = buf_rsrc(static_cast<const char*>(gp) + (size_t)p0 * pm * es, np * pm * es);
         const auto rsM = buf_rsrc(code + (size_t)p0 * pm, np * pm);
-        const int col = threadIdx.x % NM, pt = threadIdx.x / NM;
-        const bool colok = s0 + col < a.w1;
-        const uint32_t o0 = (uint32_t)pt * pm + (uint32_t)r0 * a.w1 + s0 + col;
-        auto put = [&](uint32_t* v, uint32_t* c, int k, bool ok, uint32_t off) {
-            const int o = ok ? (int)off : kOOB / es;
-            const uint32_t m = __builtin_amdgcn_raw_buffer_load_b8(rsM, o, 0, 0);
+        const int col = threadIdx.x % NM, rt = row0();
+        // element offset of the thread's first cell; cell k adds the uniform kp(k) pm + kr(k) w1
+        const uint32_t o0 = (uint32_t)patch0() * pm + (uint32_t)(r0 + rt) * a.w1 + s0 + col;
+        auto put = [&](uint32_t* v, uint32_t* c, int k, uint32_t om, uint32_t og) {
+            const uint32_t m = __builtin_amdgcn_raw_buffer_load_b8(rsM, (int)om, 0, 0);
+            // BF16 keeps value and code apart until the LDS store: joining
+            // them here would wait for the loads.
             if constexpr (BF16) {
-                v[k] = ((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rsG, o * 2, 0, 0) << 16) | m;
+                v[k] = __builtin_amdgcn_raw_buffer_load_b16(rsG, (int)og, 0, 0);
+                c[k] = m;
             } else {
-                v[k] = __builtin_amdgcn_raw_buffer_load_b32(rsG, o * 4, 0, 0);
+                v[k] = __builtin_amdgcn_raw_buffer_load_b32(rsG, (int)og, 0, 0);
                 if (k % 4 == 0) c[k / 4] = m;
                 else c[k / 4] |= m << (8 * (k % 4));
             }
         };
+        if (r0 + NR <= a.h1 && s0 + NM + 1 <= a.w1) {   // uniform: no cell leaves the map
+            const uint32_t ob = o0 * es;
 #pragma unroll
-        for (int k = 0; k < PM; ++k)
-            put(vm, cm, k, colok && r0 + kr(k) < a.h1, o0 + (uint32_t)kp(k) * pm + (uint32_t)kr(k) * a.w1);
+            for (int k = 0; k < PM; ++k) {
+                const uint32_t d = (uint32_t)kp(k) * pm + (uint32_t)kr(k) * a.w1;   // uniform
+                put(vm, cm, k, o0 + d, ob + d * es);
+            }
+        } else {
+            const bool colok = s0 + col < a.w1;
+#pragma unroll
+            for (int k = 0; k < PM; ++k) {
+                const bool ok = colok && r0 + rt + kr(k) < a.h1;
+                const uint32_t o = ok ? o0 + (uint32_t)kp(k) * pm + (uint32_t)kr(k) * a.w1 : (uint32_t)(kOOB / es);
+                put(vm, cm, k, o, o * es);
+            }
+        }
 #pragma unroll
         for (int k = 0; k < PX; ++k) {
             const int e = threadIdx.x + 256 * k, r = e / NP, p = e - r * NP;
-            put(vx, cx, k, e < NX && s0 + NM < a.w1 && r0 + r < a.h1,
-                (uint32_t)p * pm + (uint32_t)(r0 + r) * a.w1 + s0 + NM);
+            const bool ok = e < NX && s0 + NM < a.w1 && r0 + r < a.h1;
+            const uint32_t o = ok ? (uint32_t)p * pm + (uint32_t)(r0 + r) * a.w1 + s0 + NM : (uint32_t)(kOOB / es);
+            put(vx, cx, k, o, o * es);
         }
     }
     __device__ __forceinline__ void store(uint32_t* __restrict__ img, uint8_t* __restrict__ cimg) const {
-        const int col = threadIdx.x % NM, pt = threadIdx.x / NM;
-        const int mi = pt * S + col;
-        const bool dup = col > 0 && col % 4 == 0;
-        const int di = D0 + (col / 4 - 1) * NR * NP + pt;
+        const int col = threadIdx.x % NM, rt = row0(), pt = patch0();
+        const int mi = pt * S + rt * NM + col;
+        const bool dup = DUP && col > 0 && col % 4 == 0;
+        const int di = D0 + ((col / 4 - 1) * NR + rt) * NP + pt;
         auto put = [&](int slot, uint32_t v, const uint32_t* c, int k) {
-            img[slot] = v;
-            if constexpr (!BF16) cimg[slot] = (uint8_t)(c[k / 4] >> (8 * (k % 4)));
+            if constexpr (BF16) {
+                img[slot] = (v << 16) | c[k];
+            } else {
+                img[slot] = v;
+                cimg[slot] = (uint8_t)(c[k / 4] >> (8 * (k % 4)));
+            }
         };
 #pragma unroll
         for (int k = 0; k < PM; ++k) {
@@ -212,33 +244,45 @@ struct CellImage {
 #pragma unroll
         for (int k = 0; k < PX; ++k) {
             const int e = threadIdx.x + 256 * k;
-            if (NX % 256 == 0 || e < NX) put(D0 + (NM / 4 - 1) * NR * NP + e, vx[k], cx, k);
+            if (NX % 256 == 0 || e < NX) put(X0 + e, vx[k], cx, k);
         }
     }
-    // Cells (r, 4 q4 .. 4 q4 + 4) of patch p: values g and codes m.
+    __device__ static __forceinline__ void decode(uint32_t w, uint32_t cb, float& g, int& m) {
+        if constexpr (BF16) {
+            g = __uint_as_float(w & 0xFFFF0000u);
+            m = (int)(w & 0xFFu);
+        } else {
+            g = __uint_as_float(w);
+            m = (int)cb;
+        }
+    }
+    // Cells (r, 4 q4 .. 4 q4 + 4) of patch p (DUP): values g and codes m.
     __device__ static __forceinline__ void run5(const uint32_t* __restrict__ img, const uint8_t* __restrict__ cimg,
                                                 int p, int r, int q4, float g[5], int m[5]) {
-        const int mi = p * S + r * NM + 4 * q4, di = D0 + (q4 * NR + r) * NP + p;
+        static_assert(DUP, "the cell after a run comes from dup");
+        const int mi = p * S + r * NM + 4 * q4;
+        const int di = (q4 + 1) * 4 == NM ? X0 + r * NP + p : D0 + (q4 * NR + r) * NP + p;
         const u32x4 w = *reinterpret_cast<const u32x4*>(img + mi);
-        const uint32_t nx = img[di];
-        if constexpr (BF16) {
+        const uint32_t cw = BF16 ? 0u : *reinterpret_cast<const uint32_t*>(cimg + mi);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                g[j] = __uint_as_float(w[j] & 0xFFFF0000u);
-                m[j] = (int)(w[j] & 0xFFu);
-            }
-            g[4] = __uint_as_float(nx & 0xFFFF0000u);
-            m[4] = (int)(nx & 0xFFu);
-        } else {
-            const uint32_t cw = *reinterpret_cast<const uint32_t*>(cimg + mi);
+        for (int j = 0; j < 4; ++j) decode(w[j], (cw >> (8 * j)) & 0xFFu, g[j], m[j]);
+        decode(img[di], BF16 ? 0u : cimg[di], g[4], m[4]);
+    }
+    // The same for BF16 without DUP when the 64 lanes of the wave take runs
+    // q4 = lane / 16 of 16 patches (NM = 16): the cell after a run is the
+    // first cell of the run of the lane 16 places up, and for the last run
+    // the column-NM cell, which the lane of run 0 sends (64 lanes wrap).
+    __device__ static __forceinline__ void run5_lanes(const uint32_t* __restrict__ img, int p, int r, int q4,
+                                                      float g[5], int m[5]) {
+        static_assert(BF16 && !DUP && NM == 16, "four runs over the 64 lanes");
+        const u32x4 w = *reinterpret_cast<const u32x4*>(img + p * S + r * NM + 4 * q4);
+        const uint32_t xc = img[X0 + r * NP + p];   // read by every lane: no branch around it
+        const uint32_t send = q4 == 0 ? xc : w[0];
+        const int src = (((int)threadIdx.x & 63) + 16) & 63;
+        const uint32_t nx = (uint32_t)__builtin_amdgcn_ds_bpermute(src * 4, (int)send);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                g[j] = __uint_as_float(w[j]);
-                m[j] = (int)((cw >> (8 * j)) & 0xFFu);
-            }
-            g[4] = __uint_as_float(nx);
-            m[4] = (int)cimg[di];
-        }
+        for (int j = 0; j < 4; ++j) decode(w[j], 0u, g[j], m[j]);
+        decode(nx, 0u, g[4], m[4]);
     }
 };
 
@@ -314,8 +358,9 @@ __device__ __forceinline__ void bwd_gemm1_body(const void* __restrict__ gp, cons
                                                int nsplit, float* __restrict__ part, int bid) {
     typedef G1<BF16> O;
     typedef typename O::E E;
-    typedef CellImage<BF16, O::M, 2, O::CW / 2> C;
-    __shared__ __align__(16) E sA[O::M][O::GK + O::PAD];
+    // BF16: a lane's gather task yields its A operand (below), no LDS tile.
+    typedef CellImage<BF16, O::M, 2, O::CW / 2, !BF16> C;
+    __shared__ __align__(16) E sA[BF16 ? 1 : O::M][O::GK + O::PAD];
     __shared__ __align__(16) E sB[144][O::GK + O::PAD];
     __shared__ __align__(16) uint32_t img[C::WORDS];
     __shared__ __align__(16) uint8_t cimg[BF16 ? 16 : C::WORDS];
@@ -365,47 +410,57 @@ __device__ __forceinline__ void bwd_gemm1_body(const void* __restrict__ gp, cons
             if (tid / O::CV + i * RB < 144) *reinterpret_cast<u32x4*>(&sB[0][0] + bdst + i * RB * (O::GK + O::PAD)) = rb[i];
         __syncthreads();
         if (c + nsplit < nch) load(c + nsplit);   // next chunk in flight during the gather and the products
-        // gather: task (patch p, run q4 of four quads) -> sA[p][i * CW + 8 q4 .. + 7];
-        // consecutive lanes take consecutive patches
-        constexpr int NG = O::CW / 8;
+        if constexpr (BF16) {
+            // Lane (n, g) of wave w gathers run g of patch 32 w + 16 mt + n:
+            // target rows 2t and 2t + 1, columns 8g .. 8g + 7, which are the
+            // K elements 8g .. 8g + 7 of row n of the A operand for s = 0
+            // and s = 1 (chunk order: K = i * CW + column).
+            bf8 av[2][2];
 #pragma unroll
-        for (int k = 0; k < O::M * NG / 256; ++k) {
-            const int q = tid + 256 * k, p = q % O::M, q4 = q / O::M;
-            float g0[5], g1[5], o[2][8];
-            int m0[5], m1[5];
-            C::run5(img, cimg, p, 0, q4, g0, m0);
-            C::run5(img, cimg, p, 1, q4, g1, m1);
-            gather_run(g0, m0, g1, m1, o);
+            for (int mt = 0; mt < 2; ++mt) {
+                const int p = wave * 32 + mt * 16 + n;
+                float g0[5], g1[5], o[2][8];
+                int m0[5], m1[5];
+                C::run5_lanes(img, p, 0, g, g0, m0);
+                C::run5_lanes(img, p, 1, g, g1, m1);
+                gather_run(g0, m0, g1, m1, o);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                if constexpr (BF16) {
+                for (int i = 0; i < 2; ++i) {
                     u32x4 w;
 #pragma unroll
                     for (int j = 0; j < 4; ++j) w[j] = pack_bf16x2(o[i][2 * j], o[i][2 * j + 1]);
-                    *reinterpret_cast<u32x4*>(&sA[p][i * O::CW + 8 * q4]) = w;
-                } else {
-                    *reinterpret_cast<float4*>(&sA[p][i * O::CW + 8 * q4]) = make_float4(o[i][0], o[i][1], o[i][2], o[i][3]);
-                    *reinterpret_cast<float4*>(&sA[p][i * O::CW + 8 * q4 + 4]) =
-                        make_float4(o[i][4], o[i][5], o[i][6], o[i][7]);
+                    av[mt][i] = __builtin_bit_cast(bf8, w);
                 }
             }
-        }
-        __syncthreads();
-        if constexpr (BF16) {
 #pragma unroll
-            for (int s = 0; s < O::GK / 32; ++s) {
-                bf8 av[2];
-#pragma unroll
-                for (int mt = 0; mt < 2; ++mt) av[mt] = as_bf8(&sA[wave * 32 + mt * 16 + n][32 * s + 8 * g]);
+            for (int s = 0; s < 2; ++s)
 #pragma unroll
                 for (int nt = 0; nt < 9; ++nt) {
                     const bf8 bv = as_bf8(&sB[16 * nt + n][32 * s + 8 * g]);
 #pragma unroll
                     for (int mt = 0; mt < 2; ++mt)
-                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv, acc[mt][nt], 0, 0, 0);
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt][s], bv, acc[mt][nt], 0, 0, 0);
+                }
+        } else {
+            // gather: task (patch p, run q4 of four quads) -> sA[p][i * CW + 8 q4 .. + 7];
+            // consecutive lanes take consecutive patches
+            constexpr int NG = O::CW / 8;
+#pragma unroll
+            for (int k = 0; k < O::M * NG / 256; ++k) {
+                const int q = tid + 256 * k, p = q % O::M, q4 = q / O::M;
+                float g0[5], g1[5], o[2][8];
+                int m0[5], m1[5];
+                C::run5(img, cimg, p, 0, q4, g0, m0);
+                C::run5(img, cimg, p, 1, q4, g1, m1);
+                gather_run(g0, m0, g1, m1, o);
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    *reinterpret_cast<float4*>(&sA[p][i * O::CW + 8 * q4]) = make_float4(o[i][0], o[i][1], o[i][2], o[i][3]);
+                    *reinterpret_cast<float4*>(&sA[p][i * O::CW + 8 * q4 + 4]) =
+                        make_float4(o[i][4], o[i][5], o[i][6], o[i][7]);
                 }
             }
-        } else {
+            __syncthreads();
 #pragma unroll 4
             for (int t = 0; t < O::GK / 4; ++t) {
                 const float a0 = sA[wave * 32 + n][4 * t + g], a1 = sA[wave * 32 + 16 + n][4 * t + g];
@@ -496,7 +551,7 @@ __device__ __forceinline__ void bwd_gemm2_body(const void* __restrict__ gp, cons
                                                float* __restrict__ tt, int bid) {
     typedef G2<BF16> O;
     typedef typename O::E E;
-    typedef CellImage<BF16, O::GK, O::NR, O::TW / 2> C;
+    typedef CellImage<BF16, O::GK, O::NR, O::TW / 2, true> C;
     __shared__ __align__(16) E sA[144][O::GK + O::PAD];   // PT chunk [k][patch slot]
     __shared__ __align__(16) E sB[O::N][O::GK + O::PAD];  // dA_0 chunk [position][patch slot]
     __shared__ __align__(16) uint32_t img[C::WORDS];
@@ -788,6 +843,7 @@ BotArgs make_bot(const Geom& g) {
     a.H2p = (g.H2 + kPadH - 1) / kPadH * kPadH;
     a.Xp = a.Wp * a.H2p;
     a.Pp = (a.natom + G1<true>::M - 1) / G1<true>::M * G1<true>::M;
+    a.pm = a.h1 * a.w1;
     return a;
 }
 
