@@ -20,6 +20,10 @@ Algorithm 2) on the same pair: the paper's grid of 9 scales x 8 rotations (72
 runs of the pipeline on resampled pairs, one reciprocal check over their
 union), BF16 correlation.
 
+The "dmstar" entry is the earlier entry-point scheme (DM*, Sec. 3.3 and
+Table 1): local maxima of every level start the backtracking, scored by the
+current path sums; entry counts and agreement with the plain method.
+
 The "batch" entry is the uneven-batch workload: 32 pairs with W ~ U{128..621},
 H ~ U{96..188} (half of a 1242x375 driving-frame shape), BF16 correlation,
 FP32 pyramid, forward plus backward of the top loss, every stage one
@@ -35,51 +39,72 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
-
-# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE on the
-# kernels as they are now, scaled by the 1 GiB copy calibration (read = 2 x
-# FETCH_SIZE, written = 1 x WRITE_SIZE); source:
-# profiles/bf16_forward_512x256_hbm_bytes.md.  Only valid for the 512x256
-# pair; a kernel changed since then must be dropped from this table.
-MEASURED_TRAFFIC_512x256 = {
-    "corr_pool_bf16_l0": 43.5e6 + 1611.1e6,
-    "level_l1": 2328.0e6 + 338.1e6,
-    "level_l2": 561.2e6 + 89.2e6,
-    "level_l3": 150.0e6 + 23.1e6,
-    "level_l4": 31.6e6 + 5.2e6,
-    "backtrack_l1": 1747.7e6 + 45.3e6,
-    "backtrack_l2": 413.9e6 + 268.4e6,
-}
 PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_512x256.md")
+
+# Algorithmic bytes per entry: a correlation value is 4 bytes; an argmax code
+# (one of 9 window positions) needs 4 bits.  The library stores codes as one
+# byte, so the stored traffic is also reported (stored_* fields).
+CODE_BYTES = 0.5
+CODE_BYTES_STORED = 1.0
 
 
-def stage_work(pl, name: str, level: int, precision: str):
+def stage_work(pl, name: str, level: int, precision: str, code_bytes: float = CODE_BYTES):
     """Algorithmic work of one launch: (bound, amount, unit).  FLOPs for the
     correlation on the matrix cores when it is the bound, HBM bytes otherwise."""
     gx, gy, h, w = list(pl.gx), list(pl.gy), list(pl.h), list(pl.w)
     L = pl.lmax
+    cb = code_bytes
     # maps stored at level 0: one per atomic patch, or one per prototype
     npat = lambda l: (pl.prototypes or gx[0] * gy[0]) if l == 0 else gx[l] * gy[l]
     if name == "kmeans_assign":   # FP32 MFMA dot products of every patch with every centroid
         return "mfma", 2.0 * pl.n_atomic * pl.prototypes * 144, "FLOP"
     if name.startswith("corr_pool"):
         flops = 2.0 * npat(0) * pl.H2 * pl.W2 * 144
-        out_bytes = npat(0) * h[1] * w[1] * 5.0
+        out_bytes = npat(0) * h[1] * w[1] * (4.0 + cb)
         if precision == "fp32":
             return "mfma", flops, "FLOP"
         return "hbm", out_bytes, "B"
     if name == "level":
         rd = npat(level - 1) * h[level] * w[level] * 4.0
-        wr = npat(level) * (h[level] * w[level] * 4.0 if level == L else h[level + 1] * w[level + 1] * 5.0)
+        wr = npat(level) * (h[level] * w[level] * 4.0 if level == L else h[level + 1] * w[level + 1] * (4.0 + cb))
         return "hbm", rd + wr, "B"
     if name == "backtrack":
-        rd = npat(level - 1) * h[level] * w[level] * (5.0 if level == 1 else 4.0)
-        rd += npat(level) * (h[level] * w[level] * 4.0 if level == L else h[level + 1] * w[level + 1] * 5.0)
+        rd = npat(level - 1) * h[level] * w[level] * (4.0 + cb if level == 1 else 4.0)
+        rd += npat(level) * (h[level] * w[level] * 4.0 if level == L else h[level + 1] * w[level + 1] * (4.0 + cb))
         wr = 0.0 if level == 1 else npat(level - 1) * h[level] * w[level] * 4.0
         return "hbm", rd + wr, "B"
     if name == "descriptor":   # one launch for both images: 4 B in, 36 B out (+ 20 B BF16 copy) per pixel
         return "hbm", (pl.W1 * pl.H1 + pl.W2 * pl.H2) * (40.0 + (20.0 if precision == "bf16" else 0.0)), "B"
     return "hbm", 0.0, "B"
+
+
+def _sha256(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of a kernel at 512x256 from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE profile (its JSON block), scaled by the plain-copy
+    calibration recorded there; None when the profile lacks the kernel or the
+    kernel's source file has changed since the counters were taken."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        prof = json.loads(block)
+    except (OSError, IndexError, ValueError):
+        return None
+    k = prof.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    src = os.path.join(ROOT, "paper_1506_07656_amd", "csrc", k["source"])
+    if not os.path.exists(src) or _sha256(src) != k["source_sha256"]:
+        return None
+    cal = prof["calibration"]
+    return k["fetch_kib"] * 1024.0 * cal["read_factor"] + k["write_kib"] * 1024.0 * cal["write_factor"]
 
 
 def roofline_of(stages, pl, precision):
@@ -96,9 +121,13 @@ def roofline_of(stages, pl, precision):
             ach = amount / (avg_ms * 1e-3) / 1e9
             peak = HBM_PEAK_GBS
             u = "GB/s"
-        rows.append(dict(kernel=f"{name}{'' if level < 0 else '_l%d' % level}", bound=bound, avg_ms=avg_ms,
-                         launches=count, achieved=ach, peak=peak, unit=u, frac=ach / peak if peak else None,
-                         work=amount))
+        row = dict(kernel=f"{name}{'' if level < 0 else '_l%d' % level}", bound=bound, avg_ms=avg_ms,
+                   launches=count, achieved=ach, peak=peak, unit=u, frac=ach / peak if peak else None, work=amount)
+        if unit == "B":
+            stored = stage_work(pl, name, level, precision, CODE_BYTES_STORED)[1]
+            row["stored_achieved"] = stored / (avg_ms * 1e-3) / 1e9
+            row["stored_frac"] = row["stored_achieved"] / peak if peak else None
+        rows.append(row)
     rows.sort(key=lambda r: -r["avg_ms"] * r["launches"])
     return rows
 
@@ -164,44 +193,47 @@ def within_1px(a, b):
     return ok / max(1, len(b))
 
 
-def cpu_baseline(pair, cw=384, ch=192):
-    """The FP64 oracle on the central cw x ch crop of the pair, scaled to a
-    full pair by the method's O(L L') cost (factor (W H)^2 / (cw ch)^2)."""
-    import numpy as np
-    from oracle import dm_oracle as O
+def _blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        return max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
-        cores = os.cpu_count()
+        return os.cpu_count()
+
+
+def cpu_baseline(pair, cw=128, ch=128):
+    """The FP64 oracle from images to matches on the full pair (the
+    benchmark's workload), with every BLAS thread of the host; beside it the
+    central cw x ch crop with every thread and with one (the paper's CPU
+    timings are for one core), the thread count checked inside the limit."""
+    import numpy as np
+    from oracle import dm_oracle as O
+    cores = _blas_threads()
     H, W = pair["img1"].shape
+    t0 = time.perf_counter()
+    O.match(pair["img1"], pair["img2"], O.Params())
+    t = time.perf_counter() - t0
     y0, x0 = (H - ch) // 2, (W - cw) // 2
     c1 = np.ascontiguousarray(pair["img1"][y0:y0 + ch, x0:x0 + cw])
     c2 = np.ascontiguousarray(pair["img2"][y0:y0 + ch, x0:x0 + cw])
-    t0 = time.perf_counter()
-    O.match(c1, c2, O.Params())
-    t = time.perf_counter() - t0
-    scale = (W * H) ** 2 / (cw * ch) ** 2
-    # The 64x64 pair in full, with every thread and with one (the paper's
-    # CPU timings are for one core).
-    import synth
-    small = synth.make_pair("c1")
     t1 = time.perf_counter()
-    O.match(small["img1"], small["img2"], O.Params(max_patch=32))
-    t_small = time.perf_counter() - t1
-    t_small_1 = None
+    O.match(c1, c2, O.Params())
+    t_crop = time.perf_counter() - t1
+    t_crop_1, threads_1 = None, None
     try:
         from threadpoolctl import threadpool_limits
         with threadpool_limits(limits=1):
+            threads_1 = _blas_threads()
             t1 = time.perf_counter()
-            O.match(small["img1"], small["img2"], O.Params(max_patch=32))
-            t_small_1 = round(time.perf_counter() - t1, 3)
+            O.match(c1, c2, O.Params())
+            t_crop_1 = round(time.perf_counter() - t1, 3)
     except Exception:
         pass
-    return dict(value=1.0 / (t * scale), unit="pairs/s", cores=int(cores), kind="oracle",
-                sample=f"oracle (FP64 NumPy) descriptors-to-matches on the central {cw}x{ch} crop of the {W}x{H} "
-                       f"pair: {t:.1f} s, scaled by the O(LL') cost ratio {scale:.0f} to a full pair",
-                c1_64x64_s=round(t_small, 3), c1_64x64_s_one_thread=t_small_1, host=host_info())
+    return dict(value=1.0 / t, unit="pairs/s", cores=int(cores), kind="oracle",
+                sample=f"oracle (FP64 NumPy) from images to reciprocal matches on the whole {W}x{H} pair, "
+                       f"{t:.1f} s with {cores} BLAS threads",
+                crop=f"central {cw}x{ch} crop of the pair", crop_s=round(t_crop, 3), crop_s_one_thread=t_crop_1,
+                one_thread_blas_threads=threads_1, host=host_info())
 
 
 def host_info():
@@ -242,15 +274,20 @@ def pair_work(pl):
     gx, gy, h, w, L = list(pl.gx), list(pl.gy), list(pl.h), list(pl.w), pl.lmax
     npat = lambda l: gx[l] * gy[l]
     by = (pl.W1 * pl.H1 + pl.W2 * pl.H2) * (4 + 36 + 20)                 # descriptors: image in, FP32 + BF16 out
-    by += pl.n_atomic * h[1] * w[1] * 5.0                                   # C'_0 + codes out of the correlation
+    by += pl.n_atomic * h[1] * w[1] * (4.0 + CODE_BYTES)                    # C'_0 + codes out of the correlation
     for l in range(1, L + 1):
         by += stage_work(pl, "level", l, "bf16")[1] + stage_work(pl, "backtrack", l, "bf16")[1]
     fl = 2.0 * pl.n_atomic * pl.H2 * pl.W2 * 144
-    npos = pl.H2 * pl.W2
-    bb = npat(L) * h[L] * w[L] * 8.0                                          # top + its gradient
+    cb = CODE_BYTES
+    # backward: the top and its gradient; per level adjoint, the pooled child
+    # values (for the rectification factor) read and their gradient written,
+    # the parent gradient and codes read; the bottom reads the pooled
+    # gradient and codes of level 0 once and both descriptor fields, and
+    # writes both gradients.
+    bb = npat(L) * h[L] * w[L] * 8.0
     for l in range(1, L + 1):
-        bb += npat(l - 1) * h[l] * w[l] * (4 + 4 + 1) + (npat(l) * h[l + 1] * w[l + 1] * 5.0 if l < L else 0)
-    bb += pl.n_atomic * npos * 2 * 3.0 + (pl.W1 * pl.H1 + pl.W2 * pl.H2) * 9 * 4 * 2   # dense dA: write + 2 reads
+        bb += npat(l - 1) * h[l] * w[l] * (4 + 4) + (npat(l) * h[l + 1] * w[l + 1] * (4.0 + cb) if l < L else 0)
+    bb += pl.n_atomic * h[1] * w[1] * (4.0 + cb) + (pl.W1 * pl.H1 + pl.W2 * pl.H2) * 9 * 4 * 2
     return by, fl, bb, 2 * fl
 
 
@@ -356,6 +393,29 @@ def approx_bench(dm, torch, img1, img2, exact_matches, exact_plan, steps, warmup
     return res
 
 
+def dmstar_bench(dm, torch, img1, img2, plain_matches, plain_ms, steps, warmup):
+    """DM* entry points (Sec. 3.3, Table 1's middle configuration) on the same
+    pair: local maxima of every level start the backtracking, path-sum
+    scores; BF16 correlation.  Entry counts of the pooled levels come from
+    the marks the library leaves in the codes."""
+    dt, matches, stages, pl = time_path(dm, torch, img1, img2, "bf16", steps, warmup, entry_points="local_maxima")
+    m = dm.Matcher(img1.shape[1], img1.shape[0], img2.shape[1], img2.shape[0],
+                   dm.params(precision="bf16", entry_points="local_maxima"))
+    m.run_images(img1, img2)
+    torch.cuda.synchronize()
+    views = dm.workspace_views(m.ws, m.plan)
+    entries = [int(((lv["code"] & 0x10) != 0).sum().item()) for lv in views["levels"]]
+    del m
+    rows = roofline_of(stages, pl, "bf16")
+    return dict(pairs_s=round(1.0 / dt, 3), ms_per_step=round(dt * 1e3, 4), vs_plain_ms=round(plain_ms, 4),
+                matches=int(len(matches)), plain_matches=int(len(plain_matches)),
+                plain_matches_within_1px=round(within_1px(matches, plain_matches), 5),
+                entries_per_pooled_level=entries,
+                top_kernels=[(r["kernel"], round(r["avg_ms"] * r["launches"] / steps, 4)) for r in rows[:6]],
+                workload="the same 512x256 pair; entry points at the local maxima of every level, path-sum "
+                         "scores; BF16 correlation, FP32 pyramid")
+
+
 def invariant_bench(dm, torch, img1, img2, plain_ms, steps, warmup):
     """Algorithm 2 on the pair: the full 9 x 8 grid, and per-stage times."""
     prm = dm.params(precision="bf16")
@@ -457,6 +517,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-pair uneven batch")
     ap.add_argument("--no-approx", action="store_true", help="skip approximate DeepMatching")
     ap.add_argument("--no-invariant", action="store_true", help="skip scale and rotation invariant DeepMatching")
+    ap.add_argument("--no-dmstar", action="store_true", help="skip the DM* entry points")
     ap.add_argument("--only", choices=("all", "fwd_bf16", "fwd_bwd_bf16", "approx1024", "approx64", "invariant",
                                        "batch_fwd"),
                     default="all",
@@ -570,14 +631,17 @@ def main():
                                             for n, l, c, t in fb["fp32"]["stages"]], key=lambda x: -x[1])[:6],
         "roofline": {"bound": dom["bound"], "kernel": dom["kernel"], "achieved": round(dom["achieved"], 2),
                      "peak": dom["peak"], "unit": dom["unit"], "frac": round(dom["frac"], 4),
-                     "traffic": MEASURED_TRAFFIC_512x256.get(dom["kernel"]),
+                     "traffic": measured_traffic(dom["kernel"]),
                      "algorithmic_bytes": round(dom["work"]) if dom["unit"] == "GB/s" else None,
                      "avg_ms": round(dom["avg_ms"], 5),
+                     # the same launch counted with the one-byte codes the library stores
+                     "stored_achieved": round(dom.get("stored_achieved", 0.0), 2) or None,
+                     "stored_frac": round(dom["stored_frac"], 4) if dom.get("stored_frac") else None,
                      # context: the bandwidth a plain 1 GiB copy reaches on this GPU
                      "copy_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(dom["achieved"] / copy_gbs, 4) if dom["unit"] == "GB/s" else None},
         "kernels_bf16": [dict({k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items() if k != "work"},
-                              traffic=MEASURED_TRAFFIC_512x256.get(r["kernel"])) for r in rows],
+                              traffic=measured_traffic(r["kernel"])) for r in rows],
         "kernels_fp32": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items() if k != "work"}
                          for r in rows32[:4]],
     }
@@ -586,6 +650,8 @@ def main():
         out["approx"] = approx_bench(dm, torch, img1, img2, head["matches"], head["plan"], args.steps, args.warmup)
     if not args.no_invariant:
         out["invariant"] = invariant_bench(dm, torch, img1, img2, head["ms"], args.steps, args.warmup)
+    if not args.no_dmstar:
+        out["dmstar"] = dmstar_bench(dm, torch, img1, img2, head["matches"], head["ms"], args.steps, args.warmup)
     if not args.no_batch:
         out["batch"] = batch_bench(dm, torch, max(3, args.steps // 2))
     if not args.no_cpu_baseline:
