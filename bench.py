@@ -519,7 +519,7 @@ def main():
     ap.add_argument("--no-invariant", action="store_true", help="skip scale and rotation invariant DeepMatching")
     ap.add_argument("--no-dmstar", action="store_true", help="skip the DM* entry points")
     ap.add_argument("--only", choices=("all", "fwd_bf16", "fwd_bwd_bf16", "approx1024", "approx64", "invariant",
-                                       "batch_fwd"),
+                                       "batch_fwd", "batch_fwd_bwd"),
                     default="all",
                     help="run only that pass (short profiler runs); prints no JSON line")
     args = ap.parse_args()
@@ -556,11 +556,11 @@ def main():
         dt, _, _, _ = time_path(dm, torch, img1, img2, "bf16", args.steps, args.warmup, prototypes=D)
         print(f"approximate (D={D}) bf16 forward: {dt * 1e3:.3f} ms/pair", flush=True)
         return
-    if args.only == "batch_fwd":   # the 32-pair uneven batch, forward only, autotuned, one graph replay per step
+    if args.only in ("batch_fwd", "batch_fwd_bwd"):   # the 32-pair uneven batch, autotuned, one graph replay per step
         import synth
         pairs = synth.make_batch(32)
         sizes = [(p["img1"].shape[1], p["img1"].shape[0], p["img2"].shape[1], p["img2"].shape[0]) for p in pairs]
-        F = dm.Batch(sizes, dm.params(precision="bf16"), bwd=False, graph=True, autotune=True)
+        F = dm.Batch(sizes, dm.params(precision="bf16"), bwd=args.only == "batch_fwd_bwd", graph=True, autotune=True)
         F.set_images([torch.from_numpy(p["img1"]).cuda() for p in pairs],
                      [torch.from_numpy(p["img2"]).cuda() for p in pairs])
         for _ in range(max(1, args.warmup)):
@@ -570,7 +570,7 @@ def main():
         for _ in range(args.steps):
             F.run()
         torch.cuda.synchronize()
-        print(f"batch of 32 forward: {(time.perf_counter() - t0) / args.steps * 1e3:.3f} ms", flush=True)
+        print(f"batch of 32 {args.only[6:]}: {(time.perf_counter() - t0) / args.steps * 1e3:.3f} ms", flush=True)
         F.release()
         return
     if args.only == "fwd_bwd_bf16":
