@@ -354,6 +354,14 @@ dm_status dm_pyramid_backward(const void* d1, int W1, int H1, const void* d2, in
  *                     heights of the streaming level and backtracking
  *                     kernels, resident blocks per CU of each grouped launch)
  *                     on this batch and keep the fastest (dm_batch_tiles_get).
+ *                     Tuned tiles persist in a JSON file, the path in the
+ *                     environment variable DM_TILE_CACHE (default
+ *                     $HOME/.cache/dm_mi355x/tiles.json; set to "" to turn
+ *                     the file off), keyed by precision, direction and a size
+ *                     bucket (pair count, largest target width and height,
+ *                     total pixels, each rounded up to a power of two); a
+ *                     batch whose key is there takes those tiles untimed.
+ *                     A file that cannot be read or written is ignored.
  * The schedule (job tables in the workspace, tiles, graph) is cached per
  * workspace and rebuilt when any argument changes.  Precisions DM_FP32 and
  * DM_BF16; every pair needs at least one pooled level (N_max >= 8). */
@@ -383,8 +391,8 @@ typedef struct {
     int32_t level_rows;          /* pooled rows per band, streaming level kernel  */
     int32_t bt_rows;             /* rows per band, streaming backtracking kernel  */
     int32_t blocks_per_cu[32];   /* resident blocks per CU, per grouped kernel kind */
-    int32_t tuned;               /* 1 if the autotuner chose these values         */
-    float tuned_ms;              /* forward time of the batch with them (tuner)   */
+    int32_t tuned;               /* 0 defaults, 1 tuned on this batch, 2 read from the tile cache */
+    float tuned_ms;              /* time of the batch with them when tuned        */
 } dm_batch_tiles;
 
 /* Sizes of a batch of n pairs (1 <= n <= DM_MAX_BATCH).  Host only; reads

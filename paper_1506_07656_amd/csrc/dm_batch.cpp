@@ -15,13 +15,17 @@
 // per CU of each grouped launch, one parameter at a time (each stage can be
 // re-run on its own: it rewrites its outputs from inputs that stay put, and
 // the bottom reduction takes maxima, so a re-run leaves the same values).
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "dm_group.h"
@@ -96,7 +100,7 @@ int default_res(int kind) {
 struct Tiles {
     int level_rows = 16, bt_rows = 32;
     int res[JK_COUNT];
-    bool tuned = false;
+    int tuned = 0;   // 0: defaults, 1: tuned on this batch, 2: read from the tile cache
     float tuned_ms = 0.f;
     Tiles() {
         for (int k = 0; k < JK_COUNT; ++k) res[k] = default_res(k);
@@ -429,9 +433,134 @@ dm_status autotune(Schedule& S, int n, const dm_pair* pairs, const dm_params* pr
         }
         S.tiles.res[kind] = bestv;
     }
-    S.tiles.tuned = true;
+    S.tiles.tuned = 1;
     S.tiles.tuned_ms = time_runs(S, ws, s, nullptr, true, reps);
     return DM_OK;
+}
+
+// ---------------------------------------------------------------- tile cache
+// Tuned tiles persist in a JSON file (DM_TILE_CACHE, else
+// $HOME/.cache/dm_mi355x/tiles.json; DM_TILE_CACHE set to "" turns it off),
+// keyed by precision, direction and a size bucket: the pair count and the
+// largest target width and height rounded up to powers of two, and the
+// total pixel count to its power of two.  The file holds one entry per line
+// (this writer's own layout, read back line by line); an unreadable or
+// foreign entry is skipped and re-tuned.
+std::string tile_cache_path() {
+    const char* e = getenv("DM_TILE_CACHE");
+    if (e) return std::string(e);
+    const char* home = getenv("HOME");
+    return home && *home ? std::string(home) + "/.cache/dm_mi355x/tiles.json" : std::string();
+}
+
+std::string tile_key(int n, const dm_pair* pairs, const dm_params* prm, int flags) {
+    auto pow2 = [](long v) {
+        long p = 1;
+        while (p < v) p <<= 1;
+        return p;
+    };
+    long wmax = 0, hmax = 0, area = 0;
+    for (int k = 0; k < n; ++k) {
+        wmax = std::max<long>(wmax, pairs[k].W2);
+        hmax = std::max<long>(hmax, pairs[k].H2);
+        area += (long)pairs[k].W1 * pairs[k].H1 + (long)pairs[k].W2 * pairs[k].H2;
+    }
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s/%s/n%ld/w%ld/h%ld/a%ld/k%d", prm->precision == DM_BF16 ? "bf16" : "fp32",
+             (flags & DM_BATCH_BWD) ? "fwd_bwd" : "fwd", pow2(n), pow2(wmax), pow2(hmax), pow2(area), (int)JK_COUNT);
+    return std::string(buf);
+}
+
+// The cache's entries: key -> line.
+std::map<std::string, std::string> tile_cache_read(const std::string& path) {
+    std::map<std::string, std::string> m;
+    FILE* f = fopen(path.c_str(), "r");
+    if (!f) return m;
+    char line[1024];
+    const char tag[] = "{\"key\": \"";
+    while (fgets(line, sizeof line, f)) {
+        const char* a = strstr(line, tag);
+        if (!a) continue;
+        a += sizeof(tag) - 1;
+        const char* b = strchr(a, '"');
+        if (!b) continue;
+        std::string l(line);
+        while (!l.empty() && (l.back() == '\n' || l.back() == ',' || l.back() == '\r')) l.pop_back();
+        m[std::string(a, b)] = l;
+    }
+    fclose(f);
+    return m;
+}
+
+bool tile_cache_parse(const std::string& line, Tiles& t) {
+    auto num = [&](const char* field, double& v) {
+        const char* p = strstr(line.c_str(), field);
+        if (!p) return false;
+        char* end = nullptr;
+        v = strtod(p + strlen(field), &end);
+        return end != p + strlen(field);
+    };
+    double lr, br, ms;
+    if (!num("\"level_rows\": ", lr) || !num("\"bt_rows\": ", br) || !num("\"tuned_ms\": ", ms)) return false;
+    const char* r = strstr(line.c_str(), "\"res\": [");
+    if (!r) return false;
+    r += strlen("\"res\": [");
+    Tiles u;
+    for (int k = 0; k < JK_COUNT; ++k) {
+        char* end = nullptr;
+        const long v = strtol(r, &end, 10);
+        if (end == r || v < 1 || v > 16) return false;
+        u.res[k] = (int)v;
+        r = end;
+        while (*r == ',' || *r == ' ') ++r;
+    }
+    const int cand[4] = {8, 16, 32, 64};
+    if (std::find(cand, cand + 4, (int)lr) == cand + 4 || std::find(cand, cand + 4, (int)br) == cand + 4) return false;
+    u.level_rows = (int)lr;
+    u.bt_rows = (int)br;
+    u.tuned = 2;
+    u.tuned_ms = (float)ms;
+    t = u;
+    return true;
+}
+
+bool tile_cache_lookup(const std::string& key, Tiles& t) {
+    const std::string path = tile_cache_path();
+    if (path.empty()) return false;
+    const auto m = tile_cache_read(path);
+    const auto it = m.find(key);
+    return it != m.end() && tile_cache_parse(it->second, t);
+}
+
+// Adds or replaces the entry (written to a temporary file, then renamed
+// over the cache).  Failures to write are ignored: the cache is an
+// optimisation.
+void tile_cache_store(const std::string& key, const Tiles& t) {
+    const std::string path = tile_cache_path();
+    if (path.empty()) return;
+    auto m = tile_cache_read(path);
+    std::string l = "{\"key\": \"" + key + "\", \"level_rows\": " + std::to_string(t.level_rows) +
+                    ", \"bt_rows\": " + std::to_string(t.bt_rows) + ", \"res\": [";
+    for (int k = 0; k < JK_COUNT; ++k) l += (k ? ", " : "") + std::to_string(t.res[k]);
+    char ms[32];
+    snprintf(ms, sizeof ms, "%.4f", t.tuned_ms);
+    l += std::string("], \"tuned_ms\": ") + ms + "}";
+    m[key] = l;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) {   // create the directory chain
+        std::string dir = path.substr(0, slash);
+        for (size_t i = 1; i <= dir.size(); ++i)
+            if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+    }
+    const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fprintf(f, "{\"format\": \"dm_mi355x tiles 1\", \"entries\": [\n");
+    size_t i = 0;
+    for (const auto& kv : m) fprintf(f, "%s%s\n", kv.second.c_str(), ++i < m.size() ? "," : "");
+    fprintf(f, "]}\n");
+    const bool ok = fclose(f) == 0;
+    if (!ok || rename(tmp.c_str(), path.c_str()) != 0) (void)remove(tmp.c_str());
 }
 
 std::vector<unsigned char> make_key(int n, const dm_pair* pairs, const dm_params* prm, int flags, size_t ws_bytes,
@@ -525,9 +654,11 @@ dm_status dm_match_batch(int n, const dm_pair* pairs, const dm_params* prm, int 
         uint64_t end;
         if ((st = plan_pairs(n, pairs, prm, flags, fresh->P, end)) != DM_OK) return st;
         fresh->table_off = end;
-        if (flags & DM_BATCH_AUTOTUNE) {
+        const std::string tkey = tile_key(n, pairs, prm, flags);
+        if ((flags & DM_BATCH_AUTOTUNE) && !tile_cache_lookup(tkey, fresh->tiles)) {
             if ((st = autotune(*fresh, n, pairs, prm, flags, ws, out, out_offsets_host, n_out, stream)) != DM_OK)
                 return st;
+            tile_cache_store(tkey, fresh->tiles);
         } else {
             Builder B;
             build(n, pairs, prm, flags, fresh->P, fresh->table_off, ws, out, out_offsets_host, n_out, fresh->tiles, B);
@@ -567,7 +698,7 @@ dm_status dm_batch_tiles_get(const void* ws, dm_batch_tiles* out) {
     out->level_rows = t.level_rows;
     out->bt_rows = t.bt_rows;
     for (int k = 0; k < JK_COUNT && k < 32; ++k) out->blocks_per_cu[k] = t.res[k];
-    out->tuned = t.tuned ? 1 : 0;
+    out->tuned = t.tuned;
     out->tuned_ms = t.tuned_ms;
     return DM_OK;
 }

@@ -198,7 +198,13 @@ def test_batch_backward_equals_single_pyramid():
     B.release()
 
 
-def test_autotuner_keeps_results():
+def test_autotuner_keeps_results(tmp_path, monkeypatch):
+    """The tuner changes launch shapes only; its tiles persist in the tile
+    cache (DM_TILE_CACHE), from which a second batch of the same size bucket
+    takes them untimed, with the same matches."""
+    import json
+    cache = tmp_path / "tiles.json"
+    monkeypatch.setenv("DM_TILE_CACHE", str(cache))
     i1, i2 = batch_images()
     T = dm.Batch(SIZES, dm.params(precision="bf16"), graph=True, autotune=True)
     T.set_images(i1, i2)
@@ -210,3 +216,26 @@ def test_autotuner_keeps_results():
     for k, g in enumerate(T.matches()):
         assert torch.equal(g, ref[k]), k
     T.release()
+    entries = json.loads(cache.read_text())["entries"]
+    assert len(entries) == 1 and entries[0]["level_rows"] == t.level_rows and entries[0]["bt_rows"] == t.bt_rows
+    assert entries[0]["key"].startswith("bf16/fwd/n8/")
+    # a second batch of the same bucket reads the tiles from the cache
+    T2 = dm.Batch(SIZES, dm.params(precision="bf16"), graph=True, autotune=True)
+    T2.set_images(i1, i2)
+    T2.run()
+    t2 = T2.tiles()
+    assert t2.tuned == 2 and (t2.level_rows, t2.bt_rows) == (t.level_rows, t.bt_rows)
+    assert list(t2.blocks_per_cu) == list(t.blocks_per_cu)
+    for k, g in enumerate(T2.matches()):
+        assert torch.equal(g, ref[k]), k
+    T2.release()
+    # a foreign or damaged file is ignored and rewritten
+    cache.write_text("not json\n")
+    T3 = dm.Batch(SIZES, dm.params(precision="bf16"), graph=False, autotune=True)
+    T3.set_images(i1, i2)
+    T3.run()
+    assert T3.tiles().tuned == 1
+    for k, g in enumerate(T3.matches()):
+        assert torch.equal(g, ref[k]), k
+    T3.release()
+    assert len(json.loads(cache.read_text())["entries"]) == 1
