@@ -316,7 +316,7 @@ __device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, int nbytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, nbytes, 0x00020000);
 }
 
-template <bool RECT, int TILE, bool BOTTOM>
+template <bool RECT, int TILE, bool BOTTOM, bool DMSTAR = false>
 __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __restrict__ cp_prev,
                                       const uint8_t* __restrict__ code_prev, const float* __restrict__ u_cur,
                                       const uint8_t* __restrict__ code_cur, const uint8_t* __restrict__ vt,
@@ -370,7 +370,7 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
         const __amdgpu_buffer_rsrc_t rsU = rsrc(u_cur, nparent * usz * 4), rsM = rsrc(code_cur, nparent * usz);
         const size_t cmap = (size_t)child_slot(g, a.l, c) * csz;
         const __amdgpu_buffer_rsrc_t rsC = rsrc(cp_prev + cmap, csz * 4);
-        const __amdgpu_buffer_rsrc_t rsK = rsrc(code_prev + cmap, BOTTOM ? csz : 0);
+        const __amdgpu_buffer_rsrc_t rsK = rsrc(code_prev + cmap, (BOTTOM || DMSTAR) ? csz : 0);
         // Element offset of each parent's map, or a large negative value for a
         // missing parent: with a lane's row offset added (also large negative
         // when the lane or row has no U_l entry), an entry exists exactly when
@@ -420,6 +420,7 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
                 const float v =
                     __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsU, ok ? off * 4 : kOOB, 0, 0));
                 st.m[p] = __builtin_amdgcn_raw_buffer_load_b8(rsM, ok ? off : kOOB, 0, 0);
+                if constexpr (DMSTAR) st.m[p] &= 15;   // codes of a pooled level carry the entry mark above bit 3
                 st.u[p] = ok ? v : -1.f;
             }
         };
@@ -441,10 +442,12 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
                 const int ry = 2 * rp - 2 + dy;
                 const bool rok = ry >= R0 && ry < R1;                          // uniform
                 o.vb[dy] = (rok && lane_o) ? atomicExch(&ring[ry & (kBtRing - 1)][t], 0u) : 0u;
-                const int off = ry * a.w + rx;   // element offset in the child's map, used only where a tuple arrived
-                o.cv[dy] = __uint_as_float(
-                    __builtin_amdgcn_raw_buffer_load_b32(rsC, o.vb[dy] ? off * 4 : kOOB, 0, 0));
-                o.cm[dy] = __builtin_amdgcn_raw_buffer_load_b8(rsK, o.vb[dy] ? off : kOOB, 0, 0);
+                // element offset in the child's map, used only where a tuple
+                // arrived (DM*: at every cell, which may be an entry point)
+                const int off = ry * a.w + rx;
+                const bool need = DMSTAR ? (rok && lane_o) : o.vb[dy] != 0u;
+                o.cv[dy] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsC, need ? off * 4 : kOOB, 0, 0));
+                o.cm[dy] = __builtin_amdgcn_raw_buffer_load_b8(rsK, need ? off : kOOB, 0, 0);
             }
         };
         auto finish = [&](int rp, const OBuf& o) {
@@ -452,12 +455,15 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
             for (int dy = 0; dy < 2; ++dy) {
                 const int ry = 2 * rp - 2 + dy;
                 if (ry < R0 || ry >= R1 || !lane_o) continue;
-                const uint32_t vb = o.vb[dy];
+                uint32_t vb = o.vb[dy];
+                // DM*: an entry point where no tuple arrives starts one with its own value
+                if constexpr (DMSTAR)
+                    if (!vb && (o.cm[dy] & kEntryBit)) vb = enc(0.f);
                 if constexpr (!BOTTOM) {
                     u_prev[((size_t)c * a.h + ry) * a.w + rx] = vb ? o.cv[dy] + dec(vb) : -INFINITY;
                 } else if (vb) {
                     const float uu = o.cv[dy] + dec(vb);
-                    const int mm = o.cm[dy];
+                    const int mm = DMSTAR ? (o.cm[dy] & 15) : o.cm[dy];
                     const int xy = 2 * ry + code_my(mm) - 1, xx = 2 * rx + code_mx(mm) - 1;
                     const unsigned long long hi = (unsigned long long)__float_as_uint(uu) << 32;
                     if constexpr (RECT) {
@@ -672,20 +678,52 @@ __global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __rest
 }
 
 // DM* entry points: kEntryBit on the codes of the local maxima of C'_l (maps
-// of existing patches only).
-__global__ void k_mark_entries(const float* __restrict__ cp, uint8_t* __restrict__ code,
-                               const uint8_t* __restrict__ vt, Geom g, int l) {
+// of existing patches only).  Block = (patch, band of kMarkRows rows, 256
+// columns); a thread owns one column and walks down the band with the 3 x 3
+// neighbourhood in registers, loading the three values of the next row (its
+// left and right ones are the neighbouring threads' centres, served by the
+// cache).  Neighbours outside the map are -inf, which every comparison
+// passes: the same decision as local_max, which skips them.
+constexpr int kMarkRows = 32;
+__global__ __launch_bounds__(256) void k_mark_entries(const float* __restrict__ cp, uint8_t* __restrict__ code,
+                                                      const uint8_t* __restrict__ vt, Geom g, int l, int nxt,
+                                                      int nband) {
     const int h = g.h[l + 1], w = g.w[l + 1];
-    const size_t pm = (size_t)h * w, n = (size_t)g.gx[l] * g.gy[l] * pm;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int c = (int)(i / pm), r = (int)(i - (size_t)c * pm), y = r / w, x = r - y * w;
+    const int bid = blockIdx.x;
+    const int xt = bid % nxt, rest = bid / nxt, band = rest % nband, c = rest / nband;   // uniform
     const int cb = c / g.gx[l], ca = c - cb * g.gx[l];
     if (!vtab(vt, g, l, 0)[ca] || !vtab(vt, g, l, 1)[cb]) return;
-    if (local_max(cp + (size_t)c * pm, h, w, y, x)) code[i] |= kEntryBit;
+    const int x = xt * 256 + (int)threadIdx.x;
+    if (x >= w) return;
+    const size_t pm = (size_t)h * w;
+    const float* __restrict__ m = cp + (size_t)c * pm;
+    uint8_t* __restrict__ k = code + (size_t)c * pm;
+    const int y0 = band * kMarkRows, y1 = min(y0 + kMarkRows, h);
+    auto row = [&](int y, float& vl, float& vc, float& vr) {
+        if (y < 0 || y >= h) {
+            vl = vc = vr = -INFINITY;
+            return;
+        }
+        const float* p = m + (size_t)y * w + x;
+        vc = p[0];
+        vl = x > 0 ? p[-1] : -INFINITY;
+        vr = x + 1 < w ? p[1] : -INFINITY;
+    };
+    float ul, uc, ur, ml, mc, mr, dl, dc, dr;
+    row(y0 - 1, ul, uc, ur);
+    row(y0, ml, mc, mr);
+    for (int y = y0; y < y1; ++y) {
+        row(y + 1, dl, dc, dr);
+        const float v = mc;
+        // before it in raster order: strictly above; after it: not below
+        const bool e = v > 0.f && v > ul && v > uc && v > ur && v > ml && v >= mr && v >= dl && v >= dc && v >= dr;
+        if (e) k[(size_t)y * w + x] |= kEntryBit;
+        ul = ml, uc = mc, ur = mr;
+        ml = dl, mc = dc, mr = dr;
+    }
 }
 
-template <bool RECT, int TILE, bool BOTTOM>
+template <bool RECT, int TILE, bool BOTTOM, bool DMSTAR = false>
 __global__ __launch_bounds__(64 * kBtWaves) void k_backtrack_stream(
     BtStreamArgs a, const float* __restrict__ cp_prev, const uint8_t* __restrict__ code_prev,
     const float* __restrict__ u_cur, const uint8_t* __restrict__ code_cur, const uint8_t* __restrict__ vt, Geom g,
@@ -693,7 +731,8 @@ __global__ __launch_bounds__(64 * kBtWaves) void k_backtrack_stream(
     int nblocks) {
     const int bid = xcd_block(nblocks);
     if (bid >= nblocks) return;
-    bt_stream_body<RECT, TILE, BOTTOM>(a, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, best, cell, bid);
+    bt_stream_body<RECT, TILE, BOTTOM, DMSTAR>(a, cp_prev, code_prev, u_cur, code_cur, vt, g, u_prev, best, cell,
+                                               bid);
 }
 
 template <bool RECT>
@@ -862,24 +901,29 @@ template <>
 hipError_t launch_backtrack<float>(int l, const float* cp_prev, const uint8_t* code_prev, const float* u_cur,
                                    const uint8_t* code_cur, const float* top, const uint8_t* vt, const Geom& g,
                                    float* u_prev, uint64_t* best, uint64_t* cell, hipStream_t s) {
-    if (!g.dmstar && use_bt_stream(l, g)) {
+    if (use_bt_stream(l, g) && !(g.dmstar && g.rect.on)) {
         int nb;
         const BtStreamArgs b = make_bt_stream_args(l, g, kBtTR, nb);
         auto* b64 = (unsigned long long*)best;
         auto* c64 = (unsigned long long*)cell;
         const dim3 grid(((nb + 7) / 8) * 8), block(64 * kBtWaves);
-#define DM_BT_STREAM(R, T, B)                                                                                   \
-    hipLaunchKernelGGL((k_backtrack_stream<R, T, B>), grid, block, 0, s, b, cp_prev, code_prev, u_cur, code_cur, \
+#define DM_BT_STREAM(R, T, B, D)                                                                                    \
+    hipLaunchKernelGGL((k_backtrack_stream<R, T, B, D>), grid, block, 0, s, b, cp_prev, code_prev, u_cur, code_cur, \
                        vt, g, u_prev, b64, c64, nb)
         // The rectified (invariant) form differs from the plain one at the bottom level only.
-        if (b.is_bottom) {
-            if (g.rect.on && b.tile == 60) DM_BT_STREAM(true, 60, true);
-            else if (g.rect.on) DM_BT_STREAM(true, 64, true);
-            else if (b.tile == 60) DM_BT_STREAM(false, 60, true);
-            else DM_BT_STREAM(false, 64, true);
+        if (g.dmstar) {
+            if (b.is_bottom && b.tile == 60) DM_BT_STREAM(false, 60, true, true);
+            else if (b.is_bottom) DM_BT_STREAM(false, 64, true, true);
+            else if (b.tile == 60) DM_BT_STREAM(false, 60, false, true);
+            else DM_BT_STREAM(false, 64, false, true);
+        } else if (b.is_bottom) {
+            if (g.rect.on && b.tile == 60) DM_BT_STREAM(true, 60, true, false);
+            else if (g.rect.on) DM_BT_STREAM(true, 64, true, false);
+            else if (b.tile == 60) DM_BT_STREAM(false, 60, true, false);
+            else DM_BT_STREAM(false, 64, true, false);
         } else {
-            if (b.tile == 60) DM_BT_STREAM(false, 60, false);
-            else DM_BT_STREAM(false, 64, false);
+            if (b.tile == 60) DM_BT_STREAM(false, 60, false, false);
+            else DM_BT_STREAM(false, 64, false, false);
         }
 #undef DM_BT_STREAM
         return hipGetLastError();
@@ -1000,9 +1044,12 @@ hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t s) {
 
 hipError_t launch_mark_entries(int l, const float* cp, uint8_t* code, const uint8_t* vt, const Geom& g,
                                hipStream_t s) {
-    const size_t n = (size_t)g.gx[l] * g.gy[l] * g.h[l + 1] * g.w[l + 1];
-    if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_mark_entries, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cp, code, vt, g, l);
+    const int h = g.h[l + 1], w = g.w[l + 1], np = g.gx[l] * g.gy[l];
+    if (!h || !w || !np) return hipSuccess;
+    const int nxt = (w + 255) / 256, nband = (h + kMarkRows - 1) / kMarkRows;
+    const long long nb = (long long)np * nband * nxt;
+    if (nb >= (1ll << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mark_entries, dim3((unsigned)nb), dim3(256), 0, s, cp, code, vt, g, l, nxt, nband);
     return hipGetLastError();
 }
 
