@@ -419,6 +419,83 @@ dm_status dm_batch_tiles_get(const void* ws, dm_batch_tiles* out);
  * or reusing ws for other data.  Errors: none. */
 dm_status dm_batch_release(const void* ws);
 
+/* ---------------------------------------------------------------- DeepFlow
+ * Variational refinement of a flow field w = (u, v) from I to I' with
+ * DeepMatching's matches as its matching term (Sec. 4.3, Eqs. (17)-(19)):
+ * E(w) = int E_D + alpha(x) E_S + beta c phi Psi(|w - w'|^2), with E_D the
+ * normalised colour (weight delta) and gradient (weight gamma) constancy
+ * terms, E_S = Psi(|grad u|^2 + |grad v|^2), alpha(x) = exp(-kappa
+ * |grad I|), Psi(s^2) = sqrt(s^2 + eps^2).  Solved coarse to fine (factor
+ * eta, down to a smaller side of min_size) with incremental warping,
+ * n_fixed fixed-point iterations per level and n_sor red-black SOR sweeps
+ * (relaxation omega) per fixed point; beta^k = beta (k / k_max)^b at level k
+ * (0 = finest).  phi = sqrt(lam_scale lambda_min) / (sigma_M sqrt(2 pi))
+ * exp(-Delta / (2 sigma_M)) per match.  Images are grayscale in [0, 1],
+ * smoothed by a Gaussian of standard deviation sigma.  The library's
+ * readings of what the paper leaves open are listed in k_deepflow.hip. */
+#define DM_FLOW_MAX_LEVELS 128
+
+typedef struct {
+    float sigma;        /* pre-smoothing (0.5)                               */
+    float eta;          /* downsampling factor between levels (0.95)         */
+    int32_t min_size;   /* smaller side of the coarsest level, at least (16) */
+    int32_t n_fixed;    /* fixed-point iterations per level (5)              */
+    int32_t n_sor;      /* SOR sweeps per fixed point (25)                   */
+    float omega;        /* SOR relaxation (1.6)                              */
+    float kappa;        /* alpha(x) = exp(-kappa |grad I|) (5)               */
+    float beta;         /* matching weight (300)                             */
+    float b;            /* exponent of beta^k (0.6)                          */
+    float gamma;        /* gradient constancy weight (0.8)                   */
+    float delta;        /* colour constancy weight (0)                       */
+    float eps;          /* Psi's epsilon (0.001)                             */
+    float zeta;         /* data-term normalisation (0.1)                     */
+    float sigma_m;      /* phi's sigma_M (50)                                */
+    float lam_scale;    /* lambda~ = lam_scale x the smaller eigenvalue (10) */
+    int32_t reserved[4];
+} dm_flow_params;
+
+typedef struct {
+    int32_t n_levels;                 /* levels 0 (finest) .. n_levels - 1 */
+    int32_t W[DM_FLOW_MAX_LEVELS];    /* level sizes                       */
+    int32_t H[DM_FLOW_MAX_LEVELS];
+    uint64_t workspace_bytes;         /* for dm_deepflow                   */
+} dm_flow_info;
+
+/* The paper's parameters (the values in parentheses above).  Errors:
+ * DM_ERR_INVALID_ARG (null pointer). */
+dm_status dm_flow_default_params(dm_flow_params* p);
+
+/* Level sizes and workspace of DeepFlow on W x H images with at most
+ * max_matches matches.  Host only.  Errors: DM_ERR_INVALID_ARG (parameters
+ * out of range: sigma in (0, 7/3], eta in (0, 1), omega in (0, 2), ...),
+ * DM_ERR_SHAPE (empty or more than 2^26 pixels, or more than
+ * DM_FLOW_MAX_LEVELS levels). */
+dm_status dm_flow_plan(int W, int H, int max_matches, const dm_flow_params* p, dm_flow_info* out);
+
+#define DM_FLOW_GRAPH 1
+
+/* Flow from img1 to img2 (device, W x H, leading dimension ld, intensities
+ * in [0, 1]) into flow (device, H x W x 2, (u, v) per pixel, row-major).
+ * matches (device) holds max_matches entries of which the first
+ * min(*n_matches, max_matches) are used (n_matches on the device, as
+ * dm_match_images leaves it); a match (x1, y1) -> (x2, y2) states
+ * w'(x1, y1) = (x2 - x1, y2 - y1).  max_matches = 0: no matching term (the
+ * match pointers may be null).  ws (device, 256-byte aligned) holds
+ * workspace_bytes of dm_flow_plan; it and flow belong to the caller.  All
+ * work is enqueued on stream.  flags: DM_FLOW_GRAPH captures the launches
+ * (several thousand small kernels) into a HIP graph on the first call and
+ * replays it while every argument stays the same (stream must not be the
+ * null stream; the graph is kept per workspace until dm_flow_release).
+ * Errors: those of dm_flow_plan, DM_ERR_INVALID_ARG, DM_ERR_WORKSPACE,
+ * DM_ERR_HIP. */
+dm_status dm_deepflow(const float* img1, const float* img2, int W, int H, int ld, const dm_match* matches,
+                      const int32_t* n_matches, int max_matches, const dm_flow_params* p, int flags, float* flow,
+                      void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Drops the graph kept for workspace ws (DM_FLOW_GRAPH); call before freeing
+ * or reusing ws.  Errors: none. */
+dm_status dm_flow_release(const void* ws);
+
 /* Per-stage timing (for benchmarks and profiling).  While enabled, every
  * kernel launch the library makes is bracketed by two HIP events recorded on
  * the stream of the call, so the measured time is that kernel's own time on

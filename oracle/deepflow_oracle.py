@@ -58,7 +58,8 @@ library takes the same ones):
      x - w' is taken as the target x + w'.  The exponent is -Delta /
      (2 sigma_M).  At level k a match sits at the nearest level pixel of its
      source, its flow scaled by the level's size ratios; where several land
-     on one pixel the one with the larger phi is kept (ties: the first).
+     on one pixel the first in the match list is kept (a rule that depends
+     on the order only, not on the rounding of phi).
  D8  beta^k = beta (k / k_max)^b with k = 0 the finest level (no matching
      term there) and beta^0 = beta when there is a single level.
 
@@ -212,10 +213,11 @@ def match_field(matches, phi, W, H, Wk, Hk):
     taken = np.zeros((Hk, Wk), dtype=bool)
     for i in range(len(matches)):
         x1, y1, x2, y2 = (float(v) for v in matches[i, :4])
-        # nearest level pixel of the source centre (x1 + 0.5) sx - 0.5
-        xk = min(max(int(math.floor((x1 + 0.5) * sx)), 0), Wk - 1)
-        yk = min(max(int(math.floor((y1 + 0.5) * sy)), 0), Hk - 1)
-        if taken[yk, xk] and phi[i] <= cphi[yk, xk]:
+        # nearest level pixel of the source centre (x1 + 0.5) sx - 0.5:
+        # floor((2 x1 + 1) Wk / (2 W)), in integers (negative sources clamp to 0)
+        xk = min(max((2 * int(x1) + 1) * Wk // (2 * W), 0), Wk - 1)
+        yk = min(max((2 * int(y1) + 1) * Hk // (2 * H), 0), Hk - 1)
+        if taken[yk, xk]:
             continue
         taken[yk, xk] = True
         up[yk, xk], vp[yk, xk], cphi[yk, xk] = (x2 - x1) * sx, (y2 - y1) * sy, phi[i]

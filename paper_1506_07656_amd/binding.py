@@ -107,6 +107,21 @@ class BatchTiles(ctypes.Structure):
                 ("tuned", c_int32), ("tuned_ms", c_float)]
 
 
+DM_FLOW_MAX_LEVELS = 128
+
+
+class FlowParams(ctypes.Structure):
+    _fields_ = [("sigma", c_float), ("eta", c_float), ("min_size", c_int32), ("n_fixed", c_int32),
+                ("n_sor", c_int32), ("omega", c_float), ("kappa", c_float), ("beta", c_float), ("b", c_float),
+                ("gamma", c_float), ("delta", c_float), ("eps", c_float), ("zeta", c_float),
+                ("sigma_m", c_float), ("lam_scale", c_float), ("reserved", c_int32 * 4)]
+
+
+class FlowInfo(ctypes.Structure):
+    _fields_ = [("n_levels", c_int32), ("W", c_int32 * DM_FLOW_MAX_LEVELS), ("H", c_int32 * DM_FLOW_MAX_LEVELS),
+                ("workspace_bytes", c_uint64)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/dm.h.
 SIGNATURES = {
     "dm_default_params": (c_int, [POINTER(Params)]),
@@ -134,6 +149,11 @@ SIGNATURES = {
     "dm_match_invariant": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_int, c_int, POINTER(Params),
                                    ctypes.c_uint32, ctypes.c_uint32, c_void_p, c_size_t, c_void_p, c_int, c_void_p,
                                    c_void_p]),
+    "dm_flow_default_params": (c_int, [POINTER(FlowParams)]),
+    "dm_flow_plan": (c_int, [c_int, c_int, c_int, POINTER(FlowParams), POINTER(FlowInfo)]),
+    "dm_deepflow": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_int,
+                            POINTER(FlowParams), c_int, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "dm_flow_release": (c_int, [c_void_p]),
     "dm_timing_enable": (c_int, [c_int]),
     "dm_timing_read": (c_int, [POINTER(StageTime), c_int, POINTER(c_int)]),
     "dm_status_string": (c_char_p, [c_int]),
@@ -285,6 +305,118 @@ def match_images_noalloc(img1: torch.Tensor, img2: torch.Tensor, prm: Params | N
                                          c_void_p(buf.data_ptr()), pl.max_matches, c_void_p(n_out.data_ptr()),
                                          _stream()))
     return _matches_tensor(buf, int(n_out.item()))
+
+
+def flow_params(**kw) -> FlowParams:
+    """The paper's DeepFlow parameters (dm_flow_default_params), with overrides."""
+    p = FlowParams()
+    _check(lib().dm_flow_default_params(ctypes.byref(p)))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def flow_plan(W: int, H: int, max_matches: int = 0, prm: FlowParams | None = None) -> FlowInfo:
+    info = FlowInfo()
+    _check(lib().dm_flow_plan(W, H, max_matches, ctypes.byref(prm or flow_params()), ctypes.byref(info)))
+    return info
+
+
+def deepflow(img1: torch.Tensor, img2: torch.Tensor, matches: torch.Tensor | None = None,
+             n_matches: torch.Tensor | None = None, prm: FlowParams | None = None,
+             ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Flow (H x W x 2) from img1 to img2 (H x W float32 images in [0, 1])
+    with DeepMatching's matches: an n x 4 or n x 5 device tensor of rows
+    (x1, y1, x2, y2[, score]) as match_images returns them (any dtype; the
+    coordinates are rounded to whole pixels), or the library's own n x 5
+    int32 records; n_matches optionally a device count that limits how many
+    rows are used."""
+    prm = prm or flow_params()
+    img1 = _dev(img1, torch.float32, 2, "img1")
+    img2 = _dev(img2, torch.float32, 2, "img2")
+    if img1.shape != img2.shape:
+        raise ValueError("DeepFlow needs two images of one size")
+    H, W = img1.shape
+    if matches is None:
+        matches = torch.zeros((0, 5), dtype=torch.int32, device=img1.device)
+    if not matches.is_cuda or matches.dim() != 2 or matches.shape[1] not in (4, 5):
+        raise ValueError("matches must be an n x 4 or n x 5 device tensor")
+    if matches.dtype != torch.int32 or matches.shape[1] != 5:   # marshal into dm_match records
+        rec = torch.zeros((matches.shape[0], 5), dtype=torch.int32, device=matches.device)
+        rec[:, :4] = torch.round(matches[:, :4].to(torch.float64)).to(torch.int32)
+        if matches.shape[1] == 5:
+            rec[:, 4] = matches[:, 4].to(torch.float32).view(torch.int32)
+        matches = rec
+    matches = matches.contiguous()
+    nm = matches.shape[0]
+    if n_matches is None:
+        n_matches = torch.full((1,), nm, dtype=torch.int32, device=img1.device)
+    info = flow_plan(W, H, nm, prm)
+    ws = torch.empty(int(info.workspace_bytes), dtype=torch.uint8, device=img1.device) if ws is None else ws
+    flow = torch.empty((H, W, 2), dtype=torch.float32, device=img1.device)
+    _check(lib().dm_deepflow(c_void_p(img1.data_ptr()), c_void_p(img2.data_ptr()), W, H, img1.stride(0),
+                             c_void_p(matches.data_ptr() if nm else None),
+                             c_void_p(n_matches.data_ptr() if nm else None), nm, ctypes.byref(prm), 0,
+                             c_void_p(flow.data_ptr()), c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return flow
+
+
+DM_FLOW_GRAPH = 1
+
+
+class DeepFlow:
+    """Repeated DeepFlow on W x H pairs with up to max_matches matches, its
+    launches captured into one HIP graph (DM_FLOW_GRAPH) and replayed.  The
+    inputs, workspace and output live here so that every call presents the
+    same arguments; set() copies a pair (and its matches) in, run() enqueues
+    the flow on a side stream of default priority, joined with the current
+    stream on entry and exit."""
+
+    def __init__(self, W: int, H: int, max_matches: int, prm: FlowParams | None = None, graph: bool = True,
+                 device="cuda"):
+        self.W, self.H, self.max_matches = W, H, max_matches
+        self.prm = prm or flow_params()
+        self.flags = DM_FLOW_GRAPH if graph else 0
+        self.img1 = torch.zeros((H, W), dtype=torch.float32, device=device)
+        self.img2 = torch.zeros((H, W), dtype=torch.float32, device=device)
+        self.matches = torch.zeros((max(1, max_matches), 5), dtype=torch.int32, device=device)
+        self.n = torch.zeros(1, dtype=torch.int32, device=device)
+        info = flow_plan(W, H, max_matches, self.prm)
+        self.ws = torch.empty(int(info.workspace_bytes), dtype=torch.uint8, device=device)
+        self.flow = torch.zeros((H, W, 2), dtype=torch.float32, device=device)
+        self.stream = torch.cuda.Stream(device=device)
+
+    def set(self, img1: torch.Tensor, img2: torch.Tensor, matches: torch.Tensor | None = None,
+            n_matches: torch.Tensor | None = None):
+        """Copies the images and the first rows of matches (as deepflow()
+        takes them) in; n_matches (device) may limit the count further."""
+        self.img1.copy_(img1)
+        self.img2.copy_(img2)
+        k = 0 if matches is None else min(int(matches.shape[0]), self.max_matches)
+        if k:
+            rec = torch.zeros((k, 5), dtype=torch.int32, device=self.img1.device)
+            rec[:, :4] = torch.round(matches[:k, :4].to(torch.float64)).to(torch.int32)
+            self.matches[:k].copy_(rec)
+        self.n.fill_(k)
+        if n_matches is not None:
+            torch.minimum(self.n, n_matches.to(torch.int32).reshape(1), out=self.n)
+
+    def run(self) -> torch.Tensor:
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        with torch.cuda.stream(self.stream):
+            _check(lib().dm_deepflow(c_void_p(self.img1.data_ptr()), c_void_p(self.img2.data_ptr()), self.W, self.H,
+                                     self.W, c_void_p(self.matches.data_ptr()), c_void_p(self.n.data_ptr()),
+                                     self.max_matches, ctypes.byref(self.prm), self.flags,
+                                     c_void_p(self.flow.data_ptr()), c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                     c_void_p(self.stream.cuda_stream)))
+        cur.wait_stream(self.stream)
+        return self.flow
+
+    def release(self):
+        lib().dm_flow_release(c_void_p(self.ws.data_ptr()))
 
 
 def plan_invariant(W1: int, H1: int, W2: int, H2: int, prm: Params | None = None, scales_mask: int = 0x1FF,

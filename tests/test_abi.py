@@ -339,3 +339,49 @@ def test_match_invariant_validation_before_any_launch():
     assert call(prm=dm.params(precision="fp64")) == -5
     assert call(prm=dm.params(prototypes=4)) == -5
     assert b"prototypes" in L.dm_last_error()
+
+
+def test_flow_params_and_plan_against_the_oracle():
+    """dm_flow_default_params holds the paper's values (Sec. 4.3 and its
+    parameter study) and dm_flow_plan the oracle's level sizes."""
+    from oracle import deepflow_oracle as F
+    p, q = dm.flow_params(), F.FlowParams()
+    for name in ("sigma", "eta", "min_size", "n_fixed", "n_sor", "omega", "kappa", "beta", "b", "gamma", "delta",
+                 "eps", "zeta", "sigma_m", "lam_scale"):
+        assert abs(getattr(p, name) - getattr(q, name)) <= 1e-6 * max(1.0, abs(getattr(q, name))), name
+    for W, H in ((64, 56), (512, 256), (128, 96), (17, 40), (16, 16)):
+        info = dm.flow_plan(W, H, 100)
+        sizes = F.level_sizes(W, H, q)
+        assert info.n_levels == len(sizes)
+        assert [(info.W[k], info.H[k]) for k in range(info.n_levels)] == sizes
+        assert info.workspace_bytes > 8 * W * H * 4
+
+
+def test_deepflow_validation_before_any_launch():
+    L = dm.lib()
+    p = dm.flow_params()
+    info = dm.FlowInfo()
+    img, ws, fl = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x100000), ctypes.c_void_p(0x2000)
+    big = ctypes.c_size_t(1 << 40)
+    # parameters out of range
+    for k, v in (("sigma", 0.0), ("sigma", 3.0), ("eta", 1.0), ("omega", 2.0), ("min_size", 1), ("eps", 0.0),
+                 ("n_sor", -1), ("beta", -1.0)):
+        q = dm.flow_params(**{k: v})
+        assert L.dm_flow_plan(64, 64, 0, ctypes.byref(q), ctypes.byref(info)) == -1, k
+    assert L.dm_flow_plan(0, 64, 0, ctypes.byref(p), ctypes.byref(info)) == -2
+    assert L.dm_flow_plan(64, 64, -1, ctypes.byref(p), ctypes.byref(info)) == -1
+    assert L.dm_flow_plan(64, 64, 0, ctypes.byref(p), None) == -1
+    # a level count past the limit
+    assert L.dm_flow_plan(1 << 12, 1 << 12, 0, ctypes.byref(dm.flow_params(eta=0.999)), ctypes.byref(info)) == -2
+    # null pointers, leading dimension, workspace size and alignment
+    assert L.dm_deepflow(None, img, 64, 64, 64, None, None, 0, ctypes.byref(p), 0, fl, ws, big, None) == -1
+    assert L.dm_deepflow(img, img, 64, 64, 63, None, None, 0, ctypes.byref(p), 0, fl, ws, big, None) == -2
+    assert L.dm_deepflow(img, img, 64, 64, 64, None, None, 10, ctypes.byref(p), 0, fl, ws, big, None) == -1
+    assert L.dm_deepflow(img, img, 64, 64, 64, None, None, 0, ctypes.byref(p), 0, fl, ctypes.c_void_p(0x100010), big,
+                         None) == -1
+    assert L.dm_deepflow(img, img, 64, 64, 64, None, None, 0, ctypes.byref(p), 0, fl, ws, ctypes.c_size_t(1024),
+                         None) == -3
+    # unknown flags; a graph needs a stream of its own
+    assert L.dm_deepflow(img, img, 64, 64, 64, None, None, 0, ctypes.byref(p), 4, fl, ws, big, None) == -1
+    assert L.dm_deepflow(img, img, 64, 64, 64, None, None, 0, ctypes.byref(p), 1, fl, ws, big, None) == -1
+    assert L.dm_flow_release(ws) == 0

@@ -150,11 +150,11 @@ def test_min_eigenvalue_against_lapack():
             assert np.isclose(lam[y, x], np.linalg.eigvalsh(M)[0], rtol=1e-9, atol=1e-9 * M.max())
 
 
-def test_match_field_keeps_the_best_match_per_pixel():
+def test_match_field_keeps_the_first_match_per_pixel():
     m = np.array([[10, 10, 12, 9], [11, 10, 15, 10], [40, 20, 41, 20]], np.float64)
     phi = np.array([0.2, 0.5, 0.1])
     up, vp, cphi = F.match_field(m, phi, 64, 32, 32, 16)   # half size: (10,10) and (11,10) meet at (5,5)
-    assert cphi[5, 5] == 0.5 and up[5, 5] == 2.0 and vp[5, 5] == 0.0
+    assert cphi[5, 5] == 0.2 and up[5, 5] == 1.0 and vp[5, 5] == -0.5
     assert cphi[10, 20] == 0.1 and up[10, 20] == 0.5
     assert (cphi > 0).sum() == 2
 
