@@ -416,6 +416,75 @@ def dmstar_bench(dm, torch, img1, img2, plain_matches, plain_ms, steps, warmup):
                          "scores; BF16 correlation, FP32 pyramid")
 
 
+def deepflow_bench(dm, torch, pair, img1, img2, matches, steps, warmup):
+    """DeepFlow (Sec. 4.3) on the pair with the BF16 matches: time per pair
+    (eager launches; with the launch graph beside it), the stage breakdown,
+    the roofline of the SOR half-sweeps, and the end-point error against the
+    pair's ground-truth field next to that of the matches themselves."""
+    import numpy as np
+    H, W = img1.shape
+    f = dm.deepflow(img1, img2, matches)
+    for _ in range(max(0, warmup - 1)):
+        f = dm.deepflow(img1, img2, matches)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f = dm.deepflow(img1, img2, matches)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    R = dm.DeepFlow(W, H, int(matches.shape[0]), graph=True)
+    R.set(img1, img2, matches)
+    R.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        R.run()
+    torch.cuda.synchronize()
+    dt_graph = (time.perf_counter() - t0) / steps
+    R.release()
+    dm.timing_enable(True)
+    dm.deepflow(img1, img2, matches)
+    torch.cuda.synchronize()
+    rows = dm.timing_read()
+    dm.timing_enable(False)
+    agg = {}
+    for name, level, count, ms in rows:
+        a = agg.setdefault(name, [0, 0.0])
+        a[0] += count
+        a[1] += ms
+    # SOR half-sweep of an n-pixel level: every pixel's smoothness weight,
+    # flow and increment read (neighbours), the updating half's five system
+    # entries read and its increment written: 34 n bytes.
+    info = dm.flow_plan(W, H, int(matches.shape[0]))
+    prm = dm.flow_params()
+    small = 2048
+    sor_bytes = sum(34.0 * info.W[k] * info.H[k] * 2 * prm.n_sor * prm.n_fixed
+                    for k in range(info.n_levels) if info.W[k] * info.H[k] > small)
+    sor_ms = agg.get("df_sor", [0, 0.0])[1]
+    ach = sor_bytes / (sor_ms * 1e-3) / 1e9 if sor_ms else 0.0
+    # end-point errors against the ground truth (interior, 16 px margin)
+    flow = f.cpu().numpy()
+    ys, xs = np.mgrid[16:H - 16, 16:W - 16]
+    qx, qy = pair["flow"](xs.astype(np.float64), ys.astype(np.float64))
+    epe = np.hypot(flow[16:H - 16, 16:W - 16, 0] - (qx - xs), flow[16:H - 16, 16:W - 16, 1] - (qy - ys))
+    m = matches.cpu().numpy()
+    mx, my = m[:, 0], m[:, 1]
+    mqx, mqy = pair["flow"](mx, my)
+    m_epe = np.hypot(m[:, 2] - mqx, m[:, 3] - mqy)
+    return dict(ms_per_pair=round(dt * 1e3, 3), pairs_s=round(1.0 / dt, 3), ms_per_pair_graph=round(dt_graph * 1e3, 3),
+                levels=int(info.n_levels), matches=int(matches.shape[0]),
+                stage_ms={k: round(v[1], 3) for k, v in sorted(agg.items(), key=lambda kv: -kv[1][1])[:6]},
+                launches=int(sum(v[0] for v in agg.values())),
+                sor_roofline={"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(ach / HBM_PEAK_GBS, 4), "launches": int(agg.get("df_sor", [0])[0]),
+                              "avg_us": round(sor_ms * 1e3 / max(1, agg.get("df_sor", [1])[0]), 2)},
+                epe_px={"mean": round(float(epe.mean()), 3), "median": round(float(np.median(epe)), 3),
+                        "within_1px": round(float((epe < 1).mean()), 4)},
+                match_epe_px={"mean": round(float(m_epe.mean()), 3), "median": round(float(np.median(m_epe)), 3)},
+                workload="DeepFlow on the 512x256 pair, matches from the BF16 path, the paper's parameters "
+                         "(eta 0.95: %d levels, 5 fixed points x 25 SOR sweeps per level), FP32" % info.n_levels)
+
+
 def invariant_bench(dm, torch, img1, img2, plain_ms, steps, warmup):
     """Algorithm 2 on the pair: the full 9 x 8 grid, and per-stage times."""
     prm = dm.params(precision="bf16")
@@ -518,6 +587,7 @@ def main():
     ap.add_argument("--no-approx", action="store_true", help="skip approximate DeepMatching")
     ap.add_argument("--no-invariant", action="store_true", help="skip scale and rotation invariant DeepMatching")
     ap.add_argument("--no-dmstar", action="store_true", help="skip the DM* entry points")
+    ap.add_argument("--no-deepflow", action="store_true", help="skip DeepFlow")
     ap.add_argument("--only", choices=("all", "fwd_bf16", "fwd_bwd_bf16", "approx1024", "approx64", "invariant",
                                        "batch_fwd", "batch_fwd_bwd"),
                     default="all",
@@ -652,6 +722,10 @@ def main():
         out["invariant"] = invariant_bench(dm, torch, img1, img2, head["ms"], args.steps, args.warmup)
     if not args.no_dmstar:
         out["dmstar"] = dmstar_bench(dm, torch, img1, img2, head["matches"], head["ms"], args.steps, args.warmup)
+    if not args.no_deepflow:
+        out["deepflow"] = deepflow_bench(dm, torch, pair, img1, img2, torch.from_numpy(head["matches"]).cuda()
+                                         if not torch.is_tensor(head["matches"]) else head["matches"],
+                                         max(2, args.steps // 4), args.warmup)
     if not args.no_batch:
         out["batch"] = batch_bench(dm, torch, max(3, args.steps // 2))
     if not args.no_cpu_baseline:
