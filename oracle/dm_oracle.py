@@ -112,6 +112,14 @@ library takes the same ones):
      raster order (one maximum per plateau, since pooling repeats values in
      adjacent cells); an entry starts with its map value, tuples from above
      and entries merge by max at equal (N, p, p').
+ R26 DM*'s start/end-point scoring (Sec. 5, the comparison with the earlier
+     version, says only that an atomic correspondence was scored from the
+     correlation values at the start and the end of its backtracking path):
+     the score is the path sum of Eq. (14) restricted to the path's first
+     and last nodes, i.e. the entry's value plus the atomic value C'_0 the
+     path ends on (a path of one node, an entry at the bottom level, counts
+     its value once); equal (N, p, p') still merge by max, which is exact
+     because the end value depends on the atomic node alone.
 
 Parity of the descriptor against the paper itself is unpinned (R10 fills in
 details the paper does not give); it is pinned only by its invariants.
@@ -147,6 +155,10 @@ class Params:
     # 0 = every position of the top level; 1 = the earlier scheme (DM*,
     # compared in Table 1), local maxima of the maps of every level (R24).
     entry_points: int = 0
+    # Scores of the atomic correspondences: 0 = the sum over the whole
+    # backtracking path (Eq. (14)); 1 = the earlier scheme of Table 1, the
+    # values at the path's start and end only (R26).
+    scoring: int = 0
 
 
 # ----------------------------------------------------------------------------
@@ -542,8 +554,12 @@ def _dedup_max(key: np.ndarray, s: np.ndarray):
     return keep, gap
 
 
-def backtrack(pyr: Pyramid, entries=None, level_entries=None):
+def backtrack(pyr: Pyramid, entries=None, level_entries=None, start_end: bool = False):
     """M' = B o ... o B (M), Eq. (15), merging equal (N, p, p') by max.
+
+    start_end: score by the values at the start and end of each path (R26):
+    B carries the score unchanged above the bottom level and adds the atomic
+    value C'_0 in its last step.
 
     Entry points are all top-level (p, p') (Sec. 3.3, "Merging
     correspondences"), or the tuples of `level_entries` (a dict level ->
@@ -586,7 +602,8 @@ def backtrack(pyr: Pyramid, entries=None, level_entries=None):
             out["a"].append(ca)
             out["qy"].append(2 * ry + (k // 3 - 1))        # p'_i = 2(p' + o_i) + m_i, Eq. (13)
             out["qx"].append(2 * rx + (k % 3 - 1))
-            out["s"].append(s[ok] + pyr.Cp[lv - 1][cb, ca, ry, rx])   # Eq. (14)
+            step = pyr.Cp[lv - 1][cb, ca, ry, rx]
+            out["s"].append(s[ok] if start_end and lv > 1 else s[ok] + step)   # Eq. (14); R26
             out["m"].append(np.minimum(margin[ok], risky(pyr.gap[lv - 1][cb, ca, ry, rx])))
         if level_entries is not None:   # the entries of level lv - 1 join before the merge
             for k, e in zip(("b", "a", "qy", "qx", "s", "m"), level_entries[lv - 1]):
@@ -601,7 +618,8 @@ def backtrack(pyr: Pyramid, entries=None, level_entries=None):
 
 # ----------------------------------------------------------------------------
 # Entry points of the earlier DeepMatching (DM*, Sec. 3.3 and Table 1): local
-# maxima of the correlation maps of every level, scored by path sums (R24)
+# maxima of the correlation maps of every level, scored by path sums (R24) or by
+# the values at the start and end of each path (R26)
 # ----------------------------------------------------------------------------
 
 def local_maxima(M: np.ndarray, ids: np.ndarray | None = None):
@@ -724,7 +742,8 @@ def match_descriptors(D1: np.ndarray, D2: np.ndarray, prm: Params = Params()):
     # DM* entries need the value identities of pooling_stability, which read
     # the maps before rectification above level 0
     pyr = pyramid(D1, D2, prm, keep_full=bool(prm.entry_points), keep_bottom=False)
-    M = backtrack(pyr, level_entries=dmstar_entries(pyr) if prm.entry_points else None)
+    M = backtrack(pyr, level_entries=dmstar_entries(pyr) if prm.entry_points else None,
+                  start_end=prm.scoring == 1)
     out, margin = reciprocal(M, pyr.W, pyr.H, pyr.W2, pyr.H2)
     return out, margin, pyr, M
 

@@ -540,6 +540,52 @@ def test_dmstar_equals_unmerged_enumeration():
     assert all(got[k] <= plain[k] + 1e-13 for k in got if k in plain)
 
 
+def test_start_end_scoring_equals_unmerged_enumeration():
+    """R26: every entry of every level expanded without merging; an atomic
+    correspondence scores its entry's value plus the value of C_0 (read in the
+    unpooled map) at the node its path ends on, once for a one-node path; the
+    max per (p, p') is the merged start/end backtracking, tuple for tuple."""
+    rng = np.random.default_rng(9)
+    img1 = synth.blurred_noise(rng, 24, 24)
+    img2 = synth.shift_reflect(img1, 1, 2) + rng.normal(0, 0.05, (24, 24))
+    prm = O.Params(max_patch=16)
+    pyr = O.pyramid(O.descriptors(img1, prm), O.descriptors(img2, prm), prm, keep_full=True)
+    E = O.dmstar_entries(pyr)
+    best = {}
+    for lv in range(pyr.lmax + 1):
+        for b, a, qy, qx, s in zip(*E[lv][:5]):
+            leaves = []
+            _enumerate(pyr, lv, int(b), int(a), int(qy), int(qx), 0.0, [], leaves)
+            for lb, la, ly, lx, _, path in leaves:
+                end = float(O.rectify(pyr.A[0][lb, la, ly, lx], pyr.lam)) if path else 0.0
+                k = (lb, la, ly, lx)
+                best[k] = max(best.get(k, -np.inf), float(s) + end)
+    M = O.backtrack(pyr, level_entries=E, start_end=True)
+    got = {(b, a, y, x): s for b, a, y, x, s in zip(M["b"], M["a"], M["qy"], M["qx"], M["s"])}
+    assert set(got) == set(best)
+    for k in best:
+        assert abs(got[k] - best[k]) < 1e-13
+    # path sums add the non-negative values in between: never below, equal
+    # for paths of at most two nodes (entries at levels 0 and 1), and above
+    # for many of those from higher entries
+    P = O.backtrack(pyr, level_entries=E)
+    ps = {(b, a, y, x): s for b, a, y, x, s in zip(P["b"], P["a"], P["qy"], P["qx"], P["s"])}
+    assert set(ps) == set(got)
+    assert all(ps[k] >= got[k] - 1e-13 for k in got)
+    assert sum(ps[k] > got[k] + 1e-9 for k in got) > len(got) // 4
+
+
+def test_start_end_scoring_recovers_translation():
+    p = synth.make_pair("c1")
+    i1 = p["img1"].astype(np.float64)
+    i2 = synth.shift_reflect(i1, 5, -3)
+    out, margin, pyr, M = O.match(i1, i2, O.Params(max_patch=32, entry_points=1, scoring=1))
+    x1, y1 = out[:, 0], out[:, 1]
+    inner = (x1 >= 8) & (x1 < 64 - 8 - 5) & (y1 >= 8 + 3) & (y1 < 64 - 8)
+    assert inner.sum() > 100
+    assert (out[inner, 2] == x1[inner] + 5).all() and (out[inner, 3] == y1[inner] - 3).all()
+
+
 def test_dmstar_recovers_translation():
     p = synth.make_pair("c1")
     i1 = p["img1"].astype(np.float64)
