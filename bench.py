@@ -22,7 +22,9 @@ union), BF16 correlation.
 
 The "dmstar" entry is the earlier entry-point scheme (DM*, Sec. 3.3 and
 Table 1): local maxima of every level start the backtracking, scored by the
-current path sums; entry counts and agreement with the plain method.
+current path sums; entry counts and agreement with the plain method; and
+the same entry points with the earlier start/end-point scores (Table 1's
+first configuration), time and agreement beside it.
 
 The "batch" entry is the uneven-batch workload: 32 pairs with W ~ U{128..621},
 H ~ U{96..188} (half of a 1242x375 driving-frame shape), BF16 correlation,
@@ -407,13 +409,18 @@ def dmstar_bench(dm, torch, img1, img2, plain_matches, plain_ms, steps, warmup):
     entries = [int(((lv["code"] & 0x10) != 0).sum().item()) for lv in views["levels"]]
     del m
     rows = roofline_of(stages, pl, "bf16")
+    dt_se, m_se, _, _ = time_path(dm, torch, img1, img2, "bf16", steps, warmup, entry_points="local_maxima",
+                                  scoring="start_end")
     return dict(pairs_s=round(1.0 / dt, 3), ms_per_step=round(dt * 1e3, 4), vs_plain_ms=round(plain_ms, 4),
                 matches=int(len(matches)), plain_matches=int(len(plain_matches)),
                 plain_matches_within_1px=round(within_1px(matches, plain_matches), 5),
                 entries_per_pooled_level=entries,
                 top_kernels=[(r["kernel"], round(r["avg_ms"] * r["launches"] / steps, 4)) for r in rows[:6]],
+                start_end=dict(pairs_s=round(1.0 / dt_se, 3), ms_per_step=round(dt_se * 1e3, 4),
+                               matches=int(len(m_se)),
+                               plain_matches_within_1px=round(within_1px(m_se, plain_matches), 5)),
                 workload="the same 512x256 pair; entry points at the local maxima of every level, path-sum "
-                         "scores; BF16 correlation, FP32 pyramid")
+                         "scores (start_end: start/end-point scores); BF16 correlation, FP32 pyramid")
 
 
 def deepflow_bench(dm, torch, pair, img1, img2, matches, steps, warmup):

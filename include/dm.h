@@ -94,7 +94,8 @@ typedef struct {
     int32_t prototypes;         /* D of approximate DeepMatching, 0 = exact     */
     int32_t kmeans_iters;       /* k-means rounds (prototypes > 0), 0..1000     */
     int32_t entry_points;       /* DM_ENTRIES_TOP or DM_ENTRIES_LOCAL_MAXIMA    */
-    int32_t reserved[4];        /* must be 0 */
+    int32_t scoring;            /* DM_SCORE_PATH_SUM or DM_SCORE_START_END      */
+    int32_t reserved[3];        /* must be 0 */
 } dm_params;
 
 /* Entry points of the backtracking (Sec. 3.3, "Merging correspondences").
@@ -112,9 +113,23 @@ typedef struct {
 #define DM_ENTRIES_TOP 0
 #define DM_ENTRIES_LOCAL_MAXIMA 1
 
+/* Scores of the atomic correspondences.  DM_SCORE_PATH_SUM: the sum of the
+ * correlation values along the whole backtracking path (Eq. (14), the
+ * method of the paper).  DM_SCORE_START_END: the earlier scheme of Table 1
+ * (Sec. 5), which scored a correspondence from the values at the start and
+ * the end of its path only: here the entry's value plus the atomic value
+ * C'_0 the path ends on (an entry at the bottom level counts its value
+ * once), equal (N, p, p') merging by max as before.  Table 1 pairs it with
+ * the local-maxima entry points, and so does this library:
+ * DM_SCORE_START_END requires entry_points = DM_ENTRIES_LOCAL_MAXIMA
+ * (DM_ERR_UNSUPPORTED otherwise). */
+#define DM_SCORE_PATH_SUM 0
+#define DM_SCORE_START_END 1
+
 /* One correspondence: atomic patch centre p = (x1, y1) in I, pixel
  * p' = (x2, y2) in I', score s = the top-level value plus the pooled child
- * values along the backtracking path (Eq. (14)). */
+ * values along the backtracking path (Eq. (14)); with DM_SCORE_START_END the
+ * entry's value plus the atomic value at the path's end. */
 typedef struct {
     int32_t x1, y1, x2, y2;
     float score;

@@ -653,7 +653,8 @@ def local_maxima(M: np.ndarray, ids: np.ndarray | None = None):
             v = P[..., 1 + dy:1 + dy + h, 1 + dx:1 + dx + w]
             ok = (M > v) if (dy, dx) < (0, 0) else (M >= v)
             mask &= ok
-            d = np.abs(M - v)
+            with np.errstate(invalid="ignore"):   # -inf against -inf: no comparison, set below
+                d = np.abs(M - v)
             if ids is None:
                 same = np.zeros(M.shape, dtype=bool)
             else:

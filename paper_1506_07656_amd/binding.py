@@ -31,13 +31,16 @@ class Params(ctypes.Structure):
     _fields_ = [("nu1", c_float), ("nu2", c_float), ("nu3", c_float), ("sigmoid_slope", c_float),
                 ("mu", c_float), ("intensity_scale", c_float), ("lam", c_float),
                 ("max_patch", c_int32), ("precision", c_int32), ("prototypes", c_int32),
-                ("kmeans_iters", c_int32), ("entry_points", c_int32), ("reserved", c_int32 * 4)]
+                ("kmeans_iters", c_int32), ("entry_points", c_int32), ("scoring", c_int32),
+                ("reserved", c_int32 * 3)]
 
 
 NOALLOC_MAX_BYTES = 128 << 20   # the static workspace of dm_match_images_noalloc
 
 DM_ENTRIES_TOP = 0
 DM_ENTRIES_LOCAL_MAXIMA = 1
+DM_SCORE_PATH_SUM = 0
+DM_SCORE_START_END = 1
 
 
 class Match(ctypes.Structure):
@@ -187,7 +190,8 @@ def _check(status: int):
 def params(**kw) -> Params:
     """Library defaults overridden by keyword (nu1, nu2, nu3, sigmoid_slope, mu,
     intensity_scale, lam, max_patch, precision in {'fp32','bf16','fp64'} or int,
-    prototypes, kmeans_iters, entry_points in {'top', 'local_maxima'} or int)."""
+    prototypes, kmeans_iters, entry_points in {'top', 'local_maxima'} or int,
+    scoring in {'path_sum', 'start_end'} or int)."""
     p = Params()
     _check(lib().dm_default_params(ctypes.byref(p)))
     for k, v in kw.items():
@@ -195,6 +199,8 @@ def params(**kw) -> Params:
             v = PRECISIONS[v]
         if k == "entry_points" and isinstance(v, str):
             v = {"top": DM_ENTRIES_TOP, "local_maxima": DM_ENTRIES_LOCAL_MAXIMA}[v]
+        if k == "scoring" and isinstance(v, str):
+            v = {"path_sum": DM_SCORE_PATH_SUM, "start_end": DM_SCORE_START_END}[v]
         if k == "lambda":
             k = "lam"
         if not hasattr(p, k):

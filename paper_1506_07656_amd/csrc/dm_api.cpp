@@ -110,7 +110,7 @@ dm_status dm::run_match(const float* d1, const float* d2, const dm_plan_info& pi
     // DM* entry points: the local maxima of every pooled level (the top's are
     // tested during its backtracking step).
     if (prm->entry_points == DM_ENTRIES_LOCAL_MAXIMA) {
-        g.dmstar = 1;
+        g.dmstar = prm->scoring == DM_SCORE_START_END ? 2 : 1;
         for (int l = 0; l < pi.lmax; ++l) DM_LAUNCH("mark_entries", l, launch_mark_entries(l, cp(l), code(l), vt, g, s));
     }
     // a3 + a4: backtracking, bottom reduction, reciprocal check, compaction.

@@ -58,7 +58,8 @@ struct Geom {
     const int32_t* slot0;
     int nslot0;
     RectMap rect;   // invariant matching: the run's map back to the input images
-    int dmstar;     // entry points at the local maxima of every level (bit 4 of the codes marks them)
+    int dmstar;     // entry points at the local maxima of every level (bit 4 of the codes marks them):
+                    // 1 = path-sum scores, 2 = start/end-point scores, 0 = every top position
 };
 
 // Map index, in the level l-1 buffer, of child lattice index c of a level-l

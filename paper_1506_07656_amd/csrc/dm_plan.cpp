@@ -54,6 +54,10 @@ dm_status check_params(const dm_params* p) {
         return fail(DM_ERR_INVALID_ARG, "kmeans_iters must be in [0, 1000]");
     if (p->entry_points != DM_ENTRIES_TOP && p->entry_points != DM_ENTRIES_LOCAL_MAXIMA)
         return fail(DM_ERR_INVALID_ARG, "entry_points must be DM_ENTRIES_TOP or DM_ENTRIES_LOCAL_MAXIMA");
+    if (p->scoring != DM_SCORE_PATH_SUM && p->scoring != DM_SCORE_START_END)
+        return fail(DM_ERR_INVALID_ARG, "scoring must be DM_SCORE_PATH_SUM or DM_SCORE_START_END");
+    if (p->scoring == DM_SCORE_START_END && p->entry_points != DM_ENTRIES_LOCAL_MAXIMA)
+        return fail(DM_ERR_UNSUPPORTED, "start/end-point scoring comes with the local-maxima entry points");
     for (int r : p->reserved)
         if (r != 0) return fail(DM_ERR_INVALID_ARG, "reserved fields must be 0");
     return DM_OK;

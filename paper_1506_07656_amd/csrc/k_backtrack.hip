@@ -67,9 +67,14 @@ constexpr uint8_t kEntryBit = 0x10;   // DM*: the pooled cell is an entry point 
 // the input images and reduces into the tables shared by all runs.
 // DMSTAR: entry points at the local maxima of every level (codes carry
 // kEntryBit): a top position enters only at a local maximum, and a pooled
-// cell marked as an entry starts a tuple with its own value where no tuple
-// arrives from above (one that arrives scores at least as much).
-template <bool RECT, bool DMSTAR = false>
+// cell marked as an entry starts a tuple with its own value.  DMSTAR = 1
+// scores by path sums: where a tuple arrives from above it scores at least as
+// much as the entry, so the entry counts only where none arrives.
+// DMSTAR = 2 scores by the start and end of each path: above the bottom a
+// node keeps the larger of the arriving start value and its own value if it
+// is an entry, and the bottom step adds the atomic value (as for path sums,
+// so the bottom step is the same code for both).
+template <bool RECT, int DMSTAR = 0>
 __device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_prev,
                                const uint8_t* __restrict__ code_prev, const float* __restrict__ u_cur,
                                const uint8_t* __restrict__ code_cur, const float* __restrict__ top,
@@ -181,11 +186,12 @@ __device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_pre
         int mv[4];
         uint32_t vb[4];
         size_t off[4];
-        bool live[4];
+        bool live[4], ent[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {   // loads of 4 entries first, so they overlap
             const int e = e0 + u * 256;
             live[u] = false;
+            ent[u] = false;
             vb[u] = 0u;
             cpv[u] = 0.f;
             mv[u] = 0;
@@ -199,11 +205,11 @@ __device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_pre
 #pragma unroll
             for (int side = 0; side < 4; ++side) vb[u] = max(vb[u], sV[((k * 4 + side) * a.TR + ty) * a.TC + tx]);
             off[u] = ((size_t)child_slot(g, a.l, cblk * a.CB + k) * a.h + ry) * a.w + rx;
-            if constexpr (DMSTAR) {
+            if constexpr (DMSTAR != 0) {
                 const int cm = code_prev[off[u]];
-                if (!vb[u] && (cm & kEntryBit)) vb[u] = enc(0.f);   // an entry: its own value, nothing above
+                ent[u] = (cm & kEntryBit) != 0;
                 mv[u] = cm & 15;
-                if (vb[u] || !a.is_bottom) cpv[u] = cp_prev[off[u]];
+                if (vb[u] || ent[u] || !a.is_bottom) cpv[u] = cp_prev[off[u]];
             } else if (vb[u] || !a.is_bottom) {
                 cpv[u] = cp_prev[off[u]];
                 if (a.is_bottom) mv[u] = code_prev[off[u]];
@@ -212,8 +218,14 @@ __device__ inline void bt_body(const BtArgs& a, const float* __restrict__ cp_pre
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (!live[u]) continue;
+            const uint32_t arrived = vb[u];
+            if (ent[u] && !vb[u]) vb[u] = enc(0.f);   // an entry with nothing above: its own value
             if (!a.is_bottom) {
-                u_prev[off[u]] = vb[u] ? cpv[u] + dec(vb[u]) : -INFINITY;
+                if constexpr (DMSTAR == 2)   // start/end scores: the start value passes down unchanged
+                    u_prev[off[u]] = arrived ? (ent[u] ? fmaxf(dec(arrived), cpv[u]) : dec(arrived))
+                                             : (ent[u] ? cpv[u] : -INFINITY);
+                else
+                    u_prev[off[u]] = vb[u] ? cpv[u] + dec(vb[u]) : -INFINITY;
                 continue;
             }
             if (!vb[u]) continue;
@@ -316,7 +328,7 @@ __device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, int nbytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, nbytes, 0x00020000);
 }
 
-template <bool RECT, int TILE, bool BOTTOM, bool DMSTAR = false>
+template <bool RECT, int TILE, bool BOTTOM, int DMSTAR = 0>
 __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __restrict__ cp_prev,
                                       const uint8_t* __restrict__ code_prev, const float* __restrict__ u_cur,
                                       const uint8_t* __restrict__ code_cur, const uint8_t* __restrict__ vt,
@@ -455,12 +467,17 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
             for (int dy = 0; dy < 2; ++dy) {
                 const int ry = 2 * rp - 2 + dy;
                 if (ry < R0 || ry >= R1 || !lane_o) continue;
-                uint32_t vb = o.vb[dy];
+                const uint32_t arrived = o.vb[dy];
                 // DM*: an entry point where no tuple arrives starts one with its own value
-                if constexpr (DMSTAR)
-                    if (!vb && (o.cm[dy] & kEntryBit)) vb = enc(0.f);
+                const bool ent = DMSTAR != 0 && (o.cm[dy] & kEntryBit);
+                const uint32_t vb = ent && !arrived ? enc(0.f) : arrived;
                 if constexpr (!BOTTOM) {
-                    u_prev[((size_t)c * a.h + ry) * a.w + rx] = vb ? o.cv[dy] + dec(vb) : -INFINITY;
+                    float uv;
+                    if constexpr (DMSTAR == 2)   // start/end scores: the start value passes down unchanged
+                        uv = arrived ? (ent ? fmaxf(dec(arrived), o.cv[dy]) : dec(arrived)) : (ent ? o.cv[dy] : -INFINITY);
+                    else
+                        uv = vb ? o.cv[dy] + dec(vb) : -INFINITY;
+                    u_prev[((size_t)c * a.h + ry) * a.w + rx] = uv;
                 } else if (vb) {
                     const float uu = o.cv[dy] + dec(vb);
                     const int mm = DMSTAR ? (o.cm[dy] & 15) : o.cm[dy];
@@ -663,7 +680,7 @@ __device__ inline void valid_body(const Geom& g, uint8_t* __restrict__ vt) {
     }
 }
 
-template <bool RECT, bool DMSTAR = false>
+template <bool RECT, int DMSTAR = 0>
 __global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __restrict__ cp_prev,
                                                    const uint8_t* __restrict__ code_prev,
                                                    const float* __restrict__ u_cur,
@@ -723,7 +740,7 @@ __global__ __launch_bounds__(256) void k_mark_entries(const float* __restrict__ 
     }
 }
 
-template <bool RECT, int TILE, bool BOTTOM, bool DMSTAR = false>
+template <bool RECT, int TILE, bool BOTTOM, int DMSTAR = 0>
 __global__ __launch_bounds__(64 * kBtWaves) void k_backtrack_stream(
     BtStreamArgs a, const float* __restrict__ cp_prev, const uint8_t* __restrict__ code_prev,
     const float* __restrict__ u_cur, const uint8_t* __restrict__ code_cur, const uint8_t* __restrict__ vt, Geom g,
@@ -910,20 +927,23 @@ hipError_t launch_backtrack<float>(int l, const float* cp_prev, const uint8_t* c
 #define DM_BT_STREAM(R, T, B, D)                                                                                    \
     hipLaunchKernelGGL((k_backtrack_stream<R, T, B, D>), grid, block, 0, s, b, cp_prev, code_prev, u_cur, code_cur, \
                        vt, g, u_prev, b64, c64, nb)
-        // The rectified (invariant) form differs from the plain one at the bottom level only.
+        // The rectified (invariant) form differs from the plain one at the
+        // bottom level only; so do DM*'s two scoring schemes, the other way round.
         if (g.dmstar) {
-            if (b.is_bottom && b.tile == 60) DM_BT_STREAM(false, 60, true, true);
-            else if (b.is_bottom) DM_BT_STREAM(false, 64, true, true);
-            else if (b.tile == 60) DM_BT_STREAM(false, 60, false, true);
-            else DM_BT_STREAM(false, 64, false, true);
+            if (b.is_bottom && b.tile == 60) DM_BT_STREAM(false, 60, true, 1);
+            else if (b.is_bottom) DM_BT_STREAM(false, 64, true, 1);
+            else if (g.dmstar == 2 && b.tile == 60) DM_BT_STREAM(false, 60, false, 2);
+            else if (g.dmstar == 2) DM_BT_STREAM(false, 64, false, 2);
+            else if (b.tile == 60) DM_BT_STREAM(false, 60, false, 1);
+            else DM_BT_STREAM(false, 64, false, 1);
         } else if (b.is_bottom) {
-            if (g.rect.on && b.tile == 60) DM_BT_STREAM(true, 60, true, false);
-            else if (g.rect.on) DM_BT_STREAM(true, 64, true, false);
-            else if (b.tile == 60) DM_BT_STREAM(false, 60, true, false);
-            else DM_BT_STREAM(false, 64, true, false);
+            if (g.rect.on && b.tile == 60) DM_BT_STREAM(true, 60, true, 0);
+            else if (g.rect.on) DM_BT_STREAM(true, 64, true, 0);
+            else if (b.tile == 60) DM_BT_STREAM(false, 60, true, 0);
+            else DM_BT_STREAM(false, 64, true, 0);
         } else {
-            if (b.tile == 60) DM_BT_STREAM(false, 60, false, false);
-            else DM_BT_STREAM(false, 64, false, false);
+            if (b.tile == 60) DM_BT_STREAM(false, 60, false, 0);
+            else DM_BT_STREAM(false, 64, false, 0);
         }
 #undef DM_BT_STREAM
         return hipGetLastError();
@@ -932,8 +952,11 @@ hipError_t launch_backtrack<float>(int l, const float* cp_prev, const uint8_t* c
     size_t smem;
     const BtArgs a = make_bt_args(l, g, nblocks, smem);
     const dim3 grid(((nblocks + 7) / 8) * 8);
-    if (g.dmstar)
-        hipLaunchKernelGGL((k_backtrack<false, true>), grid, dim3(256), smem, s, a, cp_prev, code_prev, u_cur,
+    if (g.dmstar == 2)
+        hipLaunchKernelGGL((k_backtrack<false, 2>), grid, dim3(256), smem, s, a, cp_prev, code_prev, u_cur,
+                           code_cur, top, vt, g, u_prev, (unsigned long long*)best, (unsigned long long*)cell, nblocks);
+    else if (g.dmstar)
+        hipLaunchKernelGGL((k_backtrack<false, 1>), grid, dim3(256), smem, s, a, cp_prev, code_prev, u_cur,
                            code_cur, top, vt, g, u_prev, (unsigned long long*)best, (unsigned long long*)cell, nblocks);
     else if (g.rect.on)
         hipLaunchKernelGGL(k_backtrack<true>, grid, dim3(256), smem, s, a, cp_prev, code_prev, u_cur, code_cur, top,

@@ -79,7 +79,7 @@ def test_plan_rejects_bad_shapes():
             dm.plan(*args, dm.params())
         assert e.value.status == -2
     p = dm.params()
-    p.reserved[3] = 1
+    p.reserved[2] = 1
     with pytest.raises(dm.DMError):
         dm.plan(64, 64, 64, 64, p)
 
@@ -197,8 +197,12 @@ def test_entry_points_validation():
     L = dm.lib()
     pl = dm.plan(64, 64, 64, 64, dm.params(entry_points="local_maxima"))
     assert pl.lmax == 4
+    pl = dm.plan(64, 64, 64, 64, dm.params(entry_points="local_maxima", scoring="start_end"))
+    assert pl.lmax == 4
     for kw, want in ((dict(entry_points=2), -1), (dict(entry_points=-1), -1),
-                     (dict(entry_points=1, prototypes=8), -5), (dict(entry_points=1, max_patch=4), -5)):
+                     (dict(entry_points=1, prototypes=8), -5), (dict(entry_points=1, max_patch=4), -5),
+                     (dict(scoring=2), -1), (dict(scoring=-1), -1), (dict(entry_points=1, scoring=2), -1),
+                     (dict(scoring=1), -5), (dict(entry_points=1, scoring=1, prototypes=8), -5)):
         with pytest.raises(dm.DMError) as e:
             dm.plan(64, 64, 64, 64, dm.params(**kw))
         assert e.value.status == want, kw
