@@ -459,14 +459,15 @@ def deepflow_bench(dm, torch, pair, img1, img2, matches, steps, warmup):
         a = agg.setdefault(name, [0, 0.0])
         a[0] += count
         a[1] += ms
-    # SOR half-sweep of an n-pixel level: every pixel's smoothness weight,
-    # flow and increment read (neighbours), the updating half's five system
-    # entries read and its increment written: 34 n bytes.
+    # SOR launch on an n-pixel level (up to 10 half-sweeps on chip per
+    # launch): every pixel's flow, increment, smoothness weight and five
+    # system entries read once and its increment written once: 48 n bytes.
+    # Pixel updates: every SOR sweep updates each pixel once.
     info = dm.flow_plan(W, H, int(matches.shape[0]))
     prm = dm.flow_params()
-    small = 2048
-    sor_bytes = sum(34.0 * info.W[k] * info.H[k] * 2 * prm.n_sor * prm.n_fixed
-                    for k in range(info.n_levels) if info.W[k] * info.H[k] > small)
+    sor_rows = [(level, count) for name, level, count, _ in rows if name == "df_sor"]
+    sor_bytes = sum(48.0 * info.W[l] * info.H[l] * c for l, c in sor_rows)
+    sor_updates = sum(float(info.W[l] * info.H[l]) * prm.n_fixed * prm.n_sor for l in {l for l, _ in sor_rows})
     sor_ms = agg.get("df_sor", [0, 0.0])[1]
     ach = sor_bytes / (sor_ms * 1e-3) / 1e9 if sor_ms else 0.0
     # end-point errors against the ground truth (interior, 16 px margin)
@@ -484,7 +485,8 @@ def deepflow_bench(dm, torch, pair, img1, img2, matches, steps, warmup):
                 launches=int(sum(v[0] for v in agg.values())),
                 sor_roofline={"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(ach / HBM_PEAK_GBS, 4), "launches": int(agg.get("df_sor", [0])[0]),
-                              "avg_us": round(sor_ms * 1e3 / max(1, agg.get("df_sor", [1])[0]), 2)},
+                              "avg_us": round(sor_ms * 1e3 / max(1, agg.get("df_sor", [1])[0]), 2),
+                              "pixel_updates_per_s": round(sor_updates / (sor_ms * 1e-3), 1) if sor_ms else None},
                 epe_px={"mean": round(float(epe.mean()), 3), "median": round(float(np.median(epe)), 3),
                         "within_1px": round(float((epe < 1).mean()), 4)},
                 match_epe_px={"mean": round(float(m_epe.mean()), 3), "median": round(float(np.median(m_epe)), 3)},
@@ -596,7 +598,7 @@ def main():
     ap.add_argument("--no-dmstar", action="store_true", help="skip the DM* entry points")
     ap.add_argument("--no-deepflow", action="store_true", help="skip DeepFlow")
     ap.add_argument("--only", choices=("all", "fwd_bf16", "fwd_bwd_bf16", "approx1024", "approx64", "invariant",
-                                       "batch_fwd", "batch_fwd_bwd"),
+                                       "batch_fwd", "batch_fwd_bwd", "deepflow"),
                     default="all",
                     help="run only that pass (short profiler runs); prints no JSON line")
     args = ap.parse_args()
@@ -649,6 +651,11 @@ def main():
         torch.cuda.synchronize()
         print(f"batch of 32 {args.only[6:]}: {(time.perf_counter() - t0) / args.steps * 1e3:.3f} ms", flush=True)
         F.release()
+        return
+    if args.only == "deepflow":
+        m = dm.match_images(img1, img2, dm.params(precision="bf16"))
+        r = deepflow_bench(dm, torch, pair, img1, img2, m, args.steps, args.warmup)
+        print("deepflow: " + json.dumps(r), flush=True)
         return
     if args.only == "fwd_bwd_bf16":
         d1, d2 = dm.descriptors(img1), dm.descriptors(img2)

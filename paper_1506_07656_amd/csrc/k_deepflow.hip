@@ -83,20 +83,29 @@ __global__ void k_df_smooth_v(const float* __restrict__ src, int W, int H, Taps 
     dst[i] = acc;
 }
 
-// dst (W x H) = mul * bilinear resampling of src (w x h), pixel centres aligned.
-__global__ void k_df_resize(const float* __restrict__ src, int w, int h, float* __restrict__ dst, int W, int H,
-                            float mul) {
+// dst_k (W x H) = mul_k * bilinear resampling of src_k (w x h), pixel
+// centres aligned, for the two maps k = 0, 1 (the two images of a pyramid
+// level, or the two flow components).
+struct Resize2 {
+    const float* src[2];
+    float* dst[2];
+    float mul[2];
+};
+__global__ void k_df_resize2(Resize2 r, int w, int h, int W, int H) {
     const long i = (long)blockIdx.x * kDfThreads + threadIdx.x;
     if (i >= (long)W * H) return;
     const int y = (int)(i / W), x = (int)(i - (long)y * W);
     const float sx = ((float)x + 0.5f) * ((float)w / (float)W) - 0.5f;
     const float sy = ((float)y + 0.5f) * ((float)h / (float)H) - 0.5f;
-    dst[i] = mul * bilinear(src, w, h, sx, sy);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) r.dst[k][i] = r.mul[k] * bilinear(r.src[k], w, h, sx, sy);
 }
 
-__global__ void k_df_fill(float* __restrict__ p, long n, float v) {
+__global__ void k_df_fill2(float* __restrict__ p, float* __restrict__ q, long n, float v) {
     const long i = (long)blockIdx.x * kDfThreads + threadIdx.x;
-    if (i < n) p[i] = v;
+    if (i >= n) return;
+    p[i] = v;
+    q[i] = v;
 }
 __global__ void k_df_fill_i32(int* __restrict__ p, long n, int v) {
     const long i = (long)blockIdx.x * kDfThreads + threadIdx.x;
@@ -159,7 +168,9 @@ __device__ inline int level_pixel(const dm_match& q, const FieldArgs& a) {
     return yk * a.Wk + xk;
 }
 
-// The first match (smallest index) landing on each level pixel owns it.
+// The first match (smallest index) landing on each level pixel owns it
+// (owner holds 0x7fffffff everywhere before: filled once per call, and
+// reset by k_df_field where it reads).
 __global__ void k_df_owner(const dm_match* __restrict__ m, const int* __restrict__ n_matches, FieldArgs a,
                            int* __restrict__ owner) {
     const int i = blockIdx.x * kDfThreads + threadIdx.x;
@@ -167,11 +178,12 @@ __global__ void k_df_owner(const dm_match* __restrict__ m, const int* __restrict
     atomicMin(&owner[level_pixel(m[i], a)], i);
 }
 __global__ void k_df_field(const dm_match* __restrict__ m, const float* __restrict__ phi,
-                           const int* __restrict__ owner, FieldArgs a, float* __restrict__ up, float* __restrict__ vp,
+                           int* __restrict__ owner, FieldArgs a, float* __restrict__ up, float* __restrict__ vp,
                            float* __restrict__ cphi) {
     const long i = (long)blockIdx.x * kDfThreads + threadIdx.x;
     if (i >= (long)a.Wk * a.Hk) return;
     const int o = owner[i];
+    owner[i] = 0x7fffffff;   // clean for the next level's owners
     if (o == 0x7fffffff) {
         up[i] = vp[i] = cphi[i] = 0.f;
         return;
@@ -291,36 +303,6 @@ __device__ inline void px_weights(const LevelMaps& L, long i, const WeightArgs& 
     A[4 * n + i] = -wJ[4] - wM * (v - L.vp[i]);
 }
 
-// One SOR half-sweep over the pixels of one colour ((x + y) % 2 == colour):
-// the 2 x 2 block of each pixel solved against its neighbours' current
-// increments, then relaxed by omega.  Same-colour pixels are never
-// neighbours, so the pixels of a half-sweep are independent.
-__device__ inline void px_sor(const LevelMaps& L, long i, int colour, float omega) {
-    const long n = (long)L.W * L.H;
-    const int W = L.W, H = L.H;
-    const int y = (int)(i / W), x = (int)(i - (long)y * W);
-    if (((x + y) & 1) != colour) return;
-    const float s = L.sw[i];
-    float G = 0.f, su = 0.f, sv = 0.f;
-    auto edge = [&](long k) {
-        const float g = 0.5f * (s + L.sw[k]);
-        G += g;
-        su += g * (L.u[k] + L.du[k]);
-        sv += g * (L.v[k] + L.dv[k]);
-    };
-    if (x > 0) edge(i - 1);
-    if (x + 1 < W) edge(i + 1);
-    if (y > 0) edge(i - W);
-    if (y + 1 < H) edge(i + W);
-    const float* A = L.A;
-    const float a11 = A[0 * n + i] + G, a12 = A[1 * n + i], a22 = A[2 * n + i] + G;
-    const float r1 = A[3 * n + i] - G * L.u[i] + su, r2 = A[4 * n + i] - G * L.v[i] + sv;
-    const float det = a11 * a22 - a12 * a12;
-    const float nu = (r1 * a22 - r2 * a12) / det, nv = (a11 * r2 - a12 * r1) / det;
-    L.du[i] += omega * (nu - L.du[i]);
-    L.dv[i] += omega * (nv - L.dv[i]);
-}
-
 #define DF_PIXEL_KERNEL(name, body, ...)                              \
     __global__ void name(LevelMaps L, __VA_ARGS__) {                   \
         const long i = (long)blockIdx.x * kDfThreads + threadIdx.x;   \
@@ -331,19 +313,261 @@ __global__ void k_df_warp(LevelMaps L) {
     if (i < (long)L.W * L.H) px_warp(L, i);
 }
 DF_PIXEL_KERNEL(k_df_grad1, px_grad1(L, i, kappa), float kappa)
-DF_PIXEL_KERNEL(k_df_tensors, px_tensors(L, i, zeta), float zeta)
+DF_PIXEL_KERNEL(k_df_tensors, (px_tensors(L, i, zeta), L.du[i] = 0.f, L.dv[i] = 0.f), float zeta)
 DF_PIXEL_KERNEL(k_df_weights, px_weights(L, i, w), WeightArgs w)
-DF_PIXEL_KERNEL(k_df_sor, px_sor(L, i, colour, omega), int colour, float omega)
 #undef DF_PIXEL_KERNEL
+
+// ---------------------------------------------------------------- SOR
+// Red-black block SOR: in one half-sweep every pixel of one colour
+// ((x + y) % 2) solves its 2 x 2 block, with the edges to its (up to 4)
+// neighbours, against the neighbours' current flow u + du, v + dv, and
+// relaxes its increment by omega.  Same-colour pixels are never neighbours,
+// so the pixels of a half-sweep are independent.  The frozen system does not
+// change during the sweeps, so a pixel keeps its edge weights (0 for an edge
+// leaving the level), the inverse of its matrix and the constant part of its
+// right-hand side in registers, and reads its neighbours' flow from LDS.
+struct SorPx {
+    float u, v, du, dv;    // flow and increment
+    float g[4];            // edge weights: left, right, top, bottom
+    float i11, i12, i22;   // inverse of [[a11, a12], [a12, a22]]
+    float r1b, r2b;        // right-hand side without the neighbours' flow
+};
+
+// sc: the pixel's alpha psi'; sn[k]: its neighbours' (ignored where ex[k] is
+// false); A: the pixel's five entries of the frozen system without edges.
+__device__ inline void sor_px_init(SorPx& p, float sc, const float (&sn)[4], const bool (&ex)[4],
+                                   const float (&A)[5]) {
+    float G = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        p.g[k] = ex[k] ? 0.5f * (sc + sn[k]) : 0.f;
+        G += p.g[k];
+    }
+    const float a11 = A[0] + G, a12 = A[1], a22 = A[2] + G;
+    const float rdet = 1.f / (a11 * a22 - a12 * a12);   // > 0: G > 0 and the data part is semi-definite
+    p.i11 = a22 * rdet;
+    p.i12 = a12 * rdet;
+    p.i22 = a11 * rdet;
+    p.r1b = A[3] - G * p.u;
+    p.r2b = A[4] - G * p.v;
+}
+
+// One update from the neighbours' flow nb (left, right, top, bottom; any
+// finite value where the edge weight is 0); returns the new u + du, v + dv.
+__device__ inline float2 sor_px_update(SorPx& p, const float2 (&nb)[4], float omega) {
+    float su = 0.f, sv = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        su += p.g[k] * nb[k].x;
+        sv += p.g[k] * nb[k].y;
+    }
+    const float r1 = p.r1b + su, r2 = p.r2b + sv;
+    const float nu = p.i11 * r1 - p.i12 * r2, nv = p.i22 * r2 - p.i12 * r1;
+    p.du += omega * (nu - p.du);
+    p.dv += omega * (nv - p.dv);
+    return make_float2(p.u + p.du, p.v + p.dv);
+}
+
+__device__ inline void load_system(const LevelMaps& L, long n, long i, float (&A)[5]) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) A[c] = L.A[c * n + i];
+}
+
+// Large levels: several half-sweeps per launch.  A workgroup holds a tile
+// of kSorLX x kSorLY pixels on chip, runs up to kSorHalo half-sweeps on it
+// and writes back the inner (kSorLX - 2 kSorHalo) x (kSorLY - 2 kSorHalo)
+// pixels.  A pixel with a neighbour inside the level but outside the tile is
+// never updated; the error this leaves moves one pixel inward per
+// half-sweep, so after at most kSorHalo half-sweeps every inner pixel holds
+// what the same half-sweeps over the whole level give.  The increments go
+// from one buffer to another, since a tile's rim overlaps other tiles' inner
+// pixels.  Thread t owns the two columns 2 (t % 32) + {0, 1} of kSorRPT
+// consecutive rows, a red and a black pixel per row, so each half-sweep
+// updates one pixel per row and thread.  Tile origins are even, so a
+// pixel's colour is that of its position in the tile, known at compile time.
+constexpr int kSorCP = 32;                                 // column pairs per tile row
+constexpr int kSorLX = 2 * kSorCP;                         // tile columns
+constexpr int kSorThreads = 256;
+constexpr int kSorRPT = 4;                                 // rows per thread (even)
+constexpr int kSorLY = kSorThreads / kSorCP * kSorRPT;     // tile rows
+constexpr int kSorHalo = 10;                               // half-sweeps per launch at most (even)
+constexpr int kSorIX = kSorLX - 2 * kSorHalo;              // inner columns
+constexpr int kSorIY = kSorLY - 2 * kSorHalo;              // inner rows
+static_assert(kSorIX > 0 && kSorIY > 0 && kSorIX % 2 == 0 && kSorIY % 2 == 0 && kSorHalo % 2 == 0 &&
+                  kSorRPT % 2 == 0,
+              "tile origins must be even");
+
+struct SorArgs {
+    int ntx;     // tiles along x
+    int nhalf;   // half-sweeps of this launch: even, at most kSorHalo, the first of colour 0
+    float omega;
+    const float *du_in, *dv_in;
+    float *du_out, *dv_out;
+    float *u_fin, *v_fin;   // last launch of the level: the level's flow u + du, v + dv goes here instead
+};
+
+__global__ __launch_bounds__(kSorThreads) void k_df_sor_tiles(LevelMaps L, SorArgs a) {
+    __shared__ float2 sUV[kSorLY + 2][kSorLX + 2];   // u + du, v + dv; a zero border
+    __shared__ float sS[kSorLY + 2][kSorLX + 2];     // alpha psi' (0 outside the level)
+    const int W = L.W, H = L.H;
+    const long n = (long)W * H;
+    const int tx = blockIdx.x % a.ntx, ty = blockIdx.x / a.ntx;
+    const int X0 = tx * kSorIX - kSorHalo, Y0 = ty * kSorIY - kSorHalo;
+    const int t = threadIdx.x, cp = t % kSorCP, rg = t / kSorCP;
+    for (int e = t; e < 2 * (kSorLX + 2) + 2 * kSorLY; e += kSorThreads) {
+        int yy, xx;
+        if (e < 2 * (kSorLX + 2)) {
+            yy = e < kSorLX + 2 ? 0 : kSorLY + 1;
+            xx = e % (kSorLX + 2);
+        } else {
+            const int k = e - 2 * (kSorLX + 2);
+            yy = 1 + (k >> 1);
+            xx = (k & 1) ? kSorLX + 1 : 0;
+        }
+        sUV[yy][xx] = make_float2(0.f, 0.f);
+        sS[yy][xx] = 0.f;
+    }
+    SorPx q[kSorRPT][2];
+    bool upd[kSorRPT][2];
+    float Av[kSorRPT][2][5];
+#pragma unroll
+    for (int r = 0; r < kSorRPT; ++r)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int lx = 2 * cp + j, ly = rg * kSorRPT + r, x = X0 + lx, y = Y0 + ly;
+            const bool in = x >= 0 && x < W && y >= 0 && y < H;
+            // updated: inside the level, every neighbour inside the level lies inside the tile
+            upd[r][j] = in && (x == 0 || lx > 0) && (x + 1 == W || lx + 1 < kSorLX) && (y == 0 || ly > 0) &&
+                        (y + 1 == H || ly + 1 < kSorLY);
+            const long i = in ? (long)y * W + x : 0;
+            SorPx& p = q[r][j];
+            p.u = in ? L.u[i] : 0.f;
+            p.v = in ? L.v[i] : 0.f;
+            p.du = in ? a.du_in[i] : 0.f;
+            p.dv = in ? a.dv_in[i] : 0.f;
+            if (upd[r][j]) load_system(L, n, i, Av[r][j]);
+            sUV[ly + 1][lx + 1] = make_float2(p.u + p.du, p.v + p.dv);
+            sS[ly + 1][lx + 1] = in ? L.sw[i] : 0.f;
+        }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSorRPT; ++r)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (!upd[r][j]) continue;
+            const int lx = 2 * cp + j, ly = rg * kSorRPT + r, x = X0 + lx, y = Y0 + ly;
+            const float sn[4] = {sS[ly + 1][lx], sS[ly + 1][lx + 2], sS[ly][lx + 1], sS[ly + 2][lx + 1]};
+            const bool ex[4] = {x > 0, x + 1 < W, y > 0, y + 1 < H};
+            sor_px_init(q[r][j], sS[ly + 1][lx + 1], sn, ex, Av[r][j]);
+        }
+    for (int h = 0; h < a.nhalf; h += 2) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            // the neighbours of this colour's pixels (all of the other colour) first, then the updates
+            float2 nb[kSorRPT][4];
+#pragma unroll
+            for (int r = 0; r < kSorRPT; ++r) {
+                const int j = (c + r) & 1, lx = 2 * cp + j, ly = rg * kSorRPT + r;
+                nb[r][0] = sUV[ly + 1][lx];
+                nb[r][1] = sUV[ly + 1][lx + 2];
+                nb[r][2] = sUV[ly][lx + 1];
+                nb[r][3] = sUV[ly + 2][lx + 1];
+            }
+#pragma unroll
+            for (int r = 0; r < kSorRPT; ++r) {
+                const int j = (c + r) & 1, lx = 2 * cp + j, ly = rg * kSorRPT + r;
+                if (upd[r][j]) sUV[ly + 1][lx + 1] = sor_px_update(q[r][j], nb[r], a.omega);
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kSorRPT; ++r)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int lx = 2 * cp + j, ly = rg * kSorRPT + r, x = X0 + lx, y = Y0 + ly;
+            if (lx < kSorHalo || lx >= kSorHalo + kSorIX || ly < kSorHalo || ly >= kSorHalo + kSorIY || x >= W ||
+                y >= H)
+                continue;
+            const long i = (long)y * W + x;
+            if (a.u_fin) {
+                a.u_fin[i] = q[r][j].u + q[r][j].du;
+                a.v_fin[i] = q[r][j].v + q[r][j].dv;
+            } else {
+                a.du_out[i] = q[r][j].du;
+                a.dv_out[i] = q[r][j].dv;
+            }
+        }
+}
 
 // A whole level in one workgroup (small levels): every step of the level in
 // order, each a block-stride loop over the pixels, a barrier between steps
 // (the workgroup's global-memory writes are visible to it after a barrier).
+// The SOR of each fixed point runs on chip: u + du, v + dv and alpha psi' of
+// the whole level in LDS, each thread's pixels (i = t + 1024 k) in registers.
 constexpr int kDfSmallThreads = 1024;
-constexpr long kDfSmallPixels = 2048;   // levels up to this size run in one workgroup
+constexpr long kDfSmallPixels = 2048;   // levels up to this size run in one workgroup (more would spill registers)
+constexpr int kDfSmallPPT = (int)((kDfSmallPixels + kDfSmallThreads - 1) / kDfSmallThreads);
+
+__device__ inline void sor_level_small(const LevelMaps& L, int n_sor, float omega, float2* sUV, float* sS) {
+    const int W = L.W, H = L.H, n = W * H, t = threadIdx.x;
+    SorPx q[kDfSmallPPT];
+    int col[kDfSmallPPT];   // colour, and bits 1-4: the left, right, top, bottom neighbours exist; -1: no pixel
+#pragma unroll
+    for (int k = 0; k < kDfSmallPPT; ++k) {
+        const int i = t + k * kDfSmallThreads;
+        if (i >= n) continue;
+        q[k].u = L.u[i];
+        q[k].v = L.v[i];
+        q[k].du = L.du[i];
+        q[k].dv = L.dv[i];
+        sUV[i] = make_float2(q[k].u + q[k].du, q[k].v + q[k].dv);
+        sS[i] = L.sw[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kDfSmallPPT; ++k) {
+        const int i = t + k * kDfSmallThreads;
+        col[k] = -1;
+        if (i >= n) continue;
+        const int y = i / W, x = i - y * W;
+        const bool ex[4] = {x > 0, x + 1 < W, y > 0, y + 1 < H};
+        const float sn[4] = {sS[ex[0] ? i - 1 : i], sS[ex[1] ? i + 1 : i], sS[ex[2] ? i - W : i], sS[ex[3] ? i + W : i]};
+        float A[5];
+        load_system(L, n, i, A);
+        sor_px_init(q[k], sS[i], sn, ex, A);
+        col[k] = ((x + y) & 1) | (ex[0] << 1) | (ex[1] << 2) | (ex[2] << 3) | (ex[3] << 4);
+    }
+    for (int it = 0; it < n_sor; ++it)
+        for (int c = 0; c < 2; ++c) {
+            // a pixel's neighbours are of the other colour: no update of this
+            // half-sweep changes them
+#pragma unroll
+            for (int k = 0; k < kDfSmallPPT; ++k) {
+                const int m = col[k];
+                if (m < 0 || (m & 1) != c) continue;
+                const int i = t + k * kDfSmallThreads;
+                const float2 nb[4] = {sUV[(m & 2) ? i - 1 : i], sUV[(m & 4) ? i + 1 : i], sUV[(m & 8) ? i - W : i],
+                                      sUV[(m & 16) ? i + W : i]};
+                sUV[i] = sor_px_update(q[k], nb, omega);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+    for (int k = 0; k < kDfSmallPPT; ++k) {
+        const int i = t + k * kDfSmallThreads;
+        if (i >= n) continue;
+        L.du[i] = q[k].du;
+        L.dv[i] = q[k].dv;
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kDfSmallThreads) void k_df_level_small(LevelMaps L, float kappa, float zeta,
                                                                      WeightArgs w, int n_fixed, int n_sor,
                                                                      float omega) {
+    __shared__ float2 sUV[kDfSmallPixels];
+    __shared__ float sS[kDfSmallPixels];
     const long n = (long)L.W * L.H;
     const long t = threadIdx.x;
 #define DF_ALL(stmt)                                               \
@@ -356,10 +580,7 @@ __global__ __launch_bounds__(kDfSmallThreads) void k_df_level_small(LevelMaps L,
     DF_ALL((px_tensors(L, i, zeta), L.du[i] = 0.f, L.dv[i] = 0.f));
     for (int f = 0; f < n_fixed; ++f) {
         DF_ALL(px_weights(L, i, w));
-        for (int it = 0; it < n_sor; ++it) {
-            DF_ALL(px_sor(L, i, 0, omega));
-            DF_ALL(px_sor(L, i, 1, omega));
-        }
+        sor_level_small(L, n_sor, omega, sUV, sS);
     }
     DF_ALL((L.u[i] += L.du[i], L.v[i] += L.dv[i]));
 #undef DF_ALL
@@ -385,7 +606,7 @@ __global__ void k_df_pack(const float* __restrict__ u, const float* __restrict__
 struct FlowLayout {
     std::vector<int> W, H;     // level sizes, 0 = finest
     std::vector<size_t> off1, off2;   // pyramid images of each level
-    size_t u, v, u2, v2, du, dv, up, vp, cphi, owner, I2w, Ax, Ay, It, Ixt, Iyt, alpha, J, A, sw, phi, tmp;
+    size_t u, v, u2, v2, du, dv, du2, dv2, up, vp, cphi, owner, I2w, Ax, Ay, It, Ixt, Iyt, alpha, J, A, sw, phi, tmp;
     size_t total;
 };
 
@@ -421,7 +642,8 @@ dm_status flow_layout(int W, int H, int max_matches, const dm_flow_params& p, Fl
         L.off2.push_back(take((size_t)L.W[k] * L.H[k] * 4));
     }
     L.u = take(n * 4), L.v = take(n * 4), L.u2 = take(n * 4), L.v2 = take(n * 4);
-    L.du = take(n * 4), L.dv = take(n * 4), L.up = take(n * 4), L.vp = take(n * 4), L.cphi = take(n * 4);
+    L.du = take(n * 4), L.dv = take(n * 4), L.du2 = take(n * 4), L.dv2 = take(n * 4);
+    L.up = take(n * 4), L.vp = take(n * 4), L.cphi = take(n * 4);
     L.owner = take(n * 4), L.I2w = take(n * 4), L.Ax = take(n * 4), L.Ay = take(n * 4), L.It = take(n * 4);
     L.Ixt = take(n * 4), L.Iyt = take(n * 4), L.alpha = take(n * 4), L.J = take(12 * n * 4), L.A = take(5 * n * 4);
     L.sw = take(n * 4), L.phi = take((size_t)(max_matches > 0 ? max_matches : 1) * 4), L.tmp = take(n * 4);
@@ -533,31 +755,28 @@ dm_status flow_enqueue(const float* img1, const float* img2, int W, int H, int l
            PhiArgs{W, H, max_matches, p->lam_scale, p->sigma_m}, matches, n_matches, F(Lo.phi));
     for (int k = 1; k <= K; ++k) {
         const long nk = (long)Lo.W[k] * Lo.H[k];
-        DF("df_pyramid", k, 0, k_df_resize, dim3(nblk(nk)), dim3(kDfThreads), 0, s, F(Lo.off1[k - 1]), Lo.W[k - 1],
-           Lo.H[k - 1], F(Lo.off1[k]), Lo.W[k], Lo.H[k], 1.f);
-        DF("df_pyramid", k, 0, k_df_resize, dim3(nblk(nk)), dim3(kDfThreads), 0, s, F(Lo.off2[k - 1]), Lo.W[k - 1],
-           Lo.H[k - 1], F(Lo.off2[k]), Lo.W[k], Lo.H[k], 1.f);
+        const Resize2 r{{F(Lo.off1[k - 1]), F(Lo.off2[k - 1])}, {F(Lo.off1[k]), F(Lo.off2[k])}, {1.f, 1.f}};
+        DF("df_pyramid", k, 0, k_df_resize2, dim3(nblk(nk)), dim3(kDfThreads), 0, s, r, Lo.W[k - 1], Lo.H[k - 1],
+           Lo.W[k], Lo.H[k]);
     }
+    DF("df_matches", -1, 0, k_df_fill_i32, dim3(nblk(n0)), dim3(kDfThreads), 0, s,
+       reinterpret_cast<int*>(base + Lo.owner), n0, 0x7fffffff);
     float *u = F(Lo.u), *v = F(Lo.v), *u2 = F(Lo.u2), *v2 = F(Lo.v2);
     for (int k = K; k >= 0; --k) {
         const int Wk = Lo.W[k], Hk = Lo.H[k];
         const long nk = (long)Wk * Hk;
         const dim3 g(nblk(nk)), b(kDfThreads);
         if (k == K) {
-            DF("df_init", k, 0, k_df_fill, g, b, 0, s, u, nk, 0.f);
-            DF("df_init", k, 0, k_df_fill, g, b, 0, s, v, nk, 0.f);
+            DF("df_init", k, 0, k_df_fill2, g, b, 0, s, u, v, nk, 0.f);
         } else {   // the flow of level k + 1 (u2, v2), resampled and scaled
-            DF("df_upsample", k, 0, k_df_resize, g, b, 0, s, u2, Lo.W[k + 1], Lo.H[k + 1], u, Wk, Hk,
-               (float)Wk / (float)Lo.W[k + 1]);
-            DF("df_upsample", k, 0, k_df_resize, g, b, 0, s, v2, Lo.W[k + 1], Lo.H[k + 1], v, Wk, Hk,
-               (float)Hk / (float)Lo.H[k + 1]);
+            const Resize2 r{{u2, v2}, {u, v}, {(float)Wk / (float)Lo.W[k + 1], (float)Hk / (float)Lo.H[k + 1]}};
+            DF("df_upsample", k, 0, k_df_resize2, g, b, 0, s, r, Lo.W[k + 1], Lo.H[k + 1], Wk, Hk);
         }
         const FieldArgs fa{W, H, Wk, Hk, max_matches, (float)Wk / (float)W, (float)Hk / (float)H};
-        DF("df_matches", k, 0, k_df_fill_i32, g, b, 0, s, reinterpret_cast<int*>(base + Lo.owner), nk, 0x7fffffff);
         if (max_matches > 0)
             DF("df_matches", k, 0, k_df_owner, dim3(nblk(max_matches)), b, 0, s, matches, n_matches, fa,
                reinterpret_cast<int*>(base + Lo.owner));
-        DF("df_matches", k, 0, k_df_field, g, b, 0, s, matches, F(Lo.phi), reinterpret_cast<const int*>(base + Lo.owner),
+        DF("df_matches", k, 0, k_df_field, g, b, 0, s, matches, F(Lo.phi), reinterpret_cast<int*>(base + Lo.owner),
            fa, F(Lo.up), F(Lo.vp), F(Lo.cphi));
         LevelMaps M{Wk,        Hk,        F(Lo.off1[k]), F(Lo.off2[k]), u,         v,           F(Lo.du),
                     F(Lo.dv),  F(Lo.up),  F(Lo.vp),      F(Lo.cphi),    F(Lo.I2w), F(Lo.Ax),    F(Lo.Ay),
@@ -570,17 +789,26 @@ dm_status flow_enqueue(const float* img1, const float* img2, int W, int H, int l
         } else {
             DF("df_warp", k, 0, k_df_warp, g, b, 0, s, M);
             DF("df_grad", k, 0, k_df_grad1, g, b, 0, s, M, p->kappa);
-            DF("df_tensors", k, 0, k_df_tensors, g, b, 0, s, M, p->zeta);
-            DF("df_init", k, 0, k_df_fill, g, b, 0, s, M.du, nk, 0.f);
-            DF("df_init", k, 0, k_df_fill, g, b, 0, s, M.dv, nk, 0.f);
+            DF("df_tensors", k, 0, k_df_tensors, g, b, 0, s, M, p->zeta);   // also zeroes du, dv
+            float *du_o = F(Lo.du2), *dv_o = F(Lo.dv2);   // the other increment buffers
+            const int ntx = (Wk + kSorIX - 1) / kSorIX, nty = (Hk + kSorIY - 1) / kSorIY;
+            bool flow_in_u2 = false;
             for (int f = 0; f < p->n_fixed; ++f) {
                 DF("df_weights", k, 0, k_df_weights, g, b, 0, s, M, wa);
-                for (int it = 0; it < p->n_sor; ++it) {
-                    DF("df_sor", k, 0, k_df_sor, g, b, 0, s, M, 0, p->omega);
-                    DF("df_sor", k, 0, k_df_sor, g, b, 0, s, M, 1, p->omega);
+                for (int h = 0; h < 2 * p->n_sor; h += kSorHalo) {
+                    const int nh = min(kSorHalo, 2 * p->n_sor - h);
+                    // the level's last launch writes u + du, v + dv into u2, v2 (the coarser
+                    // level's flow there has been resampled already)
+                    const bool last = f + 1 == p->n_fixed && h + nh == 2 * p->n_sor;
+                    const SorArgs sa{ntx, nh, p->omega, M.du, M.dv, du_o, dv_o, last ? u2 : nullptr, last ? v2 : nullptr};
+                    DF("df_sor", k, 0, k_df_sor_tiles, dim3(ntx * nty), dim3(kSorThreads), 0, s, M, sa);
+                    std::swap(M.du, du_o);
+                    std::swap(M.dv, dv_o);
+                    flow_in_u2 = last;
                 }
             }
-            DF("df_add", k, 0, k_df_add, g, b, 0, s, u, v, M.du, M.dv, nk);
+            if (flow_in_u2) continue;   // u2, v2 hold level k's flow
+            DF("df_add", k, 0, k_df_add, g, b, 0, s, u, v, M.du, M.dv, nk);   // no SOR sweeps: u + du
         }
         std::swap(u, u2);   // u2, v2 now hold level k's flow
         std::swap(v, v2);
