@@ -614,10 +614,12 @@ def main():
     img1 = torch.from_numpy(pair["img1"]).cuda()
     img2 = torch.from_numpy(pair["img2"]).cuda()
     if args.only == "fwd_bf16":
-        dt, _, _, _ = time_path(dm, torch, img1, img2, "bf16", args.steps, args.warmup)
+        dt, _, stages, pl = time_path(dm, torch, img1, img2, "bf16", args.steps, args.warmup)
         if args.copy_probe:
             copy_probe(torch)
         print(f"bf16 forward: {dt * 1e3:.3f} ms/pair", flush=True)
+        for r in roofline_of(stages, pl, "bf16")[:8]:
+            print(f"  {r['kernel']:<22} {r['avg_ms']:.4f} ms  {r['achieved']:.0f} {r['unit']}", flush=True)
         return
     if args.only == "invariant":
         prm = dm.params(precision="bf16")

@@ -275,6 +275,12 @@ constexpr int TILE_W = D2C * 5;                          // words per tile row
 constexpr int TILE_N = D2R * TILE_W;                     // words per tile
 constexpr int TILE_PER_T = (TILE_N + 255) / 256;         // words per thread
 constexpr int kOOB = 0x7ffffff0;                         // buffer byte offset past any buffer
+// Codes of two steps (32 pooled columns) of a wave's 16 MT patches x TR rows,
+// staged in LDS and written as 16-byte runs (a 32-byte sector per patch row)
+// when the pooled width is a multiple of 16: one step's 16 codes alone
+// leave half-written sectors, which HBM writes whole.
+constexpr int kKRow = 32;                                // bytes per staged row (two steps)
+constexpr int kKStride = TR * kKRow + 16;                // bytes per patch (padded: other banks)
 
 __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t nbytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
@@ -314,7 +320,8 @@ __device__ __forceinline__ void row_keys(const EngineBF16& eng, const PoolArgs& 
 
 __device__ inline void sweep_band_bf16(const bf8* fa, const bf8* faO, uint32_t* sD2, const uint32_t* __restrict__ d2,
                                        const PoolArgs& a, int pt, int R0, int seg, float lam, float* __restrict__ cp,
-                                       uint8_t* __restrict__ code, float (*carry)[16 * MT], float* dummy) {
+                                       uint8_t* __restrict__ code, float (*carry)[16 * MT], float* dummy,
+                                       uint8_t* __restrict__ sK) {
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = lane & 15, grp = lane >> 4;
     const int pbase = pt * PT + wave * 16 * MT;
@@ -360,6 +367,7 @@ __device__ inline void sweep_band_bf16(const bf8* fa, const bf8* faO, uint32_t* 
             ob4[mt][j] = ok ? (lp * mapsz + n) * 4 : (uint32_t)kOOB;
         }
     const StepRange sr = step_range(a, seg);
+    const bool stage = (a.w1 & 15) == 0;   // uniform
     fetch(16 * sr.s_begin);
     for (int step = sr.s_begin; step < sr.s_end; ++step) {
         const int C0 = 16 * step;
@@ -409,9 +417,28 @@ __device__ inline void sweep_band_bf16(const bf8* fa, const bf8* faO, uint32_t* 
                             __float_as_uint(__builtin_amdgcn_exp2f(lam * __builtin_amdgcn_logf(
                                 __uint_as_float(fin[mt][j] & ~15u)))), rsC,
                             (int)ob4[mt][j], 4 * rc, 0);
-                        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(15u - (fin[mt][j] & 15u)), rsK,
-                                                             (int)ob[mt][j], rc, 0);
+                        const uint8_t k = (uint8_t)(15u - (fin[mt][j] & 15u));
+                        if (stage)
+                            sK[(mt * 16 + 4 * grp + j) * kKStride + pr * kKRow + (step & 1) * 16 + n] = k;
+                        else
+                            __builtin_amdgcn_raw_buffer_store_b8(k, rsK, (int)ob[mt][j], rc, 0);
                     }
+            }
+        }
+        // After the second step of a pair (or the last step): the staged
+        // codes go out, lane pairs writing a patch row's 32 bytes.  Only this
+        // wave wrote its area, and a wave's LDS accesses complete in order.
+        if (stage && ((step & 1) || step + 1 == sr.s_end)) {
+            const int s0 = step & ~1;
+#pragma unroll
+            for (int i = 0; i < 16 * MT * TR * 2 / 64; ++i) {
+                const int e = lane + 64 * i, lp = e >> 4, pr = (e >> 1) & (TR - 1), hf = e & 1;
+                const int st = s0 + hf, r = R0 + pr, col = 16 * st;
+                const auto v = *reinterpret_cast<const __attribute__((ext_vector_type(4))) uint32_t*>(
+                    __builtin_assume_aligned(sK + lp * kKStride + pr * kKRow + hf * 16, 16));
+                // patches past natom lie past the descriptor's range: dropped
+                if (st >= sr.s_out && st <= step && r < a.h1 && col < a.w1)
+                    __builtin_amdgcn_raw_buffer_store_b128(v, rsK, (int)((uint32_t)lp * mapsz + r * a.w1 + col), 0, 0);
             }
         }
     }
@@ -454,6 +481,7 @@ __device__ inline void corr_bf16_body(const uint16_t* __restrict__ d1, const uin
     __shared__ __align__(16) uint32_t sD2[D2R * D2C * 5];
     __shared__ __align__(16) float sCarry[WAVES][ARS][16 * MT];
     __shared__ __align__(16) float sDummy[WAVES][4 * 64 + 16 * MT];   // carry writes of lanes other than the row's last
+    __shared__ __align__(16) uint8_t sK[WAVES][16 * MT * kKStride];    // staged codes
     const int pt = bid % a.n_ptiles, rest = bid / a.n_ptiles;
     const int seg = rest % a.n_seg, R0 = (rest / a.n_seg) * TR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -486,7 +514,8 @@ __device__ inline void corr_bf16_body(const uint16_t* __restrict__ d1, const uin
         }
         faO[mt * 5 + 4] = load_bf8(tmp + 16);
     }
-    sweep_band_bf16(fa, faO, sD2, (const uint32_t*)d2, a, pt, R0, seg, lam, cp, code, sCarry[wave], sDummy[wave]);
+    sweep_band_bf16(fa, faO, sD2, (const uint32_t*)d2, a, pt, R0, seg, lam, cp, code, sCarry[wave], sDummy[wave],
+                    sK[wave]);
 }
 
 __global__ __launch_bounds__(256, 2) void k_corr_pool_f32(const float* __restrict__ d1,
