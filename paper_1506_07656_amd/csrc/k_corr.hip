@@ -318,6 +318,8 @@ __device__ __forceinline__ void row_keys(const EngineBF16& eng, const PoolArgs& 
     }
 }
 
+// STAGE: the pooled width is a multiple of 16, codes go out through sK.
+template <bool STAGE>
 __device__ inline void sweep_band_bf16(const bf8* fa, const bf8* faO, uint32_t* sD2, const uint32_t* __restrict__ d2,
                                        const PoolArgs& a, int pt, int R0, int seg, float lam, float* __restrict__ cp,
                                        uint8_t* __restrict__ code, float (*carry)[16 * MT], float* dummy,
@@ -367,7 +369,6 @@ __device__ inline void sweep_band_bf16(const bf8* fa, const bf8* faO, uint32_t* 
             ob4[mt][j] = ok ? (lp * mapsz + n) * 4 : (uint32_t)kOOB;
         }
     const StepRange sr = step_range(a, seg);
-    const bool stage = (a.w1 & 15) == 0;   // uniform
     fetch(16 * sr.s_begin);
     for (int step = sr.s_begin; step < sr.s_end; ++step) {
         const int C0 = 16 * step;
@@ -418,7 +419,7 @@ __device__ inline void sweep_band_bf16(const bf8* fa, const bf8* faO, uint32_t* 
                                 __uint_as_float(fin[mt][j] & ~15u)))), rsC,
                             (int)ob4[mt][j], 4 * rc, 0);
                         const uint8_t k = (uint8_t)(15u - (fin[mt][j] & 15u));
-                        if (stage)
+                        if constexpr (STAGE)
                             sK[(mt * 16 + 4 * grp + j) * kKStride + pr * kKRow + (step & 1) * 16 + n] = k;
                         else
                             __builtin_amdgcn_raw_buffer_store_b8(k, rsK, (int)ob[mt][j], rc, 0);
@@ -428,7 +429,7 @@ __device__ inline void sweep_band_bf16(const bf8* fa, const bf8* faO, uint32_t* 
         // After the second step of a pair (or the last step): the staged
         // codes go out, lane pairs writing a patch row's 32 bytes.  Only this
         // wave wrote its area, and a wave's LDS accesses complete in order.
-        if (stage && ((step & 1) || step + 1 == sr.s_end)) {
+        if (STAGE && ((step & 1) || step + 1 == sr.s_end)) {
             const int s0 = step & ~1;
 #pragma unroll
             for (int i = 0; i < 16 * MT * TR * 2 / 64; ++i) {
@@ -514,8 +515,12 @@ __device__ inline void corr_bf16_body(const uint16_t* __restrict__ d1, const uin
         }
         faO[mt * 5 + 4] = load_bf8(tmp + 16);
     }
-    sweep_band_bf16(fa, faO, sD2, (const uint32_t*)d2, a, pt, R0, seg, lam, cp, code, sCarry[wave], sDummy[wave],
-                    sK[wave]);
+    if ((a.w1 & 15) == 0)
+        sweep_band_bf16<true>(fa, faO, sD2, (const uint32_t*)d2, a, pt, R0, seg, lam, cp, code, sCarry[wave],
+                              sDummy[wave], sK[wave]);
+    else
+        sweep_band_bf16<false>(fa, faO, sD2, (const uint32_t*)d2, a, pt, R0, seg, lam, cp, code, sCarry[wave],
+                               sDummy[wave], sK[wave]);
 }
 
 __global__ __launch_bounds__(256, 2) void k_corr_pool_f32(const float* __restrict__ d1,
