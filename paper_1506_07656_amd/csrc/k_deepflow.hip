@@ -385,10 +385,14 @@ __device__ inline void load_system(const LevelMaps& L, long n, long i, float (&A
 // consecutive rows, a red and a black pixel per row, so each half-sweep
 // updates one pixel per row and thread.  Tile origins are even, so a
 // pixel's colour is that of its position in the tile, known at compile time.
+// A launch costs about the same at every level (6 to 264 tiles): the time
+// is one tile's chain of half-sweeps, so the tile has 512 threads of 4
+// pixels (256 threads of 8 pixels took 1.35 times as long; 1024 threads
+// on 64 x 64 tiles, 1.3 times).
 constexpr int kSorCP = 32;                                 // column pairs per tile row
 constexpr int kSorLX = 2 * kSorCP;                         // tile columns
-constexpr int kSorThreads = 256;
-constexpr int kSorRPT = 4;                                 // rows per thread (even)
+constexpr int kSorThreads = 512;
+constexpr int kSorRPT = 2;                                 // rows per thread (even)
 constexpr int kSorLY = kSorThreads / kSorCP * kSorRPT;     // tile rows
 constexpr int kSorHalo = 10;                               // half-sweeps per launch at most (even)
 constexpr int kSorIX = kSorLX - 2 * kSorHalo;              // inner columns
