@@ -41,8 +41,10 @@ hipError_t launch_group(int kind, const GroupLaunch& gl, hipStream_t s) {
         case JK_CORR_F32:
             return launch_group_corr(kind, gl, s);
         case JK_LEVEL_STREAM_VEC:
+        case JK_LEVEL_STREAM_VEC8:
         case JK_LEVEL_STREAM:
         case JK_LEVEL_NARROW:
+        case JK_LEVEL_NARROW8:
         case JK_LEVEL_POOL:
         case JK_LEVEL_TOP:
             return launch_group_level(kind, gl, s);
@@ -81,8 +83,10 @@ int default_res(int kind) {
         case JK_TG_F32:
             return 2;
         case JK_LEVEL_STREAM_VEC:
+        case JK_LEVEL_STREAM_VEC8:
         case JK_LEVEL_STREAM:
         case JK_LEVEL_NARROW:
+        case JK_LEVEL_NARROW8:
         case JK_BT_STREAM:
         case JK_BT_STREAM64:
         case JK_BT_STREAM_BOT:
@@ -388,7 +392,8 @@ dm_status autotune(Schedule& S, int n, const dm_pair* pairs, const dm_params* pr
     dm_status st = rebuild();
     if (st != DM_OK) return st;
     if ((st = run(S, ws, s, false)) != DM_OK) return st;   // every stage's inputs in place
-    const std::vector<int> lev = {JK_LEVEL_STREAM_VEC, JK_LEVEL_STREAM, JK_LEVEL_NARROW},
+    const std::vector<int> lev = {JK_LEVEL_STREAM_VEC, JK_LEVEL_STREAM_VEC8, JK_LEVEL_STREAM, JK_LEVEL_NARROW,
+                                  JK_LEVEL_NARROW8},
                            bt = {JK_BT_STREAM, JK_BT_STREAM64, JK_BT_STREAM_BOT, JK_BT_STREAM64_BOT};
     const int reps = 3;
     // band heights (job tables change)

@@ -163,6 +163,8 @@ enum JobKind : int {
     JK_LEVEL_NARROW,
     JK_BT_STREAM_BOT,     // the streaming backtracking's bottom level (the key tables), per tile width
     JK_BT_STREAM64_BOT,
+    JK_LEVEL_STREAM_VEC8,   // level maps of even width (8-byte child row pieces)
+    JK_LEVEL_NARROW8,
     JK_COUNT
 };
 

@@ -193,7 +193,7 @@ struct StreamArgs {
     int gx, gy, gxc, gyc;
     int h, w, hp, wp;
     int TRo, n_band, n_ct, n_items;
-    int vec;                         // w % 4 == 0: 16-byte child row segments
+    int vec;                         // 2: w % 4 == 0, 16-byte child row pieces; 1: w even, 8-byte pieces; 0: odd w
     int narrow;                      // pooled maps <= 64 wide (and vec): several bands per wave
     int lgl;                         // narrow: log2 of the lanes per band (the wave walks 64 >> lgl bands)
 };
@@ -214,6 +214,7 @@ __device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const float* row, int nbytes) 
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(row), (short)0, nbytes, 0x00020000);
 }
 
+template <int VEC>
 __device__ inline void load_row(const StreamArgs& a, const float* prev, const float* const cmap[4], int y, int X0,
                                 int t, RowBuf& b) {
 #pragma unroll
@@ -225,11 +226,11 @@ __device__ inline void load_row(const StreamArgs& a, const float* prev, const fl
         // kOOB (a byte offset past any row), so that each load is in or out of
         // range on its own whatever the compiler folds into immediate offsets.
         const int s0 = X0 + 4 * t + dx;   // >= -2
-        if (k & 1) {   // s0 = 2 C0 + 4t >= 0: 16-byte aligned, entirely inside or outside the row
+        if ((k & 1) && VEC == 2) {   // s0 = 2 C0 + 4t >= 0: 16-byte aligned, entirely inside or outside the row
             const auto f = __builtin_amdgcn_raw_buffer_load_b128(rs, s0 * 4, 0, 0);
 #pragma unroll
             for (int j = 0; j < 4; ++j) b.v[k][j] = __uint_as_float(f[j]);
-        } else {       // s0 = 2 C0 + 4t - 2: two 8-byte halves, each inside or outside
+        } else {       // s0 = 2 C0 + 4t - 2 or 2 C0 + 4t (w even): two 8-byte halves, each inside or outside
             const auto f0 = __builtin_amdgcn_raw_buffer_load_b64(rs, s0 >= 0 ? s0 * 4 : kOOB, 0, 0);
             const auto f1 = __builtin_amdgcn_raw_buffer_load_b64(rs, s0 * 4 + 8, 0, 0);
             b.v[k][0] = __uint_as_float(f0[0]);
@@ -272,14 +273,15 @@ __device__ inline void pool_row(const StreamArgs& a, const RowBuf& b, float inv,
     }
 }
 
-// Narrow maps (at most 64 pooled columns, w % 4 == 0): the wave splits into
+// Narrow maps (at most 64 pooled columns, w even): the wave splits into
 // groups of L = 2^lgl lanes (L >= half the pooled width), each walking its
 // own band of the same parent, lane tt = t % L owning the A columns
 // 4 tt - 1 .. 4 tt + 3.  Rows differ between the groups, so each child has a
 // descriptor over its whole map and a lane's offset is kOOB wherever its row
-// or columns fall outside (w % 4 == 0 keeps every 8- and 16-byte piece
-// wholly inside or outside a row).  Same sums, same comparisons: the values
-// equal those of the 64-lane form.
+// or columns fall outside (an even w keeps every 8-byte piece, and w % 4 ==
+// 0 every 16-byte piece, wholly inside or outside a row).  Same sums, same
+// comparisons: the values equal those of the 64-lane form.
+template <int VEC>
 __device__ inline void load_row_narrow(const StreamArgs& a, const __amdgpu_buffer_rsrc_t rs[4], const bool ex[4],
                                        int y, int tt, int L, RowBuf& b) {
 #pragma unroll
@@ -288,11 +290,11 @@ __device__ inline void load_row_narrow(const StreamArgs& a, const __amdgpu_buffe
         const bool rok = ex[k] && yy >= 0 && yy < a.h;
         const int rowb = yy * a.w;
         const int s0 = 4 * tt - 1 + dx;   // -2 .. 125
-        if (k & 1) {   // s0 = 4 tt: 16 bytes inside or outside the row
+        if ((k & 1) && VEC == 2) {   // s0 = 4 tt: 16 bytes inside or outside the row
             const auto f = __builtin_amdgcn_raw_buffer_load_b128(rs[k], rok && s0 < a.w ? (rowb + s0) * 4 : kOOB, 0, 0);
 #pragma unroll
             for (int j = 0; j < 4; ++j) b.v[k][j] = __uint_as_float(f[j]);
-        } else {       // s0 = 4 tt - 2: two 8-byte halves
+        } else {       // s0 = 4 tt - 2 or 4 tt (w even): two 8-byte halves
             const auto f0 = __builtin_amdgcn_raw_buffer_load_b64(
                 rs[k], rok && s0 >= 0 && s0 < a.w ? (rowb + s0) * 4 : kOOB, 0, 0);
             const auto f1 =
@@ -338,6 +340,7 @@ __device__ inline void pool_row_narrow(const StreamArgs& a, const RowBuf& b, flo
     }
 }
 
+template <int VEC>
 __device__ inline void level_narrow_body(const StreamArgs& a, const float* __restrict__ prev, const float* const cmap[4],
                                          float inv, int P, int band2, int t, float lam, float* __restrict__ cp,
                                          uint8_t* __restrict__ code) {
@@ -353,12 +356,12 @@ __device__ inline void level_narrow_body(const StreamArgs& a, const float* __res
     RowBuf b0, b1;
     float pv[2], hv[2];
     int pk[2], hk[2];
-    load_row_narrow(a, rs, ex, 2 * R0 - 1, tt, L, b0);
-    load_row_narrow(a, rs, ex, 2 * R0, tt, L, b1);
+    load_row_narrow<VEC>(a, rs, ex, 2 * R0 - 1, tt, L, b0);
+    load_row_narrow<VEC>(a, rs, ex, 2 * R0, tt, L, b1);
     pool_row_narrow(a, b0, inv, 2 * R0 - 1, tt, L, pv, pk);
     for (int i = 0; i < a.TRo; ++i) {   // the same count in every group
         const int r = R0 + i;
-        load_row_narrow(a, rs, ex, 2 * r + 1, tt, L, b0);
+        load_row_narrow<VEC>(a, rs, ex, 2 * r + 1, tt, L, b0);
         float best[2];
         int bk[2];
 #pragma unroll
@@ -367,7 +370,7 @@ __device__ inline void level_narrow_body(const StreamArgs& a, const float* __res
 #pragma unroll
         for (int q = 0; q < 2; ++q)
             if (hv[q] > best[q]) { best[q] = hv[q]; bk[q] = 3 + hk[q]; }
-        load_row_narrow(a, rs, ex, 2 * r + 2, tt, L, b1);
+        load_row_narrow<VEC>(a, rs, ex, 2 * r + 2, tt, L, b1);
         pool_row_narrow(a, b0, inv, 2 * r + 1, tt, L, pv, pk);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -487,7 +490,7 @@ __device__ __forceinline__ void level_coalesced_body(const StreamArgs& a, const 
     }
 }
 
-template <bool VEC, bool NARROW>
+template <int VEC, bool NARROW>
 __device__ __forceinline__ void level_stream_body(const StreamArgs& a, const float* __restrict__ prev,
                                          const uint8_t* __restrict__ vt, const Geom& g, float lam,
                                          float* __restrict__ cp, uint8_t* __restrict__ code, int bid) {
@@ -521,10 +524,10 @@ __device__ __forceinline__ void level_stream_body(const StreamArgs& a, const flo
                 (ey[ky] >= 0 && ex[kx] >= 0) ? prev + (size_t)child_slot(g, a.l, ey[ky] * a.gxc + ex[kx]) * hw : nullptr;
     const float inv = 1.f / float(nx * ny);
     if constexpr (NARROW) {
-        level_narrow_body(a, prev, cmap, inv, P, band, t, lam, cp, code);
+        level_narrow_body<VEC>(a, prev, cmap, inv, P, band, t, lam, cp, code);
         return;
     }
-    if constexpr (!VEC) {
+    if constexpr (VEC == 0) {
         level_coalesced_body(a, prev, cmap, inv, P, band, ct, t, lam, cp, code);
         return;
     }
@@ -535,12 +538,12 @@ __device__ __forceinline__ void level_stream_body(const StreamArgs& a, const flo
     RowBuf b0, b1;
     float pv[2], hv[2];
     int pk[2], hk[2];
-    load_row(a, prev, cmap, 2 * R0 - 1, X0, t, b0);
-    load_row(a, prev, cmap, 2 * R0, X0, t, b1);
+    load_row<VEC>(a, prev, cmap, 2 * R0 - 1, X0, t, b0);
+    load_row<VEC>(a, prev, cmap, 2 * R0, X0, t, b1);
     pool_row(a, b0, inv, 2 * R0 - 1, X0, t, pv, pk);
     for (int r = R0; r < R1; ++r) {
         // b1 holds row 2r
-        load_row(a, prev, cmap, 2 * r + 1, X0, t, b0);
+        load_row<VEC>(a, prev, cmap, 2 * r + 1, X0, t, b0);
         float best[2];
         int bk[2];
 #pragma unroll
@@ -549,7 +552,7 @@ __device__ __forceinline__ void level_stream_body(const StreamArgs& a, const flo
 #pragma unroll
         for (int q = 0; q < 2; ++q)
             if (hv[q] > best[q]) { best[q] = hv[q]; bk[q] = 3 + hk[q]; }
-        load_row(a, prev, cmap, 2 * r + 2, X0, t, b1);   // row 2R1 is in range or masked
+        load_row<VEC>(a, prev, cmap, 2 * r + 2, X0, t, b1);   // row 2R1 is in range or masked
         pool_row(a, b0, inv, 2 * r + 1, X0, t, pv, pk);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -596,7 +599,7 @@ __global__ __launch_bounds__(256) void k_level_pool(LevelArgs a, const T* __rest
     level_pool_body<T>(a, prev, vt, g, lam, cp, code, bid);
 }
 
-template <bool VEC, bool NARROW>
+template <int VEC, bool NARROW>
 __global__ __launch_bounds__(64 * kStreamWaves) void k_level_stream(StreamArgs a, const float* __restrict__ prev,
                                                                      const uint8_t* __restrict__ vt, Geom g, float lam,
                                                                      float* __restrict__ cp,
@@ -640,7 +643,7 @@ struct LevelTopJob {
     }
 };
 
-template <bool VEC, bool NARROW>
+template <int VEC, bool NARROW>
 struct LevelStreamJob {
     StreamArgs a;
     const float* prev;
@@ -704,7 +707,7 @@ StreamArgs make_stream_args(int l, const Geom& g, int tro, int& nblocks) {
     b.TRo = b.hp < tro ? b.hp : tro;
     b.n_band = (b.hp + b.TRo - 1) / b.TRo;
     b.n_ct = (b.wp + kStreamCols - 1) / kStreamCols;
-    b.vec = (b.w % 4) == 0;
+    b.vec = (b.w % 4) == 0 ? 2 : ((b.w % 2) == 0 ? 1 : 0);
     // Narrow maps: one wave walks G = 64 / L bands (groups of bands per
     // item); each child's descriptor spans its whole map, whose byte size
     // must fit an int.
@@ -737,9 +740,11 @@ JobRec level_job(int l, const float* prev, const uint8_t* vt, const Geom& g, flo
     if (use_stream(l, g)) {
         int nb;
         const StreamArgs b = make_stream_args(l, g, tro, nb);
-        if (b.narrow) r.set(JK_LEVEL_NARROW, nb, 0, LevelStreamJob<true, true>{b, prev, vt, g, lam, cp, code});
-        else if (b.vec) r.set(JK_LEVEL_STREAM_VEC, nb, 0, LevelStreamJob<true, false>{b, prev, vt, g, lam, cp, code});
-        else r.set(JK_LEVEL_STREAM, nb, 0, LevelStreamJob<false, false>{b, prev, vt, g, lam, cp, code});
+        if (b.narrow && b.vec == 2) r.set(JK_LEVEL_NARROW, nb, 0, LevelStreamJob<2, true>{b, prev, vt, g, lam, cp, code});
+        else if (b.narrow) r.set(JK_LEVEL_NARROW8, nb, 0, LevelStreamJob<1, true>{b, prev, vt, g, lam, cp, code});
+        else if (b.vec == 2) r.set(JK_LEVEL_STREAM_VEC, nb, 0, LevelStreamJob<2, false>{b, prev, vt, g, lam, cp, code});
+        else if (b.vec == 1) r.set(JK_LEVEL_STREAM_VEC8, nb, 0, LevelStreamJob<1, false>{b, prev, vt, g, lam, cp, code});
+        else r.set(JK_LEVEL_STREAM, nb, 0, LevelStreamJob<0, false>{b, prev, vt, g, lam, cp, code});
         return r;
     }
     int nb;
@@ -752,9 +757,11 @@ JobRec level_job(int l, const float* prev, const uint8_t* vt, const Geom& g, flo
 
 hipError_t launch_group_level(int kind, const GroupLaunch& gl, hipStream_t s) {
     switch (kind) {
-        case JK_LEVEL_STREAM_VEC: return launch_grouped<LevelStreamJob<true, false>, 64 * kStreamWaves, 1>(gl, s);
-        case JK_LEVEL_STREAM: return launch_grouped<LevelStreamJob<false, false>, 64 * kStreamWaves, 1>(gl, s);
-        case JK_LEVEL_NARROW: return launch_grouped<LevelStreamJob<true, true>, 64 * kStreamWaves, 1>(gl, s);
+        case JK_LEVEL_STREAM_VEC: return launch_grouped<LevelStreamJob<2, false>, 64 * kStreamWaves, 1>(gl, s);
+        case JK_LEVEL_STREAM_VEC8: return launch_grouped<LevelStreamJob<1, false>, 64 * kStreamWaves, 1>(gl, s);
+        case JK_LEVEL_STREAM: return launch_grouped<LevelStreamJob<0, false>, 64 * kStreamWaves, 1>(gl, s);
+        case JK_LEVEL_NARROW: return launch_grouped<LevelStreamJob<2, true>, 64 * kStreamWaves, 1>(gl, s);
+        case JK_LEVEL_NARROW8: return launch_grouped<LevelStreamJob<1, true>, 64 * kStreamWaves, 1>(gl, s);
         case JK_LEVEL_POOL: return launch_grouped<LevelPoolJob, 256, 1>(gl, s);
         case JK_LEVEL_TOP: return launch_grouped<LevelTopJob, 256, 1>(gl, s);
         default: return hipErrorInvalidValue;
@@ -770,15 +777,15 @@ hipError_t launch_level(int l, const T* prev, const uint8_t* vt, const Geom& g, 
         const float* pf = reinterpret_cast<const float*>(prev);
         float* cf = reinterpret_cast<float*>(cp);
         const dim3 grid(((nb + 7) / 8) * 8);
-        if (b.narrow)
-            hipLaunchKernelGGL((k_level_stream<true, true>), grid, dim3(64 * kStreamWaves), 0, s, b, pf, vt, g,
-                               (float)lam, cf, code, nb);
-        else if (b.vec)
-            hipLaunchKernelGGL((k_level_stream<true, false>), grid, dim3(64 * kStreamWaves), 0, s, b, pf, vt, g,
-                               (float)lam, cf, code, nb);
-        else
-            hipLaunchKernelGGL((k_level_stream<false, false>), grid, dim3(64 * kStreamWaves), 0, s, b, pf, vt, g,
-                               (float)lam, cf, code, nb);
+#define DM_LEVEL_STREAM(V, N)                                                                                      \
+    hipLaunchKernelGGL((k_level_stream<V, N>), grid, dim3(64 * kStreamWaves), 0, s, b, pf, vt, g, (float)lam, cf, \
+                       code, nb)
+        if (b.narrow && b.vec == 2) DM_LEVEL_STREAM(2, true);
+        else if (b.narrow) DM_LEVEL_STREAM(1, true);
+        else if (b.vec == 2) DM_LEVEL_STREAM(2, false);
+        else if (b.vec == 1) DM_LEVEL_STREAM(1, false);
+        else DM_LEVEL_STREAM(0, false);
+#undef DM_LEVEL_STREAM
         return hipGetLastError();
     }
     int nblocks;
