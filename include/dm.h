@@ -28,10 +28,12 @@
  *    matching), known on the host from dm_plan / dm_plan_invariant before
  *    any call, and dm_last_error() repeats it.
  *  - The library keeps no state between calls other than the thread-local
- *    error text, the per-stage timing records (when enabled) and, for
- *    dm_match_batch, one cached batch schedule per workspace (job tables,
+ *    error text, the per-stage timing records (when enabled), for
+ *    dm_match_batch one cached batch schedule per workspace (job tables,
  *    chosen tile shapes and, with DM_BATCH_GRAPH, an instantiated HIP graph),
- *    dropped by dm_batch_release.  Calls on different streams with different
+ *    dropped by dm_batch_release, for dm_deepflow with DM_FLOW_GRAPH one
+ *    instantiated graph per workspace, dropped by dm_flow_release, and the
+ *    static per-device scratch array of dm_match_images_noalloc.  Calls on different streams with different
  *    workspaces may run concurrently; two calls sharing a workspace must be
  *    ordered.
  */
