@@ -40,6 +40,11 @@ dm_status dm::run_match(const float* d1, const float* d2, const dm_plan_info& pi
                         bool have_bf16, dm_match* out, int* n_out, hipStream_t s, const RectMap* rect,
                         uint64_t* rbest, uint64_t* rcell) {
     Geom g = make_geom(pi);
+    // The library's own descriptors (BF16 copy made with them) with mu > 0:
+    // the ninth component is at least mu / sqrt(8 + mu^2), and every window
+    // of a target position inside I' holds that position's own pixel, so
+    // A_0 >= (mu^2 / (8 + mu^2)) / 16 > 2^-126 for mu >= 1e-6.
+    g.pos_corr = have_bf16 && prm->mu >= 1e-6f;
     if (rect) g.rect = *rect;
     const float lam = prm->lambda;
     uint8_t* vt = at<uint8_t>(ws, pi.off_valid);

@@ -220,7 +220,10 @@ void build(int n, const dm_pair* pairs, const dm_params* prm, int flags, const s
     int Lmax = 0;
     for (const PairLayout& p : P) Lmax = std::max(Lmax, p.pi.lmax);
     std::vector<Geom> G(n);
-    for (int k = 0; k < n; ++k) G[k] = make_geom(P[k].pi);
+    for (int k = 0; k < n; ++k) {
+        G[k] = make_geom(P[k].pi);
+        G[k].pos_corr = prm->mu >= 1e-6f;   // descriptors of the library's own (see run_match)
+    }
     auto W = [&](int k) { return at<char>(ws, P[k].ws_off); };
     auto cp = [&](int k, int l) { return at<float>(W(k), P[k].pi.off_cp[l]); };
     auto code = [&](int k, int l) { return at<uint8_t>(W(k), P[k].pi.off_code[l]); };

@@ -58,6 +58,11 @@ struct Geom {
     const int32_t* slot0;
     int nslot0;
     RectMap rect;   // invariant matching: the run's map back to the input images
+    // The descriptors are the library's own with mu > 0 (dm_descriptors: a
+    // positive ninth component), so every bottom correlation at a target
+    // position inside I' is positive and normal: the bottom kernel's clamp
+    // at 0 can go.
+    int pos_corr;
     int dmstar;     // entry points at the local maxima of every level (bit 4 of the codes marks them):
                     // 1 = path-sum scores, 2 = start/end-point scores, 0 = every top position
 };

@@ -43,6 +43,7 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 struct PoolArgs {
     int natom, n0x, W1, W2, H2, h1, w1;
+    int pos;                // correlations inside I' are positive and normal (Geom::pos_corr)
     int n_ptiles, n_steps;
     int n_seg, seg_steps;   // column segments of n_steps / n_seg steps (few patches: more blocks)
 };
@@ -291,6 +292,9 @@ __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t nbytes
 // pooled column, even column, odd column), each carrying bits - k, where
 // bits = 15 - 3 (my + 1) places the row in the window.  The carry (keys of
 // the odd column left of the step) moves through LDS 4 values at a time.
+// POS: correlations inside I' are known positive and normal, so the clamp
+// at 2^-126 changes nothing and is left out.
+template <bool POS>
 __device__ __forceinline__ void row_keys(const EngineBF16& eng, const PoolArgs& a, int R0, int ia, int n,
                                          uint32_t me, uint32_t mo, uint32_t bits, const float* cr, float* cw,
                                          uint32_t (&rk)[MT][4]) {
@@ -306,8 +310,9 @@ __device__ __forceinline__ void row_keys(const EngineBF16& eng, const PoolArgs& 
         f4 kout;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const uint32_t kE = ((uint32_t)max(__float_as_int(accE[mt][j]), lo) & mE) | (bits - 1u);   // k = 1
-            const uint32_t kO = ((uint32_t)max(__float_as_int(accO[mt][j]), lo) & mO) | (bits - 2u);   // k = 2
+            const int bE = __float_as_int(accE[mt][j]), bO = __float_as_int(accO[mt][j]);
+            const uint32_t kE = ((uint32_t)(POS ? bE : max(bE, lo)) & mE) | (bits - 1u);   // k = 1
+            const uint32_t kO = ((uint32_t)(POS ? bO : max(bO, lo)) & mO) | (bits - 2u);   // k = 2
             const uint32_t kL =
                 ((uint32_t)__builtin_amdgcn_update_dpp((int)__float_as_uint(cin[j]), (int)kO, 0x111, 0xF, 0xF, false) &
                  ~15u) | bits;                                                                          // k = 0
@@ -319,7 +324,8 @@ __device__ __forceinline__ void row_keys(const EngineBF16& eng, const PoolArgs& 
 }
 
 // STAGE: the pooled width is a multiple of 16, codes go out through sK.
-template <bool STAGE>
+// POS: see row_keys.
+template <bool STAGE, bool POS>
 __device__ inline void sweep_band_bf16(const bf8* fa, const bf8* faO, uint32_t* sD2, const uint32_t* __restrict__ d2,
                                        const PoolArgs& a, int pt, int R0, int seg, float lam, float* __restrict__ cp,
                                        uint8_t* __restrict__ code, float (*carry)[16 * MT], float* dummy,
@@ -384,20 +390,20 @@ __device__ inline void sweep_band_bf16(const bf8* fa, const bf8* faO, uint32_t* 
         const int c = C0 + n;
         const uint32_t me = 2 * c < a.W2 ? ~15u : 0u, mo = 2 * c + 1 < a.W2 ? ~15u : 0u;
         uint32_t best[MT][4], rk[MT][4];
-        row_keys(eng, a, R0, 0, n, me, mo, 15u, carry[0] + 4 * grp, cw0, rk);
+        row_keys<POS>(eng, a, R0, 0, n, me, mo, 15u, carry[0] + 4 * grp, cw0, rk);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int j = 0; j < 4; ++j) best[mt][j] = rk[mt][j];   // my = -1 of pooled row R0
         for (int pr = 0; pr < TR; ++pr) {
             const int r = R0 + pr;
-            row_keys(eng, a, R0, 2 * pr + 1, n, me, mo, 12u, carry[2 * pr + 1] + 4 * grp, cw0 + (2 * pr + 1) * cstep,
+            row_keys<POS>(eng, a, R0, 2 * pr + 1, n, me, mo, 12u, carry[2 * pr + 1] + 4 * grp, cw0 + (2 * pr + 1) * cstep,
                      rk);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) best[mt][j] = max(best[mt][j], rk[mt][j]);   // my = 0
-            row_keys(eng, a, R0, 2 * pr + 2, n, me, mo, 9u, carry[2 * pr + 2] + 4 * grp, cw0 + (2 * pr + 2) * cstep,
+            row_keys<POS>(eng, a, R0, 2 * pr + 2, n, me, mo, 9u, carry[2 * pr + 2] + 4 * grp, cw0 + (2 * pr + 2) * cstep,
                      rk);
             uint32_t fin[MT][4];
 #pragma unroll
@@ -515,12 +521,14 @@ __device__ inline void corr_bf16_body(const uint16_t* __restrict__ d1, const uin
         }
         faO[mt * 5 + 4] = load_bf8(tmp + 16);
     }
-    if ((a.w1 & 15) == 0)
-        sweep_band_bf16<true>(fa, faO, sD2, (const uint32_t*)d2, a, pt, R0, seg, lam, cp, code, sCarry[wave],
-                              sDummy[wave], sK[wave]);
-    else
-        sweep_band_bf16<false>(fa, faO, sD2, (const uint32_t*)d2, a, pt, R0, seg, lam, cp, code, sCarry[wave],
-                               sDummy[wave], sK[wave]);
+#define DM_SWEEP(ST, PO)                                                                                     \
+    sweep_band_bf16<ST, PO>(fa, faO, sD2, (const uint32_t*)d2, a, pt, R0, seg, lam, cp, code, sCarry[wave], \
+                            sDummy[wave], sK[wave])
+    if ((a.w1 & 15) == 0 && a.pos) DM_SWEEP(true, true);
+    else if ((a.w1 & 15) == 0) DM_SWEEP(true, false);
+    else if (a.pos) DM_SWEEP(false, true);
+    else DM_SWEEP(false, false);
+#undef DM_SWEEP
 }
 
 __global__ __launch_bounds__(256, 2) void k_corr_pool_f32(const float* __restrict__ d1,
@@ -568,6 +576,7 @@ PoolArgs make_pool_args(const Geom& g, int& nblocks, bool split, bool bf16) {
     a.H2 = g.H2;
     a.h1 = g.h[1];
     a.w1 = g.w[1];
+    a.pos = g.pos_corr;
     a.n_ptiles = (a.natom + (bf16 ? PT : PF) - 1) / (bf16 ? PT : PF);
     a.n_steps = (a.w1 + 15) / 16;
     // Few patches (prototype maps, small images): split the sweep into

@@ -243,6 +243,29 @@ def test_identity_pair_matches_itself():
     np.testing.assert_array_equal(gpu[:, 0:2], gpu[:, 2:4])
 
 
+@pytest.mark.parametrize("W1,H1,W2,H2", [(64, 64, 64, 64), (100, 76, 90, 70), (256, 192, 256, 192)])
+def test_images_entry_equals_descriptors_entry_bf16(W1, H1, W2, H2):
+    """With the library's own descriptors (mu > 0) every bottom correlation
+    inside I' is positive, and the images entry point runs the bottom kernel
+    without its clamp at 0; matching the same descriptors through the
+    descriptors entry point (clamp kept) gives the same pooled maps, codes
+    and matches bit for bit.  Widths whose pooled maps are and are not
+    multiples of 16 (staged and direct code stores)."""
+    rng = np.random.default_rng(W1 + H2)
+    i1 = synth.blurred_noise(rng, H1, W1)
+    i2 = synth.blurred_noise(rng, H2, W2)
+    prm = dm.params(precision="bf16")
+    mi, wsi, pli = dm.match_images(cuda(i1), cuda(i2), prm, return_state=True)
+    d1, d2 = dm.descriptors(cuda(i1)), dm.descriptors(cuda(i2))
+    md, wsd, pld = dm.match_descriptors(d1, d2, prm, return_state=True)
+    torch.cuda.synchronize()
+    vi, vd = dm.workspace_views(wsi, pli), dm.workspace_views(wsd, pld)
+    for lv in range(pli.lmax):
+        assert torch.equal(vi["levels"][lv]["cp"], vd["levels"][lv]["cp"]), lv
+        assert torch.equal(vi["levels"][lv]["code"], vd["levels"][lv]["code"]), lv
+    assert torch.equal(mi, md)
+
+
 def test_deterministic():
     o = oracle_pair("c1")
     a, va, _ = run_desc(o["D1"], o["D2"], max_patch=32)
