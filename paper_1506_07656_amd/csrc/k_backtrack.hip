@@ -474,7 +474,8 @@ __device__ inline void bt_stream_body(const BtStreamArgs& a, const float* __rest
                 if constexpr (!BOTTOM) {
                     float uv;
                     if constexpr (DMSTAR == 2)   // start/end scores: the start value passes down unchanged
-                        uv = arrived ? (ent ? fmaxf(dec(arrived), o.cv[dy]) : dec(arrived)) : (ent ? o.cv[dy] : -INFINITY);
+                        uv = arrived ? (ent ? fmaxf(dec(arrived), o.cv[dy]) : dec(arrived))
+                                     : (ent ? o.cv[dy] : -INFINITY);
                     else
                         uv = vb ? o.cv[dy] + dec(vb) : -INFINITY;
                     u_prev[((size_t)c * a.h + ry) * a.w + rx] = uv;
