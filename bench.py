@@ -24,7 +24,9 @@ The "dmstar" entry is the earlier entry-point scheme (DM*, Sec. 3.3 and
 Table 1): local maxima of every level start the backtracking, scored by the
 current path sums; entry counts and agreement with the plain method; and
 the same entry points with the earlier start/end-point scores (Table 1's
-first configuration), time and agreement beside it.
+first configuration), time and agreement beside it; for all three, the
+fraction of matches within 1 px of the pair's ground-truth field (Table 1's
+accuracy measure, on the synthetic pair).
 
 The "batch" entry is the uneven-batch workload: 32 pairs with W ~ U{128..621},
 H ~ U{96..188} (half of a 1242x375 driving-frame shape), BF16 correlation,
@@ -395,7 +397,19 @@ def approx_bench(dm, torch, img1, img2, exact_matches, exact_plan, steps, warmup
     return res
 
 
-def dmstar_bench(dm, torch, img1, img2, plain_matches, plain_ms, steps, warmup):
+def truth_within_1px(pair, matches):
+    """Fraction of matches whose target lies within 1 px of where the pair's
+    ground-truth field sends the source pixel (Table 1's accuracy measure on
+    a synthetic pair)."""
+    import numpy as np
+    m = np.asarray(matches, dtype=np.float64)
+    if len(m) == 0:
+        return 0.0
+    qx, qy = pair["flow"](m[:, 0], m[:, 1])
+    return round(float((np.hypot(m[:, 2] - qx, m[:, 3] - qy) <= 1.0).mean()), 5)
+
+
+def dmstar_bench(dm, torch, pair, img1, img2, plain_matches, plain_ms, steps, warmup):
     """DM* entry points (Sec. 3.3, Table 1's middle configuration) on the same
     pair: local maxima of every level start the backtracking, path-sum
     scores; BF16 correlation.  Entry counts of the pooled levels come from
@@ -414,6 +428,9 @@ def dmstar_bench(dm, torch, img1, img2, plain_matches, plain_ms, steps, warmup):
     return dict(pairs_s=round(1.0 / dt, 3), ms_per_step=round(dt * 1e3, 4), vs_plain_ms=round(plain_ms, 4),
                 matches=int(len(matches)), plain_matches=int(len(plain_matches)),
                 plain_matches_within_1px=round(within_1px(matches, plain_matches), 5),
+                truth_within_1px={"plain": truth_within_1px(pair, plain_matches),
+                                  "dmstar": truth_within_1px(pair, matches),
+                                  "dmstar_start_end": truth_within_1px(pair, m_se)},
                 entries_per_pooled_level=entries,
                 top_kernels=[(r["kernel"], round(r["avg_ms"] * r["launches"] / steps, 4)) for r in rows[:6]],
                 start_end=dict(pairs_s=round(1.0 / dt_se, 3), ms_per_step=round(dt_se * 1e3, 4),
@@ -737,7 +754,8 @@ def main():
     if not args.no_invariant:
         out["invariant"] = invariant_bench(dm, torch, img1, img2, head["ms"], args.steps, args.warmup)
     if not args.no_dmstar:
-        out["dmstar"] = dmstar_bench(dm, torch, img1, img2, head["matches"], head["ms"], args.steps, args.warmup)
+        out["dmstar"] = dmstar_bench(dm, torch, pair, img1, img2, head["matches"], head["ms"], args.steps,
+                                     args.warmup)
     if not args.no_deepflow:
         out["deepflow"] = deepflow_bench(dm, torch, pair, img1, img2, torch.from_numpy(head["matches"]).cuda()
                                          if not torch.is_tensor(head["matches"]) else head["matches"],
