@@ -37,14 +37,15 @@ inline P* at(void* ws, uint64_t off) {
 // shared tables rbest / rcell through the run's map and nothing is
 // finalised here.
 dm_status dm::run_match(const float* d1, const float* d2, const dm_plan_info& pi, const dm_params* prm, void* ws,
-                        bool have_bf16, dm_match* out, int* n_out, hipStream_t s, const RectMap* rect,
+                        bool have_bf16, bool own_desc, dm_match* out, int* n_out, hipStream_t s,
+                        const RectMap* rect,
                         uint64_t* rbest, uint64_t* rcell) {
     Geom g = make_geom(pi);
-    // The library's own descriptors (BF16 copy made with them) with mu > 0:
-    // the ninth component is at least mu / sqrt(8 + mu^2), and every window
-    // of a target position inside I' holds that position's own pixel, so
-    // A_0 >= (mu^2 / (8 + mu^2)) / 16 > 2^-126 for mu >= 1e-6.
-    g.pos_corr = have_bf16 && prm->mu >= 1e-6f;
+    // The library's own descriptors with mu > 0: the ninth component is at
+    // least mu / sqrt(8 + mu^2), and every window of a target position inside
+    // I' holds that position's own pixel, so A_0 >= (mu^2 / (8 + mu^2)) / 16
+    // > 2^-126 for mu >= 1e-6.
+    g.pos_corr = own_desc && prm->mu >= 1e-6f;
     if (rect) g.rect = *rect;
     const float lam = prm->lambda;
     uint8_t* vt = at<uint8_t>(ws, pi.off_valid);
@@ -260,7 +261,7 @@ dm_status dm::match_images(const float* img1, int W1, int H1, int ld1, const flo
     DM_LAUNCH("descriptor", -1,
               launch_descriptor_pair(img1, W1, H1, ld1, d1, bf ? at<uint16_t>(ws, pi.off_bf1) : nullptr, img2, W2, H2,
                                      ld2, d2, bf ? at<uint16_t>(ws, pi.off_bf2) : nullptr, dp, s));
-    return run_match(d1, d2, pi, prm, ws, bf, out, n_out, stream);
+    return run_match(d1, d2, pi, prm, ws, bf, true, out, n_out, stream);
 }
 
 extern "C" {
@@ -348,7 +349,7 @@ dm_status dm_match_descriptors(const void* d1, int W1, int H1, const void* d2, i
     if ((st = check_ws(pi, ws, ws_bytes)) != DM_OK) return st;
     if ((st = check_out(pi, out, capacity, n_out)) != DM_OK) return st;
     if (prm->precision == DM_FP64) return fail(DM_ERR_UNSUPPORTED, "matching runs in FP32 or BF16");
-    return run_match((const float*)d1, (const float*)d2, pi, prm, ws, false, out, n_out, stream);
+    return run_match((const float*)d1, (const float*)d2, pi, prm, ws, false, false, out, n_out, stream);
 }
 
 dm_status dm_match_images(const float* img1, int W1, int H1, int ld1, const float* img2, int W2, int H2, int ld2,

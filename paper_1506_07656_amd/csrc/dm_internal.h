@@ -255,8 +255,11 @@ hipError_t launch_kmeans(const KmArgs& a, int iters, hipStream_t s);
 
 // Stages a1..a4 of one pair on descriptors in device memory (dm_api.cpp);
 // with rect, a run of invariant matching reducing into rbest / rcell.
+// own_desc: d1, d2 (and their BF16 copies when have_bf16) come from the
+// library's descriptor kernel.
 dm_status run_match(const float* d1, const float* d2, const dm_plan_info& pi, const dm_params* prm, void* ws,
-                    bool have_bf16, dm_match* out, int* n_out, hipStream_t s, const RectMap* rect = nullptr,
+                    bool have_bf16, bool own_desc, dm_match* out, int* n_out, hipStream_t s,
+                    const RectMap* rect = nullptr,
                     uint64_t* rbest = nullptr, uint64_t* rcell = nullptr);
 
 // Opt-in stage timing (dm_timing.cpp); calls may nest.

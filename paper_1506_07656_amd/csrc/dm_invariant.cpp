@@ -202,7 +202,8 @@ dm_status dm_match_invariant(const float* img1, int W1, int H1, int ld1, const f
         m.ciny = g.ciny;
         m.coutx = g.coutx;
         m.couty = g.couty;
-        if ((st = run_match(d1, d2, pi, prm, rws, bf, nullptr, nullptr, s, &m, best, cell)) != DM_OK) return st;
+        if ((st = run_match(d1, d2, pi, prm, rws, bf, true, nullptr, nullptr, s, &m, best, cell)) != DM_OK)
+            return st;
     }
     DM_LAUNCH("finalize", -1, launch_finalize_rect(best, cell, m, out, n_out, s));
     return DM_OK;

@@ -92,8 +92,9 @@ __device__ inline uint32_t bf16x2_scale16(uint32_t u) {
 }
 
 // One x-step of the FP32 sweep.  Engine supplies the MFMA chain for an N-tile
-// (E or O) of all MF M-tiles.
-template <typename Engine>
+// (E or O) of all MF M-tiles.  POS: correlations inside I' are known
+// positive (PoolArgs::pos), so the clamp at 0 is left out.
+template <bool POS, typename Engine>
 __device__ inline void sweep_band(const Engine& eng, const PoolArgs& a, int pt, int R0, int seg, float lam,
                                   float* __restrict__ cp, uint8_t* __restrict__ code,
                                   float (*carry)[16 * MF]) {
@@ -128,8 +129,8 @@ __device__ inline void sweep_band(const Engine& eng, const PoolArgs& a, int pt, 
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int lp = mt * 16 + 4 * grp + j;
-                    const float E = (y_ok && e_ok) ? fmaxf(accE[mt][j], 0.f) : -1.f;
-                    const float O = (y_ok && o_ok) ? fmaxf(accO[mt][j], 0.f) : -1.f;
+                    const float E = (y_ok && e_ok) ? (POS ? accE[mt][j] : fmaxf(accE[mt][j], 0.f)) : -1.f;
+                    const float O = (y_ok && o_ok) ? (POS ? accO[mt][j] : fmaxf(accO[mt][j], 0.f)) : -1.f;
                     const float cin = step > sr.s_begin ? carry[ia][lp] : -1.f;   // O of column C0-1
                     const float L = shift_in(O, cin);
                     if (n == 15) carry[ia][lp] = O;
@@ -476,7 +477,8 @@ __device__ inline void corr_f32_body(const float* __restrict__ d1, const float* 
         }
     }
     EngineF32 eng{fa, sD2, d2};
-    sweep_band(eng, a, pt, R0, seg, lam, cp, code, sCarry[wave]);
+    if (a.pos) sweep_band<true>(eng, a, pt, R0, seg, lam, cp, code, sCarry[wave]);
+    else sweep_band<false>(eng, a, pt, R0, seg, lam, cp, code, sCarry[wave]);
 }
 
 // BF16 variant: descriptors stored as H x W x 10 bf16 (9 channels + a zero),
