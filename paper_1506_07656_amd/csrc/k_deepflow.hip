@@ -504,74 +504,116 @@ __global__ __launch_bounds__(kSorThreads) void k_df_sor_tiles(LevelMaps L, SorAr
         }
 }
 
-// A whole level in one workgroup (small levels): every step of the level in
-// order, each a block-stride loop over the pixels, a barrier between steps
-// (the workgroup's global-memory writes are visible to it after a barrier).
-// The SOR of each fixed point runs on chip: u + du, v + dv and alpha psi' of
-// the whole level in LDS, each thread's pixels (i = t + 1024 k) in registers.
+// A whole level in one workgroup (small and mid-size levels): every step of
+// the level in order, each a block-stride loop over the pixels, a barrier
+// between steps (the workgroup's global-memory writes are visible to it after
+// a barrier).  The SOR of each fixed point runs on chip.  Thread t owns the
+// pixel pairs (2 p, 2 p + 1), p = t + 1024 k: two consecutive pixels in
+// raster order are always of different colours (in one row they are
+// neighbours; across a row end of an odd width W, W - 1 is even), so slot c
+// of a pair holds its pixel of colour c and every lane updates one pixel per
+// pair and half-sweep.  A slot's whole state stays in registers; u + du,
+// v + dv of the level sit in LDS split by colour, the pixel of colour c of
+// pair p at uv[c][p], so a half-sweep writes uv[c] and reads only uv[1 - c].
+// A pixel's horizontal neighbour inside its own pair is the thread's other
+// slot, read from registers.
 constexpr int kDfSmallThreads = 1024;
-constexpr long kDfSmallPixels = 2048;   // levels up to this size run in one workgroup (more would spill registers)
-constexpr int kDfSmallPPT = (int)((kDfSmallPixels + kDfSmallThreads - 1) / kDfSmallThreads);
+constexpr long kDfSmallPixels = 4096;                                        // levels up to this size run here
+constexpr int kDfSmallPairs = (int)(kDfSmallPixels / 2 / kDfSmallThreads);   // pixel pairs per thread
 
-__device__ inline void sor_level_small(const LevelMaps& L, int n_sor, float omega, float2* sUV, float* sS) {
-    const int W = L.W, H = L.H, n = W * H, t = threadIdx.x;
-    SorPx q[kDfSmallPPT];
-    int col[kDfSmallPPT];   // colour, and bits 1-4: the left, right, top, bottom neighbours exist; -1: no pixel
+struct SmallLDS {
+    float2 uv[2][kDfSmallPixels / 2];   // u + du, v + dv by colour and pair
+    float s[kDfSmallPixels];            // alpha psi' by pixel
+};
+
+__device__ inline void sor_level_small(const LevelMaps& L, int n_sor, float omega, SmallLDS& S) {
+    const int W = L.W, H = L.H, n = W * H, np = (n + 1) / 2;
+    // An opaque copy of the thread index: the pixel indices and addresses
+    // derived from it are recomputed at each call rather than kept live
+    // across the caller's other steps (which would spill registers).
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    SorPx q[kDfSmallPairs][2];
+    int px[kDfSmallPairs][2];   // pixel of the slot, -1: none
+    int nx[kDfSmallPairs][2];   // pair of the horizontal neighbour outside the pair
+    int nu[kDfSmallPairs][2];   // pairs of the top and bottom neighbours (the own pair where none)
+    int nd[kDfSmallPairs][2];
+    bool sd[kDfSmallPairs][2];  // the slot is the second pixel of its pair
 #pragma unroll
-    for (int k = 0; k < kDfSmallPPT; ++k) {
-        const int i = t + k * kDfSmallThreads;
-        if (i >= n) continue;
-        q[k].u = L.u[i];
-        q[k].v = L.v[i];
-        q[k].du = L.du[i];
-        q[k].dv = L.dv[i];
-        sUV[i] = make_float2(q[k].u + q[k].du, q[k].v + q[k].dv);
-        sS[i] = L.sw[i];
+    for (int k = 0; k < kDfSmallPairs; ++k) {
+        const int p = t + k * kDfSmallThreads, i0 = 2 * p;
+        const int y0 = i0 / W, c0 = (i0 - y0 * W + y0) & 1;   // colour of pixel i0
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int i = i0 + (c0 ^ c);
+            px[k][c] = i < n ? i : -1;
+            if (p >= np) continue;
+            SorPx& r = q[k][c];
+            r.u = r.v = r.du = r.dv = 0.f;   // the missing second pixel of an odd-sized level: a finite 0
+            if (i < n) {
+                r.u = L.u[i];
+                r.v = L.v[i];
+                r.du = L.du[i];
+                r.dv = L.dv[i];
+                S.s[i] = L.sw[i];
+            }
+            S.uv[c][p] = make_float2(r.u + r.du, r.v + r.dv);
+        }
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kDfSmallPPT; ++k) {
-        const int i = t + k * kDfSmallThreads;
-        col[k] = -1;
-        if (i >= n) continue;
-        const int y = i / W, x = i - y * W;
-        const bool ex[4] = {x > 0, x + 1 < W, y > 0, y + 1 < H};
-        const float sn[4] = {sS[ex[0] ? i - 1 : i], sS[ex[1] ? i + 1 : i], sS[ex[2] ? i - W : i], sS[ex[3] ? i + W : i]};
-        float A[5];
-        load_system(L, n, i, A);
-        sor_px_init(q[k], sS[i], sn, ex, A);
-        col[k] = ((x + y) & 1) | (ex[0] << 1) | (ex[1] << 2) | (ex[2] << 3) | (ex[3] << 4);
-    }
+    for (int k = 0; k < kDfSmallPairs; ++k)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int i = px[k][c], p = t + k * kDfSmallThreads;
+            if (i < 0) continue;
+            const int y = i / W, x = i - y * W;
+            const bool e[4] = {x > 0, x + 1 < W, y > 0, y + 1 < H};
+            const float sn[4] = {S.s[e[0] ? i - 1 : i], S.s[e[1] ? i + 1 : i], S.s[e[2] ? i - W : i],
+                                 S.s[e[3] ? i + W : i]};
+            float A[5];
+            load_system(L, n, i, A);
+            sor_px_init(q[k][c], S.s[i], sn, e, A);
+            // a neighbour that does not exist has edge weight 0: any finite value serves,
+            // the own pair's entry of the other colour is one
+            sd[k][c] = i & 1;
+            nx[k][c] = (i & 1) ? (e[1] ? p + 1 : p) : (e[0] ? p - 1 : p);
+            nu[k][c] = e[2] ? (i - W) >> 1 : p;
+            nd[k][c] = e[3] ? (i + W) >> 1 : p;
+        }
     for (int it = 0; it < n_sor; ++it)
+#pragma unroll
         for (int c = 0; c < 2; ++c) {
             // a pixel's neighbours are of the other colour: no update of this
             // half-sweep changes them
+            const float2* o = S.uv[1 - c];
 #pragma unroll
-            for (int k = 0; k < kDfSmallPPT; ++k) {
-                const int m = col[k];
-                if (m < 0 || (m & 1) != c) continue;
-                const int i = t + k * kDfSmallThreads;
-                const float2 nb[4] = {sUV[(m & 2) ? i - 1 : i], sUV[(m & 4) ? i + 1 : i], sUV[(m & 8) ? i - W : i],
-                                      sUV[(m & 16) ? i + W : i]};
-                sUV[i] = sor_px_update(q[k], nb, omega);
+            for (int k = 0; k < kDfSmallPairs; ++k) {
+                if (px[k][c] < 0) continue;
+                const SorPx& m = q[k][1 - c];
+                const float2 own = make_float2(m.u + m.du, m.v + m.dv);   // the pair's other pixel
+                const float2 h = o[nx[k][c]];
+                const float2 nb[4] = {sd[k][c] ? own : h, sd[k][c] ? h : own, o[nu[k][c]], o[nd[k][c]]};
+                S.uv[c][t + k * kDfSmallThreads] = sor_px_update(q[k][c], nb, omega);
             }
             __syncthreads();
         }
 #pragma unroll
-    for (int k = 0; k < kDfSmallPPT; ++k) {
-        const int i = t + k * kDfSmallThreads;
-        if (i >= n) continue;
-        L.du[i] = q[k].du;
-        L.dv[i] = q[k].dv;
-    }
+    for (int k = 0; k < kDfSmallPairs; ++k)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int i = px[k][c];
+            if (i < 0) continue;
+            L.du[i] = q[k][c].du;
+            L.dv[i] = q[k][c].dv;
+        }
     __syncthreads();
 }
 
 __global__ __launch_bounds__(kDfSmallThreads) void k_df_level_small(LevelMaps L, float kappa, float zeta,
                                                                      WeightArgs w, int n_fixed, int n_sor,
                                                                      float omega) {
-    __shared__ float2 sUV[kDfSmallPixels];
-    __shared__ float sS[kDfSmallPixels];
+    __shared__ SmallLDS S;
     const long n = (long)L.W * L.H;
     const long t = threadIdx.x;
 #define DF_ALL(stmt)                                               \
@@ -584,7 +626,7 @@ __global__ __launch_bounds__(kDfSmallThreads) void k_df_level_small(LevelMaps L,
     DF_ALL((px_tensors(L, i, zeta), L.du[i] = 0.f, L.dv[i] = 0.f));
     for (int f = 0; f < n_fixed; ++f) {
         DF_ALL(px_weights(L, i, w));
-        sor_level_small(L, n_sor, omega, sUV, sS);
+        sor_level_small(L, n_sor, omega, S);
     }
     DF_ALL((L.u[i] += L.du[i], L.v[i] += L.dv[i]));
 #undef DF_ALL
