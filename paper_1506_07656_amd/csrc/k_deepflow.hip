@@ -30,6 +30,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "dm_internal.h"
@@ -373,76 +374,87 @@ __device__ inline void load_system(const LevelMaps& L, long n, long i, float (&A
     for (int c = 0; c < 5; ++c) A[c] = L.A[c * n + i];
 }
 
-// Large levels: several half-sweeps per launch.  A workgroup holds a tile
-// of kSorLX x kSorLY pixels on chip, runs up to kSorHalo half-sweeps on it
-// and writes back the inner (kSorLX - 2 kSorHalo) x (kSorLY - 2 kSorHalo)
-// pixels.  A pixel with a neighbour inside the level but outside the tile is
-// never updated; the error this leaves moves one pixel inward per
-// half-sweep, so after at most kSorHalo half-sweeps every inner pixel holds
-// what the same half-sweeps over the whole level give.  The increments go
-// from one buffer to another, since a tile's rim overlaps other tiles' inner
-// pixels.  Thread t owns the two columns 2 (t % 32) + {0, 1} of kSorRPT
-// consecutive rows, a red and a black pixel per row, so each half-sweep
-// updates one pixel per row and thread.  Tile origins are even, so a
-// pixel's colour is that of its position in the tile, known at compile time.
-// A launch costs about the same at every level (6 to 264 tiles): the time
-// is one tile's chain of half-sweeps, so the tile has 512 threads of 4
-// pixels (256 threads of 8 pixels took 1.35 times as long; 1024 threads
-// on 64 x 64 tiles, 1.3 times).
-constexpr int kSorCP = 32;                                 // column pairs per tile row
-constexpr int kSorLX = 2 * kSorCP;                         // tile columns
-constexpr int kSorThreads = 512;
-constexpr int kSorRPT = 2;                                 // rows per thread (even)
-constexpr int kSorLY = kSorThreads / kSorCP * kSorRPT;     // tile rows
-constexpr int kSorHalo = 10;                               // half-sweeps per launch at most (even)
-constexpr int kSorIX = kSorLX - 2 * kSorHalo;              // inner columns
-constexpr int kSorIY = kSorLY - 2 * kSorHalo;              // inner rows
-static_assert(kSorIX > 0 && kSorIY > 0 && kSorIX % 2 == 0 && kSorIY % 2 == 0 && kSorHalo % 2 == 0 &&
-                  kSorRPT % 2 == 0,
-              "tile origins must be even");
+// Tiled levels: several half-sweeps per launch.  A workgroup holds a tile of
+// LX x LY pixels on chip, runs up to HALO half-sweeps on it and writes back
+// the inner (LX - 2 HALO) x (LY - 2 HALO) pixels.  A pixel with a neighbour
+// inside the level but outside the tile is never updated; the error this
+// leaves moves one pixel inward per half-sweep, so after at most HALO
+// half-sweeps every inner pixel holds what the same half-sweeps over the
+// whole level give.  The increments go from one buffer to another, since a
+// tile's rim overlaps other tiles' inner pixels.  Thread t owns the two
+// columns 2 (t % 32) + {0, 1} of two consecutive rows: a 2 x 2 block, two
+// pixels of each colour, so each half-sweep updates one pixel per row and
+// thread, and two of an updated pixel's four neighbours (the other pixel of
+// its row, the other row's pixel of its column) are the thread's own, read
+// from registers.  Inner sizes are even, so the tile origin X0 + Y0 is even
+// and a pixel's colour is that of its position in the tile, known at
+// compile time.
+//
+// A launch costs about 6 us whatever it does (start, loads, stores) plus
+// 0.3 us per half-sweep, so a level's 2 n_sor half-sweeps per fixed point
+// want few launches: SorWide (1024 threads, 64 x 64 tiles, a rim of 25)
+// runs them in two launches where its tiles fit the chip at once, SorNarrow
+// (512 threads, 64 x 32 tiles, a rim of 10) in five on the finest levels.
+template <int THREADS, int HALO>
+struct SorTile {
+    static constexpr int RIM = HALO;                 // half-sweeps per launch at most
+    static constexpr int CP = 32;                    // column pairs per tile row
+    static constexpr int LX = 2 * CP;                // tile columns
+    static constexpr int LY = THREADS / CP * 2;      // tile rows (two per thread)
+    static constexpr int IX = LX - 2 * HALO;         // inner columns
+    static constexpr int IY = LY - 2 * HALO;         // inner rows
+    static_assert(IX > 0 && IY > 0 && IX % 2 == 0 && IY % 2 == 0, "inner sizes must be even");
+};
+using SorNarrow = SorTile<512, 10>;
+using SorWide = SorTile<1024, 25>;
 
 struct SorArgs {
     int ntx;     // tiles along x
-    int nhalf;   // half-sweeps of this launch: even, at most kSorHalo, the first of colour 0
+    int nhalf;   // half-sweeps of this launch, at most the tile's rim
+    int c0;      // colour of the first half-sweep
     float omega;
     const float *du_in, *dv_in;
     float *du_out, *dv_out;
     float *u_fin, *v_fin;   // last launch of the level: the level's flow u + du, v + dv goes here instead
 };
 
-__global__ __launch_bounds__(kSorThreads) void k_df_sor_tiles(LevelMaps L, SorArgs a) {
-    __shared__ float2 sUV[kSorLY + 2][kSorLX + 2];   // u + du, v + dv; a zero border
-    __shared__ float sS[kSorLY + 2][kSorLX + 2];     // alpha psi' (0 outside the level)
+template <int THREADS, int HALO>
+__global__ __launch_bounds__(THREADS) void k_df_sor_tiles(LevelMaps L, SorArgs a) {
+    using T = SorTile<THREADS, HALO>;
+    constexpr int LX = T::LX, LY = T::LY;
+    __shared__ float2 sUV[LY + 2][LX + 2];   // u + du, v + dv; a zero border
+    __shared__ float sS[LY + 2][LX + 2];     // alpha psi' (0 outside the level)
     const int W = L.W, H = L.H;
     const long n = (long)W * H;
     const int tx = blockIdx.x % a.ntx, ty = blockIdx.x / a.ntx;
-    const int X0 = tx * kSorIX - kSorHalo, Y0 = ty * kSorIY - kSorHalo;
-    const int t = threadIdx.x, cp = t % kSorCP, rg = t / kSorCP;
-    for (int e = t; e < 2 * (kSorLX + 2) + 2 * kSorLY; e += kSorThreads) {
+    const int X0 = tx * T::IX - HALO, Y0 = ty * T::IY - HALO;
+    const int t = threadIdx.x, cp = t % T::CP, rg = t / T::CP;
+    for (int e = t; e < 2 * (LX + 2) + 2 * LY; e += THREADS) {
         int yy, xx;
-        if (e < 2 * (kSorLX + 2)) {
-            yy = e < kSorLX + 2 ? 0 : kSorLY + 1;
-            xx = e % (kSorLX + 2);
+        if (e < 2 * (LX + 2)) {
+            yy = e < LX + 2 ? 0 : LY + 1;
+            xx = e % (LX + 2);
         } else {
-            const int k = e - 2 * (kSorLX + 2);
+            const int k = e - 2 * (LX + 2);
             yy = 1 + (k >> 1);
-            xx = (k & 1) ? kSorLX + 1 : 0;
+            xx = (k & 1) ? LX + 1 : 0;
         }
         sUV[yy][xx] = make_float2(0.f, 0.f);
         sS[yy][xx] = 0.f;
     }
-    SorPx q[kSorRPT][2];
-    bool upd[kSorRPT][2];
-    float Av[kSorRPT][2][5];
+    SorPx q[2][2];
+    float2 w[2][2];   // u + du, v + dv of the thread's pixels (what sUV holds for them)
+    bool upd[2][2];
+    float Av[2][2][5];
 #pragma unroll
-    for (int r = 0; r < kSorRPT; ++r)
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const int lx = 2 * cp + j, ly = rg * kSorRPT + r, x = X0 + lx, y = Y0 + ly;
+            const int lx = 2 * cp + j, ly = 2 * rg + r, x = X0 + lx, y = Y0 + ly;
             const bool in = x >= 0 && x < W && y >= 0 && y < H;
             // updated: inside the level, every neighbour inside the level lies inside the tile
-            upd[r][j] = in && (x == 0 || lx > 0) && (x + 1 == W || lx + 1 < kSorLX) && (y == 0 || ly > 0) &&
-                        (y + 1 == H || ly + 1 < kSorLY);
+            upd[r][j] = in && (x == 0 || lx > 0) && (x + 1 == W || lx + 1 < LX) && (y == 0 || ly > 0) &&
+                        (y + 1 == H || ly + 1 < LY);
             const long i = in ? (long)y * W + x : 0;
             SorPx& p = q[r][j];
             p.u = in ? L.u[i] : 0.f;
@@ -450,49 +462,63 @@ __global__ __launch_bounds__(kSorThreads) void k_df_sor_tiles(LevelMaps L, SorAr
             p.du = in ? a.du_in[i] : 0.f;
             p.dv = in ? a.dv_in[i] : 0.f;
             if (upd[r][j]) load_system(L, n, i, Av[r][j]);
-            sUV[ly + 1][lx + 1] = make_float2(p.u + p.du, p.v + p.dv);
+            w[r][j] = make_float2(p.u + p.du, p.v + p.dv);
+            sUV[ly + 1][lx + 1] = w[r][j];
             sS[ly + 1][lx + 1] = in ? L.sw[i] : 0.f;
         }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSorRPT; ++r)
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             if (!upd[r][j]) continue;
-            const int lx = 2 * cp + j, ly = rg * kSorRPT + r, x = X0 + lx, y = Y0 + ly;
+            const int lx = 2 * cp + j, ly = 2 * rg + r, x = X0 + lx, y = Y0 + ly;
             const float sn[4] = {sS[ly + 1][lx], sS[ly + 1][lx + 2], sS[ly][lx + 1], sS[ly + 2][lx + 1]};
             const bool ex[4] = {x > 0, x + 1 < W, y > 0, y + 1 < H};
             sor_px_init(q[r][j], sS[ly + 1][lx + 1], sn, ex, Av[r][j]);
         }
-    for (int h = 0; h < a.nhalf; h += 2) {
+    // One half-sweep of colour C: the pixel of colour C in row r is column
+    // j = (C + r) & 1; the other pixel of its row and the other row's pixel
+    // of its column are of the other colour and the thread's own.
+    auto half = [&](auto cc) {
+        constexpr int C = decltype(cc)::value;
+        float2 nb[2][4];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            // the neighbours of this colour's pixels (all of the other colour) first, then the updates
-            float2 nb[kSorRPT][4];
-#pragma unroll
-            for (int r = 0; r < kSorRPT; ++r) {
-                const int j = (c + r) & 1, lx = 2 * cp + j, ly = rg * kSorRPT + r;
-                nb[r][0] = sUV[ly + 1][lx];
-                nb[r][1] = sUV[ly + 1][lx + 2];
-                nb[r][2] = sUV[ly][lx + 1];
-                nb[r][3] = sUV[ly + 2][lx + 1];
-            }
-#pragma unroll
-            for (int r = 0; r < kSorRPT; ++r) {
-                const int j = (c + r) & 1, lx = 2 * cp + j, ly = rg * kSorRPT + r;
-                if (upd[r][j]) sUV[ly + 1][lx + 1] = sor_px_update(q[r][j], nb[r], a.omega);
-            }
-            __syncthreads();
+        for (int r = 0; r < 2; ++r) {
+            const int j = (C + r) & 1, lx = 2 * cp + j, ly = 2 * rg + r;
+            const float2 side = j ? sUV[ly + 1][lx + 2] : sUV[ly + 1][lx];   // the neighbour outside the block
+            const float2 vert = r ? sUV[ly + 2][lx + 1] : sUV[ly][lx + 1];
+            nb[r][0] = j ? w[r][0] : side;       // left
+            nb[r][1] = j ? side : w[r][1];       // right
+            nb[r][2] = r ? w[0][j] : vert;       // top
+            nb[r][3] = r ? vert : w[1][j];       // bottom
         }
-    }
 #pragma unroll
-    for (int r = 0; r < kSorRPT; ++r)
+        for (int r = 0; r < 2; ++r) {
+            const int j = (C + r) & 1, lx = 2 * cp + j, ly = 2 * rg + r;
+            if (upd[r][j]) {
+                w[r][j] = sor_px_update(q[r][j], nb[r], a.omega);
+                sUV[ly + 1][lx + 1] = w[r][j];
+            }
+        }
+        __syncthreads();
+    };
+    int h = 0;
+    if (a.c0) {
+        half(std::integral_constant<int, 1>());
+        h = 1;
+    }
+    for (; h + 2 <= a.nhalf; h += 2) {
+        half(std::integral_constant<int, 0>());
+        half(std::integral_constant<int, 1>());
+    }
+    if (h < a.nhalf) half(std::integral_constant<int, 0>());
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const int lx = 2 * cp + j, ly = rg * kSorRPT + r, x = X0 + lx, y = Y0 + ly;
-            if (lx < kSorHalo || lx >= kSorHalo + kSorIX || ly < kSorHalo || ly >= kSorHalo + kSorIY || x >= W ||
-                y >= H)
-                continue;
+            const int lx = 2 * cp + j, ly = 2 * rg + r, x = X0 + lx, y = Y0 + ly;
+            if (lx < HALO || lx >= HALO + T::IX || ly < HALO || ly >= HALO + T::IY || x >= W || y >= H) continue;
             const long i = (long)y * W + x;
             if (a.u_fin) {
                 a.u_fin[i] = q[r][j].u + q[r][j].du;
@@ -775,6 +801,11 @@ dm_status flow_enqueue(const float* img1, const float* img2, int W, int H, int l
     char* base = static_cast<char*>(ws);
     auto F = [&](size_t o) { return reinterpret_cast<float*>(base + o); };
     const int K = (int)Lo.W.size() - 1;
+    int dev = 0, n_cu = 0;
+    if ((st = check_hip(hipGetDevice(&dev), "hipGetDevice")) != DM_OK) return st;
+    if ((st = check_hip(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev),
+                        "hipDeviceGetAttribute")) != DM_OK)
+        return st;
     Taps taps;
     {
         const int r = (int)ceil(3.0 * p->sigma);
@@ -837,17 +868,27 @@ dm_status flow_enqueue(const float* img1, const float* img2, int W, int H, int l
             DF("df_grad", k, 0, k_df_grad1, g, b, 0, s, M, p->kappa);
             DF("df_tensors", k, 0, k_df_tensors, g, b, 0, s, M, p->zeta);   // also zeroes du, dv
             float *du_o = F(Lo.du2), *dv_o = F(Lo.dv2);   // the other increment buffers
-            const int ntx = (Wk + kSorIX - 1) / kSorIX, nty = (Hk + kSorIY - 1) / kSorIY;
+            const int ntx_w = (Wk + SorWide::IX - 1) / SorWide::IX, nty_w = (Hk + SorWide::IY - 1) / SorWide::IY;
+            const bool wide = ntx_w * nty_w <= n_cu;   // one wide tile per compute unit at most
+            const int halo = wide ? SorWide::RIM : SorNarrow::RIM;
+            const int ntx = wide ? ntx_w : (Wk + SorNarrow::IX - 1) / SorNarrow::IX;
+            const int nty = wide ? nty_w : (Hk + SorNarrow::IY - 1) / SorNarrow::IY;
             bool flow_in_u2 = false;
             for (int f = 0; f < p->n_fixed; ++f) {
                 DF("df_weights", k, 0, k_df_weights, g, b, 0, s, M, wa);
-                for (int h = 0; h < 2 * p->n_sor; h += kSorHalo) {
-                    const int nh = min(kSorHalo, 2 * p->n_sor - h);
+                for (int h = 0; h < 2 * p->n_sor; h += halo) {
+                    const int nh = min(halo, 2 * p->n_sor - h);
                     // the level's last launch writes u + du, v + dv into u2, v2 (the coarser
                     // level's flow there has been resampled already)
                     const bool last = f + 1 == p->n_fixed && h + nh == 2 * p->n_sor;
-                    const SorArgs sa{ntx, nh, p->omega, M.du, M.dv, du_o, dv_o, last ? u2 : nullptr, last ? v2 : nullptr};
-                    DF("df_sor", k, 0, k_df_sor_tiles, dim3(ntx * nty), dim3(kSorThreads), 0, s, M, sa);
+                    const SorArgs sa{ntx, nh, h & 1, p->omega, M.du, M.dv, du_o, dv_o, last ? u2 : nullptr,
+                                     last ? v2 : nullptr};
+                    if (wide)
+                        DF("df_sor", k, 0, (k_df_sor_tiles<1024, SorWide::RIM>), dim3(ntx * nty), dim3(1024), 0, s, M,
+                           sa);
+                    else
+                        DF("df_sor", k, 0, (k_df_sor_tiles<512, SorNarrow::RIM>), dim3(ntx * nty), dim3(512), 0, s, M,
+                           sa);
                     std::swap(M.du, du_o);
                     std::swap(M.dv, dv_o);
                     flow_in_u2 = last;
