@@ -477,42 +477,56 @@ __global__ __launch_bounds__(THREADS) void k_df_sor_tiles(LevelMaps L, SorArgs a
             const bool ex[4] = {x > 0, x + 1 < W, y > 0, y + 1 < H};
             sor_px_init(q[r][j], sS[ly + 1][lx + 1], sn, ex, Av[r][j]);
         }
-    // One half-sweep of colour C: the pixel of colour C in row r is column
-    // j = (C + r) & 1; the other pixel of its row and the other row's pixel
-    // of its column are of the other colour and the thread's own.
-    auto half = [&](auto cc) {
+    // Distance (rows or columns, the larger) of each pixel from the inner
+    // region: a value computed at a half-sweep after which R half-sweeps
+    // remain reaches at most R pixels further, so a pixel farther than R from
+    // the inner region is left as it is (whole waves skip the rows that are).
+    auto dist = [&](int v, int inner) { return max(max(HALO - v, v - (HALO + inner - 1)), 0); };
+    int far[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) far[r][j] = max(dist(2 * rg + r, T::IY), dist(2 * cp + j, T::IX));
+    // One half-sweep of colour C (the hh-th of the launch): the pixel of
+    // colour C in row r is column j = (C + r) & 1; the other pixel of its row
+    // and the other row's pixel of its column are of the other colour and the
+    // thread's own.
+    auto half = [&](auto cc, int hh) {
         constexpr int C = decltype(cc)::value;
-        float2 nb[2][4];
+        const int R = a.nhalf - 1 - hh;
+        if (min(far[0][C & 1], far[1][(C + 1) & 1]) <= R) {
+            float2 nb[2][4];
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int j = (C + r) & 1, lx = 2 * cp + j, ly = 2 * rg + r;
-            const float2 side = j ? sUV[ly + 1][lx + 2] : sUV[ly + 1][lx];   // the neighbour outside the block
-            const float2 vert = r ? sUV[ly + 2][lx + 1] : sUV[ly][lx + 1];
-            nb[r][0] = j ? w[r][0] : side;       // left
-            nb[r][1] = j ? side : w[r][1];       // right
-            nb[r][2] = r ? w[0][j] : vert;       // top
-            nb[r][3] = r ? vert : w[1][j];       // bottom
-        }
+            for (int r = 0; r < 2; ++r) {
+                const int j = (C + r) & 1, lx = 2 * cp + j, ly = 2 * rg + r;
+                const float2 side = j ? sUV[ly + 1][lx + 2] : sUV[ly + 1][lx];   // the neighbour outside the block
+                const float2 vert = r ? sUV[ly + 2][lx + 1] : sUV[ly][lx + 1];
+                nb[r][0] = j ? w[r][0] : side;       // left
+                nb[r][1] = j ? side : w[r][1];       // right
+                nb[r][2] = r ? w[0][j] : vert;       // top
+                nb[r][3] = r ? vert : w[1][j];       // bottom
+            }
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int j = (C + r) & 1, lx = 2 * cp + j, ly = 2 * rg + r;
-            if (upd[r][j]) {
-                w[r][j] = sor_px_update(q[r][j], nb[r], a.omega);
-                sUV[ly + 1][lx + 1] = w[r][j];
+            for (int r = 0; r < 2; ++r) {
+                const int j = (C + r) & 1, lx = 2 * cp + j, ly = 2 * rg + r;
+                if (upd[r][j] && far[r][j] <= R) {
+                    w[r][j] = sor_px_update(q[r][j], nb[r], a.omega);
+                    sUV[ly + 1][lx + 1] = w[r][j];
+                }
             }
         }
         __syncthreads();
     };
     int h = 0;
     if (a.c0) {
-        half(std::integral_constant<int, 1>());
+        half(std::integral_constant<int, 1>(), 0);
         h = 1;
     }
     for (; h + 2 <= a.nhalf; h += 2) {
-        half(std::integral_constant<int, 0>());
-        half(std::integral_constant<int, 1>());
+        half(std::integral_constant<int, 0>(), h);
+        half(std::integral_constant<int, 1>(), h + 1);
     }
-    if (h < a.nhalf) half(std::integral_constant<int, 0>());
+    if (h < a.nhalf) half(std::integral_constant<int, 0>(), h);
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
