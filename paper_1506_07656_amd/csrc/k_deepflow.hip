@@ -391,10 +391,10 @@ __device__ inline void load_system(const LevelMaps& L, long n, long i, float (&A
 // compile time.
 //
 // A launch costs about 6 us whatever it does (start, loads, stores) plus
-// 0.3 us per half-sweep, so a level's 2 n_sor half-sweeps per fixed point
-// want few launches: SorWide (1024 threads, 64 x 64 tiles, a rim of 25)
-// runs them in two launches where its tiles fit the chip at once, SorNarrow
-// (512 threads, 64 x 32 tiles, a rim of 10) in five on the finest levels.
+// 0.3 to 0.5 us per half-sweep, so a level's 2 n_sor half-sweeps per fixed
+// point want few launches: 1024 threads on 64 x 64 tiles with a rim of 25
+// (two launches for 25 sweeps) or 17 (three) where the tiles fit the chip
+// at once, else 512 threads on 64 x 32 tiles with a rim of 10 (five).
 template <int THREADS, int HALO>
 struct SorTile {
     static constexpr int RIM = HALO;                 // half-sweeps per launch at most
@@ -407,6 +407,7 @@ struct SorTile {
 };
 using SorNarrow = SorTile<512, 10>;
 using SorWide = SorTile<1024, 25>;
+using SorMid = SorTile<1024, 17>;
 
 struct SorArgs {
     int ntx;     // tiles along x
@@ -882,11 +883,21 @@ dm_status flow_enqueue(const float* img1, const float* img2, int W, int H, int l
             DF("df_grad", k, 0, k_df_grad1, g, b, 0, s, M, p->kappa);
             DF("df_tensors", k, 0, k_df_tensors, g, b, 0, s, M, p->zeta);   // also zeroes du, dv
             float *du_o = F(Lo.du2), *dv_o = F(Lo.dv2);   // the other increment buffers
-            const int ntx_w = (Wk + SorWide::IX - 1) / SorWide::IX, nty_w = (Hk + SorWide::IY - 1) / SorWide::IY;
-            const bool wide = ntx_w * nty_w <= n_cu;   // one wide tile per compute unit at most
-            const int halo = wide ? SorWide::RIM : SorNarrow::RIM;
-            const int ntx = wide ? ntx_w : (Wk + SorNarrow::IX - 1) / SorNarrow::IX;
-            const int nty = wide ? nty_w : (Hk + SorNarrow::IY - 1) / SorNarrow::IY;
+            // the 64 x 64 shape with the fewest launches whose tiles fit the
+            // compute units at once (on equal launches the larger inner region),
+            // else the 64 x 32 one
+            const int nh_fp = 2 * p->n_sor;
+            auto launches = [&](int rim) { return (nh_fp + rim - 1) / rim; };
+            auto tiles = [&](int ix, int iy) { return ((Wk + ix - 1) / ix) * ((Hk + iy - 1) / iy); };
+            int shape = 0;   // 0: 64 x 32, rim 10; 1: 64 x 64, rim 17; 2: 64 x 64, rim 25
+            if (tiles(SorMid::IX, SorMid::IY) <= n_cu) shape = 1;
+            if (tiles(SorWide::IX, SorWide::IY) <= n_cu &&
+                (shape == 0 || launches(SorWide::RIM) < launches(SorMid::RIM)))
+                shape = 2;
+            const int halo = shape == 2 ? SorWide::RIM : shape == 1 ? SorMid::RIM : SorNarrow::RIM;
+            const int ix = shape == 2 ? SorWide::IX : shape == 1 ? SorMid::IX : SorNarrow::IX;
+            const int iy = shape == 2 ? SorWide::IY : shape == 1 ? SorMid::IY : SorNarrow::IY;
+            const int ntx = (Wk + ix - 1) / ix, nty = (Hk + iy - 1) / iy;
             bool flow_in_u2 = false;
             for (int f = 0; f < p->n_fixed; ++f) {
                 DF("df_weights", k, 0, k_df_weights, g, b, 0, s, M, wa);
@@ -897,8 +908,11 @@ dm_status flow_enqueue(const float* img1, const float* img2, int W, int H, int l
                     const bool last = f + 1 == p->n_fixed && h + nh == 2 * p->n_sor;
                     const SorArgs sa{ntx, nh, h & 1, p->omega, M.du, M.dv, du_o, dv_o, last ? u2 : nullptr,
                                      last ? v2 : nullptr};
-                    if (wide)
+                    if (shape == 2)
                         DF("df_sor", k, 0, (k_df_sor_tiles<1024, SorWide::RIM>), dim3(ntx * nty), dim3(1024), 0, s, M,
+                           sa);
+                    else if (shape == 1)
+                        DF("df_sor", k, 0, (k_df_sor_tiles<1024, SorMid::RIM>), dim3(ntx * nty), dim3(1024), 0, s, M,
                            sa);
                     else
                         DF("df_sor", k, 0, (k_df_sor_tiles<512, SorNarrow::RIM>), dim3(ntx * nty), dim3(512), 0, s, M,

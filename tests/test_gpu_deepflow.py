@@ -70,9 +70,9 @@ def test_ground_truth_matches_equal_oracle(W, H):
 @pytest.mark.parametrize("kw", [dict(n_sor=7), dict(n_sor=0), dict(n_fixed=0), dict(n_sor=3, n_fixed=2, omega=1.2)])
 def test_sweep_counts_equal_oracle(kw):
     """Other SOR schedules on a warped pair whose fine levels take the tiled
-    SOR (64 x 64 tiles, up to 25 half-sweeps per launch): 7 sweeps (one
-    launch of 14 half-sweeps per fixed point), 3 sweeps with 2 fixed points,
-    no sweeps or no fixed points (each level keeps the flow it receives, and
+    SOR on 64 x 64 tiles: 7 sweeps (one launch of 14 half-sweeps per fixed
+    point, on the tiles with a rim of 17), 3 sweeps with 2 fixed points, no
+    sweeps or no fixed points (each level keeps the flow it receives, and
     the level's add runs instead of the last SOR launch)."""
     W, H = 96, 72
     p = synth.make_warp_pair(505, W, H, 5.0)
@@ -85,21 +85,28 @@ def test_sweep_counts_equal_oracle(kw):
     compare(f"{W}x{H} pair, {kw}", g, o)
 
 
-def test_narrow_and_wide_tiles_equal_oracle():
-    """A 240 x 240 pair: on a 256-CU device its two finest levels need more
-    64 x 64 tiles (rim 25, two launches per fixed point) than there are
-    compute units and take the 64 x 32 tiles (rim 10, five launches); the
-    levels below take the 64 x 64 tiles, and those of at most 4096 pixels
-    one workgroup."""
-    W = H = 240
-    p = synth.make_warp_pair(515, W, H, 5.0)
-    ys, xs = np.mgrid[2:H:4, 2:W:4]
+def grid_matches(p, W, H, step):
+    ys, xs = np.mgrid[2:H:step, 2:W:step]
     qx, qy = p["flow"](xs, ys)
-    m = np.stack([xs.ravel(), ys.ravel(), np.rint(qx).ravel(), np.rint(qy).ravel(),
-                  np.zeros(xs.size)], axis=1).astype(np.int64)
-    o = F.deepflow(p["img1"], p["img2"], m[:, :4].astype(np.float64), F.FlowParams())
-    g = gpu_flow(p["img1"], p["img2"], m)
-    compare(f"{W}x{H} pair, {len(m)} matches", g, o)
+    return np.stack([xs.ravel(), ys.ravel(), np.rint(qx).ravel(), np.rint(qy).ravel(),
+                     np.zeros(xs.size)], axis=1).astype(np.int64)
+
+
+@pytest.mark.parametrize("W,H,kw", [(240, 240, {}), (520, 460, dict(n_fixed=1, n_sor=5))])
+def test_every_tile_shape_equals_oracle(W, H, kw):
+    """On a 256-CU device: the 240 x 240 pair's two finest levels take the
+    64 x 64 tiles with a rim of 17 (three launches per fixed point: the
+    tiles with a rim of 25 would be more than the compute units), the levels
+    below those with a rim of 25 (two launches), the last ones of at most
+    4096 pixels one workgroup; the 520 x 460 pair's finest level needs more
+    64 x 64 tiles than compute units even with a rim of 17 and takes the
+    64 x 32 tiles with a rim of 10 (one fixed point of 5 sweeps keeps the
+    oracle quick)."""
+    p = synth.make_warp_pair(515 + W, W, H, 5.0)
+    m = grid_matches(p, W, H, 4 if W < 400 else 8)
+    o = F.deepflow(p["img1"], p["img2"], m[:, :4].astype(np.float64), F.FlowParams(**kw))
+    g = gpu_flow(p["img1"], p["img2"], m, **kw)
+    compare(f"{W}x{H} pair, {len(m)} matches, {kw}", g, o)
 
 
 def test_deepmatching_matches_of_the_oracle():
