@@ -31,8 +31,6 @@ namespace {
 
 constexpr double kTie = 1e-11;     // dot products this close to the largest are equal
 constexpr float kGap = 5e-4f;      // FP32 gap that certifies a decision (see above)
-constexpr int KM_NT = 2;           // patch tiles of 16 per wave in the FP32 pass
-constexpr int KM_PB = 64 * KM_NT;  // patches per block (4 waves)
 constexpr int KM_LD = 148;         // LDS row stride (floats) of a staged centroid
 constexpr int KM_FIX = 64;         // patches per block of the decision kernel (one wave)
 constexpr int KM_G3 = 16;          // patches per group of the all-centroid FP64 path
@@ -198,14 +196,19 @@ __device__ inline Top3 shfl_xor_top3(const Top3& s, int m) {
     return o;
 }
 
-// FP32 pass: block (patch block, centroid chunk of KM_CH).  The chunk's
-// centroids are staged in LDS; each wave keeps KM_NT tiles of 16 patches in
+// FP32 pass: block (patch block, centroid chunk of KM_CH); NT = 2 patch
+// tiles per wave where that still makes two blocks per compute unit (many
+// centroids), else 1 (twice the blocks: with 64 centroids the 2-tile grid
+// has 64 blocks, and its launch takes 1.3 times as long).  The chunk's
+// centroids are staged in LDS; each wave keeps NT tiles of 16 patches in
 // registers as the B operand of v_mfma_f32_16x16x4f32 (K = 144 split so that
 // the 16-lane group g of a wave owns the 36 values of patch row g, one
 // contiguous run in both layouts) and takes the centroids 16 at a time as the
 // A operand.  Lane (g, n) receives centroids 4g..4g+3 of the tile for patch
 // n and folds them into its running Top3.
+template <int NT>
 __global__ __launch_bounds__(256) void k_km_assign(KmArgs a) {
+    constexpr int PB = 64 * NT;   // patches per block (4 waves)
     __shared__ __align__(16) float sC[KM_CH * KM_LD];
     __shared__ int sSh[KM_CH];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -221,11 +224,11 @@ __global__ __launch_bounds__(256) void k_km_assign(KmArgs a) {
         *(f4*)(sC + i * KM_LD + 36 * r + 4 * v) = x;
     }
     if (tid < KM_CH) sSh[tid] = tid < nd ? a.shadow[d0 + tid] : 1;
-    float fb[KM_NT][36];
-    int pp[KM_NT];
+    float fb[NT][36];
+    int pp[NT];
 #pragma unroll
-    for (int nt = 0; nt < KM_NT; ++nt) {
-        const int p = blockIdx.x * KM_PB + wave * 16 * KM_NT + nt * 16 + n;
+    for (int nt = 0; nt < NT; ++nt) {
+        const int p = blockIdx.x * PB + wave * 16 * NT + nt * 16 + n;
         pp[nt] = p;
         if (p < a.n) {
             const int b = p / a.gx0, aa = p - b * a.gx0;
@@ -238,23 +241,23 @@ __global__ __launch_bounds__(256) void k_km_assign(KmArgs a) {
         }
     }
     __syncthreads();
-    Top3 st[KM_NT];
+    Top3 st[NT];
 #pragma unroll
-    for (int nt = 0; nt < KM_NT; ++nt) st[nt] = Top3{-INFINITY, -INFINITY, -INFINITY, 0x7fffffff, 0x7fffffff};
+    for (int nt = 0; nt < NT; ++nt) st[nt] = Top3{-INFINITY, -INFINITY, -INFINITY, 0x7fffffff, 0x7fffffff};
     for (int ct = 0; ct * 16 < nd; ++ct) {
         const float* src = sC + (ct * 16 + n) * KM_LD + grp * 36;
-        f4 acc[KM_NT];
+        f4 acc[NT];
 #pragma unroll
-        for (int nt = 0; nt < KM_NT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int nt = 0; nt < NT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < 36; ++t) {
             const float fa = src[t];
 #pragma unroll
-            for (int nt = 0; nt < KM_NT; ++nt)
+            for (int nt = 0; nt < NT; ++nt)
                 acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa, fb[nt][t], acc[nt], 0, 0, 0);
         }
 #pragma unroll
-        for (int nt = 0; nt < KM_NT; ++nt)
+        for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = ct * 16 + 4 * grp + r;
@@ -262,7 +265,7 @@ __global__ __launch_bounds__(256) void k_km_assign(KmArgs a) {
             }
     }
 #pragma unroll
-    for (int nt = 0; nt < KM_NT; ++nt) {
+    for (int nt = 0; nt < NT; ++nt) {
         merge(st[nt], shfl_xor_top3(st[nt], 16));
         merge(st[nt], shfl_xor_top3(st[nt], 32));
         const int p = pp[nt];
@@ -526,7 +529,8 @@ hipError_t launch_kmeans(const KmArgs& a, int iters, hipStream_t s) {
     if (a.D < 1 || a.D > DM_MAX_PROTOTYPES || a.D > a.n || a.nchunk != kmeans_chunks(a.D) ||
         a.nsplit != kmeans_update_splits(a.D))
         return hipErrorInvalidValue;
-    const dim3 g_assign((a.n + KM_PB - 1) / KM_PB, a.nchunk), g_fix((a.n + KM_FIX - 1) / KM_FIX);
+    const bool nt2 = (long)((a.n + 127) / 128) * a.nchunk >= 512;
+    const dim3 g_assign((a.n + (nt2 ? 127 : 63)) / (nt2 ? 128 : 64), a.nchunk), g_fix((a.n + KM_FIX - 1) / KM_FIX);
     const dim3 g_shadow((a.D + 3) / 4);
     timing_begin("kmeans_init", 0, s);
     hipLaunchKernelGGL(k_km_init, dim3(a.D), dim3(64), 0, s, a);
@@ -537,7 +541,10 @@ hipError_t launch_kmeans(const KmArgs& a, int iters, hipStream_t s) {
     hipError_t e = hipGetLastError();
     for (int it = 0; it <= iters && e == hipSuccess; ++it) {
         timing_begin("kmeans_assign", 0, s);
-        hipLaunchKernelGGL(k_km_assign, g_assign, dim3(256), 0, s, a);
+        if (nt2)
+            hipLaunchKernelGGL(k_km_assign<2>, g_assign, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL(k_km_assign<1>, g_assign, dim3(256), 0, s, a);
         timing_end(s);
         timing_begin("kmeans_fix", 0, s);
         hipLaunchKernelGGL(k_km_fix, g_fix, dim3(KM_FIX), 0, s, a);
