@@ -698,11 +698,17 @@ __global__ __launch_bounds__(256) void k_backtrack(BtArgs a, const float* __rest
 // DM* entry points: kEntryBit on the codes of the local maxima of C'_l (maps
 // of existing patches only).  Block = (patch, band of kMarkRows rows, 256
 // columns); a thread owns one column and walks down the band with the 3 x 3
-// neighbourhood in registers, loading the three values of the next row (its
-// left and right ones are the neighbouring threads' centres, served by the
-// cache).  Neighbours outside the map are -inf, which every comparison
-// passes: the same decision as local_max, which skips them.
+// neighbourhood in registers.  It loads one value per row, kMarkAhead rows
+// at a time (the walk is bound by load latency, not by bytes), and sets
+// the bit with a store that nothing waits for; the left and right values
+// come from the neighbouring lanes, and the first and last lanes of a wave
+// load the column beside the wave.  The code array is 256-byte aligned in
+// the workspace, so the word around any of its bytes lies inside it.  Neighbours outside the
+// map are -inf, which every comparison passes: the same decision as
+// local_max, which skips them.
 constexpr int kMarkRows = 32;
+constexpr int kMarkAhead = 8;
+static_assert(kMarkRows % kMarkAhead == 0, "bands are whole groups of rows");
 __global__ __launch_bounds__(256) void k_mark_entries(const float* __restrict__ cp, uint8_t* __restrict__ code,
                                                       const uint8_t* __restrict__ vt, Geom g, int l, int nxt,
                                                       int nband) {
@@ -711,33 +717,55 @@ __global__ __launch_bounds__(256) void k_mark_entries(const float* __restrict__ 
     const int xt = bid % nxt, rest = bid / nxt, band = rest % nband, c = rest / nband;   // uniform
     const int cb = c / g.gx[l], ca = c - cb * g.gx[l];
     if (!vtab(vt, g, l, 0)[ca] || !vtab(vt, g, l, 1)[cb]) return;
+    const int lane = (int)threadIdx.x & 63;
     const int x = xt * 256 + (int)threadIdx.x;
-    if (x >= w) return;
+    if (__builtin_amdgcn_readfirstlane(xt * 256 + ((int)threadIdx.x & ~63)) >= w) return;   // whole wave past the map
+    const bool in = x < w;
+    // the column this lane loads besides its own: left of the wave (lane 0) or right of it (lane 63)
+    const int xh = lane == 0 ? x - 1 : x + 1;
+    const bool hok = (lane == 0 || lane == 63) && xh >= 0 && xh < w;
     const size_t pm = (size_t)h * w;
     const float* __restrict__ m = cp + (size_t)c * pm;
     uint8_t* __restrict__ k = code + (size_t)c * pm;
     const int y0 = band * kMarkRows, y1 = min(y0 + kMarkRows, h);
-    auto row = [&](int y, float& vl, float& vc, float& vr) {
-        if (y < 0 || y >= h) {
-            vl = vc = vr = -INFINITY;
-            return;
-        }
-        const float* p = m + (size_t)y * w + x;
-        vc = p[0];
-        vl = x > 0 ? p[-1] : -INFINITY;
-        vr = x + 1 < w ? p[1] : -INFINITY;
+    auto centre = [&](int y) { return (in && y >= 0 && y < h) ? m[(size_t)y * w + x] : -INFINITY; };
+    auto side = [&](int y) { return (hok && y >= 0 && y < h) ? m[(size_t)y * w + xh] : -INFINITY; };
+    // left and right values of a row from the lanes beside (the wave's edge lanes: their own side value)
+    auto spread = [&](float vc, float vh, float& vl, float& vr) {
+        const float up = __shfl_up(vc, 1), dn = __shfl_down(vc, 1);
+        vl = lane == 0 ? vh : up;
+        vr = lane == 63 ? vh : dn;
     };
-    float ul, uc, ur, ml, mc, mr, dl, dc, dr;
-    row(y0 - 1, ul, uc, ur);
-    row(y0, ml, mc, mr);
-    for (int y = y0; y < y1; ++y) {
-        row(y + 1, dl, dc, dr);
-        const float v = mc;
-        // before it in raster order: strictly above; after it: not below
-        const bool e = v > 0.f && v > ul && v > uc && v > ur && v > ml && v >= mr && v >= dl && v >= dc && v >= dr;
-        if (e) k[(size_t)y * w + x] |= kEntryBit;
-        ul = ml, uc = mc, ur = mr;
-        ml = dl, mc = dc, mr = dr;
+    float ul, uc, ur, ml, mc, mr;
+    uc = centre(y0 - 1);
+    spread(uc, side(y0 - 1), ul, ur);
+    mc = centre(y0);
+    spread(mc, side(y0), ml, mr);
+    for (int yb = y0; yb < y1; yb += kMarkAhead) {
+        float cn[kMarkAhead], hn[kMarkAhead];   // rows yb + 1 .. yb + kMarkAhead, loaded together
+#pragma unroll
+        for (int i = 0; i < kMarkAhead; ++i) {
+            cn[i] = centre(yb + 1 + i);
+            hn[i] = side(yb + 1 + i);
+        }
+#pragma unroll
+        for (int i = 0; i < kMarkAhead; ++i) {
+            const int y = yb + i;
+            float dl, dr;
+            const float dc = cn[i];
+            spread(dc, hn[i], dl, dr);
+            const float v = mc;
+            // before it in raster order: strictly above; after it: not below
+            const bool e = v > 0.f && v > ul && v > uc && v > ur && v > ml && v >= mr && v >= dl && v >= dc && v >= dr;
+            if (in && y < y1 && e) {
+                // no-return atomic OR on the aligned word holding the byte: the walk does
+                // not wait for a load of the code (the other bytes stay as they are)
+                const uintptr_t ad = reinterpret_cast<uintptr_t>(k + (size_t)y * w + x);
+                atomicOr(reinterpret_cast<unsigned int*>(ad & ~uintptr_t(3)), (unsigned int)kEntryBit << (8 * (ad & 3)));
+            }
+            ul = ml, uc = mc, ur = mr;
+            ml = dl, mc = dc, mr = dr;
+        }
     }
 }
 
